@@ -1,0 +1,143 @@
+"""CPU oracle for subgraph-embedding enumeration (ctypes wrapper over oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  The product
+path (the HIP library and its Python binding) never imports, links or calls
+it, and the oracle imports nothing from the product package.
+
+What it computes is the definition of the paper's Sec. III-A restricted to
+edge preservation (non-induced embeddings): every injective
+``f: V_p -> V_d`` with ``{f(u), f(v)} in E_d`` for each pattern edge, as a
+lexicographically sorted ``int32`` table with column ``j`` = ``f(j)``.  See
+``oracle.c`` for the method and the return codes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OK, INVALID, RANGE, DISCONNECTED, SELF_LOOP, NOMEM, DUPLICATE = 0, -1, -2, -3, -4, -5, -9
+
+_lock = threading.Lock()
+_libs: dict[str, C.CDLL] = {}
+
+
+def build(out: str = LIB, mutant: int = 0, force: bool = True) -> str:
+    """Compile ``oracle.c`` with gcc into a shared library (seconds)."""
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
+        return out
+    tmp = out + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", f"-DORACLE_MUTANT={mutant}", SRC, "-o", tmp]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def load(path: str = LIB) -> C.CDLL:
+    with _lock:
+        if path in _libs:
+            return _libs[path]
+        if path == LIB and (not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
+            build(LIB)
+        lib = C.CDLL(path)
+        i32p = C.POINTER(C.c_int32)
+        lib.oracle_normalize.restype = C.c_int64
+        lib.oracle_normalize.argtypes = [C.c_int32, C.c_int64, i32p, i32p, i32p]
+        lib.oracle_enumerate.restype = C.c_int
+        lib.oracle_enumerate.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
+                                         C.c_int64, C.POINTER(i32p), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int64)]
+        lib.oracle_count_hash.restype = C.c_int
+        lib.oracle_count_hash.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
+                                          C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
+                                          C.POINTER(C.c_uint64)]
+        lib.oracle_row_hash.restype = C.c_uint64
+        lib.oracle_row_hash.argtypes = [i32p, C.c_int32]
+        lib.oracle_mix64.restype = C.c_uint64
+        lib.oracle_mix64.argtypes = [C.c_uint64]
+        lib.oracle_free.restype = None
+        lib.oracle_free.argtypes = [C.c_void_p]
+        lib.oracle_mutant_id.restype = C.c_int
+        _libs[path] = lib
+        return lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle returned {code}")
+        self.code = code
+
+
+def _edges(e) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(e, dtype=np.int32).reshape(-1, 2))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def normalize(n: int, edges, lib: C.CDLL | None = None):
+    """Sorted, duplicate-free, loop-free adjacency (CSR) of an undirected graph."""
+    lib = lib or load()
+    e = _edges(edges)
+    row_ptr = np.zeros(n + 1, np.int32)
+    col = np.zeros(max(2 * len(e), 1), np.int32)
+    nnz = lib.oracle_normalize(n, len(e), _p(e), _p(row_ptr), _p(col))
+    if nnz < 0:
+        raise OracleError(int(nnz))
+    return row_ptr, col[:nnz].copy()
+
+
+def enumerate_embeddings(n_d: int, edges_d, n_p: int, edges_p, cap: int = -1,
+                         lib: C.CDLL | None = None):
+    """Return ``(rows[int32, n x n_p], total)``: the lexicographically first
+    ``cap`` embeddings (all when ``cap < 0``) and the full count."""
+    lib = lib or load()
+    ed, ep = _edges(edges_d), _edges(edges_p)
+    rows = C.POINTER(C.c_int32)()
+    n_rows, total = C.c_int64(0), C.c_int64(0)
+    rc = lib.oracle_enumerate(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep), cap,
+                              C.byref(rows), C.byref(n_rows), C.byref(total))
+    if rc != 0:
+        raise OracleError(rc)
+    try:
+        nr = n_rows.value
+        if nr:
+            out = np.ctypeslib.as_array(rows, shape=(nr * n_p,)).reshape(nr, n_p).copy()
+        else:
+            out = np.zeros((0, n_p), np.int32)
+    finally:
+        if rows:
+            lib.oracle_free(C.cast(rows, C.c_void_p))
+    return out, total.value
+
+
+def count_hash(n_d: int, edges_d, n_p: int, edges_p, lib: C.CDLL | None = None):
+    """Streaming ``(count, hash_sum, hash_xor)`` without storing rows."""
+    lib = lib or load()
+    ed, ep = _edges(edges_d), _edges(edges_p)
+    cnt, hs, hx = C.c_int64(0), C.c_uint64(0), C.c_uint64(0)
+    rc = lib.oracle_count_hash(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep),
+                               C.byref(cnt), C.byref(hs), C.byref(hx))
+    if rc != 0:
+        raise OracleError(rc)
+    return cnt.value, hs.value, hx.value
+
+
+def row_hash(row, lib: C.CDLL | None = None) -> int:
+    lib = lib or load()
+    r = np.ascontiguousarray(np.asarray(row, dtype=np.int32))
+    return int(lib.oracle_row_hash(_p(r), len(r)))
+
+
+def mix64(x: int, lib: C.CDLL | None = None) -> int:
+    lib = lib or load()
+    return int(lib.oracle_mix64(C.c_uint64(x & (2**64 - 1))))

@@ -1,0 +1,362 @@
+"""Pins for the CPU oracle: facts fixed by the paper's definitions or by
+mathematics, independent of the oracle's own code.
+
+Each ``pin_*`` takes the ctypes library to check (the real oracle, or a
+mutation build that plants a mistake) and raises ``AssertionError`` when the
+library disagrees with the fact.  Sources of truth used here:
+
+* brute force over all injective maps ``V_p -> V_d`` on tiny graphs (the
+  definition of the paper's Sec. III-A, edge-preserving reading);
+* closed forms: ``#P_k`` in ``C_n`` is ``2n``; a pattern embeds into itself
+  ``|Aut(P)|`` times; the 12-cycles of a heavy-hex lattice are its faces, each
+  counted ``2*12 = 24`` times; degree-sum formulas for ``P2``, ``P3``, ``K1,3``;
+  square-grid counts of 4-cycles, 2x3 and 3x3 blocks;
+* textbook reductions: below the girth, ``#P_k`` equals the number of
+  non-backtracking walks ``1^T B^(k-2) 1`` (B = Hashimoto matrix); trees with
+  diameter below the girth embed exactly as locally injective homomorphisms,
+  countable by dynamic programming over (vertex, image, parent image);
+* invariants: rows injective, edge-preserving, strictly increasing; planted
+  embeddings present; adding a pattern edge never adds embeddings; a cap keeps
+  the lexicographic prefix;
+* the published SplitMix64 outputs for seed 0 (0xE220A8397B1DCDAF,
+  0x6E789E6AA1B965F4) for the streaming multiset hash.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+import oracle
+from paper_2508_21287_amd import workloads as W
+
+M64 = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------- helpers
+
+def _adjset(n, edges):
+    s = set()
+    for u, v in np.asarray(edges).reshape(-1, 2).tolist():
+        if u != v:
+            s.add((u, v))
+            s.add((v, u))
+    return s
+
+
+def brute_force_rows(nd, ed, k, ep):
+    adj = _adjset(nd, ed)
+    ep = np.asarray(ep).reshape(-1, 2).tolist()
+    rows = [f for f in itertools.permutations(range(nd), k)
+            if all((f[a], f[b]) in adj for a, b in ep)]
+    return np.array(rows, dtype=np.int32).reshape(-1, k)
+
+
+def automorphisms(p):
+    e = {tuple(sorted(x)) for x in p.edges.tolist()}
+    auts = []
+    for perm in itertools.permutations(range(p.n)):
+        if all(tuple(sorted((perm[a], perm[b]))) in e for a, b in e):
+            auts.append(perm)
+    return auts
+
+
+def degrees(g):
+    return np.array([len(a) for a in W.adjacency_lists(g)], dtype=np.int64)
+
+
+def nonbacktracking_paths(g, k):
+    """1^T B^(k-2) 1 over directed edges (k >= 2)."""
+    adj = W.adjacency_lists(g)
+    darcs = [(u, v) for u in range(g.n) for v in adj[u]]
+    idx = {a: i for i, a in enumerate(darcs)}
+    vec = np.ones(len(darcs), dtype=object)
+    for _ in range(k - 2):
+        nxt = np.zeros(len(darcs), dtype=object)
+        # walk (u->v) then (v->w), w != u : value flows from arc (u,v) to arc (v,w)
+        for (u, v), i in idx.items():
+            for w in adj[v]:
+                if w != u:
+                    nxt[idx[(v, w)]] += vec[i]
+        vec = nxt
+    return int(vec.sum())
+
+
+def tree_dp_count(g, t):
+    """Locally injective homomorphisms of tree ``t`` into ``g`` (children of a
+    vertex go to distinct neighbours of its image, other than the parent's
+    image).  Equals the embedding count when diam(t) < girth(g)."""
+    adj = W.adjacency_lists(g)
+    tadj = W.adjacency_lists(t)
+    order, parent = [0], {0: -1}
+    for u in order:
+        for w in tadj[u]:
+            if w not in parent:
+                parent[w] = u
+                order.append(w)
+    children = {v: [w for w in tadj[v] if parent.get(w) == v] for v in range(t.n)}
+    cnt = {}
+    for v in reversed(order):
+        table = {}
+        for x in range(g.n):
+            pimgs = adj[x] if parent[v] >= 0 else [-1]
+            for y in pimgs:
+                avail = [z for z in adj[x] if z != y]
+                ch = children[v]
+                tot = 0
+                for assign in itertools.permutations(avail, len(ch)):
+                    prod = 1
+                    for c, z in zip(ch, assign):
+                        prod *= cnt[c].get((z, x), 0)
+                        if prod == 0:
+                            break
+                    tot += prod
+                table[(x, y)] = tot
+        cnt[v] = table
+    return sum(cnt[0][(x, -1)] for x in range(g.n))
+
+
+def py_mix64(x):
+    z = (x + 0x9E3779B97F4A7C15) & M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def py_row_hash(row):
+    inner = 0
+    for j, v in enumerate(row):
+        inner = (inner + py_mix64((j << 32) | (int(v) & 0xFFFFFFFF))) & M64
+    return py_mix64(inner)
+
+
+def count(lib, g, p):
+    return oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, lib=lib)[1]
+
+
+def rows_of(lib, g, p, cap=-1):
+    return oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, cap=cap, lib=lib)
+
+
+# ---------------------------------------------------------------- patterns
+
+def small_patterns():
+    P = W.Pattern
+    pats = [W.path(1), W.path(2), W.path(3), W.path(4), W.path(5), W.cycle(3), W.cycle(4),
+            W.cycle(5), W.star(3),
+            P(4, [[0, 1], [1, 2], [2, 0], [2, 3]], "paw"),
+            P(4, [[0, 1], [1, 2], [2, 3], [3, 0], [0, 2]], "diamond"),
+            # BFS order from 0 differs from the labelling: 0,3,1,4,2
+            P(5, [[0, 3], [3, 1], [1, 2], [3, 4]], "tree-relabelled"),
+            P(5, [[4, 0], [0, 2], [2, 4], [2, 1], [1, 3]], "tri-tail-relabelled")]
+    return pats
+
+
+def small_data_graphs():
+    gs = []
+    for n, p, s in [(6, 0.5, 1), (7, 0.45, 2), (8, 0.35, 3), (7, 0.7, 4)]:
+        g = W.random_gnp(n, p, s)
+        # inject a self-loop and a duplicate (reversed) edge: both must vanish
+        extra = [[0, 0]]
+        if len(g.edges):
+            extra.append([int(g.edges[0, 1]), int(g.edges[0, 0])])
+        gs.append(W.Graph(g.n, np.vstack([g.edges, np.array(extra, np.int32)]), g.name + "+noise"))
+    c7 = W.cycle(7)
+    gs.append(W.Graph(c7.n, c7.edges, "C7"))
+    gs.append(W.grid(3, 3))
+    return gs
+
+
+# ---------------------------------------------------------------- pins
+
+def pin_brute_force(lib, quick=False):
+    gs = small_data_graphs()
+    pats = small_patterns()
+    if quick:
+        gs, pats = gs[:3] + gs[4:5], pats
+    for g in gs:
+        for p in pats:
+            if p.n > 5:
+                continue
+            want = brute_force_rows(g.n, g.edges, p.n, p.edges)
+            got, total = rows_of(lib, g, p)
+            assert total == len(want), (g.name, p.name, total, len(want))
+            assert np.array_equal(got, want), (g.name, p.name)
+    hh = W.heavy_hex(2, 5)
+    for p in [W.path(4), W.star(3), W.Pattern(4, [[0, 2], [2, 1], [1, 3]], "p4-relabelled")]:
+        want = brute_force_rows(hh.n, hh.edges, p.n, p.edges)
+        got, total = rows_of(lib, hh, p)
+        assert np.array_equal(got, want), (hh.name, p.name)
+
+
+def pin_cycle_paths(lib):
+    for n in (5, 7, 9):
+        cn = W.cycle(n)
+        g = W.Graph(cn.n, cn.edges, f"C{n}")
+        for k in range(1, n + 1):
+            want = n if k == 1 else 2 * n
+            assert count(lib, g, W.path(k)) == want, (n, k)
+
+
+def pin_self_embedding(lib):
+    cases = [(W.path(1), 1)] + [(W.path(k), 2) for k in range(2, 8)]
+    cases += [(W.cycle(k), 2 * k) for k in range(3, 9)]
+    cases += [(W.star(r), math.factorial(r)) for r in range(2, 6)]
+    g23, g33 = W.grid(2, 3), W.grid(3, 3)
+    cases += [(W.Pattern(g23.n, g23.edges, "grid2x3"), 4), (W.Pattern(g33.n, g33.edges, "grid3x3"), 8)]
+    for p, aut in cases:
+        g = W.Graph(p.n, p.edges, p.name)
+        assert count(lib, g, p) == aut, (p.name, aut)
+    # trees: |Aut| by brute force over permutations
+    for s in range(4):
+        t = W.prufer_tree(7, s)
+        g = W.Graph(t.n, t.edges, t.name)
+        assert count(lib, g, t) == len(automorphisms(t)), t.name
+
+
+def pin_heavy_hex_cells(lib, sizes=((3, 9), (4, 13), (7, 19))):
+    c12 = W.cycle(12)
+    for R, Cc in sizes:
+        g = W.heavy_hex(R, Cc)
+        assert count(lib, g, c12) == 24 * W.heavy_hex_cells(R, Cc), (R, Cc)
+
+
+def pin_degree_sums(lib):
+    for g in [W.heavy_hex(7, 19), W.grid(6, 7), W.random_gnp(30, 0.2, 7)]:
+        d = degrees(g)
+        assert count(lib, g, W.path(2)) == int(d.sum()), g.name
+        assert count(lib, g, W.path(3)) == int((d * (d - 1)).sum()), g.name
+        assert count(lib, g, W.star(3)) == int((d * (d - 1) * (d - 2)).sum()), g.name
+
+
+def pin_grid_closed_forms(lib):
+    g23, g33 = W.grid(2, 3), W.grid(3, 3)
+    p23 = W.Pattern(g23.n, g23.edges, "grid2x3")
+    p33 = W.Pattern(g33.n, g33.edges, "grid3x3")
+    for n in (4, 5, 6):
+        g = W.grid(n, n)
+        assert count(lib, g, W.cycle(4)) == 8 * (n - 1) ** 2, n
+        assert count(lib, g, p23) == 8 * (n - 1) * (n - 2), n
+        assert count(lib, g, p33) == 8 * (n - 2) ** 2, n
+
+
+def pin_nonbacktracking(lib):
+    hh = W.heavy_hex(3, 9)
+    for k in range(2, 13):
+        assert count(lib, hh, W.path(k)) == nonbacktracking_paths(hh, k), k
+    hh7 = W.heavy_hex(7, 19)
+    for k in (8, 12):
+        assert count(lib, hh7, W.path(k)) == nonbacktracking_paths(hh7, k), k
+
+
+def pin_tree_dp(lib):
+    for g in [W.heavy_hex(3, 9), W.heavy_hex(7, 19)]:
+        for k in (4, 6, 8):
+            for s in range(3):
+                t = W.prufer_tree(k, s)
+                assert count(lib, g, t) == tree_dp_count(g, t), (g.name, t.name)
+
+
+def check_table(g, p, rows, planted=None):
+    """Invariants every embedding table satisfies."""
+    rows = np.asarray(rows)
+    if len(rows) == 0:
+        return
+    assert rows.shape[1] == p.n
+    assert rows.min() >= 0 and rows.max() < g.n
+    s = np.sort(rows, axis=1)
+    assert (np.diff(s, axis=1) != 0).all(), "row not injective"
+    adj = np.zeros((g.n, g.n), dtype=bool)
+    e = g.edges[g.edges[:, 0] != g.edges[:, 1]]
+    adj[e[:, 0], e[:, 1]] = True
+    adj[e[:, 1], e[:, 0]] = True
+    for a, b in p.edges.tolist():
+        assert adj[rows[:, a], rows[:, b]].all(), "edge not preserved"
+    # strictly increasing in lexicographic order
+    diff = rows[1:] != rows[:-1]
+    first = diff.argmax(axis=1)
+    assert diff.any(axis=1).all(), "duplicate rows"
+    r = np.arange(len(first))
+    assert (rows[1:][r, first] > rows[:-1][r, first]).all(), "not sorted"
+    if planted is not None:
+        assert (rows == planted[None, :]).all(axis=1).any(), "planted embedding missing"
+
+
+def pin_invariants(lib, n_cfg2=8):
+    g, pats = W.config1()
+    for p in pats:
+        rows, total = rows_of(lib, g, p)
+        assert total == len(rows)
+        check_table(g, p, rows)
+    g2, pats2 = W.config2()
+    for p in pats2[:n_cfg2]:
+        rows, total = rows_of(lib, g2, p)
+        assert total == len(rows) and total > 0
+        check_table(g2, p, rows, planted=p.planted)
+        # |Aut(P)| divides the count for small patterns
+    for p in [W.path(6), W.cycle(12), W.prufer_tree(6, 0)]:
+        if p.n <= 7:
+            assert count(lib, g, p) % len(automorphisms(p)) == 0
+    # monotone: one more pattern edge never adds embeddings
+    p = pats2[0]
+    es = {tuple(x) for x in p.edges.tolist()}
+    extra = next((a, b) for a in range(p.n) for b in range(a + 1, p.n) if (a, b) not in es)
+    p2 = W.Pattern(p.n, np.vstack([p.edges, np.array([extra], np.int32)]), p.name + "+e")
+    assert count(lib, g2, p2) <= count(lib, g2, p)
+
+
+def pin_cap(lib):
+    g, pats = W.config1()
+    for p in pats:
+        full, total = rows_of(lib, g, p)
+        for cap in (0, 1, 5, total - 1, total, total + 3):
+            if cap < 0:
+                continue
+            got, t2 = rows_of(lib, g, p, cap=cap)
+            assert t2 == total
+            assert np.array_equal(got, full[:cap]), (p.name, cap)
+
+
+def pin_edge_cases(lib):
+    g = W.heavy_hex(3, 9)
+    rows, total = rows_of(lib, g, W.path(1))
+    assert total == g.n and np.array_equal(rows[:, 0], np.arange(g.n))
+    small = W.Graph(3, [[0, 1], [1, 2]], "P3")
+    assert count(lib, small, W.path(4)) == 0          # more pattern than data vertices
+    empty = W.Graph(0, np.zeros((0, 2), np.int32), "empty")
+    assert count(lib, empty, W.path(2)) == 0
+    iso = W.Graph(4, np.zeros((0, 2), np.int32), "isolated")
+    assert count(lib, iso, W.path(2)) == 0
+    codes = []
+    for pat in [W.Pattern(2, [[0, 0], [0, 1]], "loop"), W.Pattern(4, [[0, 1], [2, 3]], "split"),
+                W.Pattern(2, [[0, 2]], "range")]:
+        try:
+            count(lib, g, pat)
+            codes.append(0)
+        except oracle.OracleError as e:
+            codes.append(e.code)
+    assert codes == [oracle.SELF_LOOP, oracle.DISCONNECTED, oracle.RANGE], codes
+    # multi-edges in the pattern merge
+    assert count(lib, g, W.Pattern(2, [[0, 1], [1, 0], [0, 1]], "multi")) == 2 * 34
+
+
+def pin_hash(lib):
+    assert oracle.mix64(0, lib=lib) == 0xE220A8397B1DCDAF
+    assert oracle.mix64(0x9E3779B97F4A7C15, lib=lib) == 0x6E789E6AA1B965F4
+    assert py_mix64(0) == 0xE220A8397B1DCDAF
+    gs = small_data_graphs()[:3] + [W.heavy_hex(2, 5)]
+    for g in gs:
+        for p in [W.path(3), W.path(4), small_patterns()[11], W.cycle(4)]:
+            want = brute_force_rows(g.n, g.edges, p.n, p.edges)
+            hs = [py_row_hash(r) for r in want.tolist()]
+            c, s, x = oracle.count_hash(g.n, g.edges, p.n, p.edges, lib=lib)
+            xr = 0
+            for h in hs:
+                xr ^= h
+            assert (c, s, x) == (len(hs), sum(hs) & M64, xr), (g.name, p.name)
+
+
+ALL_PINS = [pin_brute_force, pin_cycle_paths, pin_self_embedding, pin_heavy_hex_cells,
+            pin_degree_sums, pin_grid_closed_forms, pin_nonbacktracking, pin_tree_dp,
+            pin_invariants, pin_cap, pin_edge_cases, pin_hash]
