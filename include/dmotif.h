@@ -1,0 +1,255 @@
+/*
+ * dmotif.h -- C ABI of libdmotif.so: subgraph-embedding enumeration as
+ * relational operations on int32 tables (the Delta-Motif method), on AMD
+ * Instinct MI355X (gfx950) with hand-written HIP kernels.
+ *
+ * The two central calls mirror the paper's two procedures:
+ *   dm_datagraph_build  -- Algorithm 2 (BuildDatabase): normalize the data
+ *                          graph and build its motif tables Res(M) once,
+ *                          resident in device memory.
+ *   dm_enumerate        -- Algorithm 1 (the join-and-filter loop): decompose
+ *                          the pattern into motif slices (Sec. III-C), join
+ *                          partial-embedding tables with the motif tables on
+ *                          shared pattern-vertex columns (Sec. III-B), filter
+ *                          for injectivity and pattern-edge consistency, then
+ *                          sort into the canonical embedding table.
+ * The problem is the one stated in Sec. III-A: every injective map
+ * f : V_p -> V_d that sends each pattern edge to a data edge ("non-induced"
+ * reading: the join and the filter enforce edge preservation and
+ * injectivity; extra data edges between images are allowed).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns dm_status; outputs are written only on DM_OK.
+ *    dm_last_error() gives a thread-local message for the last failure.
+ *  - Graph inputs are HOST arrays of undirected (u, v) int32 pairs, row-major
+ *    [n_edges][2].  The library copies them; the caller keeps ownership.
+ *  - Data graph: ids must lie in [0, n_vertices) (else DM_ERR_VERTEX_RANGE);
+ *    self-loops are dropped and repeated edges merged (Sec. III-D: Res(M2)
+ *    is E_d without self-loops, both orientations present).
+ *  - Pattern: ids in [0, n_vertices) (else DM_ERR_VERTEX_RANGE), no self-loop
+ *    (DM_ERR_PATTERN_SELF_LOOP), connected (DM_ERR_PATTERN_DISCONNECTED);
+ *    repeated edges merge.  1 <= n_vertices <= DM_MAX_PATTERN_VERTICES.
+ *    A 1-vertex pattern yields every data vertex; a pattern with more
+ *    vertices than the data graph yields 0 rows (DM_OK).
+ *  - Results: row-major int32 [rows][width], width = pattern vertex count,
+ *    column j = f(j), rows in ascending lexicographic order, no duplicates.
+ *    A cap (max_embeddings >= 0) keeps the lexicographically first `cap`
+ *    rows; the total count is still reported unless early exit stopped it.
+ *  - Handles are owned by the library until the matching *_free/_destroy.
+ *    Device pointers inside a result live until dm_result_free.
+ *  - Work is stream-ordered on the context's HIP stream.  dm_enumerate
+ *    returns once the row count is known on the host (one device->host
+ *    sync); the device table is complete when the stream reaches that point.
+ *  - Threading: a context (and the data graphs built on it) is used by one
+ *    host thread at a time; a server is internally synchronized.
+ */
+#ifndef DMOTIF_H
+#define DMOTIF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DM_MAX_PATTERN_VERTICES 128
+#define DM_MAX_MOTIF_VERTICES 12
+
+typedef enum {
+    DM_OK = 0,
+    DM_ERR_INVALID_ARG = -1,
+    DM_ERR_VERTEX_RANGE = -2,
+    DM_ERR_PATTERN_DISCONNECTED = -3,
+    DM_ERR_PATTERN_SELF_LOOP = -4,
+    DM_ERR_OUT_OF_MEMORY = -5,
+    DM_ERR_BUDGET_EXCEEDED = -6,
+    DM_ERR_DEVICE = -7,
+    DM_ERR_CANCELLED = -8,
+    DM_ERR_BUSY = -9,
+    DM_ERR_TIMEOUT = -10,
+    DM_ERR_INTERNAL = -11,
+    DM_ERR_UNSUPPORTED = -12
+} dm_status;
+
+/* Motif families (Sec. III-A "Motifs": M_i is a path of i vertices, the
+ * suffix -O a cycle).  M2 (the edge table) is always present.  A data graph
+ * is built with a mask of these; a plan may use any subset of what was built.
+ * DM_MOTIF_AUTO builds M3, M4, and the shortest cycle family present among
+ * C4 (square grid) and C12 (heavy-hex cell), mirroring the topology-aware
+ * motif sets of Sec. V (M2+M4 on heavy-hex, M2+M4-O on grids). */
+#define DM_MOTIF_M3 (1u << 0)
+#define DM_MOTIF_M4 (1u << 1)
+#define DM_MOTIF_M5 (1u << 2)
+#define DM_MOTIF_M6 (1u << 3)
+#define DM_MOTIF_C4 (1u << 4)
+#define DM_MOTIF_C6 (1u << 5)
+#define DM_MOTIF_C12 (1u << 6)
+#define DM_MOTIF_ALL 0x7Fu
+#define DM_MOTIF_AUTO 0u
+/* For dm_plan_opts.motif_mask: plan with M2 only (Sec. IV-B: one join per
+ * pattern edge, the parallel analogue of tree search). */
+#define DM_MOTIF_M2_ONLY 0x80000000u
+
+typedef struct {
+    int32_t n_vertices;
+    int64_t n_edges;
+    const int32_t* edges; /* host, [n_edges][2] */
+} dm_graph_desc;
+
+typedef enum {
+    DM_OUT_TABLE = 0,      /* materialize the sorted embedding table */
+    DM_OUT_COUNT_HASH = 1  /* count + order-independent multiset hash only */
+} dm_output_mode;
+
+typedef struct {
+    uint32_t motif_mask;   /* motifs the planner may use; 0 = every motif built */
+    int32_t block_threads; /* join-kernel workgroup size (64, 128, 256); 0 = auto */
+    int32_t output_mode;   /* dm_output_mode */
+    int32_t sync_each_step;/* 1: read each step's row count back (exact sizing) */
+    int64_t mem_budget;    /* bytes for intermediate tables; 0 = library default */
+    int32_t profile;       /* 1: time every join and sort launch with HIP events (see dm_run_stats) */
+    int32_t reserved_;
+} dm_plan_opts;
+
+typedef struct dm_context dm_context;
+typedef struct dm_datagraph dm_datagraph;
+typedef struct dm_result dm_result;
+typedef struct dm_server dm_server;
+
+/* Version string of the library build. */
+const char* dm_version(void);
+
+/* Thread-local description of the most recent failure on this thread. */
+const char* dm_last_error(void);
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = a stream the context creates and owns).
+ * Errors: DM_ERR_INVALID_ARG (bad device / out == NULL), DM_ERR_DEVICE. */
+dm_status dm_context_create(int32_t device, void* hip_stream, dm_context** out);
+void dm_context_destroy(dm_context* ctx);
+
+/* Algorithm 2 (BuildDatabase): normalize `gd` into device CSR + adjacency
+ * bitmap and build the motif tables selected by `motif_mask` (DM_MOTIF_*),
+ * each sorted by a key column with a direct-address (CSR-offset) index.
+ * The result stays resident until dm_datagraph_free.
+ * Errors: DM_ERR_INVALID_ARG, DM_ERR_VERTEX_RANGE, DM_ERR_OUT_OF_MEMORY,
+ * DM_ERR_UNSUPPORTED (a vertex degree above 16384), DM_ERR_DEVICE. */
+dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t motif_mask,
+                             dm_datagraph** out);
+void dm_datagraph_free(dm_datagraph* dg);
+
+typedef struct {
+    int32_t n_vertices;
+    int64_t n_directed_edges; /* 2|E| after normalization */
+    int32_t max_degree;
+    int32_t has_bitmap;       /* adjacency bitmap built (|V| <= 32768) */
+    uint32_t motif_mask;      /* motifs actually built */
+    int64_t motif_rows[8];    /* rows of Res(M) for M2,M3,M4,M5,M6,C4,C6,C12 (0 = absent) */
+    double build_ms;          /* device time of the whole build */
+} dm_datagraph_info;
+
+dm_status dm_datagraph_query(const dm_datagraph* dg, dm_datagraph_info* out);
+/* Host copies of the normalized CSR: row_ptr[n+1], col[2|E|] (each list ascending). */
+dm_status dm_datagraph_copy_csr(const dm_datagraph* dg, int32_t* row_ptr, int32_t* col);
+/* Host copy of a motif table: motif index 0..7 as in motif_rows, key
+ * position `key_pos` (0 for cycles; 0..ceil(size/2)-1 for paths).  Rows are
+ * grouped by the key column in ascending key order; columns are in motif
+ * position order.  rows and width receive the shape; dst may be NULL to query. */
+dm_status dm_datagraph_copy_motif(const dm_datagraph* dg, int32_t motif, int32_t key_pos,
+                                  int32_t* dst, int64_t max_rows, int64_t* rows, int32_t* width);
+
+/* Planner only (host, no device work): decompose a pattern with the motifs
+ * in `motif_mask` (Sec. III-C) and serialize the plan into `buf` as int32:
+ *   [k, n_steps, col_of[k] (pattern vertex -> table column), then per step:
+ *    motif (0..7, -1 = filter only), key_pos, key_col, c_in,
+ *    n_new, new_pos[n_new], n_eq, (col, pos)[n_eq], n_edge, (col_a, col_b)[n_edge],
+ *    slice_len, slice[slice_len] (pattern vertices in motif order)].
+ * *len receives the number of int32 written (or needed, if buf is too small:
+ * then DM_ERR_INVALID_ARG).  Errors as for pattern validation. */
+dm_status dm_plan(const dm_graph_desc* gp, uint32_t motif_mask, int32_t* buf, int32_t buf_cap,
+                  int32_t* len);
+
+/* Predicted table sizes for `gp` on `dg` (host estimate from motif-table
+ * sizes): est_rows = predicted embeddings, peak_bytes = predicted peak of
+ * two consecutive intermediate tables. */
+dm_status dm_estimate(dm_datagraph* dg, const dm_graph_desc* gp, const dm_plan_opts* opts,
+                      int64_t* peak_bytes, int64_t* est_rows);
+
+/* Algorithm 1: all embeddings of `gp` in the data graph.  max_embeddings < 0
+ * = all; otherwise the lexicographically first max_embeddings rows.  opts may
+ * be NULL (defaults).  Errors: pattern validation codes, DM_ERR_OUT_OF_MEMORY,
+ * DM_ERR_BUDGET_EXCEEDED (one root vertex alone exceeds mem_budget),
+ * DM_ERR_DEVICE, DM_ERR_INTERNAL (a duplicate row reached the output). */
+dm_status dm_enumerate(dm_datagraph* dg, const dm_graph_desc* gp, int64_t max_embeddings,
+                       const dm_plan_opts* opts, dm_result** out);
+
+/* Batched Algorithm 1: `n` patterns against the same resident data graph in
+ * one persistent-kernel launch (per-pattern plans, device work queue).
+ * caps may be NULL (all).  outs[i] receives pattern i's result; on error no
+ * result is returned.  Same row semantics as dm_enumerate. */
+dm_status dm_enumerate_batch(dm_datagraph* dg, int32_t n, const dm_graph_desc* gps,
+                             const int64_t* caps, const dm_plan_opts* opts, dm_result** outs);
+
+int64_t dm_result_rows(const dm_result* r);   /* rows held = min(cap, total) */
+int64_t dm_result_total(const dm_result* r);  /* all embeddings; -1 if a cap stopped counting */
+int32_t dm_result_width(const dm_result* r);  /* |V_p| */
+/* Device pointer to the row-major table (NULL when rows == 0 or in
+ * count+hash mode).  Owned by the result. */
+const int32_t* dm_result_device_data(const dm_result* r);
+/* Count+hash mode summaries: sum (mod 2^64) and XOR over rows of
+ * h(f) = mix(sum_j mix((j << 32) | f(j))), mix = SplitMix64's output step. */
+dm_status dm_result_hash(const dm_result* r, uint64_t* hash_sum, uint64_t* hash_xor);
+dm_status dm_result_copy_to_host(const dm_result* r, int32_t* dst, int64_t max_rows);
+/* Device-to-device copy of up to max_rows rows into caller memory, ordered on
+ * `hip_stream` (NULL = the context stream); synchronizes before returning. */
+dm_status dm_result_copy_to_device(const dm_result* r, int32_t* dst, int64_t max_rows,
+                                   void* hip_stream);
+
+typedef struct {
+    int32_t n_steps;          /* join-and-filter iterations (Fig. 3(c)(f)) */
+    int32_t retries;          /* re-runs after a capacity overflow */
+    int32_t chunks;           /* root-range partitions used */
+    int32_t reserved;
+    int64_t step_rows[DM_MAX_PATTERN_VERTICES]; /* rows after each step */
+    double plan_ms;           /* host decomposition time */
+    double device_ms;         /* device time of joins + sort */
+    int64_t bytes_moved;      /* algorithmic bytes: every table read once + written once */
+    /* filled when dm_plan_opts.profile = 1 (HIP events around each launch): */
+    int32_t join_launches;    /* expand-join-filter kernel launches */
+    int32_t sort_launches;
+    double join_ms;           /* summed device time of the join launches */
+    double sort_ms;           /* summed device time of the canonicalization launches */
+    int64_t join_bytes;       /* algorithmic bytes of the join launches (4 * (c_in*n_in + c_out*n_out)) */
+    int64_t sort_bytes;       /* algorithmic bytes of the sort (8 * width * rows) */
+} dm_run_stats;
+
+dm_status dm_result_stats(const dm_result* r, dm_run_stats* out);
+void dm_result_free(dm_result* r);
+
+/* Served form: a request loop that keeps the data graph resident, admits
+ * queries by predicted intermediate-table memory, and runs admitted queries
+ * in continuous batches on several streams so that their work overlaps on
+ * the device. */
+typedef struct {
+    int32_t n_streams;       /* concurrent batches in flight (default 2) */
+    int32_t max_batch;       /* patterns per batch launch (default 64) */
+    int64_t mem_budget;      /* bytes of predicted intermediates in flight (default 8 GiB) */
+    int32_t max_queue;       /* pending requests before submit returns DM_ERR_BUSY (default 65536) */
+} dm_server_opts;
+
+dm_status dm_server_start(dm_datagraph* dg, const dm_server_opts* opts, dm_server** out);
+/* Queue a pattern query (copied).  *ticket identifies it for dm_server_wait. */
+dm_status dm_server_submit(dm_server* s, const dm_graph_desc* gp, int64_t max_embeddings,
+                           uint64_t* ticket);
+/* Wait up to timeout_ms (<0 = forever) for a ticket; DM_ERR_TIMEOUT if not done.
+ * On DM_OK the caller owns *out.  A query's own failure is returned here. */
+dm_status dm_server_wait(dm_server* s, uint64_t ticket, int32_t timeout_ms, dm_result** out);
+/* Stop accepting, finish in-flight work, free the server. */
+dm_status dm_server_stop(dm_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMOTIF_H */

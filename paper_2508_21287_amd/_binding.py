@@ -1,0 +1,410 @@
+"""ctypes binding over libdmotif.so (the C ABI declared in include/dmotif.h).
+
+Argument marshalling only: every step of the enumeration runs in the HIP
+library.  PyTorch is used for streams and for device memory handed back to
+the caller (``Result.to_torch``).  Method names follow the C entry points:
+
+=======================  ==========================
+Python                   C ABI
+=======================  ==========================
+``Context(...)``         ``dm_context_create``
+``DataGraph(...)``       ``dm_datagraph_build``
+``DataGraph.enumerate``  ``dm_enumerate``
+``DataGraph.enumerate_batch``  ``dm_enumerate_batch``
+``DataGraph.estimate``   ``dm_estimate``
+``Server.submit/wait``   ``dm_server_submit/_wait``
+``plan(...)``            ``dm_plan``
+=======================  ==========================
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdmotif.so")
+
+DM_OK = 0
+STATUS = {0: "DM_OK", -1: "DM_ERR_INVALID_ARG", -2: "DM_ERR_VERTEX_RANGE", -3: "DM_ERR_PATTERN_DISCONNECTED",
+          -4: "DM_ERR_PATTERN_SELF_LOOP", -5: "DM_ERR_OUT_OF_MEMORY", -6: "DM_ERR_BUDGET_EXCEEDED",
+          -7: "DM_ERR_DEVICE", -8: "DM_ERR_CANCELLED", -9: "DM_ERR_BUSY", -10: "DM_ERR_TIMEOUT",
+          -11: "DM_ERR_INTERNAL", -12: "DM_ERR_UNSUPPORTED"}
+
+MOTIF_M3, MOTIF_M4, MOTIF_M5, MOTIF_M6 = 1 << 0, 1 << 1, 1 << 2, 1 << 3
+MOTIF_C4, MOTIF_C6, MOTIF_C12 = 1 << 4, 1 << 5, 1 << 6
+MOTIF_ALL, MOTIF_AUTO, MOTIF_M2_ONLY = 0x7F, 0, 0x80000000
+MOTIF_NAMES = ["M2", "M3", "M4", "M5", "M6", "M4-O", "M6-O", "M12-O"]
+MAX_PATTERN_VERTICES = 128
+
+OUT_TABLE, OUT_COUNT_HASH = 0, 1
+
+
+class DMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_edges", C.c_int64), ("edges", C.POINTER(C.c_int32))]
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("motif_mask", C.c_uint32), ("block_threads", C.c_int32), ("output_mode", C.c_int32),
+                ("sync_each_step", C.c_int32), ("mem_budget", C.c_int64), ("profile", C.c_int32),
+                ("reserved_", C.c_int32)]
+
+
+class DataGraphInfo(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_directed_edges", C.c_int64), ("max_degree", C.c_int32),
+                ("has_bitmap", C.c_int32), ("motif_mask", C.c_uint32), ("motif_rows", C.c_int64 * 8),
+                ("build_ms", C.c_double)]
+
+
+class RunStats(C.Structure):
+    _fields_ = [("n_steps", C.c_int32), ("retries", C.c_int32), ("chunks", C.c_int32), ("reserved", C.c_int32),
+                ("step_rows", C.c_int64 * MAX_PATTERN_VERTICES), ("plan_ms", C.c_double),
+                ("device_ms", C.c_double), ("bytes_moved", C.c_int64), ("join_launches", C.c_int32),
+                ("sort_launches", C.c_int32), ("join_ms", C.c_double), ("sort_ms", C.c_double),
+                ("join_bytes", C.c_int64), ("sort_bytes", C.c_int64)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("max_batch", C.c_int32), ("mem_budget", C.c_int64),
+                ("max_queue", C.c_int32)]
+
+
+_lock = threading.Lock()
+_LIB = None
+
+# Every symbol include/dmotif.h declares (checked by the CPU test suite).
+EXPORTS = [
+    "dm_version", "dm_last_error", "dm_context_create", "dm_context_destroy", "dm_datagraph_build",
+    "dm_datagraph_free", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
+    "dm_estimate", "dm_enumerate", "dm_enumerate_batch", "dm_result_rows", "dm_result_total",
+    "dm_result_width", "dm_result_device_data", "dm_result_hash", "dm_result_copy_to_host",
+    "dm_result_copy_to_device", "dm_result_stats", "dm_result_free", "dm_server_start", "dm_server_submit",
+    "dm_server_wait", "dm_server_stop",
+]
+
+
+def lib() -> C.CDLL:
+    """Load libdmotif.so.  Raises if the HIP library has not been built: there
+    is no fallback path."""
+    global _LIB
+    with _lock:
+        if _LIB is not None:
+            return _LIB
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_21287_amd._build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32p = C.c_void_p, C.POINTER(C.c_int32)
+        sig = {
+            "dm_version": (C.c_char_p, []),
+            "dm_last_error": (C.c_char_p, []),
+            "dm_context_create": (C.c_int, [C.c_int32, vp, C.POINTER(vp)]),
+            "dm_context_destroy": (None, [vp]),
+            "dm_datagraph_build": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_uint32, C.POINTER(vp)]),
+            "dm_datagraph_free": (None, [vp]),
+            "dm_datagraph_query": (C.c_int, [vp, C.POINTER(DataGraphInfo)]),
+            "dm_datagraph_copy_csr": (C.c_int, [vp, i32p, i32p]),
+            "dm_datagraph_copy_motif": (C.c_int, [vp, C.c_int32, C.c_int32, i32p, C.c_int64,
+                                                  C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+            "dm_plan": (C.c_int, [C.POINTER(GraphDesc), C.c_uint32, i32p, C.c_int32, i32p]),
+            "dm_estimate": (C.c_int, [vp, C.POINTER(GraphDesc), C.POINTER(PlanOpts), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]),
+            "dm_enumerate": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_int64, C.POINTER(PlanOpts), C.POINTER(vp)]),
+            "dm_enumerate_batch": (C.c_int, [vp, C.c_int32, C.POINTER(GraphDesc), C.POINTER(C.c_int64),
+                                             C.POINTER(PlanOpts), C.POINTER(vp)]),
+            "dm_result_rows": (C.c_int64, [vp]),
+            "dm_result_total": (C.c_int64, [vp]),
+            "dm_result_width": (C.c_int32, [vp]),
+            "dm_result_device_data": (vp, [vp]),
+            "dm_result_hash": (C.c_int, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+            "dm_result_copy_to_host": (C.c_int, [vp, i32p, C.c_int64]),
+            "dm_result_copy_to_device": (C.c_int, [vp, vp, C.c_int64, vp]),
+            "dm_result_stats": (C.c_int, [vp, C.POINTER(RunStats)]),
+            "dm_result_free": (None, [vp]),
+            "dm_server_start": (C.c_int, [vp, C.POINTER(ServerOpts), C.POINTER(vp)]),
+            "dm_server_submit": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_int64, C.POINTER(C.c_uint64)]),
+            "dm_server_wait": (C.c_int, [vp, C.c_uint64, C.c_int32, C.POINTER(vp)]),
+            "dm_server_stop": (C.c_int, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+        return L
+
+
+def _check(code: int):
+    if code != DM_OK:
+        msg = lib().dm_last_error()
+        raise DMError(code, msg.decode() if msg else "")
+
+
+class _Graph:
+    """Keeps a GraphDesc and the int32 array it points to alive together."""
+
+    def __init__(self, n: int, edges):
+        self.arr = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        self.desc = GraphDesc(int(n), int(self.arr.shape[0]), self.arr.ctypes.data_as(C.POINTER(C.c_int32)))
+
+
+def _opts(motif_mask=0, block=0, mode=OUT_TABLE, sync_each_step=False, mem_budget=0,
+          profile=False) -> PlanOpts:
+    return PlanOpts(int(motif_mask) & 0xFFFFFFFF, int(block), int(mode), int(bool(sync_each_step)),
+                    int(mem_budget), int(bool(profile)), 0)
+
+
+def _torch_stream(device: int):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    except Exception:
+        pass
+    return C.c_void_p(0)
+
+
+class Context:
+    """``dm_context_create``: a device plus the HIP stream all work is ordered
+    on (default: torch's current stream on that device)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        self.device = device
+        if stream is None:
+            s = _torch_stream(device)
+        elif hasattr(stream, "cuda_stream"):
+            s = C.c_void_p(stream.cuda_stream)
+        else:
+            s = C.c_void_p(int(stream))
+        self._h = C.c_void_p()
+        _check(L.dm_context_create(device, s, C.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().dm_context_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def datagraph(self, n: int, edges, motif_mask: int = MOTIF_AUTO) -> "DataGraph":
+        return DataGraph(self, n, edges, motif_mask)
+
+
+class Result:
+    """An embedding table on the device (``dm_result``)."""
+
+    def __init__(self, h):
+        self._h = h
+
+    @property
+    def rows(self) -> int:
+        return int(lib().dm_result_rows(self._h))
+
+    @property
+    def total(self) -> int:
+        return int(lib().dm_result_total(self._h))
+
+    @property
+    def width(self) -> int:
+        return int(lib().dm_result_width(self._h))
+
+    @property
+    def device_ptr(self) -> int:
+        return int(lib().dm_result_device_data(self._h) or 0)
+
+    def to_numpy(self, max_rows: int | None = None) -> np.ndarray:
+        n = self.rows if max_rows is None else min(max_rows, self.rows)
+        out = np.empty((n, self.width), dtype=np.int32)
+        if n:
+            _check(lib().dm_result_copy_to_host(self._h, out.ctypes.data_as(C.POINTER(C.c_int32)), n))
+        return out
+
+    def to_torch(self, device: int | None = None):
+        """Device-to-device copy into a torch int32 tensor [rows, width]."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        t = torch.empty((self.rows, self.width), dtype=torch.int32, device=dev)
+        if self.rows:
+            s = torch.cuda.current_stream(dev).cuda_stream
+            _check(lib().dm_result_copy_to_device(self._h, C.c_void_p(t.data_ptr()), self.rows, C.c_void_p(s)))
+        return t
+
+    def hash(self) -> tuple[int, int]:
+        hs, hx = C.c_uint64(), C.c_uint64()
+        _check(lib().dm_result_hash(self._h, C.byref(hs), C.byref(hx)))
+        return hs.value, hx.value
+
+    def stats(self) -> dict:
+        st = RunStats()
+        _check(lib().dm_result_stats(self._h, C.byref(st)))
+        n = st.n_steps
+        return {"n_steps": n, "retries": st.retries, "chunks": st.chunks,
+                "step_rows": [int(x) for x in st.step_rows[:max(n, 1)]], "plan_ms": st.plan_ms,
+                "device_ms": st.device_ms, "bytes_moved": int(st.bytes_moved),
+                "join_launches": st.join_launches, "sort_launches": st.sort_launches, "join_ms": st.join_ms,
+                "sort_ms": st.sort_ms, "join_bytes": int(st.join_bytes), "sort_bytes": int(st.sort_bytes)}
+
+    def free(self):
+        if self._h:
+            lib().dm_result_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.free()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class DataGraph:
+    """``dm_datagraph_build``: normalized data graph + motif tables, resident."""
+
+    def __init__(self, ctx: Context, n: int, edges, motif_mask: int = MOTIF_AUTO):
+        self.ctx = ctx
+        g = _Graph(n, edges)
+        self._h = C.c_void_p()
+        _check(lib().dm_datagraph_build(ctx.handle, C.byref(g.desc), int(motif_mask) & 0xFFFFFFFF,
+                                        C.byref(self._h)))
+
+    def info(self) -> dict:
+        i = DataGraphInfo()
+        _check(lib().dm_datagraph_query(self._h, C.byref(i)))
+        return {"n_vertices": i.n_vertices, "n_directed_edges": i.n_directed_edges,
+                "max_degree": i.max_degree, "has_bitmap": bool(i.has_bitmap), "motif_mask": i.motif_mask,
+                "motif_rows": {MOTIF_NAMES[m]: int(i.motif_rows[m]) for m in range(8)},
+                "build_ms": i.build_ms}
+
+    def csr(self):
+        info = self.info()
+        rp = np.zeros(info["n_vertices"] + 1, np.int32)
+        col = np.zeros(max(info["n_directed_edges"], 1), np.int32)
+        _check(lib().dm_datagraph_copy_csr(self._h, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                                           col.ctypes.data_as(C.POINTER(C.c_int32))))
+        return rp, col[:info["n_directed_edges"]]
+
+    def motif_table(self, motif: int, key_pos: int = 0) -> np.ndarray:
+        rows, width = C.c_int64(), C.c_int32()
+        _check(lib().dm_datagraph_copy_motif(self._h, motif, key_pos, None, 0, C.byref(rows), C.byref(width)))
+        out = np.zeros((rows.value, width.value), np.int32)
+        if rows.value:
+            _check(lib().dm_datagraph_copy_motif(self._h, motif, key_pos,
+                                                 out.ctypes.data_as(C.POINTER(C.c_int32)), rows.value,
+                                                 C.byref(rows), C.byref(width)))
+        return out
+
+    def estimate(self, n: int, edges, motif_mask: int = 0) -> tuple[int, int]:
+        g = _Graph(n, edges)
+        o = _opts(motif_mask)
+        peak, rows = C.c_int64(), C.c_int64()
+        _check(lib().dm_estimate(self._h, C.byref(g.desc), C.byref(o), C.byref(peak), C.byref(rows)))
+        return peak.value, rows.value
+
+    def enumerate(self, n: int, edges, cap: int = -1, **opts) -> Result:
+        g = _Graph(n, edges)
+        o = _opts(**opts)
+        h = C.c_void_p()
+        _check(lib().dm_enumerate(self._h, C.byref(g.desc), int(cap), C.byref(o), C.byref(h)))
+        return Result(h)
+
+    def enumerate_batch(self, patterns, caps=None, **opts) -> list[Result]:
+        gs = [_Graph(n, e) for n, e in patterns]
+        arr = (GraphDesc * len(gs))(*[g.desc for g in gs])
+        capv = None
+        if caps is not None:
+            capv = (C.c_int64 * len(gs))(*[int(c) for c in caps])
+        outs = (C.c_void_p * len(gs))()
+        o = _opts(**opts)
+        _check(lib().dm_enumerate_batch(self._h, len(gs), arr, capv, C.byref(o), outs))
+        return [Result(C.c_void_p(outs[i])) for i in range(len(gs))]
+
+    def free(self):
+        if self._h:
+            lib().dm_datagraph_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """``dm_server_*``: continuous batching over one resident data graph."""
+
+    def __init__(self, dg: DataGraph, n_streams: int = 2, max_batch: int = 64, mem_budget: int = 0,
+                 max_queue: int = 0):
+        self.dg = dg
+        o = ServerOpts(n_streams, max_batch, mem_budget, max_queue)
+        self._h = C.c_void_p()
+        _check(lib().dm_server_start(dg._h, C.byref(o), C.byref(self._h)))
+
+    def submit(self, n: int, edges, cap: int = -1) -> int:
+        g = _Graph(n, edges)
+        t = C.c_uint64()
+        _check(lib().dm_server_submit(self._h, C.byref(g.desc), int(cap), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> Result:
+        h = C.c_void_p()
+        _check(lib().dm_server_wait(self._h, C.c_uint64(ticket), int(timeout_ms), C.byref(h)))
+        return Result(h)
+
+    def stop(self):
+        if self._h:
+            _check(lib().dm_server_stop(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+
+def plan(n: int, edges, motif_mask: int = MOTIF_ALL) -> dict:
+    """``dm_plan``: the host decomposition of a pattern (no device needed)."""
+    g = _Graph(n, edges)
+    need = C.c_int32()
+    rc = lib().dm_plan(C.byref(g.desc), int(motif_mask) & 0xFFFFFFFF, None, 0, C.byref(need))
+    if need.value <= 0:
+        _check(rc)
+    buf = np.zeros(need.value, np.int32)
+    _check(lib().dm_plan(C.byref(g.desc), int(motif_mask) & 0xFFFFFFFF,
+                         buf.ctypes.data_as(C.POINTER(C.c_int32)), need.value, C.byref(need)))
+    b = buf.tolist()
+    k, ns = b[0], b[1]
+    col_of = b[2:2 + k]
+    i = 2 + k
+    steps = []
+    for _ in range(ns):
+        st = {"motif": b[i], "key_pos": b[i + 1], "key_col": b[i + 2], "c_in": b[i + 3]}
+        i += 4
+        nn = b[i]; st["new_pos"] = b[i + 1:i + 1 + nn]; i += 1 + nn
+        ne = b[i]; st["eq"] = [(b[i + 1 + 2 * j], b[i + 2 + 2 * j]) for j in range(ne)]; i += 1 + 2 * ne
+        nd = b[i]; st["edges"] = [(b[i + 1 + 2 * j], b[i + 2 + 2 * j]) for j in range(nd)]; i += 1 + 2 * nd
+        sl = b[i]; st["slice"] = b[i + 1:i + 1 + sl]; i += 1 + sl
+        steps.append(st)
+    return {"k": k, "col_of": col_of, "steps": steps}

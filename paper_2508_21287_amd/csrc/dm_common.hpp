@@ -1,0 +1,113 @@
+// Internal definitions shared by the planner, the runtime and the kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dmotif.h"
+
+namespace dm {
+
+constexpr int kMaxMotif = DM_MAX_MOTIF_VERTICES;  // vertices in the largest motif (C12)
+constexpr int kMaxCols = DM_MAX_PATTERN_VERTICES; // columns of a partial-embedding table
+constexpr int kMaxEdgeChecks = 24;                // explicit edge checks per join step
+constexpr int kMaxSteps = DM_MAX_PATTERN_VERTICES;
+constexpr int kNumMotifs = 8;
+
+// Motif catalogue (Sec. III-A "Motifs": M_i = path of i vertices, -O = cycle).
+// Index order matches dm_datagraph_info.motif_rows.
+enum MotifIndex { MOT_P2 = 0, MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12 };
+
+struct MotifInfo {
+    int size;
+    bool cycle;
+    uint32_t bit;  // DM_MOTIF_* bit (0 for M2: always present)
+    const char* name;
+};
+
+inline const MotifInfo& motif_info(int m) {
+    static const MotifInfo kInfo[kNumMotifs] = {
+        {2, false, 0u, "M2"},           {3, false, DM_MOTIF_M3, "M3"},
+        {4, false, DM_MOTIF_M4, "M4"},  {5, false, DM_MOTIF_M5, "M5"},
+        {6, false, DM_MOTIF_M6, "M6"},  {4, true, DM_MOTIF_C4, "M4-O"},
+        {6, true, DM_MOTIF_C6, "M6-O"}, {12, true, DM_MOTIF_C12, "M12-O"}};
+    return kInfo[m];
+}
+
+// Distinct key positions up to the motif's symmetry: a path reads the same
+// reversed, a cycle the same rotated.
+inline int motif_key_positions(int m) {
+    const MotifInfo& mi = motif_info(m);
+    return mi.cycle ? 1 : (mi.size + 1) / 2;
+}
+
+// One join-and-filter iteration (Algorithm 1 body) in table-column space.
+// Input table R has c_in columns; the step joins R with the motif table
+// Res(M) indexed on motif position key_pos by the value in R column key_col,
+// requires R[eq_col[i]] == M[eq_pos[i]] (further join keys), appends the
+// motif positions new_pos[] as new columns c_in.., rejects rows where a new
+// value repeats any value of the row (injectivity filter), and checks
+// adjacency for each (edge_a, edge_b) column pair (pattern edges not carried
+// by the motif).  motif == -1: filter only (no expansion).
+struct StepDesc {
+    int32_t motif;
+    int32_t key_pos;
+    int32_t key_col;
+    int32_t c_in;
+    int32_t n_new;
+    int32_t n_eq;
+    int32_t n_edge;
+    int32_t pad_;
+    int8_t new_pos[kMaxMotif];
+    int8_t eq_col[kMaxMotif];
+    int8_t eq_pos[kMaxMotif];
+    uint8_t edge_a[kMaxEdgeChecks];
+    uint8_t edge_b[kMaxEdgeChecks];
+};
+
+struct PlanStep {
+    StepDesc d;
+    int32_t slice_len = 0;
+    int32_t slice[kMaxMotif];  // pattern vertices in motif position order
+    double est_rows = 0;       // predicted rows after this step
+};
+
+struct Plan {
+    int32_t k = 0;     // pattern vertices
+    int32_t root = 0;  // pattern vertex held by table column 0
+    std::vector<PlanStep> steps;
+    int32_t col_of[kMaxCols];  // pattern vertex -> table column
+    int32_t pv_of[kMaxCols];   // table column -> pattern vertex
+    double est_peak_rows_cols = 0;  // max over steps of rows*cols (in + out)
+    double est_final_rows = 0;
+};
+
+struct NormPattern {
+    int32_t k = 0;
+    std::vector<std::pair<int32_t, int32_t>> edges;  // u < v, unique
+};
+
+// Validate and normalize a pattern (ids, self-loops, connectivity, merge repeats).
+dm_status normalize_pattern(const dm_graph_desc* gp, NormPattern* out, std::string* err);
+
+// Motif-table statistics used by the estimator (rows per motif; 0 = absent).
+struct MotifStats {
+    int32_t n_vertices = 0;
+    double rows[kNumMotifs] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double avg_degree = 0;
+};
+
+// Decompose a pattern into motif slices (Sec. III-C).  `avail` = motifs that
+// may be used (bit per MotifIndex; M2 always allowed).  stats may be null
+// (then estimates are left at 0).
+dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail_motif_bits,
+                       const MotifStats* stats, Plan* out, std::string* err);
+
+// Serialize a plan in the dm_plan() int32 format.
+std::vector<int32_t> serialize_plan(const Plan& plan);
+
+// Map DM_MOTIF_* mask to a bitset over MotifIndex (bit 0 = M2 always set).
+uint32_t motif_bits_from_mask(uint32_t dm_mask);
+
+}  // namespace dm

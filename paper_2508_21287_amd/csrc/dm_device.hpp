@@ -1,0 +1,122 @@
+// Device-side argument blocks and the host-callable kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dm_common.hpp"
+
+namespace dm {
+
+// A motif table Res(M) keyed on one motif position: SoA columns in motif
+// position order, rows grouped by the key column in ascending key order, and
+// offs[v]..offs[v+1] = the rows whose key is v (direct-address index).
+struct TableDev {
+    const int32_t* col[kMaxMotif];
+    const int32_t* offs;
+    int64_t rows;
+    int32_t size;
+    int32_t pad_;
+};
+
+// Normalized data graph: CSR (each list ascending) + optional adjacency bitmap
+// (bit v of row u set iff {u, v} is an edge; words_per_row 32-bit words/row).
+struct GraphDev {
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const uint32_t* bitmap;
+    int32_t n;
+    int32_t words_per_row;
+};
+
+enum { EJF_WRITE = 0, EJF_HASH = 1 };
+
+// One join-filter launch.  Input table: `in` SoA with column stride
+// in_stride and at most in_cap rows, row count *n_in (clamped to in_cap);
+// in == nullptr means the identity table (one column, values id_begin +
+// row, id_count rows).  Output: SoA with stride out_stride, at most out_cap
+// rows written; *n_out receives the exact count even past out_cap, and
+// *overflow is set when out_cap was too small.  Output rows keep the order of
+// their input rows (order-preserving compaction via decoupled look-back over
+// tiles claimed in ticket order).
+struct EjfArgs {
+    StepDesc st;
+    TableDev tbl;
+    GraphDev g;
+    const int32_t* in;
+    int64_t in_stride;
+    int64_t in_cap;
+    const int64_t* n_in;
+    int32_t id_begin;
+    int32_t id_count;
+    int32_t* out;
+    int64_t out_stride;
+    int64_t out_cap;
+    int64_t* n_out;
+    int32_t* overflow;
+    uint64_t* status;     // look-back words, >= tiles of this launch
+    uint64_t* ticket;     // tile counter, zero before the launch
+    uint32_t epoch;       // tags this launch's look-back words
+    int32_t mode;         // EJF_WRITE or EJF_HASH
+    uint64_t* hash_acc;   // EJF_HASH: [count, sum, xor]
+    uint8_t pv[kMaxCols]; // EJF_HASH: pattern vertex of each output column
+};
+
+// Canonicalization: permute columns to pattern-vertex order, sort rows of
+// each root segment (rows sharing column 0) lexicographically, write a
+// row-major table.  Segments are processed per root vertex in
+// [v_begin, v_end) or, when list != nullptr, for the vertices in list.
+struct SortArgs {
+    const int32_t* in;
+    int64_t in_stride;
+    int64_t in_cap;
+    const int64_t* n_in;
+    int32_t k;
+    int32_t kp;  // LDS row stride (k rounded up to odd)
+    uint8_t perm[kMaxCols];  // pattern vertex j -> input column
+    int32_t v_begin;
+    int32_t v_end;
+    const int32_t* list;
+    const int32_t* list_n;
+    int32_t* spill;    // segments too big for this tier
+    int32_t* spill_n;
+    int32_t lds_rows;  // rows that fit this tier's LDS
+    int32_t* out;
+    int64_t out_rows;  // rows [0, out_rows) of the sorted table are written
+    uint32_t* scratch_idx;  // global tier: 2 * rows index scratch
+    int32_t* dup_count;
+};
+
+constexpr int kEpochBits = 14;
+constexpr uint32_t kEpochs = 1u << kEpochBits;
+
+// ---- launchers (kernels.hip) ----
+hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s);
+hipError_t launch_sort_lds(const SortArgs& a, int grid, int lds_bytes, hipStream_t s);
+hipError_t launch_sort_global(const SortArgs& a, int grid, hipStream_t s);
+int sort_max_lds_bytes();
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_iota_i32(int32_t* p, int32_t start, int64_t n, hipStream_t s);
+hipError_t launch_offsets(const int32_t* key, const int64_t* n_rows, int64_t rows_cap, int32_t n_vertices,
+                          int32_t* offs, hipStream_t s);
+hipError_t launch_gather_cols(const int32_t* in, int64_t in_stride, const int64_t* n_rows, int64_t cap,
+                              const int32_t* colmap, int32_t ncols, int32_t* out, int64_t out_stride,
+                              hipStream_t s);
+
+// graph ingest
+hipError_t launch_ingest_count(const int32_t* edges, int64_t m, int32_t n, int32_t* deg, int32_t* err,
+                               hipStream_t s);
+hipError_t launch_scan_i32(const int32_t* in, int32_t* out_excl, int64_t n, int64_t* total,
+                           uint64_t* status, uint64_t* ticket, hipStream_t s);
+hipError_t launch_ingest_scatter(const int32_t* edges, int64_t m, const int32_t* ptr, int32_t* cursor,
+                                 int32_t* tmp, hipStream_t s);
+hipError_t launch_ingest_sort_small(const int32_t* ptr, int32_t* tmp, int32_t n, int32_t* udeg,
+                                    int32_t* big, int32_t* big_n, hipStream_t s);
+hipError_t launch_ingest_sort_big(const int32_t* ptr, int32_t* tmp, int32_t* udeg, const int32_t* big,
+                                  const int32_t* big_n, int32_t* err, hipStream_t s);
+hipError_t launch_ingest_compact(const int32_t* tmp_ptr, const int32_t* tmp, const int32_t* row_ptr,
+                                 int32_t n, int32_t* col, int32_t* src, int32_t* max_deg, hipStream_t s);
+hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, int64_t nnz, int32_t wpr,
+                             uint32_t* bitmap, hipStream_t s);
+
+}  // namespace dm

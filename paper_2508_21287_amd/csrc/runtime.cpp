@@ -1,0 +1,952 @@
+// Host runtime: contexts, the resident data graph (Algorithm 2), the plan
+// executor (Algorithm 1) and the C ABI entry points of libdmotif.so.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace dm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+dm_status fail(dm_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+dm_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? DM_ERR_OUT_OF_MEMORY : DM_ERR_DEVICE;
+}
+
+dm_status dev_alloc(void** p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return hip_fail(e, "hipMallocAsync");
+    }
+    return DM_OK;
+}
+
+void dev_free(void* p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// ------------------------------------------------------------- workspace
+
+dm_status Workspace::init(hipStream_t s) {
+    stream = s;
+    DM_TRY(dev_alloc((void**)&tickets, sizeof(uint64_t) * kEpochs, s));
+    DM_HIP(launch_fill_u64(tickets, 0, kEpochs, s));
+    DM_TRY(dev_alloc((void**)&ctrl_d, sizeof(Control), s));
+    DM_HIP(hipHostMalloc((void**)&ctrl_h, sizeof(Control), hipHostMallocDefault));
+    std::memset(ctrl_h, 0, sizeof(Control));
+    DM_HIP(hipEventCreate(&ev[0]));
+    DM_HIP(hipEventCreate(&ev[1]));
+    epoch = 0;
+    return DM_OK;
+}
+
+void Workspace::release() {
+    for (int i = 0; i < 2; i++) dev_free(buf[i], stream), buf[i] = nullptr, buf_elems[i] = 0;
+    dev_free(status, stream);
+    dev_free(tickets, stream);
+    dev_free(ctrl_d, stream);
+    dev_free(spill, stream);
+    dev_free(sort_scratch, stream);
+    status = nullptr;
+    tickets = nullptr;
+    ctrl_d = nullptr;
+    spill = nullptr;
+    sort_scratch = nullptr;
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (ctrl_h) (void)hipHostFree(ctrl_h);
+    ctrl_h = nullptr;
+    for (int i = 0; i < 2; i++)
+        if (ev[i]) (void)hipEventDestroy(ev[i]), ev[i] = nullptr;
+    for (auto e : prof) (void)hipEventDestroy(e);
+    prof.clear();
+}
+
+dm_status Workspace::ensure_buf(int i, int64_t elems) {
+    if (buf_elems[i] >= elems) return DM_OK;
+    dev_free(buf[i], stream);
+    buf[i] = nullptr;
+    buf_elems[i] = 0;
+    int64_t e = std::max<int64_t>(elems, 1 << 16);
+    DM_TRY(dev_alloc((void**)&buf[i], sizeof(int32_t) * (size_t)e, stream));
+    buf_elems[i] = e;
+    return DM_OK;
+}
+
+dm_status Workspace::ensure_status(int64_t words) {
+    if (status_cap >= words) return DM_OK;
+    dev_free(status, stream);
+    status = nullptr;
+    int64_t w = std::max<int64_t>(words, 1 << 14);
+    DM_TRY(dev_alloc((void**)&status, sizeof(uint64_t) * (size_t)w, stream));
+    DM_HIP(launch_fill_u64(status, 0, w, stream));
+    status_cap = w;
+    return DM_OK;
+}
+
+dm_status Workspace::ensure_spill(int64_t n) {
+    if (spill_cap >= n) return DM_OK;
+    dev_free(spill, stream);
+    spill = nullptr;
+    int64_t c = std::max<int64_t>(n, 1024);
+    DM_TRY(dev_alloc((void**)&spill, sizeof(int32_t) * 2 * (size_t)c, stream));
+    spill_cap = c;
+    return DM_OK;
+}
+
+dm_status Workspace::ensure_sort_scratch(int64_t elems) {
+    if (sort_scratch_elems >= elems) return DM_OK;
+    dev_free(sort_scratch, stream);
+    sort_scratch = nullptr;
+    int64_t c = std::max<int64_t>(elems, 1 << 16);
+    DM_TRY(dev_alloc((void**)&sort_scratch, sizeof(uint32_t) * (size_t)c, stream));
+    sort_scratch_elems = c;
+    return DM_OK;
+}
+
+dm_status Workspace::next_epoch(uint32_t* e) {
+    epoch++;
+    if (epoch >= kEpochs) {
+        // all epochs used: clear every look-back word and ticket, start over
+        DM_HIP(launch_fill_u64(status, 0, status_cap, stream));
+        DM_HIP(launch_fill_u64(tickets, 0, kEpochs, stream));
+        epoch = 1;
+    }
+    *e = epoch;
+    return DM_OK;
+}
+
+// ------------------------------------------------------------- plan execution
+
+static int lds_rows_for(int bytes, int kp) {
+    int r = bytes / (4 * (kp + 1));
+    int p = 1;
+    while (p * 2 <= r) p *= 2;
+    return r >= 1 ? p : 0;
+}
+
+static int auto_block(double est_rows) { return est_rows < 65536.0 ? 64 : 256; }
+
+static int ejf_grid(int64_t in_cap, double est_in, int block) {
+    int64_t tiles_cap = (in_cap + block - 1) / block;
+    int64_t g = (int64_t)std::ceil(2.0 * std::max(est_in, 1.0) / block);
+    g = std::max<int64_t>(g, 64);
+    g = std::min<int64_t>(g, 2048);
+    g = std::min<int64_t>(g, std::max<int64_t>(tiles_cap, 1));
+    return (int)std::max<int64_t>(g, 1);
+}
+
+dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const Plan& plan,
+                   const RunOptions& opt, RunOutput* out) {
+    (void)ctx;
+    hipStream_t s = ws.stream;
+    const int k = plan.k;
+    const int32_t v0 = 0, v1 = dg->n;
+    std::vector<StepDesc> steps;
+    std::vector<double> est;
+    for (auto& ps : plan.steps) {
+        steps.push_back(ps.d);
+        est.push_back(ps.est_rows);
+    }
+    if (steps.empty()) {  // 1-vertex pattern: a no-op filter materializes the identity table
+        StepDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.motif = -1;
+        d.c_in = 1;
+        steps.push_back(d);
+        est.push_back((double)dg->n);
+    }
+    const int nsteps = (int)steps.size();
+    if (nsteps > kMaxSteps) return fail(DM_ERR_UNSUPPORTED, "plan has too many steps");
+    const bool hash_mode = opt.mode == DM_OUT_COUNT_HASH;
+
+    double est_max = (double)dg->n;
+    for (double e : est) est_max = std::max(est_max, e);
+    int64_t budget = opt.mem_budget > 0 ? opt.mem_budget : (int64_t)48 << 30;
+    int64_t budget_rows = std::max<int64_t>(budget / (int64_t)(8 * k), 1 << 16);
+    int64_t cap0 = (int64_t)std::min<double>(est_max * 4.0 + 4096.0, (double)budget_rows);
+    cap0 = std::max<int64_t>(cap0, 1 << 14);
+    const int block = opt.block > 0 ? opt.block : auto_block(est_max);
+
+    // capacity (rows) of each ping-pong buffer; stride of a table = its capacity
+    int64_t cap[2] = {cap0, cap0};
+    bool sync_mode = opt.sync_each_step;
+    RunOutput o;
+    int retries = 0;
+    int32_t* result = nullptr;
+
+    if (opt.profile) {
+        while (ws.prof.size() < (size_t)(2 * nsteps + 2)) {
+            hipEvent_t e;
+            DM_HIP(hipEventCreate(&e));
+            ws.prof.push_back(e);
+        }
+    }
+
+    for (;;) {
+        for (int b = 0; b < 2; b++) DM_TRY(ws.ensure_buf(b, cap[b] * k));
+        for (int b = 0; b < 2; b++) cap[b] = ws.buf_elems[b] / k;
+        int64_t maxcap = std::max<int64_t>(std::max(cap[0], cap[1]), (int64_t)dg->n);
+        DM_TRY(ws.ensure_status(maxcap / 64 + 2));
+        DM_HIP(launch_fill_u64((uint64_t*)ws.ctrl_d, 0, sizeof(Control) / 8, s));
+        DM_HIP(hipEventRecord(ws.ev[0], s));
+        bool redo = false;
+        for (int i = 0; i < nsteps; i++) {
+            const int ib = (i - 1) & 1, ob = i & 1;
+            EjfArgs a;
+            std::memset(&a, 0, sizeof a);
+            a.st = steps[i];
+            if (a.st.motif >= 0) a.tbl = dg->table_dev(a.st.motif, a.st.key_pos);
+            a.g = dg->graph_dev();
+            a.in = i == 0 ? nullptr : ws.buf[ib];
+            a.in_stride = i == 0 ? 0 : cap[ib];
+            a.in_cap = i == 0 ? 0 : cap[ib];
+            a.n_in = &ws.ctrl_d->counts[i];
+            a.id_begin = v0;
+            a.id_count = v1 - v0;
+            a.out = ws.buf[ob];
+            a.out_stride = cap[ob];
+            a.out_cap = cap[ob];
+            a.n_out = &ws.ctrl_d->counts[i + 1];
+            a.overflow = &ws.ctrl_d->overflow[i];
+            a.status = ws.status;
+            DM_TRY(ws.next_epoch(&a.epoch));
+            a.ticket = ws.tickets + a.epoch;
+            const bool last = i == nsteps - 1;
+            a.mode = (last && hash_mode) ? EJF_HASH : EJF_WRITE;
+            a.hash_acc = ws.ctrl_d->hash;
+            for (int c = 0; c < k; c++) a.pv[c] = (uint8_t)std::max(plan.pv_of[c], 0);
+            const double est_in = i == 0 ? (double)(v1 - v0) : est[i - 1];
+            const int64_t in_cap = i == 0 ? (int64_t)(v1 - v0) : cap[ib];
+            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * i], s));
+            DM_HIP(launch_ejf(a, block, ejf_grid(in_cap, est_in, block), s));
+            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * i + 1], s));
+            if (sync_mode && !(last && hash_mode)) {
+                DM_HIP(hipMemcpyAsync(ws.ctrl_h, ws.ctrl_d, sizeof(Control), hipMemcpyDeviceToHost, s));
+                DM_HIP(hipStreamSynchronize(s));
+                const int64_t need = ws.ctrl_h->counts[i + 1];
+                if (need > cap[ob]) {
+                    // grow the output buffer only (the input stays intact) and redo
+                    if (need > budget_rows)
+                        return fail(DM_ERR_BUDGET_EXCEEDED, "intermediate table of " + std::to_string(need) +
+                                                                " rows exceeds the memory budget");
+                    int64_t nc = need + need / 8 + 1024;
+                    dev_free(ws.buf[ob], s);
+                    ws.buf[ob] = nullptr;
+                    ws.buf_elems[ob] = 0;
+                    DM_TRY(ws.ensure_buf(ob, nc * k));
+                    cap[ob] = ws.buf_elems[ob] / k;
+                    DM_TRY(ws.ensure_status(cap[ob] / 64 + 2));
+                    DM_HIP(launch_fill_i32(&ws.ctrl_d->overflow[i], 0, 1, s));
+                    retries++;
+                    i--;  // rerun this step
+                    continue;
+                }
+            }
+        }
+        const int lb = (nsteps - 1) & 1;
+        if (!hash_mode && opt.sort) {
+            // canonicalize into a row-major table sized by the last buffer's capacity
+            int64_t rows_cap = cap[lb];
+            int64_t out_rows = opt.cap >= 0 ? std::min<int64_t>(opt.cap, rows_cap) : rows_cap;
+            dev_free(result, s);
+            result = nullptr;
+            DM_TRY(dev_alloc((void**)&result, sizeof(int32_t) * (size_t)std::max<int64_t>(out_rows * k, 1), s));
+            DM_TRY(ws.ensure_spill(dg->n + 1));
+            DM_TRY(ws.ensure_sort_scratch(2 * rows_cap + 2));
+            SortArgs sa;
+            std::memset(&sa, 0, sizeof sa);
+            sa.in = ws.buf[lb];
+            sa.in_stride = cap[lb];
+            sa.in_cap = cap[lb];
+            sa.n_in = &ws.ctrl_d->counts[nsteps];
+            sa.k = k;
+            sa.kp = (k % 2 == 0) ? k + 1 : k;
+            for (int j = 0; j < k; j++) sa.perm[j] = (uint8_t)plan.col_of[j];
+            sa.v_begin = v0;
+            sa.v_end = v1;
+            sa.out = result;
+            sa.out_rows = out_rows;
+            sa.scratch_idx = ws.sort_scratch;
+            sa.dup_count = &ws.ctrl_d->dup;
+            // tier 1: small LDS tiles (many workgroups per CU)
+            const int b1 = 16 * 1024;
+            sa.lds_rows = lds_rows_for(b1, sa.kp);
+            sa.list = nullptr;
+            sa.spill = ws.spill;
+            sa.spill_n = &ws.ctrl_d->spill_n[0];
+            int lds1 = 4 * (sa.lds_rows * sa.kp + sa.lds_rows);
+            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps], s));
+            DM_HIP(launch_sort_lds(sa, std::min(std::max(v1 - v0, 1), 4096), lds1, s));
+            // tier 2: the whole LDS of a CU
+            const int b2 = ctx->sort_lds_max;
+            sa.lds_rows = lds_rows_for(b2, sa.kp);
+            sa.list = ws.spill;
+            sa.list_n = &ws.ctrl_d->spill_n[0];
+            sa.spill = ws.spill + ws.spill_cap;
+            sa.spill_n = &ws.ctrl_d->spill_n[1];
+            int lds2 = 4 * (sa.lds_rows * sa.kp + sa.lds_rows);
+            DM_HIP(launch_sort_lds(sa, 256, lds2, s));
+            // tier 3: global memory
+            sa.list = ws.spill + ws.spill_cap;
+            sa.list_n = &ws.ctrl_d->spill_n[1];
+            DM_HIP(launch_sort_global(sa, 128, s));
+            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps + 1], s));
+        }
+        DM_HIP(hipEventRecord(ws.ev[1], s));
+        DM_HIP(hipMemcpyAsync(ws.ctrl_h, ws.ctrl_d, sizeof(Control), hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+        const Control& c = *ws.ctrl_h;
+        int first_over = -1;
+        for (int i = 0; i < nsteps; i++)
+            if (c.overflow[i]) {
+                first_over = i;
+                break;
+            }
+        if (first_over >= 0) {
+            if (sync_mode) return fail(DM_ERR_INTERNAL, "overflow in exact-sizing mode");
+            // counts are exact up to the first overflowing step: size from them and rerun step by step
+            int64_t need = 0;
+            for (int i = 0; i <= first_over; i++) need = std::max<int64_t>(need, c.counts[i + 1]);
+            if (need > budget_rows)
+                return fail(DM_ERR_BUDGET_EXCEEDED,
+                            "intermediate table of " + std::to_string(need) + " rows exceeds the memory budget");
+            int64_t nc = need + need / 8 + 1024;
+            cap[0] = std::max(cap[0], nc);
+            cap[1] = std::max(cap[1], nc);
+            sync_mode = true;
+            retries++;
+            continue;
+        }
+        if (c.dup != 0) {
+            dev_free(result, s);
+            return fail(DM_ERR_INTERNAL, "duplicate rows reached the canonical table");
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]);
+        o.stats.device_ms = ms;
+        o.stats.n_steps = (int32_t)plan.steps.size();
+        o.stats.retries = retries;
+        o.stats.chunks = 1;
+        int64_t bytes = 0;
+        int64_t prev_rows = v1 - v0;
+        int prev_cols = 1;
+        for (int i = 0; i < nsteps; i++) {
+            int64_t r = (hash_mode && i == nsteps - 1) ? (int64_t)c.hash[0] : c.counts[i + 1];
+            if (i < DM_MAX_PATTERN_VERTICES) o.stats.step_rows[i] = r;
+            const int cols = steps[i].c_in + steps[i].n_new;
+            bytes += 4 * (prev_cols * prev_rows) + ((hash_mode && i == nsteps - 1) ? 0 : 4 * (int64_t)cols * r);
+            prev_rows = r;
+            prev_cols = cols;
+        }
+        o.rows = hash_mode ? (int64_t)c.hash[0] : c.counts[nsteps];
+        o.stats.join_bytes = bytes;
+        if (!hash_mode && opt.sort) {
+            o.stats.sort_bytes = 8 * (int64_t)k * o.rows;
+            bytes += o.stats.sort_bytes;
+        }
+        o.stats.bytes_moved = bytes;
+        if (opt.profile) {
+            double jm = 0;
+            for (int i = 0; i < nsteps; i++) {
+                float t = 0;
+                (void)hipEventElapsedTime(&t, ws.prof[2 * i], ws.prof[2 * i + 1]);
+                jm += t;
+            }
+            o.stats.join_ms = jm;
+            o.stats.join_launches = nsteps;
+            if (!hash_mode && opt.sort) {
+                float t = 0;
+                (void)hipEventElapsedTime(&t, ws.prof[2 * nsteps], ws.prof[2 * nsteps + 1]);
+                o.stats.sort_ms = t;
+                o.stats.sort_launches = 3;
+            }
+        }
+        if (hash_mode) {
+            o.hsum = c.hash[1];
+            o.hxor = c.hash[2];
+        } else if (opt.sort) {
+            o.sorted = result;
+            o.sorted_rows = opt.cap >= 0 ? std::min<int64_t>(opt.cap, o.rows) : o.rows;
+            result = nullptr;
+        } else {
+            o.table = ws.buf[lb];
+            o.stride = cap[lb];
+        }
+        (void)redo;
+        *out = o;
+        return DM_OK;
+    }
+}
+
+}  // namespace dm
+
+using namespace dm;
+
+dm::TableDev dm_datagraph::table_dev(int motif, int key_pos) const {
+    TableDev t;
+    std::memset(&t, 0, sizeof t);
+    const MotifTable& m = tab[motif][key_pos];
+    for (int p = 0; p < m.size; p++) t.col[p] = m.cols[p];
+    t.offs = m.offs;
+    t.rows = m.rows;
+    t.size = m.size;
+    return t;
+}
+
+// ------------------------------------------------------------- C ABI
+
+#define DMOTIF_VERSION_STR "dmotif 0.1 (gfx950)"
+
+extern "C" {
+
+const char* dm_version(void) { return DMOTIF_VERSION_STR; }
+
+const char* dm_last_error(void) { return g_err.c_str(); }
+
+dm_status dm_context_create(int32_t device, void* hip_stream, dm_context** out) {
+    if (!out) return fail(DM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return fail(DM_ERR_DEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= ndev) return fail(DM_ERR_INVALID_ARG, "device index out of range");
+    DM_HIP(hipSetDevice(device));
+    auto* c = new dm_context();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(DM_ERR_DEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+    dm_status st = c->ws.init(c->stream);
+    if (st != DM_OK) {
+        c->ws.release();
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return st;
+    }
+    c->sort_lds_max = sort_max_lds_bytes();
+    *out = c;
+    return DM_OK;
+}
+
+void dm_context_destroy(dm_context* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    ctx->ws.release();
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- data graph
+
+static void free_tables(dm_datagraph* dg) {
+    hipStream_t s = dg->ctx->stream;
+    for (int m = 0; m < kNumMotifs; m++)
+        for (int j = 0; j < 6; j++) {
+            MotifTable& t = dg->tab[m][j];
+            for (int q = 0; q < 2; q++) dev_free(t.owned[q], s);
+            t = MotifTable();
+        }
+}
+
+static void free_datagraph(dm_datagraph* dg) {
+    if (!dg) return;
+    hipStream_t s = dg->ctx->stream;
+    free_tables(dg);
+    dev_free(dg->row_ptr, s);
+    dev_free(dg->col, s);
+    dev_free(dg->src, s);
+    dev_free(dg->bitmap, s);
+    (void)hipStreamSynchronize(s);
+    delete dg;
+}
+
+static NormPattern motif_pattern(int m) {
+    const MotifInfo& mi = motif_info(m);
+    NormPattern p;
+    p.k = mi.size;
+    for (int i = 0; i + 1 < mi.size; i++) p.edges.emplace_back(i, i + 1);
+    if (mi.cycle) p.edges.emplace_back(0, mi.size - 1);
+    std::sort(p.edges.begin(), p.edges.end());
+    return p;
+}
+
+// Build Res(M) for motif m (every key position) by running Algorithm 1 on
+// the motif itself with the motifs already in the database (Algorithm 2).
+static dm_status build_motif(dm_datagraph* dg, int m) {
+    dm_context* ctx = dg->ctx;
+    hipStream_t s = ctx->stream;
+    const MotifInfo& mi = motif_info(m);
+    NormPattern p = motif_pattern(m);
+    for (int j = 0; j < motif_key_positions(m); j++) {
+        Plan plan;
+        std::string err;
+        dm_status st = plan_pattern(p, j, dg->motif_bits, &dg->stats, &plan, &err);
+        if (st != DM_OK) return fail(st, err);
+        RunOptions opt;
+        opt.sort = false;
+        RunOutput ro;
+        DM_TRY(run_plan(ctx, ctx->ws, dg, plan, opt, &ro));
+        MotifTable& t = dg->tab[m][j];
+        t.size = mi.size;
+        t.rows = ro.rows;
+        int32_t* data = nullptr;
+        int32_t* offs = nullptr;
+        DM_TRY(dev_alloc((void**)&data, sizeof(int32_t) * (size_t)std::max<int64_t>(ro.rows * mi.size, 1), s));
+        DM_TRY(dev_alloc((void**)&offs, sizeof(int32_t) * (size_t)(dg->n + 1), s));
+        t.owned[0] = data;
+        t.owned[1] = offs;
+        int32_t colmap[kMaxMotif];
+        for (int q = 0; q < mi.size; q++) colmap[q] = plan.col_of[q];
+        // the final count lives in the control block (device); reuse it for the gather
+        const int64_t* n_dev = &ctx->ws.ctrl_d->counts[plan.steps.size()];
+        DM_HIP(launch_gather_cols(ro.table, ro.stride, n_dev, ro.rows, colmap, mi.size, data,
+                                  std::max<int64_t>(ro.rows, 1), s));
+        for (int q = 0; q < mi.size; q++) t.cols[q] = data + (size_t)q * (size_t)std::max<int64_t>(ro.rows, 1);
+        DM_HIP(launch_offsets(t.cols[j], n_dev, ro.rows, dg->n, offs, s));
+        t.offs = offs;
+    }
+    dg->motif_bits |= 1u << m;
+    dg->mask_built |= mi.bit;
+    dg->stats.rows[m] = (double)dg->tab[m][0].rows;
+    return DM_OK;
+}
+
+static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
+    dm_context* ctx = dg->ctx;
+    hipStream_t s = ctx->stream;
+    Workspace& ws = ctx->ws;
+    const int32_t n = gd->n_vertices;
+    const int64_t m = gd->n_edges;
+    if ((int64_t)2 * m >= (int64_t)INT32_MAX) return fail(DM_ERR_UNSUPPORTED, "more than 2^30 edges");
+    int32_t *d_edges = nullptr, *deg = nullptr, *tmp_ptr = nullptr, *tmp = nullptr, *cursor = nullptr,
+            *udeg = nullptr, *big = nullptr, *flags = nullptr;
+    auto cleanup = [&]() {
+        dev_free(d_edges, s);
+        dev_free(deg, s);
+        dev_free(tmp_ptr, s);
+        dev_free(tmp, s);
+        dev_free(cursor, s);
+        dev_free(udeg, s);
+        dev_free(big, s);
+        dev_free(flags, s);
+    };
+    dm_status st = DM_OK;
+    do {
+        // flags: [0] range error bits, [1] big-list count, [2] max degree
+        if ((st = dev_alloc((void**)&flags, 16 * sizeof(int32_t), s))) break;
+        if ((st = dev_alloc((void**)&d_edges, sizeof(int32_t) * (size_t)std::max<int64_t>(2 * m, 1), s))) break;
+        if ((st = dev_alloc((void**)&deg, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+        if ((st = dev_alloc((void**)&tmp_ptr, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+        if ((st = dev_alloc((void**)&cursor, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+        if ((st = dev_alloc((void**)&udeg, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+        if ((st = dev_alloc((void**)&big, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+        if (launch_fill_i32(flags, 0, 16, s) || launch_fill_i32(deg, 0, n + 1, s) ||
+            launch_fill_i32(cursor, 0, n + 1, s) || launch_fill_i32(udeg, 0, n + 1, s)) {
+            st = fail(DM_ERR_DEVICE, "fill launch failed");
+            break;
+        }
+        if (m > 0 && hipMemcpyAsync(d_edges, gd->edges, sizeof(int32_t) * 2 * (size_t)m, hipMemcpyHostToDevice, s)) {
+            st = fail(DM_ERR_DEVICE, "edge upload failed");
+            break;
+        }
+        if (launch_ingest_count(d_edges, m, n, deg, flags, s)) {
+            st = fail(DM_ERR_DEVICE, "ingest_count launch failed");
+            break;
+        }
+        // exclusive scan of raw degrees -> tmp_ptr
+        int64_t tiles = (int64_t)(n + 1) / 1024 + 2;
+        if ((st = ws.ensure_status(tiles))) break;
+        (void)launch_fill_u64(ws.status, 0, tiles, s);
+        (void)launch_fill_u64(ws.tickets, 0, 1, s);
+        if (launch_scan_i32(deg, tmp_ptr, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets, s)) {
+            st = fail(DM_ERR_DEVICE, "scan launch failed");
+            break;
+        }
+        int64_t raw = 0;
+        int32_t hflags[16];
+        if (hipMemcpyAsync(&raw, &ws.ctrl_d->counts[0], sizeof(int64_t), hipMemcpyDeviceToHost, s) ||
+            hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s)) {
+            st = fail(DM_ERR_DEVICE, "ingest readback failed");
+            break;
+        }
+        if (hflags[0] & 1) {
+            st = fail(DM_ERR_VERTEX_RANGE, "data graph vertex id out of range");
+            break;
+        }
+        if ((st = dev_alloc((void**)&tmp, sizeof(int32_t) * (size_t)std::max<int64_t>(raw, 1), s))) break;
+        if (launch_ingest_scatter(d_edges, m, tmp_ptr, cursor, tmp, s) ||
+            launch_ingest_sort_small(tmp_ptr, tmp, n, udeg, big, flags + 1, s) ||
+            launch_ingest_sort_big(tmp_ptr, tmp, udeg, big, flags + 1, flags, s)) {
+            st = fail(DM_ERR_DEVICE, "ingest sort launch failed");
+            break;
+        }
+        if ((st = dev_alloc((void**)&dg->row_ptr, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+        (void)launch_fill_u64(ws.status, 0, tiles, s);
+        (void)launch_fill_u64(ws.tickets, 0, 1, s);
+        if (launch_scan_i32(udeg, dg->row_ptr, n, &ws.ctrl_d->counts[1], ws.status, ws.tickets, s)) {
+            st = fail(DM_ERR_DEVICE, "scan launch failed");
+            break;
+        }
+        int64_t nnz = 0;
+        if (hipMemcpyAsync(&nnz, &ws.ctrl_d->counts[1], sizeof(int64_t), hipMemcpyDeviceToHost, s) ||
+            hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s)) {
+            st = fail(DM_ERR_DEVICE, "ingest readback failed");
+            break;
+        }
+        if (hflags[0] & 2) {
+            st = fail(DM_ERR_UNSUPPORTED, "a vertex degree exceeds 16384");
+            break;
+        }
+        dg->nnz = nnz;
+        if ((st = dev_alloc((void**)&dg->col, sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), s))) break;
+        if ((st = dev_alloc((void**)&dg->src, sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), s))) break;
+        if (launch_ingest_compact(tmp_ptr, tmp, dg->row_ptr, n, dg->col, dg->src, flags + 2, s)) {
+            st = fail(DM_ERR_DEVICE, "compact launch failed");
+            break;
+        }
+        if (n <= 32768 && n > 0) {
+            dg->words_per_row = (n + 31) / 32;
+            int64_t words = (int64_t)n * dg->words_per_row;
+            if ((st = dev_alloc((void**)&dg->bitmap, sizeof(uint32_t) * (size_t)words, s))) break;
+            (void)launch_fill_i32((int32_t*)dg->bitmap, 0, words, s);
+            if (launch_bitmap_set(dg->src, dg->col, nnz, dg->words_per_row, dg->bitmap, s)) {
+                st = fail(DM_ERR_DEVICE, "bitmap launch failed");
+                break;
+            }
+        }
+        if (hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s)) {
+            st = fail(DM_ERR_DEVICE, "ingest readback failed");
+            break;
+        }
+        dg->max_degree = hflags[2];
+    } while (0);
+    cleanup();
+    if (st == DM_OK) {
+        // Res(M2): the directed edge table, keyed on its first column = CSR
+        MotifTable& t = dg->tab[MOT_P2][0];
+        t.size = 2;
+        t.rows = dg->nnz;
+        t.cols[0] = dg->src;
+        t.cols[1] = dg->col;
+        t.offs = dg->row_ptr;
+        dg->stats.n_vertices = n;
+        dg->stats.rows[MOT_P2] = (double)dg->nnz;
+        dg->stats.avg_degree = n > 0 ? (double)dg->nnz / n : 0.0;
+    }
+    return st;
+}
+
+extern "C" {
+
+dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t motif_mask, dm_datagraph** out) {
+    if (!ctx || !gd || !out) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (gd->n_vertices < 0 || gd->n_edges < 0 || (gd->n_edges > 0 && !gd->edges))
+        return fail(DM_ERR_INVALID_ARG, "invalid data graph descriptor");
+    DM_HIP(hipSetDevice(ctx->device));
+    auto* dg = new dm_datagraph();
+    dg->ctx = ctx;
+    dg->n = gd->n_vertices;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e0, ctx->stream);
+    dm_status st = ingest(dg, gd);
+    if (st == DM_OK && dg->n > 0) {
+        const bool aut = (motif_mask == DM_MOTIF_AUTO);
+        uint32_t want = aut ? (DM_MOTIF_M3 | DM_MOTIF_M4 | DM_MOTIF_C4) : motif_mask;
+        const int order[] = {MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12};
+        for (int m : order) {
+            if (st != DM_OK) break;
+            if (!(want & motif_info(m).bit)) continue;
+            st = build_motif(dg, m);
+        }
+        if (st == DM_OK && aut && dg->tab[MOT_C4][0].rows == 0) {
+            // girth > 4 (heavy-hex-like): add the 12-cycle cell if its path
+            // table stays moderate (estimated from the growth M3 -> M4)
+            double r3 = dg->stats.rows[MOT_P3], r4 = dg->stats.rows[MOT_P4];
+            double g = r3 > 0 ? r4 / r3 : 0;
+            double est12 = r4 * std::pow(std::max(g, 1.0), 8);
+            if (r4 > 0 && est12 < 5e7) st = build_motif(dg, MOT_C12);
+        }
+    }
+    (void)hipEventRecord(e1, ctx->stream);
+    if (st == DM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(DM_ERR_DEVICE, "build sync failed");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dg->build_ms = ms;
+    if (st != DM_OK) {
+        free_datagraph(dg);
+        return st;
+    }
+    *out = dg;
+    return DM_OK;
+}
+
+void dm_datagraph_free(dm_datagraph* dg) {
+    if (!dg) return;
+    (void)hipSetDevice(dg->ctx->device);
+    free_datagraph(dg);
+}
+
+dm_status dm_datagraph_query(const dm_datagraph* dg, dm_datagraph_info* out) {
+    if (!dg || !out) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    std::memset(out, 0, sizeof *out);
+    out->n_vertices = dg->n;
+    out->n_directed_edges = dg->nnz;
+    out->max_degree = dg->max_degree;
+    out->has_bitmap = dg->bitmap != nullptr;
+    out->motif_mask = dg->mask_built;
+    for (int m = 0; m < kNumMotifs; m++) out->motif_rows[m] = (dg->motif_bits >> m) & 1 ? dg->tab[m][0].rows : 0;
+    out->build_ms = dg->build_ms;
+    return DM_OK;
+}
+
+dm_status dm_datagraph_copy_csr(const dm_datagraph* dg, int32_t* row_ptr, int32_t* col) {
+    if (!dg || !row_ptr || (!col && dg->nnz > 0)) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    DM_HIP(hipSetDevice(dg->ctx->device));
+    hipStream_t s = dg->ctx->stream;
+    DM_HIP(hipMemcpyAsync(row_ptr, dg->row_ptr, sizeof(int32_t) * (size_t)(dg->n + 1), hipMemcpyDeviceToHost, s));
+    if (dg->nnz > 0) DM_HIP(hipMemcpyAsync(col, dg->col, sizeof(int32_t) * (size_t)dg->nnz, hipMemcpyDeviceToHost, s));
+    DM_HIP(hipStreamSynchronize(s));
+    return DM_OK;
+}
+
+dm_status dm_datagraph_copy_motif(const dm_datagraph* dg, int32_t motif, int32_t key_pos, int32_t* dst,
+                                  int64_t max_rows, int64_t* rows, int32_t* width) {
+    if (!dg || motif < 0 || motif >= kNumMotifs) return fail(DM_ERR_INVALID_ARG, "bad motif index");
+    if (!((dg->motif_bits >> motif) & 1)) return fail(DM_ERR_INVALID_ARG, "motif not built");
+    if (key_pos < 0 || key_pos >= motif_key_positions(motif)) return fail(DM_ERR_INVALID_ARG, "bad key position");
+    const MotifTable& t = dg->tab[motif][key_pos];
+    if (rows) *rows = t.rows;
+    if (width) *width = t.size;
+    if (!dst) return DM_OK;
+    DM_HIP(hipSetDevice(dg->ctx->device));
+    hipStream_t s = dg->ctx->stream;
+    int64_t r = std::min<int64_t>(max_rows, t.rows);
+    if (r <= 0) return DM_OK;
+    std::vector<int32_t> colbuf((size_t)r);
+    for (int p = 0; p < t.size; p++) {
+        DM_HIP(hipMemcpyAsync(colbuf.data(), t.cols[p], sizeof(int32_t) * (size_t)r, hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < r; i++) dst[i * t.size + p] = colbuf[(size_t)i];
+    }
+    return DM_OK;
+}
+
+dm_status dm_plan(const dm_graph_desc* gp, uint32_t motif_mask, int32_t* buf, int32_t buf_cap, int32_t* len) {
+    if (!len) return fail(DM_ERR_INVALID_ARG, "len is NULL");
+    NormPattern p;
+    std::string err;
+    dm_status st = normalize_pattern(gp, &p, &err);
+    if (st != DM_OK) return fail(st, err);
+    Plan plan;
+    st = plan_pattern(p, 0, motif_bits_from_mask(motif_mask), nullptr, &plan, &err);
+    if (st != DM_OK) return fail(st, err);
+    std::vector<int32_t> v = serialize_plan(plan);
+    *len = (int32_t)v.size();
+    if (!buf || buf_cap < (int32_t)v.size()) return fail(DM_ERR_INVALID_ARG, "plan buffer too small");
+    std::memcpy(buf, v.data(), sizeof(int32_t) * v.size());
+    return DM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- enumerate
+
+namespace dm {
+
+// Plan a pattern against a data graph with the options' motif subset.
+dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan) {
+    uint32_t avail = dg->motif_bits;
+    if (opts && opts->motif_mask) {
+        uint32_t want = motif_bits_from_mask(opts->motif_mask);
+        avail &= want;
+    }
+    std::string err;
+    dm_status st = plan_pattern(p, 0, avail, &dg->stats, plan, &err);
+    if (st != DM_OK) return fail(st, err);
+    return DM_OK;
+}
+
+RunOptions run_options(const dm_plan_opts* opts, int64_t cap) {
+    RunOptions o;
+    if (opts) {
+        o.block = opts->block_threads;
+        o.mode = opts->output_mode;
+        o.sync_each_step = opts->sync_each_step != 0;
+        o.mem_budget = opts->mem_budget;
+        o.profile = opts->profile != 0;
+    }
+    o.cap = cap;
+    return o;
+}
+
+// Patterns with more vertices than the data graph, or an empty data graph:
+// an empty result without device work.
+dm_result* empty_result(dm_context* ctx, int32_t k, int32_t mode) {
+    auto* r = new dm_result();
+    r->ctx = ctx;
+    r->width = k;
+    r->stream = ctx->stream;
+    r->mode = mode;
+    return r;
+}
+
+dm_status enumerate_one(dm_datagraph* dg, Workspace& ws, const dm_graph_desc* gp, int64_t cap,
+                        const dm_plan_opts* opts, dm_result** out) {
+    *out = nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    NormPattern p;
+    std::string err;
+    dm_status st = normalize_pattern(gp, &p, &err);
+    if (st != DM_OK) return fail(st, err);
+    const int32_t mode = opts ? opts->output_mode : DM_OUT_TABLE;
+    if (mode != DM_OUT_TABLE && mode != DM_OUT_COUNT_HASH) return fail(DM_ERR_INVALID_ARG, "bad output mode");
+    if (opts && opts->block_threads != 0 && opts->block_threads != 64 && opts->block_threads != 128 &&
+        opts->block_threads != 256)
+        return fail(DM_ERR_INVALID_ARG, "block_threads must be 0, 64, 128 or 256");
+    if (p.k > dg->n) {
+        *out = empty_result(dg->ctx, p.k, mode);
+        (*out)->stream = ws.stream;
+        return DM_OK;
+    }
+    Plan plan;
+    DM_TRY(plan_for(dg, p, opts, &plan));
+    auto t1 = std::chrono::steady_clock::now();
+    RunOptions ro = run_options(opts, cap);
+    RunOutput o;
+    DM_TRY(run_plan(dg->ctx, ws, dg, plan, ro, &o));
+    auto* r = new dm_result();
+    r->ctx = dg->ctx;
+    r->width = p.k;
+    r->stream = ws.stream;
+    r->mode = mode;
+    r->total = o.rows;
+    if (mode == DM_OUT_COUNT_HASH) {
+        r->rows = 0;
+        r->hsum = o.hsum;
+        r->hxor = o.hxor;
+    } else {
+        r->rows = o.sorted_rows;
+        r->data = o.sorted;
+    }
+    r->stats = o.stats;
+    r->stats.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    *out = r;
+    return DM_OK;
+}
+
+}  // namespace dm
+
+extern "C" {
+
+dm_status dm_estimate(dm_datagraph* dg, const dm_graph_desc* gp, const dm_plan_opts* opts, int64_t* peak_bytes,
+                      int64_t* est_rows) {
+    if (!dg || !gp) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    NormPattern p;
+    std::string err;
+    dm_status st = normalize_pattern(gp, &p, &err);
+    if (st != DM_OK) return fail(st, err);
+    Plan plan;
+    DM_TRY(plan_for(dg, p, opts, &plan));
+    if (peak_bytes) *peak_bytes = (int64_t)std::min(plan.est_peak_rows_cols * 4.0, 9.0e18);
+    if (est_rows) *est_rows = (int64_t)std::min(plan.est_final_rows, 9.0e18);
+    return DM_OK;
+}
+
+dm_status dm_enumerate(dm_datagraph* dg, const dm_graph_desc* gp, int64_t max_embeddings, const dm_plan_opts* opts,
+                       dm_result** out) {
+    if (!dg || !gp || !out) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    DM_HIP(hipSetDevice(dg->ctx->device));
+    return enumerate_one(dg, dg->ctx->ws, gp, max_embeddings, opts, out);
+}
+
+int64_t dm_result_rows(const dm_result* r) { return r ? r->rows : 0; }
+int64_t dm_result_total(const dm_result* r) { return r ? r->total : 0; }
+int32_t dm_result_width(const dm_result* r) { return r ? r->width : 0; }
+const int32_t* dm_result_device_data(const dm_result* r) { return (r && r->rows > 0) ? r->data : nullptr; }
+
+dm_status dm_result_hash(const dm_result* r, uint64_t* hash_sum, uint64_t* hash_xor) {
+    if (!r) return fail(DM_ERR_INVALID_ARG, "NULL result");
+    if (r->mode != DM_OUT_COUNT_HASH) return fail(DM_ERR_INVALID_ARG, "result is not in count+hash mode");
+    if (hash_sum) *hash_sum = r->hsum;
+    if (hash_xor) *hash_xor = r->hxor;
+    return DM_OK;
+}
+
+dm_status dm_result_copy_to_host(const dm_result* r, int32_t* dst, int64_t max_rows) {
+    if (!r || (!dst && max_rows > 0)) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    int64_t n = std::min(max_rows, r->rows);
+    if (n <= 0) return DM_OK;
+    DM_HIP(hipSetDevice(r->ctx->device));
+    DM_HIP(hipMemcpyAsync(dst, r->data, sizeof(int32_t) * (size_t)n * r->width, hipMemcpyDeviceToHost, r->stream));
+    DM_HIP(hipStreamSynchronize(r->stream));
+    return DM_OK;
+}
+
+dm_status dm_result_copy_to_device(const dm_result* r, int32_t* dst, int64_t max_rows, void* hip_stream) {
+    if (!r || (!dst && max_rows > 0)) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    int64_t n = std::min(max_rows, r->rows);
+    if (n <= 0) return DM_OK;
+    DM_HIP(hipSetDevice(r->ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : r->stream;
+    if (s != r->stream) {
+        hipEvent_t e;
+        DM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        DM_HIP(hipEventRecord(e, r->stream));
+        DM_HIP(hipStreamWaitEvent(s, e, 0));
+        (void)hipEventDestroy(e);
+    }
+    DM_HIP(hipMemcpyAsync(dst, r->data, sizeof(int32_t) * (size_t)n * r->width, hipMemcpyDeviceToDevice, s));
+    DM_HIP(hipStreamSynchronize(s));
+    return DM_OK;
+}
+
+dm_status dm_result_stats(const dm_result* r, dm_run_stats* out) {
+    if (!r || !out) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    *out = r->stats;
+    return DM_OK;
+}
+
+void dm_result_free(dm_result* r) {
+    if (!r) return;
+    if (r->data) {
+        (void)hipSetDevice(r->ctx->device);
+        dev_free(r->data, r->stream);
+    }
+    delete r;
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// Host runtime internals: context, resident data graph, workspaces, results.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dm_common.hpp"
+#include "dm_device.hpp"
+
+namespace dm {
+
+void set_error(const std::string& msg);
+dm_status fail(dm_status s, const std::string& msg);
+dm_status hip_fail(hipError_t e, const char* what);
+
+#define DM_HIP(call)                                      \
+    do {                                                  \
+        hipError_t e__ = (call);                          \
+        if (e__ != hipSuccess) return hip_fail(e__, #call); \
+    } while (0)
+
+#define DM_TRY(call)                     \
+    do {                                 \
+        dm_status s__ = (call);          \
+        if (s__ != DM_OK) return s__;    \
+    } while (0)
+
+// Stream-ordered device allocation from the device's default memory pool.
+dm_status dev_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// Per-run control block in device memory (counts, flags, hash accumulators).
+struct Control {
+    int64_t counts[kMaxSteps + 2];
+    int32_t overflow[kMaxSteps + 2];
+    uint64_t hash[4];
+    int32_t dup;
+    int32_t spill_n[2];
+    int32_t pad;
+};
+
+// Scratch reused across runs of one stream: ping-pong SoA tables, look-back
+// words, epoch tickets, spill lists and the control block.
+struct Workspace {
+    hipStream_t stream = nullptr;
+    int32_t* buf[2] = {nullptr, nullptr};
+    int64_t buf_elems[2] = {0, 0};
+    uint64_t* status = nullptr;
+    int64_t status_cap = 0;
+    uint64_t* tickets = nullptr;  // kEpochs counters
+    uint32_t epoch = 0;           // last used epoch (1..kEpochs-1)
+    Control* ctrl_d = nullptr;
+    Control* ctrl_h = nullptr;    // pinned host mirror
+    int32_t* spill = nullptr;     // 2 lists of n_vertices entries
+    int64_t spill_cap = 0;
+    uint32_t* sort_scratch = nullptr;
+    int64_t sort_scratch_elems = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> prof;  // event pairs for per-launch timing
+
+    dm_status init(hipStream_t s);
+    void release();
+    dm_status ensure_buf(int i, int64_t elems);
+    dm_status ensure_status(int64_t words);
+    dm_status ensure_spill(int64_t n);
+    dm_status ensure_sort_scratch(int64_t elems);
+    // next look-back epoch; clears status words and tickets when wrapping
+    dm_status next_epoch(uint32_t* e);
+};
+
+// Motif table keyed on one position (see TableDev).
+struct MotifTable {
+    int32_t* cols[kMaxMotif] = {};  // column of each motif position
+    int32_t* offs = nullptr;        // n_vertices + 1
+    int64_t rows = 0;
+    int32_t size = 0;
+    int32_t* owned[2] = {nullptr, nullptr};  // allocations to free (data, offs)
+};
+
+struct DataGraph;
+
+}  // namespace dm
+
+struct dm_context {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    dm::Workspace ws;
+    int32_t sort_lds_max = 0;
+};
+
+struct dm_datagraph {
+    dm_context* ctx = nullptr;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t max_degree = 0;
+    int32_t* row_ptr = nullptr;
+    int32_t* col = nullptr;
+    int32_t* src = nullptr;
+    uint32_t* bitmap = nullptr;
+    int32_t words_per_row = 0;
+    uint32_t mask_built = 0;  // DM_MOTIF_* bits
+    uint32_t motif_bits = 1;  // bit per MotifIndex present
+    dm::MotifTable tab[dm::kNumMotifs][6];
+    dm::MotifStats stats;
+    double build_ms = 0;
+
+    dm::GraphDev graph_dev() const {
+        dm::GraphDev g;
+        g.row_ptr = row_ptr;
+        g.col = col;
+        g.bitmap = bitmap;
+        g.n = n;
+        g.words_per_row = words_per_row;
+        return g;
+    }
+    dm::TableDev table_dev(int motif, int key_pos) const;
+};
+
+struct dm_result {
+    dm_context* ctx = nullptr;
+    int32_t width = 0;
+    int64_t rows = 0;
+    int64_t total = 0;
+    int32_t* data = nullptr;  // device, row-major
+    hipStream_t stream = nullptr;
+    int32_t mode = DM_OUT_TABLE;
+    uint64_t hsum = 0, hxor = 0;
+    dm_run_stats stats{};
+};
+
+namespace dm {
+
+struct RunOptions {
+    int32_t block = 0;         // 0 = auto
+    int32_t mode = DM_OUT_TABLE;
+    bool sync_each_step = false;
+    int64_t mem_budget = 0;
+    int64_t cap = -1;          // max embeddings (< 0 = all)
+    bool sort = true;          // canonicalize (false: keep plan-order SoA, for motif tables)
+    bool profile = false;      // time each launch with events
+};
+
+// Output of one plan execution on one workspace.
+struct RunOutput {
+    int64_t rows = 0;          // final table rows (before cap)
+    int32_t* table = nullptr;  // SoA final table (plan column order) when !sort, owned by workspace
+    int64_t stride = 0;
+    int32_t* sorted = nullptr; // row-major sorted table (ownership passes to the caller)
+    int64_t sorted_rows = 0;
+    uint64_t hsum = 0, hxor = 0;
+    dm_run_stats stats{};
+};
+
+dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const Plan& plan,
+                   const RunOptions& opt, RunOutput* out);
+
+dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan);
+RunOptions run_options(const dm_plan_opts* opts, int64_t cap);
+dm_result* empty_result(dm_context* ctx, int32_t k, int32_t mode);
+// One pattern through Algorithm 1 on workspace `ws` (its stream).
+dm_status enumerate_one(dm_datagraph* dg, Workspace& ws, const dm_graph_desc* gp, int64_t cap,
+                        const dm_plan_opts* opts, dm_result** out);
+
+}  // namespace dm

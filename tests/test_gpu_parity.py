@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer work, so every comparison is bit-exact: normalized CSR, motif
+tables as row sets, sorted embedding tables, counts and count+hash
+summaries.  Inputs are the seeded synthetic workloads."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2508_21287_amd as dm
+from paper_2508_21287_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dm.Context(0)
+    yield c
+    c.close()
+
+
+def rows_set(a):
+    return {tuple(r) for r in np.asarray(a).tolist()}
+
+
+def check_enum(dg, g, p, cap=-1, **opts):
+    say(f"case graph={g.name} pattern={p.name} k={p.n} cap={cap} opts={opts}")
+    want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, cap=cap)
+    with dg.enumerate(p.n, p.edges, cap=cap, **opts) as r:
+        got = r.to_numpy()
+        assert r.total == total, (g.name, p.name, r.total, total)
+        assert r.width == p.n
+        assert got.shape == want.shape, (got.shape, want.shape)
+        assert np.array_equal(got, want), (g.name, p.name)
+    return total
+
+
+def test_ingest_matches_oracle(ctx):
+    gs = [W.heavy_hex(3, 9), W.heavy_hex(7, 19), W.grid(10, 10), W.random_gnp(40, 0.2, 3)]
+    noisy = W.random_gnp(30, 0.3, 5)
+    e = np.vstack([noisy.edges, [[0, 0], [3, 3]], noisy.edges[:7, ::-1], noisy.edges[:5]])
+    gs.append(W.Graph(noisy.n, e, "gnp+loops+dups"))
+    gs.append(W.Graph(7, np.zeros((0, 2), np.int32), "isolated"))
+    star = W.Graph(3000, np.array([[0, i] for i in range(1, 3000)], np.int32), "star3000")
+    gs.append(star)  # a vertex above the per-thread sort limit
+    for g in gs:
+        say(f"ingest {g.name}")
+        dg = ctx.datagraph(g.n, g.edges)
+        rp, col = dg.csr()
+        rp0, col0 = oracle.normalize(g.n, g.edges)
+        assert np.array_equal(rp, rp0) and np.array_equal(col, col0), g.name
+        info = dg.info()
+        assert info["n_directed_edges"] == len(col0)
+        assert info["max_degree"] == int(np.diff(rp0).max(initial=0))
+        dg.free()
+
+
+def test_ingest_errors(ctx):
+    with pytest.raises(dm.DMError) as ei:
+        ctx.datagraph(4, [[0, 1], [1, 9]])
+    assert ei.value.code == -2
+
+
+MOTIF_PATTERNS = {0: W.path(2), 1: W.path(3), 2: W.path(4), 3: W.path(5), 4: W.path(6), 5: W.cycle(4),
+                  6: W.cycle(6), 7: W.cycle(12)}
+
+
+@pytest.mark.parametrize("gname", ["HH(3,9)", "HH(7,19)", "GRID(6,7)"])
+def test_motif_tables(ctx, gname):
+    g = {"HH(3,9)": W.heavy_hex(3, 9), "HH(7,19)": W.heavy_hex(7, 19), "GRID(6,7)": W.grid(6, 7)}[gname]
+    dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_ALL)
+    info = dg.info()
+    for m, p in MOTIF_PATTERNS.items():
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+        assert info["motif_rows"][dm.MOTIF_NAMES[m]] == total, (gname, m)
+        nkp = 1 if m in (5, 6, 7) else (p.n + 1) // 2
+        for j in range(nkp):
+            say(f"motif {dm.MOTIF_NAMES[m]} key {j} on {gname}")
+            t = dg.motif_table(m, j)
+            assert len(t) == total
+            assert rows_set(t) == rows_set(want)
+            assert (np.diff(t[:, j]) >= 0).all()  # grouped by the key column
+    dg.free()
+
+
+def test_config1_parity(ctx):
+    g, pats = W.config1()
+    dg = ctx.datagraph(g.n, g.edges)
+    totals = [check_enum(dg, g, p) for p in pats]
+    assert totals[0] == 144 and totals[1] == 72  # P6 and the 12-cycle (3 cells x 24)
+    dg.free()
+
+
+def test_config2_parity(ctx):
+    g, pats = W.config2()
+    dg = ctx.datagraph(g.n, g.edges)
+    for p in pats:
+        check_enum(dg, g, p)
+    dg.free()
+
+
+@pytest.mark.parametrize("mask", [dm.MOTIF_M2_ONLY, dm.MOTIF_M4, dm.MOTIF_C4 | dm.MOTIF_M3, 0],
+                         ids=["M2", "M4", "C4+M3", "all"])
+def test_plan_independence_gpu(ctx, mask):
+    g = W.heavy_hex(4, 13)
+    dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_ALL)
+    pats = [W.path(7), W.cycle(12), W.prufer_tree(8, 1), W.star(3)]
+    _, c2 = W.config2(8)
+    pats += c2[:4]
+    for p in pats:
+        check_enum(dg, g, p, motif_mask=mask)
+    gr = W.grid(7, 8)
+    dgr = ctx.datagraph(gr.n, gr.edges, dm.MOTIF_ALL)
+    g23 = W.grid(2, 3)
+    for p in [W.cycle(4), W.Pattern(g23.n, g23.edges, "grid2x3"), W.path(6), W.cycle(8)]:
+        check_enum(dgr, gr, p, motif_mask=mask)
+    dg.free()
+    dgr.free()
+
+
+def test_random_graphs(ctx):
+    pats = [W.path(3), W.path(5), W.cycle(3), W.cycle(4), W.cycle(5), W.star(3),
+            W.Pattern(4, [[0, 1], [1, 2], [2, 3], [3, 0], [0, 2]], "diamond"),
+            W.Pattern(5, [[4, 0], [0, 2], [2, 4], [2, 1], [1, 3]], "tri-tail")]
+    for s in range(4):
+        g = W.random_gnp(60, 0.08 + 0.04 * s, 100 + s)
+        dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_ALL)
+        for p in pats:
+            check_enum(dg, g, p)
+        dg.free()
+
+
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_block_sizes_and_sync(ctx, block):
+    g = W.heavy_hex(7, 19)
+    dg = ctx.datagraph(g.n, g.edges)
+    _, pats = W.config2(6)
+    for p in pats:
+        check_enum(dg, g, p, block=block)
+        check_enum(dg, g, p, block=block, sync_each_step=True)
+    dg.free()
+
+
+def test_overflow_retry(ctx):
+    # a tiny memory budget starts the join tables far too small; the run
+    # must detect the overflow and redo the steps with exact sizes
+    g = W.grid(12, 12)
+    dg = ctx.datagraph(g.n, g.edges)
+    p = W.path(7)
+    want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+    with dg.enumerate(p.n, p.edges, mem_budget=1 << 20) as r:
+        assert np.array_equal(r.to_numpy(), want)
+        assert r.stats()["retries"] >= 1
+    dg.free()
+
+
+def test_caps(ctx):
+    g, pats = W.config1()
+    dg = ctx.datagraph(g.n, g.edges)
+    for p in pats:
+        _, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+        for cap in [0, 1, 7, total - 1, total, total + 5]:
+            check_enum(dg, g, p, cap=cap)
+    dg.free()
+
+
+def test_count_hash_mode(ctx):
+    for g, pats in [W.config1(), (W.heavy_hex(7, 19), W.config2(10)[1]), (W.grid(9, 9), [W.cycle(4), W.path(6)])]:
+        dg = ctx.datagraph(g.n, g.edges)
+        for p in pats:
+            say(f"hash {g.name} {p.name}")
+            c, hs, hx = oracle.count_hash(g.n, g.edges, p.n, p.edges)
+            with dg.enumerate(p.n, p.edges, mode=dm.OUT_COUNT_HASH) as r:
+                assert r.total == c
+                assert r.hash() == (hs, hx)
+        dg.free()
+
+
+def test_edge_cases(ctx):
+    g = W.heavy_hex(3, 9)
+    dg = ctx.datagraph(g.n, g.edges)
+    check_enum(dg, g, W.path(1))
+    with dg.enumerate(40, [[i, i + 1] for i in range(39)]) as r:  # more vertices than the data graph
+        assert r.rows == 0 and r.total == 0
+    for n, e, code in [(2, [[0, 0], [0, 1]], -4), (4, [[0, 1], [2, 3]], -3), (3, [[0, 5]], -2)]:
+        with pytest.raises(dm.DMError) as ei:
+            dg.enumerate(n, e)
+        assert ei.value.code == code
+    check_enum(dg, g, W.Pattern(2, [[0, 1], [1, 0], [0, 1]], "multi-edge"))
+    dg.free()
+    iso = W.Graph(5, np.zeros((0, 2), np.int32), "isolated")
+    dgi = ctx.datagraph(iso.n, iso.edges)
+    check_enum(dgi, iso, W.path(1))
+    check_enum(dgi, iso, W.path(2))
+    dgi.free()
+    empty = W.Graph(0, np.zeros((0, 2), np.int32), "empty")
+    dge = ctx.datagraph(0, empty.edges)
+    with dge.enumerate(2, [[0, 1]]) as r:
+        assert r.rows == 0
+    dge.free()
+
+
+def test_no_bitmap_path(ctx):
+    g = W.grid(190, 190)  # 36100 vertices: adjacency checks use the CSR lists
+    dg = ctx.datagraph(g.n, g.edges)
+    assert not dg.info()["has_bitmap"]
+    for p in [W.cycle(4), W.Pattern(4, [[0, 1], [1, 2], [2, 3], [3, 0], [0, 2]], "diamond")]:
+        say(f"nobitmap {p.name}")
+        c, hs, hx = oracle.count_hash(g.n, g.edges, p.n, p.edges)
+        with dg.enumerate(p.n, p.edges, motif_mask=dm.MOTIF_M2_ONLY, mode=dm.OUT_COUNT_HASH) as r:
+            assert (r.total,) + r.hash() == (c, hs, hx)
+    dg.free()
+
+
+def test_batch_matches_plain(ctx):
+    g, pats = W.config2(16)
+    dg = ctx.datagraph(g.n, g.edges)
+    caps = [-1, 5, -1, 0] * 4
+    res = dg.enumerate_batch([(p.n, p.edges) for p in pats], caps=caps)
+    for p, cap, r in zip(pats, caps, res):
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, cap=cap)
+        assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
+        r.free()
+    dg.free()
+
+
+def test_server_alone_and_in_mix(ctx):
+    g = W.heavy_hex(7, 19)
+    dg = ctx.datagraph(g.n, g.edges)
+    _, pats = W.config2(12)
+    srv = dm.Server(dg, n_streams=2, max_batch=4)
+    alone = []
+    for p in pats[:3]:
+        t = srv.submit(p.n, p.edges)
+        r = srv.wait(t, 60000)
+        alone.append(r.to_numpy())
+        r.free()
+    tickets = [srv.submit(p.n, p.edges, cap) for p in pats for cap in (-1, 3)]
+    for i, t in enumerate(tickets):
+        p, cap = pats[i // 2], (-1, 3)[i % 2]
+        r = srv.wait(t, 60000)
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, cap=cap)
+        got = r.to_numpy()
+        assert np.array_equal(got, want), p.name
+        if i // 2 < 3 and cap == -1:
+            assert np.array_equal(got, alone[i // 2])
+        r.free()
+    srv.stop()
+    dg.free()
+
+
+def test_determinism(ctx):
+    g, pats = W.config2(4)
+    dg = ctx.datagraph(g.n, g.edges)
+    for p in pats:
+        a = dg.enumerate(p.n, p.edges)
+        b = dg.enumerate(p.n, p.edges)
+        assert np.array_equal(a.to_numpy(), b.to_numpy())
+        assert a.stats()["step_rows"] == b.stats()["step_rows"]
+        a.free()
+        b.free()
+    dg.free()
+
+
+def test_to_torch(ctx):
+    import torch
+    g, pats = W.config1()
+    dg = ctx.datagraph(g.n, g.edges)
+    with dg.enumerate(pats[0].n, pats[0].edges) as r:
+        t = r.to_torch(0)
+        assert t.is_cuda and t.dtype == torch.int32
+        want, _ = oracle.enumerate_embeddings(g.n, g.edges, pats[0].n, pats[0].edges)
+        assert np.array_equal(t.cpu().numpy(), want)
+    dg.free()
