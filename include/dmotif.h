@@ -110,6 +110,8 @@ typedef struct {
     int64_t mem_budget;    /* bytes for intermediate tables; 0 = library default */
     int32_t profile;       /* 1: time every join and sort launch with HIP events (see dm_run_stats) */
     int32_t reserved_;
+    int64_t initial_rows;  /* first-attempt capacity of each intermediate table in rows; 0 = from the
+                              planner's estimate.  Too small only costs a re-run with exact sizes. */
 } dm_plan_opts;
 
 typedef struct dm_context dm_context;
@@ -127,6 +129,7 @@ const char* dm_last_error(void);
  * (a hipStream_t; NULL = a stream the context creates and owns).
  * Errors: DM_ERR_INVALID_ARG (bad device / out == NULL), DM_ERR_DEVICE. */
 dm_status dm_context_create(int32_t device, void* hip_stream, dm_context** out);
+/* Free data graphs, results and servers created on a context before destroying it. */
 void dm_context_destroy(dm_context* ctx);
 
 /* Algorithm 2 (BuildDatabase): normalize `gd` into device CSR + adjacency

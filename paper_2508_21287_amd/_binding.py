@@ -21,6 +21,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import threading
+import weakref
 
 import numpy as np
 
@@ -55,7 +56,7 @@ class GraphDesc(C.Structure):
 class PlanOpts(C.Structure):
     _fields_ = [("motif_mask", C.c_uint32), ("block_threads", C.c_int32), ("output_mode", C.c_int32),
                 ("sync_each_step", C.c_int32), ("mem_budget", C.c_int64), ("profile", C.c_int32),
-                ("reserved_", C.c_int32)]
+                ("reserved_", C.c_int32), ("initial_rows", C.c_int64)]
 
 
 class DataGraphInfo(C.Structure):
@@ -100,6 +101,14 @@ def lib() -> C.CDLL:
             return _LIB
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_21287_amd._build`")
+        # PyTorch ships its own HIP runtime with the same soname as the system
+        # one (libamdhip64.so.7).  Loading torch first makes the library bind to
+        # that already-loaded runtime, so the process holds a single HIP/HSA
+        # instance and streams/pointers are shared with torch.
+        try:
+            import torch  # noqa: F401
+        except Exception:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32p = C.c_void_p, C.POINTER(C.c_int32)
         sig = {
@@ -156,9 +165,9 @@ class _Graph:
 
 
 def _opts(motif_mask=0, block=0, mode=OUT_TABLE, sync_each_step=False, mem_budget=0,
-          profile=False) -> PlanOpts:
+          profile=False, initial_rows=0) -> PlanOpts:
     return PlanOpts(int(motif_mask) & 0xFFFFFFFF, int(block), int(mode), int(bool(sync_each_step)),
-                    int(mem_budget), int(bool(profile)), 0)
+                    int(mem_budget), int(bool(profile)), 0, int(initial_rows))
 
 
 def _torch_stream(device: int):
@@ -185,14 +194,28 @@ class Context:
         else:
             s = C.c_void_p(int(stream))
         self._h = C.c_void_p()
+        self._children = weakref.WeakSet()
         _check(L.dm_context_create(device, s, C.byref(self._h)))
 
     @property
     def handle(self):
         return self._h
 
+    def _adopt(self, obj):
+        self._children.add(obj)
+        return obj
+
     def close(self):
         if self._h:
+            # servers first (they hold results), then results, then data graphs
+            kids = list(self._children)
+            for kind in (Server, Result, DataGraph):
+                for o in kids:
+                    if isinstance(o, kind):
+                        try:
+                            o._release()
+                        except Exception:
+                            pass
             lib().dm_context_destroy(self._h)
             self._h = C.c_void_p()
 
@@ -209,8 +232,10 @@ class Context:
 class Result:
     """An embedding table on the device (``dm_result``)."""
 
-    def __init__(self, h):
+    def __init__(self, h, ctx: "Context | None" = None):
         self._h = h
+        if ctx is not None:
+            ctx._adopt(self)
 
     @property
     def rows(self) -> int:
@@ -265,6 +290,8 @@ class Result:
             lib().dm_result_free(self._h)
             self._h = None
 
+    _release = free
+
     def __enter__(self):
         return self
 
@@ -287,6 +314,7 @@ class DataGraph:
         self._h = C.c_void_p()
         _check(lib().dm_datagraph_build(ctx.handle, C.byref(g.desc), int(motif_mask) & 0xFFFFFFFF,
                                         C.byref(self._h)))
+        ctx._adopt(self)
 
     def info(self) -> dict:
         i = DataGraphInfo()
@@ -326,7 +354,7 @@ class DataGraph:
         o = _opts(**opts)
         h = C.c_void_p()
         _check(lib().dm_enumerate(self._h, C.byref(g.desc), int(cap), C.byref(o), C.byref(h)))
-        return Result(h)
+        return Result(h, self.ctx)
 
     def enumerate_batch(self, patterns, caps=None, **opts) -> list[Result]:
         gs = [_Graph(n, e) for n, e in patterns]
@@ -337,12 +365,14 @@ class DataGraph:
         outs = (C.c_void_p * len(gs))()
         o = _opts(**opts)
         _check(lib().dm_enumerate_batch(self._h, len(gs), arr, capv, C.byref(o), outs))
-        return [Result(C.c_void_p(outs[i])) for i in range(len(gs))]
+        return [Result(C.c_void_p(outs[i]), self.ctx) for i in range(len(gs))]
 
     def free(self):
         if self._h:
             lib().dm_datagraph_free(self._h)
             self._h = C.c_void_p()
+
+    _release = free
 
     def __del__(self):
         try:
@@ -360,6 +390,7 @@ class Server:
         o = ServerOpts(n_streams, max_batch, mem_budget, max_queue)
         self._h = C.c_void_p()
         _check(lib().dm_server_start(dg._h, C.byref(o), C.byref(self._h)))
+        dg.ctx._adopt(self)
 
     def submit(self, n: int, edges, cap: int = -1) -> int:
         g = _Graph(n, edges)
@@ -370,12 +401,14 @@ class Server:
     def wait(self, ticket: int, timeout_ms: int = -1) -> Result:
         h = C.c_void_p()
         _check(lib().dm_server_wait(self._h, C.c_uint64(ticket), int(timeout_ms), C.byref(h)))
-        return Result(h)
+        return Result(h, self.dg.ctx)
 
     def stop(self):
         if self._h:
             _check(lib().dm_server_stop(self._h))
             self._h = C.c_void_p()
+
+    _release = stop
 
     def __del__(self):
         try:

@@ -343,8 +343,13 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
             d.edge_b[d.n_edge] = (uint8_t)checks[i].second;
             d.n_edge++;
         }
-        // estimate
+        // estimate: motif rows per key vertex; once the key vertex already has
+        // placed neighbours, each motif edge at the key competes with them
         double fan = estimate_fanout(stats, chosen);
+        if (d.c_in > 1) {
+            const int key_deg = mi.cycle ? 2 : ((key == 0 || key == L - 1) ? 1 : 2);
+            fan *= std::pow(std::max(deg - 1.0, 0.5) / deg, key_deg);
+        }
         double nrows = rows * fan;
         for (int e = 0; e < d.n_eq; e++) nrows /= std::max(1.0, deg * std::pow(br, std::max(0, min_eq_dist - 1)));
         for (int e = 0; e < (int)checks.size(); e++) nrows /= std::max(1.0, deg * br);

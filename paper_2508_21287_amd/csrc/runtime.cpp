@@ -175,9 +175,13 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
     double est_max = (double)dg->n;
     for (double e : est) est_max = std::max(est_max, e);
     int64_t budget = opt.mem_budget > 0 ? opt.mem_budget : (int64_t)48 << 30;
-    int64_t budget_rows = std::max<int64_t>(budget / (int64_t)(8 * k), 1 << 16);
-    int64_t cap0 = (int64_t)std::min<double>(est_max * 4.0 + 4096.0, (double)budget_rows);
-    cap0 = std::max<int64_t>(cap0, 1 << 14);
+    int64_t budget_rows = std::max<int64_t>(budget / (int64_t)(8 * k), 1024);
+    // first attempt: twice the estimate, at most 1 GiB per table; a larger
+    // real table costs one re-run with exact sizes (sync mode)
+    const int64_t first_max = std::min<int64_t>(budget_rows, ((int64_t)1 << 28) / k);
+    int64_t cap0 = (int64_t)std::min<double>(est_max * 2.0 + 4096.0, (double)first_max);
+    cap0 = std::max<int64_t>(cap0, std::min<int64_t>(1 << 14, budget_rows));
+    if (opt.initial_rows > 0) cap0 = std::min<int64_t>(opt.initial_rows, budget_rows);
     const int block = opt.block > 0 ? opt.block : auto_block(est_max);
 
     // capacity (rows) of each ping-pong buffer; stride of a table = its capacity
@@ -197,7 +201,9 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
 
     for (;;) {
         for (int b = 0; b < 2; b++) DM_TRY(ws.ensure_buf(b, cap[b] * k));
-        for (int b = 0; b < 2; b++) cap[b] = ws.buf_elems[b] / k;
+        // use the whole buffer unless the caller pinned the first-attempt capacity
+        if (opt.initial_rows <= 0 || retries > 0)
+            for (int b = 0; b < 2; b++) cap[b] = ws.buf_elems[b] / k;
         int64_t maxcap = std::max<int64_t>(std::max(cap[0], cap[1]), (int64_t)dg->n);
         DM_TRY(ws.ensure_status(maxcap / 64 + 2));
         DM_HIP(launch_fill_u64((uint64_t*)ws.ctrl_d, 0, sizeof(Control) / 8, s));
@@ -808,6 +814,7 @@ RunOptions run_options(const dm_plan_opts* opts, int64_t cap) {
         o.sync_each_step = opts->sync_each_step != 0;
         o.mem_budget = opts->mem_budget;
         o.profile = opts->profile != 0;
+        o.initial_rows = opts->initial_rows;
     }
     o.cap = cap;
     return o;

@@ -143,6 +143,7 @@ struct RunOptions {
     int64_t cap = -1;          // max embeddings (< 0 = all)
     bool sort = true;          // canonicalize (false: keep plan-order SoA, for motif tables)
     bool profile = false;      // time each launch with events
+    int64_t initial_rows = 0;  // first-attempt table capacity (0 = estimate)
 };
 
 // Output of one plan execution on one workspace.
