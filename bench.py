@@ -104,6 +104,19 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
 
+    # the same steps with one plain launch sequence per pattern, for comparison
+    plain_steps = max(1, min(args.steps, 3))
+    saved = args.mode
+    args.mode = "plain"
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    pemb = 0
+    for _ in range(plain_steps):
+        pemb += step(False)[0]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - tp
+    args.mode = saved
+
     # query-only throughput (data graph resident: the paper's GPU* measure)
     dg = dm.DataGraph(ctx, g.n, g.edges)
     torch.cuda.synchronize()
@@ -137,6 +150,8 @@ def main():
                    "mode": args.mode, "embeddings_per_step": emb // max(args.steps, 1),
                    "step": "data-graph build + motif tables + plan + joins + sort"},
         "query_only_embeddings_per_s": qemb / tq,
+        "plain_embeddings_per_s": pemb / tp,
+        "batched_over_plain": (emb / el) / (pemb / tp) if pemb else None,
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "ejf_kernel (expand-join-filter)",

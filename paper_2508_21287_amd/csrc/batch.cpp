@@ -1,6 +1,19 @@
 // Batched and served forms of Algorithm 1 over one resident data graph.
+//
+// Batched: every pattern is decomposed on the host, then all join steps of
+// all patterns run in ONE persistent kernel launch (device-side stage
+// counters and per-(pattern, step) tile tickets, see batch_kernel), followed
+// by one launch per sort tier that canonicalizes every pattern's table.
+// Patterns whose first-attempt table capacity overflowed are re-run alone
+// with exact sizing.
+//
+// Served: a request loop keeps the data graph resident, admits queries by
+// their predicted intermediate-table memory, and runs admitted queries as
+// continuous batches on several streams, so work of queries that arrive
+// while others are on the GPU overlaps on the device.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -13,19 +26,371 @@
 
 using namespace dm;
 
+namespace {
+
+constexpr int kBatchTile = 64;       // rows per tile in the persistent kernel
+constexpr int kBatchMaxCols = 64;    // widest input table the persistent kernel holds in registers
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct DevBlock {
+    void* p = nullptr;
+    hipStream_t s = nullptr;
+    ~DevBlock() { dev_free(p, s); }
+};
+
+struct Item {
+    int32_t idx;       // position in the caller's array
+    int32_t k;
+    int64_t cap = -1;  // max embeddings
+    Plan plan;
+    std::vector<StepDesc> steps;
+    int64_t tcap = 0;  // table capacity (rows) of each ping-pong buffer
+    int64_t out_rows = 0;
+    // arena offsets (bytes)
+    size_t off_buf[2] = {0, 0}, off_status = 0, off_counts = 0, off_flags = 0, off_hash = 0, off_res = 0;
+};
+
+}  // namespace
+
+namespace dm {
+
+// Run a set of already-validated patterns as one batch on workspace `ws`.
+// results[i] receives item i's result (owned by the caller).
+static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& items, const dm_plan_opts* opts,
+                           std::vector<dm_result*>& results) {
+    dm_context* ctx = dg->ctx;
+    hipStream_t s = ws.stream;
+    const int32_t nv = dg->n;
+    const int nb = (int)items.size();
+    const bool hash_mode = opts && opts->output_mode == DM_OUT_COUNT_HASH;
+    const bool profile = opts && opts->profile;
+    results.assign(nb, nullptr);
+    if (nb == 0) return DM_OK;
+
+    // ---- layout: one arena for tables + control, one block for results
+    size_t arena = 0, resb = 0;
+    int total_steps = 0, cmax = 1;
+    for (auto& it : items) {
+        double est = (double)nv;
+        for (auto& ps : it.plan.steps) est = std::max(est, ps.est_rows);
+        const int64_t first_max = std::min<int64_t>(((int64_t)1 << 28) / it.k, (int64_t)1 << 26);
+        it.tcap = std::max<int64_t>(std::min<int64_t>((int64_t)(2.0 * est) + 4096, first_max), 4096);
+        if (opts && opts->initial_rows > 0) it.tcap = opts->initial_rows;
+        it.out_rows = it.cap >= 0 ? std::min<int64_t>(it.cap, it.tcap) : it.tcap;
+        for (int b = 0; b < 2; b++) {
+            it.off_buf[b] = arena;
+            arena = align256(arena + sizeof(int32_t) * (size_t)(it.tcap * it.k));
+        }
+        total_steps += (int)it.steps.size();
+        for (auto& d : it.steps) cmax = std::max(cmax, (int)d.c_in);
+        if (!hash_mode) {
+            it.off_res = resb;
+            resb = align256(resb + sizeof(int32_t) * (size_t)std::max<int64_t>(it.out_rows * it.k, 1));
+        }
+    }
+    const size_t ctl_begin = arena;
+    for (auto& it : items) {
+        it.off_status = arena;
+        // look-back words: one per tile of the largest input (the identity has nv rows)
+        arena = align256(arena + sizeof(uint64_t) * (size_t)(std::max<int64_t>(it.tcap, nv) / kBatchTile + 2));
+        it.off_counts = arena;
+        arena = align256(arena + sizeof(int64_t) * (it.steps.size() + 2));
+        it.off_flags = arena;
+        arena = align256(arena + sizeof(int32_t) * (it.steps.size() + 2));
+        it.off_hash = arena;
+        arena = align256(arena + sizeof(uint64_t) * 4);
+    }
+    const size_t off_misc = arena;  // finished, spill_n[2], dup
+    arena = align256(arena + 64);
+    const size_t ctl_end = arena;
+    const size_t off_ctl = arena;
+    arena = align256(arena + sizeof(BatchCtl) * nb);
+    const size_t off_first = arena;
+    arena = align256(arena + sizeof(int32_t) * nb);
+    const size_t off_nsteps = arena;
+    arena = align256(arena + sizeof(int32_t) * nb);
+    const size_t off_args = arena;
+    arena = align256(arena + sizeof(EjfArgs) * total_steps);
+    const size_t off_jobs = arena;
+    arena = align256(arena + sizeof(SortJob) * nb);
+    const size_t off_upload = off_ctl;  // ctl .. jobs are staged on the host and uploaded at once
+
+    char* A = nullptr;
+    DM_TRY(dev_alloc((void**)&A, arena, s));
+    std::unique_ptr<DevBlock> arena_guard(new DevBlock{A, s});
+    std::shared_ptr<DevBlock> res_block;
+    char* R = nullptr;
+    if (!hash_mode) {
+        DM_TRY(dev_alloc((void**)&R, resb, s));
+        res_block.reset(new DevBlock{R, s});
+    }
+
+    // ---- host staging of controllers, argument blocks and sort jobs
+    std::vector<char> host(arena - off_upload, 0);
+    BatchCtl* ctl = (BatchCtl*)(host.data() + (off_ctl - off_upload));
+    int32_t* first = (int32_t*)(host.data() + (off_first - off_upload));
+    int32_t* nsteps = (int32_t*)(host.data() + (off_nsteps - off_upload));
+    EjfArgs* args = (EjfArgs*)(host.data() + (off_args - off_upload));
+    SortJob* jobs = (SortJob*)(host.data() + (off_jobs - off_upload));
+    int a_i = 0;
+    const GraphDev g = dg->graph_dev();
+    for (int p = 0; p < nb; p++) {
+        Item& it = items[p];
+        const int ns = (int)it.steps.size();
+        first[p] = a_i;
+        nsteps[p] = ns;
+        ctl[p].n_in[0] = nv;
+        ctl[p].ntiles[0] = (nv + kBatchTile - 1) / kBatchTile;
+        int64_t* counts = (int64_t*)(A + it.off_counts);
+        int32_t* flags = (int32_t*)(A + it.off_flags);
+        for (int i = 0; i < ns; i++) {
+            EjfArgs& a = args[a_i++];
+            std::memset(&a, 0, sizeof a);
+            a.st = it.steps[i];
+            if (a.st.motif >= 0) a.tbl = dg->table_dev(a.st.motif, a.st.key_pos);
+            a.g = g;
+            const int ib = (i - 1) & 1, ob = i & 1;
+            a.in = i == 0 ? nullptr : (const int32_t*)(A + it.off_buf[ib]);
+            a.in_stride = i == 0 ? 0 : it.tcap;
+            a.in_cap = i == 0 ? nv : it.tcap;
+            a.n_in = &counts[i];
+            a.id_begin = 0;
+            a.id_count = nv;
+            a.out = (int32_t*)(A + it.off_buf[ob]);
+            a.out_stride = it.tcap;
+            a.out_cap = it.tcap;
+            a.n_out = &counts[i + 1];
+            a.overflow = &flags[i];
+            a.status = (uint64_t*)(A + it.off_status);
+            a.epoch = (uint32_t)(i + 1);
+            a.ticket = nullptr;
+            a.mode = (hash_mode && i == ns - 1) ? EJF_HASH : EJF_WRITE;
+            a.hash_acc = (uint64_t*)(A + it.off_hash);
+            for (int c = 0; c < it.k; c++) a.pv[c] = (uint8_t)std::max(it.plan.pv_of[c], 0);
+        }
+        SortJob& j = jobs[p];
+        std::memset(&j, 0, sizeof j);
+        const int lb = (ns - 1) & 1;
+        j.in = (const int32_t*)(A + it.off_buf[lb]);
+        j.in_stride = it.tcap;
+        j.in_cap = it.tcap;
+        j.n_in = &counts[ns];
+        j.out = hash_mode ? nullptr : (int32_t*)(R + it.off_res);
+        j.out_rows = it.out_rows;
+        // the other ping-pong buffer is idle after the last step: index scratch
+        j.scratch_idx = (uint32_t*)(A + it.off_buf[lb ^ 1]);
+        j.k = it.k;
+        j.kp = (it.k % 2 == 0) ? it.k + 1 : it.k;
+        for (int c = 0; c < it.k; c++) j.perm[c] = (uint8_t)it.plan.col_of[c];
+    }
+    int32_t* misc = (int32_t*)(A + off_misc);
+
+    DM_HIP(launch_fill_u64((uint64_t*)(A + ctl_begin), 0, (int64_t)((ctl_end - ctl_begin) / 8), s));
+    DM_HIP(hipMemcpyAsync(A + off_upload, host.data(), host.size(), hipMemcpyHostToDevice, s));
+
+    hipEvent_t ev[4];
+    for (auto& e : ev) DM_HIP(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() {
+            for (int i = 0; i < 4; i++) (void)hipEventDestroy(e[i]);
+        }
+    } evg{ev};
+
+    BatchDev bd;
+    bd.args = (const EjfArgs*)(A + off_args);
+    bd.first = (const int32_t*)(A + off_first);
+    bd.nsteps = (const int32_t*)(A + off_nsteps);
+    bd.ctl = (BatchCtl*)(A + off_ctl);
+    bd.finished = &misc[0];
+    bd.n_patterns = nb;
+    DM_HIP(hipEventRecord(ev[0], s));
+    DM_HIP(launch_batch(bd, cmax, 2048, s));
+    DM_HIP(hipEventRecord(ev[1], s));
+    if (!hash_mode)
+        DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, &misc[1], &misc[3]));
+    DM_HIP(hipEventRecord(ev[2], s));
+
+    // ---- one readback of every count, flag and hash
+    std::vector<char> back(ctl_end - ctl_begin);
+    DM_HIP(hipMemcpyAsync(back.data(), A + ctl_begin, back.size(), hipMemcpyDeviceToHost, s));
+    DM_HIP(hipStreamSynchronize(s));
+    float ms_join = 0, ms_sort = 0;
+    (void)hipEventElapsedTime(&ms_join, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&ms_sort, ev[1], ev[2]);
+    auto hb = [&](size_t off) { return back.data() + (off - ctl_begin); };
+    const int32_t* hmisc = (const int32_t*)hb(off_misc);
+    if (hmisc[0] != nb) return fail(DM_ERR_INTERNAL, "persistent kernel retired " + std::to_string(hmisc[0]) +
+                                                         " of " + std::to_string(nb) + " patterns");
+    if (hmisc[3] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached a canonical table");
+
+    int64_t all_bytes = 0;
+    std::vector<int64_t> pbytes(nb, 0);
+    for (int p = 0; p < nb; p++) {
+        Item& it = items[p];
+        const int ns = (int)it.steps.size();
+        const int64_t* counts = (const int64_t*)hb(it.off_counts);
+        const int32_t* flags = (const int32_t*)hb(it.off_flags);
+        const uint64_t* hash = (const uint64_t*)hb(it.off_hash);
+        bool over = false;
+        for (int i = 0; i < ns; i++) over |= flags[i] != 0;
+        dm_result* r = nullptr;
+        if (over) {
+            // first-attempt capacity too small: redo this pattern alone, exact sizes
+            RunOptions ro = run_options(opts, it.cap);
+            ro.sync_each_step = true;
+            RunOutput o;
+            DM_TRY(run_plan(ctx, ws, dg, it.plan, ro, &o));
+            r = new dm_result();
+            r->ctx = ctx;
+            r->width = it.k;
+            r->stream = ctx->stream;
+            r->mode = hash_mode ? DM_OUT_COUNT_HASH : DM_OUT_TABLE;
+            r->total = o.rows;
+            if (hash_mode) {
+                r->hsum = o.hsum;
+                r->hxor = o.hxor;
+            } else {
+                r->rows = o.sorted_rows;
+                r->data = o.sorted;
+            }
+            r->stats = o.stats;
+            r->stats.retries += 1;
+        } else {
+            r = new dm_result();
+            r->ctx = ctx;
+            r->width = it.k;
+            r->stream = ctx->stream;
+            r->mode = hash_mode ? DM_OUT_COUNT_HASH : DM_OUT_TABLE;
+            const int64_t n_final = hash_mode ? (int64_t)hash[0] : counts[ns];
+            r->total = n_final;
+            if (hash_mode) {
+                r->hsum = hash[1];
+                r->hxor = hash[2];
+            } else {
+                r->rows = it.cap >= 0 ? std::min<int64_t>(it.cap, n_final) : n_final;
+                r->data = (int32_t*)(R + it.off_res);
+                r->block = res_block;
+            }
+            r->stats.n_steps = (int32_t)it.plan.steps.size();
+            r->stats.chunks = 1;
+            int64_t prev_rows = nv, bytes = 0;
+            int prev_cols = 1;
+            for (int i = 0; i < ns; i++) {
+                const int64_t rr = (hash_mode && i == ns - 1) ? (int64_t)hash[0] : counts[i + 1];
+                if (i < DM_MAX_PATTERN_VERTICES) r->stats.step_rows[i] = rr;
+                const int cols = it.steps[i].c_in + it.steps[i].n_new;
+                bytes += (i == 0 ? 0 : 4 * (int64_t)prev_cols * prev_rows) +
+                         ((hash_mode && i == ns - 1) ? 0 : 4 * (int64_t)cols * rr);
+                prev_rows = rr;
+                prev_cols = cols;
+            }
+            r->stats.join_bytes = bytes;
+            if (!hash_mode) r->stats.sort_bytes = 8 * (int64_t)it.k * n_final;
+            r->stats.bytes_moved = r->stats.join_bytes + r->stats.sort_bytes;
+            pbytes[p] = bytes;
+            all_bytes += bytes;
+        }
+        results[p] = r;
+    }
+    // batch-level device times, split by each pattern's share of the bytes so
+    // that sums over the batch give the launch totals
+    int64_t all_sort = 0;
+    for (auto* r : results) all_sort += r->stats.sort_bytes;
+    for (int p = 0; p < nb; p++) {
+        dm_result* r = results[p];
+        if (pbytes[p] == 0 && r->stats.retries > 0) continue;
+        const double fj = all_bytes > 0 ? (double)pbytes[p] / all_bytes : 1.0 / nb;
+        const double fs = all_sort > 0 ? (double)r->stats.sort_bytes / all_sort : 1.0 / nb;
+        r->stats.device_ms = fj * ms_join + fs * ms_sort;
+        if (profile) {
+            r->stats.join_ms = fj * ms_join;
+            r->stats.sort_ms = fs * ms_sort;
+            r->stats.join_launches = p == 0 ? 1 : 0;
+            r->stats.sort_launches = (p == 0 && !hash_mode) ? 3 : 0;
+        }
+    }
+    return DM_OK;
+}
+
+// Validate and plan a batch; patterns the persistent kernel cannot hold
+// (more than kBatchMaxCols input columns) or with more vertices than the
+// data graph are handled apart.
+dm_status enumerate_many(dm_datagraph* dg, Workspace& ws, int32_t n, const dm_graph_desc* gps, const int64_t* caps,
+                         const dm_plan_opts* opts, dm_result** outs) {
+    for (int32_t i = 0; i < n; i++) outs[i] = nullptr;
+    const int32_t mode = opts ? opts->output_mode : DM_OUT_TABLE;
+    if (mode != DM_OUT_TABLE && mode != DM_OUT_COUNT_HASH) return fail(DM_ERR_INVALID_ARG, "bad output mode");
+    std::vector<Item> items;
+    std::vector<int32_t> solo;
+    std::vector<dm_result*> done(n, nullptr);
+    auto cleanup = [&]() {
+        for (auto*& r : done) dm_result_free(r), r = nullptr;
+    };
+    for (int32_t i = 0; i < n; i++) {
+        NormPattern p;
+        std::string err;
+        dm_status st = normalize_pattern(&gps[i], &p, &err);
+        if (st != DM_OK) {
+            cleanup();
+            return fail(st, "pattern " + std::to_string(i) + ": " + err);
+        }
+        const int64_t cap = caps ? caps[i] : -1;
+        if (p.k > dg->n) {
+            done[i] = empty_result(dg->ctx, p.k, mode);
+            continue;
+        }
+        Item it;
+        it.idx = i;
+        it.k = p.k;
+        it.cap = cap;
+        st = plan_for(dg, p, opts, &it.plan);
+        if (st != DM_OK) {
+            cleanup();
+            return st;
+        }
+        for (auto& ps : it.plan.steps) it.steps.push_back(ps.d);
+        if (it.steps.empty()) {
+            StepDesc d;
+            std::memset(&d, 0, sizeof d);
+            d.motif = -1;
+            d.c_in = 1;
+            it.steps.push_back(d);
+        }
+        int cm = 0;
+        for (auto& d : it.steps) cm = std::max(cm, (int)d.c_in);
+        if (cm > kBatchMaxCols || (int)it.steps.size() > kMaxSteps) {
+            solo.push_back(i);
+            continue;
+        }
+        items.push_back(std::move(it));
+    }
+    std::vector<dm_result*> res;
+    dm_status st = run_batch(dg, ws, items, opts, res);
+    if (st != DM_OK) {
+        cleanup();
+        return st;
+    }
+    for (size_t j = 0; j < items.size(); j++) done[items[j].idx] = res[j];
+    for (int32_t i : solo) {
+        st = enumerate_one(dg, ws, &gps[i], caps ? caps[i] : -1, opts, &done[i]);
+        if (st != DM_OK) {
+            cleanup();
+            return st;
+        }
+    }
+    for (int32_t i = 0; i < n; i++) outs[i] = done[i];
+    return DM_OK;
+}
+
+}  // namespace dm
+
 extern "C" dm_status dm_enumerate_batch(dm_datagraph* dg, int32_t n, const dm_graph_desc* gps, const int64_t* caps,
                                         const dm_plan_opts* opts, dm_result** outs) {
     if (!dg || n < 0 || (n > 0 && (!gps || !outs))) return fail(DM_ERR_INVALID_ARG, "invalid batch arguments");
     DM_HIP(hipSetDevice(dg->ctx->device));
-    for (int32_t i = 0; i < n; i++) outs[i] = nullptr;
-    for (int32_t i = 0; i < n; i++) {
-        dm_status st = enumerate_one(dg, dg->ctx->ws, &gps[i], caps ? caps[i] : -1, opts, &outs[i]);
-        if (st != DM_OK) {
-            for (int32_t j = 0; j < i; j++) dm_result_free(outs[j]), outs[j] = nullptr;
-            return st;
-        }
-    }
-    return DM_OK;
+    return enumerate_many(dg, dg->ctx->ws, n, gps, caps, opts, outs);
 }
 
 // ------------------------------------------------------------------ server
@@ -62,6 +427,11 @@ struct dm_server {
     bool stopping = false;
 };
 
+// Each worker owns one stream + workspace.  It takes every admissible
+// request at the head of the queue (up to max_batch, within the memory
+// budget of predicted intermediate tables) and runs them as one batch; while
+// that batch is on the GPU, the other workers admit newly arrived requests
+// and run them on their own streams, so batches overlap on the device.
 static void server_worker(dm_server* s, int w) {
     (void)hipSetDevice(s->dg->ctx->device);
     Workspace& ws = *s->ws[w];
@@ -71,7 +441,6 @@ static void server_worker(dm_server* s, int w) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
             if (s->queue.empty() && s->stopping) return;
-            // admit from the head while the predicted memory fits (always admit one)
             while (!s->queue.empty() && (int32_t)batch.size() < s->opts.max_batch) {
                 auto& r = s->queue.front();
                 if (!batch.empty() || s->inflight > 0) {
@@ -83,22 +452,51 @@ static void server_worker(dm_server* s, int w) {
                 s->queue.pop_front();
             }
         }
+        if (batch.empty()) {
+            // budget full: wait for another batch to finish
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_done.wait_for(lk, std::chrono::milliseconds(5));
+            continue;
+        }
+        std::vector<dm_graph_desc> gps;
+        std::vector<int64_t> caps;
         for (auto& r : batch) {
-            dm_graph_desc gp{r->nv, (int64_t)(r->edges.size() / 2), r->edges.data()};
-            dm_result* res = nullptr;
-            dm_status st = enumerate_one(s->dg, ws, &gp, r->cap, nullptr, &res);
-            std::string err = st == DM_OK ? std::string() : std::string(dm_last_error());
-            // the worker synchronized its stream, so the table is complete; later
-            // copies and the free are ordered on the context stream, which
-            // outlives the server's own streams
-            if (res) res->stream = s->dg->ctx->stream;
+            gps.push_back(dm_graph_desc{r->nv, (int64_t)(r->edges.size() / 2), r->edges.data()});
+            caps.push_back(r->cap);
+        }
+        std::vector<dm_result*> outs(batch.size(), nullptr);
+        dm_status st = enumerate_many(s->dg, ws, (int32_t)batch.size(), gps.data(), caps.data(), nullptr,
+                                      outs.data());
+        std::string err = st == DM_OK ? std::string() : std::string(dm_last_error());
+        if (st != DM_OK && batch.size() > 1) {
+            // isolate the failing request(s): run them one by one
+            for (size_t i = 0; i < batch.size(); i++) {
+                dm_status si = enumerate_many(s->dg, ws, 1, &gps[i], &caps[i], nullptr, &outs[i]);
+                std::lock_guard<std::mutex> lk(s->mu);
+                batch[i]->status = si;
+                batch[i]->err = si == DM_OK ? std::string() : std::string(dm_last_error());
+            }
+        } else {
             std::lock_guard<std::mutex> lk(s->mu);
-            r->status = st;
-            r->err = err;
-            r->result = res;
-            r->done = true;
-            s->inflight_bytes -= r->est_bytes;
-            s->inflight--;
+            for (auto& r : batch) {
+                r->status = st;
+                r->err = err;
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (size_t i = 0; i < batch.size(); i++) {
+                auto& r = batch[i];
+                // the worker synchronized its stream, so the table is complete;
+                // later copies and the free are ordered on the context stream,
+                // which outlives the server's own streams
+                if (outs[i]) outs[i]->stream = s->dg->ctx->stream;
+                r->result = r->status == DM_OK ? outs[i] : nullptr;
+                if (r->status != DM_OK && outs[i]) dm_result_free(outs[i]);
+                r->done = true;
+                s->inflight_bytes -= r->est_bytes;
+                s->inflight--;
+            }
         }
         s->cv_done.notify_all();
         s->cv_work.notify_all();
@@ -124,6 +522,7 @@ dm_status dm_server_start(dm_datagraph* dg, const dm_server_opts* opts, dm_serve
     for (int i = 0; i < o.n_streams; i++) {
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (auto& x : s->ws) x->release();
             for (auto x : s->streams) (void)hipStreamDestroy(x);
             delete s;
             return fail(DM_ERR_DEVICE, "stream creation failed");

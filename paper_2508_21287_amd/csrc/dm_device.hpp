@@ -61,29 +61,55 @@ struct EjfArgs {
     uint8_t pv[kMaxCols]; // EJF_HASH: pattern vertex of each output column
 };
 
-// Canonicalization: permute columns to pattern-vertex order, sort rows of
-// each root segment (rows sharing column 0) lexicographically, write a
-// row-major table.  Segments are processed per root vertex in
-// [v_begin, v_end) or, when list != nullptr, for the vertices in list.
-struct SortArgs {
+// Canonicalization of one final table: permute columns to pattern-vertex
+// order, sort the rows of each root segment (rows sharing column 0)
+// lexicographically, write rows [0, out_rows) of the sorted table row-major.
+struct SortJob {
     const int32_t* in;
     int64_t in_stride;
     int64_t in_cap;
     const int64_t* n_in;
+    int32_t* out;
+    int64_t out_rows;
+    uint32_t* scratch_idx;  // global tier: 2 * in_cap index scratch
     int32_t k;
-    int32_t kp;  // LDS row stride (k rounded up to odd)
-    uint8_t perm[kMaxCols];  // pattern vertex j -> input column
+    int32_t kp;             // LDS row stride (k rounded up to odd)
+    uint8_t perm[kMaxCols]; // pattern vertex j -> input column
+};
+
+// One sort launch over n_jobs tables; item = job * n_vertices + (v - v_begin)
+// for every root vertex v, or the items in `list` for the later tiers.
+// Segments that do not fit this tier's LDS are appended to `spill`.
+struct SortLaunch {
+    const SortJob* jobs;
+    int32_t n_jobs;
+    int32_t n_vertices;
     int32_t v_begin;
-    int32_t v_end;
+    int32_t lds_bytes;
     const int32_t* list;
     const int32_t* list_n;
-    int32_t* spill;    // segments too big for this tier
+    int32_t* spill;
     int32_t* spill_n;
-    int32_t lds_rows;  // rows that fit this tier's LDS
-    int32_t* out;
-    int64_t out_rows;  // rows [0, out_rows) of the sorted table are written
-    uint32_t* scratch_idx;  // global tier: 2 * rows index scratch
     int32_t* dup_count;
+};
+
+// Batched form: per-pattern progress of the persistent join kernel.
+struct BatchCtl {
+    int32_t stage;  // step being processed; == n_steps once retired
+    int32_t pad_[3];
+    int32_t ntiles[kMaxSteps];
+    int32_t claim[kMaxSteps];
+    int32_t done[kMaxSteps];
+    int64_t n_in[kMaxSteps];
+};
+
+struct BatchDev {
+    const EjfArgs* args;   // all (pattern, step) argument blocks
+    const int32_t* first;  // per pattern: index of its step 0 in args
+    const int32_t* nsteps; // per pattern
+    BatchCtl* ctl;         // per pattern, zeroed except ntiles[0]/n_in[0]
+    int32_t* finished;     // retired patterns
+    int32_t n_patterns;
 };
 
 constexpr int kEpochBits = 14;
@@ -91,8 +117,9 @@ constexpr uint32_t kEpochs = 1u << kEpochBits;
 
 // ---- launchers (kernels.hip) ----
 hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s);
-hipError_t launch_sort_lds(const SortArgs& a, int grid, int lds_bytes, hipStream_t s);
-hipError_t launch_sort_global(const SortArgs& a, int grid, hipStream_t s);
+hipError_t launch_sort_lds(const SortLaunch& a, int grid, int lds_bytes, hipStream_t s);
+hipError_t launch_sort_global(const SortLaunch& a, int grid, hipStream_t s);
+hipError_t launch_batch(const BatchDev& b, int cmax, int grid, hipStream_t s);
 int sort_max_lds_bytes();
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

@@ -140,26 +140,173 @@ __device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t (&v)[
     return true;
 }
 
+template <int BLOCK>
+struct TileShared {
+    int64_t base;
+    int32_t wsum[BLOCK / 64];
+    int32_t wexcl[BLOCK / 64];
+};
+
+// One tile (BLOCK consecutive input rows) of a join-filter step: count the
+// surviving candidates of every row, take this tile's output offset from the
+// look-back chain, then write the surviving rows in input order.  In hash
+// mode the survivors only feed the per-thread (count, sum, xor) accumulators.
 template <int CMAX, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
+__device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t n_in, int64_t n_tiles,
+                                         TileShared<BLOCK>& sh, uint64_t& h_cnt, uint64_t& h_sum,
+                                         uint64_t& h_xor) {
     constexpr int NW = BLOCK / 64;
-    __shared__ int64_t s_tile;
-    __shared__ int64_t s_base;
-    __shared__ int32_t s_wsum[NW];
-    __shared__ int32_t s_wexcl[NW];
-    __shared__ uint64_t s_red[3][NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const StepDesc& st = a.st;
-    int64_t n_in;
-    if (a.in) {
-        n_in = *a.n_in;
-        n_in = n_in < 0 ? 0 : (n_in > a.in_cap ? a.in_cap : n_in);
-    } else {
-        n_in = a.id_count;
+    const int64_t row = tile * BLOCK + tid;
+    const bool valid = row < n_in;
+    int32_t v[CMAX];
+#pragma unroll
+    for (int c = 0; c < CMAX; c++) v[c] = -1;
+    if (valid) {
+        if (a.in) {
+#pragma unroll
+            for (int c = 0; c < CMAX; c++)
+                if (c < st.c_in) v[c] = a.in[(int64_t)c * a.in_stride + row];
+        } else {
+            v[0] = a.id_begin + (int32_t)row;
+        }
     }
+    int32_t lo = 0, hi = 0;
+    if (valid) {
+        if (st.motif >= 0) {
+            const int32_t key = a.in ? a.in[(int64_t)st.key_col * a.in_stride + row] : v[0];
+            lo = a.tbl.offs[key];
+            hi = a.tbl.offs[key + 1];
+        } else {
+            hi = 1;  // filter-only step: the row itself is the one candidate
+        }
+    }
+    int32_t nv[kMaxMotif];
+#pragma unroll
+    for (int t = 0; t < kMaxMotif; t++) nv[t] = -1;
+
+    if (a.mode == EJF_HASH) {
+        uint64_t inner_old = 0;
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < CMAX; c++)
+                if (c < st.c_in) inner_old += mix64(((uint64_t)a.pv[c] << 32) | (uint32_t)v[c]);
+        }
+        for (int32_t m = lo; m < hi; m++) {
+            if (!ejf_accept<CMAX>(a, v, row, m, nv)) continue;
+            uint64_t inner = inner_old;
+#pragma unroll
+            for (int t = 0; t < kMaxMotif; t++)
+                if (t < st.n_new) inner += mix64(((uint64_t)a.pv[st.c_in + t] << 32) | (uint32_t)nv[t]);
+            const uint64_t h = mix64(inner);
+            h_cnt++;
+            h_sum += h;
+            h_xor ^= h;
+        }
+        return;
+    }
+
+    uint64_t mask = 0;
+    int32_t cnt = 0;
+    for (int32_t m = lo; m < hi; m++) {
+        if (ejf_accept<CMAX>(a, v, row, m, nv)) {
+            if (m - lo < 64) mask |= 1ull << (m - lo);
+            cnt++;
+        }
+    }
+    // block-wide exclusive scan of per-row survivor counts
+    int32_t x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh.wsum[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int32_t w = lane < NW ? sh.wsum[lane] : 0;
+        int32_t wi = w;
+#pragma unroll
+        for (int o = 1; o < NW; o <<= 1) {
+            const int32_t y = __shfl_up(wi, o, 64);
+            if (lane >= o) wi += y;
+        }
+        if (lane < NW) sh.wexcl[lane] = wi - w;
+        const int32_t total = __shfl(wi, NW - 1, 64);
+        const int64_t excl = lookback_wave(a.status, a.epoch, tile, (uint64_t)total, lane);
+        if (lane == 0) {
+            sh.base = excl;
+            if (tile == n_tiles - 1) *a.n_out = excl + total;
+            if (excl + total > a.out_cap) *a.overflow = 1;
+        }
+    }
+    __syncthreads();
+    const int64_t off = sh.base + sh.wexcl[wid] + (x - cnt);
+    if (cnt > 0) {
+        int32_t r = 0;
+        for (int32_t m = lo; m < hi && r < cnt; m++) {
+            const bool ok = (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : ejf_accept<CMAX>(a, v, row, m, nv);
+            if (!ok) continue;
+            const int64_t o = off + r;
+            r++;
+            if (o >= a.out_cap) break;
+#pragma unroll
+            for (int c = 0; c < CMAX; c++)
+                if (c < st.c_in) a.out[(int64_t)c * a.out_stride + o] = v[c];
+            if (st.motif >= 0) {
+                for (int t = 0; t < st.n_new; t++)
+                    a.out[(int64_t)(st.c_in + t) * a.out_stride + o] = a.tbl.col[st.new_pos[t]][m];
+            }
+        }
+    }
+}
+
+template <int BLOCK>
+__device__ void hash_flush(uint64_t* acc, uint64_t h_cnt, uint64_t h_sum, uint64_t h_xor, uint64_t (*red)[BLOCK / 64]) {
+    constexpr int NW = BLOCK / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        h_cnt += __shfl_xor(h_cnt, o, 64);
+        h_sum += __shfl_xor(h_sum, o, 64);
+        h_xor ^= __shfl_xor(h_xor, o, 64);
+    }
+    if (lane == 0) {
+        red[0][wid] = h_cnt;
+        red[1][wid] = h_sum;
+        red[2][wid] = h_xor;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t c = 0, s = 0, xr = 0;
+        for (int w = 0; w < NW; w++) {
+            c += red[0][w];
+            s += red[1][w];
+            xr ^= red[2][w];
+        }
+        if (c) {
+            atomicAdd((unsigned long long*)&acc[0], (unsigned long long)c);
+            atomicAdd((unsigned long long*)&acc[1], (unsigned long long)s);
+            atomicXor((unsigned long long*)&acc[2], (unsigned long long)xr);
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int64_t clamp_rows(int64_t n, int64_t cap) { return n < 0 ? 0 : (n > cap ? cap : n); }
+
+// One join-filter step over one table: workgroups claim tiles in ticket order
+// until the input is exhausted.
+template <int CMAX, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
+    __shared__ TileShared<BLOCK> sh;
+    __shared__ int64_t s_tile;
+    __shared__ uint64_t s_red[3][BLOCK / 64];
+    const int tid = threadIdx.x;
+    const int64_t n_in = a.in ? clamp_rows(*a.n_in, a.in_cap) : (int64_t)a.id_count;
     const int64_t n_tiles = (n_in + BLOCK - 1) / BLOCK;
     uint64_t h_cnt = 0, h_sum = 0, h_xor = 0;
-
     for (;;) {
         if (tid == 0) s_tile = (int64_t)atomicAdd((unsigned long long*)a.ticket, 1ull);
         __syncthreads();
@@ -169,138 +316,9 @@ __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
             if (a.mode == EJF_WRITE && tile == 0 && tid == 0) *a.n_out = 0;
             break;
         }
-        const int64_t row = tile * BLOCK + tid;
-        const bool valid = row < n_in;
-        int32_t v[CMAX];
-#pragma unroll
-        for (int c = 0; c < CMAX; c++) v[c] = -1;
-        if (valid) {
-            if (a.in) {
-#pragma unroll
-                for (int c = 0; c < CMAX; c++)
-                    if (c < st.c_in) v[c] = a.in[(int64_t)c * a.in_stride + row];
-            } else {
-                v[0] = a.id_begin + (int32_t)row;
-            }
-        }
-        int32_t lo = 0, hi = 0;
-        if (valid) {
-            if (st.motif >= 0) {
-                const int32_t key = a.in ? a.in[(int64_t)st.key_col * a.in_stride + row] : v[0];
-                lo = a.tbl.offs[key];
-                hi = a.tbl.offs[key + 1];
-            } else {
-                hi = 1;  // filter-only step: the row itself is the one candidate
-            }
-        }
-        int32_t nv[kMaxMotif];
-#pragma unroll
-        for (int t = 0; t < kMaxMotif; t++) nv[t] = -1;
-
-        if (a.mode == EJF_HASH) {
-            uint64_t inner_old = 0;
-            if (valid) {
-#pragma unroll
-                for (int c = 0; c < CMAX; c++)
-                    if (c < st.c_in) inner_old += mix64(((uint64_t)a.pv[c] << 32) | (uint32_t)v[c]);
-            }
-            for (int32_t m = lo; m < hi; m++) {
-                if (!ejf_accept<CMAX>(a, v, row, m, nv)) continue;
-                uint64_t inner = inner_old;
-#pragma unroll
-                for (int t = 0; t < kMaxMotif; t++)
-                    if (t < st.n_new) inner += mix64(((uint64_t)a.pv[st.c_in + t] << 32) | (uint32_t)nv[t]);
-                const uint64_t h = mix64(inner);
-                h_cnt++;
-                h_sum += h;
-                h_xor ^= h;
-            }
-            continue;
-        }
-
-        uint64_t mask = 0;
-        int32_t cnt = 0;
-        for (int32_t m = lo; m < hi; m++) {
-            if (ejf_accept<CMAX>(a, v, row, m, nv)) {
-                if (m - lo < 64) mask |= 1ull << (m - lo);
-                cnt++;
-            }
-        }
-        // block-wide exclusive scan of per-row survivor counts
-        int32_t x = cnt;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) s_wsum[wid] = x;
-        __syncthreads();
-        if (wid == 0) {
-            int32_t w = lane < NW ? s_wsum[lane] : 0;
-            int32_t wi = w;
-#pragma unroll
-            for (int o = 1; o < NW; o <<= 1) {
-                const int32_t y = __shfl_up(wi, o, 64);
-                if (lane >= o) wi += y;
-            }
-            if (lane < NW) s_wexcl[lane] = wi - w;
-            const int32_t total = __shfl(wi, NW - 1, 64);
-            const int64_t excl = lookback_wave(a.status, a.epoch, tile, (uint64_t)total, lane);
-            if (lane == 0) {
-                s_base = excl;
-                if (tile == n_tiles - 1) *a.n_out = excl + total;
-                if (excl + total > a.out_cap) *a.overflow = 1;
-            }
-        }
-        __syncthreads();
-        const int64_t off = s_base + s_wexcl[wid] + (x - cnt);
-        if (cnt > 0) {
-            int32_t r = 0;
-            for (int32_t m = lo; m < hi && r < cnt; m++) {
-                const bool ok = (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : ejf_accept<CMAX>(a, v, row, m, nv);
-                if (!ok) continue;
-                const int64_t o = off + r;
-                r++;
-                if (o >= a.out_cap) break;
-#pragma unroll
-                for (int c = 0; c < CMAX; c++)
-                    if (c < st.c_in) a.out[(int64_t)c * a.out_stride + o] = v[c];
-                if (st.motif >= 0) {
-                    for (int t = 0; t < st.n_new; t++)
-                        a.out[(int64_t)(st.c_in + t) * a.out_stride + o] = a.tbl.col[st.new_pos[t]][m];
-                }
-            }
-        }
+        ejf_tile<CMAX, BLOCK>(a, tile, n_in, n_tiles, sh, h_cnt, h_sum, h_xor);
     }
-
-    if (a.mode == EJF_HASH) {
-        // block reduction of (count, sum, xor), one atomic triple per workgroup
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            h_cnt += __shfl_xor(h_cnt, o, 64);
-            h_sum += __shfl_xor(h_sum, o, 64);
-            h_xor ^= __shfl_xor(h_xor, o, 64);
-        }
-        if (lane == 0) {
-            s_red[0][wid] = h_cnt;
-            s_red[1][wid] = h_sum;
-            s_red[2][wid] = h_xor;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint64_t c = 0, s = 0, xr = 0;
-            for (int w = 0; w < NW; w++) {
-                c += s_red[0][w];
-                s += s_red[1][w];
-                xr ^= s_red[2][w];
-            }
-            if (c) {
-                atomicAdd((unsigned long long*)&a.hash_acc[0], (unsigned long long)c);
-                atomicAdd((unsigned long long*)&a.hash_acc[1], (unsigned long long)s);
-                atomicXor((unsigned long long*)&a.hash_acc[2], (unsigned long long)xr);
-            }
-        }
-    }
+    if (a.mode == EJF_HASH) hash_flush<BLOCK>(a.hash_acc, h_cnt, h_sum, h_xor, s_red);
 }
 
 template <int CMAX>
@@ -323,8 +341,152 @@ hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// batched form: one persistent launch runs every pattern's join steps
+// ---------------------------------------------------------------------------
+//
+// Work unit = (pattern p, step s, tile t).  A pattern's step s becomes
+// claimable once its step s-1 finished (ctl.stage == s); its tiles are
+// claimed in ticket order from ctl.claim[s], so the order-preserving
+// look-back of a tile only ever waits on tiles held by running workgroups.
+// The workgroup that finishes the last tile of a step publishes the next
+// step (or retires the pattern).  Every workgroup exits once all patterns
+// are retired, so the grid always drains.
+
+__device__ __forceinline__ int32_t ld_acq_i32(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel_i32(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int CMAX>
+__device__ void batch_tile_dispatch(const EjfArgs& a, int64_t tile, int64_t n_in, int64_t n_tiles,
+                                    TileShared<64>& sh, uint64_t& hc, uint64_t& hs, uint64_t& hx) {
+    const int c = a.st.c_in;
+    if (CMAX >= 64 && c > 32) ejf_tile<(CMAX >= 64 ? 64 : CMAX), 64>(a, tile, n_in, n_tiles, sh, hc, hs, hx);
+    else if (CMAX >= 32 && c > 16) ejf_tile<(CMAX >= 32 ? 32 : CMAX), 64>(a, tile, n_in, n_tiles, sh, hc, hs, hx);
+    else if (CMAX >= 16 && c > 8) ejf_tile<(CMAX >= 16 ? 16 : CMAX), 64>(a, tile, n_in, n_tiles, sh, hc, hs, hx);
+    else ejf_tile<8, 64>(a, tile, n_in, n_tiles, sh, hc, hs, hx);
+}
+
+template <int CMAX>
+__global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
+    __shared__ TileShared<64> sh;
+    __shared__ EjfArgs sa;
+    __shared__ uint64_t s_red[3][1];
+    const int lane = threadIdx.x;
+    const int N = b.n_patterns;
+    int rot = (int)((blockIdx.x * 7919u) % (unsigned)(N > 0 ? N : 1));
+    uint64_t hc = 0, hs = 0, hx = 0;
+    for (;;) {
+        // ---- find a claimable tile (whole wave scans 64 patterns at a time)
+        int32_t p = -1, s = -1;
+        int64_t tile = -1;
+        bool all_done = false;
+        for (;;) {
+            bool got = false;
+            for (int base = 0; base < N && !got; base += 64) {
+                const int q = (rot + base + lane) % N;
+                bool avail = false;
+                int32_t st = 0;
+                if (base + lane < N) {
+                    st = ld_acq_i32(&b.ctl[q].stage);
+                    if (st < b.nsteps[q]) {
+                        const int32_t nt = ld_acq_i32(&b.ctl[q].ntiles[st]);
+                        avail = ld_acq_i32(&b.ctl[q].claim[st]) < nt;
+                    }
+                }
+                uint64_t m = __ballot(avail);
+                while (m) {
+                    const int l = __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    const int32_t qq = __shfl(q, l, 64);
+                    const int32_t ss = __shfl(st, l, 64);
+                    int32_t t = 0;
+                    if (lane == 0) t = atomicAdd(&b.ctl[qq].claim[ss], 1);
+                    t = __shfl(t, 0, 64);
+                    if (t < b.ctl[qq].ntiles[ss]) {
+                        p = qq;
+                        s = ss;
+                        tile = t;
+                        got = true;
+                        break;
+                    }
+                }
+            }
+            if (got) break;
+            if (ld_acq_i32(b.finished) >= N) {
+                all_done = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+        if (all_done) break;
+        rot = (p + 1) % N;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // ---- stage the step's arguments in LDS
+        {
+            const int32_t* src = (const int32_t*)&b.args[b.first[p] + s];
+            int32_t* dst = (int32_t*)&sa;
+            for (int i = lane; i < (int)(sizeof(EjfArgs) / 4); i += 64) dst[i] = src[i];
+        }
+        __syncthreads();
+        const int64_t n_in = b.ctl[p].n_in[s];
+        const int64_t n_tiles = b.ctl[p].ntiles[s];
+        batch_tile_dispatch<CMAX>(sa, tile, n_in, n_tiles, sh, hc, hs, hx);
+        if (sa.mode == EJF_HASH) {
+            hash_flush<64>(sa.hash_acc, hc, hs, hx, s_red);
+            hc = hs = hx = 0;
+        }
+        // ---- completion: the last tile of a step publishes the next one
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) {
+            const int32_t d = atomicAdd(&b.ctl[p].done[s], 1);
+            if (d == n_tiles - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                BatchCtl& c = b.ctl[p];
+                const int32_t ns = b.nsteps[p];
+                const int64_t n_out = (sa.mode == EJF_HASH) ? 0 : __hip_atomic_load(sa.n_out, __ATOMIC_RELAXED,
+                                                                                       __HIP_MEMORY_SCOPE_AGENT);
+                if (s + 1 < ns && n_out > 0) {
+                    const EjfArgs& nx = b.args[b.first[p] + s + 1];
+                    const int64_t nn = clamp_rows(n_out, nx.in_cap);
+                    c.n_in[s + 1] = nn;
+                    __hip_atomic_store(&c.ntiles[s + 1], (int32_t)((nn + 63) / 64), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    st_rel_i32(&c.stage, s + 1);
+                } else {
+                    // last step, or nothing left: the remaining steps produce 0 rows
+                    for (int q = s + 1; q < ns; q++) *b.args[b.first[p] + q].n_out = 0;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    st_rel_i32(&c.stage, ns);
+                    atomicAdd(b.finished, 1);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch(const BatchDev& b, int cmax, int grid, hipStream_t s) {
+    if (cmax <= 8) hipLaunchKernelGGL((batch_kernel<8>), dim3(grid), dim3(64), 0, s, b);
+    else if (cmax <= 16) hipLaunchKernelGGL((batch_kernel<16>), dim3(grid), dim3(64), 0, s, b);
+    else if (cmax <= 32) hipLaunchKernelGGL((batch_kernel<32>), dim3(grid), dim3(64), 0, s, b);
+    else hipLaunchKernelGGL((batch_kernel<64>), dim3(grid), dim3(64), 0, s, b);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // canonicalization: per-root-segment lexicographic sort
 // ---------------------------------------------------------------------------
+//
+// The join steps keep their input order, and the first table is the identity
+// (one row per root vertex, ascending), so a final table is already grouped
+// by the root column in ascending order.  Canonicalization therefore sorts
+// each root segment independently: in LDS when it fits (two tiers of LDS
+// size), else with a global-memory bitonic sort of row indices.  Columns are
+// permuted to pattern-vertex order on the way and the output is row-major.
 
 __device__ __forceinline__ int64_t lower_bound_i32(const int32_t* a, int64_t n, int32_t v) {
     int64_t lo = 0, hi = n;
@@ -348,45 +510,57 @@ __device__ __forceinline__ bool lds_row_less(const int32_t* rows, int kp, int k,
     return false;
 }
 
-__device__ __forceinline__ int64_t seg_rows(const SortArgs& a) {
-    int64_t n = *a.n_in;
-    return n < 0 ? 0 : (n > a.in_cap ? a.in_cap : n);
+__device__ __forceinline__ int lds_rows_of(int lds_bytes, int kp) {
+    int r = lds_bytes / (4 * (kp + 1));
+    int p = 1;
+    while (p * 2 <= r) p *= 2;
+    return r >= 1 ? p : 0;
 }
 
-__global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortArgs a) {
+// Load job j into LDS (all threads), then broadcast the segment of root v.
+__device__ __forceinline__ void sort_item_setup(const SortLaunch& L, int64_t item, SortJob& job, int64_t* seg) {
+    const int64_t j = item / L.n_vertices;
+    const int32_t v = L.v_begin + (int32_t)(item - j * L.n_vertices);
+    const int32_t* src = (const int32_t*)&L.jobs[j];
+    int32_t* dst = (int32_t*)&job;
+    for (int i = threadIdx.x; i < (int)(sizeof(SortJob) / 4); i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t n = clamp_rows(*job.n_in, job.in_cap);
+        seg[0] = lower_bound_i32(job.in, n, v);
+        seg[1] = lower_bound_i32(job.in, n, v + 1);
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L) {
     extern __shared__ int32_t lds[];
+    __shared__ SortJob job;
     __shared__ int64_t s_seg[2];
     const int tid = threadIdx.x;
-    const int64_t n = seg_rows(a);
-    const int k = a.k, kp = a.kp;
-    const int64_t n_items = a.list ? (int64_t)*a.list_n : (int64_t)(a.v_end - a.v_begin);
-    int32_t* rows = lds;
-    uint32_t* idx = (uint32_t*)(lds + (size_t)a.lds_rows * kp);
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int32_t v = a.list ? a.list[item] : a.v_begin + (int32_t)item;
-        if (tid == 0) {
-            s_seg[0] = lower_bound_i32(a.in, n, v);
-            s_seg[1] = lower_bound_i32(a.in, n, v + 1);
-        }
-        __syncthreads();
+    const int64_t n_items = L.list ? (int64_t)*L.list_n : (int64_t)L.n_jobs * L.n_vertices;
+    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int64_t item = L.list ? (int64_t)L.list[it] : it;
+        sort_item_setup(L, item, job, s_seg);
         const int64_t seg0 = s_seg[0], seg1 = s_seg[1];
-        const int64_t L = seg1 - seg0;
+        const int64_t L_ = seg1 - seg0;
+        const int k = job.k, kp = job.kp;
+        const int lds_rows = lds_rows_of(L.lds_bytes, kp);
         __syncthreads();
-        if (L == 0 || seg0 >= a.out_rows) continue;
-        if (L > a.lds_rows) {
-            if (tid == 0) {
-                const int32_t p = atomicAdd(a.spill_n, 1);
-                a.spill[p] = v;
-            }
+        if (L_ == 0 || seg0 >= job.out_rows) continue;
+        if (L_ > lds_rows) {
+            if (tid == 0) L.spill[atomicAdd(L.spill_n, 1)] = (int32_t)item;
             continue;
         }
+        int32_t* rows = lds;
+        uint32_t* idx = (uint32_t*)(lds + (size_t)lds_rows * kp);
         for (int j = 0; j < k; j++) {
-            const int32_t* src = a.in + (int64_t)a.perm[j] * a.in_stride + seg0;
-            for (int r = tid; r < L; r += kSortBlock) rows[r * kp + j] = src[r];
+            const int32_t* src = job.in + (int64_t)job.perm[j] * job.in_stride + seg0;
+            for (int r = tid; r < L_; r += kSortBlock) rows[r * kp + j] = src[r];
         }
         int P = 1;
-        while (P < L) P <<= 1;
-        for (int i = tid; i < P; i += kSortBlock) idx[i] = i < L ? (uint32_t)i : kSent;
+        while (P < L_) P <<= 1;
+        for (int i = tid; i < P; i += kSortBlock) idx[i] = i < L_ ? (uint32_t)i : kSent;
         __syncthreads();
         for (int size = 2; size <= P; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -407,11 +581,11 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortArgs a) 
                 __syncthreads();
             }
         }
-        for (int r = tid + 1; r < L; r += kSortBlock)
-            if (!lds_row_less(rows, kp, k, idx[r - 1], idx[r])) atomicAdd(a.dup_count, 1);
-        const int64_t Lw = (seg0 + L <= a.out_rows) ? L : (a.out_rows - seg0);
+        for (int r = tid + 1; r < L_; r += kSortBlock)
+            if (!lds_row_less(rows, kp, k, idx[r - 1], idx[r])) atomicAdd(L.dup_count, 1);
+        const int64_t Lw = (seg0 + L_ <= job.out_rows) ? L_ : (job.out_rows - seg0);
         const int64_t total = Lw * k;
-        int32_t* dst = a.out + seg0 * k;
+        int32_t* dst = job.out + seg0 * k;
         for (int64_t e = tid; e < total; e += kSortBlock) {
             const int64_t r = e / k;
             const int j = (int)(e - r * k);
@@ -422,9 +596,9 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortArgs a) 
 }
 
 // Global-memory tier for segments larger than any LDS tile: bitonic sort of
-// row indices in scratch (2 * rows entries, disjoint per segment), comparing
-// rows straight from the input columns.
-__device__ __forceinline__ bool glb_row_less(const SortArgs& a, int64_t seg0, uint32_t x, uint32_t y) {
+// row indices in the job's scratch (2 * rows entries, disjoint per
+// segment), comparing rows straight from the input columns.
+__device__ __forceinline__ bool glb_row_less(const SortJob& a, int64_t seg0, uint32_t x, uint32_t y) {
     for (int j = 1; j < a.k; j++) {
         const int32_t* c = a.in + (int64_t)a.perm[j] * a.in_stride + seg0;
         const int32_t p = c[x], q = c[y];
@@ -433,27 +607,23 @@ __device__ __forceinline__ bool glb_row_less(const SortArgs& a, int64_t seg0, ui
     return false;
 }
 
-__global__ __launch_bounds__(kSortBlock) void sort_global_kernel(const SortArgs a) {
+__global__ __launch_bounds__(kSortBlock) void sort_global_kernel(const SortLaunch L) {
+    __shared__ SortJob job;
     __shared__ int64_t s_seg[2];
     const int tid = threadIdx.x;
-    const int64_t n = seg_rows(a);
-    const int k = a.k;
-    const int64_t n_items = (int64_t)*a.list_n;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int32_t v = a.list[item];
-        if (tid == 0) {
-            s_seg[0] = lower_bound_i32(a.in, n, v);
-            s_seg[1] = lower_bound_i32(a.in, n, v + 1);
-        }
-        __syncthreads();
+    const int64_t n_items = (int64_t)*L.list_n;
+    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int64_t item = (int64_t)L.list[it];
+        sort_item_setup(L, item, job, s_seg);
         const int64_t seg0 = s_seg[0], seg1 = s_seg[1];
-        const int64_t L = seg1 - seg0;
+        const int64_t L_ = seg1 - seg0;
+        const int k = job.k;
         __syncthreads();
-        if (L == 0 || seg0 >= a.out_rows) continue;
-        uint32_t* idx = a.scratch_idx + 2 * seg0;
+        if (L_ == 0 || seg0 >= job.out_rows) continue;
+        uint32_t* idx = job.scratch_idx + 2 * seg0;
         int64_t P = 1;
-        while (P < L) P <<= 1;
-        for (int64_t i = tid; i < P; i += kSortBlock) idx[i] = i < L ? (uint32_t)i : kSent;
+        while (P < L_) P <<= 1;
+        for (int64_t i = tid; i < P; i += kSortBlock) idx[i] = i < L_ ? (uint32_t)i : kSent;
         __threadfence_block();
         __syncthreads();
         for (int64_t size = 2; size <= P; size <<= 1) {
@@ -466,7 +636,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_global_kernel(const SortArgs 
                     bool gt;
                     if (ia == kSent) gt = (ib != kSent);
                     else if (ib == kSent) gt = false;
-                    else gt = glb_row_less(a, seg0, ib, ia);
+                    else gt = glb_row_less(job, seg0, ib, ia);
                     if (gt == asc) {
                         idx[lo] = ib;
                         idx[hi] = ia;
@@ -476,15 +646,15 @@ __global__ __launch_bounds__(kSortBlock) void sort_global_kernel(const SortArgs 
                 __syncthreads();
             }
         }
-        for (int64_t r = tid + 1; r < L; r += kSortBlock)
-            if (!glb_row_less(a, seg0, idx[r - 1], idx[r])) atomicAdd(a.dup_count, 1);
-        const int64_t Lw = (seg0 + L <= a.out_rows) ? L : (a.out_rows - seg0);
+        for (int64_t r = tid + 1; r < L_; r += kSortBlock)
+            if (!glb_row_less(job, seg0, idx[r - 1], idx[r])) atomicAdd(L.dup_count, 1);
+        const int64_t Lw = (seg0 + L_ <= job.out_rows) ? L_ : (job.out_rows - seg0);
         const int64_t total = Lw * k;
-        int32_t* dst = a.out + seg0 * k;
+        int32_t* dst = job.out + seg0 * k;
         for (int64_t e = tid; e < total; e += kSortBlock) {
             const int64_t r = e / k;
             const int j = (int)(e - r * k);
-            dst[e] = a.in[(int64_t)a.perm[j] * a.in_stride + seg0 + idx[r]];
+            dst[e] = job.in[(int64_t)job.perm[j] * job.in_stride + seg0 + idx[r]];
         }
         __syncthreads();
     }
@@ -496,13 +666,13 @@ int sort_max_lds_bytes() {
         int dev = 0, v = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
-        v -= 256;  // static shared of the kernel
-        if (v > 160 * 1024 - 256) v = 160 * 1024 - 256;
-        if (v > 64 * 1024) {
+        v -= (int)sizeof(SortJob) + 64;  // static shared of the kernel
+        if (v > 160 * 1024 - 512) v = 160 * 1024 - 512;
+        if (v > 64 * 1024 - 512) {
             if (hipFuncSetAttribute((const void*)sort_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
                 hipSuccess) {
                 (void)hipGetLastError();
-                v = 64 * 1024 - 256;
+                v = 64 * 1024 - 512;
             }
         }
         cached = v;
@@ -510,12 +680,12 @@ int sort_max_lds_bytes() {
     return cached;
 }
 
-hipError_t launch_sort_lds(const SortArgs& a, int grid, int lds_bytes, hipStream_t s) {
+hipError_t launch_sort_lds(const SortLaunch& a, int grid, int lds_bytes, hipStream_t s) {
     hipLaunchKernelGGL(sort_lds_kernel, dim3(grid), dim3(kSortBlock), lds_bytes, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_sort_global(const SortArgs& a, int grid, hipStream_t s) {
+hipError_t launch_sort_global(const SortLaunch& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(sort_global_kernel, dim3(grid), dim3(kSortBlock), 0, s, a);
     return hipGetLastError();
 }

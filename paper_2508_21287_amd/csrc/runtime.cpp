@@ -49,6 +49,8 @@ dm_status Workspace::init(hipStream_t s) {
     std::memset(ctrl_h, 0, sizeof(Control));
     DM_HIP(hipEventCreate(&ev[0]));
     DM_HIP(hipEventCreate(&ev[1]));
+    DM_TRY(dev_alloc((void**)&job_d, sizeof(SortJob), s));
+    DM_HIP(hipHostMalloc((void**)&job_h, sizeof(SortJob), hipHostMallocDefault));
     epoch = 0;
     return DM_OK;
 }
@@ -68,6 +70,10 @@ void Workspace::release() {
     if (stream) (void)hipStreamSynchronize(stream);
     if (ctrl_h) (void)hipHostFree(ctrl_h);
     ctrl_h = nullptr;
+    dev_free(job_d, stream);
+    job_d = nullptr;
+    if (job_h) (void)hipHostFree(job_h);
+    job_h = nullptr;
     for (int i = 0; i < 2; i++)
         if (ev[i]) (void)hipEventDestroy(ev[i]), ev[i] = nullptr;
     for (auto e : prof) (void)hipEventDestroy(e);
@@ -146,6 +152,39 @@ static int ejf_grid(int64_t in_cap, double est_in, int block) {
     g = std::min<int64_t>(g, 2048);
     g = std::min<int64_t>(g, std::max<int64_t>(tiles_cap, 1));
     return (int)std::max<int64_t>(g, 1);
+}
+
+dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
+                       int32_t v0, int32_t* spill_n, int32_t* dup) {
+    hipStream_t s = ws.stream;
+    const int64_t items = (int64_t)n_jobs * nv;
+    if (items >= (int64_t)INT32_MAX) return fail(DM_ERR_UNSUPPORTED, "batch too large: patterns x vertices >= 2^31");
+    DM_TRY(ws.ensure_spill(items + 1));
+    SortLaunch L;
+    std::memset(&L, 0, sizeof L);
+    L.jobs = jobs_d;
+    L.n_jobs = n_jobs;
+    L.n_vertices = nv;
+    L.v_begin = v0;
+    L.dup_count = dup;
+    // tier 1: small LDS tiles, many workgroups per CU
+    L.lds_bytes = 16 * 1024;
+    L.list = nullptr;
+    L.spill = ws.spill;
+    L.spill_n = &spill_n[0];
+    DM_HIP(launch_sort_lds(L, (int)std::min<int64_t>(std::max<int64_t>(items, 1), 8192), L.lds_bytes, s));
+    // tier 2: the largest LDS allocation a workgroup can hold
+    L.lds_bytes = ctx->sort_lds_max;
+    L.list = ws.spill;
+    L.list_n = &spill_n[0];
+    L.spill = ws.spill + ws.spill_cap;
+    L.spill_n = &spill_n[1];
+    DM_HIP(launch_sort_lds(L, 256, L.lds_bytes, s));
+    // tier 3: global memory
+    L.list = ws.spill + ws.spill_cap;
+    L.list_n = &spill_n[1];
+    DM_HIP(launch_sort_global(L, 128, s));
+    return DM_OK;
 }
 
 dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const Plan& plan,
@@ -270,45 +309,22 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             dev_free(result, s);
             result = nullptr;
             DM_TRY(dev_alloc((void**)&result, sizeof(int32_t) * (size_t)std::max<int64_t>(out_rows * k, 1), s));
-            DM_TRY(ws.ensure_spill(dg->n + 1));
             DM_TRY(ws.ensure_sort_scratch(2 * rows_cap + 2));
-            SortArgs sa;
-            std::memset(&sa, 0, sizeof sa);
-            sa.in = ws.buf[lb];
-            sa.in_stride = cap[lb];
-            sa.in_cap = cap[lb];
-            sa.n_in = &ws.ctrl_d->counts[nsteps];
-            sa.k = k;
-            sa.kp = (k % 2 == 0) ? k + 1 : k;
-            for (int j = 0; j < k; j++) sa.perm[j] = (uint8_t)plan.col_of[j];
-            sa.v_begin = v0;
-            sa.v_end = v1;
-            sa.out = result;
-            sa.out_rows = out_rows;
-            sa.scratch_idx = ws.sort_scratch;
-            sa.dup_count = &ws.ctrl_d->dup;
-            // tier 1: small LDS tiles (many workgroups per CU)
-            const int b1 = 16 * 1024;
-            sa.lds_rows = lds_rows_for(b1, sa.kp);
-            sa.list = nullptr;
-            sa.spill = ws.spill;
-            sa.spill_n = &ws.ctrl_d->spill_n[0];
-            int lds1 = 4 * (sa.lds_rows * sa.kp + sa.lds_rows);
+            SortJob& job = *ws.job_h;
+            std::memset(&job, 0, sizeof job);
+            job.in = ws.buf[lb];
+            job.in_stride = cap[lb];
+            job.in_cap = cap[lb];
+            job.n_in = &ws.ctrl_d->counts[nsteps];
+            job.out = result;
+            job.out_rows = out_rows;
+            job.scratch_idx = ws.sort_scratch;
+            job.k = k;
+            job.kp = (k % 2 == 0) ? k + 1 : k;
+            for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
+            DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps], s));
-            DM_HIP(launch_sort_lds(sa, std::min(std::max(v1 - v0, 1), 4096), lds1, s));
-            // tier 2: the whole LDS of a CU
-            const int b2 = ctx->sort_lds_max;
-            sa.lds_rows = lds_rows_for(b2, sa.kp);
-            sa.list = ws.spill;
-            sa.list_n = &ws.ctrl_d->spill_n[0];
-            sa.spill = ws.spill + ws.spill_cap;
-            sa.spill_n = &ws.ctrl_d->spill_n[1];
-            int lds2 = 4 * (sa.lds_rows * sa.kp + sa.lds_rows);
-            DM_HIP(launch_sort_lds(sa, 256, lds2, s));
-            // tier 3: global memory
-            sa.list = ws.spill + ws.spill_cap;
-            sa.list_n = &ws.ctrl_d->spill_n[1];
-            DM_HIP(launch_sort_global(sa, 128, s));
+            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, ws.ctrl_d->spill_n, &ws.ctrl_d->dup));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps + 1], s));
         }
         DM_HIP(hipEventRecord(ws.ev[1], s));
@@ -949,7 +965,9 @@ dm_status dm_result_stats(const dm_result* r, dm_run_stats* out) {
 
 void dm_result_free(dm_result* r) {
     if (!r) return;
-    if (r->data) {
+    if (r->block) {
+        r->block.reset();
+    } else if (r->data) {
         (void)hipSetDevice(r->ctx->device);
         dev_free(r->data, r->stream);
     }

@@ -61,6 +61,8 @@ struct Workspace {
     int64_t sort_scratch_elems = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> prof;  // event pairs for per-launch timing
+    SortJob* job_d = nullptr;      // one sort job (plain path) and its pinned staging
+    SortJob* job_h = nullptr;
 
     dm_status init(hipStream_t s);
     void release();
@@ -127,6 +129,7 @@ struct dm_result {
     int64_t rows = 0;
     int64_t total = 0;
     int32_t* data = nullptr;  // device, row-major
+    std::shared_ptr<void> block;  // batched results share one allocation (data points inside)
     hipStream_t stream = nullptr;
     int32_t mode = DM_OUT_TABLE;
     uint64_t hsum = 0, hxor = 0;
@@ -159,6 +162,11 @@ struct RunOutput {
 
 dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const Plan& plan,
                    const RunOptions& opt, RunOutput* out);
+
+// Canonicalize n_jobs final tables (jobs already in device memory): three
+// sort tiers on ws.stream; spill_n[0..1] and *dup must be zero beforehand.
+dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
+                       int32_t v0, int32_t* spill_n, int32_t* dup);
 
 dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan);
 RunOptions run_options(const dm_plan_opts* opts, int64_t cap);

@@ -287,3 +287,48 @@ def test_to_torch(ctx):
         want, _ = oracle.enumerate_embeddings(g.n, g.edges, pats[0].n, pats[0].edges)
         assert np.array_equal(t.cpu().numpy(), want)
     dg.free()
+
+
+def test_batch_config4_subset(ctx):
+    g, pats = W.config4(48)
+    dg = ctx.datagraph(g.n, g.edges)
+    res = dg.enumerate_batch([(p.n, p.edges) for p in pats])
+    for p, r in zip(pats, res):
+        say(f"batch cfg4 {p.name}")
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+        assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
+        r.free()
+    dg.free()
+
+
+def test_batch_hash_and_overflow(ctx):
+    g, pats = W.config2(12)
+    dg = ctx.datagraph(g.n, g.edges)
+    specs = [(p.n, p.edges) for p in pats]
+    res = dg.enumerate_batch(specs, mode=dm.OUT_COUNT_HASH)
+    for p, r in zip(pats, res):
+        assert (r.total,) + r.hash() == oracle.count_hash(g.n, g.edges, p.n, p.edges), p.name
+        r.free()
+    # tiny first-attempt tables: every pattern overflows and is redone exactly
+    res = dg.enumerate_batch(specs, initial_rows=300)
+    for p, r in zip(pats, res):
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+        assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
+        r.free()
+    dg.free()
+
+
+def test_batch_mixed_shapes(ctx):
+    # wider than the persistent kernel's 64 input columns, 1-vertex, too large,
+    # and ordinary patterns in one call
+    n = 90
+    cyc = W.cycle(n)
+    g = W.Graph(n, cyc.edges, "C90")
+    dg = ctx.datagraph(g.n, g.edges)
+    pats = [W.path(70), W.path(1), W.path(91), W.path(5), W.cycle(90), W.star(2)]
+    res = dg.enumerate_batch([(p.n, p.edges) for p in pats], caps=[-1, 10, -1, 3, -1, -1])
+    for p, r, cap in zip(pats, res, [-1, 10, -1, 3, -1, -1]):
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, cap=cap)
+        assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
+        r.free()
+    dg.free()
