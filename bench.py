@@ -35,6 +35,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--mode", choices=["batch", "plain"], default="batch")
+    ap.add_argument("--no-serve", dest="serve", action="store_false",
+                    help="skip the served-trace measurement")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -58,6 +62,85 @@ def cpu_baseline(g, pats, budget_s=10.0):
             "sample": f"all 64 patterns x {reps} repetitions ({el:.1f} s), count+hash mode, 1 thread"}
 
 
+def serve_trace(dm, ctx, g, pats, rate=4000.0, n_queries=512, seed=4000):
+    """Open-loop Poisson trace of the benchmark patterns through the server
+    (continuous batching, 2 streams) vs the same trace solved one query at a
+    time with plain per-pattern runs (FIFO, no overlap).  Latency = completion
+    - arrival."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_queries))
+    order = rng.integers(0, len(pats), size=n_queries)
+    caps = rng.choice(np.array([1, 1000, -1]), size=n_queries)
+    dg = dm.DataGraph(ctx, g.n, g.edges)
+
+    def run_server():
+        srv = dm.Server(dg, n_streams=2, max_batch=64)
+        import threading
+        done = {}
+        tickets = []
+        t0 = time.perf_counter()
+
+        def waiter():
+            # poll every outstanding ticket (timeout 0) so completions are
+            # seen in whatever order they happen
+            pending = set()
+            seen = 0
+            while len(done) < n_queries:
+                while seen < len(tickets):
+                    pending.add(seen)
+                    seen += 1
+                for i in list(pending):
+                    try:
+                        r = srv.wait(tickets[i], 0)
+                    except dm.DMError as e:
+                        if e.code == -10:  # not finished yet
+                            continue
+                        raise
+                    done[i] = time.perf_counter() - t0
+                    r.free()
+                    pending.discard(i)
+                time.sleep(0.0001)
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        for i in range(n_queries):
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
+            p = pats[order[i]]
+            tickets.append(srv.submit(p.n, p.edges, int(caps[i])))
+        th.join()
+        el = time.perf_counter() - t0
+        srv.stop()
+        lat = np.array([done[i] - arrivals[i] for i in range(n_queries)])
+        return lat, el
+
+    def run_plain():
+        t0 = time.perf_counter()
+        fin = []
+        for i in range(n_queries):
+            now = time.perf_counter() - t0
+            if now < arrivals[i]:
+                while time.perf_counter() - t0 < arrivals[i]:
+                    pass
+            p = pats[order[i]]
+            r = dg.enumerate(p.n, p.edges, int(caps[i]))
+            r.free()
+            fin.append(time.perf_counter() - t0)
+        el = time.perf_counter() - t0
+        return np.array(fin) - arrivals, el
+
+    run_server()  # warm-up
+    lat_s, el_s = run_server()
+    lat_p, el_p = run_plain()
+    dg.free()
+    return {"trace": f"{n_queries} queries, Poisson {rate:.0f}/s, caps {{1,1000,all}}, same 64 patterns",
+            "p50_ms": 1e3 * float(np.percentile(lat_s, 50)), "p99_ms": 1e3 * float(np.percentile(lat_s, 99)),
+            "qps": n_queries / el_s,
+            "plain_p50_ms": 1e3 * float(np.percentile(lat_p, 50)),
+            "plain_p99_ms": 1e3 * float(np.percentile(lat_p, 99)), "plain_qps": n_queries / el_p}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -65,6 +148,15 @@ def main():
               "(the multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibrate:
+        n = args.copy_calibrate << 18  # int32 elements
+        a = torch.ones(n, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+        return
     import paper_2508_21287_amd as dm
     from paper_2508_21287_amd import workloads as W
 
@@ -131,6 +223,8 @@ def main():
     tq = time.perf_counter() - tq
     dg.free()
 
+    served = serve_trace(dm, ctx, g, pats) if args.serve else None
+
     ach = (join_bytes / 1e9) / (join_ms / 1e3) if join_ms > 0 else 0.0
     out = {
         "metric": "embeddings/sec + achieved HBM GB/s; batched/served vs plain per-pattern runs",
@@ -159,6 +253,8 @@ def main():
                      "bytes_per_launch": join_bytes / max(join_launches, 1)},
         "sort": {"ms_total": sort_ms, "bytes": sort_bytes},
     }
+    if served is not None:
+        out["served"] = served
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, pats)
     print(json.dumps(out), flush=True)

@@ -241,7 +241,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             RunOptions ro = run_options(opts, it.cap);
             ro.sync_each_step = true;
             RunOutput o;
-            DM_TRY(run_plan(ctx, ws, dg, it.plan, ro, &o));
+            DM_TRY(run_plan_chunked(ctx, ws, dg, it.plan, ro, &o));
             r = new dm_result();
             r->ctx = ctx;
             r->width = it.k;

@@ -192,7 +192,8 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
     (void)ctx;
     hipStream_t s = ws.stream;
     const int k = plan.k;
-    const int32_t v0 = 0, v1 = dg->n;
+    const int32_t v0 = opt.root_end > opt.root_begin ? opt.root_begin : 0;
+    const int32_t v1 = opt.root_end > opt.root_begin ? opt.root_end : dg->n;
     std::vector<StepDesc> steps;
     std::vector<double> est;
     for (auto& ps : plan.steps) {
@@ -211,8 +212,13 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
     if (nsteps > kMaxSteps) return fail(DM_ERR_UNSUPPORTED, "plan has too many steps");
     const bool hash_mode = opt.mode == DM_OUT_COUNT_HASH;
 
-    double est_max = (double)dg->n;
-    for (double e : est) est_max = std::max(est_max, e);
+    // the planner's estimates are for every root; scale them to this range
+    const double frac = dg->n > 0 ? (double)(v1 - v0) / dg->n : 1.0;
+    double est_max = (double)(v1 - v0);
+    for (double& e : est) {
+        e *= frac;
+        est_max = std::max(est_max, e);
+    }
     int64_t budget = opt.mem_budget > 0 ? opt.mem_budget : (int64_t)48 << 30;
     int64_t budget_rows = std::max<int64_t>(budget / (int64_t)(8 * k), 1024);
     // first attempt: twice the estimate, at most 1 GiB per table; a larger
@@ -411,6 +417,129 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         *out = o;
         return DM_OK;
     }
+}
+
+// Partition schedule over root ranges.  Tables stay grouped by the root image
+// in ascending order, so running the plan on consecutive root ranges and
+// concatenating the sorted outputs gives the full sorted table.  Ranges are
+// split when an intermediate table would exceed the memory budget, and a cap
+// is served from the lowest ranges first (early exit).
+dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const Plan& plan,
+                           const RunOptions& opt, RunOutput* out) {
+    const int32_t n = dg->n;
+    const bool hash_mode = opt.mode == DM_OUT_COUNT_HASH;
+    if (!opt.sort && !hash_mode) return run_plan(ctx, ws, dg, plan, opt, out);
+    std::vector<std::pair<int32_t, int32_t>> todo;  // stack, top = lowest range
+    // a cap far below the predicted total: start with small root ranges
+    int32_t first_chunk = n;
+    if (opt.cap >= 0 && !hash_mode && plan.est_final_rows > 0) {
+        const double per_root = plan.est_final_rows / std::max(n, 1);
+        const double want = 4.0 * std::max<double>((double)opt.cap, 1.0) + 1024.0;
+        if (per_root * n > 4.0 * want) first_chunk = (int32_t)std::max(1.0, std::min((double)n, want / per_root));
+    }
+    for (int64_t b = n; b > 0; b -= first_chunk) {
+        const int32_t lo = (int32_t)std::max<int64_t>(0, b - first_chunk);
+        todo.emplace_back(lo, (int32_t)b);
+    }
+    hipStream_t s = ws.stream;
+    std::vector<RunOutput> parts;
+    auto free_parts = [&]() {
+        for (auto& p : parts) dev_free(p.sorted, s);
+        parts.clear();
+    };
+    int64_t got = 0;
+    bool early = false;
+    int splits = 0;
+    while (!todo.empty()) {
+        auto rg = todo.back();
+        todo.pop_back();
+        RunOptions o2 = opt;
+        o2.root_begin = rg.first;
+        o2.root_end = rg.second;
+        if (opt.cap >= 0) o2.cap = std::max<int64_t>(opt.cap - got, 0);
+        RunOutput part;
+        dm_status st = run_plan(ctx, ws, dg, plan, o2, &part);
+        if (st == DM_ERR_BUDGET_EXCEEDED && rg.second - rg.first > 1) {
+            // split into four sub-ranges, lowest on top of the stack
+            const int32_t len = rg.second - rg.first;
+            const int32_t q = std::max(1, (len + 3) / 4);
+            std::vector<std::pair<int32_t, int32_t>> sub;
+            for (int32_t a = rg.first; a < rg.second; a += q) sub.emplace_back(a, std::min(rg.second, a + q));
+            for (auto it = sub.rbegin(); it != sub.rend(); ++it) todo.push_back(*it);
+            splits++;
+            continue;
+        }
+        if (st != DM_OK) {
+            free_parts();
+            return st;
+        }
+        parts.push_back(part);
+        got += hash_mode ? part.rows : part.sorted_rows;
+        if (opt.cap >= 0 && !hash_mode && got >= opt.cap && !todo.empty()) {
+            early = true;
+            break;
+        }
+    }
+    if (parts.size() == 1 && !early) {
+        *out = parts[0];
+        out->stats.chunks = 1;
+        out->stats.retries += splits;
+        return DM_OK;
+    }
+    RunOutput o;
+    o.stats = parts.empty() ? RunOutput().stats : parts[0].stats;
+    o.stats.chunks = (int32_t)parts.size();
+    o.stats.retries = splits;
+    int64_t total = 0, rows = 0;
+    double dev_ms = 0, join_ms = 0, sort_ms = 0;
+    int64_t jb = 0, sb = 0;
+    for (auto& p : parts) {
+        total += p.rows;
+        rows += p.sorted_rows;
+        o.hsum += p.hsum;
+        o.hxor ^= p.hxor;
+        dev_ms += p.stats.device_ms;
+        join_ms += p.stats.join_ms;
+        sort_ms += p.stats.sort_ms;
+        jb += p.stats.join_bytes;
+        sb += p.stats.sort_bytes;
+    }
+    o.stats.device_ms = dev_ms;
+    o.stats.join_ms = join_ms;
+    o.stats.sort_ms = sort_ms;
+    o.stats.join_bytes = jb;
+    o.stats.sort_bytes = sb;
+    o.stats.bytes_moved = jb + sb;
+    o.rows = early ? -1 : total;
+    if (!hash_mode) {
+        const int64_t keep = opt.cap >= 0 ? std::min<int64_t>(opt.cap, rows) : rows;
+        int32_t* dst = nullptr;
+        dm_status st = dev_alloc((void**)&dst, sizeof(int32_t) * (size_t)std::max<int64_t>(keep * plan.k, 1), s);
+        if (st != DM_OK) {
+            free_parts();
+            return st;
+        }
+        int64_t at = 0;
+        for (auto& p : parts) {
+            const int64_t r = std::min<int64_t>(p.sorted_rows, keep - at);
+            if (r > 0) {
+                hipError_t e = hipMemcpyAsync(dst + at * plan.k, p.sorted, sizeof(int32_t) * (size_t)(r * plan.k),
+                                              hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) {
+                    dev_free(dst, s);
+                    free_parts();
+                    return hip_fail(e, "hipMemcpyAsync");
+                }
+            }
+            at += std::max<int64_t>(r, 0);
+        }
+        free_parts();
+        DM_HIP(hipStreamSynchronize(s));
+        o.sorted = dst;
+        o.sorted_rows = keep;
+    }
+    *out = o;
+    return DM_OK;
 }
 
 }  // namespace dm
@@ -870,7 +999,7 @@ dm_status enumerate_one(dm_datagraph* dg, Workspace& ws, const dm_graph_desc* gp
     auto t1 = std::chrono::steady_clock::now();
     RunOptions ro = run_options(opts, cap);
     RunOutput o;
-    DM_TRY(run_plan(dg->ctx, ws, dg, plan, ro, &o));
+    DM_TRY(run_plan_chunked(dg->ctx, ws, dg, plan, ro, &o));
     auto* r = new dm_result();
     r->ctx = dg->ctx;
     r->width = p.k;

@@ -147,6 +147,8 @@ struct RunOptions {
     bool sort = true;          // canonicalize (false: keep plan-order SoA, for motif tables)
     bool profile = false;      // time each launch with events
     int64_t initial_rows = 0;  // first-attempt table capacity (0 = estimate)
+    int32_t root_begin = 0;    // root range [root_begin, root_end) of the identity table;
+    int32_t root_end = 0;      // empty range = every data vertex
 };
 
 // Output of one plan execution on one workspace.
@@ -162,6 +164,11 @@ struct RunOutput {
 
 dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const Plan& plan,
                    const RunOptions& opt, RunOutput* out);
+// run_plan over root ranges: splits a range whose tables exceed the memory
+// budget, serves a cap from the lowest ranges first; out.rows = -1 when a
+// cap stopped before every range was counted.
+dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const Plan& plan,
+                           const RunOptions& opt, RunOutput* out);
 
 // Canonicalize n_jobs final tables (jobs already in device memory): three
 // sort tiers on ws.stream; spill_n[0..1] and *dup must be zero beforehand.
