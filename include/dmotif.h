@@ -112,6 +112,9 @@ typedef struct {
     int32_t reserved_;
     int64_t initial_rows;  /* first-attempt capacity of each intermediate table in rows; 0 = from the
                               planner's estimate.  Too small only costs a re-run with exact sizes. */
+    int32_t root_begin;    /* keep only embeddings with f(0) in [root_begin, root_end); */
+    int32_t root_end;      /* root_end <= root_begin = every data vertex.  Disjoint root ranges
+                              partition the result (a shard of one pattern's enumeration). */
 } dm_plan_opts;
 
 typedef struct dm_context dm_context;

@@ -55,6 +55,10 @@ def load(path: str = LIB) -> C.CDLL:
         lib.oracle_enumerate.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
                                          C.c_int64, C.POINTER(i32p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_int64)]
+        lib.oracle_enumerate_range.restype = C.c_int
+        lib.oracle_enumerate_range.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
+                                               C.c_int64, C.c_int32, C.c_int32, C.POINTER(i32p),
+                                               C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         lib.oracle_count_hash.restype = C.c_int
         lib.oracle_count_hash.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
                                           C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
@@ -97,15 +101,21 @@ def normalize(n: int, edges, lib: C.CDLL | None = None):
 
 
 def enumerate_embeddings(n_d: int, edges_d, n_p: int, edges_p, cap: int = -1,
-                         lib: C.CDLL | None = None):
+                         lib: C.CDLL | None = None, root_range=None):
     """Return ``(rows[int32, n x n_p], total)``: the lexicographically first
-    ``cap`` embeddings (all when ``cap < 0``) and the full count."""
+    ``cap`` embeddings (all when ``cap < 0``) and the full count; with
+    ``root_range=(lo, hi)`` only embeddings with ``f(0)`` in ``[lo, hi)``."""
     lib = lib or load()
     ed, ep = _edges(edges_d), _edges(edges_p)
     rows = C.POINTER(C.c_int32)()
     n_rows, total = C.c_int64(0), C.c_int64(0)
-    rc = lib.oracle_enumerate(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep), cap,
-                              C.byref(rows), C.byref(n_rows), C.byref(total))
+    if root_range is None:
+        rc = lib.oracle_enumerate(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep), cap,
+                                  C.byref(rows), C.byref(n_rows), C.byref(total))
+    else:
+        rc = lib.oracle_enumerate_range(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep), cap,
+                                        int(root_range[0]), int(root_range[1]),
+                                        C.byref(rows), C.byref(n_rows), C.byref(total))
     if rc != 0:
         raise OracleError(rc)
     try:

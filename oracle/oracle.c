@@ -167,6 +167,7 @@ typedef struct {
     int32_t *back_ptr;
     int32_t *f;       /* pattern vertex -> data vertex */
     uint8_t *used;    /* data vertex -> in use */
+    int32_t root_lo, root_hi; /* images allowed for pattern vertex 0 */
     /* output */
     int stream;       /* 1: only count + hash */
     int32_t *rows;
@@ -209,11 +210,11 @@ static void dfs(search_t *s, int32_t pos) {
     int32_t lo, hi;
     const int32_t *cand;
     if (pos == 0) {
-        lo = 0;
+        lo = s->root_lo;
 #if ORACLE_MUTANT == 3
-        hi = s->gd->n - 1; /* wrong: skips the last data vertex */
+        hi = s->root_hi - 1; /* wrong: skips the last data vertex */
 #else
-        hi = s->gd->n;
+        hi = s->root_hi;
 #endif
         cand = NULL;
     } else {
@@ -261,7 +262,7 @@ static int cmp_row(const void *a, const void *b) {
  * stream = 1 fills count/hsum/hxor only. */
 static int run(int32_t nd, int64_t md, const int32_t *ed,
                int32_t np, int64_t mp, const int32_t *ep,
-               int stream, int64_t cap,
+               int stream, int64_t cap, int32_t root_lo, int32_t root_hi,
                int32_t **rows_out, int64_t *rows_n_out, int64_t *total_out,
                uint64_t *hsum_out, uint64_t *hxor_out) {
     if (rows_out) *rows_out = NULL;
@@ -283,6 +284,10 @@ static int run(int32_t nd, int64_t md, const int32_t *ed,
     s.gp = &gp;
     s.k = np;
     s.stream = stream;
+    /* images of pattern vertex 0 restricted to [root_lo, root_hi) within [0, nd) */
+    s.root_lo = root_lo < 0 ? 0 : root_lo;
+    s.root_hi = root_hi > nd ? nd : root_hi;
+    if (s.root_hi < s.root_lo) s.root_hi = s.root_lo;
     s.order = (int32_t *)malloc(sizeof(int32_t) * (size_t)np);
     s.parent = (int32_t *)malloc(sizeof(int32_t) * (size_t)np);
     s.back_ptr = (int32_t *)calloc((size_t)np + 1, sizeof(int32_t));
@@ -382,14 +387,22 @@ int64_t oracle_normalize(int32_t n, int64_t m, const int32_t *edges,
 int oracle_enumerate(int32_t nd, int64_t md, const int32_t *ed,
                      int32_t np, int64_t mp, const int32_t *ep, int64_t cap,
                      int32_t **rows, int64_t *n_rows, int64_t *total) {
-    return run(nd, md, ed, np, mp, ep, 0, cap, rows, n_rows, total, NULL, NULL);
+    return run(nd, md, ed, np, mp, ep, 0, cap, 0, nd, rows, n_rows, total, NULL, NULL);
+}
+
+/* As oracle_enumerate, keeping only embeddings with f(0) in [root_lo, root_hi). */
+int oracle_enumerate_range(int32_t nd, int64_t md, const int32_t *ed,
+                           int32_t np, int64_t mp, const int32_t *ep, int64_t cap,
+                           int32_t root_lo, int32_t root_hi,
+                           int32_t **rows, int64_t *n_rows, int64_t *total) {
+    return run(nd, md, ed, np, mp, ep, 0, cap, root_lo, root_hi, rows, n_rows, total, NULL, NULL);
 }
 
 /* Streaming count + order-independent multiset hash (see header). */
 int oracle_count_hash(int32_t nd, int64_t md, const int32_t *ed,
                       int32_t np, int64_t mp, const int32_t *ep,
                       int64_t *count, uint64_t *hsum, uint64_t *hxor) {
-    return run(nd, md, ed, np, mp, ep, 1, -1, NULL, NULL, count, hsum, hxor);
+    return run(nd, md, ed, np, mp, ep, 1, -1, 0, nd, NULL, NULL, count, hsum, hxor);
 }
 
 /* Hash of one row given in pattern-vertex order (for table-side summaries). */

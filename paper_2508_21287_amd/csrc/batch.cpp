@@ -360,7 +360,8 @@ dm_status enumerate_many(dm_datagraph* dg, Workspace& ws, int32_t n, const dm_gr
         }
         int cm = 0;
         for (auto& d : it.steps) cm = std::max(cm, (int)d.c_in);
-        if (cm > kBatchMaxCols || (int)it.steps.size() > kMaxSteps) {
+        const bool ranged = opts && opts->root_end > opts->root_begin;
+        if (cm > kBatchMaxCols || (int)it.steps.size() > kMaxSteps || ranged) {
             solo.push_back(i);
             continue;
         }

@@ -510,12 +510,21 @@ __device__ __forceinline__ bool lds_row_less(const int32_t* rows, int kp, int k,
     return false;
 }
 
+// Rows of kp int32 that fit an LDS tile of lds_bytes together with the
+// 16-bit index array of the bitonic network (padded to a power of two).
 __device__ __forceinline__ int lds_rows_of(int lds_bytes, int kp) {
-    int r = lds_bytes / (4 * (kp + 1));
-    int p = 1;
-    while (p * 2 <= r) p *= 2;
-    return r >= 1 ? p : 0;
+    int r = lds_bytes / (4 * kp + 4);
+    if (r > 65535) r = 65535;
+    while (r > 0) {
+        int P = 1;
+        while (P < r) P <<= 1;
+        if (4 * kp * r + 2 * P <= lds_bytes) break;
+        r--;
+    }
+    return r;
 }
+
+constexpr uint16_t kSent16 = 0xFFFFu;
 
 // Load job j into LDS (all threads), then broadcast the segment of root v.
 __device__ __forceinline__ void sort_item_setup(const SortLaunch& L, int64_t item, SortJob& job, int64_t* seg) {
@@ -553,14 +562,14 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
             continue;
         }
         int32_t* rows = lds;
-        uint32_t* idx = (uint32_t*)(lds + (size_t)lds_rows * kp);
+        uint16_t* idx = (uint16_t*)(lds + (size_t)lds_rows * kp);
         for (int j = 0; j < k; j++) {
             const int32_t* src = job.in + (int64_t)job.perm[j] * job.in_stride + seg0;
             for (int r = tid; r < L_; r += kSortBlock) rows[r * kp + j] = src[r];
         }
         int P = 1;
         while (P < L_) P <<= 1;
-        for (int i = tid; i < P; i += kSortBlock) idx[i] = i < L_ ? (uint32_t)i : kSent;
+        for (int i = tid; i < P; i += kSortBlock) idx[i] = i < L_ ? (uint16_t)i : kSent16;
         __syncthreads();
         for (int size = 2; size <= P; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -568,10 +577,10 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
                     const int lo = 2 * t - (t & (stride - 1));
                     const int hi = lo + stride;
                     const bool asc = (lo & size) == 0;
-                    const uint32_t ia = idx[lo], ib = idx[hi];
+                    const uint16_t ia = idx[lo], ib = idx[hi];
                     bool gt;
-                    if (ia == kSent) gt = (ib != kSent);
-                    else if (ib == kSent) gt = false;
+                    if (ia == kSent16) gt = (ib != kSent16);
+                    else if (ib == kSent16) gt = false;
                     else gt = lds_row_less(rows, kp, k, ib, ia);
                     if (gt == asc) {
                         idx[lo] = ib;

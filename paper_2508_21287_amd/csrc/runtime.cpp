@@ -167,8 +167,8 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.n_vertices = nv;
     L.v_begin = v0;
     L.dup_count = dup;
-    // tier 1: small LDS tiles, many workgroups per CU
-    L.lds_bytes = 16 * 1024;
+    // tier 1: small LDS tiles, five workgroups per CU
+    L.lds_bytes = 32 * 1024 - 512;
     L.list = nullptr;
     L.spill = ws.spill;
     L.spill_n = &spill_n[0];
@@ -426,20 +426,28 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
 // is served from the lowest ranges first (early exit).
 dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const Plan& plan,
                            const RunOptions& opt, RunOutput* out) {
-    const int32_t n = dg->n;
     const bool hash_mode = opt.mode == DM_OUT_COUNT_HASH;
     if (!opt.sort && !hash_mode) return run_plan(ctx, ws, dg, plan, opt, out);
+    // the caller's root range (default: every data vertex)
+    const int32_t r0 = opt.root_end > opt.root_begin ? std::max(opt.root_begin, 0) : 0;
+    const int32_t r1 = opt.root_end > opt.root_begin ? std::min(opt.root_end, dg->n) : dg->n;
+    const int32_t n = std::max(r1 - r0, 0);
     std::vector<std::pair<int32_t, int32_t>> todo;  // stack, top = lowest range
     // a cap far below the predicted total: start with small root ranges
-    int32_t first_chunk = n;
-    if (opt.cap >= 0 && !hash_mode && plan.est_final_rows > 0) {
-        const double per_root = plan.est_final_rows / std::max(n, 1);
+    int32_t first_chunk = std::max(n, 1);
+    if (opt.cap >= 0 && !hash_mode && plan.est_final_rows > 0 && n > 0) {
+        const double per_root = plan.est_final_rows / std::max(dg->n, 1);
         const double want = 4.0 * std::max<double>((double)opt.cap, 1.0) + 1024.0;
         if (per_root * n > 4.0 * want) first_chunk = (int32_t)std::max(1.0, std::min((double)n, want / per_root));
     }
-    for (int64_t b = n; b > 0; b -= first_chunk) {
-        const int32_t lo = (int32_t)std::max<int64_t>(0, b - first_chunk);
+    for (int64_t b = r1; b > r0; b -= first_chunk) {
+        const int32_t lo = (int32_t)std::max<int64_t>(r0, b - first_chunk);
         todo.emplace_back(lo, (int32_t)b);
+    }
+    if (todo.empty()) {  // empty root range: an empty table
+        RunOutput o;
+        *out = o;
+        return DM_OK;
     }
     hipStream_t s = ws.stream;
     std::vector<RunOutput> parts;
@@ -960,6 +968,8 @@ RunOptions run_options(const dm_plan_opts* opts, int64_t cap) {
         o.mem_budget = opts->mem_budget;
         o.profile = opts->profile != 0;
         o.initial_rows = opts->initial_rows;
+        o.root_begin = opts->root_begin;
+        o.root_end = opts->root_end;
     }
     o.cap = cap;
     return o;

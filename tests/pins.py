@@ -357,6 +357,21 @@ def pin_hash(lib):
             assert (c, s, x) == (len(hs), sum(hs) & M64, xr), (g.name, p.name)
 
 
+def pin_root_ranges(lib):
+    """Disjoint root ranges partition the table: their row sets, in range
+    order, concatenate to the full table."""
+    g = W.heavy_hex(3, 9)
+    for p in [W.path(5), W.cycle(12), W.prufer_tree(6, 0)]:
+        full, total = rows_of(lib, g, p)
+        parts, acc = [], 0
+        for lo, hi in [(0, 5), (5, 6), (6, 20), (20, 32)]:
+            r, t = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, lib=lib, root_range=(lo, hi))
+            assert (r[:, 0] >= lo).all() and (r[:, 0] < hi).all()
+            parts.append(r)
+            acc += t
+        assert acc == total and np.array_equal(np.vstack(parts), full), p.name
+
+
 ALL_PINS = [pin_brute_force, pin_cycle_paths, pin_self_embedding, pin_heavy_hex_cells,
             pin_degree_sums, pin_grid_closed_forms, pin_nonbacktracking, pin_tree_dp,
-            pin_invariants, pin_cap, pin_edge_cases, pin_hash]
+            pin_invariants, pin_cap, pin_edge_cases, pin_hash, pin_root_ranges]
