@@ -142,9 +142,13 @@ __device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t (&v)[
 
 template <int BLOCK>
 struct TileShared {
+    static constexpr int CH = 8 * BLOCK;  // output rows staged per write pass
     int64_t base;
+    int32_t total;
     int32_t wsum[BLOCK / 64];
     int32_t wexcl[BLOCK / 64];
+    int32_t mrow[CH];   // motif row of each staged output row
+    uint8_t src[CH];    // input row (lane of the tile) of each staged output row
 };
 
 // One tile (BLOCK consecutive input rows) of a join-filter step: count the
@@ -237,28 +241,56 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
         const int64_t excl = lookback_wave(a.status, a.epoch, tile, (uint64_t)total, lane);
         if (lane == 0) {
             sh.base = excl;
+            sh.total = total;
             if (tile == n_tiles - 1) *a.n_out = excl + total;
             if (excl + total > a.out_cap) *a.overflow = 1;
         }
     }
     __syncthreads();
-    const int64_t off = sh.base + sh.wexcl[wid] + (x - cnt);
-    if (cnt > 0) {
-        int32_t r = 0;
-        for (int32_t m = lo; m < hi && r < cnt; m++) {
-            const bool ok = (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : ejf_accept<CMAX>(a, v, row, m, nv);
+    // Write phase.  Survivors are staged in LDS in output order as (input
+    // lane, motif row); then each thread assembles whole output rows and
+    // writes them column by column, so every store of a wave covers
+    // consecutive elements of one column (coalesced), instead of each lane
+    // scattering its own survivors.
+    constexpr int CH = TileShared<BLOCK>::CH;
+    const int32_t local0 = sh.wexcl[wid] + (x - cnt);
+    const int32_t total = sh.total;
+    const int64_t base = sh.base;
+    const int c_in = st.c_in, n_new = st.motif >= 0 ? st.n_new : 0;
+    const int64_t row0 = tile * BLOCK;
+    // each thread's candidate cursor survives across passes, so every
+    // candidate is visited once however many passes the tile needs
+    int32_t m_cur = lo, r_cur = 0;
+    for (int32_t w0 = 0; w0 < total; w0 += CH) {
+        while (r_cur < cnt && m_cur < hi) {
+            const int32_t li = local0 + r_cur;
+            if (li >= w0 + CH) break;  // belongs to a later pass
+            const int32_t m = m_cur++;
+            const bool ok =
+                (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : ejf_accept<CMAX>(a, v, row, m, nv);
             if (!ok) continue;
-            const int64_t o = off + r;
-            r++;
-            if (o >= a.out_cap) break;
-#pragma unroll
-            for (int c = 0; c < CMAX; c++)
-                if (c < st.c_in) a.out[(int64_t)c * a.out_stride + o] = v[c];
-            if (st.motif >= 0) {
-                for (int t = 0; t < st.n_new; t++)
-                    a.out[(int64_t)(st.c_in + t) * a.out_stride + o] = a.tbl.col[st.new_pos[t]][m];
-            }
+            sh.src[li - w0] = (uint8_t)tid;
+            sh.mrow[li - w0] = m;
+            r_cur++;
         }
+        __syncthreads();
+        const int32_t nrows = (total - w0 < CH) ? (total - w0) : CH;
+        const int64_t obase = base + w0;
+        for (int32_t o = tid; o < nrows; o += BLOCK) {
+            const int64_t orow = obase + o;
+            if (orow >= a.out_cap) break;
+            const int64_t irow = row0 + sh.src[o];
+            const int32_t m = sh.mrow[o];
+            if (a.in) {
+                for (int c = 0; c < c_in; c++)
+                    a.out[(int64_t)c * a.out_stride + orow] = a.in[(int64_t)c * a.in_stride + irow];
+            } else {
+                a.out[orow] = a.id_begin + (int32_t)irow;
+            }
+            for (int t = 0; t < n_new; t++)
+                a.out[(int64_t)(c_in + t) * a.out_stride + orow] = a.tbl.col[st.new_pos[t]][m];
+        }
+        __syncthreads();
     }
 }
 
@@ -352,8 +384,8 @@ hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s) {
 // step (or retires the pattern).  Every workgroup exits once all patterns
 // are retired, so the grid always drains.
 
-__device__ __forceinline__ int32_t ld_acq_i32(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int32_t ld_rlx_i32(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_rel_i32(int32_t* p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -388,12 +420,16 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
             for (int base = 0; base < N && !got; base += 64) {
                 const int q = (rot + base + lane) % N;
                 bool avail = false;
-                int32_t st = 0;
+                int32_t st = 0, nt = 0;
                 if (base + lane < N) {
-                    st = ld_acq_i32(&b.ctl[q].stage);
+                    // polling uses relaxed (per-location coherent) loads: an
+                    // acquire here would invalidate L1 on every poll
+                    st = ld_rlx_i32(&b.ctl[q].stage);
                     if (st < b.nsteps[q]) {
-                        const int32_t nt = ld_acq_i32(&b.ctl[q].ntiles[st]);
-                        avail = ld_acq_i32(&b.ctl[q].claim[st]) < nt;
+                        // ntiles[s] is written once (0 -> final) before stage s is
+                        // published, so a nonzero value is the final one
+                        nt = ld_rlx_i32(&b.ctl[q].ntiles[st]);
+                        avail = ld_rlx_i32(&b.ctl[q].claim[st]) < nt;
                     }
                 }
                 uint64_t m = __ballot(avail);
@@ -402,10 +438,11 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
                     m &= m - 1;
                     const int32_t qq = __shfl(q, l, 64);
                     const int32_t ss = __shfl(st, l, 64);
+                    const int32_t ntl = __shfl(nt, l, 64);
                     int32_t t = 0;
                     if (lane == 0) t = atomicAdd(&b.ctl[qq].claim[ss], 1);
                     t = __shfl(t, 0, 64);
-                    if (t < b.ctl[qq].ntiles[ss]) {
+                    if (t < ntl) {
                         p = qq;
                         s = ss;
                         tile = t;
@@ -415,7 +452,7 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
                 }
             }
             if (got) break;
-            if (ld_acq_i32(b.finished) >= N) {
+            if (ld_rlx_i32(b.finished) >= N) {
                 all_done = true;
                 break;
             }
