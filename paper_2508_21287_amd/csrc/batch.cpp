@@ -15,6 +15,9 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -29,9 +32,17 @@ using namespace dm;
 namespace {
 
 constexpr int kBatchTile = 64;       // rows per tile in the persistent kernel
-constexpr int kBatchMaxCols = 64;    // widest input table the persistent kernel holds in registers
+constexpr int kBatchMaxCols = 127;   // widest input table the persistent kernel stages in LDS
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Tuning overrides (DMOTIF_* environment variables), read per call.
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    const int x = std::atoi(v);
+    return x > 0 ? x : dflt;
+}
 
 struct DevBlock {
     void* p = nullptr;
@@ -47,6 +58,10 @@ struct Item {
     std::vector<StepDesc> steps;
     int64_t tcap = 0;  // table capacity (rows) of each ping-pong buffer
     int64_t out_rows = 0;
+    // root range [r0, r1) of the identity table: a capped item starts with the
+    // lowest roots expected to hold the cap (grouped-by-root tables make that
+    // prefix the start of the canonical order)
+    int32_t r0 = 0, r1 = 0;
     // arena offsets (bytes)
     size_t off_buf[2] = {0, 0}, off_status = 0, off_counts = 0, off_flags = 0, off_hash = 0, off_res = 0;
 };
@@ -70,10 +85,13 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
 
     // ---- layout: one arena for tables + control, one block for results
     size_t arena = 0, resb = 0;
-    int total_steps = 0, cmax = 1;
+    int total_steps = 0, cmax = 1, max_k = 1;
+    int64_t max_tcap = 1;
     for (auto& it : items) {
-        double est = (double)nv;
-        for (auto& ps : it.plan.steps) est = std::max(est, ps.est_rows);
+        const int32_t nr = it.r1 - it.r0;
+        const double frac = nv > 0 ? (double)nr / nv : 1.0;
+        double est = (double)nr;
+        for (auto& ps : it.plan.steps) est = std::max(est, ps.est_rows * frac);
         const int64_t first_max = std::min<int64_t>(((int64_t)1 << 28) / it.k, (int64_t)1 << 26);
         it.tcap = std::max<int64_t>(std::min<int64_t>((int64_t)(2.0 * est) + 4096, first_max), 4096);
         if (opts && opts->initial_rows > 0) it.tcap = opts->initial_rows;
@@ -84,6 +102,8 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         }
         total_steps += (int)it.steps.size();
         for (auto& d : it.steps) cmax = std::max(cmax, (int)d.c_in);
+        max_k = std::max(max_k, it.k);
+        max_tcap = std::max(max_tcap, it.tcap);
         if (!hash_mode) {
             it.off_res = resb;
             resb = align256(resb + sizeof(int32_t) * (size_t)std::max<int64_t>(it.out_rows * it.k, 1));
@@ -101,7 +121,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         it.off_hash = arena;
         arena = align256(arena + sizeof(uint64_t) * 4);
     }
-    const size_t off_misc = arena;  // finished, spill_n[2], dup
+    const size_t off_misc = arena;  // finished, sort counters (spill_n[2], max_chunks, dup)
     arena = align256(arena + 64);
     const size_t ctl_end = arena;
     const size_t off_ctl = arena;
@@ -140,8 +160,9 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         const int ns = (int)it.steps.size();
         first[p] = a_i;
         nsteps[p] = ns;
-        ctl[p].n_in[0] = nv;
-        ctl[p].ntiles[0] = (nv + kBatchTile - 1) / kBatchTile;
+        const int32_t nr = it.r1 - it.r0;
+        ctl[p].n_in[0] = nr;
+        ctl[p].ntiles[0] = (nr + kBatchTile - 1) / kBatchTile;
         int64_t* counts = (int64_t*)(A + it.off_counts);
         int32_t* flags = (int32_t*)(A + it.off_flags);
         for (int i = 0; i < ns; i++) {
@@ -153,10 +174,10 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             const int ib = (i - 1) & 1, ob = i & 1;
             a.in = i == 0 ? nullptr : (const int32_t*)(A + it.off_buf[ib]);
             a.in_stride = i == 0 ? 0 : it.tcap;
-            a.in_cap = i == 0 ? nv : it.tcap;
+            a.in_cap = i == 0 ? nr : it.tcap;
             a.n_in = &counts[i];
-            a.id_begin = 0;
-            a.id_count = nv;
+            a.id_begin = it.r0;
+            a.id_count = nr;
             a.out = (int32_t*)(A + it.off_buf[ob]);
             a.out_stride = it.tcap;
             a.out_cap = it.tcap;
@@ -205,11 +226,13 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     bd.ctl = (BatchCtl*)(A + off_ctl);
     bd.finished = &misc[0];
     bd.n_patterns = nb;
+    bd.max_backoff = env_int("DMOTIF_BATCH_BACKOFF", 15);
+    const int grid = env_int("DMOTIF_BATCH_GRID", 1024);
     DM_HIP(hipEventRecord(ev[0], s));
-    DM_HIP(launch_batch(bd, cmax, 2048, s));
+    DM_HIP(launch_batch(bd, cmax, grid, s));
     DM_HIP(hipEventRecord(ev[1], s));
     if (!hash_mode)
-        DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, &misc[1], &misc[3]));
+        DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, max_tcap, max_k, &misc[1]));
     DM_HIP(hipEventRecord(ev[2], s));
 
     // ---- one readback of every count, flag and hash
@@ -220,10 +243,33 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     (void)hipEventElapsedTime(&ms_join, ev[0], ev[1]);
     (void)hipEventElapsedTime(&ms_sort, ev[1], ev[2]);
     auto hb = [&](size_t off) { return back.data() + (off - ctl_begin); };
+    if (const char* trace = std::getenv("DMOTIF_BATCH_TRACE")) {
+        // per-pattern stage timeline (device wall clock at each step's publication)
+        std::vector<BatchCtl> hc(nb);
+        DM_HIP(hipMemcpy(hc.data(), A + off_ctl, sizeof(BatchCtl) * nb, hipMemcpyDeviceToHost));
+        int khz = 100000;
+        (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device);
+        if (FILE* f = std::fopen(trace, "a")) {
+            int64_t t0 = INT64_MAX;
+            for (int p = 0; p < nb; p++) t0 = std::min(t0, hc[p].t_pub[0]);
+            for (int p = 0; p < nb; p++) {
+                const int ns = (int)items[p].steps.size();
+                const int64_t* counts = (const int64_t*)hb(items[p].off_counts);
+                std::fprintf(f, "{\"pattern\": %d, \"k\": %d, \"steps\": [", items[p].idx, items[p].k);
+                for (int i = 0; i <= ns; i++) {
+                    const double us = hc[p].t_pub[i] ? 1e3 * (double)(hc[p].t_pub[i] - t0) / khz : -1.0;
+                    std::fprintf(f, "%s[%.1f, %lld, %d]", i ? ", " : "", us, (long long)counts[i],
+                                 i < ns ? hc[p].ntiles[i] : 0);
+                }
+                std::fprintf(f, "]}\n");
+            }
+            std::fclose(f);
+        }
+    }
     const int32_t* hmisc = (const int32_t*)hb(off_misc);
     if (hmisc[0] != nb) return fail(DM_ERR_INTERNAL, "persistent kernel retired " + std::to_string(hmisc[0]) +
                                                          " of " + std::to_string(nb) + " patterns");
-    if (hmisc[3] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached a canonical table");
+    if (hmisc[4] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached a canonical table");
 
     int64_t all_bytes = 0;
     std::vector<int64_t> pbytes(nb, 0);
@@ -235,9 +281,13 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         const uint64_t* hash = (const uint64_t*)hb(it.off_hash);
         bool over = false;
         for (int i = 0; i < ns; i++) over |= flags[i] != 0;
+        // a capped item whose root prefix held fewer rows than the cap
+        const bool partial = !hash_mode && !over && it.r1 < nv && it.cap >= 0 && counts[ns] < it.cap;
+        over |= partial;
         dm_result* r = nullptr;
         if (over) {
-            // first-attempt capacity too small: redo this pattern alone, exact sizes
+            // first-attempt capacity too small (or a short root prefix): redo
+            // this pattern alone over every root, exact sizes
             RunOptions ro = run_options(opts, it.cap);
             ro.sync_each_step = true;
             RunOutput o;
@@ -264,7 +314,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             r->stream = ctx->stream;
             r->mode = hash_mode ? DM_OUT_COUNT_HASH : DM_OUT_TABLE;
             const int64_t n_final = hash_mode ? (int64_t)hash[0] : counts[ns];
-            r->total = n_final;
+            r->total = (it.r1 < nv || it.r0 > 0) ? -1 : n_final;  // a root prefix does not count them all
             if (hash_mode) {
                 r->hsum = hash[1];
                 r->hxor = hash[2];
@@ -357,6 +407,16 @@ dm_status enumerate_many(dm_datagraph* dg, Workspace& ws, int32_t n, const dm_gr
             d.motif = -1;
             d.c_in = 1;
             it.steps.push_back(d);
+        }
+        it.r0 = 0;
+        it.r1 = dg->n;
+        if (cap >= 0 && mode == DM_OUT_TABLE && !it.plan.steps.empty()) {
+            // lowest roots expected to hold the cap with a wide margin (roots at
+            // the low end may sit on the graph's boundary); a short prefix is
+            // redone over every root
+            const double per_root = std::max(it.plan.steps.back().est_rows / std::max(dg->n, 1), 1e-9);
+            const double roots = std::ceil((8.0 * (double)cap + 256.0) / per_root);
+            if (roots < (double)dg->n) it.r1 = std::min<int32_t>(dg->n, std::max<int32_t>(64, (int32_t)roots));
         }
         int cm = 0;
         for (auto& d : it.steps) cm = std::max(cm, (int)d.c_in);

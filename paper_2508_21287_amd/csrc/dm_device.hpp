@@ -7,11 +7,13 @@
 
 namespace dm {
 
-// A motif table Res(M) keyed on one motif position: SoA columns in motif
-// position order, rows grouped by the key column in ascending key order, and
-// offs[v]..offs[v+1] = the rows whose key is v (direct-address index).
+// A motif table Res(M) keyed on one motif position: one SoA block, column p
+// (motif position p) at base + p * stride, rows grouped by the key column in
+// ascending key order, and offs[v]..offs[v+1] = the rows whose key is v
+// (direct-address index).
 struct TableDev {
-    const int32_t* col[kMaxMotif];
+    const int32_t* base;
+    int64_t stride;
     const int32_t* offs;
     int64_t rows;
     int32_t size;
@@ -71,14 +73,23 @@ struct SortJob {
     const int64_t* n_in;
     int32_t* out;
     int64_t out_rows;
-    uint32_t* scratch_idx;  // global tier: 2 * in_cap index scratch
+    uint32_t* scratch_idx;  // merge tier: 2 * in_cap index scratch
     int32_t k;
     int32_t kp;             // LDS row stride (k rounded up to odd)
     uint8_t perm[kMaxCols]; // pattern vertex j -> input column
 };
 
+// A root segment passed from one sort tier to the next: rows
+// [seg0, seg0 + len) of job item / n_vertices.
+struct SegRef {
+    int32_t item;
+    int32_t pad_;
+    int64_t seg0;
+    int64_t len;
+};
+
 // One sort launch over n_jobs tables; item = job * n_vertices + (v - v_begin)
-// for every root vertex v, or the items in `list` for the later tiers.
+// for every root vertex v (list == nullptr), or the segments in `list`.
 // Segments that do not fit this tier's LDS are appended to `spill`.
 struct SortLaunch {
     const SortJob* jobs;
@@ -86,12 +97,28 @@ struct SortLaunch {
     int32_t n_vertices;
     int32_t v_begin;
     int32_t lds_bytes;
-    const int32_t* list;
+    const SegRef* list;
     const int32_t* list_n;
-    int32_t* spill;
+    SegRef* spill;
     int32_t* spill_n;
     int32_t* dup_count;
+    int32_t* max_chunks;  // merge tier: most LDS chunks of any listed segment
+    int32_t pass;         // merge tier: pass number of a merge launch
 };
+
+// Rows of kp int32 that an LDS tile of lds_bytes holds together with the
+// 16-bit index array of the bitonic network (padded to a power of two P):
+// the best r <= P over P with 4 * kp * r + 2 * P <= lds_bytes.
+__host__ __device__ inline int lds_rows_of(int lds_bytes, int kp) {
+    int best = 0;
+    for (int P = 1; P <= 65536 && 2 * P < lds_bytes; P <<= 1) {
+        int r = (lds_bytes - 2 * P) / (4 * kp);
+        if (r > P) r = P;
+        if (r > 65535) r = 65535;  // 0xFFFF is the index sentinel
+        if (r > best) best = r;
+    }
+    return best;
+}
 
 // Batched form: per-pattern progress of the persistent join kernel.
 struct BatchCtl {
@@ -101,6 +128,7 @@ struct BatchCtl {
     int32_t claim[kMaxSteps];
     int32_t done[kMaxSteps];
     int64_t n_in[kMaxSteps];
+    int64_t t_pub[kMaxSteps + 1];  // device wall clock when step s was published (s = n_steps: retired)
 };
 
 struct BatchDev {
@@ -110,16 +138,22 @@ struct BatchDev {
     BatchCtl* ctl;         // per pattern, zeroed except ntiles[0]/n_in[0]
     int32_t* finished;     // retired patterns
     int32_t n_patterns;
+    int32_t max_backoff;   // idle polling backoff cap (units of s_sleep(16))
 };
 
 constexpr int kEpochBits = 14;
 constexpr uint32_t kEpochs = 1u << kEpochBits;
 
 // ---- launchers (kernels.hip) ----
+// block size the join launch uses for c_in input columns (requested 0 = auto);
+// wide rows take smaller tiles so the LDS row tile stays small
+int ejf_block_for(int c_in, int requested);
 hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s);
 hipError_t launch_sort_lds(const SortLaunch& a, int grid, int lds_bytes, hipStream_t s);
-hipError_t launch_sort_global(const SortLaunch& a, int grid, hipStream_t s);
-hipError_t launch_batch(const BatchDev& b, int cmax, int grid, hipStream_t s);
+// chunk sort + `passes` merge launches + row write for the segments in a.list
+hipError_t launch_sort_merge_tier(const SortLaunch& a, int passes, hipStream_t s);
+// max_cols: widest input table of any step in the batch (sizes the LDS row tile)
+hipError_t launch_batch(const BatchDev& b, int max_cols, int grid, hipStream_t s);
 int sort_max_lds_bytes();
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

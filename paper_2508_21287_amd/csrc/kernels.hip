@@ -94,12 +94,28 @@ __device__ __forceinline__ bool adjacent(const GraphDev& g, int32_t u, int32_t v
 // ---------------------------------------------------------------------------
 // expand-join-filter (one iteration of the join-and-filter loop)
 // ---------------------------------------------------------------------------
+//
+// One tile = BLOCK consecutive input rows, one row per thread.  The row's
+// values are staged in LDS (odd row stride, so lanes reading different rows
+// hit different banks); a 128-bit Bloom summary of the row in registers lets
+// most injectivity tests skip the row scan.  Candidates come from the motif
+// table's direct-address index; survivors are counted, the tile's output
+// offset comes from the look-back chain, and rows are written in input order
+// with coalesced column stores.
 
-template <int CMAX>
-__device__ __forceinline__ int32_t old_val(const EjfArgs& a, const int32_t (&v)[CMAX], int c, int64_t row) {
-    if (!a.in) return v[0];
-    return a.in[(int64_t)c * a.in_stride + row];
-}
+__device__ __forceinline__ uint32_t bloom_bit(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> 25; }
+
+struct Bloom {
+    uint64_t lo, hi;
+    __device__ __forceinline__ void add(int32_t x) {
+        const uint32_t b = bloom_bit(x);
+        if (b < 64) lo |= 1ull << b; else hi |= 1ull << (b - 64);
+    }
+    __device__ __forceinline__ bool maybe(int32_t x) const {
+        const uint32_t b = bloom_bit(x);
+        return ((b < 64 ? lo : hi) >> (b & 63)) & 1ull;
+    }
+};
 
 __device__ __forceinline__ int32_t pick_new(const int32_t (&nv)[kMaxMotif], int t) {
     int32_t r = -1;
@@ -108,33 +124,38 @@ __device__ __forceinline__ int32_t pick_new(const int32_t (&nv)[kMaxMotif], int 
     return r;
 }
 
-// Does motif row m extend input row `row` (values v) into a valid partial
-// embedding?  Join keys (the index lookup plus eq checks), injectivity of the
-// new values against the row, and the step's explicit edge checks.
-template <int CMAX>
-__device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t (&v)[CMAX], int64_t row, int32_t m,
+// Does motif row m extend this thread's input row (in LDS at `my`) into a
+// valid partial embedding?  Further join keys, injectivity of the new values
+// against the row, and the step's explicit edge checks.
+__device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t* my, const Bloom& bl, int32_t m,
                                            int32_t (&nv)[kMaxMotif]) {
     const StepDesc& st = a.st;
+    const int c_in = st.c_in;
     if (st.motif >= 0) {
-        for (int e = 0; e < st.n_eq; e++) {
-            if (a.tbl.col[st.eq_pos[e]][m] != old_val(a, v, st.eq_col[e], row)) return false;
-        }
+        // issue every load of this candidate before the first compare
+        const int32_t* tb = a.tbl.base + m;
+        const int64_t ts = a.tbl.stride;
+        const int n_new = st.n_new;
+#pragma unroll
+        for (int t = 0; t < kMaxMotif; t++)
+            if (t < n_new) nv[t] = tb[(int64_t)st.new_pos[t] * ts];
+        for (int e = 0; e < st.n_eq; e++)
+            if (tb[(int64_t)st.eq_pos[e] * ts] != my[st.eq_col[e]]) return false;
 #pragma unroll
         for (int t = 0; t < kMaxMotif; t++) {
-            if (t < st.n_new) {
-                const int32_t x = a.tbl.col[st.new_pos[t]][m];
-                nv[t] = x;
-                bool clash = false;
-#pragma unroll
-                for (int c = 0; c < CMAX; c++) clash |= (v[c] == x);
-                if (clash) return false;
+            if (t < n_new) {
+                const int32_t x = nv[t];
+                if (bl.maybe(x)) {
+                    for (int c = 0; c < c_in; c++)
+                        if (my[c] == x) return false;
+                }
             }
         }
     }
     for (int e = 0; e < st.n_edge; e++) {
         const int ca = st.edge_a[e], cb = st.edge_b[e];
-        const int32_t va = ca < st.c_in ? old_val(a, v, ca, row) : pick_new(nv, ca - st.c_in);
-        const int32_t vb = cb < st.c_in ? old_val(a, v, cb, row) : pick_new(nv, cb - st.c_in);
+        const int32_t va = ca < c_in ? my[ca] : pick_new(nv, ca - c_in);
+        const int32_t vb = cb < c_in ? my[cb] : pick_new(nv, cb - c_in);
         if (!adjacent(a.g, va, vb)) return false;
     }
     return true;
@@ -151,35 +172,53 @@ struct TileShared {
     uint8_t src[CH];    // input row (lane of the tile) of each staged output row
 };
 
-// One tile (BLOCK consecutive input rows) of a join-filter step: count the
-// surviving candidates of every row, take this tile's output offset from the
-// look-back chain, then write the surviving rows in input order.  In hash
-// mode the survivors only feed the per-thread (count, sum, xor) accumulators.
-template <int CMAX, int BLOCK>
+// Row stride (in int32) of the LDS row tile for c columns: odd, >= c.
+__host__ __device__ __forceinline__ int row_stride(int c) { return c | 1; }
+
+template <int BLOCK>
 __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t n_in, int64_t n_tiles,
-                                         TileShared<BLOCK>& sh, uint64_t& h_cnt, uint64_t& h_sum,
+                                         TileShared<BLOCK>& sh, int32_t* rows, uint64_t& h_cnt, uint64_t& h_sum,
                                          uint64_t& h_xor) {
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const StepDesc& st = a.st;
+    const int c_in = st.c_in;
+    const int RS = row_stride(c_in);
     const int64_t row = tile * BLOCK + tid;
     const bool valid = row < n_in;
-    int32_t v[CMAX];
-#pragma unroll
-    for (int c = 0; c < CMAX; c++) v[c] = -1;
+    int32_t* my = rows + tid * RS;
+    Bloom bl{0ull, 0ull};
+    uint64_t inner_old = 0;
+    const bool hash = a.mode == EJF_HASH;
     if (valid) {
         if (a.in) {
+            const int32_t* src = a.in + row;
+            const int64_t is = a.in_stride;
+            for (int c0 = 0; c0 < c_in; c0 += 8) {
+                int32_t t8[8];
 #pragma unroll
-            for (int c = 0; c < CMAX; c++)
-                if (c < st.c_in) v[c] = a.in[(int64_t)c * a.in_stride + row];
+                for (int j = 0; j < 8; j++)
+                    if (c0 + j < c_in) t8[j] = src[(int64_t)(c0 + j) * is];
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    if (c0 + j < c_in) {
+                        my[c0 + j] = t8[j];
+                        bl.add(t8[j]);
+                        if (hash) inner_old += mix64(((uint64_t)a.pv[c0 + j] << 32) | (uint32_t)t8[j]);
+                    }
+                }
+            }
         } else {
-            v[0] = a.id_begin + (int32_t)row;
+            const int32_t x = a.id_begin + (int32_t)row;
+            my[0] = x;
+            bl.add(x);
+            if (hash) inner_old += mix64(((uint64_t)a.pv[0] << 32) | (uint32_t)x);
         }
     }
     int32_t lo = 0, hi = 0;
     if (valid) {
         if (st.motif >= 0) {
-            const int32_t key = a.in ? a.in[(int64_t)st.key_col * a.in_stride + row] : v[0];
+            const int32_t key = my[st.key_col];
             lo = a.tbl.offs[key];
             hi = a.tbl.offs[key + 1];
         } else {
@@ -190,31 +229,25 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
 #pragma unroll
     for (int t = 0; t < kMaxMotif; t++) nv[t] = -1;
 
-    if (a.mode == EJF_HASH) {
-        uint64_t inner_old = 0;
-        if (valid) {
-#pragma unroll
-            for (int c = 0; c < CMAX; c++)
-                if (c < st.c_in) inner_old += mix64(((uint64_t)a.pv[c] << 32) | (uint32_t)v[c]);
-        }
+    if (hash) {
         for (int32_t m = lo; m < hi; m++) {
-            if (!ejf_accept<CMAX>(a, v, row, m, nv)) continue;
+            if (!ejf_accept(a, my, bl, m, nv)) continue;
             uint64_t inner = inner_old;
 #pragma unroll
             for (int t = 0; t < kMaxMotif; t++)
-                if (t < st.n_new) inner += mix64(((uint64_t)a.pv[st.c_in + t] << 32) | (uint32_t)nv[t]);
+                if (t < st.n_new) inner += mix64(((uint64_t)a.pv[c_in + t] << 32) | (uint32_t)nv[t]);
             const uint64_t h = mix64(inner);
             h_cnt++;
             h_sum += h;
             h_xor ^= h;
         }
-        return;
+        return;  // no lane read another lane's row: the tile can be reused at once
     }
 
     uint64_t mask = 0;
     int32_t cnt = 0;
     for (int32_t m = lo; m < hi; m++) {
-        if (ejf_accept<CMAX>(a, v, row, m, nv)) {
+        if (ejf_accept(a, my, bl, m, nv)) {
             if (m - lo < 64) mask |= 1ull << (m - lo);
             cnt++;
         }
@@ -247,17 +280,16 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
         }
     }
     __syncthreads();
-    // Write phase.  Survivors are staged in LDS in output order as (input
-    // lane, motif row); then each thread assembles whole output rows and
+    // Write phase: survivors are staged in LDS in output order as (input
+    // lane, motif row); then each thread assembles whole output rows (parent
+    // values from the LDS row tile, new values from the motif table) and
     // writes them column by column, so every store of a wave covers
-    // consecutive elements of one column (coalesced), instead of each lane
-    // scattering its own survivors.
+    // consecutive elements of one column.
     constexpr int CH = TileShared<BLOCK>::CH;
     const int32_t local0 = sh.wexcl[wid] + (x - cnt);
     const int32_t total = sh.total;
     const int64_t base = sh.base;
-    const int c_in = st.c_in, n_new = st.motif >= 0 ? st.n_new : 0;
-    const int64_t row0 = tile * BLOCK;
+    const int n_new = st.motif >= 0 ? st.n_new : 0;
     // each thread's candidate cursor survives across passes, so every
     // candidate is visited once however many passes the tile needs
     int32_t m_cur = lo, r_cur = 0;
@@ -266,8 +298,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             const int32_t li = local0 + r_cur;
             if (li >= w0 + CH) break;  // belongs to a later pass
             const int32_t m = m_cur++;
-            const bool ok =
-                (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : ejf_accept<CMAX>(a, v, row, m, nv);
+            const bool ok = (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : ejf_accept(a, my, bl, m, nv);
             if (!ok) continue;
             sh.src[li - w0] = (uint8_t)tid;
             sh.mrow[li - w0] = m;
@@ -279,18 +310,26 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
         for (int32_t o = tid; o < nrows; o += BLOCK) {
             const int64_t orow = obase + o;
             if (orow >= a.out_cap) break;
-            const int64_t irow = row0 + sh.src[o];
+            const int32_t* prow = rows + sh.src[o] * RS;
             const int32_t m = sh.mrow[o];
-            if (a.in) {
-                for (int c = 0; c < c_in; c++)
-                    a.out[(int64_t)c * a.out_stride + orow] = a.in[(int64_t)c * a.in_stride + irow];
-            } else {
-                a.out[orow] = a.id_begin + (int32_t)irow;
+            int32_t* dst = a.out + orow;
+            const int64_t os = a.out_stride;
+            for (int c = 0; c < c_in; c++) dst[(int64_t)c * os] = prow[c];
+            if (n_new > 0) {
+                const int32_t* tb = a.tbl.base + m;
+                const int64_t ts = a.tbl.stride;
+                for (int t0 = 0; t0 < n_new; t0 += 4) {
+                    int32_t w4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        if (t0 + j < n_new) w4[j] = tb[(int64_t)st.new_pos[t0 + j] * ts];
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        if (t0 + j < n_new) dst[(int64_t)(c_in + t0 + j) * os] = w4[j];
+                }
             }
-            for (int t = 0; t < n_new; t++)
-                a.out[(int64_t)(c_in + t) * a.out_stride + orow] = a.tbl.col[st.new_pos[t]][m];
         }
-        __syncthreads();
+        __syncthreads();  // other lanes' rows were read: the next tile may overwrite them only now
     }
 }
 
@@ -329,9 +368,10 @@ __device__ void hash_flush(uint64_t* acc, uint64_t h_cnt, uint64_t h_sum, uint64
 __device__ __forceinline__ int64_t clamp_rows(int64_t n, int64_t cap) { return n < 0 ? 0 : (n > cap ? cap : n); }
 
 // One join-filter step over one table: workgroups claim tiles in ticket order
-// until the input is exhausted.
-template <int CMAX, int BLOCK>
+// until the input is exhausted.  Dynamic LDS: BLOCK * row_stride(c_in) int32.
+template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
+    extern __shared__ int32_t rows[];
     __shared__ TileShared<BLOCK> sh;
     __shared__ int64_t s_tile;
     __shared__ uint64_t s_red[3][BLOCK / 64];
@@ -348,28 +388,28 @@ __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
             if (a.mode == EJF_WRITE && tile == 0 && tid == 0) *a.n_out = 0;
             break;
         }
-        ejf_tile<CMAX, BLOCK>(a, tile, n_in, n_tiles, sh, h_cnt, h_sum, h_xor);
+        ejf_tile<BLOCK>(a, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
     }
     if (a.mode == EJF_HASH) hash_flush<BLOCK>(a.hash_acc, h_cnt, h_sum, h_xor, s_red);
 }
 
-template <int CMAX>
-static hipError_t launch_ejf_c(const EjfArgs& a, int block, int grid, hipStream_t s) {
-    switch (block) {
-        case 64: hipLaunchKernelGGL((ejf_kernel<CMAX, 64>), dim3(grid), dim3(64), 0, s, a); break;
-        case 128: hipLaunchKernelGGL((ejf_kernel<CMAX, 128>), dim3(grid), dim3(128), 0, s, a); break;
-        default: hipLaunchKernelGGL((ejf_kernel<CMAX, 256>), dim3(grid), dim3(256), 0, s, a); break;
-    }
-    return hipGetLastError();
+int ejf_block_for(int c_in, int requested) {
+    // the LDS row tile stays within ~34 KB: wide rows take smaller tiles
+    const int cap = c_in <= 31 ? 256 : (c_in <= 63 ? 128 : 64);
+    int b = requested > 0 ? requested : cap;
+    return b > cap ? cap : b;
 }
 
 hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s) {
     const int c = a.st.c_in;
-    if (c <= 8) return launch_ejf_c<8>(a, block, grid, s);
-    if (c <= 16) return launch_ejf_c<16>(a, block, grid, s);
-    if (c <= 32) return launch_ejf_c<32>(a, block, grid, s);
-    if (c <= 64) return launch_ejf_c<64>(a, block, grid, s);
-    return launch_ejf_c<128>(a, block, grid, s);
+    block = ejf_block_for(c, block);
+    const size_t lds = sizeof(int32_t) * (size_t)block * row_stride(c);
+    switch (block) {
+        case 64: hipLaunchKernelGGL((ejf_kernel<64>), dim3(grid), dim3(64), lds, s, a); break;
+        case 128: hipLaunchKernelGGL((ejf_kernel<128>), dim3(grid), dim3(128), lds, s, a); break;
+        default: hipLaunchKernelGGL((ejf_kernel<256>), dim3(grid), dim3(256), lds, s, a); break;
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -391,24 +431,19 @@ __device__ __forceinline__ void st_rel_i32(int32_t* p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int CMAX>
-__device__ void batch_tile_dispatch(const EjfArgs& a, int64_t tile, int64_t n_in, int64_t n_tiles,
-                                    TileShared<64>& sh, uint64_t& hc, uint64_t& hs, uint64_t& hx) {
-    const int c = a.st.c_in;
-    if (CMAX >= 64 && c > 32) ejf_tile<(CMAX >= 64 ? 64 : CMAX), 64>(a, tile, n_in, n_tiles, sh, hc, hs, hx);
-    else if (CMAX >= 32 && c > 16) ejf_tile<(CMAX >= 32 ? 32 : CMAX), 64>(a, tile, n_in, n_tiles, sh, hc, hs, hx);
-    else if (CMAX >= 16 && c > 8) ejf_tile<(CMAX >= 16 ? 16 : CMAX), 64>(a, tile, n_in, n_tiles, sh, hc, hs, hx);
-    else ejf_tile<8, 64>(a, tile, n_in, n_tiles, sh, hc, hs, hx);
-}
-
-template <int CMAX>
+// Dynamic LDS: 64 * row_stride(widest input) int32.
 __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
+    extern __shared__ int32_t rows[];
     __shared__ TileShared<64> sh;
     __shared__ EjfArgs sa;
     __shared__ uint64_t s_red[3][1];
     const int lane = threadIdx.x;
     const int N = b.n_patterns;
     int rot = (int)((blockIdx.x * 7919u) % (unsigned)(N > 0 ? N : 1));
+    int idle = 0;
+    if (blockIdx.x == 0 && lane < N) {
+        for (int q = lane; q < N; q += 64) b.ctl[q].t_pub[0] = (int64_t)wall_clock64();
+    }
     uint64_t hc = 0, hs = 0, hx = 0;
     for (;;) {
         // ---- find a claimable tile (whole wave scans 64 patterns at a time)
@@ -456,8 +491,11 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
                 all_done = true;
                 break;
             }
-            __builtin_amdgcn_s_sleep(8);
+            // idle: back off exponentially so polling does not flood the memory system
+            for (int i = 0; i < idle; i++) __builtin_amdgcn_s_sleep(16);
+            idle = idle < b.max_backoff ? 2 * idle + 1 : idle;
         }
+        idle = 0;
         if (all_done) break;
         rot = (p + 1) % N;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -470,7 +508,7 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
         __syncthreads();
         const int64_t n_in = b.ctl[p].n_in[s];
         const int64_t n_tiles = b.ctl[p].ntiles[s];
-        batch_tile_dispatch<CMAX>(sa, tile, n_in, n_tiles, sh, hc, hs, hx);
+        ejf_tile<64>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
         if (sa.mode == EJF_HASH) {
             hash_flush<64>(sa.hash_acc, hc, hs, hx, s_red);
             hc = hs = hx = 0;
@@ -489,6 +527,7 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
                     const EjfArgs& nx = b.args[b.first[p] + s + 1];
                     const int64_t nn = clamp_rows(n_out, nx.in_cap);
                     c.n_in[s + 1] = nn;
+                    c.t_pub[s + 1] = (int64_t)wall_clock64();
                     __hip_atomic_store(&c.ntiles[s + 1], (int32_t)((nn + 63) / 64), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -496,6 +535,7 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
                 } else {
                     // last step, or nothing left: the remaining steps produce 0 rows
                     for (int q = s + 1; q < ns; q++) *b.args[b.first[p] + q].n_out = 0;
+                    c.t_pub[ns] = (int64_t)wall_clock64();
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                     st_rel_i32(&c.stage, ns);
                     atomicAdd(b.finished, 1);
@@ -506,11 +546,9 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
     }
 }
 
-hipError_t launch_batch(const BatchDev& b, int cmax, int grid, hipStream_t s) {
-    if (cmax <= 8) hipLaunchKernelGGL((batch_kernel<8>), dim3(grid), dim3(64), 0, s, b);
-    else if (cmax <= 16) hipLaunchKernelGGL((batch_kernel<16>), dim3(grid), dim3(64), 0, s, b);
-    else if (cmax <= 32) hipLaunchKernelGGL((batch_kernel<32>), dim3(grid), dim3(64), 0, s, b);
-    else hipLaunchKernelGGL((batch_kernel<64>), dim3(grid), dim3(64), 0, s, b);
+hipError_t launch_batch(const BatchDev& b, int max_cols, int grid, hipStream_t s) {
+    const size_t lds = sizeof(int32_t) * 64 * (size_t)row_stride(max_cols);
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(64), lds, s, b);
     return hipGetLastError();
 }
 
@@ -535,7 +573,6 @@ __device__ __forceinline__ int64_t lower_bound_i32(const int32_t* a, int64_t n, 
 }
 
 constexpr int kSortBlock = 256;
-constexpr uint32_t kSent = 0xFFFFFFFFu;
 
 __device__ __forceinline__ bool lds_row_less(const int32_t* rows, int kp, int k, uint32_t x, uint32_t y) {
     const int32_t* a = rows + (size_t)x * kp;
@@ -547,38 +584,82 @@ __device__ __forceinline__ bool lds_row_less(const int32_t* rows, int kp, int k,
     return false;
 }
 
-// Rows of kp int32 that fit an LDS tile of lds_bytes together with the
-// 16-bit index array of the bitonic network (padded to a power of two).
-__device__ __forceinline__ int lds_rows_of(int lds_bytes, int kp) {
-    int r = lds_bytes / (4 * kp + 4);
-    if (r > 65535) r = 65535;
-    while (r > 0) {
-        int P = 1;
-        while (P < r) P <<= 1;
-        if (4 * kp * r + 2 * P <= lds_bytes) break;
-        r--;
-    }
-    return r;
-}
-
 constexpr uint16_t kSent16 = 0xFFFFu;
 
-// Load job j into LDS (all threads), then broadcast the segment of root v.
-__device__ __forceinline__ void sort_item_setup(const SortLaunch& L, int64_t item, SortJob& job, int64_t* seg) {
-    const int64_t j = item / L.n_vertices;
-    const int32_t v = L.v_begin + (int32_t)(item - j * L.n_vertices);
-    const int32_t* src = (const int32_t*)&L.jobs[j];
-    int32_t* dst = (int32_t*)&job;
-    for (int i = threadIdx.x; i < (int)(sizeof(SortJob) / 4); i += blockDim.x) dst[i] = src[i];
+// First index of the ascending a[0, n) whose value is >= v, found by one
+// full wave: each round probes 64 evenly spaced positions of the interval
+// that still holds the answer, so a search takes ~log64(n) dependent loads.
+__device__ int64_t wave_lower_bound(const int32_t* a, int64_t n, int32_t v, int lane) {
+    int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int64_t step = (hi - lo + 63) / 64;
+        int64_t p = lo + (int64_t)(lane + 1) * step - 1;
+        if (p > hi - 1) p = hi - 1;
+        const uint64_t m = __ballot(a[p] >= v);
+        if (m == 0) return hi;
+        const int f = __ffsll((long long)m) - 1;
+        int64_t pf = lo + (int64_t)(f + 1) * step - 1;
+        if (pf > hi - 1) pf = hi - 1;
+        lo = f == 0 ? lo : lo + (int64_t)f * step;  // one past the probe of lane f - 1
+        hi = pf;
+    }
+    return lo;
+}
+
+// Sort the n rows staged in LDS (row stride kp) by columns 1..k-1 with a
+// bitonic network over 16-bit row indices; idx[0, n) receives the order.
+// Called by the whole workgroup.
+__device__ void lds_bitonic(const int32_t* rows, uint16_t* idx, int n, int k, int kp) {
+    const int tid = threadIdx.x;
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = tid; i < P; i += kSortBlock) idx[i] = i < n ? (uint16_t)i : kSent16;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int64_t n = clamp_rows(*job.n_in, job.in_cap);
-        seg[0] = lower_bound_i32(job.in, n, v);
-        seg[1] = lower_bound_i32(job.in, n, v + 1);
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < (P >> 1); t += kSortBlock) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint16_t ia = idx[lo], ib = idx[hi];
+                bool gt;
+                if (ia == kSent16) gt = (ib != kSent16);
+                else if (ib == kSent16) gt = false;
+                else gt = lds_row_less(rows, kp, k, ib, ia);
+                if (gt == asc) {
+                    idx[lo] = ib;
+                    idx[hi] = ia;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Stage rows [r0, r0 + n) of a final table into LDS, columns permuted to
+// pattern-vertex order (coalesced column reads).
+__device__ __forceinline__ void lds_stage_rows(const SortJob& job, int64_t r0, int n, int32_t* rows) {
+    const int k = job.k, kp = job.kp;
+    for (int j = 0; j < k; j++) {
+        const int32_t* src = job.in + (int64_t)job.perm[j] * job.in_stride + r0;
+        for (int r = threadIdx.x; r < n; r += kSortBlock) rows[r * kp + j] = src[r];
     }
     __syncthreads();
 }
 
+__device__ __forceinline__ void push_segment(const SortLaunch& L, int32_t item, int64_t seg0, int64_t len) {
+    const int32_t q = atomicAdd(L.spill_n, 1);
+    SegRef r;
+    r.item = item;
+    r.pad_ = 0;
+    r.seg0 = seg0;
+    r.len = len;
+    L.spill[q] = r;
+}
+
+// LDS tiers: one workgroup per root segment.  Without an input list the items
+// are every (job, root vertex) pair and the segment is found by search;
+// segments larger than this tier's LDS tile are passed on.
 __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L) {
     extern __shared__ int32_t lds[];
     __shared__ SortJob job;
@@ -586,51 +667,49 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
     const int tid = threadIdx.x;
     const int64_t n_items = L.list ? (int64_t)*L.list_n : (int64_t)L.n_jobs * L.n_vertices;
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int64_t item = L.list ? (int64_t)L.list[it] : it;
-        sort_item_setup(L, item, job, s_seg);
-        const int64_t seg0 = s_seg[0], seg1 = s_seg[1];
-        const int64_t L_ = seg1 - seg0;
-        const int k = job.k, kp = job.kp;
-        const int lds_rows = lds_rows_of(L.lds_bytes, kp);
-        __syncthreads();
-        if (L_ == 0 || seg0 >= job.out_rows) continue;
-        if (L_ > lds_rows) {
-            if (tid == 0) L.spill[atomicAdd(L.spill_n, 1)] = (int32_t)item;
-            continue;
+        const int32_t item = L.list ? L.list[it].item : (int32_t)it;
+        const int64_t jb = item / L.n_vertices;
+        {
+            const int32_t* src = (const int32_t*)&L.jobs[jb];
+            int32_t* dst = (int32_t*)&job;
+            for (int i = tid; i < (int)(sizeof(SortJob) / 4); i += kSortBlock) dst[i] = src[i];
         }
-        int32_t* rows = lds;
-        uint16_t* idx = (uint16_t*)(lds + (size_t)lds_rows * kp);
-        for (int j = 0; j < k; j++) {
-            const int32_t* src = job.in + (int64_t)job.perm[j] * job.in_stride + seg0;
-            for (int r = tid; r < L_; r += kSortBlock) rows[r * kp + j] = src[r];
-        }
-        int P = 1;
-        while (P < L_) P <<= 1;
-        for (int i = tid; i < P; i += kSortBlock) idx[i] = i < L_ ? (uint16_t)i : kSent16;
         __syncthreads();
-        for (int size = 2; size <= P; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int t = tid; t < (P >> 1); t += kSortBlock) {
-                    const int lo = 2 * t - (t & (stride - 1));
-                    const int hi = lo + stride;
-                    const bool asc = (lo & size) == 0;
-                    const uint16_t ia = idx[lo], ib = idx[hi];
-                    bool gt;
-                    if (ia == kSent16) gt = (ib != kSent16);
-                    else if (ib == kSent16) gt = false;
-                    else gt = lds_row_less(rows, kp, k, ib, ia);
-                    if (gt == asc) {
-                        idx[lo] = ib;
-                        idx[hi] = ia;
-                    }
-                }
-                __syncthreads();
+        if (L.list) {
+            if (tid == 0) {
+                s_seg[0] = L.list[it].seg0;
+                s_seg[1] = L.list[it].len;
+            }
+        } else if (tid < 64) {
+            const int32_t v = L.v_begin + (int32_t)(item - jb * L.n_vertices);
+            const int64_t n = clamp_rows(*job.n_in, job.in_cap);
+            const int64_t a = wave_lower_bound(job.in, n, v, tid);
+            const int64_t b = wave_lower_bound(job.in, n, v + 1, tid);
+            if (tid == 0) {
+                s_seg[0] = a;
+                s_seg[1] = b - a;
             }
         }
-        for (int r = tid + 1; r < L_; r += kSortBlock)
+        __syncthreads();
+        const int64_t seg0 = s_seg[0], len = s_seg[1];
+        const int k = job.k, kp = job.kp;
+        const int64_t out_rows = job.out_rows;
+        const int cap_rows = lds_rows_of(L.lds_bytes, kp);
+        __syncthreads();  // every lane has read job and s_seg: the next item may overwrite them
+        if (len == 0 || seg0 >= out_rows) continue;
+        if (len > cap_rows) {
+            if (tid == 0) push_segment(L, item, seg0, len);
+            continue;
+        }
+        const int n = (int)len;
+        int32_t* rows = lds;
+        uint16_t* idx = (uint16_t*)(lds + (size_t)cap_rows * kp);
+        lds_stage_rows(job, seg0, n, rows);
+        lds_bitonic(rows, idx, n, k, kp);
+        for (int r = tid + 1; r < n; r += kSortBlock)
             if (!lds_row_less(rows, kp, k, idx[r - 1], idx[r])) atomicAdd(L.dup_count, 1);
-        const int64_t Lw = (seg0 + L_ <= job.out_rows) ? L_ : (job.out_rows - seg0);
-        const int64_t total = Lw * k;
+        const int64_t nw = (seg0 + n <= out_rows) ? n : (out_rows - seg0);
+        const int64_t total = nw * k;
         int32_t* dst = job.out + seg0 * k;
         for (int64_t e = tid; e < total; e += kSortBlock) {
             const int64_t r = e / k;
@@ -641,68 +720,121 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
     }
 }
 
-// Global-memory tier for segments larger than any LDS tile: bitonic sort of
-// row indices in the job's scratch (2 * rows entries, disjoint per
-// segment), comparing rows straight from the input columns.
-__device__ __forceinline__ bool glb_row_less(const SortJob& a, int64_t seg0, uint32_t x, uint32_t y) {
+// ---- merge tier, for segments larger than the largest LDS tile --------------
+//
+// The segment is cut into chunks of the LDS tile's row count; each chunk is
+// sorted in LDS into a run of row indices, then runs are merged pairwise,
+// one launch per pass: an element's place in the merged run is its place in
+// its own run plus its rank in the partner run (binary search comparing rows
+// in the table).  Indices ping-pong between the two halves of the job's
+// index scratch at 2 * seg0; a last launch writes the rows.  Every launch
+// spreads each segment's work over all workgroups, starting at a different
+// workgroup per segment.
+
+__device__ __forceinline__ int glb_row_cmp(const SortJob& a, int64_t seg0, uint32_t x, uint32_t y) {
     for (int j = 1; j < a.k; j++) {
         const int32_t* c = a.in + (int64_t)a.perm[j] * a.in_stride + seg0;
         const int32_t p = c[x], q = c[y];
-        if (p != q) return p < q;
+        if (p != q) return p < q ? -1 : 1;
     }
-    return false;
+    return 0;
 }
 
-__global__ __launch_bounds__(kSortBlock) void sort_global_kernel(const SortLaunch L) {
-    __shared__ SortJob job;
-    __shared__ int64_t s_seg[2];
+__device__ __forceinline__ int ceil_log2_i64(int64_t x) {
+    int r = 0;
+    while (((int64_t)1 << r) < x) r++;
+    return r;
+}
+
+// first unit of segment i that workgroup b handles when units are dealt round-robin
+__device__ __forceinline__ int64_t first_unit(int64_t i) {
+    const int64_t G = gridDim.x;
+    return ((int64_t)blockIdx.x + G - (i % G)) % G;
+}
+
+__global__ __launch_bounds__(kSortBlock) void sort_chunk_kernel(const SortLaunch L) {
+    extern __shared__ int32_t lds[];
     const int tid = threadIdx.x;
-    const int64_t n_items = (int64_t)*L.list_n;
-    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int64_t item = (int64_t)L.list[it];
-        sort_item_setup(L, item, job, s_seg);
-        const int64_t seg0 = s_seg[0], seg1 = s_seg[1];
-        const int64_t L_ = seg1 - seg0;
-        const int k = job.k;
-        __syncthreads();
-        if (L_ == 0 || seg0 >= job.out_rows) continue;
-        uint32_t* idx = job.scratch_idx + 2 * seg0;
-        int64_t P = 1;
-        while (P < L_) P <<= 1;
-        for (int64_t i = tid; i < P; i += kSortBlock) idx[i] = i < L_ ? (uint32_t)i : kSent;
-        __threadfence_block();
-        __syncthreads();
-        for (int64_t size = 2; size <= P; size <<= 1) {
-            for (int64_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int64_t t = tid; t < (P >> 1); t += kSortBlock) {
-                    const int64_t lo = 2 * t - (t & (stride - 1));
-                    const int64_t hi = lo + stride;
-                    const bool asc = (lo & size) == 0;
-                    const uint32_t ia = idx[lo], ib = idx[hi];
-                    bool gt;
-                    if (ia == kSent) gt = (ib != kSent);
-                    else if (ib == kSent) gt = false;
-                    else gt = glb_row_less(job, seg0, ib, ia);
-                    if (gt == asc) {
-                        idx[lo] = ib;
-                        idx[hi] = ia;
-                    }
-                }
-                __threadfence_block();
-                __syncthreads();
-            }
+    const int64_t n_list = *L.list_n;
+    for (int64_t i = 0; i < n_list; i++) {
+        const SegRef ref = L.list[i];
+        const SortJob& job = L.jobs[ref.item / L.n_vertices];
+        const int k = job.k, kp = job.kp;
+        const int R = lds_rows_of(L.lds_bytes, kp);
+        const int64_t nch = (ref.len + R - 1) / R;
+        if (blockIdx.x == 0 && tid == 0) atomicMax(L.max_chunks, (int32_t)(nch < INT32_MAX ? nch : INT32_MAX));
+        uint32_t* run = job.scratch_idx + 2 * ref.seg0;
+        int32_t* rows = lds;
+        uint16_t* idx = (uint16_t*)(lds + (size_t)R * kp);
+        for (int64_t c = first_unit(i); c < nch; c += gridDim.x) {
+            const int64_t r0 = c * R;
+            const int n = (int)((ref.len - r0 < R) ? (ref.len - r0) : R);
+            lds_stage_rows(job, ref.seg0 + r0, n, rows);
+            lds_bitonic(rows, idx, n, k, kp);
+            for (int r = tid; r < n; r += kSortBlock) run[r0 + r] = (uint32_t)(r0 + idx[r]);
+            __syncthreads();
         }
-        for (int64_t r = tid + 1; r < L_; r += kSortBlock)
-            if (!glb_row_less(job, seg0, idx[r - 1], idx[r])) atomicAdd(L.dup_count, 1);
-        const int64_t Lw = (seg0 + L_ <= job.out_rows) ? L_ : (job.out_rows - seg0);
-        const int64_t total = Lw * k;
-        int32_t* dst = job.out + seg0 * k;
-        for (int64_t e = tid; e < total; e += kSortBlock) {
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void sort_merge_kernel(const SortLaunch L) {
+    const int p = L.pass;
+    if (((int64_t)1 << p) >= (int64_t)*L.max_chunks) return;  // every segment is one run already
+    const int tid = threadIdx.x;
+    const int64_t n_list = *L.list_n;
+    const int64_t G = gridDim.x;
+    for (int64_t i = 0; i < n_list; i++) {
+        const SegRef ref = L.list[i];
+        const SortJob& job = L.jobs[ref.item / L.n_vertices];
+        const int R = lds_rows_of(L.lds_bytes, job.kp);
+        const int64_t len = ref.len;
+        const int64_t nch = (len + R - 1) / R;
+        if (((int64_t)1 << p) >= nch) continue;  // this segment needs fewer passes
+        const uint32_t* in = job.scratch_idx + 2 * ref.seg0 + ((p & 1) ? len : 0);
+        uint32_t* out = job.scratch_idx + 2 * ref.seg0 + ((p & 1) ? 0 : len);
+        const int64_t w = (int64_t)R << p;
+        for (int64_t e = first_unit(i) * kSortBlock + tid; e < len; e += G * kSortBlock) {
+            const uint32_t x = in[e];
+            const int64_t r = e / w, rs = r * w, ps = (r ^ 1) * w;
+            if (ps >= len) {  // no partner run in this pass
+                out[e] = x;
+                continue;
+            }
+            const int64_t pe = (ps + w < len) ? ps + w : len;
+            const bool left = (r & 1) == 0;
+            int64_t lo = ps, hi = pe;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                const int c = glb_row_cmp(job, ref.seg0, in[mid], x);
+                if (left ? (c < 0) : (c <= 0)) lo = mid + 1; else hi = mid;
+            }
+            out[(rs < ps ? rs : ps) + (e - rs) + (lo - ps)] = x;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void sort_gather_kernel(const SortLaunch L) {
+    const int tid = threadIdx.x;
+    const int64_t n_list = *L.list_n;
+    const int64_t G = gridDim.x;
+    for (int64_t i = 0; i < n_list; i++) {
+        const SegRef ref = L.list[i];
+        const SortJob& job = L.jobs[ref.item / L.n_vertices];
+        const int k = job.k;
+        const int R = lds_rows_of(L.lds_bytes, job.kp);
+        const int64_t len = ref.len;
+        const int np = ceil_log2_i64((len + R - 1) / R);
+        const uint32_t* idx = job.scratch_idx + 2 * ref.seg0 + ((np & 1) ? len : 0);
+        for (int64_t e = first_unit(i) * kSortBlock + tid; e < len; e += G * kSortBlock)
+            if (e > 0 && glb_row_cmp(job, ref.seg0, idx[e - 1], idx[e]) >= 0) atomicAdd(L.dup_count, 1);
+        const int64_t nw = (ref.seg0 + len <= job.out_rows) ? len : (job.out_rows - ref.seg0);
+        const int64_t total = nw * k;
+        int32_t* dst = job.out + ref.seg0 * k;
+        for (int64_t e = first_unit(i) * kSortBlock + tid; e < total; e += G * kSortBlock) {
             const int64_t r = e / k;
             const int j = (int)(e - r * k);
-            dst[e] = job.in[(int64_t)job.perm[j] * job.in_stride + seg0 + idx[r]];
+            dst[e] = job.in[(int64_t)job.perm[j] * job.in_stride + ref.seg0 + idx[r]];
         }
-        __syncthreads();
     }
 }
 
@@ -715,8 +847,10 @@ int sort_max_lds_bytes() {
         v -= (int)sizeof(SortJob) + 64;  // static shared of the kernel
         if (v > 160 * 1024 - 512) v = 160 * 1024 - 512;
         if (v > 64 * 1024 - 512) {
-            if (hipFuncSetAttribute((const void*)sort_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
-                hipSuccess) {
+            bool ok = true;
+            for (const void* f : {(const void*)sort_lds_kernel, (const void*)sort_chunk_kernel})
+                ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess;
+            if (!ok) {
                 (void)hipGetLastError();
                 v = 64 * 1024 - 512;
             }
@@ -731,8 +865,17 @@ hipError_t launch_sort_lds(const SortLaunch& a, int grid, int lds_bytes, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_sort_global(const SortLaunch& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(sort_global_kernel, dim3(grid), dim3(kSortBlock), 0, s, a);
+hipError_t launch_sort_merge_tier(const SortLaunch& a, int passes, hipStream_t s) {
+    hipLaunchKernelGGL(sort_chunk_kernel, dim3(256), dim3(kSortBlock), a.lds_bytes, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    SortLaunch m = a;
+    for (int p = 0; p < passes; p++) {
+        m.pass = p;
+        hipLaunchKernelGGL(sort_merge_kernel, dim3(1024), dim3(kSortBlock), 0, s, m);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(sort_gather_kernel, dim3(1024), dim3(kSortBlock), 0, s, a);
     return hipGetLastError();
 }
 

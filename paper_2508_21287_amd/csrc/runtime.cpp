@@ -107,7 +107,7 @@ dm_status Workspace::ensure_spill(int64_t n) {
     dev_free(spill, stream);
     spill = nullptr;
     int64_t c = std::max<int64_t>(n, 1024);
-    DM_TRY(dev_alloc((void**)&spill, sizeof(int32_t) * 2 * (size_t)c, stream));
+    DM_TRY(dev_alloc((void**)&spill, sizeof(SegRef) * 2 * (size_t)c, stream));
     spill_cap = c;
     return DM_OK;
 }
@@ -136,13 +136,6 @@ dm_status Workspace::next_epoch(uint32_t* e) {
 
 // ------------------------------------------------------------- plan execution
 
-static int lds_rows_for(int bytes, int kp) {
-    int r = bytes / (4 * (kp + 1));
-    int p = 1;
-    while (p * 2 <= r) p *= 2;
-    return r >= 1 ? p : 0;
-}
-
 static int auto_block(double est_rows) { return est_rows < 65536.0 ? 64 : 256; }
 
 static int ejf_grid(int64_t in_cap, double est_in, int block) {
@@ -155,7 +148,7 @@ static int ejf_grid(int64_t in_cap, double est_in, int block) {
 }
 
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
-                       int32_t v0, int32_t* spill_n, int32_t* dup) {
+                       int32_t v0, int64_t max_in_cap, int32_t max_k, int32_t* counters) {
     hipStream_t s = ws.stream;
     const int64_t items = (int64_t)n_jobs * nv;
     if (items >= (int64_t)INT32_MAX) return fail(DM_ERR_UNSUPPORTED, "batch too large: patterns x vertices >= 2^31");
@@ -166,24 +159,32 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.n_jobs = n_jobs;
     L.n_vertices = nv;
     L.v_begin = v0;
-    L.dup_count = dup;
+    L.dup_count = &counters[3];
+    L.max_chunks = &counters[2];
     // tier 1: small LDS tiles, five workgroups per CU
     L.lds_bytes = 32 * 1024 - 512;
     L.list = nullptr;
     L.spill = ws.spill;
-    L.spill_n = &spill_n[0];
+    L.spill_n = &counters[0];
     DM_HIP(launch_sort_lds(L, (int)std::min<int64_t>(std::max<int64_t>(items, 1), 8192), L.lds_bytes, s));
     // tier 2: the largest LDS allocation a workgroup can hold
     L.lds_bytes = ctx->sort_lds_max;
     L.list = ws.spill;
-    L.list_n = &spill_n[0];
+    L.list_n = &counters[0];
     L.spill = ws.spill + ws.spill_cap;
-    L.spill_n = &spill_n[1];
+    L.spill_n = &counters[1];
     DM_HIP(launch_sort_lds(L, 256, L.lds_bytes, s));
-    // tier 3: global memory
+    // tier 3: chunks of the tier-2 tile, merged pairwise
     L.list = ws.spill + ws.spill_cap;
-    L.list_n = &spill_n[1];
-    DM_HIP(launch_sort_global(L, 128, s));
+    L.list_n = &counters[1];
+    L.spill = nullptr;
+    L.spill_n = nullptr;
+    const int kp = (max_k % 2 == 0) ? max_k + 1 : max_k;
+    const int64_t r_min = std::max(lds_rows_of(L.lds_bytes, kp), 1);
+    const int64_t chunks = (std::max<int64_t>(max_in_cap, 1) + r_min - 1) / r_min;
+    int passes = 0;
+    while (((int64_t)1 << passes) < chunks) passes++;
+    DM_HIP(launch_sort_merge_tier(L, passes, s));
     return DM_OK;
 }
 
@@ -282,7 +283,8 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             const double est_in = i == 0 ? (double)(v1 - v0) : est[i - 1];
             const int64_t in_cap = i == 0 ? (int64_t)(v1 - v0) : cap[ib];
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * i], s));
-            DM_HIP(launch_ejf(a, block, ejf_grid(in_cap, est_in, block), s));
+            const int blk = ejf_block_for(a.st.c_in, block);
+            DM_HIP(launch_ejf(a, blk, ejf_grid(in_cap, est_in, blk), s));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * i + 1], s));
             if (sync_mode && !(last && hash_mode)) {
                 DM_HIP(hipMemcpyAsync(ws.ctrl_h, ws.ctrl_d, sizeof(Control), hipMemcpyDeviceToHost, s));
@@ -330,7 +332,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
             DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps], s));
-            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, ws.ctrl_d->spill_n, &ws.ctrl_d->dup));
+            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, cap[lb], k, ws.ctrl_d->sort_counters));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps + 1], s));
         }
         DM_HIP(hipEventRecord(ws.ev[1], s));
@@ -358,7 +360,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             retries++;
             continue;
         }
-        if (c.dup != 0) {
+        if (c.sort_counters[3] != 0) {
             dev_free(result, s);
             return fail(DM_ERR_INTERNAL, "duplicate rows reached the canonical table");
         }
@@ -558,7 +560,8 @@ dm::TableDev dm_datagraph::table_dev(int motif, int key_pos) const {
     TableDev t;
     std::memset(&t, 0, sizeof t);
     const MotifTable& m = tab[motif][key_pos];
-    for (int p = 0; p < m.size; p++) t.col[p] = m.cols[p];
+    t.base = m.cols[0];
+    t.stride = m.stride;
     t.offs = m.offs;
     t.rows = m.rows;
     t.size = m.size;
@@ -641,8 +644,7 @@ static void free_datagraph(dm_datagraph* dg) {
     hipStream_t s = dg->ctx->stream;
     free_tables(dg);
     dev_free(dg->row_ptr, s);
-    dev_free(dg->col, s);
-    dev_free(dg->src, s);
+    dev_free(dg->src, s);  // src and col share one allocation (src first)
     dev_free(dg->bitmap, s);
     (void)hipStreamSynchronize(s);
     delete dg;
@@ -689,7 +691,8 @@ static dm_status build_motif(dm_datagraph* dg, int m) {
         const int64_t* n_dev = &ctx->ws.ctrl_d->counts[plan.steps.size()];
         DM_HIP(launch_gather_cols(ro.table, ro.stride, n_dev, ro.rows, colmap, mi.size, data,
                                   std::max<int64_t>(ro.rows, 1), s));
-        for (int q = 0; q < mi.size; q++) t.cols[q] = data + (size_t)q * (size_t)std::max<int64_t>(ro.rows, 1);
+        t.stride = std::max<int64_t>(ro.rows, 1);
+        for (int q = 0; q < mi.size; q++) t.cols[q] = data + (size_t)q * (size_t)t.stride;
         DM_HIP(launch_offsets(t.cols[j], n_dev, ro.rows, dg->n, offs, s));
         t.offs = offs;
     }
@@ -786,8 +789,9 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
             break;
         }
         dg->nnz = nnz;
-        if ((st = dev_alloc((void**)&dg->col, sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), s))) break;
-        if ((st = dev_alloc((void**)&dg->src, sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), s))) break;
+        // src | col in one block: Res(M2) is then an ordinary 2-column SoA table
+        if ((st = dev_alloc((void**)&dg->src, sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(nnz, 1), s))) break;
+        dg->col = dg->src + std::max<int64_t>(nnz, 1);
         if (launch_ingest_compact(tmp_ptr, tmp, dg->row_ptr, n, dg->col, dg->src, flags + 2, s)) {
             st = fail(DM_ERR_DEVICE, "compact launch failed");
             break;
@@ -816,6 +820,7 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
         t.rows = dg->nnz;
         t.cols[0] = dg->src;
         t.cols[1] = dg->col;
+        t.stride = dg->col - dg->src;
         t.offs = dg->row_ptr;
         dg->stats.n_vertices = n;
         dg->stats.rows[MOT_P2] = (double)dg->nnz;

@@ -38,9 +38,7 @@ struct Control {
     int64_t counts[kMaxSteps + 2];
     int32_t overflow[kMaxSteps + 2];
     uint64_t hash[4];
-    int32_t dup;
-    int32_t spill_n[2];
-    int32_t pad;
+    int32_t sort_counters[4];  // sort tiers: spill_n[2], max_chunks, dup
 };
 
 // Scratch reused across runs of one stream: ping-pong SoA tables, look-back
@@ -55,7 +53,7 @@ struct Workspace {
     uint32_t epoch = 0;           // last used epoch (1..kEpochs-1)
     Control* ctrl_d = nullptr;
     Control* ctrl_h = nullptr;    // pinned host mirror
-    int32_t* spill = nullptr;     // 2 lists of n_vertices entries
+    SegRef* spill = nullptr;      // 2 lists of n_vertices entries (sort tier hand-over)
     int64_t spill_cap = 0;
     uint32_t* sort_scratch = nullptr;
     int64_t sort_scratch_elems = 0;
@@ -76,7 +74,8 @@ struct Workspace {
 
 // Motif table keyed on one position (see TableDev).
 struct MotifTable {
-    int32_t* cols[kMaxMotif] = {};  // column of each motif position
+    int32_t* cols[kMaxMotif] = {};  // column of each motif position (cols[p] = cols[0] + p * stride)
+    int64_t stride = 0;
     int32_t* offs = nullptr;        // n_vertices + 1
     int64_t rows = 0;
     int32_t size = 0;
@@ -170,10 +169,14 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
 dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const Plan& plan,
                            const RunOptions& opt, RunOutput* out);
 
-// Canonicalize n_jobs final tables (jobs already in device memory): three
-// sort tiers on ws.stream; spill_n[0..1] and *dup must be zero beforehand.
+// Canonicalize n_jobs final tables (jobs already in device memory) on
+// ws.stream: two LDS tiers, then chunk sort + merge passes for the rest.
+// max_in_cap / max_k bound every job's rows and width (they size the number
+// of merge passes); counters = 4 zeroed int32 in device memory
+// (spill_n[2], max_chunks, dup), dup is nonzero afterwards if two rows of a
+// segment were equal.
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
-                       int32_t v0, int32_t* spill_n, int32_t* dup);
+                       int32_t v0, int64_t max_in_cap, int32_t max_k, int32_t* counters);
 
 dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan);
 RunOptions run_options(const dm_plan_opts* opts, int64_t cap);
