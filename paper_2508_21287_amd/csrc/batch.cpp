@@ -56,14 +56,13 @@ struct Item {
     int64_t cap = -1;  // max embeddings
     Plan plan;
     std::vector<StepDesc> steps;
-    int64_t tcap = 0;  // table capacity (rows) of each ping-pong buffer
-    int64_t out_rows = 0;
+    int64_t out_rows = 0;  // rows of its sorted result
     // root range [r0, r1) of the identity table: a capped item starts with the
     // lowest roots expected to hold the cap (grouped-by-root tables make that
     // prefix the start of the canonical order)
     int32_t r0 = 0, r1 = 0;
-    // arena offsets (bytes)
-    size_t off_buf[2] = {0, 0}, off_status = 0, off_counts = 0, off_flags = 0, off_hash = 0, off_res = 0;
+    // control-arena / result-block offsets (bytes)
+    size_t off_counts = 0, off_flags = 0, off_hash = 0, off_res = 0;
 };
 
 }  // namespace
@@ -72,6 +71,11 @@ namespace dm {
 
 // Run a set of already-validated patterns as one batch on workspace `ws`.
 // results[i] receives item i's result (owned by the caller).
+//
+// One persistent launch runs every pattern's steps; step tables live in the
+// workspace's device heap, each cut when its step is published with exactly
+// the candidate bound of rows.  After one readback of the counts, the
+// result block is allocated at its exact size and the sort runs.
 static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& items, const dm_plan_opts* opts,
                            std::vector<dm_result*>& results) {
     dm_context* ctx = dg->ctx;
@@ -80,40 +84,49 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     const int nb = (int)items.size();
     const bool hash_mode = opts && opts->output_mode == DM_OUT_COUNT_HASH;
     const bool profile = opts && opts->profile;
+    const bool timing = std::getenv("DMOTIF_BATCH_TIMING") != nullptr;
+    const int64_t row_limit = opts && opts->initial_rows > 0 ? opts->initial_rows : 0;
+    const int64_t budget = opts && opts->mem_budget > 0 ? opts->mem_budget : (int64_t)48 << 30;
     results.assign(nb, nullptr);
     if (nb == 0) return DM_OK;
+    auto ms_since = [](std::chrono::steady_clock::time_point a) {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+    };
+    const auto t0 = std::chrono::steady_clock::now();
 
-    // ---- layout: one arena for tables + control, one block for results
-    size_t arena = 0, resb = 0;
+    // ---- step-0 tables are reserved here; every later table on the device
     int total_steps = 0, cmax = 1, max_k = 1;
-    int64_t max_tcap = 1;
-    for (auto& it : items) {
+    int64_t heap0 = 0, words0 = 0;
+    std::vector<int64_t> h_off(nb), w_off(nb), rows0(nb);
+    for (int p = 0; p < nb; p++) {
+        Item& it = items[p];
+        const StepDesc& d0 = it.steps[0];
         const int32_t nr = it.r1 - it.r0;
-        const double frac = nv > 0 ? (double)nr / nv : 1.0;
-        double est = (double)nr;
-        for (auto& ps : it.plan.steps) est = std::max(est, ps.est_rows * frac);
-        const int64_t first_max = std::min<int64_t>(((int64_t)1 << 28) / it.k, (int64_t)1 << 26);
-        it.tcap = std::max<int64_t>(std::min<int64_t>((int64_t)(2.0 * est) + 4096, first_max), 4096);
-        if (opts && opts->initial_rows > 0) it.tcap = opts->initial_rows;
-        it.out_rows = it.cap >= 0 ? std::min<int64_t>(it.cap, it.tcap) : it.tcap;
-        for (int b = 0; b < 2; b++) {
-            it.off_buf[b] = arena;
-            arena = align256(arena + sizeof(int32_t) * (size_t)(it.tcap * it.k));
-        }
+        int64_t r = 0;
+        if (!(hash_mode && it.steps.size() == 1))
+            r = d0.motif >= 0 ? dg->table_dev(d0.motif, d0.key_pos).rows : (int64_t)nr;
+        if (row_limit > 0) r = std::min(r, row_limit);
+        rows0[p] = r;
+        h_off[p] = heap0;
+        heap0 += (r * (d0.c_in + (d0.motif >= 0 ? d0.n_new : 0)) + 63) & ~(int64_t)63;
+        w_off[p] = words0;
+        words0 += (nr + kBatchTile - 1) / kBatchTile + 2;
         total_steps += (int)it.steps.size();
         for (auto& d : it.steps) cmax = std::max(cmax, (int)d.c_in);
         max_k = std::max(max_k, it.k);
-        max_tcap = std::max(max_tcap, it.tcap);
-        if (!hash_mode) {
-            it.off_res = resb;
-            resb = align256(resb + sizeof(int32_t) * (size_t)std::max<int64_t>(it.out_rows * it.k, 1));
-        }
     }
-    const size_t ctl_begin = arena;
+    // first heap: 1 GiB (DMOTIF_BATCH_HEAP_MB overrides), within the budget;
+    // it grows when a batch does not fit
+    const int64_t budget_elems = budget / 4;
+    const int64_t first_heap = (int64_t)env_int("DMOTIF_BATCH_HEAP_MB", 1024) << 18;
+    DM_TRY(ws.ensure_heap(std::min<int64_t>(std::max<int64_t>(ws.heap_elems, first_heap), budget_elems),
+                          2 * heap0, 2 * words0));
+    const uint32_t epoch = ws.next_heap_epoch();
+    if (epoch == 0) return fail(DM_ERR_DEVICE, "look-back word reset failed");
+
+    // ---- control arena: [counts, flags, hash per item | misc | tops] [jobs] [ctl | first | nsteps | args]
+    size_t arena = 0;
     for (auto& it : items) {
-        it.off_status = arena;
-        // look-back words: one per tile of the largest input (the identity has nv rows)
-        arena = align256(arena + sizeof(uint64_t) * (size_t)(std::max<int64_t>(it.tcap, nv) / kBatchTile + 2));
         it.off_counts = arena;
         arena = align256(arena + sizeof(int64_t) * (it.steps.size() + 2));
         it.off_flags = arena;
@@ -123,7 +136,14 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     }
     const size_t off_misc = arena;  // finished, sort counters (spill_n[2], max_chunks, dup)
     arena = align256(arena + 64);
-    const size_t ctl_end = arena;
+    const size_t off_fail = arena;
+    arena = align256(arena + sizeof(int32_t) * nb);
+    const size_t off_tops = arena;  // heap top, words top
+    arena = align256(arena + 2 * sizeof(unsigned long long));
+    const size_t zero_end = arena;
+    const size_t off_jobs = arena;
+    arena = align256(arena + sizeof(SortJob) * nb);
+    const size_t back_end = arena;
     const size_t off_ctl = arena;
     arena = align256(arena + sizeof(BatchCtl) * nb);
     const size_t off_first = arena;
@@ -132,27 +152,18 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     arena = align256(arena + sizeof(int32_t) * nb);
     const size_t off_args = arena;
     arena = align256(arena + sizeof(EjfArgs) * total_steps);
-    const size_t off_jobs = arena;
-    arena = align256(arena + sizeof(SortJob) * nb);
-    const size_t off_upload = off_ctl;  // ctl .. jobs are staged on the host and uploaded at once
 
     char* A = nullptr;
     DM_TRY(dev_alloc((void**)&A, arena, s));
     std::unique_ptr<DevBlock> arena_guard(new DevBlock{A, s});
-    std::shared_ptr<DevBlock> res_block;
-    char* R = nullptr;
-    if (!hash_mode) {
-        DM_TRY(dev_alloc((void**)&R, resb, s));
-        res_block.reset(new DevBlock{R, s});
-    }
 
-    // ---- host staging of controllers, argument blocks and sort jobs
-    std::vector<char> host(arena - off_upload, 0);
-    BatchCtl* ctl = (BatchCtl*)(host.data() + (off_ctl - off_upload));
-    int32_t* first = (int32_t*)(host.data() + (off_first - off_upload));
-    int32_t* nsteps = (int32_t*)(host.data() + (off_nsteps - off_upload));
-    EjfArgs* args = (EjfArgs*)(host.data() + (off_args - off_upload));
-    SortJob* jobs = (SortJob*)(host.data() + (off_jobs - off_upload));
+    // ---- host staging of sort jobs, controllers and argument blocks
+    std::vector<char> host(arena - off_jobs, 0);
+    SortJob* jobs = (SortJob*)(host.data() + (off_jobs - off_jobs));
+    BatchCtl* ctl = (BatchCtl*)(host.data() + (off_ctl - off_jobs));
+    int32_t* first = (int32_t*)(host.data() + (off_first - off_jobs));
+    int32_t* nsteps = (int32_t*)(host.data() + (off_nsteps - off_jobs));
+    EjfArgs* args = (EjfArgs*)(host.data() + (off_args - off_jobs));
     int a_i = 0;
     const GraphDev g = dg->graph_dev();
     for (int p = 0; p < nb; p++) {
@@ -171,44 +182,44 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             a.st = it.steps[i];
             if (a.st.motif >= 0) a.tbl = dg->table_dev(a.st.motif, a.st.key_pos);
             a.g = g;
-            const int ib = (i - 1) & 1, ob = i & 1;
-            a.in = i == 0 ? nullptr : (const int32_t*)(A + it.off_buf[ib]);
-            a.in_stride = i == 0 ? 0 : it.tcap;
-            a.in_cap = i == 0 ? nr : it.tcap;
             a.n_in = &counts[i];
             a.id_begin = it.r0;
             a.id_count = nr;
-            a.out = (int32_t*)(A + it.off_buf[ob]);
-            a.out_stride = it.tcap;
-            a.out_cap = it.tcap;
             a.n_out = &counts[i + 1];
             a.overflow = &flags[i];
-            a.status = (uint64_t*)(A + it.off_status);
-            a.epoch = (uint32_t)(i + 1);
+            a.epoch = epoch;
             a.ticket = nullptr;
             a.mode = (hash_mode && i == ns - 1) ? EJF_HASH : EJF_WRITE;
             a.hash_acc = (uint64_t*)(A + it.off_hash);
             for (int c = 0; c < it.k; c++) a.pv[c] = (uint8_t)std::max(it.plan.pv_of[c], 0);
+            if (i + 1 < ns && !(hash_mode && i + 1 == ns - 1)) {
+                const StepDesc& nx = it.steps[i + 1];
+                a.next_cand = (int64_t*)(A + off_ctl + sizeof(BatchCtl) * p + offsetof(BatchCtl, cand)) + (i + 1);
+                a.next_key_col = nx.motif >= 0 ? nx.key_col : -1;
+                a.next_offs = nx.motif >= 0 ? dg->table_dev(nx.motif, nx.key_pos).offs : nullptr;
+            }
+            if (i == 0) {
+                // identity input; output and look-back words reserved above
+                a.in = nullptr;
+                a.in_cap = nr;
+                a.out = ws.heap + h_off[p];
+                a.out_stride = std::max<int64_t>(rows0[p], 1);
+                a.out_cap = rows0[p];
+                a.status = ws.heap_words + w_off[p];
+            }
         }
         SortJob& j = jobs[p];
-        std::memset(&j, 0, sizeof j);
-        const int lb = (ns - 1) & 1;
-        j.in = (const int32_t*)(A + it.off_buf[lb]);
-        j.in_stride = it.tcap;
-        j.in_cap = it.tcap;
         j.n_in = &counts[ns];
-        j.out = hash_mode ? nullptr : (int32_t*)(R + it.off_res);
-        j.out_rows = it.out_rows;
-        // the other ping-pong buffer is idle after the last step: index scratch
-        j.scratch_idx = (uint32_t*)(A + it.off_buf[lb ^ 1]);
         j.k = it.k;
         j.kp = (it.k % 2 == 0) ? it.k + 1 : it.k;
         for (int c = 0; c < it.k; c++) j.perm[c] = (uint8_t)it.plan.col_of[c];
     }
     int32_t* misc = (int32_t*)(A + off_misc);
+    unsigned long long tops[2] = {(unsigned long long)heap0, (unsigned long long)words0};
 
-    DM_HIP(launch_fill_u64((uint64_t*)(A + ctl_begin), 0, (int64_t)((ctl_end - ctl_begin) / 8), s));
-    DM_HIP(hipMemcpyAsync(A + off_upload, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    DM_HIP(launch_fill_u64((uint64_t*)A, 0, (int64_t)(zero_end / 8), s));
+    DM_HIP(hipMemcpyAsync(A + off_tops, tops, sizeof tops, hipMemcpyHostToDevice, s));
+    DM_HIP(hipMemcpyAsync(A + off_jobs, host.data(), host.size(), hipMemcpyHostToDevice, s));
 
     hipEvent_t ev[4];
     for (auto& e : ev) DM_HIP(hipEventCreate(&e));
@@ -220,29 +231,40 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     } evg{ev};
 
     BatchDev bd;
-    bd.args = (const EjfArgs*)(A + off_args);
+    std::memset(&bd, 0, sizeof bd);
+    bd.args = (EjfArgs*)(A + off_args);
     bd.first = (const int32_t*)(A + off_first);
     bd.nsteps = (const int32_t*)(A + off_nsteps);
     bd.ctl = (BatchCtl*)(A + off_ctl);
     bd.finished = &misc[0];
+    bd.heap_fail = (int32_t*)(A + off_fail);
+    bd.jobs = hash_mode ? nullptr : (SortJob*)(A + off_jobs);
+    bd.heap = ws.heap;
+    bd.heap_cap = std::max(std::min(ws.heap_elems, budget_elems), heap0);
+    bd.heap_top = (unsigned long long*)(A + off_tops);
+    bd.words = ws.heap_words;
+    bd.words_cap = ws.heap_words_cap;
+    bd.words_top = (unsigned long long*)(A + off_tops) + 1;
+    bd.row_limit = row_limit;
     bd.n_patterns = nb;
     bd.max_backoff = env_int("DMOTIF_BATCH_BACKOFF", 15);
     const int grid = env_int("DMOTIF_BATCH_GRID", 1024);
+    const double t_stage = ms_since(t0);
     DM_HIP(hipEventRecord(ev[0], s));
     DM_HIP(launch_batch(bd, cmax, grid, s));
     DM_HIP(hipEventRecord(ev[1], s));
-    if (!hash_mode)
-        DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, max_tcap, max_k, &misc[1]));
-    DM_HIP(hipEventRecord(ev[2], s));
 
-    // ---- one readback of every count, flag and hash
-    std::vector<char> back(ctl_end - ctl_begin);
-    DM_HIP(hipMemcpyAsync(back.data(), A + ctl_begin, back.size(), hipMemcpyDeviceToHost, s));
+    // ---- readback 1: counts, flags, hashes, failures, heap use, sort jobs
+    std::vector<char> back(back_end);
+    DM_HIP(hipMemcpyAsync(back.data(), A, back.size(), hipMemcpyDeviceToHost, s));
     DM_HIP(hipStreamSynchronize(s));
-    float ms_join = 0, ms_sort = 0;
-    (void)hipEventElapsedTime(&ms_join, ev[0], ev[1]);
-    (void)hipEventElapsedTime(&ms_sort, ev[1], ev[2]);
-    auto hb = [&](size_t off) { return back.data() + (off - ctl_begin); };
+    const double t_join = ms_since(t0);
+    auto hb = [&](size_t off) { return back.data() + off; };
+    const int32_t* hmisc = (const int32_t*)hb(off_misc);
+    if (hmisc[0] != nb) return fail(DM_ERR_INTERNAL, "persistent kernel retired " + std::to_string(hmisc[0]) +
+                                                         " of " + std::to_string(nb) + " patterns");
+    const int32_t* hfail = (const int32_t*)hb(off_fail);
+    const unsigned long long* htops = (const unsigned long long*)hb(off_tops);
     if (const char* trace = std::getenv("DMOTIF_BATCH_TRACE")) {
         // per-pattern stage timeline (device wall clock at each step's publication)
         std::vector<BatchCtl> hc(nb);
@@ -250,14 +272,14 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         int khz = 100000;
         (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device);
         if (FILE* f = std::fopen(trace, "a")) {
-            int64_t t0 = INT64_MAX;
-            for (int p = 0; p < nb; p++) t0 = std::min(t0, hc[p].t_pub[0]);
+            int64_t tmin = INT64_MAX;
+            for (int p = 0; p < nb; p++) tmin = std::min(tmin, hc[p].t_pub[0]);
             for (int p = 0; p < nb; p++) {
                 const int ns = (int)items[p].steps.size();
                 const int64_t* counts = (const int64_t*)hb(items[p].off_counts);
                 std::fprintf(f, "{\"pattern\": %d, \"k\": %d, \"steps\": [", items[p].idx, items[p].k);
                 for (int i = 0; i <= ns; i++) {
-                    const double us = hc[p].t_pub[i] ? 1e3 * (double)(hc[p].t_pub[i] - t0) / khz : -1.0;
+                    const double us = hc[p].t_pub[i] ? 1e3 * (double)(hc[p].t_pub[i] - tmin) / khz : -1.0;
                     std::fprintf(f, "%s[%.1f, %lld, %d]", i ? ", " : "", us, (long long)counts[i],
                                  i < ns ? hc[p].ntiles[i] : 0);
                 }
@@ -266,13 +288,14 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             std::fclose(f);
         }
     }
-    const int32_t* hmisc = (const int32_t*)hb(off_misc);
-    if (hmisc[0] != nb) return fail(DM_ERR_INTERNAL, "persistent kernel retired " + std::to_string(hmisc[0]) +
-                                                         " of " + std::to_string(nb) + " patterns");
-    if (hmisc[4] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached a canonical table");
 
-    int64_t all_bytes = 0;
-    std::vector<int64_t> pbytes(nb, 0);
+    // ---- classify: done in the batch, or redone (overflow, short prefix, no heap room)
+    std::vector<char> redo(nb, 0), grow(nb, 0);
+    std::vector<int64_t> n_final(nb, 0);
+    size_t resb = 0;
+    int64_t max_rows = 1;
+    int n_grow = 0;
+    SortJob* hjobs = (SortJob*)hb(off_jobs);
     for (int p = 0; p < nb; p++) {
         Item& it = items[p];
         const int ns = (int)it.steps.size();
@@ -281,17 +304,110 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         const uint64_t* hash = (const uint64_t*)hb(it.off_hash);
         bool over = false;
         for (int i = 0; i < ns; i++) over |= flags[i] != 0;
+        n_final[p] = hash_mode ? (int64_t)hash[0] : counts[ns];
         // a capped item whose root prefix held fewer rows than the cap
-        const bool partial = !hash_mode && !over && it.r1 < nv && it.cap >= 0 && counts[ns] < it.cap;
-        over |= partial;
+        const bool partial = !hash_mode && !over && it.r1 < nv && it.cap >= 0 && n_final[p] < it.cap;
+        if (hfail[p]) {
+            grow[p] = 1;
+            n_grow++;
+        } else if (over || partial) {
+            redo[p] = 1;
+        }
+        SortJob& j = hjobs[p];
+        if (hash_mode || grow[p] || redo[p] || n_final[p] == 0) {
+            j.in_cap = 0;  // nothing to sort for this job
+            j.out = nullptr;
+            j.out_rows = 0;
+            it.out_rows = 0;
+            continue;
+        }
+        it.out_rows = it.cap >= 0 ? std::min<int64_t>(it.cap, n_final[p]) : n_final[p];
+        it.off_res = resb;
+        resb = align256(resb + sizeof(int32_t) * (size_t)std::max<int64_t>(it.out_rows * it.k, 1));
+        max_rows = std::max(max_rows, n_final[p]);
+    }
+
+    // ---- sort into the exact-size result block
+    std::shared_ptr<DevBlock> res_block;
+    char* R = nullptr;
+    float ms_join = 0, ms_sort = 0;
+    (void)hipEventElapsedTime(&ms_join, ev[0], ev[1]);
+    if (!hash_mode && resb > 0) {
+        DM_TRY(dev_alloc((void**)&R, resb, s));
+        res_block.reset(new DevBlock{R, s});
+        for (int p = 0; p < nb; p++) {
+            if (items[p].out_rows > 0) hjobs[p].out = (int32_t*)(R + items[p].off_res);
+            hjobs[p].out_rows = items[p].out_rows;
+        }
+        DM_HIP(hipMemcpyAsync(A + off_jobs, hjobs, sizeof(SortJob) * nb, hipMemcpyHostToDevice, s));
+        DM_HIP(hipEventRecord(ev[2], s));
+        DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, max_rows, max_k, &misc[1]));
+        DM_HIP(hipEventRecord(ev[3], s));
+        int32_t sc[4];
+        DM_HIP(hipMemcpyAsync(sc, &misc[1], sizeof sc, hipMemcpyDeviceToHost, s));
+        DM_HIP(hipStreamSynchronize(s));
+        if (sc[3] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached a canonical table");
+        (void)hipEventElapsedTime(&ms_sort, ev[2], ev[3]);
+    }
+    if (timing)
+        std::fprintf(stderr,
+                     "[batch] %d patterns | heap %.1f MB used of %.1f MB, words %llu | results %.1f MB | stage %.2f ms, "
+                     "join+readback %.2f ms, sort+readback %.2f ms | join %.2f ms, sort %.2f ms | redo %d, grow %d\n",
+                     nb, 4e-6 * (double)htops[0], 4e-6 * (double)ws.heap_elems, (unsigned long long)htops[1],
+                     resb / 1e6, t_stage, t_join - t_stage, ms_since(t0) - t_join, ms_join, ms_sort,
+                     (int)std::count(redo.begin(), redo.end(), 1), n_grow);
+
+    // ---- patterns whose tables did not fit: a larger heap, then one more batch
+    std::vector<dm_result*> regrown;
+    std::vector<int> grow_idx;
+    if (n_grow > 0) {
+        const int64_t used = (int64_t)htops[0];
+        const int64_t want = std::min<int64_t>(std::max<int64_t>(4 * bd.heap_cap, 2 * used), budget_elems);
+        std::vector<Item> sub;
+        for (int p = 0; p < nb; p++)
+            if (grow[p]) {
+                if (want > bd.heap_cap) {
+                    sub.push_back(items[p]);
+                    grow_idx.push_back(p);
+                } else {
+                    redo[p] = 1;  // the heap is at the memory budget: root-range chunks instead
+                }
+            }
+        if (!sub.empty()) {
+            DM_TRY(ws.ensure_heap(want, 0, 0));
+            DM_TRY(run_batch(dg, ws, sub, opts, regrown));
+        }
+    }
+
+    int64_t all_bytes = 0;
+    std::vector<int64_t> pbytes(nb, 0);
+    auto cleanup = [&]() {
+        for (auto*& r : results) dm_result_free(r), r = nullptr;
+        for (auto*& r : regrown) dm_result_free(r), r = nullptr;
+    };
+    for (size_t q = 0; q < grow_idx.size(); q++) {
+        results[grow_idx[q]] = regrown[q];
+        regrown[q] = nullptr;
+    }
+    for (int p = 0; p < nb; p++) {
+        if (results[p]) continue;
+        Item& it = items[p];
+        const int ns = (int)it.steps.size();
+        const int64_t* counts = (const int64_t*)hb(it.off_counts);
+        const uint64_t* hash = (const uint64_t*)hb(it.off_hash);
         dm_result* r = nullptr;
-        if (over) {
-            // first-attempt capacity too small (or a short root prefix): redo
-            // this pattern alone over every root, exact sizes
+        if (redo[p]) {
+            // first-attempt capacity too small, a short root prefix, or no
+            // heap room within the budget: redo this pattern alone over every
+            // root, exact sizes
             RunOptions ro = run_options(opts, it.cap);
             ro.sync_each_step = true;
             RunOutput o;
-            DM_TRY(run_plan_chunked(ctx, ws, dg, it.plan, ro, &o));
+            dm_status st = run_plan_chunked(ctx, ws, dg, it.plan, ro, &o);
+            if (st != DM_OK) {
+                cleanup();
+                return st;
+            }
             r = new dm_result();
             r->ctx = ctx;
             r->width = it.k;
@@ -313,19 +429,20 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             r->width = it.k;
             r->stream = ctx->stream;
             r->mode = hash_mode ? DM_OUT_COUNT_HASH : DM_OUT_TABLE;
-            const int64_t n_final = hash_mode ? (int64_t)hash[0] : counts[ns];
-            r->total = (it.r1 < nv || it.r0 > 0) ? -1 : n_final;  // a root prefix does not count them all
+            r->total = (it.r1 < nv || it.r0 > 0) ? -1 : n_final[p];  // a root prefix does not count them all
             if (hash_mode) {
                 r->hsum = hash[1];
                 r->hxor = hash[2];
             } else {
-                r->rows = it.cap >= 0 ? std::min<int64_t>(it.cap, n_final) : n_final;
-                r->data = (int32_t*)(R + it.off_res);
-                r->block = res_block;
+                r->rows = it.out_rows;
+                if (it.out_rows > 0) {
+                    r->data = (int32_t*)(R + it.off_res);
+                    r->block = res_block;
+                }
             }
             r->stats.n_steps = (int32_t)it.plan.steps.size();
             r->stats.chunks = 1;
-            int64_t prev_rows = nv, bytes = 0;
+            int64_t prev_rows = it.r1 - it.r0, bytes = 0;
             int prev_cols = 1;
             for (int i = 0; i < ns; i++) {
                 const int64_t rr = (hash_mode && i == ns - 1) ? (int64_t)hash[0] : counts[i + 1];
@@ -337,7 +454,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
                 prev_cols = cols;
             }
             r->stats.join_bytes = bytes;
-            if (!hash_mode) r->stats.sort_bytes = 8 * (int64_t)it.k * n_final;
+            if (!hash_mode) r->stats.sort_bytes = 8 * (int64_t)it.k * n_final[p];
             r->stats.bytes_moved = r->stats.join_bytes + r->stats.sort_bytes;
             pbytes[p] = bytes;
             all_bytes += bytes;
@@ -347,10 +464,11 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     // batch-level device times, split by each pattern's share of the bytes so
     // that sums over the batch give the launch totals
     int64_t all_sort = 0;
-    for (auto* r : results) all_sort += r->stats.sort_bytes;
+    for (int p = 0; p < nb; p++)
+        if (pbytes[p] > 0) all_sort += results[p]->stats.sort_bytes;
     for (int p = 0; p < nb; p++) {
         dm_result* r = results[p];
-        if (pbytes[p] == 0 && r->stats.retries > 0) continue;
+        if (pbytes[p] == 0) continue;  // redone or regrown: its own stats
         const double fj = all_bytes > 0 ? (double)pbytes[p] / all_bytes : 1.0 / nb;
         const double fs = all_sort > 0 ? (double)r->stats.sort_bytes / all_sort : 1.0 / nb;
         r->stats.device_ms = fj * ms_join + fs * ms_sort;
@@ -372,6 +490,7 @@ dm_status enumerate_many(dm_datagraph* dg, Workspace& ws, int32_t n, const dm_gr
     for (int32_t i = 0; i < n; i++) outs[i] = nullptr;
     const int32_t mode = opts ? opts->output_mode : DM_OUT_TABLE;
     if (mode != DM_OUT_TABLE && mode != DM_OUT_COUNT_HASH) return fail(DM_ERR_INVALID_ARG, "bad output mode");
+    const auto t_plan0 = std::chrono::steady_clock::now();
     std::vector<Item> items;
     std::vector<int32_t> solo;
     std::vector<dm_result*> done(n, nullptr);
@@ -427,6 +546,9 @@ dm_status enumerate_many(dm_datagraph* dg, Workspace& ws, int32_t n, const dm_gr
         }
         items.push_back(std::move(it));
     }
+    if (std::getenv("DMOTIF_BATCH_TIMING"))
+        std::fprintf(stderr, "[batch] validate+plan %d patterns: %.2f ms\n", n,
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_plan0).count());
     std::vector<dm_result*> res;
     dm_status st = run_batch(dg, ws, items, opts, res);
     if (st != DM_OK) {

@@ -60,6 +60,14 @@ struct EjfArgs {
     uint32_t epoch;       // tags this launch's look-back words
     int32_t mode;         // EJF_WRITE or EJF_HASH
     uint64_t* hash_acc;   // EJF_HASH: [count, sum, xor]
+    // Batched form: while this step writes, *next_cand accumulates the
+    // candidate count of every output row for the next step (its motif
+    // index range at column next_key_col, or 1 when next_key_col < 0: a
+    // filter step), an exact upper bound of the next step's output rows.
+    int64_t* next_cand;   // nullptr = not needed
+    const int32_t* next_offs;
+    int32_t next_key_col;
+    int32_t pad_;
     uint8_t pv[kMaxCols]; // EJF_HASH: pattern vertex of each output column
 };
 
@@ -124,6 +132,7 @@ __host__ __device__ inline int lds_rows_of(int lds_bytes, int kp) {
 struct BatchCtl {
     int32_t stage;  // step being processed; == n_steps once retired
     int32_t pad_[3];
+    int64_t cand[kMaxSteps];  // upper bound of step s's output rows (see EjfArgs::next_cand)
     int32_t ntiles[kMaxSteps];
     int32_t claim[kMaxSteps];
     int32_t done[kMaxSteps];
@@ -131,12 +140,25 @@ struct BatchCtl {
     int64_t t_pub[kMaxSteps + 1];  // device wall clock when step s was published (s = n_steps: retired)
 };
 
+// Device heap of the batched form: when a step is published, its output
+// table (rows = the exact candidate bound) and its look-back words are cut
+// from these arrays by bump allocation; a pattern whose tables do not fit
+// is retired with heap_fail set and redone by the host.
 struct BatchDev {
-    const EjfArgs* args;   // all (pattern, step) argument blocks
+    EjfArgs* args;         // all (pattern, step) argument blocks; out/in/status filled on publication
     const int32_t* first;  // per pattern: index of its step 0 in args
     const int32_t* nsteps; // per pattern
     BatchCtl* ctl;         // per pattern, zeroed except ntiles[0]/n_in[0]
     int32_t* finished;     // retired patterns
+    int32_t* heap_fail;    // per pattern: 1 = its tables did not fit the heap
+    SortJob* jobs;         // per pattern: in/in_stride/in_cap/scratch_idx set when its last step ends
+    int32_t* heap;
+    int64_t heap_cap;      // int32 elements
+    unsigned long long* heap_top;
+    uint64_t* words;
+    int64_t words_cap;
+    unsigned long long* words_top;
+    int64_t row_limit;     // > 0: cap every step's output capacity (forces the overflow path)
     int32_t n_patterns;
     int32_t max_backoff;   // idle polling backoff cap (units of s_sleep(16))
 };

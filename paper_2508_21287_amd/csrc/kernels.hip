@@ -293,6 +293,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
     // each thread's candidate cursor survives across passes, so every
     // candidate is visited once however many passes the tile needs
     int32_t m_cur = lo, r_cur = 0;
+    int64_t cand_acc = 0;  // next step's candidates of the rows this thread writes
     for (int32_t w0 = 0; w0 < total; w0 += CH) {
         while (r_cur < cnt && m_cur < hi) {
             const int32_t li = local0 + r_cur;
@@ -315,9 +316,9 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             int32_t* dst = a.out + orow;
             const int64_t os = a.out_stride;
             for (int c = 0; c < c_in; c++) dst[(int64_t)c * os] = prow[c];
+            const int32_t* tb = a.tbl.base + m;
+            const int64_t ts = a.tbl.stride;
             if (n_new > 0) {
-                const int32_t* tb = a.tbl.base + m;
-                const int64_t ts = a.tbl.stride;
                 for (int t0 = 0; t0 < n_new; t0 += 4) {
                     int32_t w4[4];
 #pragma unroll
@@ -328,8 +329,21 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
                         if (t0 + j < n_new) dst[(int64_t)(c_in + t0 + j) * os] = w4[j];
                 }
             }
+            if (a.next_cand) {
+                const int nk = a.next_key_col;
+                if (nk < 0) {
+                    cand_acc += 1;
+                } else {
+                    const int32_t kv = nk < c_in ? prow[nk] : tb[(int64_t)st.new_pos[nk - c_in] * ts];
+                    cand_acc += a.next_offs[kv + 1] - a.next_offs[kv];
+                }
+            }
         }
         __syncthreads();  // other lanes' rows were read: the next tile may overwrite them only now
+    }
+    if (a.next_cand && total > 0) {
+        const uint64_t w = wave_sum_u64((uint64_t)cand_acc);
+        if (lane == 0 && w) atomicAdd((unsigned long long*)a.next_cand, (unsigned long long)w);
     }
 }
 
@@ -523,17 +537,58 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
                 const int32_t ns = b.nsteps[p];
                 const int64_t n_out = (sa.mode == EJF_HASH) ? 0 : __hip_atomic_load(sa.n_out, __ATOMIC_RELAXED,
                                                                                        __HIP_MEMORY_SCOPE_AGENT);
+                bool next = false;
                 if (s + 1 < ns && n_out > 0) {
-                    const EjfArgs& nx = b.args[b.first[p] + s + 1];
-                    const int64_t nn = clamp_rows(n_out, nx.in_cap);
-                    c.n_in[s + 1] = nn;
-                    c.t_pub[s + 1] = (int64_t)wall_clock64();
-                    __hip_atomic_store(&c.ntiles[s + 1], (int32_t)((nn + 63) / 64), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                    st_rel_i32(&c.stage, s + 1);
-                } else {
-                    // last step, or nothing left: the remaining steps produce 0 rows
+                    // publish step s + 1: cut its output table (rows = the exact
+                    // candidate bound) and its look-back words from the heap
+                    EjfArgs& nx = b.args[b.first[p] + s + 1];
+                    const int64_t nn = clamp_rows(n_out, sa.out_cap);
+                    int64_t rows = 0;
+                    if (nx.mode == EJF_WRITE)
+                        rows = nx.st.motif >= 0 ? (int64_t)__hip_atomic_load((unsigned long long*)&c.cand[s + 1],
+                                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                                : nn;
+                    if (b.row_limit > 0 && rows > b.row_limit) rows = b.row_limit;
+                    const int c_out = nx.st.c_in + (nx.st.motif >= 0 ? nx.st.n_new : 0);
+                    const int64_t elems = (rows * c_out + 63) & ~(int64_t)63;
+                    const int64_t words = (nn + 63) / 64 + 2;
+                    const int64_t off = (int64_t)atomicAdd(b.heap_top, (unsigned long long)elems);
+                    const int64_t woff = (int64_t)atomicAdd(b.words_top, (unsigned long long)words);
+                    if (off + elems <= b.heap_cap && woff + words <= b.words_cap) {
+                        nx.in = sa.out;
+                        nx.in_stride = sa.out_stride;
+                        nx.in_cap = sa.out_cap;
+                        nx.out = b.heap + off;
+                        nx.out_stride = rows > 0 ? rows : 1;
+                        nx.out_cap = rows;
+                        nx.status = b.words + woff;
+                        c.n_in[s + 1] = nn;
+                        c.t_pub[s + 1] = (int64_t)wall_clock64();
+                        __hip_atomic_store(&c.ntiles[s + 1], (int32_t)((nn + 63) / 64), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                        st_rel_i32(&c.stage, s + 1);
+                        next = true;
+                    } else {
+                        b.heap_fail[p] = 1;
+                    }
+                } else if (s + 1 == ns && sa.mode == EJF_WRITE && n_out > 0 && b.jobs) {
+                    // the final table goes to the sort, with 2 * rows index scratch
+                    SortJob& j = b.jobs[p];
+                    const int64_t nn = clamp_rows(n_out, sa.out_cap);
+                    const int64_t elems = (2 * nn + 63) & ~(int64_t)63;
+                    const int64_t off = (int64_t)atomicAdd(b.heap_top, (unsigned long long)elems);
+                    if (off + elems <= b.heap_cap) {
+                        j.in = sa.out;
+                        j.in_stride = sa.out_stride;
+                        j.in_cap = sa.out_cap;
+                        j.scratch_idx = (uint32_t*)(b.heap + off);
+                    } else {
+                        b.heap_fail[p] = 1;
+                    }
+                }
+                if (!next) {
+                    // last step, nothing left or no room: the remaining steps produce 0 rows
                     for (int q = s + 1; q < ns; q++) *b.args[b.first[p] + q].n_out = 0;
                     c.t_pub[ns] = (int64_t)wall_clock64();
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

@@ -62,6 +62,11 @@ void Workspace::release() {
     dev_free(ctrl_d, stream);
     dev_free(spill, stream);
     dev_free(sort_scratch, stream);
+    dev_free(heap, stream);
+    dev_free(heap_words, stream);
+    heap = nullptr;
+    heap_words = nullptr;
+    heap_elems = heap_words_cap = 0;
     status = nullptr;
     tickets = nullptr;
     ctrl_d = nullptr;
@@ -110,6 +115,35 @@ dm_status Workspace::ensure_spill(int64_t n) {
     DM_TRY(dev_alloc((void**)&spill, sizeof(SegRef) * 2 * (size_t)c, stream));
     spill_cap = c;
     return DM_OK;
+}
+
+dm_status Workspace::ensure_heap(int64_t elems, int64_t min_elems, int64_t min_words) {
+    elems = std::max(elems, min_elems);
+    int64_t words = std::max<int64_t>(elems / 32 + 65536, min_words);
+    if (heap_elems >= elems && heap_words_cap >= words) return DM_OK;
+    elems = std::max(elems, heap_elems);
+    words = std::max(words, heap_words_cap);
+    dev_free(heap, stream);
+    heap = nullptr;
+    heap_elems = 0;
+    dev_free(heap_words, stream);
+    heap_words = nullptr;
+    heap_words_cap = 0;
+    DM_TRY(dev_alloc((void**)&heap, sizeof(int32_t) * (size_t)elems, stream));
+    heap_elems = elems;
+    DM_TRY(dev_alloc((void**)&heap_words, sizeof(uint64_t) * (size_t)words, stream));
+    heap_words_cap = words;
+    DM_HIP(launch_fill_u64(heap_words, 0, words, stream));
+    heap_epoch = 0;
+    return DM_OK;
+}
+
+uint32_t Workspace::next_heap_epoch() {
+    if (++heap_epoch >= kEpochs) {
+        if (launch_fill_u64(heap_words, 0, heap_words_cap, stream) != hipSuccess) return 0;
+        heap_epoch = 1;
+    }
+    return heap_epoch;
 }
 
 dm_status Workspace::ensure_sort_scratch(int64_t elems) {

@@ -61,6 +61,12 @@ struct Workspace {
     std::vector<hipEvent_t> prof;  // event pairs for per-launch timing
     SortJob* job_d = nullptr;      // one sort job (plain path) and its pinned staging
     SortJob* job_h = nullptr;
+    // batched form: device heap of step tables and look-back words (grows on demand)
+    int32_t* heap = nullptr;
+    int64_t heap_elems = 0;
+    uint64_t* heap_words = nullptr;
+    int64_t heap_words_cap = 0;
+    uint32_t heap_epoch = 0;
 
     dm_status init(hipStream_t s);
     void release();
@@ -70,6 +76,10 @@ struct Workspace {
     dm_status ensure_sort_scratch(int64_t elems);
     // next look-back epoch; clears status words and tickets when wrapping
     dm_status next_epoch(uint32_t* e);
+    // heap of at least max(elems, min_elems) int32 and min_words look-back words
+    dm_status ensure_heap(int64_t elems, int64_t min_elems, int64_t min_words);
+    // epoch tagging one batched call's look-back words (clears them on wrap); 0 = error
+    uint32_t next_heap_epoch();
 };
 
 // Motif table keyed on one position (see TableDev).

@@ -401,3 +401,23 @@ def test_batch_cap_root_prefix(ctx):
         assert np.array_equal(r.to_numpy(), want), (p.name, cap)
         r.free()
     dg.free()
+
+
+def test_batch_heap_growth_and_budget(monkeypatch):
+    # a 1 MB first table heap: patterns whose tables do not fit are redone in
+    # a grown heap; a memory budget below the tables sends them to the
+    # root-range chunk schedule instead
+    monkeypatch.setenv("DMOTIF_BATCH_HEAP_MB", "1")
+    c = dm.Context(0)
+    g, pats = W.config2(16)
+    dg = c.datagraph(g.n, g.edges)
+    specs = [(p.n, p.edges) for p in pats]
+    for budget in (0, 2 << 20):
+        say(f"heap case budget={budget}")
+        res = dg.enumerate_batch(specs, mem_budget=budget)
+        for p, r in zip(pats, res):
+            want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+            assert r.total == total and np.array_equal(r.to_numpy(), want), (p.name, budget)
+            r.free()
+    dg.free()
+    c.close()
