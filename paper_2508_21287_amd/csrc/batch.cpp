@@ -95,7 +95,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     const auto t0 = std::chrono::steady_clock::now();
 
     // ---- step-0 tables are reserved here; every later table on the device
-    int total_steps = 0, cmax = 1, max_k = 1;
+    int total_steps = 0, cmax = 1, max_k = 1, max_wp = 1;
     int64_t heap0 = 0, words0 = 0;
     std::vector<int64_t> h_off(nb), w_off(nb), rows0(nb);
     for (int p = 0; p < nb; p++) {
@@ -211,7 +211,8 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         SortJob& j = jobs[p];
         j.n_in = &counts[ns];
         j.k = it.k;
-        j.kp = (it.k % 2 == 0) ? it.k + 1 : it.k;
+        sort_pack_layout(it.k, nv, &j);
+        max_wp = std::max(max_wp, j.wp);
         for (int c = 0; c < it.k; c++) j.perm[c] = (uint8_t)it.plan.col_of[c];
     }
     int32_t* misc = (int32_t*)(A + off_misc);
@@ -341,7 +342,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         }
         DM_HIP(hipMemcpyAsync(A + off_jobs, hjobs, sizeof(SortJob) * nb, hipMemcpyHostToDevice, s));
         DM_HIP(hipEventRecord(ev[2], s));
-        DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, max_rows, max_k, &misc[1]));
+        DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, max_rows, max_wp, &misc[1]));
         DM_HIP(hipEventRecord(ev[3], s));
         int32_t sc[4];
         DM_HIP(hipMemcpyAsync(sc, &misc[1], sizeof sc, hipMemcpyDeviceToHost, s));

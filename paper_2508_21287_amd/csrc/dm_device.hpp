@@ -83,9 +83,25 @@ struct SortJob {
     int64_t out_rows;
     uint32_t* scratch_idx;  // merge tier: 2 * in_cap index scratch
     int32_t k;
-    int32_t kp;             // LDS row stride (k rounded up to odd)
+    // LDS rows are packed: columns 1..k-1 (pattern order) at `bits` bits
+    // each, cpw per 64-bit word, the earlier column in the higher bits, so
+    // comparing the words in order compares the rows lexicographically
+    int32_t wp;             // words per packed row (odd)
+    int32_t bits;
+    int32_t cpw;
+    int32_t pad_;
     uint8_t perm[kMaxCols]; // pattern vertex j -> input column
 };
+
+// Packed-row layout for k columns of vertex ids below n_vertices.
+inline void sort_pack_layout(int k, int32_t n_vertices, SortJob* j) {
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n_vertices) bits++;
+    j->bits = bits;
+    j->cpw = 64 / bits;
+    const int w = k > 1 ? (k - 1 + j->cpw - 1) / j->cpw : 1;
+    j->wp = w | 1;
+}
 
 // A root segment passed from one sort tier to the next: rows
 // [seg0, seg0 + len) of job item / n_vertices.
@@ -114,13 +130,13 @@ struct SortLaunch {
     int32_t pass;         // merge tier: pass number of a merge launch
 };
 
-// Rows of kp int32 that an LDS tile of lds_bytes holds together with the
-// 16-bit index array of the bitonic network (padded to a power of two P):
-// the best r <= P over P with 4 * kp * r + 2 * P <= lds_bytes.
-__host__ __device__ inline int lds_rows_of(int lds_bytes, int kp) {
+// Packed rows of wp 64-bit words that an LDS tile of lds_bytes holds
+// together with the 16-bit index array of the bitonic network (padded to a
+// power of two P): the best r <= P over P with 8 * wp * r + 2 * P <= lds_bytes.
+__host__ __device__ inline int lds_rows_of(int lds_bytes, int wp) {
     int best = 0;
     for (int P = 1; P <= 65536 && 2 * P < lds_bytes; P <<= 1) {
-        int r = (lds_bytes - 2 * P) / (4 * kp);
+        int r = (lds_bytes - 2 * P) / (8 * wp);
         if (r > P) r = P;
         if (r > 65535) r = 65535;  // 0xFFFF is the index sentinel
         if (r > best) best = r;

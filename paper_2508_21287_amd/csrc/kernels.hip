@@ -629,11 +629,11 @@ __device__ __forceinline__ int64_t lower_bound_i32(const int32_t* a, int64_t n, 
 
 constexpr int kSortBlock = 256;
 
-__device__ __forceinline__ bool lds_row_less(const int32_t* rows, int kp, int k, uint32_t x, uint32_t y) {
-    const int32_t* a = rows + (size_t)x * kp;
-    const int32_t* b = rows + (size_t)y * kp;
-    for (int j = 1; j < k; j++) {
-        const int32_t p = a[j], q = b[j];
+__device__ __forceinline__ bool lds_row_less(const uint64_t* rows, int wp, uint32_t x, uint32_t y) {
+    const uint64_t* a = rows + (size_t)x * wp;
+    const uint64_t* b = rows + (size_t)y * wp;
+    for (int w = 0; w < wp; w++) {
+        const uint64_t p = a[w], q = b[w];
         if (p != q) return p < q;
     }
     return false;
@@ -661,10 +661,9 @@ __device__ int64_t wave_lower_bound(const int32_t* a, int64_t n, int32_t v, int 
     return lo;
 }
 
-// Sort the n rows staged in LDS (row stride kp) by columns 1..k-1 with a
-// bitonic network over 16-bit row indices; idx[0, n) receives the order.
-// Called by the whole workgroup.
-__device__ void lds_bitonic(const int32_t* rows, uint16_t* idx, int n, int k, int kp) {
+// Sort the n packed rows staged in LDS with a bitonic network over 16-bit
+// row indices; idx[0, n) receives the order.  Called by the whole workgroup.
+__device__ void lds_bitonic(const uint64_t* rows, uint16_t* idx, int n, int wp) {
     const int tid = threadIdx.x;
     int P = 1;
     while (P < n) P <<= 1;
@@ -680,7 +679,7 @@ __device__ void lds_bitonic(const int32_t* rows, uint16_t* idx, int n, int k, in
                 bool gt;
                 if (ia == kSent16) gt = (ib != kSent16);
                 else if (ib == kSent16) gt = false;
-                else gt = lds_row_less(rows, kp, k, ib, ia);
+                else gt = lds_row_less(rows, wp, ib, ia);
                 if (gt == asc) {
                     idx[lo] = ib;
                     idx[hi] = ia;
@@ -691,15 +690,29 @@ __device__ void lds_bitonic(const int32_t* rows, uint16_t* idx, int n, int k, in
     }
 }
 
-// Stage rows [r0, r0 + n) of a final table into LDS, columns permuted to
-// pattern-vertex order (coalesced column reads).
-__device__ __forceinline__ void lds_stage_rows(const SortJob& job, int64_t r0, int n, int32_t* rows) {
-    const int k = job.k, kp = job.kp;
-    for (int j = 0; j < k; j++) {
-        const int32_t* src = job.in + (int64_t)job.perm[j] * job.in_stride + r0;
-        for (int r = threadIdx.x; r < n; r += kSortBlock) rows[r * kp + j] = src[r];
+// Stage rows [r0, r0 + n) of a final table into LDS as packed rows
+// (columns 1..k-1 in pattern-vertex order; coalesced column reads).
+__device__ __forceinline__ void lds_stage_rows(const SortJob& job, int64_t r0, int n, uint64_t* rows) {
+    const int k = job.k, wp = job.wp, bits = job.bits, cpw = job.cpw;
+    for (int r = threadIdx.x; r < n; r += kSortBlock) {
+        for (int w = 0; w < wp; w++) {
+            uint64_t word = 0;
+            for (int c = 0; c < cpw; c++) {
+                const int j = 1 + w * cpw + c;
+                const uint64_t v = j < k ? (uint64_t)(uint32_t)job.in[(int64_t)job.perm[j] * job.in_stride + r0 + r] : 0;
+                word |= v << ((cpw - 1 - c) * bits);
+            }
+            rows[(size_t)r * wp + w] = word;
+        }
     }
     __syncthreads();
+}
+
+// Column j >= 1 of packed row x.
+__device__ __forceinline__ int32_t lds_unpack(const uint64_t* rows, const SortJob& job, uint32_t x, int j) {
+    const int q = (j - 1) / job.cpw, c = (j - 1) - q * job.cpw;
+    const uint64_t word = rows[(size_t)x * job.wp + q];
+    return (int32_t)((word >> ((job.cpw - 1 - c) * job.bits)) & ((1ull << job.bits) - 1));
 }
 
 __device__ __forceinline__ void push_segment(const SortLaunch& L, int32_t item, int64_t seg0, int64_t len) {
@@ -716,7 +729,7 @@ __device__ __forceinline__ void push_segment(const SortLaunch& L, int32_t item, 
 // are every (job, root vertex) pair and the segment is found by search;
 // segments larger than this tier's LDS tile are passed on.
 __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L) {
-    extern __shared__ int32_t lds[];
+    extern __shared__ uint64_t lds[];
     __shared__ SortJob job;
     __shared__ int64_t s_seg[2];
     const int tid = threadIdx.x;
@@ -747,9 +760,9 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
         }
         __syncthreads();
         const int64_t seg0 = s_seg[0], len = s_seg[1];
-        const int k = job.k, kp = job.kp;
+        const int k = job.k, wp = job.wp;
         const int64_t out_rows = job.out_rows;
-        const int cap_rows = lds_rows_of(L.lds_bytes, kp);
+        const int cap_rows = lds_rows_of(L.lds_bytes, wp);
         __syncthreads();  // every lane has read job and s_seg: the next item may overwrite them
         if (len == 0 || seg0 >= out_rows) continue;
         if (len > cap_rows) {
@@ -757,19 +770,20 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
             continue;
         }
         const int n = (int)len;
-        int32_t* rows = lds;
-        uint16_t* idx = (uint16_t*)(lds + (size_t)cap_rows * kp);
+        uint64_t* rows = lds;
+        uint16_t* idx = (uint16_t*)(lds + (size_t)cap_rows * wp);
+        const int32_t root = job.in[(int64_t)job.perm[0] * job.in_stride + seg0];
         lds_stage_rows(job, seg0, n, rows);
-        lds_bitonic(rows, idx, n, k, kp);
+        lds_bitonic(rows, idx, n, wp);
         for (int r = tid + 1; r < n; r += kSortBlock)
-            if (!lds_row_less(rows, kp, k, idx[r - 1], idx[r])) atomicAdd(L.dup_count, 1);
+            if (!lds_row_less(rows, wp, idx[r - 1], idx[r])) atomicAdd(L.dup_count, 1);
         const int64_t nw = (seg0 + n <= out_rows) ? n : (out_rows - seg0);
         const int64_t total = nw * k;
         int32_t* dst = job.out + seg0 * k;
         for (int64_t e = tid; e < total; e += kSortBlock) {
             const int64_t r = e / k;
             const int j = (int)(e - r * k);
-            dst[e] = rows[(size_t)idx[r] * kp + j];
+            dst[e] = j == 0 ? root : lds_unpack(rows, job, idx[r], j);
         }
         __syncthreads();
     }
@@ -808,24 +822,24 @@ __device__ __forceinline__ int64_t first_unit(int64_t i) {
 }
 
 __global__ __launch_bounds__(kSortBlock) void sort_chunk_kernel(const SortLaunch L) {
-    extern __shared__ int32_t lds[];
+    extern __shared__ uint64_t lds[];
     const int tid = threadIdx.x;
     const int64_t n_list = *L.list_n;
     for (int64_t i = 0; i < n_list; i++) {
         const SegRef ref = L.list[i];
         const SortJob& job = L.jobs[ref.item / L.n_vertices];
-        const int k = job.k, kp = job.kp;
-        const int R = lds_rows_of(L.lds_bytes, kp);
+        const int wp = job.wp;
+        const int R = lds_rows_of(L.lds_bytes, wp);
         const int64_t nch = (ref.len + R - 1) / R;
         if (blockIdx.x == 0 && tid == 0) atomicMax(L.max_chunks, (int32_t)(nch < INT32_MAX ? nch : INT32_MAX));
         uint32_t* run = job.scratch_idx + 2 * ref.seg0;
-        int32_t* rows = lds;
-        uint16_t* idx = (uint16_t*)(lds + (size_t)R * kp);
+        uint64_t* rows = lds;
+        uint16_t* idx = (uint16_t*)(lds + (size_t)R * wp);
         for (int64_t c = first_unit(i); c < nch; c += gridDim.x) {
             const int64_t r0 = c * R;
             const int n = (int)((ref.len - r0 < R) ? (ref.len - r0) : R);
             lds_stage_rows(job, ref.seg0 + r0, n, rows);
-            lds_bitonic(rows, idx, n, k, kp);
+            lds_bitonic(rows, idx, n, wp);
             for (int r = tid; r < n; r += kSortBlock) run[r0 + r] = (uint32_t)(r0 + idx[r]);
             __syncthreads();
         }
@@ -841,7 +855,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_merge_kernel(const SortLaunch
     for (int64_t i = 0; i < n_list; i++) {
         const SegRef ref = L.list[i];
         const SortJob& job = L.jobs[ref.item / L.n_vertices];
-        const int R = lds_rows_of(L.lds_bytes, job.kp);
+        const int R = lds_rows_of(L.lds_bytes, job.wp);
         const int64_t len = ref.len;
         const int64_t nch = (len + R - 1) / R;
         if (((int64_t)1 << p) >= nch) continue;  // this segment needs fewer passes
@@ -876,7 +890,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_gather_kernel(const SortLaunc
         const SegRef ref = L.list[i];
         const SortJob& job = L.jobs[ref.item / L.n_vertices];
         const int k = job.k;
-        const int R = lds_rows_of(L.lds_bytes, job.kp);
+        const int R = lds_rows_of(L.lds_bytes, job.wp);
         const int64_t len = ref.len;
         const int np = ceil_log2_i64((len + R - 1) / R);
         const uint32_t* idx = job.scratch_idx + 2 * ref.seg0 + ((np & 1) ? len : 0);

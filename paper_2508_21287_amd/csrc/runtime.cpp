@@ -182,7 +182,7 @@ static int ejf_grid(int64_t in_cap, double est_in, int block) {
 }
 
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
-                       int32_t v0, int64_t max_in_cap, int32_t max_k, int32_t* counters) {
+                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters) {
     hipStream_t s = ws.stream;
     const int64_t items = (int64_t)n_jobs * nv;
     if (items >= (int64_t)INT32_MAX) return fail(DM_ERR_UNSUPPORTED, "batch too large: patterns x vertices >= 2^31");
@@ -213,8 +213,7 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.list_n = &counters[1];
     L.spill = nullptr;
     L.spill_n = nullptr;
-    const int kp = (max_k % 2 == 0) ? max_k + 1 : max_k;
-    const int64_t r_min = std::max(lds_rows_of(L.lds_bytes, kp), 1);
+    const int64_t r_min = std::max(lds_rows_of(L.lds_bytes, max_wp), 1);
     const int64_t chunks = (std::max<int64_t>(max_in_cap, 1) + r_min - 1) / r_min;
     int passes = 0;
     while (((int64_t)1 << passes) < chunks) passes++;
@@ -362,11 +361,11 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             job.out_rows = out_rows;
             job.scratch_idx = ws.sort_scratch;
             job.k = k;
-            job.kp = (k % 2 == 0) ? k + 1 : k;
+            sort_pack_layout(k, dg->n, &job);
             for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
             DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps], s));
-            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, cap[lb], k, ws.ctrl_d->sort_counters));
+            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, cap[lb], job.wp, ws.ctrl_d->sort_counters));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps + 1], s));
         }
         DM_HIP(hipEventRecord(ws.ev[1], s));

@@ -181,12 +181,12 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
 
 // Canonicalize n_jobs final tables (jobs already in device memory) on
 // ws.stream: two LDS tiers, then chunk sort + merge passes for the rest.
-// max_in_cap / max_k bound every job's rows and width (they size the number
-// of merge passes); counters = 4 zeroed int32 in device memory
+// max_in_cap / max_wp bound every job's rows and packed-row words (they size
+// the number of merge passes); counters = 4 zeroed int32 in device memory
 // (spill_n[2], max_chunks, dup), dup is nonzero afterwards if two rows of a
 // segment were equal.
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
-                       int32_t v0, int64_t max_in_cap, int32_t max_k, int32_t* counters);
+                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters);
 
 dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan);
 RunOptions run_options(const dm_plan_opts* opts, int64_t cap);

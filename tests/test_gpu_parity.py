@@ -364,10 +364,10 @@ def test_partition_schedule(ctx):
 
 @pytest.mark.parametrize("length", [16, 20])
 def test_sort_merge_tier(ctx, length):
-    # ladder graph: root segments of 2.5k (P16) and 16k (P20) rows, beyond the
-    # largest LDS tile for these widths, so they take the chunk + merge tier
-    # (1 and 4 merge passes); plain and batched paths, with and without a cap
-    # that cuts a merged segment
+    # ladder graph: root segments of 2.5k (P16: the large LDS tile) and 16k
+    # rows (P20: beyond the largest LDS tile of 6k packed rows, so chunk sort
+    # + 2 merge passes); plain and batched paths, with and without a cap that
+    # cuts a merged segment
     g = W.grid(2, 20)
     p = W.path(length)
     dg = ctx.datagraph(g.n, g.edges)
@@ -421,3 +421,25 @@ def test_batch_heap_growth_and_budget(monkeypatch):
             r.free()
     dg.free()
     c.close()
+
+
+def test_sort_wide_vertex_ids(ctx):
+    # 2.1M vertices: 22-bit ids, two per packed sort word; a permuted cycle
+    # plus a hub of 40 leaves with scattered ids, so the hub's K1,3 segment
+    # (59k rows) takes the merge tier with high-bit differences
+    n = 2_100_000
+    rng = np.random.default_rng(77)
+    perm = rng.permutation(n).astype(np.int64)
+    cyc = np.stack([perm, np.roll(perm, -1)], axis=1)
+    hub = int(perm[0])
+    leaves = rng.choice(np.setdiff1d(np.arange(n), [hub]), size=40, replace=False)
+    spokes = np.stack([np.full(40, hub), leaves], axis=1)
+    g = W.Graph(n, np.vstack([cyc, spokes]).astype(np.int32), "cycle2.1M+hub")
+    dg = ctx.datagraph(g.n, g.edges)
+    for p in (W.star(3), W.path(4)):
+        check_enum(dg, g, p)
+    res = dg.enumerate_batch([(W.star(3).n, W.star(3).edges)])
+    want, total = oracle.enumerate_embeddings(g.n, g.edges, 4, W.star(3).edges)
+    assert res[0].total == total and np.array_equal(res[0].to_numpy(), want)
+    res[0].free()
+    dg.free()
