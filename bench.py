@@ -17,6 +17,7 @@ the library's stream during the timed steps.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -250,6 +251,11 @@ def main():
 
     for _ in range(args.warmup):
         step(True)
+    # the interpreter's cyclic collector walks every live object (torch holds
+    # about a million) in its full passes, a 40-70 ms pause every few steps;
+    # move the objects alive now out of its reach, as a serving process would
+    gc.collect()
+    gc.freeze()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     emb = 0

@@ -31,7 +31,6 @@ using namespace dm;
 
 namespace {
 
-constexpr int kBatchTile = 64;       // rows per tile in the persistent kernel
 constexpr int kBatchMaxCols = 127;   // widest input table the persistent kernel stages in LDS
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -96,6 +95,10 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
 
     // ---- step-0 tables are reserved here; every later table on the device
     int total_steps = 0, cmax = 1, max_k = 1, max_wp = 1;
+    for (auto& it : items)
+        for (auto& d : it.steps) cmax = std::max(cmax, (int)d.c_in);
+    const int block = batch_block_for(cmax, env_int("DMOTIF_BATCH_BLOCK", 0));
+    const int grid = batch_grid_for(block, cmax, env_int("DMOTIF_BATCH_GRID", 0));
     int64_t heap0 = 0, words0 = 0;
     std::vector<int64_t> h_off(nb), w_off(nb), rows0(nb);
     for (int p = 0; p < nb; p++) {
@@ -110,7 +113,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         h_off[p] = heap0;
         heap0 += (r * (d0.c_in + (d0.motif >= 0 ? d0.n_new : 0)) + 63) & ~(int64_t)63;
         w_off[p] = words0;
-        words0 += (nr + kBatchTile - 1) / kBatchTile + 2;
+        words0 += (nr + block - 1) / block + 2;
         total_steps += (int)it.steps.size();
         for (auto& d : it.steps) cmax = std::max(cmax, (int)d.c_in);
         max_k = std::max(max_k, it.k);
@@ -173,7 +176,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         nsteps[p] = ns;
         const int32_t nr = it.r1 - it.r0;
         ctl[p].n_in[0] = nr;
-        ctl[p].ntiles[0] = (nr + kBatchTile - 1) / kBatchTile;
+        ctl[p].ntiles[0] = (nr + block - 1) / block;
         int64_t* counts = (int64_t*)(A + it.off_counts);
         int32_t* flags = (int32_t*)(A + it.off_flags);
         for (int i = 0; i < ns; i++) {
@@ -249,10 +252,9 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     bd.row_limit = row_limit;
     bd.n_patterns = nb;
     bd.max_backoff = env_int("DMOTIF_BATCH_BACKOFF", 15);
-    const int grid = env_int("DMOTIF_BATCH_GRID", 1024);
     const double t_stage = ms_since(t0);
     DM_HIP(hipEventRecord(ev[0], s));
-    DM_HIP(launch_batch(bd, cmax, grid, s));
+    DM_HIP(launch_batch(bd, block, cmax, grid, s));
     DM_HIP(hipEventRecord(ev[1], s));
 
     // ---- readback 1: counts, flags, hashes, failures, heap use, sort jobs
@@ -333,8 +335,11 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     char* R = nullptr;
     float ms_join = 0, ms_sort = 0;
     (void)hipEventElapsedTime(&ms_join, ev[0], ev[1]);
+    double t_ralloc = 0;
     if (!hash_mode && resb > 0) {
+        const auto ta = std::chrono::steady_clock::now();
         DM_TRY(dev_alloc((void**)&R, resb, s));
+        t_ralloc = ms_since(ta);
         res_block.reset(new DevBlock{R, s});
         for (int p = 0; p < nb; p++) {
             if (items[p].out_rows > 0) hjobs[p].out = (int32_t*)(R + items[p].off_res);
@@ -353,9 +358,10 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     if (timing)
         std::fprintf(stderr,
                      "[batch] %d patterns | heap %.1f MB used of %.1f MB, words %llu | results %.1f MB | stage %.2f ms, "
-                     "join+readback %.2f ms, sort+readback %.2f ms | join %.2f ms, sort %.2f ms | redo %d, grow %d\n",
+                     "join+readback %.2f ms, sort+readback %.2f ms (result alloc %.2f ms) | join %.2f ms, sort %.2f ms | "
+                     "redo %d, grow %d\n",
                      nb, 4e-6 * (double)htops[0], 4e-6 * (double)ws.heap_elems, (unsigned long long)htops[1],
-                     resb / 1e6, t_stage, t_join - t_stage, ms_since(t0) - t_join, ms_join, ms_sort,
+                     resb / 1e6, t_stage, t_join - t_stage, ms_since(t0) - t_join, t_ralloc, ms_join, ms_sort,
                      (int)std::count(redo.begin(), redo.end(), 1), n_grow);
 
     // ---- patterns whose tables did not fit: a larger heap, then one more batch

@@ -190,8 +190,12 @@ hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s);
 hipError_t launch_sort_lds(const SortLaunch& a, int grid, int lds_bytes, hipStream_t s);
 // chunk sort + `passes` merge launches + row write for the segments in a.list
 hipError_t launch_sort_merge_tier(const SortLaunch& a, int passes, hipStream_t s);
-// max_cols: widest input table of any step in the batch (sizes the LDS row tile)
-hipError_t launch_batch(const BatchDev& b, int max_cols, int grid, hipStream_t s);
+// Batched form: workgroup size (= tile rows) for inputs up to max_cols
+// columns (requested 0 = auto), the grid (requested 0 = 1024, at most what
+// stays resident) and the launch; max_cols sizes the LDS row tile.
+int batch_block_for(int max_cols, int requested);
+int batch_grid_for(int block, int max_cols, int requested);
+hipError_t launch_batch(const BatchDev& b, int block, int max_cols, int grid, hipStream_t s);
 int sort_max_lds_bytes();
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

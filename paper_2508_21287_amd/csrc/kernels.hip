@@ -445,71 +445,86 @@ __device__ __forceinline__ void st_rel_i32(int32_t* p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Dynamic LDS: 64 * row_stride(widest input) int32.
-__global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
+// One tile = BLOCK rows; wave 0 finds and claims tiles for the workgroup.
+// Dynamic LDS: BLOCK * row_stride(widest input) int32.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
     extern __shared__ int32_t rows[];
-    __shared__ TileShared<64> sh;
+    __shared__ TileShared<BLOCK> sh;
     __shared__ EjfArgs sa;
-    __shared__ uint64_t s_red[3][1];
-    const int lane = threadIdx.x;
+    __shared__ uint64_t s_red[3][BLOCK / 64];
+    __shared__ int32_t s_claim[4];  // pattern, step, tile, all done
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int N = b.n_patterns;
     int rot = (int)((blockIdx.x * 7919u) % (unsigned)(N > 0 ? N : 1));
     int idle = 0;
-    if (blockIdx.x == 0 && lane < N) {
-        for (int q = lane; q < N; q += 64) b.ctl[q].t_pub[0] = (int64_t)wall_clock64();
+    if (blockIdx.x == 0 && tid < N) {
+        for (int q = tid; q < N; q += BLOCK) b.ctl[q].t_pub[0] = (int64_t)wall_clock64();
     }
     uint64_t hc = 0, hs = 0, hx = 0;
     for (;;) {
-        // ---- find a claimable tile (whole wave scans 64 patterns at a time)
-        int32_t p = -1, s = -1;
-        int64_t tile = -1;
-        bool all_done = false;
-        for (;;) {
-            bool got = false;
-            for (int base = 0; base < N && !got; base += 64) {
-                const int q = (rot + base + lane) % N;
-                bool avail = false;
-                int32_t st = 0, nt = 0;
-                if (base + lane < N) {
-                    // polling uses relaxed (per-location coherent) loads: an
-                    // acquire here would invalidate L1 on every poll
-                    st = ld_rlx_i32(&b.ctl[q].stage);
-                    if (st < b.nsteps[q]) {
-                        // ntiles[s] is written once (0 -> final) before stage s is
-                        // published, so a nonzero value is the final one
-                        nt = ld_rlx_i32(&b.ctl[q].ntiles[st]);
-                        avail = ld_rlx_i32(&b.ctl[q].claim[st]) < nt;
+        // ---- find a claimable tile (wave 0 scans 64 patterns at a time)
+        if (wid == 0) {
+            int32_t p = -1, s = -1, tile = -1;
+            bool all_done = false;
+            for (;;) {
+                bool got = false;
+                for (int base = 0; base < N && !got; base += 64) {
+                    const int q = (rot + base + lane) % N;
+                    bool avail = false;
+                    int32_t st = 0, nt = 0;
+                    if (base + lane < N) {
+                        // polling uses relaxed (per-location coherent) loads: an
+                        // acquire here would invalidate L1 on every poll
+                        st = ld_rlx_i32(&b.ctl[q].stage);
+                        if (st < b.nsteps[q]) {
+                            // ntiles[s] is written once (0 -> final) before stage s is
+                            // published, so a nonzero value is the final one
+                            nt = ld_rlx_i32(&b.ctl[q].ntiles[st]);
+                            avail = ld_rlx_i32(&b.ctl[q].claim[st]) < nt;
+                        }
+                    }
+                    uint64_t m = __ballot(avail);
+                    while (m) {
+                        const int l = __ffsll((long long)m) - 1;
+                        m &= m - 1;
+                        const int32_t qq = __shfl(q, l, 64);
+                        const int32_t ss = __shfl(st, l, 64);
+                        const int32_t ntl = __shfl(nt, l, 64);
+                        int32_t t = 0;
+                        if (lane == 0) t = atomicAdd(&b.ctl[qq].claim[ss], 1);
+                        t = __shfl(t, 0, 64);
+                        if (t < ntl) {
+                            p = qq;
+                            s = ss;
+                            tile = t;
+                            got = true;
+                            break;
+                        }
                     }
                 }
-                uint64_t m = __ballot(avail);
-                while (m) {
-                    const int l = __ffsll((long long)m) - 1;
-                    m &= m - 1;
-                    const int32_t qq = __shfl(q, l, 64);
-                    const int32_t ss = __shfl(st, l, 64);
-                    const int32_t ntl = __shfl(nt, l, 64);
-                    int32_t t = 0;
-                    if (lane == 0) t = atomicAdd(&b.ctl[qq].claim[ss], 1);
-                    t = __shfl(t, 0, 64);
-                    if (t < ntl) {
-                        p = qq;
-                        s = ss;
-                        tile = t;
-                        got = true;
-                        break;
-                    }
+                if (got) break;
+                if (ld_rlx_i32(b.finished) >= N) {
+                    all_done = true;
+                    break;
                 }
+                // idle: back off exponentially so polling does not flood the memory system
+                for (int i = 0; i < idle; i++) __builtin_amdgcn_s_sleep(16);
+                idle = idle < b.max_backoff ? 2 * idle + 1 : idle;
             }
-            if (got) break;
-            if (ld_rlx_i32(b.finished) >= N) {
-                all_done = true;
-                break;
+            idle = 0;
+            if (lane == 0) {
+                s_claim[0] = p;
+                s_claim[1] = s;
+                s_claim[2] = tile;
+                s_claim[3] = all_done ? 1 : 0;
             }
-            // idle: back off exponentially so polling does not flood the memory system
-            for (int i = 0; i < idle; i++) __builtin_amdgcn_s_sleep(16);
-            idle = idle < b.max_backoff ? 2 * idle + 1 : idle;
         }
-        idle = 0;
+        __syncthreads();
+        const int32_t p = s_claim[0], s = s_claim[1];
+        const int64_t tile = s_claim[2];
+        const bool all_done = s_claim[3] != 0;
+        __syncthreads();  // s_claim is rewritten by the next scan
         if (all_done) break;
         rot = (p + 1) % N;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -517,19 +532,20 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
         {
             const int32_t* src = (const int32_t*)&b.args[b.first[p] + s];
             int32_t* dst = (int32_t*)&sa;
-            for (int i = lane; i < (int)(sizeof(EjfArgs) / 4); i += 64) dst[i] = src[i];
+            for (int i = tid; i < (int)(sizeof(EjfArgs) / 4); i += BLOCK) dst[i] = src[i];
         }
         __syncthreads();
         const int64_t n_in = b.ctl[p].n_in[s];
         const int64_t n_tiles = b.ctl[p].ntiles[s];
-        ejf_tile<64>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
+        ejf_tile<BLOCK>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
         if (sa.mode == EJF_HASH) {
-            hash_flush<64>(sa.hash_acc, hc, hs, hx, s_red);
+            hash_flush<BLOCK>(sa.hash_acc, hc, hs, hx, s_red);
             hc = hs = hx = 0;
         }
         // ---- completion: the last tile of a step publishes the next one
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) {
+        __syncthreads();  // every wave's stores are released before the count
+        if (tid == 0) {
             const int32_t d = atomicAdd(&b.ctl[p].done[s], 1);
             if (d == n_tiles - 1) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -543,15 +559,17 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
                     // candidate bound) and its look-back words from the heap
                     EjfArgs& nx = b.args[b.first[p] + s + 1];
                     const int64_t nn = clamp_rows(n_out, sa.out_cap);
-                    int64_t rows = 0;
+                    int64_t rows_out = 0;
                     if (nx.mode == EJF_WRITE)
-                        rows = nx.st.motif >= 0 ? (int64_t)__hip_atomic_load((unsigned long long*)&c.cand[s + 1],
-                                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                                : nn;
-                    if (b.row_limit > 0 && rows > b.row_limit) rows = b.row_limit;
+                        rows_out = nx.st.motif >= 0
+                                       ? (int64_t)__hip_atomic_load((unsigned long long*)&c.cand[s + 1],
+                                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                       : nn;
+                    if (b.row_limit > 0 && rows_out > b.row_limit) rows_out = b.row_limit;
                     const int c_out = nx.st.c_in + (nx.st.motif >= 0 ? nx.st.n_new : 0);
-                    const int64_t elems = (rows * c_out + 63) & ~(int64_t)63;
-                    const int64_t words = (nn + 63) / 64 + 2;
+                    const int64_t elems = (rows_out * c_out + 63) & ~(int64_t)63;
+                    const int64_t ntl = (nn + BLOCK - 1) / BLOCK;
+                    const int64_t words = ntl + 2;
                     const int64_t off = (int64_t)atomicAdd(b.heap_top, (unsigned long long)elems);
                     const int64_t woff = (int64_t)atomicAdd(b.words_top, (unsigned long long)words);
                     if (off + elems <= b.heap_cap && woff + words <= b.words_cap) {
@@ -559,13 +577,12 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
                         nx.in_stride = sa.out_stride;
                         nx.in_cap = sa.out_cap;
                         nx.out = b.heap + off;
-                        nx.out_stride = rows > 0 ? rows : 1;
-                        nx.out_cap = rows;
+                        nx.out_stride = rows_out > 0 ? rows_out : 1;
+                        nx.out_cap = rows_out;
                         nx.status = b.words + woff;
                         c.n_in[s + 1] = nn;
                         c.t_pub[s + 1] = (int64_t)wall_clock64();
-                        __hip_atomic_store(&c.ntiles[s + 1], (int32_t)((nn + 63) / 64), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&c.ntiles[s + 1], (int32_t)ntl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                         st_rel_i32(&c.stage, s + 1);
                         next = true;
@@ -601,9 +618,43 @@ __global__ __launch_bounds__(64) void batch_kernel(const BatchDev b) {
     }
 }
 
-hipError_t launch_batch(const BatchDev& b, int max_cols, int grid, hipStream_t s) {
-    const size_t lds = sizeof(int32_t) * 64 * (size_t)row_stride(max_cols);
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(64), lds, s, b);
+int batch_block_for(int max_cols, int requested) {
+    // the LDS row tile stays within ~32 KB
+    const int cap = max_cols <= 31 ? 256 : (max_cols <= 63 ? 128 : 64);
+    int blk = requested > 0 ? requested : cap;
+    return blk > cap ? cap : blk;
+}
+
+int batch_grid_for(int block, int max_cols, int requested) {
+    const size_t lds = sizeof(int32_t) * (size_t)block * row_stride(max_cols);
+    int per_cu = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (block) {
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<64>, 64, lds); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<128>, 128, lds); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<256>, 256, lds); break;
+    }
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    const int resident = per_cu * cus;
+    // fewer, wider workgroups poll the scheduler less: measured best around
+    // 1.5 workgroups per CU at 256 threads
+    const int want = requested > 0 ? requested : (block >= 256 ? 384 : (block == 128 ? 512 : 1024));
+    return want < resident ? want : resident;
+}
+
+hipError_t launch_batch(const BatchDev& b, int block, int max_cols, int grid, hipStream_t s) {
+    const size_t lds = sizeof(int32_t) * (size_t)block * row_stride(max_cols);
+    switch (block) {
+        case 64: hipLaunchKernelGGL((batch_kernel<64>), dim3(grid), dim3(64), lds, s, b); break;
+        case 128: hipLaunchKernelGGL((batch_kernel<128>), dim3(grid), dim3(128), lds, s, b); break;
+        default: hipLaunchKernelGGL((batch_kernel<256>), dim3(grid), dim3(256), lds, s, b); break;
+    }
     return hipGetLastError();
 }
 
