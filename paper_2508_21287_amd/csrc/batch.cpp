@@ -12,6 +12,8 @@
 // continuous batches on several streams, so work of queries that arrive
 // while others are on the GPU overlaps on the device.
 #include <algorithm>
+#include <functional>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -42,6 +44,81 @@ int env_int(const char* name, int dflt) {
     const int x = std::atoi(v);
     return x > 0 ? x : dflt;
 }
+
+// Host workers for the per-pattern validation and planning of a batch.
+// One parallel_for at a time (a concurrent caller runs its loop itself);
+// every worker checks in for every generation, so the loop body and its
+// count stay valid until the call returns.
+class HostPool {
+  public:
+    static HostPool& get() {
+        static HostPool pool;
+        return pool;
+    }
+    void parallel_for(int n, const std::function<void(int)>& f) {
+        std::unique_lock<std::mutex> busy(call_mu_, std::try_to_lock);
+        if (!busy.owns_lock() || workers_.empty() || n < 8) {
+            for (int i = 0; i < n; i++) f(i);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            fn_ = &f;
+            n_ = n;
+            next_.store(0);
+            checked_in_ = 0;
+            gen_++;
+        }
+        cv_.notify_all();
+        run();
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_done_.wait(lk, [&] { return checked_in_ == (int)workers_.size(); });
+        fn_ = nullptr;
+    }
+    ~HostPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : workers_) t.join();
+    }
+
+  private:
+    HostPool() {
+        const unsigned hw = std::thread::hardware_concurrency();
+        const int w = (int)std::min<unsigned>(hw > 1 ? hw - 1 : 0, 7);
+        for (int i = 0; i < w; i++) workers_.emplace_back([this] { loop(); });
+    }
+    void run() {
+        for (int i; (i = next_.fetch_add(1)) < n_;) (*fn_)(i);
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+            }
+            run();
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                checked_in_++;
+            }
+            cv_done_.notify_all();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex call_mu_, mu_;
+    std::condition_variable cv_, cv_done_;
+    const std::function<void(int)>* fn_ = nullptr;
+    std::atomic<int> next_{0};
+    int n_ = 0, checked_in_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
 
 struct DevBlock {
     void* p = nullptr;
@@ -504,28 +581,45 @@ dm_status enumerate_many(dm_datagraph* dg, Workspace& ws, int32_t n, const dm_gr
     auto cleanup = [&]() {
         for (auto*& r : done) dm_result_free(r), r = nullptr;
     };
-    for (int32_t i = 0; i < n; i++) {
+    // validate and plan every pattern (in parallel on the host workers), then
+    // take the results in order so the first failing pattern is reported
+    struct Prep {
+        dm_status st = DM_OK;
+        std::string err;
+        int32_t k = 0;
+        Plan plan;
+    };
+    std::vector<Prep> prep(n);
+    HostPool::get().parallel_for(n, [&](int i) {
+        Prep& q = prep[i];
         NormPattern p;
         std::string err;
-        dm_status st = normalize_pattern(&gps[i], &p, &err);
-        if (st != DM_OK) {
+        q.st = normalize_pattern(&gps[i], &p, &err);
+        if (q.st != DM_OK) {
+            q.err = "pattern " + std::to_string(i) + ": " + err;
+            return;
+        }
+        q.k = p.k;
+        if (p.k > dg->n) return;
+        q.st = plan_for(dg, p, opts, &q.plan);
+        if (q.st != DM_OK) q.err = dm_last_error();
+    });
+    for (int32_t i = 0; i < n; i++) {
+        Prep& q = prep[i];
+        if (q.st != DM_OK) {
             cleanup();
-            return fail(st, "pattern " + std::to_string(i) + ": " + err);
+            return fail(q.st, q.err);
         }
         const int64_t cap = caps ? caps[i] : -1;
-        if (p.k > dg->n) {
-            done[i] = empty_result(dg->ctx, p.k, mode);
+        if (q.k > dg->n) {
+            done[i] = empty_result(dg->ctx, q.k, mode);
             continue;
         }
         Item it;
         it.idx = i;
-        it.k = p.k;
+        it.k = q.k;
         it.cap = cap;
-        st = plan_for(dg, p, opts, &it.plan);
-        if (st != DM_OK) {
-            cleanup();
-            return st;
-        }
+        it.plan = std::move(q.plan);
         for (auto& ps : it.plan.steps) it.steps.push_back(ps.d);
         if (it.steps.empty()) {
             StepDesc d;

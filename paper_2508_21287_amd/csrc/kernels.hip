@@ -776,6 +776,16 @@ __device__ __forceinline__ void push_segment(const SortLaunch& L, int32_t item, 
     L.spill[q] = r;
 }
 
+// Compare rows x and y of a segment straight from the table's columns.
+__device__ __forceinline__ int glb_row_cmp(const SortJob& a, int64_t seg0, uint32_t x, uint32_t y) {
+    for (int j = 1; j < a.k; j++) {
+        const int32_t* c = a.in + (int64_t)a.perm[j] * a.in_stride + seg0;
+        const int32_t p = c[x], q = c[y];
+        if (p != q) return p < q ? -1 : 1;
+    }
+    return 0;
+}
+
 // LDS tiers: one workgroup per root segment.  Without an input list the items
 // are every (job, root vertex) pair and the segment is found by search;
 // segments larger than this tier's LDS tile are passed on.
@@ -817,6 +827,23 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
         __syncthreads();  // every lane has read job and s_seg: the next item may overwrite them
         if (len == 0 || seg0 >= out_rows) continue;
         if (len > cap_rows) {
+            if (!L.list) {
+                // a large segment the joins left in order needs no sort at all:
+                // check it in the table and write it out directly
+                int uns = 0;
+                for (int64_t r = tid + 1; r < len; r += kSortBlock) uns |= glb_row_cmp(job, seg0, r - 1, r) >= 0;
+                if (!__syncthreads_or(uns)) {
+                    const int64_t nw = (seg0 + len <= out_rows) ? len : (out_rows - seg0);
+                    int32_t* dst = job.out + seg0 * k;
+                    for (int64_t e = tid; e < nw * k; e += kSortBlock) {
+                        const int64_t r = e / k;
+                        const int j = (int)(e - r * k);
+                        dst[e] = job.in[(int64_t)job.perm[j] * job.in_stride + seg0 + r];
+                    }
+                    __syncthreads();
+                    continue;
+                }
+            }
             if (tid == 0) push_segment(L, item, seg0, len);
             continue;
         }
@@ -825,9 +852,17 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
         uint16_t* idx = (uint16_t*)(lds + (size_t)cap_rows * wp);
         const int32_t root = job.in[(int64_t)job.perm[0] * job.in_stride + seg0];
         lds_stage_rows(job, seg0, n, rows);
-        lds_bitonic(rows, idx, n, wp);
-        for (int r = tid + 1; r < n; r += kSortBlock)
-            if (!lds_row_less(rows, wp, idx[r - 1], idx[r])) atomicAdd(L.dup_count, 1);
+        int uns = 0;
+        for (int r = tid + 1; r < n; r += kSortBlock) uns |= !lds_row_less(rows, wp, r - 1, r);
+        if (__syncthreads_or(uns)) {
+            lds_bitonic(rows, idx, n, wp);
+            for (int r = tid + 1; r < n; r += kSortBlock)
+                if (!lds_row_less(rows, wp, idx[r - 1], idx[r])) atomicAdd(L.dup_count, 1);
+        } else {
+            // already in order (strictly, so free of duplicates)
+            for (int r = tid; r < n; r += kSortBlock) idx[r] = (uint16_t)r;
+            __syncthreads();
+        }
         const int64_t nw = (seg0 + n <= out_rows) ? n : (out_rows - seg0);
         const int64_t total = nw * k;
         int32_t* dst = job.out + seg0 * k;
@@ -851,14 +886,6 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
 // spreads each segment's work over all workgroups, starting at a different
 // workgroup per segment.
 
-__device__ __forceinline__ int glb_row_cmp(const SortJob& a, int64_t seg0, uint32_t x, uint32_t y) {
-    for (int j = 1; j < a.k; j++) {
-        const int32_t* c = a.in + (int64_t)a.perm[j] * a.in_stride + seg0;
-        const int32_t p = c[x], q = c[y];
-        if (p != q) return p < q ? -1 : 1;
-    }
-    return 0;
-}
 
 __device__ __forceinline__ int ceil_log2_i64(int64_t x) {
     int r = 0;
@@ -890,7 +917,14 @@ __global__ __launch_bounds__(kSortBlock) void sort_chunk_kernel(const SortLaunch
             const int64_t r0 = c * R;
             const int n = (int)((ref.len - r0 < R) ? (ref.len - r0) : R);
             lds_stage_rows(job, ref.seg0 + r0, n, rows);
-            lds_bitonic(rows, idx, n, wp);
+            int uns = 0;
+            for (int r = tid + 1; r < n; r += kSortBlock) uns |= !lds_row_less(rows, wp, r - 1, r);
+            if (__syncthreads_or(uns)) {
+                lds_bitonic(rows, idx, n, wp);
+            } else {
+                for (int r = tid; r < n; r += kSortBlock) idx[r] = (uint16_t)r;
+                __syncthreads();
+            }
             for (int r = tid; r < n; r += kSortBlock) run[r0 + r] = (uint32_t)(r0 + idx[r]);
             __syncthreads();
         }

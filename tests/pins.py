@@ -131,6 +131,49 @@ def py_row_hash(row):
     return py_mix64(inner)
 
 
+def np_mix64(x):
+    """The SplitMix64 output step over a uint64 array (wrapping arithmetic)."""
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def np_row_hashes(t):
+    """Row hashes of an int32 table [rows x k], as py_row_hash, vectorized."""
+    t = np.asarray(t)
+    inner = np.zeros(len(t), np.uint64)
+    with np.errstate(over="ignore"):
+        for j in range(t.shape[1]):
+            v = t[:, j].astype(np.int64).astype(np.uint64) & np.uint64(0xFFFFFFFF)
+            inner += np_mix64((np.uint64(j) << np.uint64(32)) | v)
+    return np_mix64(inner)
+
+
+def row_hash_sum_xor(t):
+    h = np_row_hashes(t)
+    with np.errstate(over="ignore"):
+        s = int(h.sum(dtype=np.uint64))
+    return s, int(np.bitwise_xor.reduce(h)) if len(h) else 0
+
+
+def assert_strictly_sorted(t):
+    """Rows strictly increasing in lexicographic order (hence distinct)."""
+    t = np.asarray(t)
+    if len(t) < 2:
+        return
+    for j0 in range(0, len(t) - 1, 1 << 22):
+        a = t[j0:j0 + (1 << 22)]
+        b = t[j0 + 1:j0 + 1 + (1 << 22)]
+        a = a[:len(b)]
+        ne = a != b
+        first = ne.argmax(axis=1)
+        assert ne.any(axis=1).all(), "equal adjacent rows"
+        idx = np.arange(len(a))
+        assert (a[idx, first] < b[idx, first]).all(), "rows out of order"
+
+
 def count(lib, g, p):
     return oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, lib=lib)[1]
 
@@ -355,6 +398,9 @@ def pin_hash(lib):
             for h in hs:
                 xr ^= h
             assert (c, s, x) == (len(hs), sum(hs) & M64, xr), (g.name, p.name)
+            if len(want):
+                assert [int(h) for h in np_row_hashes(want)] == hs
+                assert row_hash_sum_xor(want) == (sum(hs) & M64, xr)
 
 
 def pin_root_ranges(lib):
