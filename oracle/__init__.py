@@ -63,6 +63,14 @@ def load(path: str = LIB) -> C.CDLL:
         lib.oracle_count_hash.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
                                           C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
                                           C.POINTER(C.c_uint64)]
+        lib.oracle_enumerate_ex.restype = C.c_int
+        lib.oracle_enumerate_ex.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
+                                            C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.POINTER(i32p),
+                                            C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        lib.oracle_count_hash_ex.restype = C.c_int
+        lib.oracle_count_hash_ex.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
+                                             C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
+                                             C.POINTER(C.c_uint64)]
         lib.oracle_row_hash.restype = C.c_uint64
         lib.oracle_row_hash.argtypes = [i32p, C.c_int32]
         lib.oracle_mix64.restype = C.c_uint64
@@ -101,15 +109,20 @@ def normalize(n: int, edges, lib: C.CDLL | None = None):
 
 
 def enumerate_embeddings(n_d: int, edges_d, n_p: int, edges_p, cap: int = -1,
-                         lib: C.CDLL | None = None, root_range=None):
+                         lib: C.CDLL | None = None, root_range=None, induced: bool = False):
     """Return ``(rows[int32, n x n_p], total)``: the lexicographically first
     ``cap`` embeddings (all when ``cap < 0``) and the full count; with
-    ``root_range=(lo, hi)`` only embeddings with ``f(0)`` in ``[lo, hi)``."""
+    ``root_range=(lo, hi)`` only embeddings with ``f(0)`` in ``[lo, hi)``;
+    ``induced=True`` keeps only induced embeddings."""
     lib = lib or load()
     ed, ep = _edges(edges_d), _edges(edges_p)
     rows = C.POINTER(C.c_int32)()
     n_rows, total = C.c_int64(0), C.c_int64(0)
-    if root_range is None:
+    if induced:
+        lo, hi = root_range if root_range is not None else (0, n_d)
+        rc = lib.oracle_enumerate_ex(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep), cap, int(lo), int(hi), 1,
+                                     C.byref(rows), C.byref(n_rows), C.byref(total))
+    elif root_range is None:
         rc = lib.oracle_enumerate(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep), cap,
                                   C.byref(rows), C.byref(n_rows), C.byref(total))
     else:
@@ -130,13 +143,13 @@ def enumerate_embeddings(n_d: int, edges_d, n_p: int, edges_p, cap: int = -1,
     return out, total.value
 
 
-def count_hash(n_d: int, edges_d, n_p: int, edges_p, lib: C.CDLL | None = None):
+def count_hash(n_d: int, edges_d, n_p: int, edges_p, lib: C.CDLL | None = None, induced: bool = False):
     """Streaming ``(count, hash_sum, hash_xor)`` without storing rows."""
     lib = lib or load()
     ed, ep = _edges(edges_d), _edges(edges_p)
     cnt, hs, hx = C.c_int64(0), C.c_uint64(0), C.c_uint64(0)
-    rc = lib.oracle_count_hash(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep),
-                               C.byref(cnt), C.byref(hs), C.byref(hx))
+    rc = lib.oracle_count_hash_ex(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep), int(bool(induced)),
+                                  C.byref(cnt), C.byref(hs), C.byref(hx))
     if rc != 0:
         raise OracleError(rc)
     return cnt.value, hs.value, hx.value

@@ -19,6 +19,13 @@
  * and both orientations of every edge are present (Sec. III-D: Res(M2) is
  * E_d without self-loops); duplicate edges are merged.
  *
+ * Induced variant (flag `induced`): the definition in Sec. III-A also states
+ * the converse, {u,v} in E_p exactly when {f(u), f(v)} in E_d; with the flag
+ * set, a candidate is also rejected when it is adjacent to the image of an
+ * earlier-mapped pattern vertex that is NOT its pattern neighbour, so the
+ * result is the set of induced embeddings (the subgraph of G_d spanned by
+ * f(V_p) equals f(G_p)).
+ *
  * The result is a table with one row per f, column j holding f(j), rows in
  * ascending lexicographic order, int32 values and an int64 count.  A cap keeps
  * the lexicographically first `cap` rows.
@@ -165,6 +172,9 @@ typedef struct {
     int32_t *parent;  /* pattern vertex -> parent pattern vertex (-1 for root) */
     int32_t *back;    /* flattened earlier-mapped neighbour lists */
     int32_t *back_ptr;
+    int induced;      /* 1: also reject data edges between images of pattern non-neighbours */
+    int32_t *nonback; /* flattened earlier-mapped non-neighbour lists (induced only) */
+    int32_t *nonback_ptr;
     int32_t *f;       /* pattern vertex -> data vertex */
     uint8_t *used;    /* data vertex -> in use */
     int32_t root_lo, root_hi; /* images allowed for pattern vertex 0 */
@@ -233,6 +243,13 @@ static void dfs(search_t *s, int32_t pos) {
         for (int32_t b = s->back_ptr[p]; b < s->back_ptr[p + 1] && ok; b++)
             if (!adjacent(s->gd, c, s->f[s->back[b]])) ok = 0;
 #endif
+        if (s->induced) {
+#if ORACLE_MUTANT == 10
+            if (pos + 1 < s->k) /* wrong: the last vertex skips the non-edge check */
+#endif
+            for (int32_t b = s->nonback_ptr[p]; b < s->nonback_ptr[p + 1] && ok; b++)
+                if (adjacent(s->gd, c, s->f[s->nonback[b]])) ok = 0;
+        }
         if (!ok) continue;
         s->f[p] = c;
         s->used[c] = 1;
@@ -262,7 +279,7 @@ static int cmp_row(const void *a, const void *b) {
  * stream = 1 fills count/hsum/hxor only. */
 static int run(int32_t nd, int64_t md, const int32_t *ed,
                int32_t np, int64_t mp, const int32_t *ep,
-               int stream, int64_t cap, int32_t root_lo, int32_t root_hi,
+               int stream, int64_t cap, int32_t root_lo, int32_t root_hi, int induced,
                int32_t **rows_out, int64_t *rows_n_out, int64_t *total_out,
                uint64_t *hsum_out, uint64_t *hxor_out) {
     if (rows_out) *rows_out = NULL;
@@ -294,8 +311,12 @@ static int run(int32_t nd, int64_t md, const int32_t *ed,
     s.back = (int32_t *)malloc(sizeof(int32_t) * (size_t)(gp.row_ptr[np] + 1));
     s.f = (int32_t *)malloc(sizeof(int32_t) * (size_t)np);
     s.used = (uint8_t *)calloc((size_t)(nd > 0 ? nd : 1), 1);
+    s.induced = induced;
+    s.nonback_ptr = (int32_t *)calloc((size_t)np + 1, sizeof(int32_t));
+    s.nonback = (int32_t *)malloc(sizeof(int32_t) * ((size_t)np * (size_t)np + 1));
     int32_t *pos_of = (int32_t *)malloc(sizeof(int32_t) * (size_t)np);
-    if (!s.order || !s.parent || !s.back_ptr || !s.back || !s.f || !s.used || !pos_of) {
+    if (!s.order || !s.parent || !s.back_ptr || !s.back || !s.f || !s.used || !pos_of || !s.nonback_ptr ||
+        !s.nonback) {
         rc = OR_NOMEM;
         goto done;
     }
@@ -323,6 +344,14 @@ static int run(int32_t nd, int64_t md, const int32_t *ed,
         s.back_ptr[v + 1] = s.back_ptr[v];
         for (int32_t i = gp.row_ptr[v]; i < gp.row_ptr[v + 1]; i++)
             if (pos_of[gp.col[i]] < pos_of[v]) s.back[s.back_ptr[v + 1]++] = gp.col[i];
+    }
+    /* For each pattern vertex: the earlier-placed vertices that are not its
+     * neighbours (every pattern non-edge is checked once, at its later end). */
+    for (int32_t v = 0; v < np; v++) {
+        s.nonback_ptr[v + 1] = s.nonback_ptr[v];
+        for (int32_t w = 0; w < np; w++)
+            if (w != v && pos_of[w] < pos_of[v] && !adjacent(&gp, v, w))
+                s.nonback[s.nonback_ptr[v + 1]++] = w;
     }
 
     if (np <= nd) dfs(&s, 0);
@@ -359,6 +388,8 @@ done:
     free(s.back);
     free(s.f);
     free(s.used);
+    free(s.nonback);
+    free(s.nonback_ptr);
     free(pos_of);
     adj_free(&gd);
     adj_free(&gp);
@@ -387,7 +418,7 @@ int64_t oracle_normalize(int32_t n, int64_t m, const int32_t *edges,
 int oracle_enumerate(int32_t nd, int64_t md, const int32_t *ed,
                      int32_t np, int64_t mp, const int32_t *ep, int64_t cap,
                      int32_t **rows, int64_t *n_rows, int64_t *total) {
-    return run(nd, md, ed, np, mp, ep, 0, cap, 0, nd, rows, n_rows, total, NULL, NULL);
+    return run(nd, md, ed, np, mp, ep, 0, cap, 0, nd, 0, rows, n_rows, total, NULL, NULL);
 }
 
 /* As oracle_enumerate, keeping only embeddings with f(0) in [root_lo, root_hi). */
@@ -395,14 +426,29 @@ int oracle_enumerate_range(int32_t nd, int64_t md, const int32_t *ed,
                            int32_t np, int64_t mp, const int32_t *ep, int64_t cap,
                            int32_t root_lo, int32_t root_hi,
                            int32_t **rows, int64_t *n_rows, int64_t *total) {
-    return run(nd, md, ed, np, mp, ep, 0, cap, root_lo, root_hi, rows, n_rows, total, NULL, NULL);
+    return run(nd, md, ed, np, mp, ep, 0, cap, root_lo, root_hi, 0, rows, n_rows, total, NULL, NULL);
+}
+
+/* As oracle_enumerate_range, with induced = 1 selecting induced embeddings. */
+int oracle_enumerate_ex(int32_t nd, int64_t md, const int32_t *ed,
+                        int32_t np, int64_t mp, const int32_t *ep, int64_t cap,
+                        int32_t root_lo, int32_t root_hi, int32_t induced,
+                        int32_t **rows, int64_t *n_rows, int64_t *total) {
+    return run(nd, md, ed, np, mp, ep, 0, cap, root_lo, root_hi, induced != 0, rows, n_rows, total, NULL, NULL);
 }
 
 /* Streaming count + order-independent multiset hash (see header). */
 int oracle_count_hash(int32_t nd, int64_t md, const int32_t *ed,
                       int32_t np, int64_t mp, const int32_t *ep,
                       int64_t *count, uint64_t *hsum, uint64_t *hxor) {
-    return run(nd, md, ed, np, mp, ep, 1, -1, 0, nd, NULL, NULL, count, hsum, hxor);
+    return run(nd, md, ed, np, mp, ep, 1, -1, 0, nd, 0, NULL, NULL, count, hsum, hxor);
+}
+
+/* As oracle_count_hash, with induced = 1 selecting induced embeddings. */
+int oracle_count_hash_ex(int32_t nd, int64_t md, const int32_t *ed,
+                         int32_t np, int64_t mp, const int32_t *ep, int32_t induced,
+                         int64_t *count, uint64_t *hsum, uint64_t *hxor) {
+    return run(nd, md, ed, np, mp, ep, 1, -1, 0, nd, induced != 0, NULL, NULL, count, hsum, hxor);
 }
 
 /* Hash of one row given in pattern-vertex order (for table-side summaries). */

@@ -418,6 +418,88 @@ def pin_root_ranges(lib):
         assert acc == total and np.array_equal(np.vstack(parts), full), p.name
 
 
+def brute_force_induced_rows(nd, ed, k, ep):
+    """Injective maps under which pattern edges and data edges coincide on
+    every vertex pair (the definition's "if and only if")."""
+    adj = _adjset(nd, ed)
+    pe = {tuple(sorted(e)) for e in np.asarray(ep).reshape(-1, 2).tolist()}
+    pairs = [(a, b) for a in range(k) for b in range(a + 1, k)]
+    rows = [f for f in itertools.permutations(range(nd), k)
+            if all(((a, b) in pe) == ((f[a], f[b]) in adj) for a, b in pairs)]
+    return np.array(rows, dtype=np.int32).reshape(-1, k)
+
+
+def complement_edges(n, edges):
+    e = {tuple(sorted(x)) for x in np.asarray(edges).reshape(-1, 2).tolist() if x[0] != x[1]}
+    return np.array([(a, b) for a in range(n) for b in range(a + 1, n) if (a, b) not in e],
+                    dtype=np.int32).reshape(-1, 2)
+
+
+def is_connected(n, edges):
+    adj = [[] for _ in range(n)]
+    for a, b in np.asarray(edges).reshape(-1, 2).tolist():
+        adj[a].append(b)
+        adj[b].append(a)
+    seen, stack = {0}, [0]
+    while stack:
+        for w in adj[stack.pop()]:
+            if w not in seen:
+                seen.add(w)
+                stack.append(w)
+    return len(seen) == n
+
+
+def induced_rows(lib, g, p, cap=-1):
+    return oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, cap=cap, lib=lib, induced=True)
+
+
+def pin_induced(lib):
+    """Induced embeddings (pattern non-edges map to data non-edges)."""
+    # brute force on small graphs
+    for g in small_data_graphs()[:5]:
+        for p in small_patterns():
+            if p.n > 5:
+                continue
+            want = brute_force_induced_rows(g.n, g.edges, p.n, p.edges)
+            got, total = induced_rows(lib, g, p)
+            assert total == len(want) and np.array_equal(got, want), (g.name, p.name)
+    # a cycle has no chords: induced P_k = non-induced for k < n; P_n closes it: 0
+    for n in (5, 8):
+        cn = W.cycle(n)
+        g = W.Graph(cn.n, cn.edges, f"C{n}")
+        for k in range(1, n + 1):
+            want = n if k == 1 else (2 * n if k < n else 0)
+            assert induced_rows(lib, g, W.path(k))[1] == want, (n, k)
+        assert induced_rows(lib, g, W.cycle(n))[1] == 2 * n
+    # complements: f is induced for (P, G) exactly when it is for (co-P, co-G)
+    for g in small_data_graphs()[:4]:
+        cg = W.Graph(g.n, complement_edges(g.n, g.edges), "co-" + g.name)
+        for p in [W.path(4), W.cycle(5), W.Pattern(5, [[0, 1], [1, 2], [2, 3], [3, 4], [1, 3]], "bull-ish")]:
+            ce = complement_edges(p.n, p.edges)
+            if not is_connected(p.n, ce):
+                continue
+            a, _ = induced_rows(lib, g, p)
+            b, _ = induced_rows(lib, cg, W.Pattern(p.n, ce, "co-" + p.name))
+            assert np.array_equal(a, b), (g.name, p.name)
+    # triangle-free grids: stars and C4 have no pairs to violate
+    g = W.grid(6, 7)
+    d = degrees(g)
+    assert induced_rows(lib, g, W.star(3))[1] == int((d * (d - 1) * (d - 2)).sum())
+    assert induced_rows(lib, g, W.path(3))[1] == int((d * (d - 1)).sum())
+    assert induced_rows(lib, g, W.cycle(4))[1] == 8 * 5 * 6
+    # complete data graph: only complete patterns embed induced
+    kn = W.Graph(6, np.array([(a, b) for a in range(6) for b in range(a + 1, 6)], np.int32), "K6")
+    k4 = W.Pattern(4, np.array([(a, b) for a in range(4) for b in range(a + 1, 4)], np.int32), "K4")
+    assert induced_rows(lib, kn, k4)[1] == 6 * 5 * 4 * 3
+    assert induced_rows(lib, kn, W.path(3))[1] == 0
+    # induced rows are a subset of the non-induced ones
+    g, pats = W.config1()
+    for p in pats:
+        a, _ = induced_rows(lib, g, p)
+        b, _ = rows_of(lib, g, p)
+        assert {tuple(r) for r in a.tolist()} <= {tuple(r) for r in b.tolist()}, p.name
+
+
 ALL_PINS = [pin_brute_force, pin_cycle_paths, pin_self_embedding, pin_heavy_hex_cells,
             pin_degree_sums, pin_grid_closed_forms, pin_nonbacktracking, pin_tree_dp,
-            pin_invariants, pin_cap, pin_edge_cases, pin_hash, pin_root_ranges]
+            pin_invariants, pin_cap, pin_edge_cases, pin_hash, pin_root_ranges, pin_induced]
