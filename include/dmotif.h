@@ -109,7 +109,9 @@ typedef struct {
     int32_t sync_each_step;/* 1: read each step's row count back (exact sizing) */
     int64_t mem_budget;    /* bytes for intermediate tables; 0 = library default */
     int32_t profile;       /* 1: time every join and sort launch with HIP events (see dm_run_stats) */
-    int32_t reserved_;
+    int32_t induced;       /* 1: induced embeddings (the definition of Sec. III-A read as "if and only
+                              if"): additionally every pair of non-adjacent pattern vertices maps to
+                              non-adjacent data vertices.  0 = non-induced (the method's join). */
     int64_t initial_rows;  /* first-attempt capacity of each intermediate table in rows; 0 = from the
                               planner's estimate.  Too small only costs a re-run with exact sizes. */
     int32_t root_begin;    /* keep only embeddings with f(0) in [root_begin, root_end); */

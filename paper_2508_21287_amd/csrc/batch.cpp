@@ -271,6 +271,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             a.ticket = nullptr;
             a.mode = (hash_mode && i == ns - 1) ? EJF_HASH : EJF_WRITE;
             a.hash_acc = (uint64_t*)(A + it.off_hash);
+            a.induced = opts && opts->induced ? 1 : 0;
             for (int c = 0; c < it.k; c++) a.pv[c] = (uint8_t)std::max(it.plan.pv_of[c], 0);
             if (i + 1 < ns && !(hash_mode && i + 1 == ns - 1)) {
                 const StepDesc& nx = it.steps[i + 1];

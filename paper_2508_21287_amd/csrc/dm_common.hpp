@@ -64,6 +64,10 @@ struct StepDesc {
     int8_t eq_pos[kMaxMotif];
     uint8_t edge_a[kMaxEdgeChecks];
     uint8_t edge_b[kMaxEdgeChecks];
+    // Induced variant: bit c of padj[t] is set when the pattern vertices of
+    // column c and of new column c_in + t are adjacent (c < c_in + t); every
+    // other earlier column must hold a data vertex not adjacent to the new one.
+    uint64_t padj[kMaxMotif][2];
 };
 
 struct PlanStep {

@@ -67,7 +67,7 @@ struct EjfArgs {
     int64_t* next_cand;   // nullptr = not needed
     const int32_t* next_offs;
     int32_t next_key_col;
-    int32_t pad_;
+    int32_t induced;      // 1: pattern non-edges must map to data non-edges (StepDesc::padj)
     uint8_t pv[kMaxCols]; // EJF_HASH: pattern vertex of each output column
 };
 

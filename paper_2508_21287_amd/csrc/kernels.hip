@@ -158,6 +158,24 @@ __device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t* my, 
         const int32_t vb = cb < c_in ? my[cb] : pick_new(nv, cb - c_in);
         if (!adjacent(a.g, va, vb)) return false;
     }
+    if (a.induced && st.motif >= 0) {
+        // induced variant: every data neighbour of a new vertex that the row
+        // already holds must sit in a column whose pattern vertex is adjacent
+        for (int t = 0; t < st.n_new; t++) {
+            const int32_t x = pick_new(nv, t);
+            const uint64_t m0 = st.padj[t][0], m1 = st.padj[t][1];
+            for (int32_t i = a.g.row_ptr[x], e = a.g.row_ptr[x + 1]; i < e; i++) {
+                const int32_t w = a.g.col[i];
+                int c = -1;
+                if (bl.maybe(w))
+                    for (int q = 0; q < c_in; q++)
+                        if (my[q] == w) c = q;
+                for (int q = 0; q < t; q++)
+                    if (pick_new(nv, q) == w) c = c_in + q;
+                if (c >= 0 && !(((c < 64 ? m0 : m1) >> (c & 63)) & 1ull)) return false;
+            }
+        }
+    }
     return true;
 }
 

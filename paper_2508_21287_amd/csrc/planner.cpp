@@ -377,6 +377,21 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
         plan.col_of[v] = pl.col_of[v];
         plan.pv_of[pl.col_of[v]] = v;
     }
+    // pattern adjacency of each new column to the earlier ones (induced variant)
+    {
+        std::vector<std::vector<char>> padj(k, std::vector<char>(k, 0));
+        for (auto& e : p.edges) padj[e.first][e.second] = padj[e.second][e.first] = 1;
+        for (auto& ps : plan.steps) {
+            StepDesc& d = ps.d;
+            std::memset(d.padj, 0, sizeof d.padj);
+            const int nn = d.motif >= 0 ? d.n_new : 0;
+            for (int t = 0; t < nn; t++) {
+                const int32_t u = plan.pv_of[d.c_in + t];
+                for (int c = 0; c < d.c_in + t; c++)
+                    if (padj[u][plan.pv_of[c]]) d.padj[t][c >> 6] |= 1ull << (c & 63);
+            }
+        }
+    }
     plan.est_final_rows = rows;
     plan.est_peak_rows_cols = peak;
     *out = std::move(plan);

@@ -312,6 +312,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             const bool last = i == nsteps - 1;
             a.mode = (last && hash_mode) ? EJF_HASH : EJF_WRITE;
             a.hash_acc = ws.ctrl_d->hash;
+            a.induced = opt.induced ? 1 : 0;
             for (int c = 0; c < k; c++) a.pv[c] = (uint8_t)std::max(plan.pv_of[c], 0);
             const double est_in = i == 0 ? (double)(v1 - v0) : est[i - 1];
             const int64_t in_cap = i == 0 ? (int64_t)(v1 - v0) : cap[ib];
@@ -1008,6 +1009,7 @@ RunOptions run_options(const dm_plan_opts* opts, int64_t cap) {
         o.initial_rows = opts->initial_rows;
         o.root_begin = opts->root_begin;
         o.root_end = opts->root_end;
+        o.induced = opts->induced != 0;
     }
     o.cap = cap;
     return o;

@@ -158,6 +158,7 @@ struct RunOptions {
     int64_t initial_rows = 0;  // first-attempt table capacity (0 = estimate)
     int32_t root_begin = 0;    // root range [root_begin, root_end) of the identity table;
     int32_t root_end = 0;      // empty range = every data vertex
+    bool induced = false;      // pattern non-edges must map to data non-edges
 };
 
 // Output of one plan execution on one workspace.

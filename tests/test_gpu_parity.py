@@ -443,3 +443,37 @@ def test_sort_wide_vertex_ids(ctx):
     assert res[0].total == total and np.array_equal(res[0].to_numpy(), want)
     res[0].free()
     dg.free()
+
+
+def test_induced_variant(ctx):
+    # induced embeddings (pattern non-edges map to data non-edges): plain,
+    # count+hash and batched paths against the oracle's induced variant
+    P = W.Pattern
+    pats = [W.path(4), W.cycle(4), W.star(3), P(4, [[0, 1], [1, 2], [2, 0], [2, 3]], "paw"),
+            P(4, [[0, 1], [1, 2], [2, 3], [3, 0], [0, 2]], "diamond"), W.prufer_tree(6, 0), W.path(7)]
+    graphs = [W.heavy_hex(3, 9), W.grid(6, 7), W.random_gnp(24, 0.3, 5), W.random_gnp(40, 0.12, 9)]
+    for g in graphs:
+        dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_ALL & ~dm.MOTIF_C12)
+        for p in pats:
+            say(f"induced {g.name} {p.name}")
+            want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, induced=True)
+            with dg.enumerate(p.n, p.edges, induced=True) as r:
+                assert r.total == total and np.array_equal(r.to_numpy(), want), (g.name, p.name)
+            c, hs, hx = oracle.count_hash(g.n, g.edges, p.n, p.edges, induced=True)
+            with dg.enumerate(p.n, p.edges, induced=True, mode=dm.OUT_COUNT_HASH) as r:
+                assert (r.total,) + r.hash() == (c, hs, hx), (g.name, p.name)
+        res = dg.enumerate_batch([(p.n, p.edges) for p in pats], induced=True)
+        for p, r in zip(pats, res):
+            want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, induced=True)
+            assert r.total == total and np.array_equal(r.to_numpy(), want), (g.name, p.name, "batch")
+            r.free()
+        dg.free()
+    # a larger pattern on the benchmark lattice, batched
+    g, pats2 = W.config2(8)
+    dg = ctx.datagraph(g.n, g.edges)
+    res = dg.enumerate_batch([(p.n, p.edges) for p in pats2], induced=True)
+    for p, r in zip(pats2, res):
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, induced=True)
+        assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
+        r.free()
+    dg.free()
