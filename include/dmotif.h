@@ -167,6 +167,31 @@ dm_status dm_datagraph_copy_csr(const dm_datagraph* dg, int32_t* row_ptr, int32_
 dm_status dm_datagraph_copy_motif(const dm_datagraph* dg, int32_t motif, int32_t key_pos,
                                   int32_t* dst, int64_t max_rows, int64_t* rows, int32_t* width);
 
+/* Persist the database of `dg` -- the output of Algorithm 2: the normalized
+ * CSR and every built motif table with its key index -- to the file `path`,
+ * so that a later process reloads it instead of rebuilding it (Sec. V-A: the
+ * data preparation depends only on the device topology and is cached).
+ * Host file I/O after device-to-host copies on the context stream.
+ * File image (little-endian): "DMOTIFDB", u32 version (1), u32 0, i32 n,
+ * i64 nnz, u32 motif mask, u32 motif bits, f64 table rows[8], f64 mean
+ * degree, i32 row_ptr[n+1], i32 col[nnz]; then for every built motif except
+ * M2 (which is the CSR), for every key position: i64 rows, i32 width, the
+ * columns i32[width][rows] in motif position order, i32 index[n+1]; last a
+ * u64 FNV-1a checksum of all preceding bytes.
+ * Errors: DM_ERR_INVALID_ARG (NULL argument, file cannot be written), DM_ERR_DEVICE. */
+dm_status dm_datagraph_save(const dm_datagraph* dg, const char* path);
+
+/* Reload a database written by dm_datagraph_save onto the device of `ctx`.
+ * The file is validated before anything is created (magic, version,
+ * checksum, vertex ids in range, monotone indexes, table widths); the CSR's
+ * source column and the adjacency bitmap are rebuilt on the device exactly
+ * as dm_datagraph_build does, the motif tables are uploaded as stored.
+ * Several databases (for example one per device topology) may be resident
+ * on one context at once.  build_ms in dm_datagraph_info reports the load
+ * time.  Errors: DM_ERR_INVALID_ARG (NULL argument, unreadable, damaged or
+ * foreign file), DM_ERR_OUT_OF_MEMORY, DM_ERR_DEVICE. */
+dm_status dm_datagraph_load(dm_context* ctx, const char* path, dm_datagraph** out);
+
 /* Planner only (host, no device work): decompose a pattern with the motifs
  * in `motif_mask` (Sec. III-C) and serialize the plan into `buf` as int32:
  *   [k, n_steps, col_of[k] (pattern vertex -> table column), then per step:

@@ -85,7 +85,7 @@ _LIB = None
 # Every symbol include/dmotif.h declares (checked by the CPU test suite).
 EXPORTS = [
     "dm_version", "dm_last_error", "dm_context_create", "dm_context_destroy", "dm_datagraph_build",
-    "dm_datagraph_free", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
+    "dm_datagraph_free", "dm_datagraph_save", "dm_datagraph_load", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
     "dm_estimate", "dm_enumerate", "dm_enumerate_batch", "dm_result_rows", "dm_result_total",
     "dm_result_width", "dm_result_device_data", "dm_result_hash", "dm_result_copy_to_host",
     "dm_result_copy_to_device", "dm_result_stats", "dm_result_free", "dm_server_start", "dm_server_submit",
@@ -119,6 +119,8 @@ def lib() -> C.CDLL:
             "dm_context_destroy": (None, [vp]),
             "dm_datagraph_build": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_uint32, C.POINTER(vp)]),
             "dm_datagraph_free": (None, [vp]),
+            "dm_datagraph_save": (C.c_int, [vp, C.c_char_p]),
+            "dm_datagraph_load": (C.c_int, [vp, C.c_char_p, C.POINTER(vp)]),
             "dm_datagraph_query": (C.c_int, [vp, C.POINTER(DataGraphInfo)]),
             "dm_datagraph_copy_csr": (C.c_int, [vp, i32p, i32p]),
             "dm_datagraph_copy_motif": (C.c_int, [vp, C.c_int32, C.c_int32, i32p, C.c_int64,
@@ -310,13 +312,27 @@ class Result:
 class DataGraph:
     """``dm_datagraph_build``: normalized data graph + motif tables, resident."""
 
-    def __init__(self, ctx: Context, n: int, edges, motif_mask: int = MOTIF_AUTO):
+    def __init__(self, ctx: Context, n: int, edges, motif_mask: int = MOTIF_AUTO, _handle=None):
         self.ctx = ctx
-        g = _Graph(n, edges)
         self._h = C.c_void_p()
-        _check(lib().dm_datagraph_build(ctx.handle, C.byref(g.desc), int(motif_mask) & 0xFFFFFFFF,
-                                        C.byref(self._h)))
+        if _handle is not None:
+            self._h = _handle
+        else:
+            g = _Graph(n, edges)
+            _check(lib().dm_datagraph_build(ctx.handle, C.byref(g.desc), int(motif_mask) & 0xFFFFFFFF,
+                                            C.byref(self._h)))
         ctx._adopt(self)
+
+    @classmethod
+    def load(cls, ctx: Context, path: str) -> "DataGraph":
+        """``dm_datagraph_load``: a database written by :meth:`save`."""
+        h = C.c_void_p()
+        _check(lib().dm_datagraph_load(ctx.handle, os.fsencode(path), C.byref(h)))
+        return cls(ctx, 0, None, _handle=h)
+
+    def save(self, path: str) -> None:
+        """``dm_datagraph_save``: the CSR and every motif table, to a file."""
+        _check(lib().dm_datagraph_save(self._h, os.fsencode(path)))
 
     def info(self) -> dict:
         i = DataGraphInfo()

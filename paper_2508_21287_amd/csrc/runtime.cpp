@@ -863,6 +863,57 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
     return st;
 }
 
+// ---- persisted motif database
+//
+// File image (little-endian): "DMOTIFDB", u32 version, u32 reserved, then
+// i32 n, i64 nnz, u32 mask_built, u32 motif_bits, f64 stats rows[8], f64
+// avg_degree, i32 row_ptr[n+1], i32 col[nnz], then for every built motif
+// other than M2 (which is the CSR) and every key position: i64 rows, i32
+// size, i32 column data [size][rows] (motif position order), i32 offs[n+1];
+// last a u64 FNV-1a checksum of every byte before it.
+
+namespace {
+
+constexpr char kDbMagic[8] = {'D', 'M', 'O', 'T', 'I', 'F', 'D', 'B'};
+constexpr uint32_t kDbVersion = 1;
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; i++) {
+        h ^= b[i];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
+struct DbWriter {
+    FILE* f;
+    uint64_t h = 0xCBF29CE484222325ull;
+    bool ok = true;
+    void put(const void* p, size_t n) {
+        if (!ok || n == 0) return;
+        ok = std::fwrite(p, 1, n, f) == n;
+        h = fnv1a(p, n, h);
+    }
+    template <class T>
+    void val(const T& v) { put(&v, sizeof v); }
+};
+
+struct DbReader {
+    const unsigned char* p;
+    size_t n, at = 0;
+    bool get(void* dst, size_t len) {
+        if (len > n - at) return false;
+        std::memcpy(dst, p + at, len);
+        at += len;
+        return true;
+    }
+    template <class T>
+    bool val(T* v) { return get(v, sizeof *v); }
+};
+
+}  // namespace
+
 extern "C" {
 
 dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t motif_mask, dm_datagraph** out) {
@@ -916,6 +967,179 @@ void dm_datagraph_free(dm_datagraph* dg) {
     if (!dg) return;
     (void)hipSetDevice(dg->ctx->device);
     free_datagraph(dg);
+}
+
+
+dm_status dm_datagraph_save(const dm_datagraph* dg, const char* path) {
+    if (!dg || !path) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    DM_HIP(hipSetDevice(dg->ctx->device));
+    hipStream_t s = dg->ctx->stream;
+    std::vector<int32_t> row_ptr((size_t)dg->n + 1), col((size_t)dg->nnz);
+    DM_HIP(hipMemcpyAsync(row_ptr.data(), dg->row_ptr, sizeof(int32_t) * row_ptr.size(), hipMemcpyDeviceToHost, s));
+    if (dg->nnz > 0) DM_HIP(hipMemcpyAsync(col.data(), dg->col, sizeof(int32_t) * col.size(), hipMemcpyDeviceToHost, s));
+    DM_HIP(hipStreamSynchronize(s));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(DM_ERR_INVALID_ARG, std::string("cannot open for writing: ") + path);
+    DbWriter w{f};
+    w.put(kDbMagic, sizeof kDbMagic);
+    w.val(kDbVersion);
+    w.val((uint32_t)0);
+    w.val(dg->n);
+    w.val(dg->nnz);
+    w.val(dg->mask_built);
+    w.val(dg->motif_bits);
+    for (int m = 0; m < kNumMotifs; m++) w.val(dg->stats.rows[m]);
+    w.val(dg->stats.avg_degree);
+    w.put(row_ptr.data(), sizeof(int32_t) * row_ptr.size());
+    w.put(col.data(), sizeof(int32_t) * col.size());
+    std::vector<int32_t> buf;
+    for (int m = 0; m < kNumMotifs && w.ok; m++) {
+        if (m == MOT_P2 || !((dg->motif_bits >> m) & 1)) continue;
+        for (int j = 0; j < motif_key_positions(m) && w.ok; j++) {
+            const MotifTable& t = dg->tab[m][j];
+            w.val(t.rows);
+            w.val(t.size);
+            buf.resize((size_t)std::max<int64_t>(t.rows, 0));
+            for (int q = 0; q < t.size && w.ok; q++) {
+                if (t.rows > 0) {
+                    DM_HIP(hipMemcpyAsync(buf.data(), t.cols[q], sizeof(int32_t) * buf.size(), hipMemcpyDeviceToHost, s));
+                    DM_HIP(hipStreamSynchronize(s));
+                }
+                w.put(buf.data(), sizeof(int32_t) * buf.size());
+            }
+            buf.resize((size_t)dg->n + 1);
+            DM_HIP(hipMemcpyAsync(buf.data(), t.offs, sizeof(int32_t) * buf.size(), hipMemcpyDeviceToHost, s));
+            DM_HIP(hipStreamSynchronize(s));
+            w.put(buf.data(), sizeof(int32_t) * buf.size());
+        }
+    }
+    const uint64_t sum = w.h;
+    if (w.ok) w.ok = std::fwrite(&sum, 1, sizeof sum, f) == sizeof sum;
+    const bool closed = std::fclose(f) == 0;
+    if (!w.ok || !closed) return fail(DM_ERR_INVALID_ARG, std::string("write failed: ") + path);
+    return DM_OK;
+}
+
+dm_status dm_datagraph_load(dm_context* ctx, const char* path, dm_datagraph** out) {
+    if (!ctx || !path || !out) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    std::vector<unsigned char> img;
+    {
+        FILE* f = std::fopen(path, "rb");
+        if (!f) return fail(DM_ERR_INVALID_ARG, std::string("cannot open: ") + path);
+        unsigned char chunk[1 << 16];
+        size_t got;
+        while ((got = std::fread(chunk, 1, sizeof chunk, f)) > 0) img.insert(img.end(), chunk, chunk + got);
+        std::fclose(f);
+    }
+    auto corrupt = [&](const char* why) { return fail(DM_ERR_INVALID_ARG, std::string("not a valid motif database (") + why + "): " + path); };
+    if (img.size() < sizeof kDbMagic + 8 + sizeof(uint64_t)) return corrupt("too short");
+    uint64_t stored;
+    std::memcpy(&stored, img.data() + img.size() - sizeof stored, sizeof stored);
+    if (fnv1a(img.data(), img.size() - sizeof stored, 0xCBF29CE484222325ull) != stored) return corrupt("checksum");
+    DbReader r{img.data(), img.size() - sizeof stored};
+    char magic[8];
+    uint32_t version = 0, reserved = 0, mask = 0, bits = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    if (!r.get(magic, 8) || std::memcmp(magic, kDbMagic, 8) != 0) return corrupt("magic");
+    if (!r.val(&version) || version != kDbVersion || !r.val(&reserved)) return corrupt("version");
+    MotifStats stats;
+    if (!r.val(&n) || !r.val(&nnz) || !r.val(&mask) || !r.val(&bits) || n < 0 || nnz < 0 || nnz >= INT32_MAX)
+        return corrupt("header");
+    for (int m = 0; m < kNumMotifs; m++)
+        if (!r.val(&stats.rows[m])) return corrupt("header");
+    if (!r.val(&stats.avg_degree)) return corrupt("header");
+    std::vector<int32_t> row_ptr((size_t)n + 1), col((size_t)nnz);
+    if (!r.get(row_ptr.data(), sizeof(int32_t) * row_ptr.size()) || !r.get(col.data(), sizeof(int32_t) * col.size()))
+        return corrupt("graph");
+    if (row_ptr[0] != 0 || row_ptr[n] != nnz) return corrupt("graph");
+    // the edge list of the stored CSR (u < v); ingest rebuilds the device CSR,
+    // its source column and the bitmap exactly as a build does
+    std::vector<int32_t> edges;
+    for (int32_t u = 0; u < n; u++) {
+        if (row_ptr[u + 1] < row_ptr[u]) return corrupt("graph");
+        for (int32_t i = row_ptr[u]; i < row_ptr[u + 1]; i++) {
+            const int32_t v = col[(size_t)i];
+            if (v < 0 || v >= n) return corrupt("graph");
+            if (u < v) {
+                edges.push_back(u);
+                edges.push_back(v);
+            }
+        }
+    }
+    DM_HIP(hipSetDevice(ctx->device));
+    auto* dg = new dm_datagraph();
+    dg->ctx = ctx;
+    dg->n = n;
+    const auto t0 = std::chrono::steady_clock::now();
+    dm_graph_desc gd{n, (int64_t)edges.size() / 2, edges.empty() ? nullptr : edges.data()};
+    dm_status st = ingest(dg, &gd);
+    if (st == DM_OK && dg->nnz != nnz) st = corrupt("graph");
+    hipStream_t s = ctx->stream;
+    for (int m = 0; m < kNumMotifs && st == DM_OK; m++) {
+        if (m == MOT_P2 || !((bits >> m) & 1)) continue;
+        for (int j = 0; j < motif_key_positions(m) && st == DM_OK; j++) {
+            int64_t rows = 0;
+            int32_t size = 0;
+            if (!r.val(&rows) || !r.val(&size) || rows < 0 || size != motif_info(m).size) {
+                st = corrupt("motif table");
+                break;
+            }
+            MotifTable& t = dg->tab[m][j];
+            t.size = size;
+            t.rows = rows;
+            t.stride = std::max<int64_t>(rows, 1);
+            int32_t *data = nullptr, *offs = nullptr;
+            if ((st = dev_alloc((void**)&data, sizeof(int32_t) * (size_t)(t.stride * size), s))) break;
+            t.owned[0] = data;
+            if ((st = dev_alloc((void**)&offs, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+            t.owned[1] = offs;
+            std::vector<int32_t> colbuf((size_t)rows);
+            for (int q = 0; q < size && st == DM_OK; q++) {
+                t.cols[q] = data + (size_t)q * (size_t)t.stride;
+                if (!r.get(colbuf.data(), sizeof(int32_t) * colbuf.size())) {
+                    st = corrupt("motif table");
+                    break;
+                }
+                for (int32_t v : colbuf)
+                    if (v < 0 || v >= n) {
+                        st = corrupt("motif table");
+                        break;
+                    }
+                if (st == DM_OK && rows > 0 &&
+                    hipMemcpy(t.cols[q], colbuf.data(), sizeof(int32_t) * colbuf.size(), hipMemcpyHostToDevice))
+                    st = fail(DM_ERR_DEVICE, "motif table upload failed");
+            }
+            if (st != DM_OK) break;
+            std::vector<int32_t> ob((size_t)n + 1);
+            if (!r.get(ob.data(), sizeof(int32_t) * ob.size()) || ob[0] != 0 || ob[n] != rows) {
+                st = corrupt("motif index");
+                break;
+            }
+            for (int32_t v = 0; v < n; v++)
+                if (ob[v + 1] < ob[v]) {
+                    st = corrupt("motif index");
+                    break;
+                }
+            if (st == DM_OK && hipMemcpy(offs, ob.data(), sizeof(int32_t) * ob.size(), hipMemcpyHostToDevice))
+                st = fail(DM_ERR_DEVICE, "motif index upload failed");
+            t.offs = offs;
+        }
+    }
+    if (st == DM_OK && r.at != r.n) st = corrupt("trailing bytes");
+    if (st == DM_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(DM_ERR_DEVICE, "load sync failed");
+    if (st != DM_OK) {
+        free_datagraph(dg);
+        return st;
+    }
+    dg->motif_bits = bits | 1u;
+    dg->mask_built = mask;
+    for (int m = 0; m < kNumMotifs; m++)
+        if (m != MOT_P2) dg->stats.rows[m] = stats.rows[m];
+    dg->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = dg;
+    return DM_OK;
 }
 
 dm_status dm_datagraph_query(const dm_datagraph* dg, dm_datagraph_info* out) {

@@ -477,3 +477,51 @@ def test_induced_variant(ctx):
         assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
         r.free()
     dg.free()
+
+
+def test_motif_db_save_load(ctx, tmp_path):
+    # a persisted database reloads bit-exact (CSR, every motif table and
+    # index) and answers like the original; several databases stay resident
+    # on one context; damaged or foreign files are refused
+    graphs = [W.heavy_hex(7, 19), W.grid(12, 13), W.random_gnp(30, 0.2, 4)]
+    masks = [dm.MOTIF_AUTO, dm.MOTIF_ALL & ~dm.MOTIF_C12, dm.MOTIF_M3 | dm.MOTIF_C4]
+    loaded = []
+    for i, (g, mask) in enumerate(zip(graphs, masks)):
+        say(f"db case {g.name}")
+        dg = ctx.datagraph(g.n, g.edges, mask)
+        path = str(tmp_path / f"db{i}.dmdb")
+        dg.save(path)
+        lg = dm.DataGraph.load(ctx, path)
+        a, b = dg.info(), lg.info()
+        for key in ("n_vertices", "n_directed_edges", "max_degree", "has_bitmap", "motif_mask", "motif_rows"):
+            assert a[key] == b[key], (g.name, key)
+        for x, y in zip(dg.csr(), lg.csr()):
+            assert np.array_equal(x, y)
+        for m, name in enumerate(dm.MOTIF_NAMES):
+            if a["motif_rows"][name] == 0 or m == 0:
+                continue
+            kp = 1 if m >= 5 else (m + 3) // 2
+            for j in range(kp):
+                assert np.array_equal(dg.motif_table(m, j), lg.motif_table(m, j)), (g.name, name, j)
+        dg.free()
+        loaded.append((g, lg))
+    # all three resident, queried in turn
+    for p in [W.path(5), W.cycle(4), W.prufer_tree(6, 1)]:
+        for g, lg in loaded:
+            want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+            with lg.enumerate(p.n, p.edges) as r:
+                assert r.total == total and np.array_equal(r.to_numpy(), want), (g.name, p.name)
+    for _, lg in loaded:
+        lg.free()
+    # damaged files
+    raw = open(str(tmp_path / "db0.dmdb"), "rb").read()
+    bad = bytearray(raw)
+    bad[len(bad) // 2] ^= 0x40
+    for name, data in [("flip", bytes(bad)), ("short", raw[:100]), ("foreign", b"not a database" * 10)]:
+        path = str(tmp_path / f"bad_{name}.dmdb")
+        open(path, "wb").write(data)
+        with pytest.raises(dm.DMError) as ei:
+            dm.DataGraph.load(ctx, path)
+        assert ei.value.code == -1, name
+    with pytest.raises(dm.DMError):
+        dm.DataGraph.load(ctx, str(tmp_path / "missing.dmdb"))
