@@ -169,7 +169,7 @@ dm_status dm_datagraph_copy_motif(const dm_datagraph* dg, int32_t motif, int32_t
 
 /* Persist the database of `dg` -- the output of Algorithm 2: the normalized
  * CSR and every built motif table with its key index -- to the file `path`,
- * so that a later process reloads it instead of rebuilding it (Sec. V-A: the
+ * so that a later process reloads it instead of rebuilding it (Sec. II-A and V-B: the
  * data preparation depends only on the device topology and is cached).
  * Host file I/O after device-to-host copies on the context stream.
  * File image (little-endian): "DMOTIFDB", u32 version (1), u32 0, i32 n,

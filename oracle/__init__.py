@@ -71,6 +71,12 @@ def load(path: str = LIB) -> C.CDLL:
         lib.oracle_count_hash_ex.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
                                              C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
                                              C.POINTER(C.c_uint64)]
+        u32p, u64p = C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)
+        lib.oracle_enumerate_scored.restype = C.c_int
+        lib.oracle_enumerate_scored.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
+                                                u32p, C.c_int64, i32p, u32p, C.c_int64, C.c_int32,
+                                                C.POINTER(i32p), C.POINTER(u64p), C.POINTER(C.c_int64),
+                                                C.POINTER(C.c_int64)]
         lib.oracle_row_hash.restype = C.c_uint64
         lib.oracle_row_hash.argtypes = [i32p, C.c_int32]
         lib.oracle_mix64.restype = C.c_uint64
@@ -141,6 +147,46 @@ def enumerate_embeddings(n_d: int, edges_d, n_p: int, edges_p, cap: int = -1,
         if rows:
             lib.oracle_free(C.cast(rows, C.c_void_p))
     return out, total.value
+
+
+def enumerate_scored(n_d: int, edges_d, n_p: int, edges_p, vertex_cost=None, cost_edges=None, edge_cost=None,
+                     top_k: int = -1, induced: bool = False, lib: C.CDLL | None = None):
+    """Layout scoring: ``(rows, costs, total)`` with rows ordered by (cost,
+    row) ascending, the first ``top_k`` kept (all when negative).  Costs are
+    non-negative integers per data vertex and per listed data edge."""
+    lib = lib or load()
+    ed, ep = _edges(edges_d), _edges(edges_p)
+    vc = None
+    if vertex_cost is not None:
+        vc = np.ascontiguousarray(np.asarray(vertex_cost, dtype=np.uint32))
+        assert len(vc) == n_d
+    ce = _edges(cost_edges if cost_edges is not None else np.zeros((0, 2), np.int32))
+    ec = np.ascontiguousarray(np.asarray(edge_cost if edge_cost is not None else [], dtype=np.uint32))
+    assert len(ec) == len(ce)
+    rows = C.POINTER(C.c_int32)()
+    costs = C.POINTER(C.c_uint64)()
+    n_rows, total = C.c_int64(0), C.c_int64(0)
+    u32p = C.POINTER(C.c_uint32)
+    rc = lib.oracle_enumerate_scored(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep),
+                                     vc.ctypes.data_as(u32p) if vc is not None else None,
+                                     len(ce), _p(ce), ec.ctypes.data_as(u32p) if len(ec) else None,
+                                     int(top_k), int(bool(induced)),
+                                     C.byref(rows), C.byref(costs), C.byref(n_rows), C.byref(total))
+    if rc != 0:
+        raise OracleError(rc)
+    try:
+        nr = n_rows.value
+        if nr:
+            out = np.ctypeslib.as_array(rows, shape=(nr * n_p,)).reshape(nr, n_p).copy()
+            cst = np.ctypeslib.as_array(costs, shape=(nr,)).copy()
+        else:
+            out, cst = np.zeros((0, n_p), np.int32), np.zeros(0, np.uint64)
+    finally:
+        if rows:
+            lib.oracle_free(C.cast(rows, C.c_void_p))
+        if costs:
+            lib.oracle_free(C.cast(costs, C.c_void_p))
+    return out, cst, total.value
 
 
 def count_hash(n_d: int, edges_d, n_p: int, edges_p, lib: C.CDLL | None = None, induced: bool = False):

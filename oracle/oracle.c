@@ -26,6 +26,14 @@
  * result is the set of induced embeddings (the subgraph of G_d spanned by
  * f(V_p) equals f(G_p)).
  *
+ * Scored variant (layout scoring, Sec. VI-D): with non-negative integer costs
+ * c(x) per data vertex and c({x,y}) per data edge, the cost of f is
+ *     cost(f) = sum_{v in V_p} c(f(v)) + sum_{{u,v} in E_p} c({f(u), f(v)})
+ * (uint64, so the sum is exact and independent of evaluation order: the
+ * paper's per-join product of fidelities, taken in the log domain with
+ * fixed-point terms).  Rows are ordered by (cost ascending, row
+ * lexicographically ascending) and the first top_k kept.
+ *
  * The result is a table with one row per f, column j holding f(j), rows in
  * ascending lexicographic order, int32 values and an int64 count.  A cap keeps
  * the lexicographically first `cap` rows.
@@ -449,6 +457,130 @@ int oracle_count_hash_ex(int32_t nd, int64_t md, const int32_t *ed,
                          int32_t np, int64_t mp, const int32_t *ep, int32_t induced,
                          int64_t *count, uint64_t *hsum, uint64_t *hxor) {
     return run(nd, md, ed, np, mp, ep, 1, -1, 0, nd, induced != 0, NULL, NULL, count, hsum, hxor);
+}
+
+/* Scored enumeration (see the header): all embeddings (induced != 0: the
+ * induced ones), each with its cost, ordered by (cost, row) ascending; the
+ * first top_k rows (top_k < 0: all).  vcost: nd entries (NULL = zeros);
+ * cedges/ecost: mc data edges and their costs (each edge of G_d at most
+ * once; unlisted edges cost 0).  *rows and *costs are malloc'd (free with
+ * oracle_free).  Returns OR_INVALID for a listed pair that is not an edge of
+ * G_d or is listed twice. */
+static const int32_t *g_rows_k_base;
+static const uint64_t *g_costs_base;
+
+static int cmp_scored(const void *a, const void *b) {
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    if (g_costs_base[x] != g_costs_base[y]) return g_costs_base[x] < g_costs_base[y] ? -1 : 1;
+    const int32_t *rx = g_rows_k_base + x * g_sort_k, *ry = g_rows_k_base + y * g_sort_k;
+    for (int32_t j = 0; j < g_sort_k; j++)
+        if (rx[j] != ry[j]) return rx[j] < ry[j] ? -1 : 1;
+    return 0;
+}
+
+int oracle_enumerate_scored(int32_t nd, int64_t md, const int32_t *ed,
+                            int32_t np, int64_t mp, const int32_t *ep,
+                            const uint32_t *vcost, int64_t mc, const int32_t *cedges, const uint32_t *ecost,
+                            int64_t top_k, int32_t induced,
+                            int32_t **rows_out, uint64_t **costs_out, int64_t *n_rows, int64_t *total) {
+    *rows_out = NULL;
+    *costs_out = NULL;
+    *n_rows = 0;
+    *total = 0;
+    if (mc < 0 || (mc > 0 && (!cedges || !ecost))) return OR_INVALID;
+    adj_t gd;
+    int rc = build_adj(nd, md, ed, 1, &gd);
+    if (rc) return rc;
+    /* cost of each directed entry of the adjacency lists */
+    int64_t nnz = gd.row_ptr[nd];
+    uint32_t *ec = (uint32_t *)calloc((size_t)(nnz + 1), sizeof(uint32_t));
+    uint8_t *seen = (uint8_t *)calloc((size_t)(nnz + 1), 1);
+    if (!ec || !seen) { free(ec); free(seen); adj_free(&gd); return OR_NOMEM; }
+    for (int64_t e = 0; e < mc && rc == OR_OK; e++) {
+        for (int o = 0; o < 2 && rc == OR_OK; o++) {
+            int32_t x = cedges[2 * e + o], y = cedges[2 * e + 1 - o];
+            if (x < 0 || y < 0 || x >= nd || y >= nd) { rc = OR_INVALID; break; }
+            int32_t lo = gd.row_ptr[x], hi = gd.row_ptr[x + 1], at = -1;
+            while (lo < hi) {
+                int32_t mid = lo + (hi - lo) / 2;
+                if (gd.col[mid] == y) { at = mid; break; }
+                if (gd.col[mid] < y) lo = mid + 1; else hi = mid;
+            }
+            if (at < 0 || seen[at]) { rc = OR_INVALID; break; }
+            seen[at] = 1;
+            ec[at] = ecost[e];
+        }
+    }
+    int32_t *rows = NULL;
+    int64_t nr = 0, tot = 0;
+    if (rc == OR_OK)
+        rc = run(nd, md, ed, np, mp, ep, 0, -1, 0, nd, induced != 0, &rows, &nr, &tot, NULL, NULL);
+    uint64_t *cost = NULL;
+    int64_t *ord = NULL;
+    if (rc == OR_OK) {
+        cost = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nr + 1));
+        ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nr + 1));
+        if (!cost || !ord) rc = OR_NOMEM;
+    }
+    if (rc == OR_OK) {
+        /* pattern edges once each (u < v) */
+        adj_t gp;
+        rc = build_adj(np, mp, ep, 0, &gp);
+        for (int64_t r = 0; r < nr && rc == OR_OK; r++) {
+            const int32_t *f = rows + r * np;
+            uint64_t c = 0;
+#if ORACLE_MUTANT == 11
+            for (int32_t v = 1; v < np; v++) /* wrong: the root's vertex cost is skipped */
+#else
+            for (int32_t v = 0; v < np; v++)
+#endif
+                c += vcost ? vcost[f[v]] : 0;
+            for (int32_t u = 0; u < np; u++)
+                for (int32_t i = gp.row_ptr[u]; i < gp.row_ptr[u + 1]; i++) {
+                    int32_t v = gp.col[i];
+                    if (v < u) continue;
+                    int32_t x = f[u], y = f[v], lo = gd.row_ptr[x], hi = gd.row_ptr[x + 1];
+                    while (lo < hi) {
+                        int32_t mid = lo + (hi - lo) / 2;
+                        if (gd.col[mid] == y) { c += ec[mid]; break; }
+                        if (gd.col[mid] < y) lo = mid + 1; else hi = mid;
+                    }
+                }
+            cost[r] = c;
+            ord[r] = r;
+        }
+        if (rc == OR_OK) adj_free(&gp);
+    }
+    if (rc == OR_OK) {
+        g_sort_k = np;
+        g_rows_k_base = rows;
+        g_costs_base = cost;
+        if (nr > 1) qsort(ord, (size_t)nr, sizeof(int64_t), cmp_scored);
+        int64_t keep = (top_k >= 0 && top_k < nr) ? top_k : nr;
+        int32_t *ro = (int32_t *)malloc(sizeof(int32_t) * (size_t)(keep * np + 1));
+        uint64_t *co = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(keep + 1));
+        if (!ro || !co) {
+            free(ro);
+            free(co);
+            rc = OR_NOMEM;
+        } else {
+            for (int64_t i = 0; i < keep; i++) {
+                memcpy(ro + i * np, rows + ord[i] * np, sizeof(int32_t) * (size_t)np);
+                co[i] = cost[ord[i]];
+            }
+            *rows_out = ro;
+            *costs_out = co;
+            *n_rows = keep;
+            *total = tot;
+        }
+    }
+    free(rows);
+    free(cost);
+    free(ord);
+    free(ec);
+    free(seen);
+    adj_free(&gd);
+    return rc;
 }
 
 /* Hash of one row given in pattern-vertex order (for table-side summaries). */

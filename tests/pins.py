@@ -500,6 +500,83 @@ def pin_induced(lib):
         assert {tuple(r) for r in a.tolist()} <= {tuple(r) for r in b.tolist()}, p.name
 
 
+def scored(lib, g, p, vc=None, ce=None, ec=None, top_k=-1, induced=False):
+    return oracle.enumerate_scored(g.n, g.edges, p.n, p.edges, vc, ce, ec, top_k=top_k, induced=induced, lib=lib)
+
+
+def random_costs(g, seed, hi=1000):
+    """Seeded integer costs for every vertex and every edge of g (edges as
+    the normalized u < v list)."""
+    rng = np.random.default_rng(seed)
+    adj = W.adjacency_lists(g)
+    ce = np.array([(u, v) for u in range(g.n) for v in adj[u] if u < v], np.int32).reshape(-1, 2)
+    return (rng.integers(0, hi, g.n).astype(np.uint32), ce,
+            rng.integers(0, hi, len(ce)).astype(np.uint32))
+
+
+def py_cost(row, p, vc, emap):
+    c = sum(int(vc[x]) for x in row)
+    for a, b in {tuple(sorted(e)) for e in p.edges.tolist()}:
+        c += emap.get((min(row[a], row[b]), max(row[a], row[b])), 0)
+    return c
+
+
+def pin_scored(lib):
+    """Layout scoring: cost(f) = sum of vertex costs + sum of edge costs over
+    the pattern's vertices and edges; rows by (cost, row); top-k prefix."""
+    # brute force with random costs
+    for gi, g in enumerate(small_data_graphs()[:4] + [W.heavy_hex(2, 5)]):
+        vc, ce, ec = random_costs(g, 100 + gi)
+        emap = {(int(a), int(b)): int(c) for (a, b), c in zip(ce.tolist(), ec)}
+        for p in small_patterns():
+            if p.n > 4:
+                continue
+            base = brute_force_rows(g.n, g.edges, p.n, p.edges)
+            keyed = sorted((py_cost(r, p, vc, emap), tuple(r)) for r in base.tolist())
+            rows, cost, total = scored(lib, g, p, vc, ce, ec)
+            assert total == len(keyed)
+            assert [tuple(r) for r in rows.tolist()] == [k[1] for k in keyed], (g.name, p.name)
+            assert [int(c) for c in cost] == [k[0] for k in keyed], (g.name, p.name)
+            r5, c5, _ = scored(lib, g, p, vc, ce, ec, top_k=5)
+            assert np.array_equal(r5, rows[:5]) and np.array_equal(c5, cost[:5])
+    # zero and uniform costs keep the lexicographic order
+    g, pats = W.config1()
+    for p in pats:
+        lex, _ = rows_of(lib, g, p)
+        rows, cost, _ = scored(lib, g, p)
+        assert np.array_equal(rows, lex) and not cost.any(), p.name
+        vc = np.full(g.n, 7, np.uint32)
+        _, ce, _ = random_costs(g, 1)
+        ec = np.full(len(ce), 3, np.uint32)
+        rows, cost, _ = scored(lib, g, p, vc, ce, ec)
+        ne = len({tuple(sorted(e)) for e in p.edges.tolist()})
+        assert np.array_equal(rows, lex) and (cost == 7 * p.n + 3 * ne).all(), p.name
+    # additivity: costs of (v1 + v2, e1 + e2) are the row-wise sums
+    g = W.heavy_hex(3, 9)
+    v1, ce, e1 = random_costs(g, 5)
+    v2, _, e2 = random_costs(g, 6)
+    for p in [W.path(5), W.cycle(12), W.prufer_tree(6, 3)]:
+        maps = []
+        for vc, ec in [(v1, e1), (v2, e2), (v1 + v2, e1 + e2)]:
+            rows, cost, _ = scored(lib, g, p, vc, ce, ec)
+            maps.append({tuple(r): int(c) for r, c in zip(rows.tolist(), cost)})
+        assert maps[0].keys() == maps[2].keys()
+        assert all(maps[0][r] + maps[1][r] == maps[2][r] for r in maps[2]), p.name
+    # a planted embedding on a zero-cost region wins
+    g, pats = W.config2(4)
+    for p in pats:
+        vc = np.full(g.n, 1000, np.uint32)
+        vc[p.planted] = 0
+        rows, cost, _ = scored(lib, g, p, vc, top_k=1)
+        assert cost[0] == 0 and set(rows[0].tolist()) == set(p.planted.tolist()), p.name
+    # a listed pair that is not a data edge is refused
+    try:
+        scored(lib, W.heavy_hex(3, 9), W.path(3), None, np.array([[0, 31]], np.int32), np.array([1], np.uint32))
+        raise AssertionError("non-edge cost accepted")
+    except oracle.OracleError as e:
+        assert e.code == -1
+
+
 ALL_PINS = [pin_brute_force, pin_cycle_paths, pin_self_embedding, pin_heavy_hex_cells,
             pin_degree_sums, pin_grid_closed_forms, pin_nonbacktracking, pin_tree_dp,
-            pin_invariants, pin_cap, pin_edge_cases, pin_hash, pin_root_ranges, pin_induced]
+            pin_invariants, pin_cap, pin_edge_cases, pin_hash, pin_root_ranges, pin_induced, pin_scored]

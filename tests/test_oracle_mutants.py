@@ -1,7 +1,8 @@
 """Each mutation build of the oracle plants one plausible mistake (no
 injectivity check, tree edges only, a skipped root vertex, columns in search
 order, descending sort, one orientation per edge, a cap off by one, a wrong
-hash index, no sort, an induced check that skips the last vertex).  Every one must be caught by at least one pin, which
+hash index, no sort, an induced check that skips the last vertex, a layout
+cost without the root's vertex cost).  Every one must be caught by at least one pin, which
 shows that the pins constrain the oracle beyond its own code."""
 import os
 
@@ -13,7 +14,7 @@ import pins
 MUTANTS = {1: "no injectivity", 2: "tree edges only", 3: "skips last root vertex",
            4: "columns in search order", 5: "descending order", 6: "one orientation per edge",
            7: "cap off by one", 8: "hash index shifted", 9: "unsorted",
-           10: "induced check skips the last vertex"}
+           10: "induced check skips the last vertex", 11: "cost skips the root vertex"}
 
 
 @pytest.mark.parametrize("mutant", sorted(MUTANTS), ids=lambda m: MUTANTS[m])
