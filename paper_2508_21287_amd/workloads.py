@@ -9,7 +9,7 @@ other. Every random draw uses numpy's PCG64 (`numpy.random.default_rng(seed)`).
 Graphs are returned as ``(n_vertices, edges)`` with ``edges`` an ``int32``
 array of shape ``[m, 2]`` of undirected pairs; vertex ids are ``0..n-1``.
 
-Lattice families follow the paper's benchmark topologies (Sec. V-A: heavy-hex
+Lattice families follow the paper's benchmark topologies (Sec. VI-A: heavy-hex
 lattices with 1990/4485 vertices and square grids of 1600/3600 vertices):
 
 * ``heavy_hex(R, C)``: ``R`` horizontal chains of ``C`` vertices; chain vertex
