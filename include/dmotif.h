@@ -117,6 +117,14 @@ typedef struct {
     int32_t root_begin;    /* keep only embeddings with f(0) in [root_begin, root_end); */
     int32_t root_end;      /* root_end <= root_begin = every data vertex.  Disjoint root ranges
                               partition the result (a shard of one pattern's enumeration). */
+    int32_t score;         /* 1: layout scoring (Sec. VI-D): every row gets the cost
+                              sum_v c(f(v)) + sum_{uv in E_p} c({f(u),f(v)}) from the costs set with
+                              dm_datagraph_set_costs, accumulated join by join; with a cap k >= 0
+                              the result is the k rows with the smallest (cost, row) keys in that
+                              order (k <= 8192, else DM_ERR_UNSUPPORTED); with no cap, every row in
+                              lexicographic order with its cost.  Table mode only (the count+hash
+                              mode ignores it); batches run scored patterns one by one. */
+    int32_t reserved_;
 } dm_plan_opts;
 
 typedef struct dm_context dm_context;
@@ -192,6 +200,17 @@ dm_status dm_datagraph_save(const dm_datagraph* dg, const char* path);
  * foreign file), DM_ERR_OUT_OF_MEMORY, DM_ERR_DEVICE. */
 dm_status dm_datagraph_load(dm_context* ctx, const char* path, dm_datagraph** out);
 
+/* Layout-scoring costs of the data graph (Sec. VI-D: per-qubit and
+ * per-coupling quality): vertex_cost[n_vertices] (NULL = all zero) and, for
+ * n_cost_edges listed data edges (cost_edges: (u,v) pairs, each edge at most
+ * once, either orientation), edge_cost[n_cost_edges]; unlisted edges cost 0.
+ * Costs are non-negative integers (for fidelities: fixed-point -log values),
+ * summed exactly in 64 bits.  Replaces earlier costs; host arrays are copied.
+ * Errors: DM_ERR_INVALID_ARG (NULL, a listed pair that is not an edge of the
+ * graph or is listed twice), DM_ERR_OUT_OF_MEMORY, DM_ERR_DEVICE. */
+dm_status dm_datagraph_set_costs(dm_datagraph* dg, const uint32_t* vertex_cost, int64_t n_cost_edges,
+                                 const int32_t* cost_edges, const uint32_t* edge_cost);
+
 /* Planner only (host, no device work): decompose a pattern with the motifs
  * in `motif_mask` (Sec. III-C) and serialize the plan into `buf` as int32:
  *   [k, n_steps, col_of[k] (pattern vertex -> table column), then per step:
@@ -233,6 +252,11 @@ const int32_t* dm_result_device_data(const dm_result* r);
 /* Count+hash mode summaries: sum (mod 2^64) and XOR over rows of
  * h(f) = mix(sum_j mix((j << 32) | f(j))), mix = SplitMix64's output step. */
 dm_status dm_result_hash(const dm_result* r, uint64_t* hash_sum, uint64_t* hash_xor);
+/* Scored results: the cost of each held row (device pointer owned by the
+ * result, NULL when the run was not scored), and a host copy of the first
+ * max_rows costs (DM_ERR_INVALID_ARG when not scored). */
+const uint64_t* dm_result_device_costs(const dm_result* r);
+dm_status dm_result_copy_costs(const dm_result* r, uint64_t* dst, int64_t max_rows);
 dm_status dm_result_copy_to_host(const dm_result* r, int32_t* dst, int64_t max_rows);
 /* Device-to-device copy of up to max_rows rows into caller memory, ordered on
  * `hip_stream` (NULL = the context stream); synchronizes before returning. */

@@ -57,7 +57,7 @@ class PlanOpts(C.Structure):
     _fields_ = [("motif_mask", C.c_uint32), ("block_threads", C.c_int32), ("output_mode", C.c_int32),
                 ("sync_each_step", C.c_int32), ("mem_budget", C.c_int64), ("profile", C.c_int32),
                 ("induced", C.c_int32), ("initial_rows", C.c_int64), ("root_begin", C.c_int32),
-                ("root_end", C.c_int32)]
+                ("root_end", C.c_int32), ("score", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class DataGraphInfo(C.Structure):
@@ -85,7 +85,8 @@ _LIB = None
 # Every symbol include/dmotif.h declares (checked by the CPU test suite).
 EXPORTS = [
     "dm_version", "dm_last_error", "dm_context_create", "dm_context_destroy", "dm_datagraph_build",
-    "dm_datagraph_free", "dm_datagraph_save", "dm_datagraph_load", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
+    "dm_datagraph_free", "dm_datagraph_save", "dm_datagraph_load", "dm_datagraph_set_costs",
+    "dm_result_device_costs", "dm_result_copy_costs", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
     "dm_estimate", "dm_enumerate", "dm_enumerate_batch", "dm_result_rows", "dm_result_total",
     "dm_result_width", "dm_result_device_data", "dm_result_hash", "dm_result_copy_to_host",
     "dm_result_copy_to_device", "dm_result_stats", "dm_result_free", "dm_server_start", "dm_server_submit",
@@ -120,6 +121,10 @@ def lib() -> C.CDLL:
             "dm_datagraph_build": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_uint32, C.POINTER(vp)]),
             "dm_datagraph_free": (None, [vp]),
             "dm_datagraph_save": (C.c_int, [vp, C.c_char_p]),
+            "dm_datagraph_set_costs": (C.c_int, [vp, C.POINTER(C.c_uint32), C.c_int64, i32p,
+                                                 C.POINTER(C.c_uint32)]),
+            "dm_result_device_costs": (vp, [vp]),
+            "dm_result_copy_costs": (C.c_int, [vp, C.POINTER(C.c_uint64), C.c_int64]),
             "dm_datagraph_load": (C.c_int, [vp, C.c_char_p, C.POINTER(vp)]),
             "dm_datagraph_query": (C.c_int, [vp, C.POINTER(DataGraphInfo)]),
             "dm_datagraph_copy_csr": (C.c_int, [vp, i32p, i32p]),
@@ -168,10 +173,11 @@ class _Graph:
 
 
 def _opts(motif_mask=0, block=0, mode=OUT_TABLE, sync_each_step=False, mem_budget=0,
-          profile=False, initial_rows=0, root_range=None, induced=False) -> PlanOpts:
+          profile=False, initial_rows=0, root_range=None, induced=False, score=False) -> PlanOpts:
     rb, re = (0, 0) if root_range is None else (int(root_range[0]), int(root_range[1]))
     return PlanOpts(int(motif_mask) & 0xFFFFFFFF, int(block), int(mode), int(bool(sync_each_step)),
-                    int(mem_budget), int(bool(profile)), int(bool(induced)), int(initial_rows), rb, re)
+                    int(mem_budget), int(bool(profile)), int(bool(induced)), int(initial_rows), rb, re,
+                    int(bool(score)), 0)
 
 
 def _torch_stream(device: int):
@@ -274,6 +280,13 @@ class Result:
             _check(lib().dm_result_copy_to_device(self._h, C.c_void_p(t.data_ptr()), self.rows, C.c_void_p(s)))
         return t
 
+    def costs(self) -> np.ndarray:
+        """Scored runs: the layout cost of every held row (uint64)."""
+        out = np.zeros(self.rows, np.uint64)
+        if self.rows:
+            _check(lib().dm_result_copy_costs(self._h, out.ctypes.data_as(C.POINTER(C.c_uint64)), self.rows))
+        return out
+
     def hash(self) -> tuple[int, int]:
         hs, hx = C.c_uint64(), C.c_uint64()
         _check(lib().dm_result_hash(self._h, C.byref(hs), C.byref(hx)))
@@ -329,6 +342,24 @@ class DataGraph:
         h = C.c_void_p()
         _check(lib().dm_datagraph_load(ctx.handle, os.fsencode(path), C.byref(h)))
         return cls(ctx, 0, None, _handle=h)
+
+    def set_costs(self, vertex_cost=None, cost_edges=None, edge_cost=None) -> None:
+        """``dm_datagraph_set_costs``: integer layout costs per vertex and per
+        listed edge (unlisted edges cost 0)."""
+        u32p = C.POINTER(C.c_uint32)
+        vc = None
+        if vertex_cost is not None:
+            vc = np.ascontiguousarray(np.asarray(vertex_cost, dtype=np.uint32))
+            if len(vc) != self.info()["n_vertices"]:
+                raise ValueError("vertex_cost needs one entry per data vertex")
+        ce = np.ascontiguousarray(np.asarray(cost_edges if cost_edges is not None else np.zeros((0, 2)),
+                                             dtype=np.int32).reshape(-1, 2))
+        ec = np.ascontiguousarray(np.asarray(edge_cost if edge_cost is not None else [], dtype=np.uint32))
+        if len(ec) != len(ce):
+            raise ValueError("edge_cost needs one entry per cost edge")
+        _check(lib().dm_datagraph_set_costs(self._h, vc.ctypes.data_as(u32p) if vc is not None else None,
+                                            len(ce), ce.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            ec.ctypes.data_as(u32p) if len(ec) else None))
 
     def save(self, path: str) -> None:
         """``dm_datagraph_save``: the CSR and every motif table, to a file."""

@@ -641,8 +641,9 @@ dm_status enumerate_many(dm_datagraph* dg, Workspace& ws, int32_t n, const dm_gr
         }
         int cm = 0;
         for (auto& d : it.steps) cm = std::max(cm, (int)d.c_in);
-        const bool ranged = opts && opts->root_end > opts->root_begin;
-        if (cm > kBatchMaxCols || (int)it.steps.size() > kMaxSteps || ranged) {
+        // a caller's root range and scored runs go through the single-pattern path
+        const bool own_path = (opts && opts->root_end > opts->root_begin) || (opts && opts->score && mode == DM_OUT_TABLE);
+        if (cm > kBatchMaxCols || (int)it.steps.size() > kMaxSteps || own_path) {
             solo.push_back(i);
             continue;
         }

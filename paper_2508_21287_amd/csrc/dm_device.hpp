@@ -68,6 +68,14 @@ struct EjfArgs {
     const int32_t* next_offs;
     int32_t next_key_col;
     int32_t induced;      // 1: pattern non-edges must map to data non-edges (StepDesc::padj)
+    // Layout scoring: when out_cost is set, each output row's cost is its
+    // input row's cost (identity input: the root's vertex cost) plus the
+    // vertex costs of the new values and the edge costs of the pattern edges
+    // the new columns close (StepDesc::padj); ecost is aligned with the CSR.
+    const uint32_t* vcost;
+    const uint32_t* ecost;
+    const uint64_t* in_cost;
+    uint64_t* out_cost;
     uint8_t pv[kMaxCols]; // EJF_HASH: pattern vertex of each output column
 };
 
@@ -82,6 +90,8 @@ struct SortJob {
     int32_t* out;
     int64_t out_rows;
     uint32_t* scratch_idx;  // merge tier: 2 * in_cap index scratch
+    const uint64_t* in_cost;  // per input row cost (nullptr = none); permuted with the rows into out_cost
+    uint64_t* out_cost;
     int32_t k;
     // LDS rows are packed: columns 1..k-1 (pattern order) at `bits` bits
     // each, cpw per 64-bit word, the earlier column in the higher bits, so
@@ -179,6 +189,18 @@ struct BatchDev {
     int32_t max_backoff;   // idle polling backoff cap (units of s_sleep(16))
 };
 
+// Top-k by (cost, table position): radix selection of the k-th key, then a
+// gather and a sort of the k winners.
+struct TopkCtl {
+    unsigned long long prefix;  // selected high bits of the threshold cost / position
+    long long k_rem;            // rank still to place inside the current prefix class (1-based)
+    long long n_less;           // rows with cost below the threshold
+    unsigned long long n_out;   // gathered winners
+    unsigned int hist[256];
+    unsigned long long t_cost;  // threshold cost after the cost passes
+};
+constexpr int kTopkMax = 8192;  // winners sorted in one workgroup's LDS
+
 constexpr int kEpochBits = 14;
 constexpr uint32_t kEpochs = 1u << kEpochBits;
 
@@ -190,6 +212,12 @@ hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s);
 hipError_t launch_sort_lds(const SortLaunch& a, int grid, int lds_bytes, hipStream_t s);
 // chunk sort + `passes` merge launches + row write for the segments in a.list
 hipError_t launch_sort_merge_tier(const SortLaunch& a, int passes, hipStream_t s);
+// The k (<= kTopkMax, <= n) rows of `table` (row-major, n x width) with the
+// smallest (cost, position) keys, in that order: rows to out_rows, costs to
+// out_cost.  ctl and the k-entry scratch (sel_cost, sel_pos) are device memory.
+hipError_t launch_topk(const uint64_t* cost, int64_t n, int64_t k, TopkCtl* ctl, uint64_t* sel_cost,
+                       uint32_t* sel_pos, const int32_t* table, int32_t width, int32_t* out_rows,
+                       uint64_t* out_cost, hipStream_t s);
 // Batched form: workgroup size (= tile rows) for inputs up to max_cols
 // columns (requested 0 = auto), the grid (requested 0 = 1024, at most what
 // stays resident) and the launch; max_cols sizes the LDS row tile.

@@ -2,6 +2,7 @@
 // joins, filters, compaction, sorting and graph ingest.  None of it is a dense
 // contraction, so nothing uses MFMA; the kernels are bound by HBM bandwidth
 // (large tables) or by launch latency (small ones).
+#include <algorithm>
 #include <climits>
 
 #include "dm_device.hpp"
@@ -89,6 +90,18 @@ __device__ __forceinline__ bool adjacent(const GraphDev& g, int32_t u, int32_t v
         if (c < v) lo = mid + 1; else hi = mid;
     }
     return false;
+}
+
+// Cost of data edge {x, y} (an edge of the graph): ecost at y's CSR position in x's list.
+__device__ __forceinline__ uint32_t edge_cost(const GraphDev& g, const uint32_t* ecost, int32_t x, int32_t y) {
+    int32_t lo = g.row_ptr[x], hi = g.row_ptr[x + 1];
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        const int32_t c = g.col[mid];
+        if (c == y) return ecost[mid];
+        if (c < y) lo = mid + 1; else hi = mid;
+    }
+    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -346,6 +359,28 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
                     for (int j = 0; j < 4; j++)
                         if (t0 + j < n_new) dst[(int64_t)(c_in + t0 + j) * os] = w4[j];
                 }
+            }
+            if (a.out_cost) {
+                // layout cost: the parent's plus the new vertices' and the new edges'
+                uint64_t cst = a.in ? a.in_cost[tile * BLOCK + sh.src[o]] : (uint64_t)a.vcost[prow[0]];
+                for (int t = 0; t < n_new; t++) {
+                    const int32_t x = tb[(int64_t)st.new_pos[t] * ts];
+                    cst += a.vcost[x];
+                    uint64_t m0 = st.padj[t][0], m1 = st.padj[t][1];
+                    while (m0 | m1) {
+                        int c;
+                        if (m0) {
+                            c = __ffsll((long long)m0) - 1;
+                            m0 &= m0 - 1;
+                        } else {
+                            c = 64 + __ffsll((long long)m1) - 1;
+                            m1 &= m1 - 1;
+                        }
+                        const int32_t y = c < c_in ? prow[c] : tb[(int64_t)st.new_pos[c - c_in] * ts];
+                        cst += edge_cost(a.g, a.ecost, x, y);
+                    }
+                }
+                a.out_cost[orow] = cst;
             }
             if (a.next_cand) {
                 const int nk = a.next_key_col;
@@ -858,6 +893,8 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
                         const int j = (int)(e - r * k);
                         dst[e] = job.in[(int64_t)job.perm[j] * job.in_stride + seg0 + r];
                     }
+                    if (job.out_cost)
+                        for (int64_t r = tid; r < nw; r += kSortBlock) job.out_cost[seg0 + r] = job.in_cost[seg0 + r];
                     __syncthreads();
                     continue;
                 }
@@ -889,6 +926,8 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
             const int j = (int)(e - r * k);
             dst[e] = j == 0 ? root : lds_unpack(rows, job, idx[r], j);
         }
+        if (job.out_cost)
+            for (int64_t r = tid; r < nw; r += kSortBlock) job.out_cost[seg0 + r] = job.in_cost[seg0 + idx[r]];
         __syncthreads();
     }
 }
@@ -1007,7 +1046,166 @@ __global__ __launch_bounds__(kSortBlock) void sort_gather_kernel(const SortLaunc
             const int j = (int)(e - r * k);
             dst[e] = job.in[(int64_t)job.perm[j] * job.in_stride + ref.seg0 + idx[r]];
         }
+        if (job.out_cost)
+            for (int64_t r = first_unit(i) * kSortBlock + tid; r < nw; r += G * kSortBlock)
+                job.out_cost[ref.seg0 + r] = job.in_cost[ref.seg0 + idx[r]];
     }
+}
+
+// ---------------------------------------------------------------------------
+// top-k by (cost, position) over a sorted table with a cost per row
+// ---------------------------------------------------------------------------
+//
+// Phases 0..7 select the threshold cost T digit by digit (8 bits, most
+// significant first) among the rows still in the candidate class; phases
+// 8..11 select, among the rows costing exactly T, the position P of the
+// (k - #rows below T)-th one.  The winners are then the rows with cost < T
+// and those with cost == T at a position <= P: exactly k rows.
+
+__global__ void topk_init_kernel(TopkCtl* ctl, int64_t k) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        ctl->prefix = 0;
+        ctl->k_rem = k;
+        ctl->n_less = 0;
+        ctl->n_out = 0;
+        ctl->t_cost = 0;
+    }
+    for (int i = t; i < 256; i += blockDim.x) ctl->hist[i] = 0;
+}
+
+__device__ __forceinline__ int topk_shift(int phase) { return phase < 8 ? 56 - 8 * phase : 24 - 8 * (phase - 8); }
+
+__global__ __launch_bounds__(256) void topk_hist_kernel(const uint64_t* cost, int64_t n, TopkCtl* ctl, int phase) {
+    __shared__ unsigned int h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int shift = topk_shift(phase);
+    const unsigned long long prefix = ctl->prefix;
+    const unsigned long long t_cost = ctl->t_cost;
+    const bool by_cost = phase < 8;
+    const unsigned long long above = (by_cost ? (phase == 0 ? 0ull : ~0ull << (shift + 8))
+                                              : (phase == 8 ? 0ull : ~0ull << (shift + 8)));
+    for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
+        const unsigned long long c = cost[i];
+        unsigned long long key;
+        if (by_cost) {
+            key = c;
+        } else {
+            if (c != t_cost) continue;
+            key = (unsigned long long)i;
+        }
+        if (((key ^ prefix) & above) != 0) continue;
+        atomicAdd(&h[(key >> shift) & 255ull], 1u);
+    }
+    __syncthreads();
+    if (h[tid]) atomicAdd(&ctl->hist[tid], h[tid]);
+}
+
+__global__ void topk_pick_kernel(TopkCtl* ctl, int phase) {
+    if (threadIdx.x == 0) {
+        const long long k = ctl->k_rem;
+        long long cum = 0;
+        int d = 0;
+        for (; d < 255; d++) {
+            if (cum + (long long)ctl->hist[d] >= k) break;
+            cum += ctl->hist[d];
+        }
+        ctl->k_rem = k - cum;
+        ctl->prefix |= (unsigned long long)d << topk_shift(phase);
+        if (phase < 8) ctl->n_less += cum;
+        if (phase == 7) {
+            ctl->t_cost = ctl->prefix;
+            ctl->prefix = 0;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) ctl->hist[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void topk_gather_kernel(const uint64_t* cost, int64_t n, TopkCtl* ctl,
+                                                          uint64_t* sel_cost, uint32_t* sel_pos) {
+    const unsigned long long t = ctl->t_cost, p = ctl->prefix;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const unsigned long long c = cost[i];
+        if (c < t || (c == t && (unsigned long long)i <= p)) {
+            const unsigned long long j = atomicAdd(&ctl->n_out, 1ull);
+            sel_cost[j] = c;
+            sel_pos[j] = (uint32_t)i;
+        }
+    }
+}
+
+// One workgroup: bitonic sort of the k winners by (cost, position) in LDS,
+// then their rows and costs are written in that order.
+__global__ __launch_bounds__(1024) void topk_sort_kernel(const uint64_t* sel_cost, const uint32_t* sel_pos, int32_t k,
+                                                         const int32_t* table, int32_t width, int32_t* out_rows,
+                                                         uint64_t* out_cost) {
+    extern __shared__ uint64_t sm[];
+    int P = 1;
+    while (P < k) P <<= 1;
+    uint64_t* kc = sm;
+    uint32_t* kp = (uint32_t*)(sm + P);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P; i += blockDim.x) {
+        kc[i] = i < k ? sel_cost[i] : ~0ull;
+        kp[i] = i < k ? sel_pos[i] : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < (P >> 1); t += blockDim.x) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint64_t ca = kc[lo], cb = kc[hi];
+                const uint32_t pa = kp[lo], pb = kp[hi];
+                const bool gt = ca > cb || (ca == cb && pa > pb);
+                if (gt == asc) {
+                    kc[lo] = cb;
+                    kc[hi] = ca;
+                    kp[lo] = pb;
+                    kp[hi] = pa;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < k; i += blockDim.x) out_cost[i] = kc[i];
+    for (int64_t e = tid; e < (int64_t)k * width; e += blockDim.x) {
+        const int64_t r = e / width;
+        const int j = (int)(e - r * width);
+        out_rows[e] = table[(int64_t)kp[r] * width + j];
+    }
+}
+
+hipError_t launch_topk(const uint64_t* cost, int64_t n, int64_t k, TopkCtl* ctl, uint64_t* sel_cost,
+                       uint32_t* sel_pos, const int32_t* table, int32_t width, int32_t* out_rows,
+                       uint64_t* out_cost, hipStream_t s) {
+    if (k <= 0 || k > kTopkMax || k > n) return hipErrorInvalidValue;
+    static const bool lds_ok = [] {
+        const bool ok = hipFuncSetAttribute((const void*)topk_sort_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            12 * kTopkMax) == hipSuccess;
+        if (!ok) (void)hipGetLastError();
+        return ok;
+    }();
+    if (!lds_ok) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(topk_init_kernel, dim3(1), dim3(256), 0, s, ctl, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>((n + 2047) / 2048, 1), 1024);
+    for (int phase = 0; phase < 12; phase++) {
+        hipLaunchKernelGGL(topk_hist_kernel, dim3(grid), dim3(256), 0, s, cost, n, ctl, phase);
+        hipLaunchKernelGGL(topk_pick_kernel, dim3(1), dim3(256), 0, s, ctl, phase);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(topk_gather_kernel, dim3(grid), dim3(256), 0, s, cost, n, ctl, sel_cost, sel_pos);
+    int P = 1;
+    while (P < k) P <<= 1;
+    hipLaunchKernelGGL(topk_sort_kernel, dim3(1), dim3(1024), (size_t)12 * P, s, sel_cost, sel_pos, (int32_t)k, table,
+                       width, out_rows, out_cost);
+    return hipGetLastError();
 }
 
 int sort_max_lds_bytes() {

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 
 namespace dm {
 
@@ -64,6 +65,7 @@ void Workspace::release() {
     dev_free(sort_scratch, stream);
     dev_free(heap, stream);
     dev_free(heap_words, stream);
+    for (int i = 0; i < 2; i++) dev_free(cbuf[i], stream), cbuf[i] = nullptr, cbuf_rows[i] = 0;
     heap = nullptr;
     heap_words = nullptr;
     heap_elems = heap_words_cap = 0;
@@ -114,6 +116,16 @@ dm_status Workspace::ensure_spill(int64_t n) {
     int64_t c = std::max<int64_t>(n, 1024);
     DM_TRY(dev_alloc((void**)&spill, sizeof(SegRef) * 2 * (size_t)c, stream));
     spill_cap = c;
+    return DM_OK;
+}
+
+dm_status Workspace::ensure_cbuf(int i, int64_t rows) {
+    if (cbuf_rows[i] >= rows) return DM_OK;
+    dev_free(cbuf[i], stream);
+    cbuf[i] = nullptr;
+    cbuf_rows[i] = 0;
+    DM_TRY(dev_alloc((void**)&cbuf[i], sizeof(uint64_t) * (size_t)std::max<int64_t>(rows, 1), stream));
+    cbuf_rows[i] = rows;
     return DM_OK;
 }
 
@@ -269,6 +281,20 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
     RunOutput o;
     int retries = 0;
     int32_t* result = nullptr;
+    uint64_t* result_cost = nullptr;  // scored runs: cost of each sorted row
+    const bool score = opt.score && !hash_mode && opt.sort;
+    if (score && opt.cap > kTopkMax)
+        return fail(DM_ERR_UNSUPPORTED, "scored enumeration keeps at most " + std::to_string(kTopkMax) + " rows");
+    // frees the run's own result buffers on every early return
+    struct ResultGuard {
+        int32_t** r;
+        uint64_t** c;
+        hipStream_t s;
+        ~ResultGuard() {
+            dev_free(*r, s);
+            dev_free(*c, s);
+        }
+    } result_guard{&result, &result_cost, s};
 
     if (opt.profile) {
         while (ws.prof.size() < (size_t)(2 * nsteps + 2)) {
@@ -283,6 +309,8 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         // use the whole buffer unless the caller pinned the first-attempt capacity
         if (opt.initial_rows <= 0 || retries > 0)
             for (int b = 0; b < 2; b++) cap[b] = ws.buf_elems[b] / k;
+        if (score)
+            for (int b = 0; b < 2; b++) DM_TRY(ws.ensure_cbuf(b, cap[b]));
         int64_t maxcap = std::max<int64_t>(std::max(cap[0], cap[1]), (int64_t)dg->n);
         DM_TRY(ws.ensure_status(maxcap / 64 + 2));
         DM_HIP(launch_fill_u64((uint64_t*)ws.ctrl_d, 0, sizeof(Control) / 8, s));
@@ -313,6 +341,12 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             a.mode = (last && hash_mode) ? EJF_HASH : EJF_WRITE;
             a.hash_acc = ws.ctrl_d->hash;
             a.induced = opt.induced ? 1 : 0;
+            if (score) {
+                a.vcost = dg->vcost;
+                a.ecost = dg->ecost;
+                a.in_cost = i == 0 ? nullptr : ws.cbuf[ib];
+                a.out_cost = ws.cbuf[ob];
+            }
             for (int c = 0; c < k; c++) a.pv[c] = (uint8_t)std::max(plan.pv_of[c], 0);
             const double est_in = i == 0 ? (double)(v1 - v0) : est[i - 1];
             const int64_t in_cap = i == 0 ? (int64_t)(v1 - v0) : cap[ib];
@@ -335,6 +369,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
                     ws.buf_elems[ob] = 0;
                     DM_TRY(ws.ensure_buf(ob, nc * k));
                     cap[ob] = ws.buf_elems[ob] / k;
+                    if (score) DM_TRY(ws.ensure_cbuf(ob, cap[ob]));
                     DM_TRY(ws.ensure_status(cap[ob] / 64 + 2));
                     DM_HIP(launch_fill_i32(&ws.ctrl_d->overflow[i], 0, 1, s));
                     retries++;
@@ -347,10 +382,16 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         if (!hash_mode && opt.sort) {
             // canonicalize into a row-major table sized by the last buffer's capacity
             int64_t rows_cap = cap[lb];
-            int64_t out_rows = opt.cap >= 0 ? std::min<int64_t>(opt.cap, rows_cap) : rows_cap;
+            // a scored run sorts every row: its cap selects by cost afterwards
+            int64_t out_rows = (opt.cap >= 0 && !score) ? std::min<int64_t>(opt.cap, rows_cap) : rows_cap;
             dev_free(result, s);
             result = nullptr;
             DM_TRY(dev_alloc((void**)&result, sizeof(int32_t) * (size_t)std::max<int64_t>(out_rows * k, 1), s));
+            if (score) {
+                dev_free(result_cost, s);
+                result_cost = nullptr;
+                DM_TRY(dev_alloc((void**)&result_cost, sizeof(uint64_t) * (size_t)std::max<int64_t>(out_rows, 1), s));
+            }
             DM_TRY(ws.ensure_sort_scratch(2 * rows_cap + 2));
             SortJob& job = *ws.job_h;
             std::memset(&job, 0, sizeof job);
@@ -361,6 +402,10 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             job.out = result;
             job.out_rows = out_rows;
             job.scratch_idx = ws.sort_scratch;
+            if (score) {
+                job.in_cost = ws.cbuf[lb];
+                job.out_cost = result_cost;
+            }
             job.k = k;
             sort_pack_layout(k, dg->n, &job);
             for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
@@ -394,10 +439,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             retries++;
             continue;
         }
-        if (c.sort_counters[3] != 0) {
-            dev_free(result, s);
-            return fail(DM_ERR_INTERNAL, "duplicate rows reached the canonical table");
-        }
+        if (c.sort_counters[3] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached the canonical table");
         float ms = 0;
         (void)hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]);
         o.stats.device_ms = ms;
@@ -441,10 +483,38 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         if (hash_mode) {
             o.hsum = c.hash[1];
             o.hxor = c.hash[2];
+        } else if (score && opt.cap >= 0) {
+            // the cap best rows by (cost, row): radix selection over the sorted table
+            const int64_t kk = std::min<int64_t>(opt.cap, o.rows);
+            if (kk > 0) {
+                int32_t* top = nullptr;
+                uint64_t *top_cost = nullptr, *sel = nullptr;
+                DM_TRY(dev_alloc((void**)&top, sizeof(int32_t) * (size_t)(kk * k), s));
+                std::unique_ptr<int32_t, std::function<void(int32_t*)>> top_guard(
+                    top, [s](int32_t* p) { dev_free(p, s); });
+                DM_TRY(dev_alloc((void**)&top_cost, sizeof(uint64_t) * (size_t)kk, s));
+                std::unique_ptr<uint64_t, std::function<void(uint64_t*)>> cost_guard(
+                    top_cost, [s](uint64_t* p) { dev_free(p, s); });
+                // scratch: control block, then k costs and k positions
+                const size_t scratch = sizeof(TopkCtl) + (sizeof(uint64_t) + sizeof(uint32_t)) * (size_t)kk + 64;
+                DM_TRY(dev_alloc((void**)&sel, scratch, s));
+                std::unique_ptr<uint64_t, std::function<void(uint64_t*)>> sel_guard(
+                    sel, [s](uint64_t* p) { dev_free(p, s); });
+                TopkCtl* ctl = (TopkCtl*)sel;
+                uint64_t* sel_cost = (uint64_t*)((char*)sel + ((sizeof(TopkCtl) + 15) & ~(size_t)15));
+                uint32_t* sel_pos = (uint32_t*)(sel_cost + kk);
+                DM_HIP(launch_topk(result_cost, o.rows, kk, ctl, sel_cost, sel_pos, result, k, top, top_cost, s));
+                DM_HIP(hipStreamSynchronize(s));
+                o.sorted = top_guard.release();
+                o.costs = cost_guard.release();
+            }
+            o.sorted_rows = kk;
         } else if (opt.sort) {
             o.sorted = result;
             o.sorted_rows = opt.cap >= 0 ? std::min<int64_t>(opt.cap, o.rows) : o.rows;
             result = nullptr;
+            o.costs = result_cost;
+            result_cost = nullptr;
         } else {
             o.table = ws.buf[lb];
             o.stride = cap[lb];
@@ -464,6 +534,8 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
                            const RunOptions& opt, RunOutput* out) {
     const bool hash_mode = opt.mode == DM_OUT_COUNT_HASH;
     if (!opt.sort && !hash_mode) return run_plan(ctx, ws, dg, plan, opt, out);
+    // a scored cap ranks every row by cost: no early exit and no splitting
+    if (opt.score && !hash_mode) return run_plan(ctx, ws, dg, plan, opt, out);
     // the caller's root range (default: every data vertex)
     const int32_t r0 = opt.root_end > opt.root_begin ? std::max(opt.root_begin, 0) : 0;
     const int32_t r1 = opt.root_end > opt.root_begin ? std::min(opt.root_end, dg->n) : dg->n;
@@ -677,6 +749,8 @@ static void free_datagraph(dm_datagraph* dg) {
     if (!dg) return;
     hipStream_t s = dg->ctx->stream;
     free_tables(dg);
+    dev_free(dg->vcost, s);
+    dev_free(dg->ecost, s);
     dev_free(dg->row_ptr, s);
     dev_free(dg->src, s);  // src and col share one allocation (src first)
     dev_free(dg->bitmap, s);
@@ -1155,6 +1229,44 @@ dm_status dm_datagraph_query(const dm_datagraph* dg, dm_datagraph_info* out) {
     return DM_OK;
 }
 
+dm_status dm_datagraph_set_costs(dm_datagraph* dg, const uint32_t* vertex_cost, int64_t n_cost_edges,
+                                 const int32_t* cost_edges, const uint32_t* edge_cost) {
+    if (!dg || n_cost_edges < 0 || (n_cost_edges > 0 && (!cost_edges || !edge_cost)))
+        return fail(DM_ERR_INVALID_ARG, "invalid cost arguments");
+    DM_HIP(hipSetDevice(dg->ctx->device));
+    hipStream_t s = dg->ctx->stream;
+    // place each listed edge's cost at both of its CSR positions (host copy of the CSR)
+    std::vector<int32_t> row_ptr((size_t)dg->n + 1), col((size_t)dg->nnz);
+    DM_HIP(hipMemcpyAsync(row_ptr.data(), dg->row_ptr, sizeof(int32_t) * row_ptr.size(), hipMemcpyDeviceToHost, s));
+    if (dg->nnz > 0) DM_HIP(hipMemcpyAsync(col.data(), dg->col, sizeof(int32_t) * col.size(), hipMemcpyDeviceToHost, s));
+    DM_HIP(hipStreamSynchronize(s));
+    std::vector<uint32_t> ec((size_t)std::max<int64_t>(dg->nnz, 1), 0u);
+    std::vector<char> seen((size_t)std::max<int64_t>(dg->nnz, 1), 0);
+    for (int64_t e = 0; e < n_cost_edges; e++) {
+        for (int o = 0; o < 2; o++) {
+            const int32_t x = cost_edges[2 * e + o], y = cost_edges[2 * e + 1 - o];
+            if (x < 0 || y < 0 || x >= dg->n || y >= dg->n)
+                return fail(DM_ERR_INVALID_ARG, "cost edge " + std::to_string(e) + " has a vertex out of range");
+            auto b = col.begin() + row_ptr[x], en = col.begin() + row_ptr[x + 1];
+            auto it = std::lower_bound(b, en, y);
+            if (it == en || *it != y)
+                return fail(DM_ERR_INVALID_ARG, "cost edge " + std::to_string(e) + " is not an edge of the graph");
+            const size_t at = (size_t)(it - col.begin());
+            if (seen[at]) return fail(DM_ERR_INVALID_ARG, "cost edge " + std::to_string(e) + " is listed twice");
+            seen[at] = 1;
+            ec[at] = edge_cost[e];
+        }
+    }
+    DM_TRY(ensure_costs(dg));
+    if (vertex_cost)
+        DM_HIP(hipMemcpyAsync(dg->vcost, vertex_cost, sizeof(uint32_t) * (size_t)dg->n, hipMemcpyHostToDevice, s));
+    else
+        DM_HIP(launch_fill_i32((int32_t*)dg->vcost, 0, std::max(dg->n, 1), s));
+    DM_HIP(hipMemcpyAsync(dg->ecost, ec.data(), sizeof(uint32_t) * ec.size(), hipMemcpyHostToDevice, s));
+    DM_HIP(hipStreamSynchronize(s));
+    return DM_OK;
+}
+
 dm_status dm_datagraph_copy_csr(const dm_datagraph* dg, int32_t* row_ptr, int32_t* col) {
     if (!dg || !row_ptr || (!col && dg->nnz > 0)) return fail(DM_ERR_INVALID_ARG, "NULL argument");
     DM_HIP(hipSetDevice(dg->ctx->device));
@@ -1234,6 +1346,7 @@ RunOptions run_options(const dm_plan_opts* opts, int64_t cap) {
         o.root_begin = opts->root_begin;
         o.root_end = opts->root_end;
         o.induced = opts->induced != 0;
+        o.score = opts->score != 0;
     }
     o.cap = cap;
     return o;
@@ -1248,6 +1361,22 @@ dm_result* empty_result(dm_context* ctx, int32_t k, int32_t mode) {
     r->stream = ctx->stream;
     r->mode = mode;
     return r;
+}
+
+// Layout costs default to zero: allocate zero arrays the first time a scored
+// run needs them.
+dm_status ensure_costs(dm_datagraph* dg) {
+    if (dg->vcost && dg->ecost) return DM_OK;
+    hipStream_t s = dg->ctx->stream;
+    if (!dg->vcost) {
+        DM_TRY(dev_alloc((void**)&dg->vcost, sizeof(uint32_t) * (size_t)std::max(dg->n, 1), s));
+        DM_HIP(launch_fill_i32((int32_t*)dg->vcost, 0, std::max(dg->n, 1), s));
+    }
+    if (!dg->ecost) {
+        DM_TRY(dev_alloc((void**)&dg->ecost, sizeof(uint32_t) * (size_t)std::max<int64_t>(dg->nnz, 1), s));
+        DM_HIP(launch_fill_i32((int32_t*)dg->ecost, 0, std::max<int64_t>(dg->nnz, 1), s));
+    }
+    return DM_OK;
 }
 
 dm_status enumerate_one(dm_datagraph* dg, Workspace& ws, const dm_graph_desc* gp, int64_t cap,
@@ -1272,6 +1401,7 @@ dm_status enumerate_one(dm_datagraph* dg, Workspace& ws, const dm_graph_desc* gp
     DM_TRY(plan_for(dg, p, opts, &plan));
     auto t1 = std::chrono::steady_clock::now();
     RunOptions ro = run_options(opts, cap);
+    if (ro.score && mode == DM_OUT_TABLE) DM_TRY(ensure_costs(dg));
     RunOutput o;
     DM_TRY(run_plan_chunked(dg->ctx, ws, dg, plan, ro, &o));
     auto* r = new dm_result();
@@ -1287,6 +1417,7 @@ dm_status enumerate_one(dm_datagraph* dg, Workspace& ws, const dm_graph_desc* gp
     } else {
         r->rows = o.sorted_rows;
         r->data = o.sorted;
+        r->costs = o.costs;
     }
     r->stats = o.stats;
     r->stats.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -1374,7 +1505,24 @@ void dm_result_free(dm_result* r) {
         (void)hipSetDevice(r->ctx->device);
         dev_free(r->data, r->stream);
     }
+    if (r->costs) {
+        (void)hipSetDevice(r->ctx->device);
+        dev_free(r->costs, r->stream);
+    }
     delete r;
+}
+
+const uint64_t* dm_result_device_costs(const dm_result* r) { return (r && r->rows > 0) ? r->costs : nullptr; }
+
+dm_status dm_result_copy_costs(const dm_result* r, uint64_t* dst, int64_t max_rows) {
+    if (!r || (!dst && max_rows > 0)) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    if (!r->costs && r->rows > 0) return fail(DM_ERR_INVALID_ARG, "result was not scored");
+    const int64_t n = std::min<int64_t>(max_rows, r->rows);
+    if (n <= 0) return DM_OK;
+    DM_HIP(hipSetDevice(r->ctx->device));
+    DM_HIP(hipMemcpyAsync(dst, r->costs, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToHost, r->stream));
+    DM_HIP(hipStreamSynchronize(r->stream));
+    return DM_OK;
 }
 
 }  // extern "C"

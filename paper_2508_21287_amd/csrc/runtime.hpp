@@ -61,6 +61,9 @@ struct Workspace {
     std::vector<hipEvent_t> prof;  // event pairs for per-launch timing
     SortJob* job_d = nullptr;      // one sort job (plain path) and its pinned staging
     SortJob* job_h = nullptr;
+    uint64_t* cbuf[2] = {nullptr, nullptr};  // scored runs: cost of each row of buf[i]
+    int64_t cbuf_rows[2] = {0, 0};
+    dm_status ensure_cbuf(int i, int64_t rows);
     // batched form: device heap of step tables and look-back words (grows on demand)
     int32_t* heap = nullptr;
     int64_t heap_elems = 0;
@@ -114,6 +117,8 @@ struct dm_datagraph {
     int32_t* src = nullptr;
     uint32_t* bitmap = nullptr;
     int32_t words_per_row = 0;
+    uint32_t* vcost = nullptr;  // layout costs: per vertex (n) and per CSR entry (nnz); zeros until set
+    uint32_t* ecost = nullptr;
     uint32_t mask_built = 0;  // DM_MOTIF_* bits
     uint32_t motif_bits = 1;  // bit per MotifIndex present
     dm::MotifTable tab[dm::kNumMotifs][6];
@@ -138,6 +143,7 @@ struct dm_result {
     int64_t rows = 0;
     int64_t total = 0;
     int32_t* data = nullptr;  // device, row-major
+    uint64_t* costs = nullptr;  // scored results: device, one per row (owned)
     std::shared_ptr<void> block;  // batched results share one allocation (data points inside)
     hipStream_t stream = nullptr;
     int32_t mode = DM_OUT_TABLE;
@@ -159,6 +165,7 @@ struct RunOptions {
     int32_t root_begin = 0;    // root range [root_begin, root_end) of the identity table;
     int32_t root_end = 0;      // empty range = every data vertex
     bool induced = false;      // pattern non-edges must map to data non-edges
+    bool score = false;        // layout costs per row; with cap >= 0 the cap best rows by (cost, row)
 };
 
 // Output of one plan execution on one workspace.
@@ -168,6 +175,7 @@ struct RunOutput {
     int64_t stride = 0;
     int32_t* sorted = nullptr; // row-major sorted table (ownership passes to the caller)
     int64_t sorted_rows = 0;
+    uint64_t* costs = nullptr; // scored runs: cost of each sorted row (ownership passes to the caller)
     uint64_t hsum = 0, hxor = 0;
     dm_run_stats stats{};
 };
@@ -190,6 +198,8 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
                        int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters);
 
 dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan);
+// zero layout costs for a data graph that has none set yet
+dm_status ensure_costs(dm_datagraph* dg);
 RunOptions run_options(const dm_plan_opts* opts, int64_t cap);
 dm_result* empty_result(dm_context* ctx, int32_t k, int32_t mode);
 // One pattern through Algorithm 1 on workspace `ws` (its stream).

@@ -525,3 +525,62 @@ def test_motif_db_save_load(ctx, tmp_path):
         assert ei.value.code == -1, name
     with pytest.raises(dm.DMError):
         dm.DataGraph.load(ctx, str(tmp_path / "missing.dmdb"))
+
+
+def _costs(g, seed, hi=1000):
+    rng = np.random.default_rng(seed)
+    adj = W.adjacency_lists(g)
+    ce = np.array([(u, v) for u in range(g.n) for v in adj[u] if u < v], np.int32).reshape(-1, 2)
+    return rng.integers(0, hi, g.n).astype(np.uint32), ce, rng.integers(0, hi, len(ce)).astype(np.uint32)
+
+
+def test_layout_scoring(ctx):
+    # per-row layout costs accumulated join by join and the top-k by (cost,
+    # row), against the oracle's scored enumeration
+    g, pats = W.config2(10)
+    cases = [(g, pats[:10])]
+    g3 = W.heavy_hex(3, 9)
+    cases.append((g3, [W.path(6), W.cycle(12), W.prufer_tree(6, 0)]))
+    gg = W.grid(9, 9)
+    g23 = W.grid(2, 3)
+    cases.append((gg, [W.cycle(4), W.Pattern(g23.n, g23.edges, "2x3"), W.path(5), W.star(3)]))
+    for gi, (g, ps) in enumerate(cases):
+        vc, ce, ec = _costs(g, 40 + gi)
+        dg = ctx.datagraph(g.n, g.edges)
+        dg.set_costs(vc, ce, ec)
+        for p in ps:
+            want_rows, want_cost, total = oracle.enumerate_scored(g.n, g.edges, p.n, p.edges, vc, ce, ec)
+            for k in (1, 7, 100, 8192):
+                say(f"scored {g.name} {p.name} k={k}")
+                with dg.enumerate(p.n, p.edges, cap=k, score=True) as r:
+                    kk = min(k, total)
+                    assert r.total == total and r.rows == kk, (p.name, k)
+                    assert np.array_equal(r.to_numpy(), want_rows[:kk]), (g.name, p.name, k)
+                    assert np.array_equal(r.costs(), want_cost[:kk]), (g.name, p.name, k)
+            # no cap: every row in lexicographic order with its cost
+            lex, _ = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+            cost_of = {tuple(rw): int(c) for rw, c in zip(want_rows.tolist(), want_cost)}
+            with dg.enumerate(p.n, p.edges, score=True) as r:
+                got = r.to_numpy()
+                assert np.array_equal(got, lex)
+                assert [int(c) for c in r.costs()] == [cost_of[tuple(rw)] for rw in got.tolist()]
+        # batched calls route scored patterns through the single-pattern path
+        res = dg.enumerate_batch([(p.n, p.edges) for p in ps], caps=[5] * len(ps), score=True)
+        for p, r in zip(ps, res):
+            want_rows, want_cost, _ = oracle.enumerate_scored(g.n, g.edges, p.n, p.edges, vc, ce, ec, top_k=5)
+            assert np.array_equal(r.to_numpy(), want_rows) and np.array_equal(r.costs(), want_cost), p.name
+            r.free()
+        dg.free()
+    # default costs are zero; a top-k larger than the limit is refused
+    g = W.heavy_hex(3, 9)
+    dg = ctx.datagraph(g.n, g.edges)
+    lex, total = oracle.enumerate_embeddings(g.n, g.edges, 6, W.path(6).edges)
+    with dg.enumerate(6, W.path(6).edges, cap=10, score=True) as r:
+        assert np.array_equal(r.to_numpy(), lex[:10]) and not r.costs().any()
+    with pytest.raises(dm.DMError) as ei:
+        dg.enumerate(6, W.path(6).edges, cap=8193, score=True)
+    assert ei.value.code == -12
+    with pytest.raises(dm.DMError) as ei:
+        dg.set_costs(None, np.array([[0, 31]], np.int32), np.array([3], np.uint32))
+    assert ei.value.code == -1
+    dg.free()
