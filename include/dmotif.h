@@ -85,7 +85,12 @@ typedef enum {
 #define DM_MOTIF_C4 (1u << 4)
 #define DM_MOTIF_C6 (1u << 5)
 #define DM_MOTIF_C12 (1u << 6)
-#define DM_MOTIF_ALL 0x7Fu
+/* General shapes (Sec. VI-B): M4-1 = the claw K1,3 (centre + 3 leaves),
+ * M6-2O = the 2x3 grid (two squares sharing an edge). */
+#define DM_MOTIF_M4_1 (1u << 7)
+#define DM_MOTIF_M6_2O (1u << 8)
+#define DM_MOTIF_ALL 0x1FFu
+#define DM_NUM_MOTIFS 10
 #define DM_MOTIF_AUTO 0u
 /* For dm_plan_opts.motif_mask: plan with M2 only (Sec. IV-B: one join per
  * pattern edge, the parallel analogue of tree search). */
@@ -161,15 +166,17 @@ typedef struct {
     int32_t max_degree;
     int32_t has_bitmap;       /* adjacency bitmap built (|V| <= 32768) */
     uint32_t motif_mask;      /* motifs actually built */
-    int64_t motif_rows[8];    /* rows of Res(M) for M2,M3,M4,M5,M6,C4,C6,C12 (0 = absent) */
+    int64_t motif_rows[DM_NUM_MOTIFS]; /* rows of Res(M) for M2,M3,M4,M5,M6,C4,C6,C12,M4-1,M6-2O
+                                          (0 = absent) */
     double build_ms;          /* device time of the whole build */
 } dm_datagraph_info;
 
 dm_status dm_datagraph_query(const dm_datagraph* dg, dm_datagraph_info* out);
 /* Host copies of the normalized CSR: row_ptr[n+1], col[2|E|] (each list ascending). */
 dm_status dm_datagraph_copy_csr(const dm_datagraph* dg, int32_t* row_ptr, int32_t* col);
-/* Host copy of a motif table: motif index 0..7 as in motif_rows, key
- * position `key_pos` (0 for cycles; 0..ceil(size/2)-1 for paths).  Rows are
+/* Host copy of a motif table: motif index 0..DM_NUM_MOTIFS-1 as in motif_rows, key
+ * position `key_pos` (0 for cycles; 0..ceil(size/2)-1 for paths; 0..1 for M4-1
+ * (centre, leaf) and M6-2O (corner, middle)).  Rows are
  * grouped by the key column in ascending key order; columns are in motif
  * position order.  rows and width receive the shape; dst may be NULL to query. */
 dm_status dm_datagraph_copy_motif(const dm_datagraph* dg, int32_t motif, int32_t key_pos,
@@ -180,8 +187,8 @@ dm_status dm_datagraph_copy_motif(const dm_datagraph* dg, int32_t motif, int32_t
  * so that a later process reloads it instead of rebuilding it (Sec. II-A and V-B: the
  * data preparation depends only on the device topology and is cached).
  * Host file I/O after device-to-host copies on the context stream.
- * File image (little-endian): "DMOTIFDB", u32 version (1), u32 0, i32 n,
- * i64 nnz, u32 motif mask, u32 motif bits, f64 table rows[8], f64 mean
+ * File image (little-endian): "DMOTIFDB", u32 version (2), u32 0, i32 n,
+ * i64 nnz, u32 motif mask, u32 motif bits, f64 table rows[DM_NUM_MOTIFS], f64 mean
  * degree, i32 row_ptr[n+1], i32 col[nnz]; then for every built motif except
  * M2 (which is the CSR), for every key position: i64 rows, i32 width, the
  * columns i32[width][rows] in motif position order, i32 index[n+1]; last a
@@ -214,7 +221,7 @@ dm_status dm_datagraph_set_costs(dm_datagraph* dg, const uint32_t* vertex_cost, 
 /* Planner only (host, no device work): decompose a pattern with the motifs
  * in `motif_mask` (Sec. III-C) and serialize the plan into `buf` as int32:
  *   [k, n_steps, col_of[k] (pattern vertex -> table column), then per step:
- *    motif (0..7, -1 = filter only), key_pos, key_col, c_in,
+ *    motif (0..DM_NUM_MOTIFS-1, -1 = filter only), key_pos, key_col, c_in,
  *    n_new, new_pos[n_new], n_eq, (col, pos)[n_eq], n_edge, (col_a, col_b)[n_edge],
  *    slice_len, slice[slice_len] (pattern vertices in motif order)].
  * *len receives the number of int32 written (or needed, if buf is too small:

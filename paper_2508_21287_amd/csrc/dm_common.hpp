@@ -13,32 +13,56 @@ constexpr int kMaxMotif = DM_MAX_MOTIF_VERTICES;  // vertices in the largest mot
 constexpr int kMaxCols = DM_MAX_PATTERN_VERTICES; // columns of a partial-embedding table
 constexpr int kMaxEdgeChecks = 24;                // explicit edge checks per join step
 constexpr int kMaxSteps = DM_MAX_PATTERN_VERTICES;
-constexpr int kNumMotifs = 8;
+constexpr int kNumMotifs = DM_NUM_MOTIFS;
+constexpr int kMaxMotifEdges = 8;  // edges of a general-shape motif
 
-// Motif catalogue (Sec. III-A "Motifs": M_i = path of i vertices, -O = cycle).
+// Motif catalogue (Sec. III-A "Motifs": M_i = path of i vertices, -O =
+// cycle; the general shapes of Sec. VI-B: M4-1 = claw, M6-2O = 2x3 grid).
 // Index order matches dm_datagraph_info.motif_rows.
-enum MotifIndex { MOT_P2 = 0, MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12 };
+enum MotifIndex { MOT_P2 = 0, MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23 };
 
 struct MotifInfo {
     int size;
     bool cycle;
     uint32_t bit;  // DM_MOTIF_* bit (0 for M2: always present)
     const char* name;
+    bool general;  // neither path nor cycle: shape given by `edges`
+    int n_edges;
+    int8_t edges[kMaxMotifEdges][2];
 };
 
+// General shapes are labelled so that positions 0..K-1 are one
+// representative of each orbit of the motif's automorphism group (K = the
+// number of orbits), as for paths (0..(L-1)/2) and cycles (0): the motif
+// table keyed on position j serves every position of j's orbit.
 inline const MotifInfo& motif_info(int m) {
     static const MotifInfo kInfo[kNumMotifs] = {
-        {2, false, 0u, "M2"},           {3, false, DM_MOTIF_M3, "M3"},
-        {4, false, DM_MOTIF_M4, "M4"},  {5, false, DM_MOTIF_M5, "M5"},
-        {6, false, DM_MOTIF_M6, "M6"},  {4, true, DM_MOTIF_C4, "M4-O"},
-        {6, true, DM_MOTIF_C6, "M6-O"}, {12, true, DM_MOTIF_C12, "M12-O"}};
+        {2, false, 0u, "M2", false, 0, {}},
+        {3, false, DM_MOTIF_M3, "M3", false, 0, {}},
+        {4, false, DM_MOTIF_M4, "M4", false, 0, {}},
+        {5, false, DM_MOTIF_M5, "M5", false, 0, {}},
+        {6, false, DM_MOTIF_M6, "M6", false, 0, {}},
+        {4, true, DM_MOTIF_C4, "M4-O", false, 0, {}},
+        {6, true, DM_MOTIF_C6, "M6-O", false, 0, {}},
+        {12, true, DM_MOTIF_C12, "M12-O", false, 0, {}},
+        // claw: centre 0, leaves 1..3 (orbits {0}, {1,2,3})
+        {4, false, DM_MOTIF_M4_1, "M4-1", true, 3, {{0, 1}, {0, 2}, {0, 3}}},
+        // 2x3 grid: rows 0-1-2 over 3-4-5 (orbits: corners {0,2,3,5}, middles {1,4})
+        {6, false, DM_MOTIF_M6_2O, "M6-2O", true, 7, {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 3}, {1, 4}, {2, 5}}}};
     return kInfo[m];
 }
 
+// Automorphism orbits of a general-shape motif (computed once).
+int general_motif_orbits(int m);                 // number of orbits
+int general_motif_orbit_rep(int m, int pos);     // the orbit's representative position (< orbits)
+// an automorphism (position -> position) mapping `pos` to its representative
+const int8_t* general_motif_to_rep(int m, int pos);
+
 // Distinct key positions up to the motif's symmetry: a path reads the same
-// reversed, a cycle the same rotated.
+// reversed, a cycle the same rotated, a general shape by its automorphisms.
 inline int motif_key_positions(int m) {
     const MotifInfo& mi = motif_info(m);
+    if (mi.general) return general_motif_orbits(m);
     return mi.cycle ? 1 : (mi.size + 1) / 2;
 }
 
@@ -98,7 +122,7 @@ dm_status normalize_pattern(const dm_graph_desc* gp, NormPattern* out, std::stri
 // Motif-table statistics used by the estimator (rows per motif; 0 = absent).
 struct MotifStats {
     int32_t n_vertices = 0;
-    double rows[kNumMotifs] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double rows[kNumMotifs] = {};
     double avg_degree = 0;
 };
 

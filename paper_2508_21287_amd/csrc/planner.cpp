@@ -22,6 +22,67 @@
 
 namespace dm {
 
+// ---- general-shape motifs: automorphisms by brute force (size <= 6)
+
+namespace {
+
+struct GeneralMotif {
+    int orbits = 0;
+    int8_t rep[kMaxMotif];               // position -> representative
+    int8_t to_rep[kMaxMotif][kMaxMotif]; // position -> an automorphism taking it to rep
+};
+
+GeneralMotif compute_general(int m) {
+    const MotifInfo& mi = motif_info(m);
+    const int L = mi.size;
+    bool adj[kMaxMotif][kMaxMotif] = {};
+    for (int e = 0; e < mi.n_edges; e++) adj[mi.edges[e][0]][mi.edges[e][1]] = adj[mi.edges[e][1]][mi.edges[e][0]] = true;
+    GeneralMotif g;
+    int perm[kMaxMotif];
+    for (int i = 0; i < L; i++) {
+        perm[i] = i;
+        g.rep[i] = (int8_t)i;
+        for (int j = 0; j < L; j++) g.to_rep[i][j] = (int8_t)j;
+    }
+    bool have[kMaxMotif] = {};
+    do {
+        bool ok = true;
+        for (int a = 0; a < L && ok; a++)
+            for (int b = 0; b < L && ok; b++)
+                if (adj[a][b] != adj[perm[a]][perm[b]]) ok = false;
+        if (!ok) continue;
+        for (int i = 0; i < L; i++) {
+            const int j = perm[i];
+            // the smallest position reachable from i is its representative
+            if (j < g.rep[i] || (j == g.rep[i] && !have[i])) {
+                g.rep[i] = (int8_t)j;
+                have[i] = true;
+                for (int q = 0; q < L; q++) g.to_rep[i][q] = (int8_t)perm[q];
+            }
+        }
+    } while (std::next_permutation(perm, perm + L));
+    int reps = 0;
+    for (int i = 0; i < L; i++) reps += g.rep[i] == i;
+    g.orbits = reps;
+    return g;
+}
+
+const GeneralMotif& general(int m) {
+    static const std::vector<GeneralMotif> table = [] {
+        std::vector<GeneralMotif> t(kNumMotifs);
+        for (int q = 0; q < kNumMotifs; q++)
+            if (motif_info(q).general) t[q] = compute_general(q);
+        return t;
+    }();
+    return table[m];
+}
+
+}  // namespace
+
+int general_motif_orbits(int m) { return general(m).orbits; }
+int general_motif_orbit_rep(int m, int pos) { return general(m).rep[pos]; }
+const int8_t* general_motif_to_rep(int m, int pos) { return general(m).to_rep[pos]; }
+
 uint32_t motif_bits_from_mask(uint32_t m) {
     uint32_t bits = 1u << MOT_P2;
     if (m & DM_MOTIF_M2_ONLY) return bits;
@@ -203,6 +264,128 @@ struct Planner {
         }
         return best_score >= 0;
     }
+
+    // ---- general-shape motifs: embeddings of the motif graph into the
+    // pattern (motif edges onto pattern edges, covered or not) that share a
+    // placed vertex, bring a new one and cover at least one uncovered edge
+    const MotifInfo* gm = nullptr;
+    bool gadj[kMaxMotif][kMaxMotif];
+    int32_t gord[kMaxMotif], gpar[kMaxMotif];
+    int32_t gseq[kMaxMotif];  // motif position -> pattern vertex
+    std::vector<std::vector<char>> padj;  // pattern adjacency (all edges)
+
+    bool is_gmotif_edge(const int32_t* sq, int32_t a, int32_t b) const {
+        for (int e = 0; e < gm->n_edges; e++) {
+            const int32_t x = sq[gm->edges[e][0]], y = sq[gm->edges[e][1]];
+            if ((x == a && y == b) || (x == b && y == a)) return true;
+        }
+        return false;
+    }
+
+    int count_checks_general(const int32_t* sq) const {
+        char ins[kMaxCols];
+        std::memset(ins, 0, sizeof ins);
+        for (int i = 0; i < L; i++) ins[sq[i]] = 1;
+        int c = 0;
+        for (int i = 0; i < L; i++) {
+            int32_t u = sq[i];
+            if (mapped(u)) continue;
+            for (int32_t w : nbrs[u]) {
+                if (!uncov[u][w]) continue;
+                if (!(mapped(w) || ins[w])) continue;
+                if (is_gmotif_edge(sq, u, w)) continue;
+                if (!mapped(w) && w < u) continue;
+                c++;
+            }
+        }
+        return c;
+    }
+
+    void consider_general() {
+        found++;
+        int keys = 0, nnew = 0;
+        for (int i = 0; i < L; i++) (mapped(gseq[i]) ? keys : nnew)++;
+        if (keys == 0 || nnew == 0) return;
+        bool covers = false;
+        for (int e = 0; e < gm->n_edges && !covers; e++) covers = uncov[gseq[gm->edges[e][0]]][gseq[gm->edges[e][1]]];
+        if (!covers) return;
+        int score = 2 * keys + count_checks_general(gseq);
+        if (score > best_score) {
+            best_score = score;
+            std::memcpy(best, gseq, sizeof(int32_t) * L);
+        }
+    }
+
+    void gdfs(int depth) {
+        if (found >= kMaxFound || expansions >= kMaxExpansions) return;
+        expansions++;
+        if (depth == L) {
+            consider_general();
+            return;
+        }
+        const int pos = gord[depth];
+        const int32_t anchor = gseq[gpar[pos]];
+        for (int32_t w : nbrs[anchor]) {
+            if (inseq[w]) continue;
+            bool ok = true;
+            for (int d = 0; d < depth && ok; d++) {
+                const int q = gord[d];
+                if (gadj[pos][q] && !padj[w][gseq[q]]) ok = false;
+            }
+            if (!ok) continue;
+            gseq[pos] = w;
+            inseq[w] = 1;
+            gdfs(depth + 1);
+            inseq[w] = 0;
+            if (found >= kMaxFound || expansions >= kMaxExpansions) return;
+        }
+    }
+
+    bool search_general(int m) {
+        gm = &motif_info(m);
+        L = gm->size;
+        cyc = false;
+        expansions = found = 0;
+        best_score = -1;
+        std::memset(inseq, 0, sizeof inseq);
+        std::memset(gadj, 0, sizeof gadj);
+        for (int e = 0; e < gm->n_edges; e++) gadj[gm->edges[e][0]][gm->edges[e][1]] = gadj[gm->edges[e][1]][gm->edges[e][0]] = true;
+        // anchor: a placed vertex (placement order) at each motif position in turn
+        std::vector<std::pair<int32_t, int32_t>> placed;
+        for (int32_t v = 0; v < k; v++)
+            if (mapped(v)) placed.emplace_back(col_of[v], v);
+        std::sort(placed.begin(), placed.end());
+        for (auto& pv : placed) {
+            const int32_t v = pv.second;
+            bool has_uncov = false;
+            for (int32_t w : nbrs[v]) has_uncov |= (bool)uncov[v][w];
+            if (!has_uncov) continue;
+            for (int a = 0; a < L; a++) {
+                // BFS order of the motif from position a
+                int head = 0, tail = 0;
+                bool seen[kMaxMotif] = {};
+                gord[tail++] = a;
+                seen[a] = true;
+                gpar[a] = a;
+                while (head < tail) {
+                    const int x = gord[head++];
+                    for (int y = 0; y < L; y++)
+                        if (gadj[x][y] && !seen[y]) {
+                            seen[y] = true;
+                            gpar[y] = x;
+                            gord[tail++] = y;
+                        }
+                }
+                gseq[a] = v;
+                inseq[v] = 1;
+                gdfs(1);
+                inseq[v] = 0;
+                if (found >= kMaxFound || expansions >= kMaxExpansions) break;
+            }
+            if (found >= kMaxFound || expansions >= kMaxExpansions) break;
+        }
+        return best_score >= 0;
+    }
 };
 
 double estimate_fanout(const MotifStats* st, int m) {
@@ -230,6 +413,8 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
         pl.uncov[e.first][e.second] = pl.uncov[e.second][e.first] = 1;
     }
     for (auto& nb : pl.nbrs) std::sort(nb.begin(), nb.end());
+    pl.padj.assign(k, std::vector<char>(k, 0));
+    for (auto& e : p.edges) pl.padj[e.first][e.second] = pl.padj[e.second][e.first] = 1;
     for (int32_t v = 0; v < kMaxCols; v++) pl.col_of[v] = -1;
     pl.col_of[root] = 0;
     pl.ncols = 1;
@@ -246,7 +431,8 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
     std::sort(order.begin(), order.end(), [](int a, int b) {
         const MotifInfo &x = motif_info(a), &y = motif_info(b);
         if (x.size != y.size) return x.size > y.size;
-        return x.cycle && !y.cycle;
+        const int rx = x.cycle ? 0 : (x.general ? 1 : 2), ry = y.cycle ? 0 : (y.general ? 1 : 2);
+        return rx < ry;
     });
 
     const double nv = stats ? (double)stats->n_vertices : 0.0;
@@ -260,7 +446,7 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
         for (int m : order) {
             const MotifInfo& mi = motif_info(m);
             if (mi.size > k) continue;
-            if (pl.search(mi.size, mi.cycle)) {
+            if (mi.general ? pl.search_general(m) : pl.search(mi.size, mi.cycle)) {
                 chosen = m;
                 break;
             }
@@ -275,7 +461,21 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
         std::memcpy(s, pl.best, sizeof(int32_t) * L);
         // canonical orientation: key at the smallest available key position
         int key = -1;
-        if (mi.cycle) {
+        if (mi.general) {
+            // key: the placed position with the smallest orbit representative,
+            // moved onto that representative by an automorphism
+            int bestrep = 1 << 30;
+            for (int i = 0; i < L; i++)
+                if (pl.mapped(s[i]) && general_motif_orbit_rep(chosen, i) < bestrep) {
+                    bestrep = general_motif_orbit_rep(chosen, i);
+                    key = i;
+                }
+            const int8_t* a = general_motif_to_rep(chosen, key);
+            int32_t r[kMaxMotif];
+            for (int i = 0; i < L; i++) r[a[i]] = s[i];
+            std::memcpy(s, r, sizeof(int32_t) * L);
+            key = bestrep;
+        } else if (mi.cycle) {
             for (int i = 0; i < L && key < 0; i++)
                 if (pl.mapped(s[i])) key = i;
             int32_t r[kMaxMotif];
@@ -312,6 +512,7 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
                 d.n_eq++;
                 int dist = std::abs(i - key);
                 if (mi.cycle) dist = std::min(dist, L - dist);
+                if (mi.general) dist = 1;
                 min_eq_dist = std::max(min_eq_dist, dist);
             }
         }
@@ -322,8 +523,15 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
             }
         }
         // motif edges are now covered
-        for (int i = 0; i + 1 < L; i++) pl.uncov[s[i]][s[i + 1]] = pl.uncov[s[i + 1]][s[i]] = 0;
-        if (mi.cycle) pl.uncov[s[L - 1]][s[0]] = pl.uncov[s[0]][s[L - 1]] = 0;
+        if (mi.general) {
+            for (int e = 0; e < mi.n_edges; e++) {
+                const int32_t x = s[mi.edges[e][0]], y = s[mi.edges[e][1]];
+                pl.uncov[x][y] = pl.uncov[y][x] = 0;
+            }
+        } else {
+            for (int i = 0; i + 1 < L; i++) pl.uncov[s[i]][s[i + 1]] = pl.uncov[s[i + 1]][s[i]] = 0;
+            if (mi.cycle) pl.uncov[s[L - 1]][s[0]] = pl.uncov[s[0]][s[L - 1]] = 0;
+        }
         // explicit edge checks for remaining pattern edges among placed vertices
         std::vector<std::pair<int, int>> checks;
         for (int i = 0; i < L; i++) {
@@ -347,7 +555,11 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
         // placed neighbours, each motif edge at the key competes with them
         double fan = estimate_fanout(stats, chosen);
         if (d.c_in > 1) {
-            const int key_deg = mi.cycle ? 2 : ((key == 0 || key == L - 1) ? 1 : 2);
+            int key_deg = mi.cycle ? 2 : ((key == 0 || key == L - 1) ? 1 : 2);
+            if (mi.general) {
+                key_deg = 0;
+                for (int e = 0; e < mi.n_edges; e++) key_deg += (mi.edges[e][0] == key) + (mi.edges[e][1] == key);
+            }
             fan *= std::pow(std::max(deg - 1.0, 0.5) / deg, key_deg);
         }
         double nrows = rows * fan;

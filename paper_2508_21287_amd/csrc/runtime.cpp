@@ -762,8 +762,13 @@ static NormPattern motif_pattern(int m) {
     const MotifInfo& mi = motif_info(m);
     NormPattern p;
     p.k = mi.size;
-    for (int i = 0; i + 1 < mi.size; i++) p.edges.emplace_back(i, i + 1);
-    if (mi.cycle) p.edges.emplace_back(0, mi.size - 1);
+    if (mi.general) {
+        for (int e = 0; e < mi.n_edges; e++)
+            p.edges.emplace_back(std::min(mi.edges[e][0], mi.edges[e][1]), std::max(mi.edges[e][0], mi.edges[e][1]));
+    } else {
+        for (int i = 0; i + 1 < mi.size; i++) p.edges.emplace_back(i, i + 1);
+        if (mi.cycle) p.edges.emplace_back(0, mi.size - 1);
+    }
     std::sort(p.edges.begin(), p.edges.end());
     return p;
 }
@@ -940,7 +945,7 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
 // ---- persisted motif database
 //
 // File image (little-endian): "DMOTIFDB", u32 version, u32 reserved, then
-// i32 n, i64 nnz, u32 mask_built, u32 motif_bits, f64 stats rows[8], f64
+// i32 n, i64 nnz, u32 mask_built, u32 motif_bits, f64 stats rows[kNumMotifs], f64
 // avg_degree, i32 row_ptr[n+1], i32 col[nnz], then for every built motif
 // other than M2 (which is the CSR) and every key position: i64 rows, i32
 // size, i32 column data [size][rows] (motif position order), i32 offs[n+1];
@@ -949,7 +954,7 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
 namespace {
 
 constexpr char kDbMagic[8] = {'D', 'M', 'O', 'T', 'I', 'F', 'D', 'B'};
-constexpr uint32_t kDbVersion = 1;
+constexpr uint32_t kDbVersion = 2;
 
 uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
     const unsigned char* b = (const unsigned char*)p;
@@ -1007,7 +1012,7 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
     if (st == DM_OK && dg->n > 0) {
         const bool aut = (motif_mask == DM_MOTIF_AUTO);
         uint32_t want = aut ? (DM_MOTIF_M3 | DM_MOTIF_M4 | DM_MOTIF_C4) : motif_mask;
-        const int order[] = {MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12};
+        const int order[] = {MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23};
         for (int m : order) {
             if (st != DM_OK) break;
             if (!(want & motif_info(m).bit)) continue;

@@ -14,12 +14,23 @@ import oracle
 from paper_2508_21287_amd import workloads as W
 
 MOTIF_SHAPES = {0: ("path", 2), 1: ("path", 3), 2: ("path", 4), 3: ("path", 5), 4: ("path", 6),
-                5: ("cycle", 4), 6: ("cycle", 6), 7: ("cycle", 12)}
+                5: ("cycle", 4), 6: ("cycle", 6), 7: ("cycle", 12), 8: ("claw", 4), 9: ("grid2x3", 6)}
+
+
+def motif_pattern(m):
+    kind, size = MOTIF_SHAPES[m]
+    if kind == "path":
+        return W.path(size)
+    if kind == "cycle":
+        return W.cycle(size)
+    if kind == "claw":  # centre 0, leaves 1..3
+        return W.star(3)
+    # 2x3 grid: 0-1-2 over 3-4-5
+    return W.Pattern(6, [[0, 1], [1, 2], [3, 4], [4, 5], [0, 3], [1, 4], [2, 5]], "2x3")
 
 
 def motif_rows(g, m):
-    kind, size = MOTIF_SHAPES[m]
-    p = W.path(size) if kind == "path" else W.cycle(size)
+    p = motif_pattern(m)
     rows, _ = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
     return rows
 

@@ -77,7 +77,9 @@ def test_ingest_errors(ctx):
 
 
 MOTIF_PATTERNS = {0: W.path(2), 1: W.path(3), 2: W.path(4), 3: W.path(5), 4: W.path(6), 5: W.cycle(4),
-                  6: W.cycle(6), 7: W.cycle(12)}
+                  6: W.cycle(6), 7: W.cycle(12), 8: W.star(3),
+                  9: W.Pattern(6, [[0, 1], [1, 2], [3, 4], [4, 5], [0, 3], [1, 4], [2, 5]], "2x3")}
+MOTIF_KEY_POSITIONS = {0: 1, 1: 2, 2: 2, 3: 3, 4: 3, 5: 1, 6: 1, 7: 1, 8: 2, 9: 2}
 
 
 @pytest.mark.parametrize("gname", ["HH(3,9)", "HH(7,19)", "GRID(6,7)"])
@@ -88,8 +90,7 @@ def test_motif_tables(ctx, gname):
     for m, p in MOTIF_PATTERNS.items():
         want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
         assert info["motif_rows"][dm.MOTIF_NAMES[m]] == total, (gname, m)
-        nkp = 1 if m in (5, 6, 7) else (p.n + 1) // 2
-        for j in range(nkp):
+        for j in range(MOTIF_KEY_POSITIONS[m]):
             say(f"motif {dm.MOTIF_NAMES[m]} key {j} on {gname}")
             t = dg.motif_table(m, j)
             assert len(t) == total
@@ -114,8 +115,9 @@ def test_config2_parity(ctx):
     dg.free()
 
 
-@pytest.mark.parametrize("mask", [dm.MOTIF_M2_ONLY, dm.MOTIF_M4, dm.MOTIF_C4 | dm.MOTIF_M3, 0],
-                         ids=["M2", "M4", "C4+M3", "all"])
+@pytest.mark.parametrize("mask", [dm.MOTIF_M2_ONLY, dm.MOTIF_M4, dm.MOTIF_C4 | dm.MOTIF_M3, dm.MOTIF_M4_1,
+                                  dm.MOTIF_M6_2O | dm.MOTIF_C4, 0],
+                         ids=["M2", "M4", "C4+M3", "M4-1", "M6-2O+C4", "all"])
 def test_plan_independence_gpu(ctx, mask):
     g = W.heavy_hex(4, 13)
     dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_ALL)
@@ -127,7 +129,9 @@ def test_plan_independence_gpu(ctx, mask):
     gr = W.grid(7, 8)
     dgr = ctx.datagraph(gr.n, gr.edges, dm.MOTIF_ALL)
     g23 = W.grid(2, 3)
-    for p in [W.cycle(4), W.Pattern(g23.n, g23.edges, "grid2x3"), W.path(6), W.cycle(8)]:
+    g33, g34 = W.grid(3, 3), W.grid(3, 4)
+    for p in [W.cycle(4), W.Pattern(g23.n, g23.edges, "grid2x3"), W.path(6), W.cycle(8),
+              W.Pattern(g33.n, g33.edges, "grid3x3"), W.Pattern(g34.n, g34.edges, "grid3x4"), W.star(3)]:
         check_enum(dgr, gr, p, motif_mask=mask)
     dg.free()
     dgr.free()

@@ -83,11 +83,13 @@ def test_plan_structure(mask):
                 assert len(sl) == size and len(set(sl)) == size
                 placed = [i for i in range(size) if pl["col_of"][sl[i]] < cols]
                 assert placed and st["key_pos"] in placed  # slices overlap earlier ones (Sec. III-B)
-                me = [tuple(sorted((sl[i], sl[i + 1]))) for i in range(size - 1)]
-                if kind == "cycle":
-                    me.append(tuple(sorted((sl[0], sl[-1]))))
+                me = [tuple(sorted((sl[a], sl[b]))) for a, b in plan_exec.motif_pattern(st["motif"]).edges.tolist()]
+                fresh = [e for e in me if e not in covered]
+                assert fresh  # every slice covers a new pattern edge
+                if kind in ("path", "cycle"):
+                    assert len(fresh) == len(me)  # path and cycle slices follow uncovered edges only
                 for e in me:
-                    assert e in edges and e not in covered
+                    assert e in edges  # motif edges land on pattern edges (covered ones repeat a constraint)
                     covered.add(e)
                 cols += len(st["new_pos"])
             for a, b in st["edges"]:
