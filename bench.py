@@ -68,6 +68,14 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print one JSON line per large-table case "
                          "(10k-vertex lattices) with the join and sort kernels' bandwidth")
+    ap.add_argument("--motif-sets", action="store_true",
+                    help="instead of the benchmark line, time random lattice-subgraph patterns under each "
+                         "motif set (with and without building the motif tables) and count the join "
+                         "iterations, one JSON line per (topology, motif set)")
+    ap.add_argument("--pattern-size", type=int, default=60, help="motif-set study: heavy-hex pattern vertices")
+    ap.add_argument("--grid-pattern-size", type=int, default=16,
+                    help="motif-set study: grid pattern vertices (tree-like grid subgraphs explode beyond ~20)")
+    ap.add_argument("--patterns", type=int, default=8)
     return ap.parse_args()
 
 
@@ -209,6 +217,58 @@ def sweep(dm, W, ctx, reps=3):
         dg.free()
 
 
+def motif_sets(dm, W, ctx, k_hh, k_grid, n_patterns):
+    """Runtime and join iterations per motif set (the motif-selection study):
+    random connected subgraphs (random BFS + thinning, seeds 1000..) of the
+    4485-vertex heavy-hex lattice (k_hh vertices) and the 3600-vertex grid
+    (k_grid vertices), count+hash mode.  'total' includes building the motif tables of the set
+    (a fresh data graph per set), 'query' excludes it."""
+    import numpy as np
+    import torch
+    sets = {
+        "HH(60,60)": [("M2", dm.MOTIF_M2_ONLY), ("M2+M3", dm.MOTIF_M3), ("M2+M4", dm.MOTIF_M4),
+                      ("M2+M4-1", dm.MOTIF_M4_1), ("M2+M6", dm.MOTIF_M6), ("M2+M12-O", dm.MOTIF_C12),
+                      ("auto", dm.MOTIF_AUTO)],
+        "GRID(60,60)": [("M2", dm.MOTIF_M2_ONLY), ("M2+M4", dm.MOTIF_M4), ("M2+M4-O", dm.MOTIF_C4),
+                        ("M2+M4-1", dm.MOTIF_M4_1), ("M2+M6-2O", dm.MOTIF_M6_2O | dm.MOTIF_C4),
+                        ("auto", dm.MOTIF_AUTO)],
+    }
+    for gname, g, k in [("HH(60,60)", W.heavy_hex(60, 60), k_hh), ("GRID(60,60)", W.grid(60, 60), k_grid)]:
+        adj = W.adjacency_lists(g)
+        pats = [W.lattice_subgraph_pattern(g, k, np.random.default_rng(1000 + s), adj=adj)
+                for s in range(n_patterns)]
+        for sname, mask in sets[gname]:
+            tot, qry, its, counts = [], [], [], []
+            for p in pats:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                dg = dm.DataGraph(ctx, g.n, g.edges, mask)
+                t1 = time.perf_counter()
+                try:
+                    with dg.enumerate(p.n, p.edges, mode=dm.OUT_COUNT_HASH,
+                                      motif_mask=mask if mask != dm.MOTIF_AUTO else 0) as r:
+                        st = r.stats()
+                        counts.append(r.total)
+                        its.append(st["n_steps"])
+                    t2 = time.perf_counter()
+                    tot.append(1e3 * (t2 - t0))
+                    qry.append(1e3 * (t2 - t1))
+                except dm.DMError as e:
+                    counts.append(None)
+                    its.append(None)
+                    print(json.dumps({"motif_set": sname, "graph": gname, "pattern": p.name, "error": str(e)}),
+                          flush=True)
+                dg.free()
+            ok = [i for i, c in enumerate(counts) if c is not None]
+
+            def mmm(xs):
+                xs = [xs[i] for i in ok]
+                return {"mean": float(np.mean(xs)), "min": float(np.min(xs)), "max": float(np.max(xs))} if xs else None
+            print(json.dumps({"motif_sets": gname, "set": sname, "pattern_vertices": k, "patterns": len(pats),
+                              "completed": len(ok), "total_ms": mmm(tot), "query_ms": mmm(qry),
+                              "iterations": mmm(its), "embeddings": mmm(counts)}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -233,6 +293,9 @@ def main():
     ctx = dm.Context(0)
     if args.sweep:
         sweep(dm, W, ctx)
+        return
+    if args.motif_sets:
+        motif_sets(dm, W, ctx, args.pattern_size, args.grid_pattern_size, args.patterns)
         return
 
     def step(profile: bool):

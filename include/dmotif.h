@@ -75,9 +75,11 @@ typedef enum {
 /* Motif families (Sec. III-A "Motifs": M_i is a path of i vertices, the
  * suffix -O a cycle).  M2 (the edge table) is always present.  A data graph
  * is built with a mask of these; a plan may use any subset of what was built.
- * DM_MOTIF_AUTO builds M3, M4, and the shortest cycle family present among
- * C4 (square grid) and C12 (heavy-hex cell), mirroring the topology-aware
- * motif sets of Sec. V (M2+M4 on heavy-hex, M2+M4-O on grids). */
+ * DM_MOTIF_AUTO is topology-aware (Sec. VI-B): on a graph with 4-cycles
+ * (grid-like) it builds M3, M4 and M4-O; without them and with low degrees
+ * (heavy-hex-like: at most 5e7 claws) the claw M4-1, the set that measured
+ * fastest on heavy-hex lattices (as in the paper's {M2, M4-1}); otherwise M3,
+ * M4 and, when its table stays moderate, the 12-cycle M12-O. */
 #define DM_MOTIF_M3 (1u << 0)
 #define DM_MOTIF_M4 (1u << 1)
 #define DM_MOTIF_M5 (1u << 2)
@@ -217,6 +219,18 @@ dm_status dm_datagraph_load(dm_context* ctx, const char* path, dm_datagraph** ou
  * graph or is listed twice), DM_ERR_OUT_OF_MEMORY, DM_ERR_DEVICE. */
 dm_status dm_datagraph_set_costs(dm_datagraph* dg, const uint32_t* vertex_cost, int64_t n_cost_edges,
                                  const int32_t* cost_edges, const uint32_t* edge_cost);
+
+/* Motif-set tuning (Sec. VI-B: the best motif set depends on the topology):
+ * for each of n_candidates DM_MOTIF_* masks (DM_MOTIF_AUTO and
+ * DM_MOTIF_M2_ONLY allowed), build the data graph `gd` with that set and
+ * enumerate the n_sample patterns in `sample` as one batch in count+hash
+ * mode, reps times; the median wall time of build + enumeration goes to
+ * ms_per_candidate[c] (may be NULL) and the fastest mask to *best_mask
+ * (the first one on ties).  Synchronous on the context stream.
+ * Errors: DM_ERR_INVALID_ARG, and any error of the builds or enumerations. */
+dm_status dm_autotune_motifs(dm_context* ctx, const dm_graph_desc* gd, int32_t n_sample,
+                             const dm_graph_desc* sample, const uint32_t* candidates, int32_t n_candidates,
+                             int32_t reps, uint32_t* best_mask, double* ms_per_candidate);
 
 /* Planner only (host, no device work): decompose a pattern with the motifs
  * in `motif_mask` (Sec. III-C) and serialize the plan into `buf` as int32:

@@ -87,7 +87,7 @@ _LIB = None
 EXPORTS = [
     "dm_version", "dm_last_error", "dm_context_create", "dm_context_destroy", "dm_datagraph_build",
     "dm_datagraph_free", "dm_datagraph_save", "dm_datagraph_load", "dm_datagraph_set_costs",
-    "dm_result_device_costs", "dm_result_copy_costs", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
+    "dm_result_device_costs", "dm_result_copy_costs", "dm_autotune_motifs", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
     "dm_estimate", "dm_enumerate", "dm_enumerate_batch", "dm_result_rows", "dm_result_total",
     "dm_result_width", "dm_result_device_data", "dm_result_hash", "dm_result_copy_to_host",
     "dm_result_copy_to_device", "dm_result_stats", "dm_result_free", "dm_server_start", "dm_server_submit",
@@ -122,6 +122,9 @@ def lib() -> C.CDLL:
             "dm_datagraph_build": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_uint32, C.POINTER(vp)]),
             "dm_datagraph_free": (None, [vp]),
             "dm_datagraph_save": (C.c_int, [vp, C.c_char_p]),
+            "dm_autotune_motifs": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_int32, C.POINTER(GraphDesc),
+                                             C.POINTER(C.c_uint32), C.c_int32, C.c_int32, C.POINTER(C.c_uint32),
+                                             C.POINTER(C.c_double)]),
             "dm_datagraph_set_costs": (C.c_int, [vp, C.POINTER(C.c_uint32), C.c_int64, i32p,
                                                  C.POINTER(C.c_uint32)]),
             "dm_result_device_costs": (vp, [vp]),
@@ -235,6 +238,19 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def autotune_motifs(self, n: int, edges, sample, candidates, reps: int = 3):
+        """``dm_autotune_motifs``: the fastest motif set for this data graph on
+        a sample of patterns; returns ``(best_mask, {mask: median_ms})``."""
+        g = _Graph(n, edges)
+        gs = [_Graph(pn, pe) for pn, pe in sample]
+        arr = (GraphDesc * len(gs))(*[x.desc for x in gs])
+        cand = (C.c_uint32 * len(candidates))(*[int(c) & 0xFFFFFFFF for c in candidates])
+        ms = (C.c_double * len(candidates))()
+        best = C.c_uint32()
+        _check(lib().dm_autotune_motifs(self.handle, C.byref(g.desc), len(gs), arr, cand, len(candidates),
+                                        int(reps), C.byref(best), ms))
+        return best.value, {int(c) & 0xFFFFFFFF: ms[i] for i, c in enumerate(candidates)}
 
     def datagraph(self, n: int, edges, motif_mask: int = MOTIF_AUTO) -> "DataGraph":
         return DataGraph(self, n, edges, motif_mask)

@@ -679,6 +679,47 @@ extern "C" dm_status dm_enumerate_batch(dm_datagraph* dg, int32_t n, const dm_gr
     return enumerate_many(dg, dg->ctx->ws, n, gps, caps, opts, outs);
 }
 
+// ------------------------------------------------------------------ motif-set tuning
+
+extern "C" dm_status dm_autotune_motifs(dm_context* ctx, const dm_graph_desc* gd, int32_t n_sample,
+                                        const dm_graph_desc* sample, const uint32_t* candidates,
+                                        int32_t n_candidates, int32_t reps, uint32_t* best_mask,
+                                        double* ms_per_candidate) {
+    if (!ctx || !gd || !best_mask || n_sample <= 0 || !sample || n_candidates <= 0 || !candidates || reps <= 0)
+        return fail(DM_ERR_INVALID_ARG, "invalid tuning arguments");
+    DM_HIP(hipSetDevice(ctx->device));
+    dm_plan_opts opts;
+    std::memset(&opts, 0, sizeof opts);
+    opts.output_mode = DM_OUT_COUNT_HASH;
+    std::vector<dm_result*> outs((size_t)n_sample, nullptr);
+    double best = 1e300;
+    int best_i = -1;
+    for (int32_t c = 0; c < n_candidates; c++) {
+        // the planner may use every table the data graph holds
+        opts.motif_mask = candidates[c] == DM_MOTIF_M2_ONLY ? DM_MOTIF_M2_ONLY : 0;
+        std::vector<double> t;
+        for (int32_t r = 0; r < reps; r++) {
+            const auto t0 = std::chrono::steady_clock::now();
+            dm_datagraph* dg = nullptr;
+            DM_TRY(dm_datagraph_build(ctx, gd, candidates[c], &dg));
+            dm_status st = enumerate_many(dg, ctx->ws, n_sample, sample, nullptr, &opts, outs.data());
+            for (auto*& o : outs) dm_result_free(o), o = nullptr;
+            dm_datagraph_free(dg);
+            if (st != DM_OK) return st;
+            t.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        std::sort(t.begin(), t.end());
+        const double med = t[t.size() / 2];
+        if (ms_per_candidate) ms_per_candidate[c] = med;
+        if (med < best) {
+            best = med;
+            best_i = c;
+        }
+    }
+    *best_mask = candidates[best_i];
+    return DM_OK;
+}
+
 // ------------------------------------------------------------------ server
 
 namespace {

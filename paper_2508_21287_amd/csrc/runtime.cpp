@@ -745,6 +745,19 @@ static void free_tables(dm_datagraph* dg) {
         }
 }
 
+// Drop one motif's tables from the database.
+static void free_motif(dm_datagraph* dg, int m) {
+    hipStream_t s = dg->ctx->stream;
+    for (int j = 0; j < 6; j++) {
+        MotifTable& t = dg->tab[m][j];
+        for (int q = 0; q < 2; q++) dev_free(t.owned[q], s);
+        t = MotifTable();
+    }
+    dg->motif_bits &= ~(1u << m);
+    dg->mask_built &= ~motif_info(m).bit;
+    dg->stats.rows[m] = 0;
+}
+
 static void free_datagraph(dm_datagraph* dg) {
     if (!dg) return;
     hipStream_t s = dg->ctx->stream;
@@ -1011,16 +1024,36 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
     dm_status st = ingest(dg, gd);
     if (st == DM_OK && dg->n > 0) {
         const bool aut = (motif_mask == DM_MOTIF_AUTO);
-        uint32_t want = aut ? (DM_MOTIF_M3 | DM_MOTIF_M4 | DM_MOTIF_C4) : motif_mask;
+        uint32_t want = motif_mask;
+        if (aut) {
+            // topology-aware set (Sec. VI-B): the square cell on grid-like graphs,
+            // the claw on low-degree graphs without 4-cycles (heavy-hex-like)
+            st = build_motif(dg, MOT_C4);
+            if (st == DM_OK && dg->tab[MOT_C4][0].rows > 0) {
+                want = DM_MOTIF_M3 | DM_MOTIF_M4 | DM_MOTIF_C4;
+            } else if (st == DM_OK) {
+                free_motif(dg, MOT_C4);
+                // the claw table has sum_v d(d-1)(d-2) rows: only for low degrees
+                std::vector<int32_t> rp((size_t)dg->n + 1);
+                if (hipMemcpy(rp.data(), dg->row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost) != hipSuccess)
+                    st = fail(DM_ERR_DEVICE, "degree readback failed");
+                double claws = 0;
+                for (int32_t v = 0; v < dg->n; v++) {
+                    const double d = rp[v + 1] - rp[v];
+                    claws += d * (d - 1) * (d - 2);
+                }
+                want = claws <= 5e7 ? DM_MOTIF_M4_1 : (DM_MOTIF_M3 | DM_MOTIF_M4);
+            }
+        }
         const int order[] = {MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23};
         for (int m : order) {
             if (st != DM_OK) break;
-            if (!(want & motif_info(m).bit)) continue;
+            if (!(want & motif_info(m).bit) || ((dg->motif_bits >> m) & 1)) continue;
             st = build_motif(dg, m);
         }
-        if (st == DM_OK && aut && dg->tab[MOT_C4][0].rows == 0) {
-            // girth > 4 (heavy-hex-like): add the 12-cycle cell if its path
-            // table stays moderate (estimated from the growth M3 -> M4)
+        if (st == DM_OK && aut && !(want & (DM_MOTIF_C4 | DM_MOTIF_M4_1))) {
+            // high-degree graph without 4-cycles: the 12-cycle cell when its
+            // path table stays moderate (estimated from the growth M3 -> M4)
             double r3 = dg->stats.rows[MOT_P3], r4 = dg->stats.rows[MOT_P4];
             double g = r3 > 0 ? r4 / r3 : 0;
             double est12 = r4 * std::pow(std::max(g, 1.0), 8);

@@ -588,3 +588,18 @@ def test_layout_scoring(ctx):
         dg.set_costs(None, np.array([[0, 31]], np.int32), np.array([3], np.uint32))
     assert ei.value.code == -1
     dg.free()
+
+
+def test_autotune_motifs(ctx):
+    g, pats = W.config2(8)
+    cands = [dm.MOTIF_AUTO, dm.MOTIF_M2_ONLY, dm.MOTIF_M4_1, dm.MOTIF_M3 | dm.MOTIF_M4 | dm.MOTIF_C12]
+    best, ms = ctx.autotune_motifs(g.n, g.edges, [(p.n, p.edges) for p in pats], cands, reps=2)
+    assert best in ms and all(t > 0 for t in ms.values())
+    assert ms[best] == min(ms.values())
+    # the tuned set answers like any other
+    dg = ctx.datagraph(g.n, g.edges, best)
+    for p in pats[:3]:
+        check_enum(dg, g, p)
+    dg.free()
+    with pytest.raises(dm.DMError):
+        ctx.autotune_motifs(g.n, g.edges, [], cands)
