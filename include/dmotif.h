@@ -54,7 +54,7 @@ extern "C" {
 #endif
 
 #define DM_MAX_PATTERN_VERTICES 128
-#define DM_MAX_MOTIF_VERTICES 12
+#define DM_MAX_MOTIF_VERTICES 18
 
 typedef enum {
     DM_OK = 0,
@@ -88,11 +88,13 @@ typedef enum {
 #define DM_MOTIF_C6 (1u << 5)
 #define DM_MOTIF_C12 (1u << 6)
 /* General shapes (Sec. VI-B): M4-1 = the claw K1,3 (centre + 3 leaves),
- * M6-2O = the 2x3 grid (two squares sharing an edge). */
+ * M6-2O = the 2x3 grid (two squares sharing an edge), M18-O-6 = the
+ * heavy-hex cell (a 12-cycle) with a pendant vertex at every other vertex. */
 #define DM_MOTIF_M4_1 (1u << 7)
 #define DM_MOTIF_M6_2O (1u << 8)
-#define DM_MOTIF_ALL 0x1FFu
-#define DM_NUM_MOTIFS 10
+#define DM_MOTIF_M18_O_6 (1u << 9)
+#define DM_MOTIF_ALL 0x3FFu
+#define DM_NUM_MOTIFS 11
 #define DM_MOTIF_AUTO 0u
 /* For dm_plan_opts.motif_mask: plan with M2 only (Sec. IV-B: one join per
  * pattern edge, the parallel analogue of tree search). */
@@ -168,8 +170,8 @@ typedef struct {
     int32_t max_degree;
     int32_t has_bitmap;       /* adjacency bitmap built (|V| <= 32768) */
     uint32_t motif_mask;      /* motifs actually built */
-    int64_t motif_rows[DM_NUM_MOTIFS]; /* rows of Res(M) for M2,M3,M4,M5,M6,C4,C6,C12,M4-1,M6-2O
-                                          (0 = absent) */
+    int64_t motif_rows[DM_NUM_MOTIFS]; /* rows of Res(M) for M2,M3,M4,M5,M6,C4,C6,C12,M4-1,M6-2O,
+                                          M18-O-6 (0 = absent) */
     double build_ms;          /* device time of the whole build */
 } dm_datagraph_info;
 
@@ -178,7 +180,8 @@ dm_status dm_datagraph_query(const dm_datagraph* dg, dm_datagraph_info* out);
 dm_status dm_datagraph_copy_csr(const dm_datagraph* dg, int32_t* row_ptr, int32_t* col);
 /* Host copy of a motif table: motif index 0..DM_NUM_MOTIFS-1 as in motif_rows, key
  * position `key_pos` (0 for cycles; 0..ceil(size/2)-1 for paths; 0..1 for M4-1
- * (centre, leaf) and M6-2O (corner, middle)).  Rows are
+ * (centre, leaf) and M6-2O (corner, middle); 0..2 for M18-O-6 (cycle vertex
+ * with pendant, cycle vertex without, pendant)).  Rows are
  * grouped by the key column in ascending key order; columns are in motif
  * position order.  rows and width receive the shape; dst may be NULL to query. */
 dm_status dm_datagraph_copy_motif(const dm_datagraph* dg, int32_t motif, int32_t key_pos,

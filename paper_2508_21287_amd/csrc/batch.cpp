@@ -332,7 +332,10 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     bd.max_backoff = env_int("DMOTIF_BATCH_BACKOFF", 15);
     const double t_stage = ms_since(t0);
     DM_HIP(hipEventRecord(ev[0], s));
-    DM_HIP(launch_batch(bd, block, cmax, grid, s));
+    bool wide = false;
+    for (auto& it : items)
+        for (auto& d : it.steps) wide |= d.motif >= 0 && d.n_new > kNarrowNew;
+    DM_HIP(launch_batch(bd, block, cmax, wide, grid, s));
     DM_HIP(hipEventRecord(ev[1], s));
 
     // ---- readback 1: counts, flags, hashes, failures, heap use, sort jobs

@@ -9,17 +9,19 @@
 
 namespace dm {
 
-constexpr int kMaxMotif = DM_MAX_MOTIF_VERTICES;  // vertices in the largest motif (C12)
+constexpr int kMaxMotif = DM_MAX_MOTIF_VERTICES;  // vertices in the largest motif (M18-O-6)
+constexpr int kNarrowNew = 12;  // new values per step of the join kernels' common instantiation
 constexpr int kMaxCols = DM_MAX_PATTERN_VERTICES; // columns of a partial-embedding table
 constexpr int kMaxEdgeChecks = 24;                // explicit edge checks per join step
 constexpr int kMaxSteps = DM_MAX_PATTERN_VERTICES;
 constexpr int kNumMotifs = DM_NUM_MOTIFS;
-constexpr int kMaxMotifEdges = 8;  // edges of a general-shape motif
+constexpr int kMaxMotifEdges = 18;  // edges of a general-shape motif
 
 // Motif catalogue (Sec. III-A "Motifs": M_i = path of i vertices, -O =
-// cycle; the general shapes of Sec. VI-B: M4-1 = claw, M6-2O = 2x3 grid).
+// cycle; the general shapes of Sec. VI-B: M4-1 = claw, M6-2O = 2x3 grid,
+// M18-O-6 = the heavy-hex cell with a pendant at every other vertex).
 // Index order matches dm_datagraph_info.motif_rows.
-enum MotifIndex { MOT_P2 = 0, MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23 };
+enum MotifIndex { MOT_P2 = 0, MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23, MOT_H18 };
 
 struct MotifInfo {
     int size;
@@ -48,7 +50,13 @@ inline const MotifInfo& motif_info(int m) {
         // claw: centre 0, leaves 1..3 (orbits {0}, {1,2,3})
         {4, false, DM_MOTIF_M4_1, "M4-1", true, 3, {{0, 1}, {0, 2}, {0, 3}}},
         // 2x3 grid: rows 0-1-2 over 3-4-5 (orbits: corners {0,2,3,5}, middles {1,4})
-        {6, false, DM_MOTIF_M6_2O, "M6-2O", true, 7, {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 3}, {1, 4}, {2, 5}}}};
+        {6, false, DM_MOTIF_M6_2O, "M6-2O", true, 7, {{0, 1}, {1, 2}, {3, 4}, {4, 5}, {0, 3}, {1, 4}, {2, 5}}},
+        // heavy-hex cell: cycle 0-1-3-4-...-12-0; pendants 2,13..17 on the even
+        // cycle vertices 0,3,5,7,9,11 (orbits: those {0,..}, the odd ones {1,..},
+        // the pendants {2,..})
+        {18, false, DM_MOTIF_M18_O_6, "M18-O-6", true, 18,
+         {{0, 1}, {1, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {7, 8}, {8, 9}, {9, 10}, {10, 11}, {11, 12}, {12, 0},
+          {0, 2}, {3, 13}, {5, 14}, {7, 15}, {9, 16}, {11, 17}}}};
     return kInfo[m];
 }
 

@@ -223,7 +223,8 @@ hipError_t launch_topk(const uint64_t* cost, int64_t n, int64_t k, TopkCtl* ctl,
 // stays resident) and the launch; max_cols sizes the LDS row tile.
 int batch_block_for(int max_cols, int requested);
 int batch_grid_for(int block, int max_cols, int requested);
-hipError_t launch_batch(const BatchDev& b, int block, int max_cols, int grid, hipStream_t s);
+// wide: some step adds more than kNarrowNew values (the wide instantiation)
+hipError_t launch_batch(const BatchDev& b, int block, int max_cols, bool wide, int grid, hipStream_t s);
 int sort_max_lds_bytes();
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

@@ -130,18 +130,22 @@ struct Bloom {
     }
 };
 
-__device__ __forceinline__ int32_t pick_new(const int32_t (&nv)[kMaxMotif], int t) {
+template <int NV>
+__device__ __forceinline__ int32_t pick_new(const int32_t (&nv)[NV], int t) {
     int32_t r = -1;
 #pragma unroll
-    for (int i = 0; i < kMaxMotif; i++) r = (i == t) ? nv[i] : r;
+    for (int i = 0; i < NV; i++) r = (i == t) ? nv[i] : r;
     return r;
 }
 
 // Does motif row m extend this thread's input row (in LDS at `my`) into a
 // valid partial embedding?  Further join keys, injectivity of the new values
 // against the row, and the step's explicit edge checks.
+// NV: the most new values a step of this instantiation adds (registers per
+// candidate); steps adding more than kNarrowNew values use the wide one.
+template <int NV>
 __device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t* my, const Bloom& bl, int32_t m,
-                                           int32_t (&nv)[kMaxMotif]) {
+                                           int32_t (&nv)[NV]) {
     const StepDesc& st = a.st;
     const int c_in = st.c_in;
     if (st.motif >= 0) {
@@ -150,12 +154,12 @@ __device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t* my, 
         const int64_t ts = a.tbl.stride;
         const int n_new = st.n_new;
 #pragma unroll
-        for (int t = 0; t < kMaxMotif; t++)
+        for (int t = 0; t < NV; t++)
             if (t < n_new) nv[t] = tb[(int64_t)st.new_pos[t] * ts];
         for (int e = 0; e < st.n_eq; e++)
             if (tb[(int64_t)st.eq_pos[e] * ts] != my[st.eq_col[e]]) return false;
 #pragma unroll
-        for (int t = 0; t < kMaxMotif; t++) {
+        for (int t = 0; t < NV; t++) {
             if (t < n_new) {
                 const int32_t x = nv[t];
                 if (bl.maybe(x)) {
@@ -206,7 +210,7 @@ struct TileShared {
 // Row stride (in int32) of the LDS row tile for c columns: odd, >= c.
 __host__ __device__ __forceinline__ int row_stride(int c) { return c | 1; }
 
-template <int BLOCK>
+template <int BLOCK, int NV>
 __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t n_in, int64_t n_tiles,
                                          TileShared<BLOCK>& sh, int32_t* rows, uint64_t& h_cnt, uint64_t& h_sum,
                                          uint64_t& h_xor) {
@@ -256,16 +260,16 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             hi = 1;  // filter-only step: the row itself is the one candidate
         }
     }
-    int32_t nv[kMaxMotif];
+    int32_t nv[NV];
 #pragma unroll
-    for (int t = 0; t < kMaxMotif; t++) nv[t] = -1;
+    for (int t = 0; t < NV; t++) nv[t] = -1;
 
     if (hash) {
         for (int32_t m = lo; m < hi; m++) {
             if (!ejf_accept(a, my, bl, m, nv)) continue;
             uint64_t inner = inner_old;
 #pragma unroll
-            for (int t = 0; t < kMaxMotif; t++)
+            for (int t = 0; t < NV; t++)
                 if (t < st.n_new) inner += mix64(((uint64_t)a.pv[c_in + t] << 32) | (uint32_t)nv[t]);
             const uint64_t h = mix64(inner);
             h_cnt++;
@@ -436,7 +440,7 @@ __device__ __forceinline__ int64_t clamp_rows(int64_t n, int64_t cap) { return n
 
 // One join-filter step over one table: workgroups claim tiles in ticket order
 // until the input is exhausted.  Dynamic LDS: BLOCK * row_stride(c_in) int32.
-template <int BLOCK>
+template <int BLOCK, int NV>
 __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
     extern __shared__ int32_t rows[];
     __shared__ TileShared<BLOCK> sh;
@@ -455,7 +459,7 @@ __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
             if (a.mode == EJF_WRITE && tile == 0 && tid == 0) *a.n_out = 0;
             break;
         }
-        ejf_tile<BLOCK>(a, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
+        ejf_tile<BLOCK, NV>(a, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
     }
     if (a.mode == EJF_HASH) hash_flush<BLOCK>(a.hash_acc, h_cnt, h_sum, h_xor, s_red);
 }
@@ -471,10 +475,18 @@ hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s) {
     const int c = a.st.c_in;
     block = ejf_block_for(c, block);
     const size_t lds = sizeof(int32_t) * (size_t)block * row_stride(c);
-    switch (block) {
-        case 64: hipLaunchKernelGGL((ejf_kernel<64>), dim3(grid), dim3(64), lds, s, a); break;
-        case 128: hipLaunchKernelGGL((ejf_kernel<128>), dim3(grid), dim3(128), lds, s, a); break;
-        default: hipLaunchKernelGGL((ejf_kernel<256>), dim3(grid), dim3(256), lds, s, a); break;
+    if (a.st.n_new > kNarrowNew) {
+        switch (block) {
+            case 64: hipLaunchKernelGGL((ejf_kernel<64, kMaxMotif>), dim3(grid), dim3(64), lds, s, a); break;
+            case 128: hipLaunchKernelGGL((ejf_kernel<128, kMaxMotif>), dim3(grid), dim3(128), lds, s, a); break;
+            default: hipLaunchKernelGGL((ejf_kernel<256, kMaxMotif>), dim3(grid), dim3(256), lds, s, a); break;
+        }
+    } else {
+        switch (block) {
+            case 64: hipLaunchKernelGGL((ejf_kernel<64, kNarrowNew>), dim3(grid), dim3(64), lds, s, a); break;
+            case 128: hipLaunchKernelGGL((ejf_kernel<128, kNarrowNew>), dim3(grid), dim3(128), lds, s, a); break;
+            default: hipLaunchKernelGGL((ejf_kernel<256, kNarrowNew>), dim3(grid), dim3(256), lds, s, a); break;
+        }
     }
     return hipGetLastError();
 }
@@ -500,7 +512,7 @@ __device__ __forceinline__ void st_rel_i32(int32_t* p, int32_t v) {
 
 // One tile = BLOCK rows; wave 0 finds and claims tiles for the workgroup.
 // Dynamic LDS: BLOCK * row_stride(widest input) int32.
-template <int BLOCK>
+template <int BLOCK, int NV>
 __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
     extern __shared__ int32_t rows[];
     __shared__ TileShared<BLOCK> sh;
@@ -590,7 +602,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
         __syncthreads();
         const int64_t n_in = b.ctl[p].n_in[s];
         const int64_t n_tiles = b.ctl[p].ntiles[s];
-        ejf_tile<BLOCK>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
+        ejf_tile<BLOCK, NV>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
         if (sa.mode == EJF_HASH) {
             hash_flush<BLOCK>(sa.hash_acc, hc, hs, hx, s_red);
             hc = hs = hx = 0;
@@ -683,9 +695,9 @@ int batch_grid_for(int block, int max_cols, int requested) {
     int per_cu = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (block) {
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<64>, 64, lds); break;
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<128>, 128, lds); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<256>, 256, lds); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<64, kNarrowNew>, 64, lds); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<128, kNarrowNew>, 128, lds); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<256, kNarrowNew>, 256, lds); break;
     }
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
@@ -701,12 +713,20 @@ int batch_grid_for(int block, int max_cols, int requested) {
     return want < resident ? want : resident;
 }
 
-hipError_t launch_batch(const BatchDev& b, int block, int max_cols, int grid, hipStream_t s) {
+hipError_t launch_batch(const BatchDev& b, int block, int max_cols, bool wide, int grid, hipStream_t s) {
     const size_t lds = sizeof(int32_t) * (size_t)block * row_stride(max_cols);
-    switch (block) {
-        case 64: hipLaunchKernelGGL((batch_kernel<64>), dim3(grid), dim3(64), lds, s, b); break;
-        case 128: hipLaunchKernelGGL((batch_kernel<128>), dim3(grid), dim3(128), lds, s, b); break;
-        default: hipLaunchKernelGGL((batch_kernel<256>), dim3(grid), dim3(256), lds, s, b); break;
+    if (wide) {
+        switch (block) {
+            case 64: hipLaunchKernelGGL((batch_kernel<64, kMaxMotif>), dim3(grid), dim3(64), lds, s, b); break;
+            case 128: hipLaunchKernelGGL((batch_kernel<128, kMaxMotif>), dim3(grid), dim3(128), lds, s, b); break;
+            default: hipLaunchKernelGGL((batch_kernel<256, kMaxMotif>), dim3(grid), dim3(256), lds, s, b); break;
+        }
+    } else {
+        switch (block) {
+            case 64: hipLaunchKernelGGL((batch_kernel<64, kNarrowNew>), dim3(grid), dim3(64), lds, s, b); break;
+            case 128: hipLaunchKernelGGL((batch_kernel<128, kNarrowNew>), dim3(grid), dim3(128), lds, s, b); break;
+            default: hipLaunchKernelGGL((batch_kernel<256, kNarrowNew>), dim3(grid), dim3(256), lds, s, b); break;
+        }
     }
     return hipGetLastError();
 }

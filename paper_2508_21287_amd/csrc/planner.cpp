@@ -15,6 +15,8 @@
 // an explicit adjacency check at the step that places their second endpoint;
 // this is the paper's all-overlap join written as a filter.
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <cmath>
 #include <cstring>
 
@@ -32,35 +34,66 @@ struct GeneralMotif {
     int8_t to_rep[kMaxMotif][kMaxMotif]; // position -> an automorphism taking it to rep
 };
 
+// Automorphisms by backtracking over positions in BFS order (each later
+// position has an earlier neighbour), matching degrees and adjacency to the
+// positions already mapped.
+void motif_automorphisms(int L, const bool (&adj)[kMaxMotif][kMaxMotif], std::vector<std::array<int8_t, kMaxMotif>>* out) {
+    int deg[kMaxMotif] = {};
+    for (int a = 0; a < L; a++)
+        for (int b = 0; b < L; b++) deg[a] += adj[a][b];
+    int ord[kMaxMotif], head = 0, tail = 0;
+    bool seen[kMaxMotif] = {};
+    ord[tail++] = 0;
+    seen[0] = true;
+    while (head < tail) {
+        const int x = ord[head++];
+        for (int y = 0; y < L; y++)
+            if (adj[x][y] && !seen[y]) {
+                seen[y] = true;
+                ord[tail++] = y;
+            }
+    }
+    std::array<int8_t, kMaxMotif> img{};
+    bool used[kMaxMotif] = {};
+    std::function<void(int)> go = [&](int d) {
+        if (d == L) {
+            out->push_back(img);
+            return;
+        }
+        const int x = ord[d];
+        for (int w = 0; w < L; w++) {
+            if (used[w] || deg[w] != deg[x]) continue;
+            bool ok = true;
+            for (int e = 0; e < d && ok; e++) ok = adj[x][ord[e]] == adj[w][img[ord[e]]];
+            if (!ok) continue;
+            img[x] = (int8_t)w;
+            used[w] = true;
+            go(d + 1);
+            used[w] = false;
+        }
+    };
+    go(0);
+}
+
 GeneralMotif compute_general(int m) {
     const MotifInfo& mi = motif_info(m);
     const int L = mi.size;
     bool adj[kMaxMotif][kMaxMotif] = {};
     for (int e = 0; e < mi.n_edges; e++) adj[mi.edges[e][0]][mi.edges[e][1]] = adj[mi.edges[e][1]][mi.edges[e][0]] = true;
+    std::vector<std::array<int8_t, kMaxMotif>> auts;
+    motif_automorphisms(L, adj, &auts);
     GeneralMotif g;
-    int perm[kMaxMotif];
     for (int i = 0; i < L; i++) {
-        perm[i] = i;
         g.rep[i] = (int8_t)i;
-        for (int j = 0; j < L; j++) g.to_rep[i][j] = (int8_t)j;
+        for (int j = 0; j < L; j++) g.to_rep[i][j] = (int8_t)j;  // the identity
     }
-    bool have[kMaxMotif] = {};
-    do {
-        bool ok = true;
-        for (int a = 0; a < L && ok; a++)
-            for (int b = 0; b < L && ok; b++)
-                if (adj[a][b] != adj[perm[a]][perm[b]]) ok = false;
-        if (!ok) continue;
-        for (int i = 0; i < L; i++) {
-            const int j = perm[i];
-            // the smallest position reachable from i is its representative
-            if (j < g.rep[i] || (j == g.rep[i] && !have[i])) {
-                g.rep[i] = (int8_t)j;
-                have[i] = true;
-                for (int q = 0; q < L; q++) g.to_rep[i][q] = (int8_t)perm[q];
+    // the representative of i is the smallest position an automorphism takes it to
+    for (auto& a : auts)
+        for (int i = 0; i < L; i++)
+            if (a[i] < g.rep[i]) {
+                g.rep[i] = a[i];
+                for (int q = 0; q < L; q++) g.to_rep[i][q] = a[q];
             }
-        }
-    } while (std::next_permutation(perm, perm + L));
     int reps = 0;
     for (int i = 0; i < L; i++) reps += g.rep[i] == i;
     g.orbits = reps;

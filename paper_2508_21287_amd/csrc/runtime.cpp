@@ -1045,7 +1045,7 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
                 want = claws <= 5e7 ? DM_MOTIF_M4_1 : (DM_MOTIF_M3 | DM_MOTIF_M4);
             }
         }
-        const int order[] = {MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23};
+        const int order[] = {MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23, MOT_H18};
         for (int m : order) {
             if (st != DM_OK) break;
             if (!(want & motif_info(m).bit) || ((dg->motif_bits >> m) & 1)) continue;

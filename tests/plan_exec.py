@@ -14,7 +14,12 @@ import oracle
 from paper_2508_21287_amd import workloads as W
 
 MOTIF_SHAPES = {0: ("path", 2), 1: ("path", 3), 2: ("path", 4), 3: ("path", 5), 4: ("path", 6),
-                5: ("cycle", 4), 6: ("cycle", 6), 7: ("cycle", 12), 8: ("claw", 4), 9: ("grid2x3", 6)}
+                5: ("cycle", 4), 6: ("cycle", 6), 7: ("cycle", 12), 8: ("claw", 4), 9: ("grid2x3", 6),
+                10: ("cell18", 18)}
+
+# heavy-hex cell with pendants: cycle 0-1-3-4-...-12-0, pendants 2,13..17 on 0,3,5,7,9,11
+CELL18_EDGES = [[0, 1], [1, 3], [3, 4], [4, 5], [5, 6], [6, 7], [7, 8], [8, 9], [9, 10], [10, 11], [11, 12],
+                [12, 0], [0, 2], [3, 13], [5, 14], [7, 15], [9, 16], [11, 17]]
 
 
 def motif_pattern(m):
@@ -25,6 +30,8 @@ def motif_pattern(m):
         return W.cycle(size)
     if kind == "claw":  # centre 0, leaves 1..3
         return W.star(3)
+    if kind == "cell18":
+        return W.Pattern(18, CELL18_EDGES, "M18-O-6")
     # 2x3 grid: 0-1-2 over 3-4-5
     return W.Pattern(6, [[0, 1], [1, 2], [3, 4], [4, 5], [0, 3], [1, 4], [2, 5]], "2x3")
 

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+import plan_exec
 import paper_2508_21287_amd as dm
 from paper_2508_21287_amd import workloads as W
 
@@ -78,8 +79,9 @@ def test_ingest_errors(ctx):
 
 MOTIF_PATTERNS = {0: W.path(2), 1: W.path(3), 2: W.path(4), 3: W.path(5), 4: W.path(6), 5: W.cycle(4),
                   6: W.cycle(6), 7: W.cycle(12), 8: W.star(3),
-                  9: W.Pattern(6, [[0, 1], [1, 2], [3, 4], [4, 5], [0, 3], [1, 4], [2, 5]], "2x3")}
-MOTIF_KEY_POSITIONS = {0: 1, 1: 2, 2: 2, 3: 3, 4: 3, 5: 1, 6: 1, 7: 1, 8: 2, 9: 2}
+                  9: W.Pattern(6, [[0, 1], [1, 2], [3, 4], [4, 5], [0, 3], [1, 4], [2, 5]], "2x3"),
+                  10: W.Pattern(18, plan_exec.CELL18_EDGES, "M18-O-6")}
+MOTIF_KEY_POSITIONS = {0: 1, 1: 2, 2: 2, 3: 3, 4: 3, 5: 1, 6: 1, 7: 1, 8: 2, 9: 2, 10: 3}
 
 
 @pytest.mark.parametrize("gname", ["HH(3,9)", "HH(7,19)", "GRID(6,7)"])
@@ -144,7 +146,7 @@ def test_random_graphs(ctx):
     for s in range(4):
         g = W.random_gnp(60, 0.08 + 0.04 * s, 100 + s)
         # every motif but the 12-cycle, whose 12-path table is astronomically large here
-        dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_ALL & ~dm.MOTIF_C12)
+        dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_ALL & ~(dm.MOTIF_C12 | dm.MOTIF_M18_O_6))
         for p in pats:
             check_enum(dg, g, p)
         dg.free()
@@ -457,7 +459,7 @@ def test_induced_variant(ctx):
             P(4, [[0, 1], [1, 2], [2, 3], [3, 0], [0, 2]], "diamond"), W.prufer_tree(6, 0), W.path(7)]
     graphs = [W.heavy_hex(3, 9), W.grid(6, 7), W.random_gnp(24, 0.3, 5), W.random_gnp(40, 0.12, 9)]
     for g in graphs:
-        dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_ALL & ~dm.MOTIF_C12)
+        dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_ALL & ~(dm.MOTIF_C12 | dm.MOTIF_M18_O_6))
         for p in pats:
             say(f"induced {g.name} {p.name}")
             want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, induced=True)
@@ -488,7 +490,7 @@ def test_motif_db_save_load(ctx, tmp_path):
     # index) and answers like the original; several databases stay resident
     # on one context; damaged or foreign files are refused
     graphs = [W.heavy_hex(7, 19), W.grid(12, 13), W.random_gnp(30, 0.2, 4)]
-    masks = [dm.MOTIF_AUTO, dm.MOTIF_ALL & ~dm.MOTIF_C12, dm.MOTIF_M3 | dm.MOTIF_C4]
+    masks = [dm.MOTIF_AUTO, dm.MOTIF_ALL & ~(dm.MOTIF_C12 | dm.MOTIF_M18_O_6), dm.MOTIF_M3 | dm.MOTIF_C4]
     loaded = []
     for i, (g, mask) in enumerate(zip(graphs, masks)):
         say(f"db case {g.name}")
@@ -603,3 +605,21 @@ def test_autotune_motifs(ctx):
     dg.free()
     with pytest.raises(dm.DMError):
         ctx.autotune_motifs(g.n, g.edges, [], cands)
+
+
+def test_cell_motif_wide_steps(ctx):
+    # M18-O-6 adds up to 17 columns in one step: the wide join instantiation,
+    # plain and batched, against the oracle
+    g = W.heavy_hex(7, 19)
+    dg = ctx.datagraph(g.n, g.edges, dm.MOTIF_M18_O_6 | dm.MOTIF_C12 | dm.MOTIF_M4_1)
+    cell = W.Pattern(18, plan_exec.CELL18_EDGES, "M18-O-6")
+    two = W.heavy_hex(3, 9)  # three cells side by side
+    pats = [cell, W.Pattern(two.n, two.edges, "HH(3,9)"), W.cycle(12), W.path(7)]
+    for p in pats:
+        check_enum(dg, g, p, motif_mask=dm.MOTIF_M18_O_6 | dm.MOTIF_C12 | dm.MOTIF_M4_1)
+    res = dg.enumerate_batch([(p.n, p.edges) for p in pats])
+    for p, r in zip(pats, res):
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+        assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
+        r.free()
+    dg.free()
