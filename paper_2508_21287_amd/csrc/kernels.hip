@@ -210,7 +210,9 @@ struct TileShared {
 // Row stride (in int32) of the LDS row tile for c columns: odd, >= c.
 __host__ __device__ __forceinline__ int row_stride(int c) { return c | 1; }
 
-template <int BLOCK, int NV>
+// SCORE: the layout-cost column is carried (scored runs only; the batched
+// form never scores, so its instantiation carries no cost code).
+template <int BLOCK, int NV, bool SCORE>
 __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t n_in, int64_t n_tiles,
                                          TileShared<BLOCK>& sh, int32_t* rows, uint64_t& h_cnt, uint64_t& h_sum,
                                          uint64_t& h_xor) {
@@ -364,7 +366,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
                         if (t0 + j < n_new) dst[(int64_t)(c_in + t0 + j) * os] = w4[j];
                 }
             }
-            if (a.out_cost) {
+            if (SCORE && a.out_cost) {
                 // layout cost: the parent's plus the new vertices' and the new edges'
                 uint64_t cst = a.in ? a.in_cost[tile * BLOCK + sh.src[o]] : (uint64_t)a.vcost[prow[0]];
                 for (int t = 0; t < n_new; t++) {
@@ -440,7 +442,7 @@ __device__ __forceinline__ int64_t clamp_rows(int64_t n, int64_t cap) { return n
 
 // One join-filter step over one table: workgroups claim tiles in ticket order
 // until the input is exhausted.  Dynamic LDS: BLOCK * row_stride(c_in) int32.
-template <int BLOCK, int NV>
+template <int BLOCK, int NV, bool SCORE>
 __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
     extern __shared__ int32_t rows[];
     __shared__ TileShared<BLOCK> sh;
@@ -459,7 +461,7 @@ __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
             if (a.mode == EJF_WRITE && tile == 0 && tid == 0) *a.n_out = 0;
             break;
         }
-        ejf_tile<BLOCK, NV>(a, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
+        ejf_tile<BLOCK, NV, SCORE>(a, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
     }
     if (a.mode == EJF_HASH) hash_flush<BLOCK>(a.hash_acc, h_cnt, h_sum, h_xor, s_red);
 }
@@ -475,19 +477,24 @@ hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s) {
     const int c = a.st.c_in;
     block = ejf_block_for(c, block);
     const size_t lds = sizeof(int32_t) * (size_t)block * row_stride(c);
-    if (a.st.n_new > kNarrowNew) {
-        switch (block) {
-            case 64: hipLaunchKernelGGL((ejf_kernel<64, kMaxMotif>), dim3(grid), dim3(64), lds, s, a); break;
-            case 128: hipLaunchKernelGGL((ejf_kernel<128, kMaxMotif>), dim3(grid), dim3(128), lds, s, a); break;
-            default: hipLaunchKernelGGL((ejf_kernel<256, kMaxMotif>), dim3(grid), dim3(256), lds, s, a); break;
-        }
-    } else {
-        switch (block) {
-            case 64: hipLaunchKernelGGL((ejf_kernel<64, kNarrowNew>), dim3(grid), dim3(64), lds, s, a); break;
-            case 128: hipLaunchKernelGGL((ejf_kernel<128, kNarrowNew>), dim3(grid), dim3(128), lds, s, a); break;
-            default: hipLaunchKernelGGL((ejf_kernel<256, kNarrowNew>), dim3(grid), dim3(256), lds, s, a); break;
-        }
+    // instantiations: wide (more than kNarrowNew new values) or narrow, scored or not
+#define DM_EJF_LAUNCH(NV, SC)                                                                      \
+    switch (block) {                                                                               \
+        case 64: hipLaunchKernelGGL((ejf_kernel<64, NV, SC>), dim3(grid), dim3(64), lds, s, a); break;    \
+        case 128: hipLaunchKernelGGL((ejf_kernel<128, NV, SC>), dim3(grid), dim3(128), lds, s, a); break; \
+        default: hipLaunchKernelGGL((ejf_kernel<256, NV, SC>), dim3(grid), dim3(256), lds, s, a); break;  \
     }
+    const bool wide = a.st.n_new > kNarrowNew, scored = a.out_cost != nullptr;
+    if (wide && scored) {
+        DM_EJF_LAUNCH(kMaxMotif, true)
+    } else if (wide) {
+        DM_EJF_LAUNCH(kMaxMotif, false)
+    } else if (scored) {
+        DM_EJF_LAUNCH(kNarrowNew, true)
+    } else {
+        DM_EJF_LAUNCH(kNarrowNew, false)
+    }
+#undef DM_EJF_LAUNCH
     return hipGetLastError();
 }
 
@@ -602,7 +609,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
         __syncthreads();
         const int64_t n_in = b.ctl[p].n_in[s];
         const int64_t n_tiles = b.ctl[p].ntiles[s];
-        ejf_tile<BLOCK, NV>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
+        ejf_tile<BLOCK, NV, false>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
         if (sa.mode == EJF_HASH) {
             hash_flush<BLOCK>(sa.hash_acc, hc, hs, hx, s_red);
             hc = hs = hx = 0;
