@@ -209,7 +209,8 @@ constexpr uint32_t kEpochs = 1u << kEpochBits;
 // wide rows take smaller tiles so the LDS row tile stays small
 int ejf_block_for(int c_in, int requested);
 hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s);
-hipError_t launch_sort_lds(const SortLaunch& a, int grid, int lds_bytes, hipStream_t s);
+// threads: workgroup size, a multiple of 64 up to 1024
+hipError_t launch_sort_lds(const SortLaunch& a, int grid, int threads, int lds_bytes, hipStream_t s);
 // chunk sort + `passes` merge launches + row write for the segments in a.list
 hipError_t launch_sort_merge_tier(const SortLaunch& a, int passes, hipStream_t s);
 // The k (<= kTopkMax, <= n) rows of `table` (row-major, n x width) with the

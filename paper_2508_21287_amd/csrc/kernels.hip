@@ -19,6 +19,12 @@ __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
 __device__ __forceinline__ void st_relaxed(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Output-table store, coherent at agent scope: the value goes through to the
+// point every XCD reads from instead of sitting dirty in this XCD's L2, so the
+// tile's release fence has no table lines left to write back.
+__device__ __forceinline__ void st_out(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Look-back word: [epoch:14 | flag:2 | value:48]; flag 1 = tile aggregate,
 // 2 = inclusive prefix.  A word from another epoch reads as "not ready".
@@ -110,24 +116,49 @@ __device__ __forceinline__ uint32_t edge_cost(const GraphDev& g, const uint32_t*
 //
 // One tile = BLOCK consecutive input rows, one row per thread.  The row's
 // values are staged in LDS (odd row stride, so lanes reading different rows
-// hit different banks); a 128-bit Bloom summary of the row in registers lets
-// most injectivity tests skip the row scan.  Candidates come from the motif
+// hit different banks); a 128- or 256-bit summary of the row's values in
+// registers settles most injectivity tests without the row scan.  On graphs
+// with no more vertices than the summary has bits it is the exact vertex set
+// (bit = vertex id), so a hit means a repeat and no test scans the row.  Candidates come from the motif
 // table's direct-address index; survivors are counted, the tile's output
 // offset comes from the look-back chain, and rows are written in input order
 // with coalesced column stores.
 
-__device__ __forceinline__ uint32_t bloom_bit(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> 25; }
-
+// NW (2 or 4) 64-bit words, kept as named members so they stay in
+// registers; bit of x = the top log2(64 NW) bits of x * mul.  EXACT: on
+// graphs of at most 64 NW vertices mul = 2^(32 - log2(64 NW)), so bit = x.
+template <int NW, bool EXACT>
 struct Bloom {
-    uint64_t lo, hi;
+    static constexpr int kLogBits = NW == 4 ? 8 : 7;
+    static constexpr uint32_t kHashMul = 0x9E3779B1u;
+    uint64_t w0, w1, w2, w3;
+    uint32_t mul;
+    bool exact;
+    __device__ __forceinline__ void init(int32_t n_vertices) {
+        w0 = w1 = w2 = w3 = 0;
+        exact = EXACT && n_vertices <= 64 * NW;
+        mul = exact ? (1u << (32 - kLogBits)) : kHashMul;
+    }
+    __device__ __forceinline__ uint32_t bit(int32_t x) const {
+        return ((uint32_t)x * (EXACT ? mul : kHashMul)) >> (32 - kLogBits);
+    }
     __device__ __forceinline__ void add(int32_t x) {
-        const uint32_t b = bloom_bit(x);
-        if (b < 64) lo |= 1ull << b; else hi |= 1ull << (b - 64);
+        const uint32_t b = bit(x), q = b >> 6;
+        const uint64_t m = 1ull << (b & 63);
+        w0 |= q == 0 ? m : 0ull;
+        w1 |= q == 1 ? m : 0ull;
+        if (NW == 4) {
+            w2 |= q == 2 ? m : 0ull;
+            w3 |= q == 3 ? m : 0ull;
+        }
     }
     __device__ __forceinline__ bool maybe(int32_t x) const {
-        const uint32_t b = bloom_bit(x);
-        return ((b < 64 ? lo : hi) >> (b & 63)) & 1ull;
+        const uint32_t b = bit(x), q = b >> 6;
+        uint64_t v = q == 0 ? w0 : w1;
+        if (NW == 4) v = q == 2 ? w2 : (q == 3 ? w3 : v);
+        return (v >> (b & 63)) & 1ull;
     }
+    __device__ __forceinline__ bool is_exact() const { return EXACT && exact; }
 };
 
 template <int NV>
@@ -143,8 +174,10 @@ __device__ __forceinline__ int32_t pick_new(const int32_t (&nv)[NV], int t) {
 // against the row, and the step's explicit edge checks.
 // NV: the most new values a step of this instantiation adds (registers per
 // candidate); steps adding more than kNarrowNew values use the wide one.
-template <int NV>
-__device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t* my, const Bloom& bl, int32_t m,
+// NEQ: further join keys loaded together with the new values (the rest are
+// loaded and tested one at a time).
+template <int NV, int NEQ, class BL>
+__device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t* my, const BL& bl, int32_t m,
                                            int32_t (&nv)[NV]) {
     const StepDesc& st = a.st;
     const int c_in = st.c_in;
@@ -152,17 +185,25 @@ __device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t* my, 
         // issue every load of this candidate before the first compare
         const int32_t* tb = a.tbl.base + m;
         const int64_t ts = a.tbl.stride;
-        const int n_new = st.n_new;
+        const int n_new = st.n_new, n_eq = st.n_eq;
+        int32_t ev[NEQ > 0 ? NEQ : 1];
+#pragma unroll
+        for (int e = 0; e < NEQ; e++)
+            if (e < n_eq) ev[e] = tb[(int64_t)st.eq_pos[e] * ts];
 #pragma unroll
         for (int t = 0; t < NV; t++)
             if (t < n_new) nv[t] = tb[(int64_t)st.new_pos[t] * ts];
-        for (int e = 0; e < st.n_eq; e++)
+#pragma unroll
+        for (int e = 0; e < NEQ; e++)
+            if (e < n_eq && ev[e] != my[st.eq_col[e]]) return false;
+        for (int e = NEQ; e < n_eq; e++)
             if (tb[(int64_t)st.eq_pos[e] * ts] != my[st.eq_col[e]]) return false;
 #pragma unroll
         for (int t = 0; t < NV; t++) {
             if (t < n_new) {
                 const int32_t x = nv[t];
                 if (bl.maybe(x)) {
+                    if (bl.is_exact()) return false;
                     for (int c = 0; c < c_in; c++)
                         if (my[c] == x) return false;
                 }
@@ -212,7 +253,12 @@ __host__ __device__ __forceinline__ int row_stride(int c) { return c | 1; }
 
 // SCORE: the layout-cost column is carried (scored runs only; the batched
 // form never scores, so its instantiation carries no cost code).
-template <int BLOCK, int NV, bool SCORE>
+// LAT: the latency-bound persistent form.  Its tiles hand tables to other
+// XCDs through a release per tile, so outputs are stored coherently at agent
+// scope (nothing dirty left in L2 for the release to write back), and its
+// summary is 256 bits wide (exact up to 256 vertices).  The per-launch form
+// is throughput-bound on large tables: plain stores, 128 bits.
+template <int BLOCK, int NV, bool SCORE, bool LAT>
 __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t n_in, int64_t n_tiles,
                                          TileShared<BLOCK>& sh, int32_t* rows, uint64_t& h_cnt, uint64_t& h_sum,
                                          uint64_t& h_xor) {
@@ -224,24 +270,27 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
     const int64_t row = tile * BLOCK + tid;
     const bool valid = row < n_in;
     int32_t* my = rows + tid * RS;
-    Bloom bl{0ull, 0ull};
+    Bloom<LAT ? 4 : 2, LAT> bl;
+    bl.init(a.g.n);
+    constexpr int NEQ = LAT ? 4 : 0;
+    constexpr int RCH = LAT ? 16 : 8;  // input columns loaded per round
     uint64_t inner_old = 0;
     const bool hash = a.mode == EJF_HASH;
     if (valid) {
         if (a.in) {
             const int32_t* src = a.in + row;
             const int64_t is = a.in_stride;
-            for (int c0 = 0; c0 < c_in; c0 += 8) {
-                int32_t t8[8];
+            for (int c0 = 0; c0 < c_in; c0 += RCH) {
+                int32_t tv[RCH];
 #pragma unroll
-                for (int j = 0; j < 8; j++)
-                    if (c0 + j < c_in) t8[j] = src[(int64_t)(c0 + j) * is];
+                for (int j = 0; j < RCH; j++)
+                    if (c0 + j < c_in) tv[j] = src[(int64_t)(c0 + j) * is];
 #pragma unroll
-                for (int j = 0; j < 8; j++) {
+                for (int j = 0; j < RCH; j++) {
                     if (c0 + j < c_in) {
-                        my[c0 + j] = t8[j];
-                        bl.add(t8[j]);
-                        if (hash) inner_old += mix64(((uint64_t)a.pv[c0 + j] << 32) | (uint32_t)t8[j]);
+                        my[c0 + j] = tv[j];
+                        bl.add(tv[j]);
+                        if (hash) inner_old += mix64(((uint64_t)a.pv[c0 + j] << 32) | (uint32_t)tv[j]);
                     }
                 }
             }
@@ -268,7 +317,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
 
     if (hash) {
         for (int32_t m = lo; m < hi; m++) {
-            if (!ejf_accept(a, my, bl, m, nv)) continue;
+            if (!ejf_accept<NV, NEQ>(a, my, bl, m, nv)) continue;
             uint64_t inner = inner_old;
 #pragma unroll
             for (int t = 0; t < NV; t++)
@@ -283,10 +332,34 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
 
     uint64_t mask = 0;
     int32_t cnt = 0;
-    for (int32_t m = lo; m < hi; m++) {
-        if (ejf_accept(a, my, bl, m, nv)) {
-            if (m - lo < 64) mask |= 1ull << (m - lo);
-            cnt++;
+    if (LAT && st.motif >= 0 && st.n_eq > 0) {
+        // Most candidates fail the first further join key: test it for eight
+        // candidates per round of loads, then run the full test on the rest.
+        const int32_t* kcol = a.tbl.base + (int64_t)st.eq_pos[0] * a.tbl.stride;
+        const int32_t want = my[st.eq_col[0]];
+        for (int32_t m0 = lo; m0 < hi; m0 += 8) {
+            int32_t k8[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) k8[j] = (m0 + j < hi) ? kcol[m0 + j] : ~want;
+            uint32_t pm = 0;
+#pragma unroll
+            for (int j = 0; j < 8; j++) pm |= (uint32_t)(k8[j] == want) << j;
+            while (pm) {
+                const int j = __ffs((int)pm) - 1;
+                pm &= pm - 1;
+                const int32_t m = m0 + j;
+                if (ejf_accept<NV, NEQ>(a, my, bl, m, nv)) {
+                    if (m - lo < 64) mask |= 1ull << (m - lo);
+                    cnt++;
+                }
+            }
+        }
+    } else {
+        for (int32_t m = lo; m < hi; m++) {
+            if (ejf_accept<NV, NEQ>(a, my, bl, m, nv)) {
+                if (m - lo < 64) mask |= 1ull << (m - lo);
+                cnt++;
+            }
         }
     }
     // block-wide exclusive scan of per-row survivor counts
@@ -336,7 +409,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             const int32_t li = local0 + r_cur;
             if (li >= w0 + CH) break;  // belongs to a later pass
             const int32_t m = m_cur++;
-            const bool ok = (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : ejf_accept(a, my, bl, m, nv);
+            const bool ok = (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : ejf_accept<NV, NEQ>(a, my, bl, m, nv);
             if (!ok) continue;
             sh.src[li - w0] = (uint8_t)tid;
             sh.mrow[li - w0] = m;
@@ -352,7 +425,10 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             const int32_t m = sh.mrow[o];
             int32_t* dst = a.out + orow;
             const int64_t os = a.out_stride;
-            for (int c = 0; c < c_in; c++) dst[(int64_t)c * os] = prow[c];
+            for (int c = 0; c < c_in; c++) {
+                if (LAT) st_out(dst + (int64_t)c * os, prow[c]);
+                else dst[(int64_t)c * os] = prow[c];
+            }
             const int32_t* tb = a.tbl.base + m;
             const int64_t ts = a.tbl.stride;
             if (n_new > 0) {
@@ -363,7 +439,10 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
                         if (t0 + j < n_new) w4[j] = tb[(int64_t)st.new_pos[t0 + j] * ts];
 #pragma unroll
                     for (int j = 0; j < 4; j++)
-                        if (t0 + j < n_new) dst[(int64_t)(c_in + t0 + j) * os] = w4[j];
+                        if (t0 + j < n_new) {
+                            if (LAT) st_out(dst + (int64_t)(c_in + t0 + j) * os, w4[j]);
+                            else dst[(int64_t)(c_in + t0 + j) * os] = w4[j];
+                        }
                 }
             }
             if (SCORE && a.out_cost) {
@@ -461,7 +540,7 @@ __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
             if (a.mode == EJF_WRITE && tile == 0 && tid == 0) *a.n_out = 0;
             break;
         }
-        ejf_tile<BLOCK, NV, SCORE>(a, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
+        ejf_tile<BLOCK, NV, SCORE, false>(a, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
     }
     if (a.mode == EJF_HASH) hash_flush<BLOCK>(a.hash_acc, h_cnt, h_sum, h_xor, s_red);
 }
@@ -525,7 +604,8 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
     __shared__ TileShared<BLOCK> sh;
     __shared__ EjfArgs sa;
     __shared__ uint64_t s_red[3][BLOCK / 64];
-    __shared__ int32_t s_claim[4];  // pattern, step, tile, all done
+    __shared__ int32_t s_claim[5];  // pattern, step, tile, all done, tiles of the step
+    __shared__ int64_t s_nin;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int N = b.n_patterns;
     int rot = (int)((blockIdx.x * 7919u) % (unsigned)(N > 0 ? N : 1));
@@ -537,7 +617,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
     for (;;) {
         // ---- find a claimable tile (wave 0 scans 64 patterns at a time)
         if (wid == 0) {
-            int32_t p = -1, s = -1, tile = -1;
+            int32_t p = -1, s = -1, tile = -1, ntiles = 0;
             bool all_done = false;
             for (;;) {
                 bool got = false;
@@ -570,6 +650,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
                             p = qq;
                             s = ss;
                             tile = t;
+                            ntiles = ntl;
                             got = true;
                             break;
                         }
@@ -590,12 +671,14 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
                 s_claim[1] = s;
                 s_claim[2] = tile;
                 s_claim[3] = all_done ? 1 : 0;
+                s_claim[4] = ntiles;
             }
         }
         __syncthreads();
         const int32_t p = s_claim[0], s = s_claim[1];
         const int64_t tile = s_claim[2];
         const bool all_done = s_claim[3] != 0;
+        const int64_t n_tiles = s_claim[4];
         __syncthreads();  // s_claim is rewritten by the next scan
         if (all_done) break;
         rot = (p + 1) % N;
@@ -605,11 +688,11 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
             const int32_t* src = (const int32_t*)&b.args[b.first[p] + s];
             int32_t* dst = (int32_t*)&sa;
             for (int i = tid; i < (int)(sizeof(EjfArgs) / 4); i += BLOCK) dst[i] = src[i];
+            if (tid == 0) s_nin = b.ctl[p].n_in[s];  // written before the step was published
         }
         __syncthreads();
-        const int64_t n_in = b.ctl[p].n_in[s];
-        const int64_t n_tiles = b.ctl[p].ntiles[s];
-        ejf_tile<BLOCK, NV, false>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
+        const int64_t n_in = s_nin;
+        ejf_tile<BLOCK, NV, false, true>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
         if (sa.mode == EJF_HASH) {
             hash_flush<BLOCK>(sa.hash_acc, hc, hs, hx, s_red);
             hc = hs = hx = 0;
@@ -772,24 +855,33 @@ __device__ __forceinline__ bool lds_row_less(const uint64_t* rows, int wp, uint3
 
 constexpr uint16_t kSent16 = 0xFFFFu;
 
-// First index of the ascending a[0, n) whose value is >= v, found by one
-// full wave: each round probes 64 evenly spaced positions of the interval
-// that still holds the answer, so a search takes ~log64(n) dependent loads.
-__device__ int64_t wave_lower_bound(const int32_t* a, int64_t n, int32_t v, int lane) {
-    int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+// The run of value v in the ascending a[0, n), found by one full wave: lanes
+// 0-31 look for the first element >= v, lanes 32-63 for the first > v.  Each
+// round a half probes 32 evenly spaced positions of the interval that still
+// holds its answer, so both ends take ~log32(n) dependent loads together.
+__device__ void wave_equal_range(const int32_t* a, int64_t n, int32_t v, int lane, int64_t* first, int64_t* end) {
+    const int half = lane >> 5, hl = lane & 31;
+    const int32_t t = half ? v + 1 : v;  // v < INT32_MAX: vertex ids
+    int64_t lo = 0, hi = n;              // this half's answer lies in [lo, hi]
     while (lo < hi) {
-        const int64_t step = (hi - lo + 63) / 64;
-        int64_t p = lo + (int64_t)(lane + 1) * step - 1;
+        const int64_t step = (hi - lo + 31) / 32;
+        int64_t p = lo + (int64_t)(hl + 1) * step - 1;
         if (p > hi - 1) p = hi - 1;
-        const uint64_t m = __ballot(a[p] >= v);
-        if (m == 0) return hi;
-        const int f = __ffsll((long long)m) - 1;
+        const uint32_t m = (uint32_t)(__ballot(a[p] >= t) >> (32 * half));
+        if (m == 0) {
+            lo = hi;
+            break;
+        }
+        const int f = __ffs((int)m) - 1;
         int64_t pf = lo + (int64_t)(f + 1) * step - 1;
         if (pf > hi - 1) pf = hi - 1;
         lo = f == 0 ? lo : lo + (int64_t)f * step;  // one past the probe of lane f - 1
         hi = pf;
     }
-    return lo;
+    if (hl == 0) {
+        if (half) *end = lo;
+        else *first = lo;
+    }
 }
 
 // Sort the n packed rows staged in LDS with a bitonic network over 16-bit
@@ -798,11 +890,11 @@ __device__ void lds_bitonic(const uint64_t* rows, uint16_t* idx, int n, int wp) 
     const int tid = threadIdx.x;
     int P = 1;
     while (P < n) P <<= 1;
-    for (int i = tid; i < P; i += kSortBlock) idx[i] = i < n ? (uint16_t)i : kSent16;
+    for (int i = tid; i < P; i += (int)blockDim.x) idx[i] = i < n ? (uint16_t)i : kSent16;
     __syncthreads();
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = tid; t < (P >> 1); t += kSortBlock) {
+            for (int t = tid; t < (P >> 1); t += (int)blockDim.x) {
                 const int lo = 2 * t - (t & (stride - 1));
                 const int hi = lo + stride;
                 const bool asc = (lo & size) == 0;
@@ -822,18 +914,36 @@ __device__ void lds_bitonic(const uint64_t* rows, uint16_t* idx, int n, int wp) 
 }
 
 // Stage rows [r0, r0 + n) of a final table into LDS as packed rows
-// (columns 1..k-1 in pattern-vertex order; coalesced column reads).
+// (columns 1..k-1 in pattern-vertex order).  Work is dealt by element,
+// column-major so neighbouring lanes read neighbouring rows of one column;
+// each thread issues four independent loads before OR-ing the values into
+// the zeroed words, so a row's columns are fetched in parallel, not in turn.
 __device__ __forceinline__ void lds_stage_rows(const SortJob& job, int64_t r0, int n, uint64_t* rows) {
     const int k = job.k, wp = job.wp, bits = job.bits, cpw = job.cpw;
-    for (int r = threadIdx.x; r < n; r += kSortBlock) {
-        for (int w = 0; w < wp; w++) {
-            uint64_t word = 0;
-            for (int c = 0; c < cpw; c++) {
-                const int j = 1 + w * cpw + c;
-                const uint64_t v = j < k ? (uint64_t)(uint32_t)job.in[(int64_t)job.perm[j] * job.in_stride + r0 + r] : 0;
-                word |= v << ((cpw - 1 - c) * bits);
+    const int nt = (int)blockDim.x;
+    for (int i = threadIdx.x; i < n * wp; i += nt) rows[i] = 0;
+    __syncthreads();
+    const int total = n * (k - 1);
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * nt) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = e0 + u * nt;
+            v[u] = 0;
+            if (e < total) {
+                const int j = 1 + e / n, r = e - (j - 1) * n;
+                v[u] = (uint32_t)job.in[(int64_t)job.perm[j] * job.in_stride + r0 + r];
             }
-            rows[(size_t)r * wp + w] = word;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = e0 + u * nt;
+            if (e < total) {
+                const int j = 1 + e / n, r = e - (j - 1) * n;
+                const int q = (j - 1) / cpw, c = (j - 1) - q * cpw;
+                atomicOr((unsigned long long*)&rows[(size_t)r * wp + q],
+                         (unsigned long long)v[u] << ((cpw - 1 - c) * bits));
+            }
         }
     }
     __syncthreads();
@@ -869,7 +979,7 @@ __device__ __forceinline__ int glb_row_cmp(const SortJob& a, int64_t seg0, uint3
 // LDS tiers: one workgroup per root segment.  Without an input list the items
 // are every (job, root vertex) pair and the segment is found by search;
 // segments larger than this tier's LDS tile are passed on.
-__global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L) {
+__global__ __launch_bounds__(1024) void sort_lds_kernel(const SortLaunch L) {
     extern __shared__ uint64_t lds[];
     __shared__ SortJob job;
     __shared__ int64_t s_seg[2];
@@ -881,7 +991,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
         {
             const int32_t* src = (const int32_t*)&L.jobs[jb];
             int32_t* dst = (int32_t*)&job;
-            for (int i = tid; i < (int)(sizeof(SortJob) / 4); i += kSortBlock) dst[i] = src[i];
+            for (int i = tid; i < (int)(sizeof(SortJob) / 4); i += (int)blockDim.x) dst[i] = src[i];
         }
         __syncthreads();
         if (L.list) {
@@ -892,15 +1002,10 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
         } else if (tid < 64) {
             const int32_t v = L.v_begin + (int32_t)(item - jb * L.n_vertices);
             const int64_t n = clamp_rows(*job.n_in, job.in_cap);
-            const int64_t a = wave_lower_bound(job.in, n, v, tid);
-            const int64_t b = wave_lower_bound(job.in, n, v + 1, tid);
-            if (tid == 0) {
-                s_seg[0] = a;
-                s_seg[1] = b - a;
-            }
+            wave_equal_range(job.in, n, v, tid, &s_seg[0], &s_seg[1]);
         }
         __syncthreads();
-        const int64_t seg0 = s_seg[0], len = s_seg[1];
+        const int64_t seg0 = s_seg[0], len = L.list ? s_seg[1] : s_seg[1] - s_seg[0];
         const int k = job.k, wp = job.wp;
         const int64_t out_rows = job.out_rows;
         const int cap_rows = lds_rows_of(L.lds_bytes, wp);
@@ -911,17 +1016,17 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
                 // a large segment the joins left in order needs no sort at all:
                 // check it in the table and write it out directly
                 int uns = 0;
-                for (int64_t r = tid + 1; r < len; r += kSortBlock) uns |= glb_row_cmp(job, seg0, r - 1, r) >= 0;
+                for (int64_t r = tid + 1; r < len; r += (int)blockDim.x) uns |= glb_row_cmp(job, seg0, r - 1, r) >= 0;
                 if (!__syncthreads_or(uns)) {
                     const int64_t nw = (seg0 + len <= out_rows) ? len : (out_rows - seg0);
                     int32_t* dst = job.out + seg0 * k;
-                    for (int64_t e = tid; e < nw * k; e += kSortBlock) {
+                    for (int64_t e = tid; e < nw * k; e += (int)blockDim.x) {
                         const int64_t r = e / k;
                         const int j = (int)(e - r * k);
                         dst[e] = job.in[(int64_t)job.perm[j] * job.in_stride + seg0 + r];
                     }
                     if (job.out_cost)
-                        for (int64_t r = tid; r < nw; r += kSortBlock) job.out_cost[seg0 + r] = job.in_cost[seg0 + r];
+                        for (int64_t r = tid; r < nw; r += (int)blockDim.x) job.out_cost[seg0 + r] = job.in_cost[seg0 + r];
                     __syncthreads();
                     continue;
                 }
@@ -935,26 +1040,26 @@ __global__ __launch_bounds__(kSortBlock) void sort_lds_kernel(const SortLaunch L
         const int32_t root = job.in[(int64_t)job.perm[0] * job.in_stride + seg0];
         lds_stage_rows(job, seg0, n, rows);
         int uns = 0;
-        for (int r = tid + 1; r < n; r += kSortBlock) uns |= !lds_row_less(rows, wp, r - 1, r);
+        for (int r = tid + 1; r < n; r += (int)blockDim.x) uns |= !lds_row_less(rows, wp, r - 1, r);
         if (__syncthreads_or(uns)) {
             lds_bitonic(rows, idx, n, wp);
-            for (int r = tid + 1; r < n; r += kSortBlock)
+            for (int r = tid + 1; r < n; r += (int)blockDim.x)
                 if (!lds_row_less(rows, wp, idx[r - 1], idx[r])) atomicAdd(L.dup_count, 1);
         } else {
             // already in order (strictly, so free of duplicates)
-            for (int r = tid; r < n; r += kSortBlock) idx[r] = (uint16_t)r;
+            for (int r = tid; r < n; r += (int)blockDim.x) idx[r] = (uint16_t)r;
             __syncthreads();
         }
         const int64_t nw = (seg0 + n <= out_rows) ? n : (out_rows - seg0);
         const int64_t total = nw * k;
         int32_t* dst = job.out + seg0 * k;
-        for (int64_t e = tid; e < total; e += kSortBlock) {
+        for (int64_t e = tid; e < total; e += (int)blockDim.x) {
             const int64_t r = e / k;
             const int j = (int)(e - r * k);
             dst[e] = j == 0 ? root : lds_unpack(rows, job, idx[r], j);
         }
         if (job.out_cost)
-            for (int64_t r = tid; r < nw; r += kSortBlock) job.out_cost[seg0 + r] = job.in_cost[seg0 + idx[r]];
+            for (int64_t r = tid; r < nw; r += (int)blockDim.x) job.out_cost[seg0 + r] = job.in_cost[seg0 + idx[r]];
         __syncthreads();
     }
 }
@@ -983,7 +1088,7 @@ __device__ __forceinline__ int64_t first_unit(int64_t i) {
     return ((int64_t)blockIdx.x + G - (i % G)) % G;
 }
 
-__global__ __launch_bounds__(kSortBlock) void sort_chunk_kernel(const SortLaunch L) {
+__global__ __launch_bounds__(1024) void sort_chunk_kernel(const SortLaunch L) {
     extern __shared__ uint64_t lds[];
     const int tid = threadIdx.x;
     const int64_t n_list = *L.list_n;
@@ -1002,14 +1107,14 @@ __global__ __launch_bounds__(kSortBlock) void sort_chunk_kernel(const SortLaunch
             const int n = (int)((ref.len - r0 < R) ? (ref.len - r0) : R);
             lds_stage_rows(job, ref.seg0 + r0, n, rows);
             int uns = 0;
-            for (int r = tid + 1; r < n; r += kSortBlock) uns |= !lds_row_less(rows, wp, r - 1, r);
+            for (int r = tid + 1; r < n; r += (int)blockDim.x) uns |= !lds_row_less(rows, wp, r - 1, r);
             if (__syncthreads_or(uns)) {
                 lds_bitonic(rows, idx, n, wp);
             } else {
-                for (int r = tid; r < n; r += kSortBlock) idx[r] = (uint16_t)r;
+                for (int r = tid; r < n; r += (int)blockDim.x) idx[r] = (uint16_t)r;
                 __syncthreads();
             }
-            for (int r = tid; r < n; r += kSortBlock) run[r0 + r] = (uint32_t)(r0 + idx[r]);
+            for (int r = tid; r < n; r += (int)blockDim.x) run[r0 + r] = (uint32_t)(r0 + idx[r]);
             __syncthreads();
         }
     }
@@ -1257,13 +1362,14 @@ int sort_max_lds_bytes() {
     return cached;
 }
 
-hipError_t launch_sort_lds(const SortLaunch& a, int grid, int lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL(sort_lds_kernel, dim3(grid), dim3(kSortBlock), lds_bytes, s, a);
+hipError_t launch_sort_lds(const SortLaunch& a, int grid, int threads, int lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(sort_lds_kernel, dim3(grid), dim3(threads), lds_bytes, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_sort_merge_tier(const SortLaunch& a, int passes, hipStream_t s) {
-    hipLaunchKernelGGL(sort_chunk_kernel, dim3(256), dim3(kSortBlock), a.lds_bytes, s, a);
+    // one 160 KB tile per CU: 1024 threads share each network
+    hipLaunchKernelGGL(sort_chunk_kernel, dim3(256), dim3(1024), a.lds_bytes, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     SortLaunch m = a;

@@ -212,14 +212,15 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.list = nullptr;
     L.spill = ws.spill;
     L.spill_n = &counters[0];
-    DM_HIP(launch_sort_lds(L, (int)std::min<int64_t>(std::max<int64_t>(items, 1), 8192), L.lds_bytes, s));
-    // tier 2: the largest LDS allocation a workgroup can hold
+    DM_HIP(launch_sort_lds(L, (int)std::min<int64_t>(std::max<int64_t>(items, 1), 8192), 256, L.lds_bytes, s));
+    // tier 2: the largest LDS allocation a workgroup can hold; one such
+    // workgroup fills a CU, so it takes the largest block
     L.lds_bytes = ctx->sort_lds_max;
     L.list = ws.spill;
     L.list_n = &counters[0];
     L.spill = ws.spill + ws.spill_cap;
     L.spill_n = &counters[1];
-    DM_HIP(launch_sort_lds(L, 256, L.lds_bytes, s));
+    DM_HIP(launch_sort_lds(L, 256, 1024, L.lds_bytes, s));
     // tier 3: chunks of the tier-2 tile, merged pairwise
     L.list = ws.spill + ws.spill_cap;
     L.list_n = &counters[1];
