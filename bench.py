@@ -72,6 +72,13 @@ def parse():
                     help="instead of the benchmark line, time random lattice-subgraph patterns under each "
                          "motif set (with and without building the motif tables) and count the join "
                          "iterations, one JSON line per (topology, motif set)")
+    ap.add_argument("--served-sweep", action="store_true",
+                    help="instead of the benchmark line, replay Poisson traces of circuit patterns on HH(56,56) "
+                         "at 100..5000 queries/s through the server and one at a time, one JSON line per rate")
+    ap.add_argument("--queries", type=int, default=500, help="served sweep: queries per rate")
+    ap.add_argument("--batched-config4", action="store_true",
+                    help="instead of the benchmark line, time 256 circuit patterns on HH(28,28) as one "
+                         "batched call vs 256 plain calls")
     ap.add_argument("--pattern-size", type=int, default=60, help="motif-set study: heavy-hex pattern vertices")
     ap.add_argument("--grid-pattern-size", type=int, default=16,
                     help="motif-set study: grid pattern vertices (tree-like grid subgraphs explode beyond ~20)")
@@ -99,23 +106,35 @@ def cpu_baseline(g, pats, budget_s=10.0):
             "sample": f"all 64 patterns x {reps} repetitions ({el:.1f} s), count+hash mode, 1 thread"}
 
 
-def serve_trace(dm, ctx, g, pats, rate=4000.0, n_queries=512, seed=4000):
-    """Open-loop Poisson trace of the benchmark patterns through the server
-    (continuous batching, 2 streams) vs the same trace solved one query at a
-    time with plain per-pattern runs (FIFO, no overlap).  Latency = completion
-    - arrival."""
+def wait_until(t0, t):
+    """Wait until perf_counter() - t0 reaches t: sleep (which lets the other
+    Python threads run) and spin only the last 100 us."""
+    while True:
+        dt = t - (time.perf_counter() - t0)
+        if dt <= 0:
+            return
+        if dt > 2e-4:
+            time.sleep(dt - 1e-4)
+
+
+def replay(dm, dg, arrivals, pats, caps, mem_budget=0):
+    """Open-loop replay of one trace: through the server (continuous batching,
+    2 streams) and, on the same queries, one plain solve at a time (FIFO, no
+    overlap).  Latency = completion - arrival, also for a query the library
+    refuses (over its memory budget: counted as rejected).  Returns
+    ``(server_latencies, server_seconds, server_rejected, plain_latencies,
+    plain_seconds, plain_rejected, rows)``; rows = rows delivered by the
+    server."""
+    import threading
     import numpy as np
-    rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_queries))
-    order = rng.integers(0, len(pats), size=n_queries)
-    caps = rng.choice(np.array([1, 1000, -1]), size=n_queries)
-    dg = dm.DataGraph(ctx, g.n, g.edges)
+    n_queries = len(pats)
+    budget_code = -6  # DM_ERR_BUDGET_EXCEEDED
 
     def run_server():
-        srv = dm.Server(dg, n_streams=2, max_batch=64)
-        import threading
+        srv = dm.Server(dg, n_streams=2, max_batch=64, mem_budget=mem_budget)
         done = {}
         tickets = []
+        state = {"rejected": 0, "rows": 0}
         t0 = time.perf_counter()
 
         def waiter():
@@ -133,49 +152,131 @@ def serve_trace(dm, ctx, g, pats, rate=4000.0, n_queries=512, seed=4000):
                     except dm.DMError as e:
                         if e.code == -10:  # not finished yet
                             continue
-                        raise
+                        if e.code != budget_code:
+                            raise
+                        state["rejected"] += 1
+                        r = None
                     done[i] = time.perf_counter() - t0
-                    r.free()
+                    if r is not None:
+                        state["rows"] += r.rows
+                        r.free()
                     pending.discard(i)
                 time.sleep(0.0001)
 
         th = threading.Thread(target=waiter)
         th.start()
         for i in range(n_queries):
-            while time.perf_counter() - t0 < arrivals[i]:
-                pass
-            p = pats[order[i]]
+            wait_until(t0, arrivals[i])
+            p = pats[i]
             tickets.append(srv.submit(p.n, p.edges, int(caps[i])))
         th.join()
         el = time.perf_counter() - t0
         srv.stop()
         lat = np.array([done[i] - arrivals[i] for i in range(n_queries)])
-        return lat, el
+        return lat, el, state["rejected"], state["rows"]
 
     def run_plain():
+        # the server runs each query within its budget: so do the plain solves
+        opts = {"mem_budget": mem_budget, "result_mb": mem_budget >> 20} if mem_budget else {}
         t0 = time.perf_counter()
         fin = []
+        rejected = 0
         for i in range(n_queries):
-            now = time.perf_counter() - t0
-            if now < arrivals[i]:
-                while time.perf_counter() - t0 < arrivals[i]:
-                    pass
-            p = pats[order[i]]
-            r = dg.enumerate(p.n, p.edges, int(caps[i]))
-            r.free()
+            wait_until(t0, arrivals[i])
+            p = pats[i]
+            try:
+                dg.enumerate(p.n, p.edges, int(caps[i]), **opts).free()
+            except dm.DMError as e:
+                if e.code != budget_code:
+                    raise
+                rejected += 1
             fin.append(time.perf_counter() - t0)
         el = time.perf_counter() - t0
-        return np.array(fin) - arrivals, el
+        return np.array(fin) - arrivals, el, rejected
 
-    run_server()  # warm-up
-    lat_s, el_s = run_server()
-    lat_p, el_p = run_plain()
+    lat_s, el_s, rej_s, rows = run_server()
+    lat_p, el_p, rej_p = run_plain()
+    return lat_s, el_s, rej_s, lat_p, el_p, rej_p, rows
+
+
+def serve_trace(dm, ctx, g, pats, rate=4000.0, n_queries=512, seed=4000):
+    """Poisson trace of the benchmark patterns (caps drawn from {1, 1000,
+    all}) through the server vs the same trace solved one query at a time."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_queries))
+    order = rng.integers(0, len(pats), size=n_queries)
+    caps = rng.choice(np.array([1, 1000, -1]), size=n_queries)
+    dg = dm.DataGraph(ctx, g.n, g.edges)
+    qp = [pats[i] for i in order]
+    replay(dm, dg, arrivals, qp, caps)  # warm-up
+    lat_s, el_s, _, lat_p, el_p, _, _ = replay(dm, dg, arrivals, qp, caps)
     dg.free()
     return {"trace": f"{n_queries} queries, Poisson {rate:.0f}/s, caps {{1,1000,all}}, same 64 patterns",
             "p50_ms": 1e3 * float(np.percentile(lat_s, 50)), "p99_ms": 1e3 * float(np.percentile(lat_s, 99)),
             "qps": n_queries / el_s,
             "plain_p50_ms": 1e3 * float(np.percentile(lat_p, 50)),
             "plain_p99_ms": 1e3 * float(np.percentile(lat_p, 99)), "plain_qps": n_queries / el_p}
+
+
+def batched_config4(dm, W, ctx, reps=5):
+    """256 circuit patterns (4-40 qubits) on HH(28,28): one batched call (the
+    persistent join launch for all patterns, then the sort tiers) vs 256
+    plain calls on the same stream; full tables.  One JSON line."""
+    import numpy as np
+    import torch
+    g, pats = W.config4(256)
+    specs = [(p.n, p.edges) for p in pats]
+    dg = dm.DataGraph(ctx, g.n, g.edges)
+    rows = 0
+    for _ in range(2):
+        res = dg.enumerate_batch(specs)
+        rows = sum(r.rows for r in res)
+        for r in res:
+            r.free()
+    tb, tp = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in dg.enumerate_batch(specs):
+            r.free()
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        for p in pats:
+            dg.enumerate(p.n, p.edges).free()
+        torch.cuda.synchronize()
+        tp.append(time.perf_counter() - t0)
+    b, q = float(np.median(tb)), float(np.median(tp))
+    print(json.dumps({"batched": "HH(28,28) x 256 circuit patterns 4-40 qubits", "rows": int(rows),
+                      "batch_ms": 1e3 * b, "plain_ms": 1e3 * q, "batch_embeddings_per_s": rows / b,
+                      "plain_embeddings_per_s": rows / q, "batched_over_plain": q / b}), flush=True)
+    dg.free()
+
+
+def served_sweep(dm, W, ctx, n_queries):
+    """Served workload on HH(56,56): at each arrival rate, an open-loop trace of
+    circuit patterns (4-60 qubits, caps {1, 1000, all}) through the server vs
+    plain solves; each query runs within the server's default 8 GiB budget
+    (a result beyond it is refused).  One JSON line per rate."""
+    import numpy as np
+    budget = 8 << 30
+    dg = None
+    for rate in (100, 300, 1000, 3000, 5000):
+        g, arrivals, pats, caps = W.config5(float(rate), n_queries=n_queries)
+        if dg is None:
+            dg = dm.DataGraph(ctx, g.n, g.edges)
+            w_arr = np.arange(8) * 1e-3
+            replay(dm, dg, w_arr, pats[:8], caps[:8], budget)  # warm-up
+        lat_s, el_s, rej_s, lat_p, el_p, rej_p, rows = replay(dm, dg, arrivals, pats, caps, budget)
+        print(json.dumps({"served": "HH(56,56) circuit patterns 4-60 qubits", "rate_per_s": rate,
+                          "queries": n_queries, "rows": int(rows), "rejected_over_budget": rej_s,
+                          "p50_ms": 1e3 * float(np.percentile(lat_s, 50)),
+                          "p99_ms": 1e3 * float(np.percentile(lat_s, 99)), "qps": n_queries / el_s,
+                          "plain_p50_ms": 1e3 * float(np.percentile(lat_p, 50)),
+                          "plain_p99_ms": 1e3 * float(np.percentile(lat_p, 99)), "plain_qps": n_queries / el_p,
+                          "plain_rejected_over_budget": rej_p}), flush=True)
+    dg.free()
 
 
 def sweep(dm, W, ctx, reps=3):
@@ -296,6 +397,12 @@ def main():
         return
     if args.motif_sets:
         motif_sets(dm, W, ctx, args.pattern_size, args.grid_pattern_size, args.patterns)
+        return
+    if args.served_sweep:
+        served_sweep(dm, W, ctx, args.queries)
+        return
+    if args.batched_config4:
+        batched_config4(dm, W, ctx)
         return
 
     def step(profile: bool):

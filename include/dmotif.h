@@ -116,7 +116,7 @@ typedef struct {
     int32_t block_threads; /* join-kernel workgroup size (64, 128, 256); 0 = auto */
     int32_t output_mode;   /* dm_output_mode */
     int32_t sync_each_step;/* 1: read each step's row count back (exact sizing) */
-    int64_t mem_budget;    /* bytes for intermediate tables; 0 = library default */
+    int64_t mem_budget;    /* bytes for intermediate tables; 0 = library default (48 GiB) */
     int32_t profile;       /* 1: time every join and sort launch with HIP events (see dm_run_stats) */
     int32_t induced;       /* 1: induced embeddings (the definition of Sec. III-A read as "if and only
                               if"): additionally every pair of non-adjacent pattern vertices maps to
@@ -133,7 +133,11 @@ typedef struct {
                               order (k <= 8192, else DM_ERR_UNSUPPORTED); with no cap, every row in
                               lexicographic order with its cost.  Table mode only (the count+hash
                               mode ignores it); batches run scored patterns one by one. */
-    int32_t reserved_;
+    int32_t result_mb;     /* the most the kept rows may take, in MiB (rows x pattern vertices x 4
+                              bytes); beyond it the call fails with DM_ERR_BUDGET_EXCEEDED as soon
+                              as the rows produced so far pass it.  0 = no limit but device memory:
+                              a result assembled from root-range parts needs its bytes twice (the
+                              parts, then the one result buffer) next to mem_budget of tables. */
 } dm_plan_opts;
 
 typedef struct dm_context dm_context;
@@ -255,7 +259,8 @@ dm_status dm_estimate(dm_datagraph* dg, const dm_graph_desc* gp, const dm_plan_o
 /* Algorithm 1: all embeddings of `gp` in the data graph.  max_embeddings < 0
  * = all; otherwise the lexicographically first max_embeddings rows.  opts may
  * be NULL (defaults).  Errors: pattern validation codes, DM_ERR_OUT_OF_MEMORY,
- * DM_ERR_BUDGET_EXCEEDED (one root vertex alone exceeds mem_budget),
+ * DM_ERR_BUDGET_EXCEEDED (one root vertex alone exceeds mem_budget, or the kept
+ * rows exceed result_mb, or with result_mb = 0 what device memory can hold),
  * DM_ERR_DEVICE, DM_ERR_INTERNAL (a duplicate row reached the output). */
 dm_status dm_enumerate(dm_datagraph* dg, const dm_graph_desc* gp, int64_t max_embeddings,
                        const dm_plan_opts* opts, dm_result** out);
@@ -308,14 +313,18 @@ typedef struct {
 dm_status dm_result_stats(const dm_result* r, dm_run_stats* out);
 void dm_result_free(dm_result* r);
 
-/* Served form: a request loop that keeps the data graph resident, admits
- * queries by predicted intermediate-table memory, and runs admitted queries
- * in continuous batches on several streams so that their work overlaps on
- * the device. */
+/* Served form: a request loop that keeps the data graph resident, groups
+ * queued queries into batches by predicted intermediate-table memory (a
+ * query predicted to need more than an eighth of the budget runs alone), and
+ * runs the batches continuously on several streams so that their work
+ * overlaps on the device. */
 typedef struct {
     int32_t n_streams;       /* concurrent batches in flight (default 2) */
     int32_t max_batch;       /* patterns per batch launch (default 64) */
-    int64_t mem_budget;      /* bytes of predicted intermediates in flight (default 8 GiB) */
+    int64_t mem_budget;      /* bytes of predicted tables per batch, and each query's own
+                                mem_budget and result_mb (default 8 GiB): a query whose result
+                                exceeds it fails with DM_ERR_BUDGET_EXCEEDED.  The server holds
+                                at most n_streams x mem_budget of tables. */
     int32_t max_queue;       /* pending requests before submit returns DM_ERR_BUSY (default 65536) */
 } dm_server_opts;
 

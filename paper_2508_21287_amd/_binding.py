@@ -58,7 +58,7 @@ class PlanOpts(C.Structure):
     _fields_ = [("motif_mask", C.c_uint32), ("block_threads", C.c_int32), ("output_mode", C.c_int32),
                 ("sync_each_step", C.c_int32), ("mem_budget", C.c_int64), ("profile", C.c_int32),
                 ("induced", C.c_int32), ("initial_rows", C.c_int64), ("root_begin", C.c_int32),
-                ("root_end", C.c_int32), ("score", C.c_int32), ("reserved_", C.c_int32)]
+                ("root_end", C.c_int32), ("score", C.c_int32), ("result_mb", C.c_int32)]
 
 
 class DataGraphInfo(C.Structure):
@@ -177,11 +177,12 @@ class _Graph:
 
 
 def _opts(motif_mask=0, block=0, mode=OUT_TABLE, sync_each_step=False, mem_budget=0,
-          profile=False, initial_rows=0, root_range=None, induced=False, score=False) -> PlanOpts:
+          profile=False, initial_rows=0, root_range=None, induced=False, score=False,
+          result_mb=0) -> PlanOpts:
     rb, re = (0, 0) if root_range is None else (int(root_range[0]), int(root_range[1]))
     return PlanOpts(int(motif_mask) & 0xFFFFFFFF, int(block), int(mode), int(bool(sync_each_step)),
                     int(mem_budget), int(bool(profile)), int(bool(induced)), int(initial_rows), rb, re,
-                    int(bool(score)), 0)
+                    int(bool(score)), int(result_mb))
 
 
 def _torch_stream(device: int):

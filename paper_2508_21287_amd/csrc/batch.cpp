@@ -406,6 +406,9 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             continue;
         }
         it.out_rows = it.cap >= 0 ? std::min<int64_t>(it.cap, n_final[p]) : n_final[p];
+        if (opts && opts->result_mb > 0 && it.out_rows * 4 * (int64_t)it.k > ((int64_t)opts->result_mb << 20))
+            return fail(DM_ERR_BUDGET_EXCEEDED, "pattern " + std::to_string(it.idx) + ": result of " +
+                                                    std::to_string(it.out_rows) + " rows exceeds result_mb");
         it.off_res = resb;
         resb = align256(resb + sizeof(int32_t) * (size_t)std::max<int64_t>(it.out_rows * it.k, 1));
         max_rows = std::max(max_rows, n_final[p]);
@@ -752,16 +755,18 @@ struct dm_server {
     std::deque<std::shared_ptr<Request>> queue;
     std::unordered_map<uint64_t, std::shared_ptr<Request>> live;
     uint64_t next_ticket = 1;
-    int64_t inflight_bytes = 0;
     int32_t inflight = 0;
     bool stopping = false;
 };
 
-// Each worker owns one stream + workspace.  It takes every admissible
-// request at the head of the queue (up to max_batch, within the memory
-// budget of predicted intermediate tables) and runs them as one batch; while
-// that batch is on the GPU, the other workers admit newly arrived requests
-// and run them on their own streams, so batches overlap on the device.
+// Each worker owns one stream + workspace.  It takes the requests at the head
+// of the queue (up to max_batch, their predicted tables within the memory
+// budget) and runs them as one batch; while that batch is on the GPU, the
+// other workers take newly arrived requests and run them on their own
+// streams, so batches overlap on the device.  A request predicted to need
+// more than an eighth of the budget runs as a batch of its own, so short
+// queries never wait inside a long one's batch.  Every query runs within the
+// budget, so the server holds at most n_streams x mem_budget of tables.
 static void server_worker(dm_server* s, int w) {
     (void)hipSetDevice(s->dg->ctx->device);
     Workspace& ws = *s->ws[w];
@@ -771,22 +776,17 @@ static void server_worker(dm_server* s, int w) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
             if (s->queue.empty() && s->stopping) return;
+            int64_t batch_bytes = 0;
             while (!s->queue.empty() && (int32_t)batch.size() < s->opts.max_batch) {
                 auto& r = s->queue.front();
-                if (!batch.empty() || s->inflight > 0) {
-                    if (s->inflight_bytes + r->est_bytes > s->opts.mem_budget) break;
-                }
-                s->inflight_bytes += r->est_bytes;
+                const bool large = r->est_bytes > s->opts.mem_budget / 8;
+                if (!batch.empty() && (large || batch_bytes + r->est_bytes > s->opts.mem_budget)) break;
+                batch_bytes += r->est_bytes;
                 s->inflight++;
                 batch.push_back(r);
                 s->queue.pop_front();
+                if (large) break;
             }
-        }
-        if (batch.empty()) {
-            // budget full: wait for another batch to finish
-            std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_done.wait_for(lk, std::chrono::milliseconds(5));
-            continue;
         }
         std::vector<dm_graph_desc> gps;
         std::vector<int64_t> caps;
@@ -795,13 +795,19 @@ static void server_worker(dm_server* s, int w) {
             caps.push_back(r->cap);
         }
         std::vector<dm_result*> outs(batch.size(), nullptr);
-        dm_status st = enumerate_many(s->dg, ws, (int32_t)batch.size(), gps.data(), caps.data(), nullptr,
+        // each query runs within the server's memory budget
+        dm_plan_opts run_opts;
+        std::memset(&run_opts, 0, sizeof run_opts);
+        run_opts.output_mode = DM_OUT_TABLE;
+        run_opts.mem_budget = s->opts.mem_budget;
+        run_opts.result_mb = (int32_t)std::min<int64_t>(std::max<int64_t>(s->opts.mem_budget >> 20, 1), INT32_MAX);
+        dm_status st = enumerate_many(s->dg, ws, (int32_t)batch.size(), gps.data(), caps.data(), &run_opts,
                                       outs.data());
         std::string err = st == DM_OK ? std::string() : std::string(dm_last_error());
         if (st != DM_OK && batch.size() > 1) {
             // isolate the failing request(s): run them one by one
             for (size_t i = 0; i < batch.size(); i++) {
-                dm_status si = enumerate_many(s->dg, ws, 1, &gps[i], &caps[i], nullptr, &outs[i]);
+                dm_status si = enumerate_many(s->dg, ws, 1, &gps[i], &caps[i], &run_opts, &outs[i]);
                 std::lock_guard<std::mutex> lk(s->mu);
                 batch[i]->status = si;
                 batch[i]->err = si == DM_OK ? std::string() : std::string(dm_last_error());
@@ -824,7 +830,6 @@ static void server_worker(dm_server* s, int w) {
                 r->result = r->status == DM_OK ? outs[i] : nullptr;
                 if (r->status != DM_OK && outs[i]) dm_result_free(outs[i]);
                 r->done = true;
-                s->inflight_bytes -= r->est_bytes;
                 s->inflight--;
             }
         }
@@ -884,8 +889,21 @@ dm_status dm_server_submit(dm_server* s, const dm_graph_desc* gp, int64_t max_em
     r->nv = gp->n_vertices;
     r->edges.assign(gp->edges, gp->edges + 2 * gp->n_edges);
     r->cap = max_embeddings;
+    // Predicted table bytes.  A capped query is run over the root prefix that
+    // should hold 8 x cap rows (as the batch does), so it is predicted over
+    // that share of the roots; no query is predicted beyond the budget it
+    // runs within.
     int64_t peak = 0, rows = 0;
-    if (dm_estimate(s->dg, gp, nullptr, &peak, &rows) == DM_OK) r->est_bytes = std::max<int64_t>(peak, 1);
+    if (dm_estimate(s->dg, gp, nullptr, &peak, &rows) == DM_OK) {
+        double est = (double)peak;
+        const int32_t nv = std::max(s->dg->n, 1);
+        if (max_embeddings >= 0 && rows > 0) {
+            const double per_root = (double)rows / nv;
+            const double roots = (8.0 * (double)max_embeddings + 256.0) / per_root;
+            est *= std::min(1.0, std::max(roots, 64.0) / nv);
+        }
+        r->est_bytes = (int64_t)std::max(1.0, std::min(est, (double)s->opts.mem_budget));
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) return fail(DM_ERR_CANCELLED, "server is stopping");
     if ((int32_t)s->queue.size() >= s->opts.max_queue) return fail(DM_ERR_BUSY, "server queue is full");

@@ -567,6 +567,14 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
     int64_t got = 0;
     bool early = false;
     int splits = 0;
+    // Result size: the caller's limit, checked as the parts come in.  Without
+    // one, the parts and then the one buffer they are joined into take the
+    // result's bytes twice; the workspace tables are allocated by then, so from
+    // the second part on the kept rows may take 45 % of the free device memory
+    // plus what the parts already hold (a tenth kept for the parts' sorts).
+    // Either way an oversized result fails early, not at the final allocation.
+    const int64_t row_bytes = 4 * (int64_t)std::max(plan.k, 1);
+    int64_t max_result_rows = opt.result_limit > 0 ? std::max<int64_t>(opt.result_limit / row_bytes, 1) : -1;
     while (!todo.empty()) {
         auto rg = todo.back();
         todo.pop_back();
@@ -592,6 +600,21 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
         }
         parts.push_back(part);
         got += hash_mode ? part.rows : part.sorted_rows;
+        if (!hash_mode) {
+            if (max_result_rows < 0 && parts.size() >= 2) {
+                size_t fr = 0, tot = 0;
+                int64_t held = 0;
+                for (auto& q : parts) held += q.sorted_rows * row_bytes;
+                if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+                    max_result_rows = std::max<int64_t>((int64_t)(0.45 * (double)((int64_t)fr + held)) / row_bytes, 1);
+            }
+            const int64_t kept = opt.cap >= 0 ? std::min<int64_t>(got, opt.cap) : got;
+            if (max_result_rows >= 0 && kept > max_result_rows) {
+                free_parts();
+                return fail(DM_ERR_BUDGET_EXCEEDED, "result of more than " + std::to_string(max_result_rows) +
+                                                        " rows exceeds the memory it may take");
+            }
+        }
         if (opt.cap >= 0 && !hash_mode && got >= opt.cap && !todo.empty()) {
             early = true;
             break;
@@ -1386,6 +1409,7 @@ RunOptions run_options(const dm_plan_opts* opts, int64_t cap) {
         o.root_end = opts->root_end;
         o.induced = opts->induced != 0;
         o.score = opts->score != 0;
+        o.result_limit = opts->result_mb > 0 ? (int64_t)opts->result_mb << 20 : 0;
     }
     o.cap = cap;
     return o;

@@ -166,6 +166,7 @@ struct RunOptions {
     int32_t root_end = 0;      // empty range = every data vertex
     bool induced = false;      // pattern non-edges must map to data non-edges
     bool score = false;        // layout costs per row; with cap >= 0 the cap best rows by (cost, row)
+    int64_t result_limit = 0;  // bytes the kept rows may take (0 = what device memory holds)
 };
 
 // Output of one plan execution on one workspace.

@@ -623,3 +623,77 @@ def test_cell_motif_wide_steps(ctx):
         assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
         r.free()
     dg.free()
+
+
+def test_result_limit(ctx):
+    # result_mb bounds the kept rows (rows x k x 4 bytes) on every path: a
+    # plain call, a batch and a served query fail with DM_ERR_BUDGET_EXCEEDED
+    # once their rows pass it, a cap below it is served, and the failure
+    # leaves the other queries of a server untouched
+    g, pats = W.config2()
+    p = pats[29]  # 29 vertices, 43 656 rows: 5.1 MB
+    small = W.path(3)
+    dg = ctx.datagraph(g.n, g.edges)
+    want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+    assert total * p.n * 4 > (1 << 20)
+    say("case plain result_mb=1")
+    with pytest.raises(dm.DMError) as ei:
+        dg.enumerate(p.n, p.edges, result_mb=1)
+    assert ei.value.code == -6
+    say("case plain result_mb=1 cap=1000")
+    with dg.enumerate(p.n, p.edges, 1000, result_mb=1) as r:
+        assert np.array_equal(r.to_numpy(), want[:1000])
+    say("case plain root-range parts, result_mb=1")
+    with pytest.raises(dm.DMError) as ei:
+        dg.enumerate(p.n, p.edges, mem_budget=1 << 20, result_mb=1)
+    assert ei.value.code == -6
+    say("case batch result_mb=1")
+    with pytest.raises(dm.DMError) as ei:
+        dg.enumerate_batch([(small.n, small.edges), (p.n, p.edges)], result_mb=1)
+    assert ei.value.code == -6
+    say("case batch result_mb=8")
+    res = dg.enumerate_batch([(small.n, small.edges), (p.n, p.edges)], result_mb=8)
+    assert np.array_equal(res[1].to_numpy(), want)
+    for r in res:
+        r.free()
+    say("case server mem_budget=4 MiB")
+    srv = dm.Server(dg, n_streams=2, max_batch=4, mem_budget=4 << 20)
+    t_big = srv.submit(p.n, p.edges)
+    t_cap = srv.submit(p.n, p.edges, 100)
+    t_small = srv.submit(small.n, small.edges)
+    with pytest.raises(dm.DMError) as ei:
+        srv.wait(t_big, 60000)
+    assert ei.value.code == -6
+    r = srv.wait(t_cap, 60000)
+    assert np.array_equal(r.to_numpy(), want[:100])
+    r.free()
+    r = srv.wait(t_small, 60000)
+    want_s, _ = oracle.enumerate_embeddings(g.n, g.edges, small.n, small.edges)
+    assert np.array_equal(r.to_numpy(), want_s)
+    r.free()
+    srv.stop()
+    dg.free()
+
+
+def test_served_config5_sample(ctx):
+    # the served workload: HH(56,56) and an open-loop trace of circuit
+    # patterns with caps {1, 1000, all}; every query of up to 30 qubits (the
+    # oracle's share of the trace) through the server, checked against the
+    # oracle's table or its lexicographic prefix
+    g, arrivals, pats, caps = W.config5(300.0, n_queries=40)
+    dg = ctx.datagraph(g.n, g.edges)
+    srv = dm.Server(dg, n_streams=2, max_batch=16)
+    sel = [i for i, p in enumerate(pats) if p.n <= 30]
+    assert len(sel) >= 20
+    tickets = [srv.submit(pats[i].n, pats[i].edges, int(caps[i])) for i in sel]
+    for i, t in zip(sel, tickets):
+        p, cap = pats[i], int(caps[i])
+        say(f"case config5 query={i} k={p.n} cap={cap}")
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges, cap=cap)
+        r = srv.wait(t, 120000)
+        assert np.array_equal(r.to_numpy(), want), (i, p.n, cap)
+        if cap < 0:
+            assert r.total == total
+        r.free()
+    srv.stop()
+    dg.free()
