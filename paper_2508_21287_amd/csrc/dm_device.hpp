@@ -241,7 +241,8 @@ hipError_t launch_ingest_count(const int32_t* edges, int64_t m, int32_t n, int32
                                hipStream_t s);
 hipError_t launch_scan_i32(const int32_t* in, int32_t* out_excl, int64_t n, int64_t* total,
                            uint64_t* status, uint64_t* ticket, hipStream_t s);
-hipError_t launch_ingest_scatter(const int32_t* edges, int64_t m, const int32_t* ptr, int32_t* cursor,
+// edges with an endpoint outside [0, n) are skipped (ingest_count flags them)
+hipError_t launch_ingest_scatter(const int32_t* edges, int64_t m, int32_t n, const int32_t* ptr, int32_t* cursor,
                                  int32_t* tmp, hipStream_t s);
 hipError_t launch_ingest_sort_small(const int32_t* ptr, int32_t* tmp, int32_t n, int32_t* udeg,
                                     int32_t* big, int32_t* big_n, hipStream_t s);
@@ -249,7 +250,8 @@ hipError_t launch_ingest_sort_big(const int32_t* ptr, int32_t* tmp, int32_t* ude
                                   const int32_t* big_n, int32_t* err, hipStream_t s);
 hipError_t launch_ingest_compact(const int32_t* tmp_ptr, const int32_t* tmp, const int32_t* row_ptr,
                                  int32_t n, int32_t* col, int32_t* src, int32_t* max_deg, hipStream_t s);
-hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, int64_t nnz, int32_t wpr,
-                             uint32_t* bitmap, hipStream_t s);
+// *nnz_dev (<= nnz_max) directed edges, read on the device
+hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int64_t nnz_max,
+                             int32_t wpr, uint32_t* bitmap, hipStream_t s);
 
 }  // namespace dm

@@ -615,7 +615,8 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
     }
     uint64_t hc = 0, hs = 0, hx = 0;
     for (;;) {
-        // ---- find a claimable tile (wave 0 scans 64 patterns at a time)
+        // ---- find a claimable tile (wave 0 scans 64 patterns at a time; the
+        // longest-chain preference holds within each group of 64)
         if (wid == 0) {
             int32_t p = -1, s = -1, tile = -1, ntiles = 0;
             bool all_done = false;
@@ -624,22 +625,32 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
                 for (int base = 0; base < N && !got; base += 64) {
                     const int q = (rot + base + lane) % N;
                     bool avail = false;
-                    int32_t st = 0, nt = 0;
+                    int32_t st = 0, nt = 0, left = 0;
                     if (base + lane < N) {
                         // polling uses relaxed (per-location coherent) loads: an
                         // acquire here would invalidate L1 on every poll
                         st = ld_rlx_i32(&b.ctl[q].stage);
-                        if (st < b.nsteps[q]) {
+                        const int32_t ns = b.nsteps[q];
+                        if (st < ns) {
                             // ntiles[s] is written once (0 -> final) before stage s is
                             // published, so a nonzero value is the final one
                             nt = ld_rlx_i32(&b.ctl[q].ntiles[st]);
                             avail = ld_rlx_i32(&b.ctl[q].claim[st]) < nt;
+                            left = ns - st;
                         }
                     }
                     uint64_t m = __ballot(avail);
                     while (m) {
-                        const int l = __ffsll((long long)m) - 1;
-                        m &= m - 1;
+                        // longest chain first: among the claimable patterns still
+                        // untried, the one with the most steps left (ties in
+                        // rotated order), so the patterns that set the launch's
+                        // length never wait behind short ones for a workgroup
+                        int32_t mx = ((m >> lane) & 1ull) ? left : -1;
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+                        const uint64_t top = m & __ballot(((m >> lane) & 1ull) && left == mx);
+                        const int l = __ffsll((long long)top) - 1;
+                        m &= ~(1ull << l);
                         const int32_t qq = __shfl(q, l, 64);
                         const int32_t ss = __shfl(st, l, 64);
                         const int32_t ntl = __shfl(nt, l, 64);
@@ -886,15 +897,23 @@ __device__ void wave_equal_range(const int32_t* a, int64_t n, int32_t v, int lan
 
 // Sort the n packed rows staged in LDS with a bitonic network over 16-bit
 // row indices; idx[0, n) receives the order.  Called by the whole workgroup.
+// The pairs t of one wave (64 consecutive t, for each multiple of the block
+// size) are (lo, lo + stride) with lo = t + (t & ~(stride - 1)): for stride <=
+// 64 they lie inside the wave's own 128-element chunk, so a run of such stages
+// needs no workgroup barrier (a wave's LDS accesses complete in order); only a
+// stage with a longer stride, or the first stage after one, waits for all.
 __device__ void lds_bitonic(const uint64_t* rows, uint16_t* idx, int n, int wp) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nt = (int)blockDim.x;
     int P = 1;
     while (P < n) P <<= 1;
-    for (int i = tid; i < P; i += (int)blockDim.x) idx[i] = i < n ? (uint16_t)i : kSent16;
+    for (int i = tid; i < P; i += nt) idx[i] = i < n ? (uint16_t)i : kSent16;
     __syncthreads();
+    int prev = 0;  // stride of the previous stage (0: the fill, followed by a barrier)
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = tid; t < (P >> 1); t += (int)blockDim.x) {
+            if (prev != 0 && (stride > 64 || prev > 64)) __syncthreads();
+            prev = stride;
+            for (int t = tid; t < (P >> 1); t += nt) {
                 const int lo = 2 * t - (t & (stride - 1));
                 const int hi = lo + stride;
                 const bool asc = (lo & size) == 0;
@@ -908,40 +927,46 @@ __device__ void lds_bitonic(const uint64_t* rows, uint16_t* idx, int n, int wp) 
                     idx[hi] = ia;
                 }
             }
-            __syncthreads();
         }
     }
+    __syncthreads();
 }
 
 // Stage rows [r0, r0 + n) of a final table into LDS as packed rows
 // (columns 1..k-1 in pattern-vertex order).  Work is dealt by element,
 // column-major so neighbouring lanes read neighbouring rows of one column;
-// each thread issues four independent loads before OR-ing the values into
+// each thread issues eight independent loads before OR-ing the values into
 // the zeroed words, so a row's columns are fetched in parallel, not in turn.
+// A thread's (column, row) advances by a fixed step: no division per element.
 __device__ __forceinline__ void lds_stage_rows(const SortJob& job, int64_t r0, int n, uint64_t* rows) {
     const int k = job.k, wp = job.wp, bits = job.bits, cpw = job.cpw;
     const int nt = (int)blockDim.x;
     for (int i = threadIdx.x; i < n * wp; i += nt) rows[i] = 0;
     __syncthreads();
     const int total = n * (k - 1);
-    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * nt) {
-        uint32_t v[4];
+    const int dj = nt / n, dr = nt - dj * n;  // element step nt = dj columns + dr rows
+    int j = 1 + (int)threadIdx.x / n, r = (int)threadIdx.x % n;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 8 * nt) {
+        uint32_t v[8];
+        int jj[8], rr[8];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int e = e0 + u * nt;
+        for (int u = 0; u < 8; u++) {
+            jj[u] = j;
+            rr[u] = r;
             v[u] = 0;
-            if (e < total) {
-                const int j = 1 + e / n, r = e - (j - 1) * n;
-                v[u] = (uint32_t)job.in[(int64_t)job.perm[j] * job.in_stride + r0 + r];
+            if (e0 + u * nt < total) v[u] = (uint32_t)job.in[(int64_t)job.perm[j] * job.in_stride + r0 + r];
+            j += dj;
+            r += dr;
+            if (r >= n) {
+                r -= n;
+                j++;
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int e = e0 + u * nt;
-            if (e < total) {
-                const int j = 1 + e / n, r = e - (j - 1) * n;
-                const int q = (j - 1) / cpw, c = (j - 1) - q * cpw;
-                atomicOr((unsigned long long*)&rows[(size_t)r * wp + q],
+        for (int u = 0; u < 8; u++) {
+            if (e0 + u * nt < total) {
+                const int q = (jj[u] - 1) / cpw, c = (jj[u] - 1) - q * cpw;
+                atomicOr((unsigned long long*)&rows[(size_t)rr[u] * wp + q],
                          (unsigned long long)v[u] << ((cpw - 1 - c) * bits));
             }
         }
@@ -949,11 +974,23 @@ __device__ __forceinline__ void lds_stage_rows(const SortJob& job, int64_t r0, i
     __syncthreads();
 }
 
-// Column j >= 1 of packed row x.
-__device__ __forceinline__ int32_t lds_unpack(const uint64_t* rows, const SortJob& job, uint32_t x, int j) {
-    const int q = (j - 1) / job.cpw, c = (j - 1) - q * job.cpw;
-    const uint64_t word = rows[(size_t)x * job.wp + q];
-    return (int32_t)((word >> ((job.cpw - 1 - c) * job.bits)) & ((1ull << job.bits) - 1));
+// Write rows idx[0, nw) of the packed tile as row-major int32 rows of k
+// columns at dst (column 0 = root): one row per thread, its words read once
+// and unpacked in registers.
+__device__ __forceinline__ void lds_write_rows(const uint64_t* rows, const uint16_t* idx, const SortJob& job,
+                                               int nw, int32_t root, int32_t* dst) {
+    const int k = job.k, wp = job.wp, bits = job.bits, cpw = job.cpw;
+    const uint64_t mask = (1ull << bits) - 1;
+    for (int r = threadIdx.x; r < nw; r += (int)blockDim.x) {
+        const uint64_t* src = rows + (size_t)idx[r] * wp;
+        int32_t* o = dst + (int64_t)r * k;
+        o[0] = root;
+        int j = 1;
+        for (int w = 0; w < wp && j < k; w++) {
+            const uint64_t word = src[w];
+            for (int c = 0; c < cpw && j < k; c++, j++) o[j] = (int32_t)((word >> ((cpw - 1 - c) * bits)) & mask);
+        }
+    }
 }
 
 __device__ __forceinline__ void push_segment(const SortLaunch& L, int32_t item, int64_t seg0, int64_t len) {
@@ -1051,13 +1088,7 @@ __global__ __launch_bounds__(1024) void sort_lds_kernel(const SortLaunch L) {
             __syncthreads();
         }
         const int64_t nw = (seg0 + n <= out_rows) ? n : (out_rows - seg0);
-        const int64_t total = nw * k;
-        int32_t* dst = job.out + seg0 * k;
-        for (int64_t e = tid; e < total; e += (int)blockDim.x) {
-            const int64_t r = e / k;
-            const int j = (int)(e - r * k);
-            dst[e] = j == 0 ? root : lds_unpack(rows, job, idx[r], j);
-        }
+        lds_write_rows(rows, idx, job, (int)nw, root, job.out + seg0 * k);
         if (job.out_cost)
             for (int64_t r = tid; r < nw; r += (int)blockDim.x) job.out_cost[seg0 + r] = job.in_cost[seg0 + idx[r]];
         __syncthreads();
@@ -1560,20 +1591,20 @@ hipError_t launch_scan_i32(const int32_t* in, int32_t* out_excl, int64_t n, int6
     return hipGetLastError();
 }
 
-__global__ void ingest_scatter_kernel(const int32_t* edges, int64_t m, const int32_t* ptr, int32_t* cursor,
+__global__ void ingest_scatter_kernel(const int32_t* edges, int64_t m, int32_t n, const int32_t* ptr, int32_t* cursor,
                                       int32_t* tmp) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t u = edges[2 * e], v = edges[2 * e + 1];
-        if (u == v) continue;
+        if (u == v || u < 0 || v < 0 || u >= n || v >= n) continue;  // range errors are flagged by the count
         tmp[ptr[u] + atomicAdd(&cursor[u], 1)] = v;
         tmp[ptr[v] + atomicAdd(&cursor[v], 1)] = u;
     }
 }
 
-hipError_t launch_ingest_scatter(const int32_t* edges, int64_t m, const int32_t* ptr, int32_t* cursor, int32_t* tmp,
-                                 hipStream_t s) {
+hipError_t launch_ingest_scatter(const int32_t* edges, int64_t m, int32_t n, const int32_t* ptr, int32_t* cursor,
+                                 int32_t* tmp, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(ingest_scatter_kernel, dim3(grid_for(m, 256)), dim3(256), 0, s, edges, m, ptr, cursor, tmp);
+    hipLaunchKernelGGL(ingest_scatter_kernel, dim3(grid_for(m, 256)), dim3(256), 0, s, edges, m, n, ptr, cursor, tmp);
     return hipGetLastError();
 }
 
@@ -1683,17 +1714,20 @@ hipError_t launch_ingest_compact(const int32_t* tmp_ptr, const int32_t* tmp, con
     return hipGetLastError();
 }
 
-__global__ void bitmap_set_kernel(const int32_t* src, const int32_t* col, int64_t nnz, int32_t wpr, uint32_t* bm) {
+__global__ void bitmap_set_kernel(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int32_t wpr,
+                                  uint32_t* bm) {
+    const int64_t nnz = *nnz_dev;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t u = src[e], w = col[e];
         atomicOr(&bm[(size_t)u * (size_t)wpr + (size_t)(w >> 5)], 1u << (w & 31));
     }
 }
 
-hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, int64_t nnz, int32_t wpr, uint32_t* bitmap,
-                             hipStream_t s) {
-    if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(bitmap_set_kernel, dim3(grid_for(nnz, 256)), dim3(256), 0, s, src, col, nnz, wpr, bitmap);
+hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int64_t nnz_max,
+                             int32_t wpr, uint32_t* bitmap, hipStream_t s) {
+    if (nnz_max <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bitmap_set_kernel, dim3(grid_for(nnz_max, 256)), dim3(256), 0, s, src, col, nnz_dev, wpr,
+                       bitmap);
     return hipGetLastError();
 }
 

@@ -810,6 +810,30 @@ static NormPattern motif_pattern(int m) {
     return p;
 }
 
+// Does the graph (CSR with ascending, merged lists) contain a 4-cycle?  Two
+// distinct 2-paths v-u-w and v-u'-w close one.  1 / 0, or -1 when the check
+// would walk more than 2e7 2-paths (the caller decides on the device).
+static int host_has_4cycle(const std::vector<int32_t>& rp, const std::vector<int32_t>& col, int32_t n) {
+    double work = 0;
+    for (int32_t v = 0; v < n; v++) {
+        const double d = rp[v + 1] - rp[v];
+        work += d * d;
+    }
+    if (work > 2e7) return -1;
+    std::vector<int32_t> seen((size_t)n, -1);
+    for (int32_t v = 0; v < n; v++)
+        for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
+            const int32_t u = col[i];
+            for (int32_t j = rp[u]; j < rp[u + 1]; j++) {
+                const int32_t w = col[j];
+                if (w == v) continue;
+                if (seen[w] == v) return 1;
+                seen[w] = v;
+            }
+        }
+    return 0;
+}
+
 // Build Res(M) for motif m (every key position) by running Algorithm 1 on
 // the motif itself with the motifs already in the database (Algorithm 2).
 static dm_status build_motif(dm_datagraph* dg, int m) {
@@ -852,7 +876,9 @@ static dm_status build_motif(dm_datagraph* dg, int m) {
     return DM_OK;
 }
 
-static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
+// host_csr (optional): receives row_ptr and col, read back with the edge count.
+static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
+                        std::pair<std::vector<int32_t>, std::vector<int32_t>>* host_csr = nullptr) {
     dm_context* ctx = dg->ctx;
     hipStream_t s = ctx->stream;
     Workspace& ws = ctx->ws;
@@ -903,19 +929,13 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
             st = fail(DM_ERR_DEVICE, "scan launch failed");
             break;
         }
-        int64_t raw = 0;
-        int32_t hflags[16];
-        if (hipMemcpyAsync(&raw, &ws.ctrl_d->counts[0], sizeof(int64_t), hipMemcpyDeviceToHost, s) ||
-            hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s)) {
-            st = fail(DM_ERR_DEVICE, "ingest readback failed");
-            break;
-        }
-        if (hflags[0] & 1) {
-            st = fail(DM_ERR_VERTEX_RANGE, "data graph vertex id out of range");
-            break;
-        }
-        if ((st = dev_alloc((void**)&tmp, sizeof(int32_t) * (size_t)std::max<int64_t>(raw, 1), s))) break;
-        if (launch_ingest_scatter(d_edges, m, tmp_ptr, cursor, tmp, s) ||
+        // Every buffer below is sized by host-known bounds (at most 2m directed
+        // edges before and after merging repeats), so the pipeline runs to the
+        // end without a readback; range and degree errors are read with the
+        // edge count once, at the end (the kernels skip the bad entries).
+        const int64_t emax = std::max<int64_t>(2 * m, 1);
+        if ((st = dev_alloc((void**)&tmp, sizeof(int32_t) * (size_t)emax, s))) break;
+        if (launch_ingest_scatter(d_edges, m, n, tmp_ptr, cursor, tmp, s) ||
             launch_ingest_sort_small(tmp_ptr, tmp, n, udeg, big, flags + 1, s) ||
             launch_ingest_sort_big(tmp_ptr, tmp, udeg, big, flags + 1, flags, s)) {
             st = fail(DM_ERR_DEVICE, "ingest sort launch failed");
@@ -928,20 +948,10 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
             st = fail(DM_ERR_DEVICE, "scan launch failed");
             break;
         }
-        int64_t nnz = 0;
-        if (hipMemcpyAsync(&nnz, &ws.ctrl_d->counts[1], sizeof(int64_t), hipMemcpyDeviceToHost, s) ||
-            hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s)) {
-            st = fail(DM_ERR_DEVICE, "ingest readback failed");
-            break;
-        }
-        if (hflags[0] & 2) {
-            st = fail(DM_ERR_UNSUPPORTED, "a vertex degree exceeds 16384");
-            break;
-        }
-        dg->nnz = nnz;
-        // src | col in one block: Res(M2) is then an ordinary 2-column SoA table
-        if ((st = dev_alloc((void**)&dg->src, sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(nnz, 1), s))) break;
-        dg->col = dg->src + std::max<int64_t>(nnz, 1);
+        // src | col in one block (column stride emax): Res(M2) is then an
+        // ordinary 2-column SoA table
+        if ((st = dev_alloc((void**)&dg->src, sizeof(int32_t) * 2 * (size_t)emax, s))) break;
+        dg->col = dg->src + emax;
         if (launch_ingest_compact(tmp_ptr, tmp, dg->row_ptr, n, dg->col, dg->src, flags + 2, s)) {
             st = fail(DM_ERR_DEVICE, "compact launch failed");
             break;
@@ -951,15 +961,39 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd) {
             int64_t words = (int64_t)n * dg->words_per_row;
             if ((st = dev_alloc((void**)&dg->bitmap, sizeof(uint32_t) * (size_t)words, s))) break;
             (void)launch_fill_i32((int32_t*)dg->bitmap, 0, words, s);
-            if (launch_bitmap_set(dg->src, dg->col, nnz, dg->words_per_row, dg->bitmap, s)) {
+            if (launch_bitmap_set(dg->src, dg->col, &ws.ctrl_d->counts[1], emax, dg->words_per_row, dg->bitmap, s)) {
                 st = fail(DM_ERR_DEVICE, "bitmap launch failed");
                 break;
             }
         }
-        if (hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s)) {
+        int64_t nnz = 0;
+        int32_t hflags[16];
+        bool copied = hipMemcpyAsync(&nnz, &ws.ctrl_d->counts[1], sizeof(int64_t), hipMemcpyDeviceToHost, s) ==
+                          hipSuccess &&
+                      hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s) == hipSuccess;
+        if (copied && host_csr) {
+            // the caller wants the CSR on the host too (row_ptr, and col up to the bound)
+            host_csr->first.resize((size_t)n + 1);
+            host_csr->second.resize((size_t)emax);
+            copied = hipMemcpyAsync(host_csr->first.data(), dg->row_ptr, sizeof(int32_t) * ((size_t)n + 1),
+                                    hipMemcpyDeviceToHost, s) == hipSuccess &&
+                     hipMemcpyAsync(host_csr->second.data(), dg->col, sizeof(int32_t) * (size_t)emax,
+                                    hipMemcpyDeviceToHost, s) == hipSuccess;
+        }
+        if (!copied || hipStreamSynchronize(s) != hipSuccess) {
             st = fail(DM_ERR_DEVICE, "ingest readback failed");
             break;
         }
+        if (hflags[0] & 1) {
+            st = fail(DM_ERR_VERTEX_RANGE, "data graph vertex id out of range");
+            break;
+        }
+        if (hflags[0] & 2) {
+            st = fail(DM_ERR_UNSUPPORTED, "a vertex degree exceeds 16384");
+            break;
+        }
+        dg->nnz = nnz;
+        if (host_csr) host_csr->second.resize((size_t)nnz);
         dg->max_degree = hflags[2];
     } while (0);
     cleanup();
@@ -1045,25 +1079,28 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, ctx->stream);
-    dm_status st = ingest(dg, gd);
+    const bool aut = (motif_mask == DM_MOTIF_AUTO);
+    std::pair<std::vector<int32_t>, std::vector<int32_t>> csr;  // host copy for the AUTO choice
+    dm_status st = ingest(dg, gd, aut ? &csr : nullptr);
     if (st == DM_OK && dg->n > 0) {
-        const bool aut = (motif_mask == DM_MOTIF_AUTO);
         uint32_t want = motif_mask;
         if (aut) {
             // topology-aware set (Sec. VI-B): the square cell on grid-like graphs,
             // the claw on low-degree graphs without 4-cycles (heavy-hex-like)
-            st = build_motif(dg, MOT_C4);
-            if (st == DM_OK && dg->tab[MOT_C4][0].rows > 0) {
+            int c4 = host_has_4cycle(csr.first, csr.second, dg->n);
+            if (c4 < 0) {
+                // too many 2-paths to check on the host: the cycle table decides
+                st = build_motif(dg, MOT_C4);
+                c4 = st == DM_OK && dg->tab[MOT_C4][0].rows > 0 ? 1 : 0;
+                if (st == DM_OK && !c4) free_motif(dg, MOT_C4);
+            }
+            if (c4) {
                 want = DM_MOTIF_M3 | DM_MOTIF_M4 | DM_MOTIF_C4;
-            } else if (st == DM_OK) {
-                free_motif(dg, MOT_C4);
+            } else {
                 // the claw table has sum_v d(d-1)(d-2) rows: only for low degrees
-                std::vector<int32_t> rp((size_t)dg->n + 1);
-                if (hipMemcpy(rp.data(), dg->row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost) != hipSuccess)
-                    st = fail(DM_ERR_DEVICE, "degree readback failed");
                 double claws = 0;
                 for (int32_t v = 0; v < dg->n; v++) {
-                    const double d = rp[v + 1] - rp[v];
+                    const double d = csr.first[v + 1] - csr.first[v];
                     claws += d * (d - 1) * (d - 2);
                 }
                 want = claws <= 5e7 ? DM_MOTIF_M4_1 : (DM_MOTIF_M3 | DM_MOTIF_M4);
