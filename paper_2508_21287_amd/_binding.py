@@ -54,6 +54,40 @@ class GraphDesc(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("n_edges", C.c_int64), ("edges", C.POINTER(C.c_int32))]
 
 
+# GraphDesc as a numpy record, for building the descriptor array of a batch
+# in one step (per-pattern ctypes objects cost microseconds each)
+_DESC_DT = np.dtype({"names": ["n_vertices", "n_edges", "edges"], "formats": [np.int32, np.int64, np.uint64],
+                     "offsets": [GraphDesc.n_vertices.offset, GraphDesc.n_edges.offset, GraphDesc.edges.offset],
+                     "itemsize": C.sizeof(GraphDesc)})
+
+
+_I32 = np.dtype(np.int32)
+
+
+def _edge_array(edges) -> np.ndarray:
+    if type(edges) is np.ndarray and edges.dtype == _I32 and edges.ndim == 2 and edges.flags.c_contiguous:
+        return edges
+    return np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+
+
+def _desc_array(patterns):
+    """(descriptor array, the one edge array it points into) for a list of
+    (n, edges): the edge lists are packed back to back, so every pointer is
+    the block's address plus an offset."""
+    arrs = [_edge_array(e) for _, e in patterns]
+    k = len(arrs)
+    m = np.fromiter((a.shape[0] for a in arrs), dtype=np.int64, count=k)
+    block = np.concatenate(arrs) if k else np.zeros((0, 2), dtype=np.int32)
+    d = np.empty(k, dtype=_DESC_DT)
+    d["n_vertices"] = np.fromiter((int(n) for n, _ in patterns), dtype=np.int32, count=k)
+    d["n_edges"] = m
+    start = np.zeros(k, dtype=np.uint64)
+    if k > 1:
+        start[1:] = np.cumsum(m[:-1]).astype(np.uint64) * np.uint64(8)
+    d["edges"] = np.uint64(block.__array_interface__["data"][0]) + start
+    return d, block
+
+
 class PlanOpts(C.Structure):
     _fields_ = [("motif_mask", C.c_uint32), ("block_threads", C.c_int32), ("output_mode", C.c_int32),
                 ("sync_each_step", C.c_int32), ("mem_budget", C.c_int64), ("profile", C.c_int32),
@@ -99,6 +133,8 @@ def lib() -> C.CDLL:
     """Load libdmotif.so.  Raises if the HIP library has not been built: there
     is no fallback path."""
     global _LIB
+    if _LIB is not None:  # set once, under the lock below
+        return _LIB
     with _lock:
         if _LIB is not None:
             return _LIB
@@ -424,15 +460,21 @@ class DataGraph:
         return Result(h, self.ctx)
 
     def enumerate_batch(self, patterns, caps=None, **opts) -> list[Result]:
-        gs = [_Graph(n, e) for n, e in patterns]
-        arr = (GraphDesc * len(gs))(*[g.desc for g in gs])
+        descs, keep = _desc_array(patterns)
+        n = len(descs)
         capv = None
         if caps is not None:
-            capv = (C.c_int64 * len(gs))(*[int(c) for c in caps])
-        outs = (C.c_void_p * len(gs))()
+            capv = np.ascontiguousarray(np.asarray(caps, dtype=np.int64))
+            if capv.shape != (n,):
+                raise ValueError("caps must give one value per pattern")
+        outs = np.zeros(max(n, 1), dtype=np.uint64)
         o = _opts(**opts)
-        _check(lib().dm_enumerate_batch(self._h, len(gs), arr, capv, C.byref(o), outs))
-        return [Result(C.c_void_p(outs[i]), self.ctx) for i in range(len(gs))]
+        _check(lib().dm_enumerate_batch(
+            self._h, n, C.cast(descs.ctypes.data, C.POINTER(GraphDesc)) if n else None,
+            None if capv is None else C.cast(capv.ctypes.data, C.POINTER(C.c_int64)), C.byref(o),
+            C.cast(outs.ctypes.data, C.POINTER(C.c_void_p))))
+        del keep  # the call copied the patterns
+        return [Result(C.c_void_p(int(h)), self.ctx) for h in outs[:n].tolist()]
 
     def free(self):
         if self._h:

@@ -641,14 +641,19 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
                     }
                     uint64_t m = __ballot(avail);
                     while (m) {
-                        // longest chain first: among the claimable patterns still
-                        // untried, the one with the most steps left (ties in
-                        // rotated order), so the patterns that set the launch's
-                        // length never wait behind short ones for a workgroup
-                        int32_t mx = ((m >> lane) & 1ull) ? left : -1;
+                        // Preference among the claimable patterns still untried:
+                        // first those whose home XCD (pattern mod 8) is this
+                        // workgroup's (workgroups are dealt to the 8 XCDs
+                        // round-robin by index), so a pattern's look-back words
+                        // mostly stay in one L2; then the longest chain (most
+                        // steps left), so the patterns that set the launch's
+                        // length never wait behind short ones; ties in rotated
+                        // order.
+                        const int32_t pr = left + (((q & 7) == (int)(blockIdx.x & 7)) ? 64 : 0);
+                        int32_t mx = ((m >> lane) & 1ull) ? pr : -1;
 #pragma unroll
                         for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-                        const uint64_t top = m & __ballot(((m >> lane) & 1ull) && left == mx);
+                        const uint64_t top = m & __ballot(((m >> lane) & 1ull) && pr == mx);
                         const int l = __ffsll((long long)top) - 1;
                         m &= ~(1ull << l);
                         const int32_t qq = __shfl(q, l, 64);

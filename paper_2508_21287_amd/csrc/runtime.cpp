@@ -207,12 +207,15 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.v_begin = v0;
     L.dup_count = &counters[3];
     L.max_chunks = &counters[2];
-    // tier 1: small LDS tiles, five workgroups per CU
+    // tier 1: small LDS tiles, five workgroups per CU; one workgroup per
+    // (job, root) item up to 65536 of them, so the hardware dispatcher, which
+    // starts a workgroup as soon as one finishes, balances the very uneven
+    // segments (a workgroup dealt two large ones would set the launch's length)
     L.lds_bytes = 32 * 1024 - 512;
     L.list = nullptr;
     L.spill = ws.spill;
     L.spill_n = &counters[0];
-    DM_HIP(launch_sort_lds(L, (int)std::min<int64_t>(std::max<int64_t>(items, 1), 8192), 256, L.lds_bytes, s));
+    DM_HIP(launch_sort_lds(L, (int)std::min<int64_t>(std::max<int64_t>(items, 1), 65536), 256, L.lds_bytes, s));
     // tier 2: the largest LDS allocation a workgroup can hold; one such
     // workgroup fills a CU, so it takes the largest block
     L.lds_bytes = ctx->sort_lds_max;
