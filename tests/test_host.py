@@ -141,3 +141,24 @@ def test_workload_shapes():
     # seeds reproduce
     _, again = W.config2()
     assert all(np.array_equal(a.edges, b.edges) for a, b in zip(pats, again))
+
+
+def test_batch_descriptor_marshalling():
+    # the batch call's descriptors are one record array over one packed edge
+    # block: every record must read back as the ctypes GraphDesc the C ABI
+    # declares, pointing at that pattern's own edges (lists, int64 arrays and
+    # empty edge lists included)
+    import ctypes as C
+    from paper_2508_21287_amd import _binding as B
+    _, pats = W.config2(12)
+    specs = [(p.n, p.edges) for p in pats]
+    specs += [(3, [(0, 1), (1, 2)]), (1, []), (2, np.array([[0, 1]], dtype=np.int64))]
+    d, block = B._desc_array(specs)
+    assert d.itemsize == C.sizeof(B.GraphDesc)
+    descs = (B.GraphDesc * len(specs)).from_address(d.ctypes.data)
+    for (n, e), g in zip(specs, descs):
+        want = np.asarray(e, dtype=np.int32).reshape(-1, 2)
+        assert g.n_vertices == n and g.n_edges == want.shape[0]
+        if want.shape[0]:
+            got = np.ctypeslib.as_array(g.edges, shape=(2 * want.shape[0],)).reshape(-1, 2)
+            assert np.array_equal(got, want)
