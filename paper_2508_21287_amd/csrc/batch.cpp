@@ -86,8 +86,9 @@ class HostPool {
 
   private:
     HostPool() {
+        // up to 15 workers + the calling thread: one GPU's share of host CPUs
         const unsigned hw = std::thread::hardware_concurrency();
-        const int w = (int)std::min<unsigned>(hw > 1 ? hw - 1 : 0, 7);
+        const int w = (int)std::min<unsigned>(hw > 1 ? hw - 1 : 0, 15);
         for (int i = 0; i < w; i++) workers_.emplace_back([this] { loop(); });
     }
     void run() {

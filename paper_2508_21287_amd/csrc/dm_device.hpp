@@ -250,6 +250,13 @@ hipError_t launch_ingest_sort_big(const int32_t* ptr, int32_t* tmp, int32_t* ude
                                   const int32_t* big_n, int32_t* err, hipStream_t s);
 hipError_t launch_ingest_compact(const int32_t* tmp_ptr, const int32_t* tmp, const int32_t* row_ptr,
                                  int32_t n, int32_t* col, int32_t* src, int32_t* max_deg, hipStream_t s);
+// The claw table (centre 0, leaves 1..3) from the CSR: per key vertex row
+// counts (key_pos 0: centre, 1: leaf), then the rows at the scanned offsets
+// (SoA, column stride `stride`)
+hipError_t launch_claw_count(const int32_t* rp, const int32_t* col, int32_t n, int32_t key_pos, int32_t* cnt,
+                             hipStream_t s);
+hipError_t launch_claw_fill(const int32_t* rp, const int32_t* col, int32_t n, int32_t key_pos, const int32_t* offs,
+                            int64_t stride, int32_t* data, hipStream_t s);
 // *nnz_dev (<= nnz_max) directed edges, read on the device
 hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int64_t nnz_max,
                              int32_t wpr, uint32_t* bitmap, hipStream_t s);

@@ -1719,6 +1719,75 @@ hipError_t launch_ingest_compact(const int32_t* tmp_ptr, const int32_t* tmp, con
     return hipGetLastError();
 }
 
+// ---- the claw table (M4-1: centre 0, leaves 1..3) straight from the CSR.
+// Keyed at the centre (key_pos 0) the rows of vertex v are (v, a, b, d) for
+// every ordered triple of distinct neighbours of v; keyed at a leaf
+// (key_pos 1) they are (c, v, a, b) for every neighbour c of v and ordered
+// pair (a, b) of distinct neighbours of c other than v.  Either way every
+// embedding of the claw appears once, grouped by the key position's image.
+__global__ void claw_count_kernel(const int32_t* rp, const int32_t* col, int32_t n, int32_t key_pos, int32_t* cnt) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = 0;
+        if (key_pos == 0) {
+            const int64_t d = rp[v + 1] - rp[v];
+            c = d * (d - 1) * (d - 2);
+        } else {
+            for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
+                const int32_t u = col[i];
+                const int64_t d = rp[u + 1] - rp[u];
+                c += (d - 1) * (d - 2);
+            }
+        }
+        cnt[v] = (int32_t)c;  // the host checked that the total fits
+    }
+}
+
+__global__ void claw_fill_kernel(const int32_t* rp, const int32_t* col, int32_t n, int32_t key_pos,
+                                 const int32_t* offs, int64_t stride, int32_t* data) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = offs[v];
+        auto put = [&](int32_t x0, int32_t x1, int32_t x2, int32_t x3) {
+            data[r] = x0;
+            data[stride + r] = x1;
+            data[2 * stride + r] = x2;
+            data[3 * stride + r] = x3;
+            r++;
+        };
+        if (key_pos == 0) {
+            for (int32_t i = rp[v]; i < rp[v + 1]; i++)
+                for (int32_t j = rp[v]; j < rp[v + 1]; j++) {
+                    if (j == i) continue;
+                    for (int32_t l = rp[v]; l < rp[v + 1]; l++)
+                        if (l != i && l != j) put((int32_t)v, col[i], col[j], col[l]);
+                }
+        } else {
+            for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
+                const int32_t c = col[i];
+                for (int32_t j = rp[c]; j < rp[c + 1]; j++) {
+                    if (col[j] == v) continue;
+                    for (int32_t l = rp[c]; l < rp[c + 1]; l++)
+                        if (l != j && col[l] != v) put(c, (int32_t)v, col[j], col[l]);
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_claw_count(const int32_t* rp, const int32_t* col, int32_t n, int32_t key_pos, int32_t* cnt,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(claw_count_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, rp, col, n, key_pos, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_claw_fill(const int32_t* rp, const int32_t* col, int32_t n, int32_t key_pos, const int32_t* offs,
+                            int64_t stride, int32_t* data, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(claw_fill_kernel, dim3(grid_for(n, 64)), dim3(64), 0, s, rp, col, n, key_pos, offs, stride,
+                       data);
+    return hipGetLastError();
+}
+
 __global__ void bitmap_set_kernel(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int32_t wpr,
                                   uint32_t* bm) {
     const int64_t nnz = *nnz_dev;

@@ -81,10 +81,30 @@ void Workspace::release() {
     job_d = nullptr;
     if (job_h) (void)hipHostFree(job_h);
     job_h = nullptr;
+    if (stage_h) (void)hipHostFree(stage_h);
+    stage_h = nullptr;
+    stage_bytes = 0;
     for (int i = 0; i < 2; i++)
         if (ev[i]) (void)hipEventDestroy(ev[i]), ev[i] = nullptr;
     for (auto e : prof) (void)hipEventDestroy(e);
     prof.clear();
+}
+
+// Pinned so that several device-to-host copies can be queued and waited for
+// once (a copy into pageable memory waits for the device by itself).  The
+// caller synchronizes the stream before the buffer is reused or grown.
+dm_status Workspace::ensure_stage(size_t bytes) {
+    if (stage_bytes >= bytes) return DM_OK;
+    if (stage_h) {
+        if (stream) DM_HIP(hipStreamSynchronize(stream));
+        (void)hipHostFree(stage_h);
+        stage_h = nullptr;
+        stage_bytes = 0;
+    }
+    const size_t c = std::max<size_t>(bytes, (size_t)1 << 16);
+    DM_HIP(hipHostMalloc((void**)&stage_h, c, hipHostMallocDefault));
+    stage_bytes = c;
+    return DM_OK;
 }
 
 dm_status Workspace::ensure_buf(int i, int64_t elems) {
@@ -837,9 +857,68 @@ static int host_has_4cycle(const std::vector<int32_t>& rp, const std::vector<int
     return 0;
 }
 
+// Res(M4-1), the claw, for both of its key positions (centre, leaf) straight
+// from the CSR: the same rows Algorithm 2's joins produce (every embedding of
+// the claw), sized on the host from the degree sequence and indexed on the
+// device (count, scan, fill), so the build reads nothing back.  Returns
+// DM_ERR_UNSUPPORTED when the host has no degree sequence or the table would
+// not fit int32 offsets (the join-based build then runs instead).
+static dm_status build_claw_direct(dm_datagraph* dg) {
+    dm_context* ctx = dg->ctx;
+    hipStream_t s = ctx->stream;
+    Workspace& ws = ctx->ws;
+    const int32_t n = dg->n;
+    if ((int32_t)dg->host_row_ptr.size() != n + 1 || n <= 0) return DM_ERR_UNSUPPORTED;
+    double rows_d = 0;
+    for (int32_t v = 0; v < n; v++) {
+        const double d = dg->host_row_ptr[v + 1] - dg->host_row_ptr[v];
+        rows_d += d * (d - 1) * (d - 2);
+    }
+    if (rows_d >= (double)INT32_MAX) return DM_ERR_UNSUPPORTED;
+    const int64_t rows = (int64_t)rows_d;
+    const int m = MOT_K13;
+    int32_t* cnt = nullptr;
+    DM_TRY(dev_alloc((void**)&cnt, sizeof(int32_t) * (size_t)(n + 1), s));
+    struct Tmp {
+        int32_t* p;
+        hipStream_t s;
+        ~Tmp() { dev_free(p, s); }
+    } tmp{cnt, s};
+    const int64_t tiles = (int64_t)(n + 1) / 1024 + 2;
+    DM_TRY(ws.ensure_status(tiles));
+    for (int j = 0; j < 2; j++) {
+        MotifTable& t = dg->tab[m][j];
+        t.size = 4;
+        t.rows = rows;
+        int32_t* data = nullptr;
+        int32_t* offs = nullptr;
+        DM_TRY(dev_alloc((void**)&data, sizeof(int32_t) * (size_t)std::max<int64_t>(rows * 4, 1), s));
+        t.owned[0] = data;
+        DM_TRY(dev_alloc((void**)&offs, sizeof(int32_t) * (size_t)(n + 1), s));
+        t.owned[1] = offs;
+        t.stride = std::max<int64_t>(rows, 1);
+        for (int q = 0; q < 4; q++) t.cols[q] = data + (size_t)q * (size_t)t.stride;
+        t.offs = offs;
+        DM_HIP(launch_claw_count(dg->row_ptr, dg->col, n, j, cnt, s));
+        DM_HIP(launch_fill_u64(ws.status, 0, tiles, s));
+        DM_HIP(launch_fill_u64(ws.tickets, 0, 1, s));
+        DM_HIP(launch_scan_i32(cnt, offs, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets, s));
+        DM_HIP(launch_claw_fill(dg->row_ptr, dg->col, n, j, offs, t.stride, data, s));
+    }
+    dg->motif_bits |= 1u << m;
+    dg->mask_built |= motif_info(m).bit;
+    dg->stats.rows[m] = (double)rows;
+    return DM_OK;
+}
+
 // Build Res(M) for motif m (every key position) by running Algorithm 1 on
 // the motif itself with the motifs already in the database (Algorithm 2).
 static dm_status build_motif(dm_datagraph* dg, int m) {
+    if (m == MOT_K13) {
+        const dm_status st = build_claw_direct(dg);
+        if (st != DM_ERR_UNSUPPORTED) return st;
+        free_motif(dg, m);  // nothing half-built stays behind
+    }
     dm_context* ctx = dg->ctx;
     hipStream_t s = ctx->stream;
     const MotifInfo& mi = motif_info(m);
@@ -890,26 +969,29 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
     if ((int64_t)2 * m >= (int64_t)INT32_MAX) return fail(DM_ERR_UNSUPPORTED, "more than 2^30 edges");
     int32_t *d_edges = nullptr, *deg = nullptr, *tmp_ptr = nullptr, *tmp = nullptr, *cursor = nullptr,
             *udeg = nullptr, *big = nullptr, *flags = nullptr;
-    auto cleanup = [&]() {
-        dev_free(d_edges, s);
-        dev_free(deg, s);
-        dev_free(tmp_ptr, s);
-        dev_free(tmp, s);
-        dev_free(cursor, s);
-        dev_free(udeg, s);
-        dev_free(big, s);
-        dev_free(flags, s);
-    };
+    // every scratch array in one allocation (sizes are host-known bounds)
+    const int64_t emax = std::max<int64_t>(2 * m, 1);
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t vbytes = a256(sizeof(int32_t) * (size_t)(n + 1));
+    const size_t ebytes = a256(sizeof(int32_t) * (size_t)emax);
+    const size_t scr_bytes = 256 + 2 * ebytes + 5 * vbytes;
+    char* scr = nullptr;
+    auto cleanup = [&]() { dev_free(scr, s); };
     dm_status st = DM_OK;
     do {
         // flags: [0] range error bits, [1] big-list count, [2] max degree
-        if ((st = dev_alloc((void**)&flags, 16 * sizeof(int32_t), s))) break;
-        if ((st = dev_alloc((void**)&d_edges, sizeof(int32_t) * (size_t)std::max<int64_t>(2 * m, 1), s))) break;
-        if ((st = dev_alloc((void**)&deg, sizeof(int32_t) * (size_t)(n + 1), s))) break;
-        if ((st = dev_alloc((void**)&tmp_ptr, sizeof(int32_t) * (size_t)(n + 1), s))) break;
-        if ((st = dev_alloc((void**)&cursor, sizeof(int32_t) * (size_t)(n + 1), s))) break;
-        if ((st = dev_alloc((void**)&udeg, sizeof(int32_t) * (size_t)(n + 1), s))) break;
-        if ((st = dev_alloc((void**)&big, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+        if ((st = dev_alloc((void**)&scr, scr_bytes, s))) break;
+        {
+            char* q = scr;
+            flags = (int32_t*)q, q += 256;
+            d_edges = (int32_t*)q, q += ebytes;
+            tmp = (int32_t*)q, q += ebytes;
+            deg = (int32_t*)q, q += vbytes;
+            tmp_ptr = (int32_t*)q, q += vbytes;
+            cursor = (int32_t*)q, q += vbytes;
+            udeg = (int32_t*)q, q += vbytes;
+            big = (int32_t*)q;
+        }
         if (launch_fill_i32(flags, 0, 16, s) || launch_fill_i32(deg, 0, n + 1, s) ||
             launch_fill_i32(cursor, 0, n + 1, s) || launch_fill_i32(udeg, 0, n + 1, s)) {
             st = fail(DM_ERR_DEVICE, "fill launch failed");
@@ -936,8 +1018,6 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
         // edges before and after merging repeats), so the pipeline runs to the
         // end without a readback; range and degree errors are read with the
         // edge count once, at the end (the kernels skip the bad entries).
-        const int64_t emax = std::max<int64_t>(2 * m, 1);
-        if ((st = dev_alloc((void**)&tmp, sizeof(int32_t) * (size_t)emax, s))) break;
         if (launch_ingest_scatter(d_edges, m, n, tmp_ptr, cursor, tmp, s) ||
             launch_ingest_sort_small(tmp_ptr, tmp, n, udeg, big, flags + 1, s) ||
             launch_ingest_sort_big(tmp_ptr, tmp, udeg, big, flags + 1, flags, s)) {
@@ -969,24 +1049,30 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
                 break;
             }
         }
-        int64_t nnz = 0;
-        int32_t hflags[16];
-        bool copied = hipMemcpyAsync(&nnz, &ws.ctrl_d->counts[1], sizeof(int64_t), hipMemcpyDeviceToHost, s) ==
-                          hipSuccess &&
-                      hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s) == hipSuccess;
-        if (copied && host_csr) {
-            // the caller wants the CSR on the host too (row_ptr, and col up to the bound)
-            host_csr->first.resize((size_t)n + 1);
-            host_csr->second.resize((size_t)emax);
-            copied = hipMemcpyAsync(host_csr->first.data(), dg->row_ptr, sizeof(int32_t) * ((size_t)n + 1),
-                                    hipMemcpyDeviceToHost, s) == hipSuccess &&
-                     hipMemcpyAsync(host_csr->second.data(), dg->col, sizeof(int32_t) * (size_t)emax,
-                                    hipMemcpyDeviceToHost, s) == hipSuccess;
-        }
+        // one readback through the pinned staging buffer: edge count, flags,
+        // row offsets, and the adjacency lists when the caller wants them
+        const size_t off_rp = 128, off_col = off_rp + a256(sizeof(int32_t) * (size_t)(n + 1));
+        const size_t need = off_col + (host_csr ? sizeof(int32_t) * (size_t)emax : 0);
+        if ((st = ws.ensure_stage(need))) break;
+        char* H = ws.stage_h;
+        bool copied =
+            hipMemcpyAsync(H, &ws.ctrl_d->counts[1], sizeof(int64_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipMemcpyAsync(H + 64, flags, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipMemcpyAsync(H + off_rp, dg->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s) ==
+                hipSuccess;
+        if (copied && host_csr)
+            copied = hipMemcpyAsync(H + off_col, dg->col, sizeof(int32_t) * (size_t)emax, hipMemcpyDeviceToHost, s) ==
+                     hipSuccess;
         if (!copied || hipStreamSynchronize(s) != hipSuccess) {
             st = fail(DM_ERR_DEVICE, "ingest readback failed");
             break;
         }
+        int64_t nnz = 0;
+        int32_t hflags[16];
+        std::memcpy(&nnz, H, sizeof nnz);
+        std::memcpy(hflags, H + 64, sizeof hflags);
+        // the degree sequence stays on the host (it sizes tables built from the CSR)
+        dg->host_row_ptr.assign((const int32_t*)(H + off_rp), (const int32_t*)(H + off_rp) + (n + 1));
         if (hflags[0] & 1) {
             st = fail(DM_ERR_VERTEX_RANGE, "data graph vertex id out of range");
             break;
@@ -996,7 +1082,10 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
             break;
         }
         dg->nnz = nnz;
-        if (host_csr) host_csr->second.resize((size_t)nnz);
+        if (host_csr) {
+            host_csr->first = dg->host_row_ptr;
+            host_csr->second.assign((const int32_t*)(H + off_col), (const int32_t*)(H + off_col) + nnz);
+        }
         dg->max_degree = hflags[2];
     } while (0);
     cleanup();
@@ -1084,7 +1173,9 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
     (void)hipEventRecord(e0, ctx->stream);
     const bool aut = (motif_mask == DM_MOTIF_AUTO);
     std::pair<std::vector<int32_t>, std::vector<int32_t>> csr;  // host copy for the AUTO choice
+    const auto tb0 = std::chrono::steady_clock::now();
     dm_status st = ingest(dg, gd, aut ? &csr : nullptr);
+    const auto tb1 = std::chrono::steady_clock::now();
     if (st == DM_OK && dg->n > 0) {
         uint32_t want = motif_mask;
         if (aut) {
@@ -1125,7 +1216,15 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
         }
     }
     (void)hipEventRecord(e1, ctx->stream);
+    const auto tb2 = std::chrono::steady_clock::now();
     if (st == DM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(DM_ERR_DEVICE, "build sync failed");
+    if (std::getenv("DMOTIF_BUILD_TIMING")) {
+        auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+            return std::chrono::duration<double, std::milli>(b - a).count();
+        };
+        std::fprintf(stderr, "[build] ingest %.3f ms, motif tables (enqueue) %.3f ms, final sync %.3f ms\n",
+                     ms(tb0, tb1), ms(tb1, tb2), ms(tb2, std::chrono::steady_clock::now()));
+    }
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);

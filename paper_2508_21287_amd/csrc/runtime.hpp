@@ -61,6 +61,9 @@ struct Workspace {
     std::vector<hipEvent_t> prof;  // event pairs for per-launch timing
     SortJob* job_d = nullptr;      // one sort job (plain path) and its pinned staging
     SortJob* job_h = nullptr;
+    char* stage_h = nullptr;       // pinned host staging for readbacks (grows on demand)
+    size_t stage_bytes = 0;
+    dm_status ensure_stage(size_t bytes);
     uint64_t* cbuf[2] = {nullptr, nullptr};  // scored runs: cost of each row of buf[i]
     int64_t cbuf_rows[2] = {0, 0};
     dm_status ensure_cbuf(int i, int64_t rows);
@@ -124,6 +127,7 @@ struct dm_datagraph {
     dm::MotifTable tab[dm::kNumMotifs][6];
     dm::MotifStats stats;
     double build_ms = 0;
+    std::vector<int32_t> host_row_ptr;  // CSR offsets read back at ingest (the degree sequence)
 
     dm::GraphDev graph_dev() const {
         dm::GraphDev g;
