@@ -166,6 +166,8 @@ void dm_context_destroy(dm_context* ctx);
  * DM_ERR_UNSUPPORTED (a vertex degree above 16384), DM_ERR_DEVICE. */
 dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t motif_mask,
                              dm_datagraph** out);
+/* Release the data graph's device memory, ordered after the work already
+ * queued on the context stream (no wait).  Stop any server using it first. */
 void dm_datagraph_free(dm_datagraph* dg);
 
 typedef struct {

@@ -814,7 +814,7 @@ static void free_datagraph(dm_datagraph* dg) {
     dev_free(dg->row_ptr, s);
     dev_free(dg->src, s);  // src and col share one allocation (src first)
     dev_free(dg->bitmap, s);
-    (void)hipStreamSynchronize(s);
+    // the frees are ordered on the context stream after the work queued there
     delete dg;
 }
 
