@@ -412,12 +412,11 @@ def main():
         else:
             res = [dg.enumerate(n, e, profile=profile) for n, e in specs]
         tot = sum(r.total for r in res)
-        st = [r.stats() for r in res]
+        st = [r.timing() for r in res]
         for r in res:
             r.free()
-        build_ms = dg.info()["build_ms"]
         dg.free()
-        return tot, st, build_ms
+        return tot, st
 
     for _ in range(args.warmup):
         step(True)
@@ -431,14 +430,14 @@ def main():
     emb = 0
     join_ms = join_bytes = join_launches = sort_ms = sort_bytes = 0
     for _ in range(args.steps):
-        tot, st, _ = step(True)
+        tot, st = step(True)
         emb += tot
-        for s in st:
-            join_ms += s["join_ms"]
-            join_bytes += s["join_bytes"]
-            join_launches += s["join_launches"]
-            sort_ms += s["sort_ms"]
-            sort_bytes += s["sort_bytes"]
+        for jm, jb, jl, sm, sb in st:
+            join_ms += jm
+            join_bytes += jb
+            join_launches += jl
+            sort_ms += sm
+            sort_bytes += sb
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
 

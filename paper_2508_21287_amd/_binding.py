@@ -356,6 +356,13 @@ class Result:
                 "join_launches": st.join_launches, "sort_launches": st.sort_launches, "join_ms": st.join_ms,
                 "sort_ms": st.sort_ms, "join_bytes": int(st.join_bytes), "sort_bytes": int(st.sort_bytes)}
 
+    def timing(self) -> tuple:
+        """(join_ms, join_bytes, join_launches, sort_ms, sort_bytes) of ``dm_result_stats``
+        without building the full dict (for per-step accounting in timed loops)."""
+        st = RunStats()
+        _check(lib().dm_result_stats(self._h, C.byref(st)))
+        return st.join_ms, st.join_bytes, st.join_launches, st.sort_ms, st.sort_bytes
+
     def free(self):
         if self._h:
             lib().dm_result_free(self._h)
