@@ -411,10 +411,11 @@ def main():
             res = dg.enumerate_batch(specs, profile=profile)
         else:
             res = [dg.enumerate(n, e, profile=profile) for n, e in specs]
-        tot = sum(r.total for r in res)
-        st = [r.timing() for r in res]
-        for r in res:
-            r.free()
+        sm = dm.summarize(res)  # one call for all results' counts and launch accounting
+        tot = int(sm["total"].sum())
+        st = [(float(sm["join_ms"].sum()), int(sm["join_bytes"].sum()), int(sm["join_launches"].sum()),
+               float(sm["sort_ms"].sum()), int(sm["sort_bytes"].sum()))]
+        dm.free_results(res)
         dg.free()
         return tot, st
 
@@ -461,9 +462,8 @@ def main():
     qemb = 0
     for _ in range(args.steps):
         res = dg.enumerate_batch(specs)
-        qemb += sum(r.total for r in res)
-        for r in res:
-            r.free()
+        qemb += int(dm.summarize(res)["total"].sum())
+        dm.free_results(res)
     torch.cuda.synchronize()
     tq = time.perf_counter() - tq
     dg.free()

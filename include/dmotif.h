@@ -315,6 +315,27 @@ typedef struct {
 dm_status dm_result_stats(const dm_result* r, dm_run_stats* out);
 void dm_result_free(dm_result* r);
 
+/* The counts and launch accounting of n results at once (a batch's results,
+ * a server's completions), one call instead of several per result. */
+typedef struct {
+    int64_t total;            /* dm_result_total */
+    int64_t rows;             /* dm_result_rows */
+    double join_ms;           /* the dm_run_stats fields of the same names */
+    double sort_ms;
+    int64_t join_bytes;
+    int64_t sort_bytes;
+    int32_t join_launches;
+    int32_t sort_launches;
+} dm_result_summary;
+
+/* rs: host array of n result handles (none NULL), out: host array of n
+ * summaries, both owned by the caller.  Errors: DM_ERR_INVALID_ARG (NULL
+ * array, n < 0 or a NULL handle; out is then unspecified). */
+dm_status dm_result_summaries(dm_result* const* rs, int32_t n, dm_result_summary* out);
+/* dm_result_free on each of the n handles of the host array rs (NULL
+ * entries are skipped); the array itself stays the caller's. */
+void dm_result_free_many(dm_result* const* rs, int32_t n);
+
 /* Served form: a request loop that keeps the data graph resident, groups
  * queued queries into batches by predicted intermediate-table memory (a
  * query predicted to need more than an eighth of the budget runs alone), and

@@ -124,8 +124,8 @@ EXPORTS = [
     "dm_result_device_costs", "dm_result_copy_costs", "dm_autotune_motifs", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
     "dm_estimate", "dm_enumerate", "dm_enumerate_batch", "dm_result_rows", "dm_result_total",
     "dm_result_width", "dm_result_device_data", "dm_result_hash", "dm_result_copy_to_host",
-    "dm_result_copy_to_device", "dm_result_stats", "dm_result_free", "dm_server_start", "dm_server_submit",
-    "dm_server_wait", "dm_server_stop",
+    "dm_result_copy_to_device", "dm_result_stats", "dm_result_free", "dm_result_summaries",
+    "dm_result_free_many", "dm_server_start", "dm_server_submit", "dm_server_wait", "dm_server_stop",
 ]
 
 
@@ -185,6 +185,8 @@ def lib() -> C.CDLL:
             "dm_result_copy_to_device": (C.c_int, [vp, vp, C.c_int64, vp]),
             "dm_result_stats": (C.c_int, [vp, C.POINTER(RunStats)]),
             "dm_result_free": (None, [vp]),
+            "dm_result_summaries": (C.c_int, [vp, C.c_int32, vp]),
+            "dm_result_free_many": (None, [vp, C.c_int32]),
             "dm_server_start": (C.c_int, [vp, C.POINTER(ServerOpts), C.POINTER(vp)]),
             "dm_server_submit": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_int64, C.POINTER(C.c_uint64)]),
             "dm_server_wait": (C.c_int, [vp, C.c_uint64, C.c_int32, C.POINTER(vp)]),
@@ -219,6 +221,48 @@ def _opts(motif_mask=0, block=0, mode=OUT_TABLE, sync_each_step=False, mem_budge
     return PlanOpts(int(motif_mask) & 0xFFFFFFFF, int(block), int(mode), int(bool(sync_each_step)),
                     int(mem_budget), int(bool(profile)), int(bool(induced)), int(initial_rows), rb, re,
                     int(bool(score)), int(result_mb))
+
+
+class ResultSummary(C.Structure):
+    _fields_ = [("total", C.c_int64), ("rows", C.c_int64), ("join_ms", C.c_double), ("sort_ms", C.c_double),
+                ("join_bytes", C.c_int64), ("sort_bytes", C.c_int64), ("join_launches", C.c_int32),
+                ("sort_launches", C.c_int32)]
+
+
+_SUMMARY_DT = np.dtype({"names": [f[0] for f in ResultSummary._fields_],
+                        "formats": [np.int64, np.int64, np.float64, np.float64, np.int64, np.int64, np.int32,
+                                    np.int32],
+                        "offsets": [getattr(ResultSummary, f[0]).offset for f in ResultSummary._fields_],
+                        "itemsize": C.sizeof(ResultSummary)})
+
+
+def _handles(results) -> np.ndarray:
+    h = np.fromiter(((r._h.value or 0) if r._h else 0 for r in results), dtype=np.uint64, count=len(results))
+    if len(results) and not h.all():
+        raise ValueError("a result was already freed")
+    return h
+
+
+def summarize(results) -> np.ndarray:
+    """``dm_result_summaries``: one record (total, rows, join_ms, sort_ms,
+    join_bytes, sort_bytes, join_launches, sort_launches) per result, in one
+    call."""
+    h = _handles(results)
+    out = np.zeros(len(results), dtype=_SUMMARY_DT)
+    if len(results):
+        _check(lib().dm_result_summaries(C.c_void_p(h.ctypes.data), len(results), C.c_void_p(out.ctypes.data)))
+    return out
+
+
+def free_results(results) -> None:
+    """``dm_result_free_many``: free every result of the list in one call."""
+    live = [r for r in results if r._h]
+    if not live:
+        return
+    h = _handles(live)
+    lib().dm_result_free_many(C.c_void_p(h.ctypes.data), len(live))
+    for r in live:
+        r._h = None
 
 
 def _torch_stream(device: int):

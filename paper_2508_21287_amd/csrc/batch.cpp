@@ -238,13 +238,18 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     DM_TRY(dev_alloc((void**)&A, arena, s));
     std::unique_ptr<DevBlock> arena_guard(new DevBlock{A, s});
 
-    // ---- host staging of sort jobs, controllers and argument blocks
-    std::vector<char> host(arena - off_jobs, 0);
-    SortJob* jobs = (SortJob*)(host.data() + (off_jobs - off_jobs));
-    BatchCtl* ctl = (BatchCtl*)(host.data() + (off_ctl - off_jobs));
-    int32_t* first = (int32_t*)(host.data() + (off_first - off_jobs));
-    int32_t* nsteps = (int32_t*)(host.data() + (off_nsteps - off_jobs));
-    EjfArgs* args = (EjfArgs*)(host.data() + (off_args - off_jobs));
+    // ---- host staging of sort jobs, controllers and argument blocks, built
+    // in the workspace's pinned buffer so the upload is an asynchronous DMA
+    // (from pageable memory it would first be copied and waited for)
+    const size_t host_size = arena - off_jobs;
+    DM_TRY(ws.ensure_stage(std::max(host_size, back_end)));
+    char* host = ws.stage_h;
+    std::memset(host, 0, host_size);
+    SortJob* jobs = (SortJob*)(host + (off_jobs - off_jobs));
+    BatchCtl* ctl = (BatchCtl*)(host + (off_ctl - off_jobs));
+    int32_t* first = (int32_t*)(host + (off_first - off_jobs));
+    int32_t* nsteps = (int32_t*)(host + (off_nsteps - off_jobs));
+    EjfArgs* args = (EjfArgs*)(host + (off_args - off_jobs));
     int a_i = 0;
     const GraphDev g = dg->graph_dev();
     for (int p = 0; p < nb; p++) {
@@ -302,7 +307,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
 
     DM_HIP(launch_fill_u64((uint64_t*)A, 0, (int64_t)(zero_end / 8), s));
     DM_HIP(hipMemcpyAsync(A + off_tops, tops, sizeof tops, hipMemcpyHostToDevice, s));
-    DM_HIP(hipMemcpyAsync(A + off_jobs, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    DM_HIP(hipMemcpyAsync(A + off_jobs, host, host_size, hipMemcpyHostToDevice, s));
 
     hipEvent_t ev[4];
     for (auto& e : ev) DM_HIP(hipEventCreate(&e));
@@ -340,9 +345,10 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     DM_HIP(hipEventRecord(ev[1], s));
 
     // ---- readback 1: counts, flags, hashes, failures, heap use, sort jobs
-    std::vector<char> back(back_end);
-    DM_HIP(hipMemcpyAsync(back.data(), A, back.size(), hipMemcpyDeviceToHost, s));
+    // (through the pinned buffer, queued after the upload that read it)
+    DM_HIP(hipMemcpyAsync(ws.stage_h, A, back_end, hipMemcpyDeviceToHost, s));
     DM_HIP(hipStreamSynchronize(s));
+    std::vector<char> back(ws.stage_h, ws.stage_h + back_end);
     const double t_join = ms_since(t0);
     auto hb = [&](size_t off) { return back.data() + off; };
     const int32_t* hmisc = (const int32_t*)hb(off_misc);

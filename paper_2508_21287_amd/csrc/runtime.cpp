@@ -1699,6 +1699,29 @@ dm_status dm_result_stats(const dm_result* r, dm_run_stats* out) {
     return DM_OK;
 }
 
+dm_status dm_result_summaries(dm_result* const* rs, int32_t n, dm_result_summary* out) {
+    if (n < 0 || (n > 0 && (!rs || !out))) return fail(DM_ERR_INVALID_ARG, "NULL argument or negative count");
+    for (int32_t i = 0; i < n; i++) {
+        const dm_result* r = rs[i];
+        if (!r) return fail(DM_ERR_INVALID_ARG, "NULL result handle");
+        dm_result_summary& o = out[i];
+        o.total = r->total;
+        o.rows = r->rows;
+        o.join_ms = r->stats.join_ms;
+        o.sort_ms = r->stats.sort_ms;
+        o.join_bytes = r->stats.join_bytes;
+        o.sort_bytes = r->stats.sort_bytes;
+        o.join_launches = r->stats.join_launches;
+        o.sort_launches = r->stats.sort_launches;
+    }
+    return DM_OK;
+}
+
+void dm_result_free_many(dm_result* const* rs, int32_t n) {
+    if (!rs) return;
+    for (int32_t i = 0; i < n; i++) dm_result_free(rs[i]);
+}
+
 void dm_result_free(dm_result* r) {
     if (!r) return;
     if (r->block) {

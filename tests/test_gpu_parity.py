@@ -700,3 +700,24 @@ def test_served_config5_sample(ctx):
         r.free()
     srv.stop()
     dg.free()
+
+
+def test_result_summaries(ctx):
+    # the batched accessors agree with the per-result ones, and freeing many
+    # results at once leaves every handle released
+    g, pats = W.config2(8)
+    dg = ctx.datagraph(g.n, g.edges)
+    res = dg.enumerate_batch([(p.n, p.edges) for p in pats], caps=[-1, 5] * 4, profile=True)
+    sm = dm.summarize(res)
+    for r, s in zip(res, sm):
+        st = r.stats()
+        assert s["total"] == r.total and s["rows"] == r.rows
+        assert s["join_bytes"] == st["join_bytes"] and s["sort_bytes"] == st["sort_bytes"]
+        assert s["join_launches"] == st["join_launches"] and s["sort_launches"] == st["sort_launches"]
+        assert s["join_ms"] == st["join_ms"] and s["sort_ms"] == st["sort_ms"]
+    dm.free_results(res)
+    assert all(not r._h for r in res)
+    dm.free_results(res)  # already freed: nothing to do
+    with pytest.raises(ValueError):
+        dm.summarize(res)
+    dg.free()
