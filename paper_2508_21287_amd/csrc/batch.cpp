@@ -266,7 +266,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             EjfArgs& a = args[a_i++];
             std::memset(&a, 0, sizeof a);
             a.st = it.steps[i];
-            if (a.st.motif >= 0) a.tbl = dg->table_dev(a.st.motif, a.st.key_pos);
+            if (a.st.motif >= 0) a.tbl = dg->table_dev_step(a.st);
             a.g = g;
             a.n_in = &counts[i];
             a.id_begin = it.r0;

@@ -17,8 +17,12 @@ struct TableDev {
     const int32_t* offs;
     int64_t rows;
     int32_t size;
-    int32_t pad_;
+    // 1 + the motif position by which the rows of every key group of at most
+    // kGroupSortMax rows are ascending (0: no such order)
+    int32_t sorted_by;
 };
+
+constexpr int kGroupSortMax = 64;
 
 // Normalized data graph: CSR (each list ascending) + optional adjacency bitmap
 // (bit v of row u set iff {u, v} is an edge; words_per_row 32-bit words/row).
@@ -257,6 +261,11 @@ hipError_t launch_claw_count(const int32_t* rp, const int32_t* col, int32_t n, i
                              hipStream_t s);
 hipError_t launch_claw_fill(const int32_t* rp, const int32_t* col, int32_t n, int32_t key_pos, const int32_t* offs,
                             int64_t stride, int32_t* data, hipStream_t s);
+// Sort the rows of every key group of at most kGroupSortMax rows (group v =
+// rows [offs[v], offs[v+1]) of the SoA table data, `size` <= 6 columns of
+// stride `stride`) by column `sec`, stably
+hipError_t launch_group_sort(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec, int32_t* data,
+                             hipStream_t s);
 // *nnz_dev (<= nnz_max) directed edges, read on the device
 hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int64_t nnz_max,
                              int32_t wpr, uint32_t* bitmap, hipStream_t s);

@@ -307,6 +307,27 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             const int32_t key = my[st.key_col];
             lo = a.tbl.offs[key];
             hi = a.tbl.offs[key + 1];
+            if (!LAT && st.n_eq > 0 && a.tbl.sorted_by == st.eq_pos[0] + 1 && hi - lo > 16 &&
+                hi - lo <= kGroupSortMax) {
+                // the key group is ordered by the first further key's position:
+                // keep only its run equal to this row's value (the rest fail that
+                // key anyway, and the test below still checks every candidate)
+                const int32_t* sc = a.tbl.base + (int64_t)st.eq_pos[0] * a.tbl.stride;
+                const int32_t want = my[st.eq_col[0]];
+                int32_t l = lo, h = hi;
+                while (l < h) {
+                    const int32_t mid = (l + h) >> 1;
+                    if (sc[mid] < want) l = mid + 1; else h = mid;
+                }
+                int32_t e = l;
+                h = hi;
+                while (e < h) {
+                    const int32_t mid = (e + h) >> 1;
+                    if (sc[mid] <= want) e = mid + 1; else h = mid;
+                }
+                lo = l;
+                hi = e;
+            }
         } else {
             hi = 1;  // filter-only step: the row itself is the one candidate
         }
@@ -1716,6 +1737,40 @@ hipError_t launch_ingest_compact(const int32_t* tmp_ptr, const int32_t* tmp, con
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(ingest_compact_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, tmp_ptr, tmp, row_ptr, n, col,
                        src, max_deg);
+    return hipGetLastError();
+}
+
+// ---- key groups ordered by a second position: one thread per group,
+// stable insertion sort (groups of at most kGroupSortMax rows)
+__global__ void group_sort_kernel(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec,
+                                  int32_t* data) {
+    const int32_t* key = data + (int64_t)sec * stride;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = offs[v], b = offs[v + 1];
+        if (b - a < 2 || b - a > kGroupSortMax) continue;
+        for (int32_t i = a + 1; i < b; i++) {
+            int32_t row[6];
+#pragma unroll
+            for (int q = 0; q < 6; q++) row[q] = q < size ? data[(int64_t)q * stride + i] : 0;
+            const int32_t x = key[i];
+            int32_t j = i - 1;
+            while (j >= a && key[j] > x) {
+#pragma unroll
+                for (int q = 0; q < 6; q++)
+                    if (q < size) data[(int64_t)q * stride + j + 1] = data[(int64_t)q * stride + j];
+                j--;
+            }
+#pragma unroll
+            for (int q = 0; q < 6; q++)
+                if (q < size) data[(int64_t)q * stride + j + 1] = row[q];
+        }
+    }
+}
+
+hipError_t launch_group_sort(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec, int32_t* data,
+                             hipStream_t s) {
+    if (n <= 0 || size > 6 || sec < 0 || sec >= size) return hipSuccess;
+    hipLaunchKernelGGL(group_sort_kernel, dim3(grid_for(n, 64)), dim3(64), 0, s, offs, n, stride, size, sec, data);
     return hipGetLastError();
 }
 

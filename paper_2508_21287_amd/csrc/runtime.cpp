@@ -345,7 +345,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             EjfArgs a;
             std::memset(&a, 0, sizeof a);
             a.st = steps[i];
-            if (a.st.motif >= 0) a.tbl = dg->table_dev(a.st.motif, a.st.key_pos);
+            if (a.st.motif >= 0) a.tbl = dg->table_dev_step(a.st);
             a.g = dg->graph_dev();
             a.in = i == 0 ? nullptr : ws.buf[ib];
             a.in_stride = i == 0 ? 0 : cap[ib];
@@ -718,6 +718,17 @@ dm::TableDev dm_datagraph::table_dev(int motif, int key_pos) const {
     t.offs = m.offs;
     t.rows = m.rows;
     t.size = m.size;
+    t.sorted_by = 0;
+    return t;
+}
+
+dm::TableDev dm_datagraph::table_dev_step(const dm::StepDesc& st) const {
+    TableDev t = table_dev(st.motif, st.key_pos);
+    const MotifTable& m = tab[st.motif][st.key_pos];
+    if (st.n_eq > 0 && m.sec_base && m.sorted_by == st.eq_pos[0] + 1) {
+        t.base = m.sec_base;
+        t.sorted_by = m.sorted_by;
+    }
     return t;
 }
 
@@ -787,7 +798,7 @@ static void free_tables(dm_datagraph* dg) {
     for (int m = 0; m < kNumMotifs; m++)
         for (int j = 0; j < 6; j++) {
             MotifTable& t = dg->tab[m][j];
-            for (int q = 0; q < 2; q++) dev_free(t.owned[q], s);
+            for (int q = 0; q < 3; q++) dev_free(t.owned[q], s);
             t = MotifTable();
         }
 }
@@ -797,7 +808,7 @@ static void free_motif(dm_datagraph* dg, int m) {
     hipStream_t s = dg->ctx->stream;
     for (int j = 0; j < 6; j++) {
         MotifTable& t = dg->tab[m][j];
-        for (int q = 0; q < 2; q++) dev_free(t.owned[q], s);
+        for (int q = 0; q < 3; q++) dev_free(t.owned[q], s);
         t = MotifTable();
     }
     dg->motif_bits &= ~(1u << m);
@@ -951,6 +962,20 @@ static dm_status build_motif(dm_datagraph* dg, int m) {
         for (int q = 0; q < mi.size; q++) t.cols[q] = data + (size_t)q * (size_t)t.stride;
         DM_HIP(launch_offsets(t.cols[j], n_dev, ro.rows, dg->n, offs, s));
         t.offs = offs;
+        if (!mi.general && !mi.cycle && j == 0 && mi.size >= 3 && mi.size <= 6 && ro.rows > 0) {
+            // a path keyed at one end: a second copy with each key group ordered by
+            // the other end, so a join that knows both ends (a cycle's closing step)
+            // can binary-search it; the table itself keeps the joins' order (paths
+            // extended from it come out in label order, which the sort skips)
+            int32_t* sec = nullptr;
+            const size_t bytes = sizeof(int32_t) * (size_t)t.stride * (size_t)mi.size;
+            DM_TRY(dev_alloc((void**)&sec, bytes, s));
+            t.owned[2] = sec;
+            DM_HIP(hipMemcpyAsync(sec, data, bytes, hipMemcpyDeviceToDevice, s));
+            DM_HIP(launch_group_sort(offs, dg->n, t.stride, mi.size, mi.size - 1, sec, s));
+            t.sec_base = sec;
+            t.sorted_by = mi.size;
+        }
     }
     dg->motif_bits |= 1u << m;
     dg->mask_built |= mi.bit;

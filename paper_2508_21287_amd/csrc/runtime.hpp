@@ -95,7 +95,11 @@ struct MotifTable {
     int32_t* offs = nullptr;        // n_vertices + 1
     int64_t rows = 0;
     int32_t size = 0;
-    int32_t* owned[2] = {nullptr, nullptr};  // allocations to free (data, offs)
+    // A second copy of the rows (same offsets) whose key groups are ordered
+    // by position sorted_by - 1, for steps whose first further key sits there
+    int32_t* sec_base = nullptr;
+    int32_t sorted_by = 0;
+    int32_t* owned[3] = {nullptr, nullptr, nullptr};  // allocations to free (data, offs, second copy)
 };
 
 struct DataGraph;
@@ -139,6 +143,9 @@ struct dm_datagraph {
         return g;
     }
     dm::TableDev table_dev(int motif, int key_pos) const;
+    // the table a join step reads: the second copy when it is ordered by the
+    // step's first further key
+    dm::TableDev table_dev_step(const dm::StepDesc& st) const;
 };
 
 struct dm_result {
