@@ -227,11 +227,12 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.v_begin = v0;
     L.dup_count = &counters[3];
     L.max_chunks = &counters[2];
-    // tier 1: small LDS tiles, five workgroups per CU; one workgroup per
-    // (job, root) item up to 65536 of them, so the hardware dispatcher, which
-    // starts a workgroup as soon as one finishes, balances the very uneven
-    // segments (a workgroup dealt two large ones would set the launch's length)
-    L.lds_bytes = 32 * 1024 - 512;
+    // tier 1: small LDS tiles (16 KB: swept on the benchmark against 8-48 KB,
+    // more resident workgroups beat holding larger segments here); one
+    // workgroup per (job, root) item up to 65536 of them, so the hardware
+    // dispatcher, which starts a workgroup as soon as one finishes, balances
+    // the very uneven segments
+    L.lds_bytes = 16 * 1024 - 512;
     L.list = nullptr;
     L.spill = ws.spill;
     L.spill_n = &counters[0];
