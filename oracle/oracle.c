@@ -414,9 +414,17 @@ int64_t oracle_normalize(int32_t n, int64_t m, const int32_t *edges,
     adj_t g;
     int rc = build_adj(n, m, edges, 1, &g);
     if (rc) return rc;
+#if ORACLE_MUTANT == 12
+    memcpy(row_ptr, g.row_ptr, sizeof(int32_t) * (size_t)n); /* last offset left out */
+#else
     memcpy(row_ptr, g.row_ptr, sizeof(int32_t) * ((size_t)n + 1));
+#endif
     int64_t nnz = g.row_ptr[n];
+#if ORACLE_MUTANT == 13
+    if (nnz > 1) memcpy(col, g.col + 1, sizeof(int32_t) * (size_t)(nnz - 1)); /* lists shifted by one */
+#else
     if (nnz) memcpy(col, g.col, sizeof(int32_t) * (size_t)nnz);
+#endif
     adj_free(&g);
     return nnz;
 }

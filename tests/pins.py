@@ -577,6 +577,39 @@ def pin_scored(lib):
         assert e.code == -1
 
 
-ALL_PINS = [pin_brute_force, pin_cycle_paths, pin_self_embedding, pin_heavy_hex_cells,
+def pin_normalize(lib):
+    """The exported CSR (the checker of the GPU ingest) against a set-based
+    construction written from the definition of Res(M2) in Sec. III-D: both
+    orientations of every edge, self-loops dropped, repeats merged, each
+    vertex's list ascending.  Also the degree histogram of the tiny heavy-hex
+    lattice ({1: 2, 2: 24, 3: 6}) and the degree sum 2|E| of loop-free
+    inputs."""
+    rng = np.random.default_rng(7)
+    cases = [W.heavy_hex(3, 9), W.grid(5, 6), W.Graph(6, np.zeros((0, 2), np.int32), "empty"),
+             W.Graph(4, np.array([[2, 2], [3, 3]], np.int32), "loops only")]
+    for seed in range(6):
+        base = W.random_gnp(25 + 3 * seed, 0.15, seed)
+        extra = [[v, v] for v in rng.integers(0, base.n, 3)]  # self-loops
+        e = np.vstack([base.edges, np.asarray(extra, np.int32), base.edges[: 5 + seed, ::-1],
+                       base.edges[: 3 + seed]])  # reversed and plain repeats
+        cases.append(W.Graph(base.n + 2, e[rng.permutation(len(e))], f"gnp{seed}+noise"))  # 2 isolated at the end
+    for g in cases:
+        rp, col = oracle.normalize(g.n, g.edges, lib=lib)
+        adj = _adjset(g.n, g.edges)
+        want = [sorted(v for (u, v) in adj if u == x) for x in range(g.n)]
+        deg = np.array([len(w) for w in want], dtype=np.int64)
+        assert len(rp) == g.n + 1 and rp[0] == 0, g.name
+        assert np.array_equal(np.diff(rp.astype(np.int64)), deg), g.name
+        assert int(rp[-1]) == len(col) == len(adj), g.name
+        flat = [v for w in want for v in w]
+        assert col.tolist() == flat, g.name
+    hh = oracle.normalize(32, W.heavy_hex(3, 9).edges, lib=lib)[0]
+    hist = np.bincount(np.diff(hh))
+    assert hist.tolist() == [0, 2, 24, 6], hist
+    gr = W.grid(5, 6)
+    assert int(oracle.normalize(gr.n, gr.edges, lib=lib)[0][-1]) == 2 * len(gr.edges)
+
+
+ALL_PINS = [pin_normalize, pin_brute_force, pin_cycle_paths, pin_self_embedding, pin_heavy_hex_cells,
             pin_degree_sums, pin_grid_closed_forms, pin_nonbacktracking, pin_tree_dp,
             pin_invariants, pin_cap, pin_edge_cases, pin_hash, pin_root_ranges, pin_induced, pin_scored]
