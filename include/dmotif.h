@@ -40,8 +40,14 @@
  *  - Work is stream-ordered on the context's HIP stream.  dm_enumerate
  *    returns once the row count is known on the host (one device->host
  *    sync); the device table is complete when the stream reaches that point.
- *  - Threading: a context (and the data graphs built on it) is used by one
- *    host thread at a time; a server is internally synchronized.
+ *  - Threading: a context is used by one host thread at a time (its calls
+ *    share the context's workspace).  A data graph is only read by the
+ *    enumeration calls, so a server's worker threads (each with a workspace
+ *    and stream of its own) and the context's thread may enumerate on it at
+ *    once; the calls that change or release it (dm_datagraph_set_costs,
+ *    dm_datagraph_free) return DM_ERR_BUSY while a server holds it.  A
+ *    server is internally synchronized; dm_context_cancel may be called from
+ *    any thread.
  */
 #ifndef DMOTIF_H
 #define DMOTIF_H
@@ -138,6 +144,12 @@ typedef struct {
                               as the rows produced so far pass it.  0 = no limit but device memory:
                               a result assembled from root-range parts needs its bytes twice (the
                               parts, then the one result buffer) next to mem_budget of tables. */
+    int32_t wait_limit_us; /* bound, in microseconds, of every device-side wait of the run (a
+                              look-back on a predecessor tile, the persistent scheduler waiting for
+                              work): when the device clock advances this long with no progress the
+                              wait gives up, the run's remaining launches do nothing and the call
+                              fails with DM_ERR_DEVICE naming the wait (pattern, step, tile,
+                              polls); the context stays usable.  0 = 10 s. */
 } dm_plan_opts;
 
 typedef struct dm_context dm_context;
@@ -151,12 +163,42 @@ const char* dm_version(void);
 /* Thread-local description of the most recent failure on this thread. */
 const char* dm_last_error(void);
 
+/* Device-memory allocator of a context.  alloc returns `bytes` of device
+ * memory usable by work ordered on `stream` (a hipStream_t), or NULL on
+ * failure; free returns a pointer alloc gave, after the work already queued
+ * on `stream` (stream-ordered, like hipFreeAsync).  `user` is passed back to
+ * both.  Both callbacks may be called from any thread that uses the context
+ * (server worker threads included) and must be thread-safe.  Every device
+ * buffer the library holds (tables, workspaces, results) comes from it;
+ * pinned host staging buffers do not. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* ptr, void* stream, void* user);
+    void* user;
+} dm_allocator;
+
 /* Create a context on HIP device `device`, issuing work on `hip_stream`
- * (a hipStream_t; NULL = a stream the context creates and owns).
- * Errors: DM_ERR_INVALID_ARG (bad device / out == NULL), DM_ERR_DEVICE. */
-dm_status dm_context_create(int32_t device, void* hip_stream, dm_context** out);
+ * (a hipStream_t; NULL = a stream the context creates and owns).  `alloc`
+ * (copied; may be NULL = stream-ordered allocation from the device's default
+ * memory pool) supplies every device buffer of the context and of the data
+ * graphs, results and servers made from it; a NULL return from alloc.alloc
+ * makes the call that needed the memory fail with DM_ERR_OUT_OF_MEMORY,
+ * freeing what that call had taken, and leaves the context usable.
+ * Errors: DM_ERR_INVALID_ARG (bad device, out == NULL, an allocator with a
+ * NULL callback -- checked before any device call), DM_ERR_DEVICE. */
+dm_status dm_context_create(int32_t device, void* hip_stream, const dm_allocator* alloc, dm_context** out);
 /* Free data graphs, results and servers created on a context before destroying it. */
 void dm_context_destroy(dm_context* ctx);
+
+/* Set (flag != 0) or clear the context's cancel word.  While it is set,
+ * dm_enumerate and dm_enumerate_batch calls on the context (and on servers
+ * of its data graphs) fail with DM_ERR_CANCELLED, and kernels of the
+ * context that are waiting -- the persistent batch kernel at its start and
+ * while idle, any look-back -- give up and leave normally, so a running
+ * call returns DM_ERR_CANCELLED without leaving work on the device.  The word
+ * stays set until cleared.  Callable from any thread (one host store into
+ * host-coherent memory the kernels poll).  Errors: DM_ERR_INVALID_ARG. */
+dm_status dm_context_cancel(dm_context* ctx, int32_t flag);
 
 /* Algorithm 2 (BuildDatabase): normalize `gd` into device CSR + adjacency
  * bitmap and build the motif tables selected by `motif_mask` (DM_MOTIF_*),
@@ -167,8 +209,9 @@ void dm_context_destroy(dm_context* ctx);
 dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t motif_mask,
                              dm_datagraph** out);
 /* Release the data graph's device memory, ordered after the work already
- * queued on the context stream (no wait).  Stop any server using it first. */
-void dm_datagraph_free(dm_datagraph* dg);
+ * queued on the context stream (no wait).  Errors: DM_ERR_BUSY (a server
+ * started on it has not been stopped; nothing is released). */
+dm_status dm_datagraph_free(dm_datagraph* dg);
 
 typedef struct {
     int32_t n_vertices;
@@ -225,7 +268,8 @@ dm_status dm_datagraph_load(dm_context* ctx, const char* path, dm_datagraph** ou
  * Costs are non-negative integers (for fidelities: fixed-point -log values),
  * summed exactly in 64 bits.  Replaces earlier costs; host arrays are copied.
  * Errors: DM_ERR_INVALID_ARG (NULL, a listed pair that is not an edge of the
- * graph or is listed twice), DM_ERR_OUT_OF_MEMORY, DM_ERR_DEVICE. */
+ * graph or is listed twice), DM_ERR_BUSY (a server holds the graph),
+ * DM_ERR_OUT_OF_MEMORY, DM_ERR_DEVICE. */
 dm_status dm_datagraph_set_costs(dm_datagraph* dg, const uint32_t* vertex_cost, int64_t n_cost_edges,
                                  const int32_t* cost_edges, const uint32_t* edge_cost);
 

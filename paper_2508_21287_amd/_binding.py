@@ -92,7 +92,8 @@ class PlanOpts(C.Structure):
     _fields_ = [("motif_mask", C.c_uint32), ("block_threads", C.c_int32), ("output_mode", C.c_int32),
                 ("sync_each_step", C.c_int32), ("mem_budget", C.c_int64), ("profile", C.c_int32),
                 ("induced", C.c_int32), ("initial_rows", C.c_int64), ("root_begin", C.c_int32),
-                ("root_end", C.c_int32), ("score", C.c_int32), ("result_mb", C.c_int32)]
+                ("root_end", C.c_int32), ("score", C.c_int32), ("result_mb", C.c_int32),
+                ("wait_limit_us", C.c_int32)]
 
 
 class DataGraphInfo(C.Structure):
@@ -114,12 +115,22 @@ class ServerOpts(C.Structure):
                 ("max_queue", C.c_int32)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """``dm_allocator``: device-memory callbacks of a context."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
 _lock = threading.Lock()
 _LIB = None
 
 # Every symbol include/dmotif.h declares (checked by the CPU test suite).
 EXPORTS = [
-    "dm_version", "dm_last_error", "dm_context_create", "dm_context_destroy", "dm_datagraph_build",
+    "dm_version", "dm_last_error", "dm_context_create", "dm_context_destroy", "dm_context_cancel",
+    "dm_datagraph_build",
     "dm_datagraph_free", "dm_datagraph_save", "dm_datagraph_load", "dm_datagraph_set_costs",
     "dm_result_device_costs", "dm_result_copy_costs", "dm_autotune_motifs", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
     "dm_estimate", "dm_enumerate", "dm_enumerate_batch", "dm_result_rows", "dm_result_total",
@@ -153,10 +164,11 @@ def lib() -> C.CDLL:
         sig = {
             "dm_version": (C.c_char_p, []),
             "dm_last_error": (C.c_char_p, []),
-            "dm_context_create": (C.c_int, [C.c_int32, vp, C.POINTER(vp)]),
+            "dm_context_create": (C.c_int, [C.c_int32, vp, C.POINTER(Allocator), C.POINTER(vp)]),
             "dm_context_destroy": (None, [vp]),
+            "dm_context_cancel": (C.c_int, [vp, C.c_int32]),
             "dm_datagraph_build": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_uint32, C.POINTER(vp)]),
-            "dm_datagraph_free": (None, [vp]),
+            "dm_datagraph_free": (C.c_int, [vp]),
             "dm_datagraph_save": (C.c_int, [vp, C.c_char_p]),
             "dm_autotune_motifs": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_int32, C.POINTER(GraphDesc),
                                              C.POINTER(C.c_uint32), C.c_int32, C.c_int32, C.POINTER(C.c_uint32),
@@ -216,11 +228,11 @@ class _Graph:
 
 def _opts(motif_mask=0, block=0, mode=OUT_TABLE, sync_each_step=False, mem_budget=0,
           profile=False, initial_rows=0, root_range=None, induced=False, score=False,
-          result_mb=0) -> PlanOpts:
+          result_mb=0, wait_limit_us=0) -> PlanOpts:
     rb, re = (0, 0) if root_range is None else (int(root_range[0]), int(root_range[1]))
     return PlanOpts(int(motif_mask) & 0xFFFFFFFF, int(block), int(mode), int(bool(sync_each_step)),
                     int(mem_budget), int(bool(profile)), int(bool(induced)), int(initial_rows), rb, re,
-                    int(bool(score)), int(result_mb))
+                    int(bool(score)), int(result_mb), int(wait_limit_us))
 
 
 class ResultSummary(C.Structure):
@@ -277,9 +289,15 @@ def _torch_stream(device: int):
 
 class Context:
     """``dm_context_create``: a device plus the HIP stream all work is ordered
-    on (default: torch's current stream on that device)."""
+    on (default: torch's current stream on that device).
 
-    def __init__(self, device: int = 0, stream=None):
+    ``allocator``: optional ``(alloc, free)`` pair of Python callables,
+    ``alloc(nbytes, stream) -> int`` (a device pointer, 0 = failure) and
+    ``free(ptr, stream)``, through which the library takes every device
+    buffer (``dm_allocator``); they may be called from the library's server
+    threads."""
+
+    def __init__(self, device: int = 0, stream=None, allocator=None):
         L = lib()
         self.device = device
         if stream is None:
@@ -290,7 +308,30 @@ class Context:
             s = C.c_void_p(int(stream))
         self._h = C.c_void_p()
         self._children = weakref.WeakSet()
-        _check(L.dm_context_create(device, s, C.byref(self._h)))
+        self._alloc = None
+        if allocator is not None:
+            fa, ff = allocator
+
+            def _a(nbytes, stream, _user):
+                try:
+                    return int(fa(int(nbytes), int(stream or 0)) or 0) or None
+                except Exception:
+                    return None
+
+            def _f(ptr, stream, _user):
+                try:
+                    ff(int(ptr or 0), int(stream or 0))
+                except Exception:
+                    pass
+
+            # the callbacks must outlive the context: keep them on it
+            self._alloc = Allocator(_ALLOC_FN(_a), _FREE_FN(_f), None)
+        _check(L.dm_context_create(device, s, C.byref(self._alloc) if self._alloc is not None else None,
+                                   C.byref(self._h)))
+
+    def cancel(self, flag: bool = True) -> None:
+        """``dm_context_cancel``: set or clear the context's cancel word."""
+        _check(lib().dm_context_cancel(self._h, int(bool(flag))))
 
     @property
     def handle(self):
@@ -529,7 +570,7 @@ class DataGraph:
 
     def free(self):
         if self._h:
-            lib().dm_datagraph_free(self._h)
+            _check(lib().dm_datagraph_free(self._h))
             self._h = C.c_void_p()
 
     _release = free

@@ -122,9 +122,10 @@ class HostPool {
 };
 
 struct DevBlock {
+    const dm_context* ctx = nullptr;
     void* p = nullptr;
-    hipStream_t s = nullptr;
-    ~DevBlock() { dev_free(p, s); }
+    hipStream_t s = nullptr;  // stream the free is ordered on
+    ~DevBlock() { dev_free(ctx, p, s); }
 };
 
 struct Item {
@@ -215,8 +216,11 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         it.off_hash = arena;
         arena = align256(arena + sizeof(uint64_t) * 4);
     }
-    const size_t off_misc = arena;  // finished, sort counters (spill_n[2], max_chunks, dup)
+    // finished, sort counters (spill_n[2], max_chunks, dup), abort word, tiles done
+    const size_t off_misc = arena;
     arena = align256(arena + 64);
+    const size_t off_diag = arena;  // the record of a wait that gave up
+    arena = align256(arena + sizeof(WaitDiag));
     const size_t off_fail = arena;
     arena = align256(arena + sizeof(int32_t) * nb);
     const size_t off_tops = arena;  // heap top, words top
@@ -235,8 +239,8 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     arena = align256(arena + sizeof(EjfArgs) * total_steps);
 
     char* A = nullptr;
-    DM_TRY(dev_alloc((void**)&A, arena, s));
-    std::unique_ptr<DevBlock> arena_guard(new DevBlock{A, s});
+    DM_TRY(dev_alloc(ctx, (void**)&A, arena, s));
+    std::unique_ptr<DevBlock> arena_guard(new DevBlock{ctx, A, s});
 
     // ---- host staging of sort jobs, controllers and argument blocks, built
     // in the workspace's pinned buffer so the upload is an asynchronous DMA
@@ -278,6 +282,10 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
             a.mode = (hash_mode && i == ns - 1) ? EJF_HASH : EJF_WRITE;
             a.hash_acc = (uint64_t*)(A + it.off_hash);
             a.induced = opts && opts->induced ? 1 : 0;
+            a.w = wait_ctl(ctx, (uint32_t*)(A + off_misc) + 5, (WaitDiag*)(A + off_diag),
+                           opts ? opts->wait_limit_us : 0);
+            a.diag_pattern = it.idx;
+            a.diag_step = i;
             for (int c = 0; c < it.k; c++) a.pv[c] = (uint8_t)std::max(it.plan.pv_of[c], 0);
             if (i + 1 < ns && !(hash_mode && i + 1 == ns - 1)) {
                 const StepDesc& nx = it.steps[i + 1];
@@ -336,6 +344,8 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     bd.row_limit = row_limit;
     bd.n_patterns = nb;
     bd.max_backoff = env_int("DMOTIF_BATCH_BACKOFF", 15);
+    bd.w = wait_ctl(ctx, (uint32_t*)&misc[5], (WaitDiag*)(A + off_diag), opts ? opts->wait_limit_us : 0);
+    bd.tiles_done = (uint32_t*)&misc[6];
     const double t_stage = ms_since(t0);
     DM_HIP(hipEventRecord(ev[0], s));
     bool wide = false;
@@ -352,6 +362,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     const double t_join = ms_since(t0);
     auto hb = [&](size_t off) { return back.data() + off; };
     const int32_t* hmisc = (const int32_t*)hb(off_misc);
+    DM_TRY(check_abort((uint32_t)hmisc[5], *(const WaitDiag*)hb(off_diag), "persistent join"));
     if (hmisc[0] != nb) return fail(DM_ERR_INTERNAL, "persistent kernel retired " + std::to_string(hmisc[0]) +
                                                          " of " + std::to_string(nb) + " patterns");
     const int32_t* hfail = (const int32_t*)hb(off_fail);
@@ -429,16 +440,17 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     double t_ralloc = 0;
     if (!hash_mode && resb > 0) {
         const auto ta = std::chrono::steady_clock::now();
-        DM_TRY(dev_alloc((void**)&R, resb, s));
+        DM_TRY(dev_alloc(ctx, (void**)&R, resb, s));
         t_ralloc = ms_since(ta);
-        res_block.reset(new DevBlock{R, s});
+        res_block.reset(new DevBlock{ctx, R, s});
         for (int p = 0; p < nb; p++) {
             if (items[p].out_rows > 0) hjobs[p].out = (int32_t*)(R + items[p].off_res);
             hjobs[p].out_rows = items[p].out_rows;
         }
         DM_HIP(hipMemcpyAsync(A + off_jobs, hjobs, sizeof(SortJob) * nb, hipMemcpyHostToDevice, s));
         DM_HIP(hipEventRecord(ev[2], s));
-        DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, max_rows, max_wp, &misc[1]));
+        DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, max_rows, max_wp, &misc[1],
+                            (const uint32_t*)&misc[5]));
         DM_HIP(hipEventRecord(ev[3], s));
         int32_t sc[4];
         DM_HIP(hipMemcpyAsync(sc, &misc[1], sizeof sc, hipMemcpyDeviceToHost, s));
@@ -672,6 +684,10 @@ dm_status enumerate_many(dm_datagraph* dg, Workspace& ws, int32_t n, const dm_gr
         return st;
     }
     for (size_t j = 0; j < items.size(); j++) done[items[j].idx] = res[j];
+    if (!solo.empty() && __atomic_load_n(dg->ctx->cancel, __ATOMIC_SEQ_CST)) {
+        cleanup();
+        return fail(DM_ERR_CANCELLED, "context is cancelled");
+    }
     for (int32_t i : solo) {
         st = enumerate_one(dg, ws, &gps[i], caps ? caps[i] : -1, opts, &done[i]);
         if (st != DM_OK) {
@@ -717,7 +733,7 @@ extern "C" dm_status dm_autotune_motifs(dm_context* ctx, const dm_graph_desc* gd
             DM_TRY(dm_datagraph_build(ctx, gd, candidates[c], &dg));
             dm_status st = enumerate_many(dg, ctx->ws, n_sample, sample, nullptr, &opts, outs.data());
             for (auto*& o : outs) dm_result_free(o), o = nullptr;
-            dm_datagraph_free(dg);
+            (void)dm_datagraph_free(dg);
             if (st != DM_OK) return st;
             t.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
         }
@@ -833,7 +849,12 @@ static void server_worker(dm_server* s, int w) {
                 // the worker synchronized its stream, so the table is complete;
                 // later copies and the free are ordered on the context stream,
                 // which outlives the server's own streams
-                if (outs[i]) outs[i]->stream = s->dg->ctx->stream;
+                if (outs[i]) {
+                    outs[i]->stream = s->dg->ctx->stream;
+                    // a batch's results share one block: its free follows the
+                    // context stream too, which outlives the worker streams
+                    if (outs[i]->block) static_cast<DevBlock*>(outs[i]->block.get())->s = s->dg->ctx->stream;
+                }
                 r->result = r->status == DM_OK ? outs[i] : nullptr;
                 if (r->status != DM_OK && outs[i]) dm_result_free(outs[i]);
                 r->done = true;
@@ -871,7 +892,7 @@ dm_status dm_server_start(dm_datagraph* dg, const dm_server_opts* opts, dm_serve
         }
         s->streams.push_back(st);
         auto w = std::make_unique<Workspace>();
-        dm_status e = w->init(st);
+        dm_status e = w->init(dg->ctx, st);
         if (e != DM_OK) {
             w->release();
             for (auto& x : s->ws) x->release();
@@ -881,6 +902,7 @@ dm_status dm_server_start(dm_datagraph* dg, const dm_server_opts* opts, dm_serve
         }
         s->ws.push_back(std::move(w));
     }
+    dg->servers.fetch_add(1);
     for (int i = 0; i < o.n_streams; i++) s->workers.emplace_back(server_worker, s, i);
     *out = s;
     return DM_OK;
@@ -954,6 +976,7 @@ dm_status dm_server_stop(dm_server* s) {
     s->live.clear();
     for (auto& w : s->ws) w->release();
     for (auto x : s->streams) (void)hipStreamDestroy(x);
+    s->dg->servers.fetch_sub(1);
     delete s;
     return DM_OK;
 }

@@ -34,6 +34,35 @@ struct GraphDev {
     int32_t words_per_row;
 };
 
+// Bounded waits.  Every spin of a kernel (a look-back on a predecessor
+// tile, the persistent scheduler waiting for work) gives up when the device
+// wall clock has advanced `limit` ticks without progress, or at once when the
+// context's cancel word (host memory, set by dm_context_cancel) or the run's
+// abort word is set.  The first wait to give up records what it waited for in
+// `diag` and sets `abort`; every workgroup then leaves its loop normally and
+// the kernels still to come in the run return at entry, so the host sees the
+// record after its next readback instead of a device that never finishes.
+enum { WAIT_NONE = 0, WAIT_LOOKBACK = 1, WAIT_IDLE = 2, WAIT_CANCEL = 3 };
+
+struct WaitDiag {
+    int32_t reason;     // WAIT_*
+    int32_t pattern;    // batch item of the wait (-1: a single-pattern run)
+    int32_t step;       // join step (idle waits: the stage of the first unfinished pattern)
+    int32_t ntiles;     // tiles of that step
+    int64_t tile;       // tile that waited (look-back) or -1
+    int64_t spins;      // polls before giving up
+    int64_t ticks;      // wall-clock ticks waited
+    int32_t claimed;    // idle waits: tiles of that step claimed / finished so far
+    int32_t finished;
+};
+
+struct WaitCtl {
+    uint32_t* abort;         // run's abort word (device, zeroed by the host before the run)
+    WaitDiag* diag;          // written once, by the wait that set `abort`
+    const uint32_t* cancel;  // context's cancel word (host-coherent memory; nullptr = none)
+    uint64_t limit;          // wall-clock ticks a wait may last without progress
+};
+
 enum { EJF_WRITE = 0, EJF_HASH = 1 };
 
 // One join-filter launch.  Input table: `in` SoA with column stride
@@ -80,6 +109,9 @@ struct EjfArgs {
     const uint32_t* ecost;
     const uint64_t* in_cost;
     uint64_t* out_cost;
+    WaitCtl w;            // bounded look-back (see WaitCtl)
+    int32_t diag_pattern; // batch item and step named by a wait that gives up
+    int32_t diag_step;
     uint8_t pv[kMaxCols]; // EJF_HASH: pattern vertex of each output column
 };
 
@@ -142,6 +174,7 @@ struct SortLaunch {
     int32_t* dup_count;
     int32_t* max_chunks;  // merge tier: most LDS chunks of any listed segment
     int32_t pass;         // merge tier: pass number of a merge launch
+    const uint32_t* abort;// nonzero: a wait of the run gave up; the launch does nothing
 };
 
 // Packed rows of wp 64-bit words that an LDS tile of lds_bytes holds
@@ -191,6 +224,8 @@ struct BatchDev {
     int64_t row_limit;     // > 0: cap every step's output capacity (forces the overflow path)
     int32_t n_patterns;
     int32_t max_backoff;   // idle polling backoff cap (units of s_sleep(16))
+    WaitCtl w;             // bounded idle waits (progress = tiles_done advancing)
+    uint32_t* tiles_done;  // tiles finished by every workgroup so far
 };
 
 // Top-k by (cost, table position): radix selection of the k-th key, then a
@@ -244,7 +279,7 @@ hipError_t launch_gather_cols(const int32_t* in, int64_t in_stride, const int64_
 hipError_t launch_ingest_count(const int32_t* edges, int64_t m, int32_t n, int32_t* deg, int32_t* err,
                                hipStream_t s);
 hipError_t launch_scan_i32(const int32_t* in, int32_t* out_excl, int64_t n, int64_t* total,
-                           uint64_t* status, uint64_t* ticket, hipStream_t s);
+                           uint64_t* status, uint64_t* ticket, const WaitCtl& w, hipStream_t s);
 // edges with an endpoint outside [0, n) are skipped (ingest_count flags them)
 hipError_t launch_ingest_scatter(const int32_t* edges, int64_t m, int32_t n, const int32_t* ptr, int32_t* cursor,
                                  int32_t* tmp, hipStream_t s);

@@ -39,11 +39,42 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
+__device__ __forceinline__ uint32_t ld_rlx_u32(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The context's cancel word lives in host memory written by the host.
+__device__ __forceinline__ uint32_t ld_sys_u32(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Give up a wait (one lane calls this): the first wait of the run to give up
+// sets the abort word and writes the record; later ones only leave.
+__device__ void wait_give_up(const WaitCtl& w, int32_t reason, int32_t pattern, int32_t step, int32_t ntiles,
+                             int64_t tile, int64_t spins, uint64_t ticks, int32_t claimed, int32_t finished) {
+    if (atomicCAS(w.abort, 0u, (uint32_t)reason) != 0u) return;
+    WaitDiag* d = w.diag;
+    d->reason = reason;
+    d->pattern = pattern;
+    d->step = step;
+    d->ntiles = ntiles;
+    d->tile = tile;
+    d->spins = spins;
+    d->ticks = (int64_t)ticks;
+    d->claimed = claimed;
+    d->finished = finished;
+    __threadfence();
+}
+
 // Decoupled look-back (single-pass chained scan) executed by one full wave.
 // Tiles are claimed in ticket order by running workgroups, so every
 // predecessor of `tile` is owned by a workgroup that is already running and
-// will publish; the wait always ends.  Returns the exclusive prefix.
-__device__ int64_t lookback_wave(uint64_t* status, uint32_t epoch, int64_t tile, uint64_t agg, int lane) {
+// publishes its aggregate before it waits itself: the wait ends.  It is
+// bounded all the same (see WaitCtl): after `w.limit` wall-clock ticks, or
+// once the run's abort word or the context's cancel word is set, it gives up
+// and returns -1 (the caller then writes nothing).  Else returns the
+// exclusive prefix.
+__device__ int64_t lookback_wave(uint64_t* status, uint32_t epoch, int64_t tile, uint64_t agg, int lane,
+                                 const WaitCtl& w, int32_t pattern, int32_t step) {
     if (tile == 0) {
         if (lane == 0) st_relaxed(&status[0], lb_pack(epoch, 2, agg));
         return 0;
@@ -51,6 +82,8 @@ __device__ int64_t lookback_wave(uint64_t* status, uint32_t epoch, int64_t tile,
     if (lane == 0) st_relaxed(&status[tile], lb_pack(epoch, 1, agg));
     uint64_t excl = 0;
     int64_t j = tile - 1;
+    int64_t spins = 0;
+    uint64_t t0 = 0;
     for (;;) {
         const int64_t idx = j - lane;
         uint32_t flag = 2;
@@ -65,6 +98,23 @@ __device__ int64_t lookback_wave(uint64_t* status, uint32_t epoch, int64_t tile,
         const int p = pm ? (__ffsll((long long)pm) - 1) : 63;
         const uint64_t range = (p == 63) ? ~0ull : ((2ull << p) - 1ull);
         if (zm & range) {
+            // a predecessor is not ready: bounded wait
+            spins++;
+            int stop = ld_rlx_u32(w.abort) != 0u ? WAIT_LOOKBACK : 0;
+            if (!stop && (spins & 63) == 0) {
+                const uint64_t now = wall_clock64();
+                if (t0 == 0) {
+                    t0 = now;
+                } else if (now - t0 > w.limit) {
+                    if (lane == 0) wait_give_up(w, WAIT_LOOKBACK, pattern, step, 0, tile, spins, now - t0, 0, 0);
+                    stop = WAIT_LOOKBACK;
+                }
+                if (!stop && (spins & 255) == 0 && w.cancel && ld_sys_u32(w.cancel) != 0u) {
+                    if (lane == 0) wait_give_up(w, WAIT_CANCEL, pattern, step, 0, tile, spins, now - t0, 0, 0);
+                    stop = WAIT_CANCEL;
+                }
+            }
+            if (__shfl(stop, 0, 64)) return -1;
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
@@ -402,12 +452,19 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
         }
         if (lane < NW) sh.wexcl[lane] = wi - w;
         const int32_t total = __shfl(wi, NW - 1, 64);
-        const int64_t excl = lookback_wave(a.status, a.epoch, tile, (uint64_t)total, lane);
+        const int64_t excl = lookback_wave(a.status, a.epoch, tile, (uint64_t)total, lane, a.w, a.diag_pattern,
+                                           a.diag_step);
         if (lane == 0) {
-            sh.base = excl;
-            sh.total = total;
-            if (tile == n_tiles - 1) *a.n_out = excl + total;
-            if (excl + total > a.out_cap) *a.overflow = 1;
+            if (excl < 0) {
+                // the look-back gave up (the run is being aborted): write nothing
+                sh.base = 0;
+                sh.total = 0;
+            } else {
+                sh.base = excl;
+                sh.total = total;
+                if (tile == n_tiles - 1) *a.n_out = excl + total;
+                if (excl + total > a.out_cap) *a.overflow = 1;
+            }
         }
     }
     __syncthreads();
@@ -553,10 +610,17 @@ __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
     const int64_t n_tiles = (n_in + BLOCK - 1) / BLOCK;
     uint64_t h_cnt = 0, h_sum = 0, h_xor = 0;
     for (;;) {
-        if (tid == 0) s_tile = (int64_t)atomicAdd((unsigned long long*)a.ticket, 1ull);
+        // an earlier wait of the run gave up: its tables are incomplete, so
+        // this step reads nothing (and claims nothing more)
+        if (tid == 0)
+            s_tile = ld_rlx_u32(a.w.abort) != 0u ? -1 : (int64_t)atomicAdd((unsigned long long*)a.ticket, 1ull);
         __syncthreads();
         const int64_t tile = s_tile;
         __syncthreads();
+        if (tile < 0) {
+            if (a.mode == EJF_WRITE && blockIdx.x == 0 && tid == 0) *a.n_out = 0;
+            break;
+        }
         if (tile >= n_tiles) {
             if (a.mode == EJF_WRITE && tile == 0 && tid == 0) *a.n_out = 0;
             break;
@@ -634,6 +698,12 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
     if (blockIdx.x == 0 && tid < N) {
         for (int q = tid; q < N; q += BLOCK) b.ctl[q].t_pub[0] = (int64_t)wall_clock64();
     }
+    // the context's cancel word, read once per workgroup at the start (later
+    // only while waiting): a cancelled run leaves before claiming anything
+    if (wid == 0 && b.w.cancel) {
+        const uint32_t c = ld_sys_u32(b.w.cancel);
+        if (lane == 0 && c != 0u) wait_give_up(b.w, WAIT_CANCEL, -1, -1, 0, -1, 0, 0, 0, 0);
+    }
     uint64_t hc = 0, hs = 0, hx = 0;
     for (;;) {
         // ---- find a claimable tile (wave 0 scans 64 patterns at a time; the
@@ -641,7 +711,15 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
         if (wid == 0) {
             int32_t p = -1, s = -1, tile = -1, ntiles = 0;
             bool all_done = false;
+            // idle waiting is bounded: progress = some tile finishing somewhere
+            uint64_t t_idle = 0;
+            uint32_t prog0 = 0;
+            int64_t polls = 0;
             for (;;) {
+                if (ld_rlx_u32(b.w.abort) != 0u) {  // a wait gave up, or the run was cancelled
+                    all_done = true;
+                    break;
+                }
                 bool got = false;
                 for (int base = 0; base < N && !got; base += 64) {
                     const int q = (rot + base + lane) % N;
@@ -698,6 +776,37 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
                     all_done = true;
                     break;
                 }
+                polls++;
+                const uint32_t prog = ld_rlx_u32(b.tiles_done);
+                const uint64_t now = wall_clock64();
+                if (t_idle == 0 || prog != prog0) {
+                    t_idle = now;
+                    prog0 = prog;
+                } else if (now - t_idle > b.w.limit) {
+                    // nothing finished anywhere for the whole limit: name the
+                    // first unfinished pattern and leave
+                    if (lane == 0) {
+                        int32_t q = 0, st = -1;
+                        for (; q < N; q++) {
+                            st = ld_rlx_i32(&b.ctl[q].stage);
+                            if (st < b.nsteps[q]) break;
+                        }
+                        int32_t nt = 0, cl = 0, dn = 0;
+                        if (q < N) {
+                            nt = ld_rlx_i32(&b.ctl[q].ntiles[st]);
+                            cl = ld_rlx_i32(&b.ctl[q].claim[st]);
+                            dn = ld_rlx_i32(&b.ctl[q].done[st]);
+                        }
+                        wait_give_up(b.w, WAIT_IDLE, q < N ? q : -1, st, nt, -1, polls, now - t_idle, cl, dn);
+                    }
+                    all_done = true;
+                    break;
+                }
+                if ((polls & 31) == 0 && b.w.cancel && ld_sys_u32(b.w.cancel) != 0u) {
+                    if (lane == 0) wait_give_up(b.w, WAIT_CANCEL, -1, -1, 0, -1, polls, now - t_idle, 0, 0);
+                    all_done = true;
+                    break;
+                }
                 // idle: back off exponentially so polling does not flood the memory system
                 for (int i = 0; i < idle; i++) __builtin_amdgcn_s_sleep(16);
                 idle = idle < b.max_backoff ? 2 * idle + 1 : idle;
@@ -739,6 +848,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
         __syncthreads();  // every wave's stores are released before the count
         if (tid == 0) {
             const int32_t d = atomicAdd(&b.ctl[p].done[s], 1);
+            __hip_atomic_fetch_add(b.tiles_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (d == n_tiles - 1) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 BatchCtl& c = b.ctl[p];
@@ -928,8 +1038,9 @@ __device__ void wave_equal_range(const int32_t* a, int64_t n, int32_t v, int lan
 // The pairs t of one wave (64 consecutive t, for each multiple of the block
 // size) are (lo, lo + stride) with lo = t + (t & ~(stride - 1)): for stride <=
 // 64 they lie inside the wave's own 128-element chunk, so a run of such stages
-// needs no workgroup barrier (a wave's LDS accesses complete in order); only a
-// stage with a longer stride, or the first stage after one, waits for all.
+// needs no workgroup barrier, only a wavefront-scope fence that orders one
+// stage's LDS stores before the next stage's loads across the wave's lanes;
+// a stage with a longer stride, or the first stage after one, waits for all.
 __device__ void lds_bitonic(const uint64_t* rows, uint16_t* idx, int n, int wp) {
     const int tid = threadIdx.x, nt = (int)blockDim.x;
     int P = 1;
@@ -939,7 +1050,15 @@ __device__ void lds_bitonic(const uint64_t* rows, uint16_t* idx, int n, int wp) 
     int prev = 0;  // stride of the previous stage (0: the fill, followed by a barrier)
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            if (prev != 0 && (stride > 64 || prev > 64)) __syncthreads();
+            if (prev != 0) {
+                if (stride > 64 || prev > 64) {
+                    __syncthreads();
+                } else {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            }
             prev = stride;
             for (int t = tid; t < (P >> 1); t += nt) {
                 const int lo = 2 * t - (t & (stride - 1));
@@ -1049,6 +1168,7 @@ __global__ __launch_bounds__(1024) void sort_lds_kernel(const SortLaunch L) {
     __shared__ SortJob job;
     __shared__ int64_t s_seg[2];
     const int tid = threadIdx.x;
+    if (L.abort && *L.abort) return;  // set by an earlier launch of the run: stable here
     const int64_t n_items = L.list ? (int64_t)*L.list_n : (int64_t)L.n_jobs * L.n_vertices;
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int32_t item = L.list ? L.list[it].item : (int32_t)it;
@@ -1150,6 +1270,7 @@ __device__ __forceinline__ int64_t first_unit(int64_t i) {
 __global__ __launch_bounds__(1024) void sort_chunk_kernel(const SortLaunch L) {
     extern __shared__ uint64_t lds[];
     const int tid = threadIdx.x;
+    if (L.abort && *L.abort) return;  // set by an earlier launch of the run: stable here
     const int64_t n_list = *L.list_n;
     for (int64_t i = 0; i < n_list; i++) {
         const SegRef ref = L.list[i];
@@ -1180,6 +1301,7 @@ __global__ __launch_bounds__(1024) void sort_chunk_kernel(const SortLaunch L) {
 }
 
 __global__ __launch_bounds__(kSortBlock) void sort_merge_kernel(const SortLaunch L) {
+    if (L.abort && *L.abort) return;  // set by an earlier launch of the run: stable here
     const int p = L.pass;
     if (((int64_t)1 << p) >= (int64_t)*L.max_chunks) return;  // every segment is one run already
     const int tid = threadIdx.x;
@@ -1216,6 +1338,7 @@ __global__ __launch_bounds__(kSortBlock) void sort_merge_kernel(const SortLaunch
 }
 
 __global__ __launch_bounds__(kSortBlock) void sort_gather_kernel(const SortLaunch L) {
+    if (L.abort && *L.abort) return;  // set by an earlier launch of the run: stable here
     const int tid = threadIdx.x;
     const int64_t n_list = *L.list_n;
     const int64_t G = gridDim.x;
@@ -1547,7 +1670,8 @@ hipError_t launch_ingest_count(const int32_t* edges, int64_t m, int32_t n, int32
 // 1024 values, decoupled look-back between tiles.
 constexpr int kScanBlock = 256, kScanItems = 4;
 __global__ __launch_bounds__(kScanBlock) void scan_i32_kernel(const int32_t* in, int32_t* out, int64_t n,
-                                                              int64_t* total, uint64_t* status, uint64_t* ticket) {
+                                                              int64_t* total, uint64_t* status, uint64_t* ticket,
+                                                              const WaitCtl wc) {
     constexpr int NW = kScanBlock / 64;
     constexpr int TILE = kScanBlock * kScanItems;
     __shared__ int64_t s_tile, s_base;
@@ -1592,7 +1716,12 @@ __global__ __launch_bounds__(kScanBlock) void scan_i32_kernel(const int32_t* in,
             }
             if (lane < NW) s_wexcl[lane] = wi - w;
             const int32_t tot = __shfl(wi, NW - 1, 64);
-            const int64_t excl = lookback_wave(status, 0, tile, (uint64_t)tot, lane);
+            // a look-back that gave up counts the missing prefix as 0: the
+            // offsets come out smaller than the true ones, so what later
+            // kernels index with them stays in bounds until the host sees the
+            // abort word and fails the build
+            int64_t excl = lookback_wave(status, 0, tile, (uint64_t)tot, lane, wc, -1, -1);
+            if (excl < 0) excl = 0;
             if (lane == 0) {
                 s_base = excl;
                 if (tile == n_tiles - 1) {
@@ -1612,10 +1741,10 @@ __global__ __launch_bounds__(kScanBlock) void scan_i32_kernel(const int32_t* in,
 }
 
 hipError_t launch_scan_i32(const int32_t* in, int32_t* out_excl, int64_t n, int64_t* total, uint64_t* status,
-                           uint64_t* ticket, hipStream_t s) {
+                           uint64_t* ticket, const WaitCtl& w, hipStream_t s) {
     const int64_t tiles = (n + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems);
     hipLaunchKernelGGL(scan_i32_kernel, dim3(grid_for(tiles, 1, 1024)), dim3(kScanBlock), 0, s, in, out_excl, n,
-                       total, status, ticket);
+                       total, status, ticket, w);
     return hipGetLastError();
 }
 

@@ -23,9 +23,15 @@ dm_status hip_fail(hipError_t e, const char* what) {
     return e == hipErrorOutOfMemory ? DM_ERR_OUT_OF_MEMORY : DM_ERR_DEVICE;
 }
 
-dm_status dev_alloc(void** p, size_t bytes, hipStream_t s) {
+dm_status dev_alloc(const dm_context* ctx, void** p, size_t bytes, hipStream_t s) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
+    if (ctx && ctx->has_alloc) {
+        *p = ctx->alloc.alloc(bytes, (void*)s, ctx->alloc.user);
+        if (!*p) return fail(DM_ERR_OUT_OF_MEMORY, "the context's allocator returned NULL for " +
+                                                       std::to_string(bytes) + " bytes");
+        return DM_OK;
+    }
     hipError_t e = hipMallocAsync(p, bytes, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -35,37 +41,70 @@ dm_status dev_alloc(void** p, size_t bytes, hipStream_t s) {
     return DM_OK;
 }
 
-void dev_free(void* p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+void dev_free(const dm_context* ctx, void* p, hipStream_t s) {
+    if (!p) return;
+    if (ctx && ctx->has_alloc) ctx->alloc.free(p, (void*)s, ctx->alloc.user);
+    else (void)hipFreeAsync(p, s);
+}
+
+WaitCtl wait_ctl(const dm_context* ctx, uint32_t* abort, WaitDiag* diag, int64_t limit_us) {
+    WaitCtl w;
+    w.abort = abort;
+    w.diag = diag;
+    w.cancel = ctx ? ctx->cancel : nullptr;
+    const int64_t us = limit_us > 0 ? limit_us : 10000000;  // default: 10 s without progress
+    const int64_t khz = ctx && ctx->wall_khz > 0 ? ctx->wall_khz : 100000;
+    w.limit = std::max<uint64_t>((uint64_t)us * (uint64_t)khz / 1000, 1);
+    return w;
+}
+
+dm_status check_abort(uint32_t abort, const WaitDiag& d, const char* where) {
+    if (abort == 0) return DM_OK;
+    if (abort == WAIT_CANCEL || d.reason == WAIT_CANCEL)
+        return fail(DM_ERR_CANCELLED, std::string(where) + ": cancelled (dm_context_cancel)");
+    char buf[320];
+    if (d.reason == WAIT_IDLE)
+        std::snprintf(buf, sizeof buf,
+                      "%s: persistent scheduler found no tile finishing for %lld wall-clock ticks (%lld polls); "
+                      "first unfinished pattern %d at step %d (%d tiles, %d claimed, %d finished)",
+                      where, (long long)d.ticks, (long long)d.spins, d.pattern, d.step, d.ntiles, d.claimed,
+                      d.finished);
+    else
+        std::snprintf(buf, sizeof buf,
+                      "%s: look-back of tile %lld (pattern %d, step %d) waited %lld wall-clock ticks (%lld polls) "
+                      "for a predecessor",
+                      where, (long long)d.tile, d.pattern, d.step, (long long)d.ticks, (long long)d.spins);
+    return fail(DM_ERR_DEVICE, buf);
 }
 
 // ------------------------------------------------------------- workspace
 
-dm_status Workspace::init(hipStream_t s) {
+dm_status Workspace::init(dm_context* c, hipStream_t s) {
+    ctx = c;
     stream = s;
-    DM_TRY(dev_alloc((void**)&tickets, sizeof(uint64_t) * kEpochs, s));
+    DM_TRY(dev_alloc(ctx, (void**)&tickets, sizeof(uint64_t) * kEpochs, s));
     DM_HIP(launch_fill_u64(tickets, 0, kEpochs, s));
-    DM_TRY(dev_alloc((void**)&ctrl_d, sizeof(Control), s));
+    DM_TRY(dev_alloc(ctx, (void**)&ctrl_d, sizeof(Control), s));
     DM_HIP(hipHostMalloc((void**)&ctrl_h, sizeof(Control), hipHostMallocDefault));
     std::memset(ctrl_h, 0, sizeof(Control));
     DM_HIP(hipEventCreate(&ev[0]));
     DM_HIP(hipEventCreate(&ev[1]));
-    DM_TRY(dev_alloc((void**)&job_d, sizeof(SortJob), s));
+    DM_TRY(dev_alloc(ctx, (void**)&job_d, sizeof(SortJob), s));
     DM_HIP(hipHostMalloc((void**)&job_h, sizeof(SortJob), hipHostMallocDefault));
     epoch = 0;
     return DM_OK;
 }
 
 void Workspace::release() {
-    for (int i = 0; i < 2; i++) dev_free(buf[i], stream), buf[i] = nullptr, buf_elems[i] = 0;
-    dev_free(status, stream);
-    dev_free(tickets, stream);
-    dev_free(ctrl_d, stream);
-    dev_free(spill, stream);
-    dev_free(sort_scratch, stream);
-    dev_free(heap, stream);
-    dev_free(heap_words, stream);
-    for (int i = 0; i < 2; i++) dev_free(cbuf[i], stream), cbuf[i] = nullptr, cbuf_rows[i] = 0;
+    for (int i = 0; i < 2; i++) dev_free(ctx, buf[i], stream), buf[i] = nullptr, buf_elems[i] = 0;
+    dev_free(ctx, status, stream);
+    dev_free(ctx, tickets, stream);
+    dev_free(ctx, ctrl_d, stream);
+    dev_free(ctx, spill, stream);
+    dev_free(ctx, sort_scratch, stream);
+    dev_free(ctx, heap, stream);
+    dev_free(ctx, heap_words, stream);
+    for (int i = 0; i < 2; i++) dev_free(ctx, cbuf[i], stream), cbuf[i] = nullptr, cbuf_rows[i] = 0;
     heap = nullptr;
     heap_words = nullptr;
     heap_elems = heap_words_cap = 0;
@@ -77,7 +116,7 @@ void Workspace::release() {
     if (stream) (void)hipStreamSynchronize(stream);
     if (ctrl_h) (void)hipHostFree(ctrl_h);
     ctrl_h = nullptr;
-    dev_free(job_d, stream);
+    dev_free(ctx, job_d, stream);
     job_d = nullptr;
     if (job_h) (void)hipHostFree(job_h);
     job_h = nullptr;
@@ -109,21 +148,21 @@ dm_status Workspace::ensure_stage(size_t bytes) {
 
 dm_status Workspace::ensure_buf(int i, int64_t elems) {
     if (buf_elems[i] >= elems) return DM_OK;
-    dev_free(buf[i], stream);
+    dev_free(ctx, buf[i], stream);
     buf[i] = nullptr;
     buf_elems[i] = 0;
     int64_t e = std::max<int64_t>(elems, 1 << 16);
-    DM_TRY(dev_alloc((void**)&buf[i], sizeof(int32_t) * (size_t)e, stream));
+    DM_TRY(dev_alloc(ctx, (void**)&buf[i], sizeof(int32_t) * (size_t)e, stream));
     buf_elems[i] = e;
     return DM_OK;
 }
 
 dm_status Workspace::ensure_status(int64_t words) {
     if (status_cap >= words) return DM_OK;
-    dev_free(status, stream);
+    dev_free(ctx, status, stream);
     status = nullptr;
     int64_t w = std::max<int64_t>(words, 1 << 14);
-    DM_TRY(dev_alloc((void**)&status, sizeof(uint64_t) * (size_t)w, stream));
+    DM_TRY(dev_alloc(ctx, (void**)&status, sizeof(uint64_t) * (size_t)w, stream));
     DM_HIP(launch_fill_u64(status, 0, w, stream));
     status_cap = w;
     return DM_OK;
@@ -131,20 +170,20 @@ dm_status Workspace::ensure_status(int64_t words) {
 
 dm_status Workspace::ensure_spill(int64_t n) {
     if (spill_cap >= n) return DM_OK;
-    dev_free(spill, stream);
+    dev_free(ctx, spill, stream);
     spill = nullptr;
     int64_t c = std::max<int64_t>(n, 1024);
-    DM_TRY(dev_alloc((void**)&spill, sizeof(SegRef) * 2 * (size_t)c, stream));
+    DM_TRY(dev_alloc(ctx, (void**)&spill, sizeof(SegRef) * 2 * (size_t)c, stream));
     spill_cap = c;
     return DM_OK;
 }
 
 dm_status Workspace::ensure_cbuf(int i, int64_t rows) {
     if (cbuf_rows[i] >= rows) return DM_OK;
-    dev_free(cbuf[i], stream);
+    dev_free(ctx, cbuf[i], stream);
     cbuf[i] = nullptr;
     cbuf_rows[i] = 0;
-    DM_TRY(dev_alloc((void**)&cbuf[i], sizeof(uint64_t) * (size_t)std::max<int64_t>(rows, 1), stream));
+    DM_TRY(dev_alloc(ctx, (void**)&cbuf[i], sizeof(uint64_t) * (size_t)std::max<int64_t>(rows, 1), stream));
     cbuf_rows[i] = rows;
     return DM_OK;
 }
@@ -155,15 +194,15 @@ dm_status Workspace::ensure_heap(int64_t elems, int64_t min_elems, int64_t min_w
     if (heap_elems >= elems && heap_words_cap >= words) return DM_OK;
     elems = std::max(elems, heap_elems);
     words = std::max(words, heap_words_cap);
-    dev_free(heap, stream);
+    dev_free(ctx, heap, stream);
     heap = nullptr;
     heap_elems = 0;
-    dev_free(heap_words, stream);
+    dev_free(ctx, heap_words, stream);
     heap_words = nullptr;
     heap_words_cap = 0;
-    DM_TRY(dev_alloc((void**)&heap, sizeof(int32_t) * (size_t)elems, stream));
+    DM_TRY(dev_alloc(ctx, (void**)&heap, sizeof(int32_t) * (size_t)elems, stream));
     heap_elems = elems;
-    DM_TRY(dev_alloc((void**)&heap_words, sizeof(uint64_t) * (size_t)words, stream));
+    DM_TRY(dev_alloc(ctx, (void**)&heap_words, sizeof(uint64_t) * (size_t)words, stream));
     heap_words_cap = words;
     DM_HIP(launch_fill_u64(heap_words, 0, words, stream));
     heap_epoch = 0;
@@ -180,10 +219,10 @@ uint32_t Workspace::next_heap_epoch() {
 
 dm_status Workspace::ensure_sort_scratch(int64_t elems) {
     if (sort_scratch_elems >= elems) return DM_OK;
-    dev_free(sort_scratch, stream);
+    dev_free(ctx, sort_scratch, stream);
     sort_scratch = nullptr;
     int64_t c = std::max<int64_t>(elems, 1 << 16);
-    DM_TRY(dev_alloc((void**)&sort_scratch, sizeof(uint32_t) * (size_t)c, stream));
+    DM_TRY(dev_alloc(ctx, (void**)&sort_scratch, sizeof(uint32_t) * (size_t)c, stream));
     sort_scratch_elems = c;
     return DM_OK;
 }
@@ -214,7 +253,7 @@ static int ejf_grid(int64_t in_cap, double est_in, int block) {
 }
 
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
-                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters) {
+                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort) {
     hipStream_t s = ws.stream;
     const int64_t items = (int64_t)n_jobs * nv;
     if (items >= (int64_t)INT32_MAX) return fail(DM_ERR_UNSUPPORTED, "batch too large: patterns x vertices >= 2^31");
@@ -227,6 +266,7 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.v_begin = v0;
     L.dup_count = &counters[3];
     L.max_chunks = &counters[2];
+    L.abort = abort;
     // tier 1: small LDS tiles (16 KB: swept on the benchmark against 8-48 KB,
     // more resident workgroups beat holding larger segments here); one
     // workgroup per (job, root) item up to 65536 of them, so the hardware
@@ -312,14 +352,15 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         return fail(DM_ERR_UNSUPPORTED, "scored enumeration keeps at most " + std::to_string(kTopkMax) + " rows");
     // frees the run's own result buffers on every early return
     struct ResultGuard {
+        const dm_context* ctx;
         int32_t** r;
         uint64_t** c;
         hipStream_t s;
         ~ResultGuard() {
-            dev_free(*r, s);
-            dev_free(*c, s);
+            dev_free(ctx, *r, s);
+            dev_free(ctx, *c, s);
         }
-    } result_guard{&result, &result_cost, s};
+    } result_guard{ctx, &result, &result_cost, s};
 
     if (opt.profile) {
         while (ws.prof.size() < (size_t)(2 * nsteps + 2)) {
@@ -366,6 +407,9 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             a.mode = (last && hash_mode) ? EJF_HASH : EJF_WRITE;
             a.hash_acc = ws.ctrl_d->hash;
             a.induced = opt.induced ? 1 : 0;
+            a.w = wait_ctl(ws.ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, opt.wait_limit_us);
+            a.diag_pattern = -1;
+            a.diag_step = i;
             if (score) {
                 a.vcost = dg->vcost;
                 a.ecost = dg->ecost;
@@ -382,6 +426,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             if (sync_mode && !(last && hash_mode)) {
                 DM_HIP(hipMemcpyAsync(ws.ctrl_h, ws.ctrl_d, sizeof(Control), hipMemcpyDeviceToHost, s));
                 DM_HIP(hipStreamSynchronize(s));
+                DM_TRY(check_abort(ws.ctrl_h->abort, ws.ctrl_h->diag, "join step"));
                 const int64_t need = ws.ctrl_h->counts[i + 1];
                 if (need > cap[ob]) {
                     // grow the output buffer only (the input stays intact) and redo
@@ -389,7 +434,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
                         return fail(DM_ERR_BUDGET_EXCEEDED, "intermediate table of " + std::to_string(need) +
                                                                 " rows exceeds the memory budget");
                     int64_t nc = need + need / 8 + 1024;
-                    dev_free(ws.buf[ob], s);
+                    dev_free(ctx, ws.buf[ob], s);
                     ws.buf[ob] = nullptr;
                     ws.buf_elems[ob] = 0;
                     DM_TRY(ws.ensure_buf(ob, nc * k));
@@ -409,13 +454,13 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             int64_t rows_cap = cap[lb];
             // a scored run sorts every row: its cap selects by cost afterwards
             int64_t out_rows = (opt.cap >= 0 && !score) ? std::min<int64_t>(opt.cap, rows_cap) : rows_cap;
-            dev_free(result, s);
+            dev_free(ctx, result, s);
             result = nullptr;
-            DM_TRY(dev_alloc((void**)&result, sizeof(int32_t) * (size_t)std::max<int64_t>(out_rows * k, 1), s));
+            DM_TRY(dev_alloc(ctx, (void**)&result, sizeof(int32_t) * (size_t)std::max<int64_t>(out_rows * k, 1), s));
             if (score) {
-                dev_free(result_cost, s);
+                dev_free(ctx, result_cost, s);
                 result_cost = nullptr;
-                DM_TRY(dev_alloc((void**)&result_cost, sizeof(uint64_t) * (size_t)std::max<int64_t>(out_rows, 1), s));
+                DM_TRY(dev_alloc(ctx, (void**)&result_cost, sizeof(uint64_t) * (size_t)std::max<int64_t>(out_rows, 1), s));
             }
             DM_TRY(ws.ensure_sort_scratch(2 * rows_cap + 2));
             SortJob& job = *ws.job_h;
@@ -436,13 +481,15 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
             DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps], s));
-            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, cap[lb], job.wp, ws.ctrl_d->sort_counters));
+            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, cap[lb], job.wp, ws.ctrl_d->sort_counters,
+                                &ws.ctrl_d->abort));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps + 1], s));
         }
         DM_HIP(hipEventRecord(ws.ev[1], s));
         DM_HIP(hipMemcpyAsync(ws.ctrl_h, ws.ctrl_d, sizeof(Control), hipMemcpyDeviceToHost, s));
         DM_HIP(hipStreamSynchronize(s));
         const Control& c = *ws.ctrl_h;
+        DM_TRY(check_abort(c.abort, c.diag, "join step"));
         int first_over = -1;
         for (int i = 0; i < nsteps; i++)
             if (c.overflow[i]) {
@@ -514,17 +561,17 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             if (kk > 0) {
                 int32_t* top = nullptr;
                 uint64_t *top_cost = nullptr, *sel = nullptr;
-                DM_TRY(dev_alloc((void**)&top, sizeof(int32_t) * (size_t)(kk * k), s));
+                DM_TRY(dev_alloc(ctx, (void**)&top, sizeof(int32_t) * (size_t)(kk * k), s));
                 std::unique_ptr<int32_t, std::function<void(int32_t*)>> top_guard(
-                    top, [s](int32_t* p) { dev_free(p, s); });
-                DM_TRY(dev_alloc((void**)&top_cost, sizeof(uint64_t) * (size_t)kk, s));
+                    top, [ctx, s](int32_t* p) { dev_free(ctx, p, s); });
+                DM_TRY(dev_alloc(ctx, (void**)&top_cost, sizeof(uint64_t) * (size_t)kk, s));
                 std::unique_ptr<uint64_t, std::function<void(uint64_t*)>> cost_guard(
-                    top_cost, [s](uint64_t* p) { dev_free(p, s); });
+                    top_cost, [ctx, s](uint64_t* p) { dev_free(ctx, p, s); });
                 // scratch: control block, then k costs and k positions
                 const size_t scratch = sizeof(TopkCtl) + (sizeof(uint64_t) + sizeof(uint32_t)) * (size_t)kk + 64;
-                DM_TRY(dev_alloc((void**)&sel, scratch, s));
+                DM_TRY(dev_alloc(ctx, (void**)&sel, scratch, s));
                 std::unique_ptr<uint64_t, std::function<void(uint64_t*)>> sel_guard(
-                    sel, [s](uint64_t* p) { dev_free(p, s); });
+                    sel, [ctx, s](uint64_t* p) { dev_free(ctx, p, s); });
                 TopkCtl* ctl = (TopkCtl*)sel;
                 uint64_t* sel_cost = (uint64_t*)((char*)sel + ((sizeof(TopkCtl) + 15) & ~(size_t)15));
                 uint32_t* sel_pos = (uint32_t*)(sel_cost + kk);
@@ -585,7 +632,7 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
     hipStream_t s = ws.stream;
     std::vector<RunOutput> parts;
     auto free_parts = [&]() {
-        for (auto& p : parts) dev_free(p.sorted, s);
+        for (auto& p : parts) dev_free(ctx, p.sorted, s);
         parts.clear();
     };
     int64_t got = 0;
@@ -678,7 +725,7 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
     if (!hash_mode) {
         const int64_t keep = opt.cap >= 0 ? std::min<int64_t>(opt.cap, rows) : rows;
         int32_t* dst = nullptr;
-        dm_status st = dev_alloc((void**)&dst, sizeof(int32_t) * (size_t)std::max<int64_t>(keep * plan.k, 1), s);
+        dm_status st = dev_alloc(ctx, (void**)&dst, sizeof(int32_t) * (size_t)std::max<int64_t>(keep * plan.k, 1), s);
         if (st != DM_OK) {
             free_parts();
             return st;
@@ -690,7 +737,7 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
                 hipError_t e = hipMemcpyAsync(dst + at * plan.k, p.sorted, sizeof(int32_t) * (size_t)(r * plan.k),
                                               hipMemcpyDeviceToDevice, s);
                 if (e != hipSuccess) {
-                    dev_free(dst, s);
+                    dev_free(ctx, dst, s);
                     free_parts();
                     return hip_fail(e, "hipMemcpyAsync");
                 }
@@ -743,9 +790,11 @@ const char* dm_version(void) { return DMOTIF_VERSION_STR; }
 
 const char* dm_last_error(void) { return g_err.c_str(); }
 
-dm_status dm_context_create(int32_t device, void* hip_stream, dm_context** out) {
+dm_status dm_context_create(int32_t device, void* hip_stream, const dm_allocator* alloc, dm_context** out) {
     if (!out) return fail(DM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(DM_ERR_INVALID_ARG, "allocator with a NULL alloc or free callback");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();
@@ -755,6 +804,10 @@ dm_status dm_context_create(int32_t device, void* hip_stream, dm_context** out) 
     DM_HIP(hipSetDevice(device));
     auto* c = new dm_context();
     c->device = device;
+    if (alloc) {
+        c->has_alloc = true;
+        c->alloc = *alloc;
+    }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
@@ -764,19 +817,33 @@ dm_status dm_context_create(int32_t device, void* hip_stream, dm_context** out) 
         }
         c->own_stream = true;
     }
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    (void)hipGetLastError();
-    dm_status st = c->ws.init(c->stream);
-    if (st != DM_OK) {
+    auto undo = [&](dm_status st) {
         c->ws.release();
+        if (c->cancel) (void)hipHostFree(c->cancel);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return st;
+    };
+    // the cancel word: host memory the device reads coherently while kernels run
+    if (hipHostMalloc((void**)&c->cancel, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        (void)hipGetLastError();
+        c->cancel = nullptr;
+        return undo(fail(DM_ERR_DEVICE, "hipHostMalloc of the cancel word failed"));
     }
+    __atomic_store_n(c->cancel, 0u, __ATOMIC_SEQ_CST);
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+        c->wall_khz = khz;
+    if (!c->has_alloc) {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+    }
+    (void)hipGetLastError();
+    dm_status st = c->ws.init(c, c->stream);
+    if (st != DM_OK) return undo(st);
     c->sort_lds_max = sort_max_lds_bytes();
     *out = c;
     return DM_OK;
@@ -786,8 +853,15 @@ void dm_context_destroy(dm_context* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     ctx->ws.release();
+    if (ctx->cancel) (void)hipHostFree(ctx->cancel);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
+}
+
+dm_status dm_context_cancel(dm_context* ctx, int32_t flag) {
+    if (!ctx || !ctx->cancel) return fail(DM_ERR_INVALID_ARG, "NULL context");
+    __atomic_store_n(ctx->cancel, flag ? 1u : 0u, __ATOMIC_SEQ_CST);
+    return DM_OK;
 }
 
 }  // extern "C"
@@ -796,10 +870,11 @@ void dm_context_destroy(dm_context* ctx) {
 
 static void free_tables(dm_datagraph* dg) {
     hipStream_t s = dg->ctx->stream;
+    const dm_context* ctx = dg->ctx;
     for (int m = 0; m < kNumMotifs; m++)
         for (int j = 0; j < 6; j++) {
             MotifTable& t = dg->tab[m][j];
-            for (int q = 0; q < 3; q++) dev_free(t.owned[q], s);
+            for (int q = 0; q < 3; q++) dev_free(ctx, t.owned[q], s);
             t = MotifTable();
         }
 }
@@ -807,9 +882,10 @@ static void free_tables(dm_datagraph* dg) {
 // Drop one motif's tables from the database.
 static void free_motif(dm_datagraph* dg, int m) {
     hipStream_t s = dg->ctx->stream;
+    const dm_context* ctx = dg->ctx;
     for (int j = 0; j < 6; j++) {
         MotifTable& t = dg->tab[m][j];
-        for (int q = 0; q < 3; q++) dev_free(t.owned[q], s);
+        for (int q = 0; q < 3; q++) dev_free(ctx, t.owned[q], s);
         t = MotifTable();
     }
     dg->motif_bits &= ~(1u << m);
@@ -820,12 +896,13 @@ static void free_motif(dm_datagraph* dg, int m) {
 static void free_datagraph(dm_datagraph* dg) {
     if (!dg) return;
     hipStream_t s = dg->ctx->stream;
+    const dm_context* ctx = dg->ctx;
     free_tables(dg);
-    dev_free(dg->vcost, s);
-    dev_free(dg->ecost, s);
-    dev_free(dg->row_ptr, s);
-    dev_free(dg->src, s);  // src and col share one allocation (src first)
-    dev_free(dg->bitmap, s);
+    dev_free(ctx, dg->vcost, s);
+    dev_free(ctx, dg->ecost, s);
+    dev_free(ctx, dg->row_ptr, s);
+    dev_free(ctx, dg->src, s);  // src and col share one allocation (src first)
+    dev_free(ctx, dg->bitmap, s);
     // the frees are ordered on the context stream after the work queued there
     delete dg;
 }
@@ -890,12 +967,13 @@ static dm_status build_claw_direct(dm_datagraph* dg) {
     const int64_t rows = (int64_t)rows_d;
     const int m = MOT_K13;
     int32_t* cnt = nullptr;
-    DM_TRY(dev_alloc((void**)&cnt, sizeof(int32_t) * (size_t)(n + 1), s));
+    DM_TRY(dev_alloc(ctx, (void**)&cnt, sizeof(int32_t) * (size_t)(n + 1), s));
     struct Tmp {
+        const dm_context* ctx;
         int32_t* p;
         hipStream_t s;
-        ~Tmp() { dev_free(p, s); }
-    } tmp{cnt, s};
+        ~Tmp() { dev_free(ctx, p, s); }
+    } tmp{ctx, cnt, s};
     const int64_t tiles = (int64_t)(n + 1) / 1024 + 2;
     DM_TRY(ws.ensure_status(tiles));
     for (int j = 0; j < 2; j++) {
@@ -904,9 +982,9 @@ static dm_status build_claw_direct(dm_datagraph* dg) {
         t.rows = rows;
         int32_t* data = nullptr;
         int32_t* offs = nullptr;
-        DM_TRY(dev_alloc((void**)&data, sizeof(int32_t) * (size_t)std::max<int64_t>(rows * 4, 1), s));
+        DM_TRY(dev_alloc(ctx, (void**)&data, sizeof(int32_t) * (size_t)std::max<int64_t>(rows * 4, 1), s));
         t.owned[0] = data;
-        DM_TRY(dev_alloc((void**)&offs, sizeof(int32_t) * (size_t)(n + 1), s));
+        DM_TRY(dev_alloc(ctx, (void**)&offs, sizeof(int32_t) * (size_t)(n + 1), s));
         t.owned[1] = offs;
         t.stride = std::max<int64_t>(rows, 1);
         for (int q = 0; q < 4; q++) t.cols[q] = data + (size_t)q * (size_t)t.stride;
@@ -914,7 +992,8 @@ static dm_status build_claw_direct(dm_datagraph* dg) {
         DM_HIP(launch_claw_count(dg->row_ptr, dg->col, n, j, cnt, s));
         DM_HIP(launch_fill_u64(ws.status, 0, tiles, s));
         DM_HIP(launch_fill_u64(ws.tickets, 0, 1, s));
-        DM_HIP(launch_scan_i32(cnt, offs, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets, s));
+        DM_HIP(launch_scan_i32(cnt, offs, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets,
+                               wait_ctl(ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, 0), s));
         DM_HIP(launch_claw_fill(dg->row_ptr, dg->col, n, j, offs, t.stride, data, s));
     }
     dg->motif_bits |= 1u << m;
@@ -949,8 +1028,8 @@ static dm_status build_motif(dm_datagraph* dg, int m) {
         t.rows = ro.rows;
         int32_t* data = nullptr;
         int32_t* offs = nullptr;
-        DM_TRY(dev_alloc((void**)&data, sizeof(int32_t) * (size_t)std::max<int64_t>(ro.rows * mi.size, 1), s));
-        DM_TRY(dev_alloc((void**)&offs, sizeof(int32_t) * (size_t)(dg->n + 1), s));
+        DM_TRY(dev_alloc(ctx, (void**)&data, sizeof(int32_t) * (size_t)std::max<int64_t>(ro.rows * mi.size, 1), s));
+        DM_TRY(dev_alloc(ctx, (void**)&offs, sizeof(int32_t) * (size_t)(dg->n + 1), s));
         t.owned[0] = data;
         t.owned[1] = offs;
         int32_t colmap[kMaxMotif];
@@ -970,7 +1049,7 @@ static dm_status build_motif(dm_datagraph* dg, int m) {
             // extended from it come out in label order, which the sort skips)
             int32_t* sec = nullptr;
             const size_t bytes = sizeof(int32_t) * (size_t)t.stride * (size_t)mi.size;
-            DM_TRY(dev_alloc((void**)&sec, bytes, s));
+            DM_TRY(dev_alloc(ctx, (void**)&sec, bytes, s));
             t.owned[2] = sec;
             DM_HIP(hipMemcpyAsync(sec, data, bytes, hipMemcpyDeviceToDevice, s));
             DM_HIP(launch_group_sort(offs, dg->n, t.stride, mi.size, mi.size - 1, sec, s));
@@ -1002,11 +1081,11 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
     const size_t ebytes = a256(sizeof(int32_t) * (size_t)emax);
     const size_t scr_bytes = 256 + 2 * ebytes + 5 * vbytes;
     char* scr = nullptr;
-    auto cleanup = [&]() { dev_free(scr, s); };
+    auto cleanup = [&]() { dev_free(ctx, scr, s); };
     dm_status st = DM_OK;
     do {
         // flags: [0] range error bits, [1] big-list count, [2] max degree
-        if ((st = dev_alloc((void**)&scr, scr_bytes, s))) break;
+        if ((st = dev_alloc(ctx, (void**)&scr, scr_bytes, s))) break;
         {
             char* q = scr;
             flags = (int32_t*)q, q += 256;
@@ -1018,7 +1097,9 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
             udeg = (int32_t*)q, q += vbytes;
             big = (int32_t*)q;
         }
-        if (launch_fill_i32(flags, 0, 16, s) || launch_fill_i32(deg, 0, n + 1, s) ||
+        // the control block (counts, the abort word of the scans' look-backs) starts clear
+        if (launch_fill_u64((uint64_t*)ws.ctrl_d, 0, sizeof(Control) / 8, s) ||
+            launch_fill_i32(flags, 0, 16, s) || launch_fill_i32(deg, 0, n + 1, s) ||
             launch_fill_i32(cursor, 0, n + 1, s) || launch_fill_i32(udeg, 0, n + 1, s)) {
             st = fail(DM_ERR_DEVICE, "fill launch failed");
             break;
@@ -1036,7 +1117,8 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
         if ((st = ws.ensure_status(tiles))) break;
         (void)launch_fill_u64(ws.status, 0, tiles, s);
         (void)launch_fill_u64(ws.tickets, 0, 1, s);
-        if (launch_scan_i32(deg, tmp_ptr, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets, s)) {
+        if (launch_scan_i32(deg, tmp_ptr, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets,
+                            wait_ctl(ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, 0), s)) {
             st = fail(DM_ERR_DEVICE, "scan launch failed");
             break;
         }
@@ -1050,16 +1132,17 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
             st = fail(DM_ERR_DEVICE, "ingest sort launch failed");
             break;
         }
-        if ((st = dev_alloc((void**)&dg->row_ptr, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+        if ((st = dev_alloc(ctx, (void**)&dg->row_ptr, sizeof(int32_t) * (size_t)(n + 1), s))) break;
         (void)launch_fill_u64(ws.status, 0, tiles, s);
         (void)launch_fill_u64(ws.tickets, 0, 1, s);
-        if (launch_scan_i32(udeg, dg->row_ptr, n, &ws.ctrl_d->counts[1], ws.status, ws.tickets, s)) {
+        if (launch_scan_i32(udeg, dg->row_ptr, n, &ws.ctrl_d->counts[1], ws.status, ws.tickets,
+                            wait_ctl(ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, 0), s)) {
             st = fail(DM_ERR_DEVICE, "scan launch failed");
             break;
         }
         // src | col in one block (column stride emax): Res(M2) is then an
         // ordinary 2-column SoA table
-        if ((st = dev_alloc((void**)&dg->src, sizeof(int32_t) * 2 * (size_t)emax, s))) break;
+        if ((st = dev_alloc(ctx, (void**)&dg->src, sizeof(int32_t) * 2 * (size_t)emax, s))) break;
         dg->col = dg->src + emax;
         if (launch_ingest_compact(tmp_ptr, tmp, dg->row_ptr, n, dg->col, dg->src, flags + 2, s)) {
             st = fail(DM_ERR_DEVICE, "compact launch failed");
@@ -1068,7 +1151,7 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
         if (n <= 32768 && n > 0) {
             dg->words_per_row = (n + 31) / 32;
             int64_t words = (int64_t)n * dg->words_per_row;
-            if ((st = dev_alloc((void**)&dg->bitmap, sizeof(uint32_t) * (size_t)words, s))) break;
+            if ((st = dev_alloc(ctx, (void**)&dg->bitmap, sizeof(uint32_t) * (size_t)words, s))) break;
             (void)launch_fill_i32((int32_t*)dg->bitmap, 0, words, s);
             if (launch_bitmap_set(dg->src, dg->col, &ws.ctrl_d->counts[1], emax, dg->words_per_row, dg->bitmap, s)) {
                 st = fail(DM_ERR_DEVICE, "bitmap launch failed");
@@ -1084,6 +1167,7 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
         bool copied =
             hipMemcpyAsync(H, &ws.ctrl_d->counts[1], sizeof(int64_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
             hipMemcpyAsync(H + 64, flags, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipMemcpyAsync(H + 8, &ws.ctrl_d->abort, sizeof(uint32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
             hipMemcpyAsync(H + off_rp, dg->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s) ==
                 hipSuccess;
         if (copied && host_csr)
@@ -1097,6 +1181,15 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
         int32_t hflags[16];
         std::memcpy(&nnz, H, sizeof nnz);
         std::memcpy(hflags, H + 64, sizeof hflags);
+        uint32_t habort = 0;
+        std::memcpy(&habort, H + 8, sizeof habort);
+        if (habort) {
+            WaitDiag d;
+            std::memset(&d, 0, sizeof d);
+            (void)hipMemcpy(&d, &ws.ctrl_d->diag, sizeof d, hipMemcpyDeviceToHost);
+            st = check_abort(habort, d, "data-graph ingest");
+            break;
+        }
         // the degree sequence stays on the host (it sizes tables built from the CSR)
         dg->host_row_ptr.assign((const int32_t*)(H + off_rp), (const int32_t*)(H + off_rp) + (n + 1));
         if (hflags[0] & 1) {
@@ -1244,6 +1337,14 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
     (void)hipEventRecord(e1, ctx->stream);
     const auto tb2 = std::chrono::steady_clock::now();
     if (st == DM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(DM_ERR_DEVICE, "build sync failed");
+    if (st == DM_OK) {
+        // a scan look-back that gave up leaves its mark in the control block
+        Control* h = ctx->ws.ctrl_h;
+        if (hipMemcpy(h, ctx->ws.ctrl_d, sizeof(Control), hipMemcpyDeviceToHost) != hipSuccess)
+            st = fail(DM_ERR_DEVICE, "build readback failed");
+        else
+            st = check_abort(h->abort, h->diag, "data-graph build");
+    }
     if (std::getenv("DMOTIF_BUILD_TIMING")) {
         auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
             return std::chrono::duration<double, std::milli>(b - a).count();
@@ -1264,10 +1365,12 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
     return DM_OK;
 }
 
-void dm_datagraph_free(dm_datagraph* dg) {
-    if (!dg) return;
+dm_status dm_datagraph_free(dm_datagraph* dg) {
+    if (!dg) return DM_OK;
+    if (dg->servers.load() > 0) return fail(DM_ERR_BUSY, "a server still holds this data graph; stop it first");
     (void)hipSetDevice(dg->ctx->device);
     free_datagraph(dg);
+    return DM_OK;
 }
 
 
@@ -1392,9 +1495,9 @@ dm_status dm_datagraph_load(dm_context* ctx, const char* path, dm_datagraph** ou
             t.rows = rows;
             t.stride = std::max<int64_t>(rows, 1);
             int32_t *data = nullptr, *offs = nullptr;
-            if ((st = dev_alloc((void**)&data, sizeof(int32_t) * (size_t)(t.stride * size), s))) break;
+            if ((st = dev_alloc(ctx, (void**)&data, sizeof(int32_t) * (size_t)(t.stride * size), s))) break;
             t.owned[0] = data;
-            if ((st = dev_alloc((void**)&offs, sizeof(int32_t) * (size_t)(n + 1), s))) break;
+            if ((st = dev_alloc(ctx, (void**)&offs, sizeof(int32_t) * (size_t)(n + 1), s))) break;
             t.owned[1] = offs;
             std::vector<int32_t> colbuf((size_t)rows);
             for (int q = 0; q < size && st == DM_OK; q++) {
@@ -1458,6 +1561,7 @@ dm_status dm_datagraph_query(const dm_datagraph* dg, dm_datagraph_info* out) {
 
 dm_status dm_datagraph_set_costs(dm_datagraph* dg, const uint32_t* vertex_cost, int64_t n_cost_edges,
                                  const int32_t* cost_edges, const uint32_t* edge_cost) {
+    if (dg && dg->servers.load() > 0) return fail(DM_ERR_BUSY, "a server holds this data graph");
     if (!dg || n_cost_edges < 0 || (n_cost_edges > 0 && (!cost_edges || !edge_cost)))
         return fail(DM_ERR_INVALID_ARG, "invalid cost arguments");
     DM_HIP(hipSetDevice(dg->ctx->device));
@@ -1575,6 +1679,7 @@ RunOptions run_options(const dm_plan_opts* opts, int64_t cap) {
         o.induced = opts->induced != 0;
         o.score = opts->score != 0;
         o.result_limit = opts->result_mb > 0 ? (int64_t)opts->result_mb << 20 : 0;
+        o.wait_limit_us = opts->wait_limit_us;
     }
     o.cap = cap;
     return o;
@@ -1597,11 +1702,11 @@ dm_status ensure_costs(dm_datagraph* dg) {
     if (dg->vcost && dg->ecost) return DM_OK;
     hipStream_t s = dg->ctx->stream;
     if (!dg->vcost) {
-        DM_TRY(dev_alloc((void**)&dg->vcost, sizeof(uint32_t) * (size_t)std::max(dg->n, 1), s));
+        DM_TRY(dev_alloc(dg->ctx, (void**)&dg->vcost, sizeof(uint32_t) * (size_t)std::max(dg->n, 1), s));
         DM_HIP(launch_fill_i32((int32_t*)dg->vcost, 0, std::max(dg->n, 1), s));
     }
     if (!dg->ecost) {
-        DM_TRY(dev_alloc((void**)&dg->ecost, sizeof(uint32_t) * (size_t)std::max<int64_t>(dg->nnz, 1), s));
+        DM_TRY(dev_alloc(dg->ctx, (void**)&dg->ecost, sizeof(uint32_t) * (size_t)std::max<int64_t>(dg->nnz, 1), s));
         DM_HIP(launch_fill_i32((int32_t*)dg->ecost, 0, std::max<int64_t>(dg->nnz, 1), s));
     }
     return DM_OK;
@@ -1674,6 +1779,7 @@ dm_status dm_estimate(dm_datagraph* dg, const dm_graph_desc* gp, const dm_plan_o
 dm_status dm_enumerate(dm_datagraph* dg, const dm_graph_desc* gp, int64_t max_embeddings, const dm_plan_opts* opts,
                        dm_result** out) {
     if (!dg || !gp || !out) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    if (__atomic_load_n(dg->ctx->cancel, __ATOMIC_SEQ_CST)) return fail(DM_ERR_CANCELLED, "context is cancelled");
     DM_HIP(hipSetDevice(dg->ctx->device));
     return enumerate_one(dg, dg->ctx->ws, gp, max_embeddings, opts, out);
 }
@@ -1754,11 +1860,11 @@ void dm_result_free(dm_result* r) {
         r->block.reset();
     } else if (r->data) {
         (void)hipSetDevice(r->ctx->device);
-        dev_free(r->data, r->stream);
+        dev_free(r->ctx, r->data, r->stream);
     }
     if (r->costs) {
         (void)hipSetDevice(r->ctx->device);
-        dev_free(r->costs, r->stream);
+        dev_free(r->ctx, r->costs, r->stream);
     }
     delete r;
 }

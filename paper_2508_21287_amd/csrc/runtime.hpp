@@ -11,6 +11,8 @@
 #include "dm_common.hpp"
 #include "dm_device.hpp"
 
+struct dm_context;
+
 namespace dm {
 
 void set_error(const std::string& msg);
@@ -29,9 +31,11 @@ dm_status hip_fail(hipError_t e, const char* what);
         if (s__ != DM_OK) return s__;    \
     } while (0)
 
-// Stream-ordered device allocation from the device's default memory pool.
-dm_status dev_alloc(void** p, size_t bytes, hipStream_t s);
-void dev_free(void* p, hipStream_t s);
+// Stream-ordered device allocation through the context's allocator (the
+// caller's dm_allocator, or the device's default memory pool): every device
+// buffer the library holds is taken and returned here.
+dm_status dev_alloc(const dm_context* ctx, void** p, size_t bytes, hipStream_t s);
+void dev_free(const dm_context* ctx, void* p, hipStream_t s);
 
 // Per-run control block in device memory (counts, flags, hash accumulators).
 struct Control {
@@ -39,11 +43,15 @@ struct Control {
     int32_t overflow[kMaxSteps + 2];
     uint64_t hash[4];
     int32_t sort_counters[4];  // sort tiers: spill_n[2], max_chunks, dup
+    uint32_t abort;            // WaitCtl::abort of the run
+    uint32_t pad_;
+    WaitDiag diag;             // WaitCtl::diag of the run
 };
 
 // Scratch reused across runs of one stream: ping-pong SoA tables, look-back
 // words, epoch tickets, spill lists and the control block.
 struct Workspace {
+    dm_context* ctx = nullptr;  // allocator, cancel word
     hipStream_t stream = nullptr;
     int32_t* buf[2] = {nullptr, nullptr};
     int64_t buf_elems[2] = {0, 0};
@@ -74,7 +82,7 @@ struct Workspace {
     int64_t heap_words_cap = 0;
     uint32_t heap_epoch = 0;
 
-    dm_status init(hipStream_t s);
+    dm_status init(dm_context* c, hipStream_t s);
     void release();
     dm_status ensure_buf(int i, int64_t elems);
     dm_status ensure_status(int64_t words);
@@ -110,6 +118,10 @@ struct dm_context {
     int32_t device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bool has_alloc = false;   // the caller's allocator (else the default pool)
+    dm_allocator alloc{};
+    uint32_t* cancel = nullptr;  // host-coherent word polled by waiting kernels (dm_context_cancel)
+    int64_t wall_khz = 100000;   // device wall-clock rate (bounded waits)
     dm::Workspace ws;
     int32_t sort_lds_max = 0;
 };
@@ -132,6 +144,7 @@ struct dm_datagraph {
     dm::MotifStats stats;
     double build_ms = 0;
     std::vector<int32_t> host_row_ptr;  // CSR offsets read back at ingest (the degree sequence)
+    std::atomic<int32_t> servers{0};    // servers started on this graph and not yet stopped
 
     dm::GraphDev graph_dev() const {
         dm::GraphDev g;
@@ -178,7 +191,15 @@ struct RunOptions {
     bool induced = false;      // pattern non-edges must map to data non-edges
     bool score = false;        // layout costs per row; with cap >= 0 the cap best rows by (cost, row)
     int64_t result_limit = 0;  // bytes the kept rows may take (0 = what device memory holds)
+    int64_t wait_limit_us = 0; // bound of device waits in microseconds (0 = the default)
 };
+
+// Bounded-wait control of one run: the run's abort word and record, the
+// context's cancel word and the limit in wall-clock ticks.
+WaitCtl wait_ctl(const dm_context* ctx, uint32_t* abort, WaitDiag* diag, int64_t limit_us);
+// DM_OK when the run's abort word (host copy) is clear, else the failure it
+// records: DM_ERR_CANCELLED, or DM_ERR_DEVICE naming the wait that gave up.
+dm_status check_abort(uint32_t abort, const WaitDiag& d, const char* where);
 
 // Output of one plan execution on one workspace.
 struct RunOutput {
@@ -206,8 +227,9 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
 // the number of merge passes); counters = 4 zeroed int32 in device memory
 // (spill_n[2], max_chunks, dup), dup is nonzero afterwards if two rows of a
 // segment were equal.
+// abort: the run's abort word (the tiers do nothing once it is set).
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
-                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters);
+                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort);
 
 dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan);
 // zero layout costs for a data graph that has none set yet

@@ -162,3 +162,17 @@ def test_batch_descriptor_marshalling():
         if want.shape[0]:
             got = np.ctypeslib.as_array(g.edges, shape=(2 * want.shape[0],)).reshape(-1, 2)
             assert np.array_equal(got, want)
+
+
+def test_context_arguments_checked_before_any_device_call():
+    import ctypes as C
+    from paper_2508_21287_amd import _binding as B
+    L = dm.lib()
+    h = C.c_void_p()
+    # an allocator without a free callback is refused before the device is touched
+    bad = B.Allocator(B._ALLOC_FN(lambda n, s, u: None), B._FREE_FN(), None)
+    assert L.dm_context_create(0, None, C.byref(bad), C.byref(h)) == -1
+    assert b"allocator" in L.dm_last_error()
+    assert not h.value
+    assert L.dm_context_create(0, None, None, None) == -1
+    assert L.dm_context_cancel(None, 1) == -1
