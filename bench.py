@@ -1,18 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark: embeddings/s of the full hot path on one MI355X.
 
-Workload: the device-scale configuration -- heavy-hex lattice HH(7,19)
-(163 vertices, 186 edges) and 64 seeded connected lattice-subgraph patterns
-of 8..30 vertices (random BFS + thinning), full enumeration as sorted int32
-tables.  One step = build the resident data graph (CSR, bitmap, motif tables
-M3/M4/M12-O) + decompose and enumerate all 64 patterns + canonical sort, i.e.
-every row of the hot path.  Inputs are host arrays of a few KB, copied by the
-library at the start of the step.
+Headline workload (the batched configuration): heavy-hex lattice HH(28,28)
+(973 vertices) and 256 seeded random-circuit interaction graphs of 4..40
+qubits (log-uniform), every embedding enumerated as a sorted int32 table.
+One step = build the resident data graph (CSR, bitmap, motif tables) + one
+batched call for all 256 patterns (host decomposition, the persistent
+join launch, the sort tiers), i.e. every row of the hot path.  Inputs are
+host arrays of a few KB, copied by the library inside the step.
 
-Prints one JSON line.  The roofline entry is for the dominant kernel (the
-expand-join-filter launches): algorithmic bytes (each table read once and
-written once) over the summed launch durations measured with HIP events on
-the library's stream during the timed steps.
+Before anything is timed, the batch's counts and multiset row hashes are
+compared with the CPU oracle's for all 256 patterns.
+
+Prints one JSON line with, besides the headline:
+* ``batched_over_plain``: the batched call against the same 256 patterns as
+  256 plain calls, both on a resident data graph (the paper's GPU* measure);
+* ``served``: Poisson traces on HH(56,56) (circuit patterns of 4..60 qubits,
+  caps {1, 1000, all}) through the server and one plain solve at a time, at
+  100..5000 queries/s, with p50/p99 latency and queries/s;
+* ``hbm``: the join and sort kernels on 10k-vertex grid tables (the
+  HBM-bound regime), GB/s against the 8 TB/s peak;
+* ``roofline``: the dominant kernel of the timed steps (HIP events on the
+  library's stream), algorithmic bytes per launch over its mean duration;
+* ``cpu_baseline``: the CPU oracle on the headline workload in table mode,
+  on one thread and on every host thread (root ranges split across threads).
 """
 from __future__ import annotations
 
@@ -27,19 +38,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# counter summary of the dominant kernel on this workload (rocprofv3 FETCH_SIZE /
-# WRITE_SIZE, scaled by a plain copy's readings); used only while the kernel
-# source is the one the counters were taken on
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "batch_kernel_hh7x19_64pat.md")
+METRIC = "embeddings/sec + achieved HBM GB/s; batched/served vs plain per-pattern runs"
+# counter summaries of the dominant kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by a plain copy's readings); used only while the kernel source is the
+# one the counters were taken on
+TRAFFIC_PROFILES = {"batch_kernel": os.path.join(ROOT, "profiles", "batch_kernel_hh28_256circ.md"),
+                    "sort": os.path.join(ROOT, "profiles", "sort_hh28_256circ.md")}
 
 
-def measured_traffic():
-    """HBM bytes per dispatch of the dominant kernel from the committed counter
-    summary, or None when it is missing or the kernel source has changed."""
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from its committed counter summary,
+    or None when it is missing or the kernel source has changed since."""
     import hashlib
     try:
-        txt = open(TRAFFIC_PROFILE).read()
-    except OSError:
+        txt = open(TRAFFIC_PROFILES[kernel]).read()
+    except (OSError, KeyError):
         return None
     vals = {}
     for line in txt.splitlines():
@@ -57,14 +70,19 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--mode", choices=["batch", "plain"], default="batch")
-    ap.add_argument("--no-serve", dest="serve", action="store_false",
-                    help="skip the served-trace measurement")
+    ap.add_argument("--no-serve", dest="serve", action="store_false", help="skip the served traces")
+    ap.add_argument("--no-hbm", dest="hbm", action="store_false", help="skip the HBM-regime cases")
+    ap.add_argument("--serve-queries", type=int, default=300, help="queries per arrival rate in the served traces")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the headline steps (no comparison legs), for profilers")
+    ap.add_argument("--config2", action="store_true",
+                    help="instead of the benchmark line, the device-scale case: HH(7,19) x 64 lattice-subgraph "
+                         "patterns, batched vs plain")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print one JSON line per large-table case "
                          "(10k-vertex lattices) with the join and sort kernels' bandwidth")
@@ -76,9 +94,6 @@ def parse():
                     help="instead of the benchmark line, replay Poisson traces of circuit patterns on HH(56,56) "
                          "at 100..5000 queries/s through the server and one at a time, one JSON line per rate")
     ap.add_argument("--queries", type=int, default=500, help="served sweep: queries per rate")
-    ap.add_argument("--batched-config4", action="store_true",
-                    help="instead of the benchmark line, time 256 circuit patterns on HH(28,28) as one "
-                         "batched call vs 256 plain calls")
     ap.add_argument("--pattern-size", type=int, default=60, help="motif-set study: heavy-hex pattern vertices")
     ap.add_argument("--grid-pattern-size", type=int, default=16,
                     help="motif-set study: grid pattern vertices (tree-like grid subgraphs explode beyond ~20)")
@@ -86,24 +101,82 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(g, pats, budget_s=10.0):
-    """The oracle as it stands (single-threaded C backtracking) on the same
-    workload, repeated until ~budget_s of CPU time (bounded sample)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def oracle_tables(g, pats, threads, lib):
+    """The oracle in table mode on every pattern: each pattern's roots split
+    into `threads` contiguous ranges run on host threads (the oracle's C code
+    releases the interpreter lock), the ranges' sorted tables concatenated in
+    root order (= the pattern's sorted table).  Returns the rows produced."""
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
     import oracle
-    oracle.load()
-    total = 0
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
+    rows = 0
+    with ThreadPoolExecutor(max_workers=threads) as ex:
         for p in pats:
-            c, _, _ = oracle.count_hash(g.n, g.edges, p.n, p.edges)
-            total += c
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or reps >= 200:
+            cuts = np.linspace(0, g.n, threads + 1).astype(int)
+            futs = [ex.submit(oracle.enumerate_embeddings, g.n, g.edges, p.n, p.edges, -1, lib,
+                              (int(cuts[i]), int(cuts[i + 1]))) for i in range(threads)]
+            parts = [f.result()[0] for f in futs]
+            rows += sum(len(t) for t in parts)
+            del parts
+    return rows
+
+
+def cpu_baseline(g, pats, budget_s=12.0):
+    """The oracle as it stands (C backtracking + qsort, table mode) on the
+    headline workload: every pattern on all host threads, and a bounded
+    sample of patterns (taken in order until ~budget_s) on one thread."""
+    import oracle
+    lib = oracle.load()
+    nt = host_threads()
+    t0 = time.perf_counter()
+    rows_n = oracle_tables(g, pats, nt, lib)
+    el_n = time.perf_counter() - t0
+    rows_1, t1, used = 0, time.perf_counter(), 0
+    for p in pats:
+        rows_1 += oracle_tables(g, [p], 1, lib)
+        used += 1
+        if time.perf_counter() - t1 > budget_s:
             break
-    return {"value": total / el, "unit": "embeddings/s", "cores": 1, "kind": "oracle",
-            "sample": f"all 64 patterns x {reps} repetitions ({el:.1f} s), count+hash mode, 1 thread"}
+    el_1 = time.perf_counter() - t1
+    return {"value": rows_n / el_n, "unit": "embeddings/s", "cores": nt, "kind": "oracle",
+            "sample": f"all {len(pats)} patterns, table mode (enumerate + sort), {nt} threads over root ranges: "
+                      f"{rows_n} rows in {el_n:.1f} s; 1 thread: the first {used} patterns, {rows_1} rows in "
+                      f"{el_1:.1f} s",
+            "value_1thread": rows_1 / el_1, "cpu_model": cpu_model()}
+
+
+def parity_gate(dm, dg, g, pats):
+    """Counts and multiset row hashes of every pattern, GPU batch (count+hash
+    mode) against the oracle (patterns spread over host threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    lib = oracle.load()
+    res = dg.enumerate_batch([(p.n, p.edges) for p in pats], mode=dm.OUT_COUNT_HASH)
+    got = [(r.total,) + r.hash() for r in res]
+    dm.free_results(res)
+    with ThreadPoolExecutor(max_workers=host_threads()) as ex:
+        want = list(ex.map(lambda p: oracle.count_hash(g.n, g.edges, p.n, p.edges, lib=lib), pats))
+    bad = [p.name for p, a, b in zip(pats, got, want) if tuple(a) != tuple(b)]
+    if bad:
+        raise SystemExit(f"bench.py: GPU results differ from the oracle for {bad[:5]} ({len(bad)} patterns)")
+    return sum(w[0] for w in want)
 
 
 def wait_until(t0, t):
@@ -219,41 +292,6 @@ def serve_trace(dm, ctx, g, pats, rate=4000.0, n_queries=512, seed=4000):
             "plain_p99_ms": 1e3 * float(np.percentile(lat_p, 99)), "plain_qps": n_queries / el_p}
 
 
-def batched_config4(dm, W, ctx, reps=5):
-    """256 circuit patterns (4-40 qubits) on HH(28,28): one batched call (the
-    persistent join launch for all patterns, then the sort tiers) vs 256
-    plain calls on the same stream; full tables.  One JSON line."""
-    import numpy as np
-    import torch
-    g, pats = W.config4(256)
-    specs = [(p.n, p.edges) for p in pats]
-    dg = dm.DataGraph(ctx, g.n, g.edges)
-    rows = 0
-    for _ in range(2):
-        res = dg.enumerate_batch(specs)
-        rows = sum(r.rows for r in res)
-        for r in res:
-            r.free()
-    tb, tp = [], []
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for r in dg.enumerate_batch(specs):
-            r.free()
-        torch.cuda.synchronize()
-        tb.append(time.perf_counter() - t0)
-        t0 = time.perf_counter()
-        for p in pats:
-            dg.enumerate(p.n, p.edges).free()
-        torch.cuda.synchronize()
-        tp.append(time.perf_counter() - t0)
-    b, q = float(np.median(tb)), float(np.median(tp))
-    print(json.dumps({"batched": "HH(28,28) x 256 circuit patterns 4-40 qubits", "rows": int(rows),
-                      "batch_ms": 1e3 * b, "plain_ms": 1e3 * q, "batch_embeddings_per_s": rows / b,
-                      "plain_embeddings_per_s": rows / q, "batched_over_plain": q / b}), flush=True)
-    dg.free()
-
-
 def served_sweep(dm, W, ctx, n_queries):
     """Served workload on HH(56,56): at each arrival rate, an open-loop trace of
     circuit patterns (4-60 qubits, caps {1, 1000, all}) through the server vs
@@ -277,6 +315,68 @@ def served_sweep(dm, W, ctx, n_queries):
                           "plain_p99_ms": 1e3 * float(np.percentile(lat_p, 99)), "plain_qps": n_queries / el_p,
                           "plain_rejected_over_budget": rej_p}), flush=True)
     dg.free()
+
+
+def served_block(dm, W, ctx, n_queries, rates=(100, 300, 1000, 3000, 5000)):
+    """The served configuration: HH(56,56) resident, at each arrival rate an
+    open-loop Poisson trace of circuit patterns (4..60 qubits, caps {1, 1000,
+    all}) through the server (continuous batching on 2 streams, admission by
+    predicted table memory, 8 GiB per query) and, on the same trace, one plain
+    solve at a time within the same 8 GiB."""
+    import numpy as np
+    budget = 8 << 30
+    dg = None
+    out = []
+    for rate in rates:
+        g, arrivals, pats, caps = W.config5(float(rate), n_queries=n_queries)
+        if dg is None:
+            dg = dm.DataGraph(ctx, g.n, g.edges)
+            replay(dm, dg, np.arange(8) * 1e-3, pats[:8], caps[:8], budget)  # warm-up
+        lat_s, el_s, rej_s, lat_p, el_p, rej_p, rows = replay(dm, dg, arrivals, pats, caps, budget)
+        out.append({"rate_per_s": rate, "queries": n_queries, "rows": int(rows),
+                    "refused": rej_s, "p50_ms": 1e3 * float(np.percentile(lat_s, 50)),
+                    "p99_ms": 1e3 * float(np.percentile(lat_s, 99)), "qps": n_queries / el_s,
+                    "plain_refused": rej_p, "plain_p50_ms": 1e3 * float(np.percentile(lat_p, 50)),
+                    "plain_p99_ms": 1e3 * float(np.percentile(lat_p, 99)), "plain_qps": n_queries / el_p})
+        print(f"bench: served {rate}/s done", file=sys.stderr, flush=True)
+    dg.free()
+    return {"trace": f"HH(56,56) (3906 vertices), {n_queries} circuit-pattern queries of 4-60 qubits per rate, "
+                     "Poisson arrivals, caps {1, 1000, all}, 8 GiB per query, 2 server streams",
+            "rates": out,
+            "qps_ge_plain_every_rate": all(r["qps"] >= r["plain_qps"] for r in out),
+            "p99_le_plain_every_rate": all(r["p99_ms"] <= r["plain_p99_ms"] for r in out)}
+
+
+def hbm_block(dm, W, ctx, reps=3):
+    """The HBM-bound regime: 10k-vertex grid tables, per-launch join and sort
+    kernels (HIP events per launch), best of `reps`."""
+    import torch
+    g = W.grid(100, 100)
+    dg = dm.DataGraph(ctx, g.n, g.edges)
+    out = {}
+    for name, p, mode in [("GRID100 P8 table", W.path(8), dm.OUT_TABLE),
+                          ("GRID100 C12 count+hash", W.cycle(12), dm.OUT_COUNT_HASH)]:
+        dg.enumerate(p.n, p.edges, mode=mode).free()  # sizes the workspace
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = dg.enumerate(p.n, p.edges, mode=mode, profile=True)
+            el = time.perf_counter() - t0
+            st, tot = r.stats(), r.total
+            r.free()
+            if best is None or el < best[0]:
+                best = (el, st, tot)
+        el, st, tot = best
+        jg = st["join_bytes"] / 1e9 / (st["join_ms"] / 1e3) if st["join_ms"] else 0.0
+        sg = st["sort_bytes"] / 1e9 / (st["sort_ms"] / 1e3) if st["sort_ms"] else None
+        out[name] = {"embeddings": tot, "wall_ms": 1e3 * el, "join_ms": st["join_ms"],
+                     "join_launches": st["join_launches"], "join_bytes": st["join_bytes"], "join_GBps": jg,
+                     "join_frac": jg / HBM_PEAK_GBS, "sort_ms": st["sort_ms"] or None,
+                     "sort_bytes": st["sort_bytes"] or None, "sort_GBps": sg,
+                     "sort_frac": sg / HBM_PEAK_GBS if sg else None}
+    dg.free()
+    return out
 
 
 def sweep(dm, W, ctx, reps=3):
@@ -370,6 +470,78 @@ def motif_sets(dm, W, ctx, k_hh, k_grid, n_patterns):
                               "iterations": mmm(its), "embeddings": mmm(counts)}), flush=True)
 
 
+def timed_steps(torch, step, steps, warmup):
+    """W untimed then K timed calls of step(); returns (seconds, [results])."""
+    for _ in range(warmup):
+        step()
+    # the interpreter's cyclic collector walks every live object (torch holds
+    # about a million) in its full passes, a 40-70 ms pause every few steps;
+    # move the objects alive now out of its reach, as a serving process would
+    gc.collect()
+    gc.freeze()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+def step_accounting(dm, res):
+    sm = dm.summarize(res)  # one call for all results' counts and launch accounting
+    return (int(sm["total"].sum()), float(sm["join_ms"].sum()), int(sm["join_bytes"].sum()),
+            int(sm["join_launches"].sum()), float(sm["sort_ms"].sum()), int(sm["sort_bytes"].sum()),
+            int(sm["sort_launches"].sum()))
+
+
+def roofline_of(acc, steps):
+    """The dominant kernel of the timed steps: the persistent join launch or
+    the sort (its tiers, one launch set per step), by summed device time."""
+    join_ms = sum(a[1] for a in acc)
+    join_b = sum(a[2] for a in acc)
+    join_l = sum(a[3] for a in acc)
+    sort_ms = sum(a[4] for a in acc)
+    sort_b = sum(a[5] for a in acc)
+    if join_ms >= sort_ms:
+        name, ms, byts, launches = "batch_kernel", join_ms, join_b, max(join_l, 1)
+        desc = "batch_kernel (persistent expand-join-filter over all patterns)"
+    else:
+        name, ms, byts, launches = "sort", sort_ms, sort_b, max(steps, 1)
+        desc = "sort tiers (per-root-segment LDS sorts, one launch set per step)"
+    ach = (byts / 1e9) / (ms / 1e3) if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic(name), "kernel": desc, "launches": launches,
+            "avg_launch_us": 1e3 * ms / launches, "bytes_per_launch": byts / launches,
+            "join_ms_per_step": join_ms / max(steps, 1), "sort_ms_per_step": sort_ms / max(steps, 1)}
+
+
+def config2_line(dm, W, ctx, torch, args):
+    """The device-scale case (HH(7,19), 64 lattice-subgraph patterns of 8..30
+    vertices): batched steps (build + batch) and plain steps."""
+    g, pats = W.config2()
+    specs = [(p.n, p.edges) for p in pats]
+
+    def step(batch=True):
+        dg = dm.DataGraph(ctx, g.n, g.edges)
+        res = dg.enumerate_batch(specs, profile=True) if batch else \
+            [dg.enumerate(n, e, profile=True) for n, e in specs]
+        acc = step_accounting(dm, res)
+        dm.free_results(res)
+        dg.free()
+        return acc
+
+    el, acc = timed_steps(torch, step, args.steps, args.warmup)
+    emb = sum(a[0] for a in acc)
+    tp, accp = timed_steps(torch, lambda: step(False), max(1, min(args.steps, 3)), 1)
+    pemb = sum(a[0] for a in accp)
+    out = {"config2": "HH(7,19) (163 vertices) x 64 lattice-subgraph patterns of 8-30 vertices",
+           "embeddings_per_s": emb / el, "ms_per_step": 1e3 * el / args.steps,
+           "plain_embeddings_per_s": pemb / tp, "batched_over_plain": (emb / el) / (pemb / tp),
+           "roofline": roofline_of(acc, args.steps)}
+    if args.serve:
+        out["served"] = serve_trace(dm, ctx, g, pats)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -389,8 +561,6 @@ def main():
     import paper_2508_21287_amd as dm
     from paper_2508_21287_amd import workloads as W
 
-    g, pats = W.config2()
-    specs = [(p.n, p.edges) for p in pats]
     ctx = dm.Context(0)
     if args.sweep:
         sweep(dm, W, ctx)
@@ -401,78 +571,31 @@ def main():
     if args.served_sweep:
         served_sweep(dm, W, ctx, args.queries)
         return
-    if args.batched_config4:
-        batched_config4(dm, W, ctx)
+    if args.config2:
+        config2_line(dm, W, ctx, torch, args)
         return
 
-    def step(profile: bool):
-        dg = dm.DataGraph(ctx, g.n, g.edges)
-        if args.mode == "batch":
-            res = dg.enumerate_batch(specs, profile=profile)
-        else:
-            res = [dg.enumerate(n, e, profile=profile) for n, e in specs]
-        sm = dm.summarize(res)  # one call for all results' counts and launch accounting
-        tot = int(sm["total"].sum())
-        st = [(float(sm["join_ms"].sum()), int(sm["join_bytes"].sum()), int(sm["join_launches"].sum()),
-               float(sm["sort_ms"].sum()), int(sm["sort_bytes"].sum()))]
-        dm.free_results(res)
-        dg.free()
-        return tot, st
-
-    for _ in range(args.warmup):
-        step(True)
-    # the interpreter's cyclic collector walks every live object (torch holds
-    # about a million) in its full passes, a 40-70 ms pause every few steps;
-    # move the objects alive now out of its reach, as a serving process would
-    gc.collect()
-    gc.freeze()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    emb = 0
-    join_ms = join_bytes = join_launches = sort_ms = sort_bytes = 0
-    for _ in range(args.steps):
-        tot, st = step(True)
-        emb += tot
-        for jm, jb, jl, sm, sb in st:
-            join_ms += jm
-            join_bytes += jb
-            join_launches += jl
-            sort_ms += sm
-            sort_bytes += sb
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-
-    # the same steps with one plain launch sequence per pattern, for comparison
-    plain_steps = max(1, min(args.steps, 3))
-    saved = args.mode
-    args.mode = "plain"
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    pemb = 0
-    for _ in range(plain_steps):
-        pemb += step(False)[0]
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - tp
-    args.mode = saved
-
-    # query-only throughput (data graph resident: the paper's GPU* measure)
+    g, pats = W.config4(256)
+    specs = [(p.n, p.edges) for p in pats]
     dg = dm.DataGraph(ctx, g.n, g.edges)
-    torch.cuda.synchronize()
-    tq = time.perf_counter()
-    qemb = 0
-    for _ in range(args.steps):
-        res = dg.enumerate_batch(specs)
-        qemb += int(dm.summarize(res)["total"].sum())
+    if not args.profile_run:
+        expect = parity_gate(dm, dg, g, pats)
+        print(f"bench: parity gate passed ({expect} embeddings, 256 patterns)", file=sys.stderr, flush=True)
+
+    def step():
+        d = dm.DataGraph(ctx, g.n, g.edges)
+        res = d.enumerate_batch(specs, profile=True)
+        acc = step_accounting(dm, res)
         dm.free_results(res)
-    torch.cuda.synchronize()
-    tq = time.perf_counter() - tq
-    dg.free()
+        d.free()
+        return acc
 
-    served = serve_trace(dm, ctx, g, pats) if args.serve else None
-
-    ach = (join_bytes / 1e9) / (join_ms / 1e3) if join_ms > 0 else 0.0
+    el, acc = timed_steps(torch, step, args.steps, args.warmup)
+    emb = sum(a[0] for a in acc)
+    if not args.profile_run and emb != expect * args.steps:
+        raise SystemExit(f"bench.py: timed steps produced {emb} rows, expected {expect * args.steps}")
     out = {
-        "metric": "embeddings/sec + achieved HBM GB/s; batched/served vs plain per-pattern runs",
+        "metric": METRIC,
         "value": emb / el,
         "unit": "embeddings/s",
         "n_gpus": 1,
@@ -484,24 +607,46 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "HH(7,19) heavy-hex (163 vertices) x 64 seeded lattice-subgraph patterns "
-                               "(8-30 vertices), full enumeration, sorted int32 tables",
-                   "mode": args.mode, "embeddings_per_step": emb // max(args.steps, 1),
-                   "step": "data-graph build + motif tables + plan + joins + sort"},
-        "query_only_embeddings_per_s": qemb / tq,
-        "plain_embeddings_per_s": pemb / tp,
-        "batched_over_plain": (emb / el) / (pemb / tp) if pemb else None,
-        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.mode == "batch" else None,
-                     "kernel": ("batch_kernel (persistent expand-join-filter over all patterns)"
-                                if args.mode == "batch" else "ejf_kernel (expand-join-filter)"),
-                     "launches": join_launches, "avg_launch_us": 1e3 * join_ms / max(join_launches, 1),
-                     "bytes_per_launch": join_bytes / max(join_launches, 1)},
-        "sort": {"ms_total": sort_ms, "bytes": sort_bytes},
+        "config": {"workload": "HH(28,28) heavy-hex (973 vertices) x 256 random-circuit interaction patterns "
+                               "(4-40 qubits, log-uniform, seeds 0-255), full enumeration, sorted int32 tables",
+                   "mode": "batch", "embeddings_per_step": emb // max(args.steps, 1),
+                   "step": "data-graph build + motif tables + plan + persistent join launch + sort"},
+        "roofline": roofline_of(acc, args.steps),
     }
-    if served is not None:
-        out["served"] = served
+    if args.profile_run:
+        print(json.dumps(out), flush=True)
+        return
+    print("bench: headline steps done", file=sys.stderr, flush=True)
+
+    # batched vs plain on the resident data graph (the paper's GPU* measure)
+    def batch_q():
+        res = dg.enumerate_batch(specs)
+        n = int(dm.summarize(res)["total"].sum())
+        dm.free_results(res)
+        return n
+
+    def plain_q():
+        n = 0
+        for p in pats:
+            r = dg.enumerate(p.n, p.edges)
+            n += r.total
+            r.free()
+        return n
+
+    tb, nb = timed_steps(torch, batch_q, 3, 1)
+    tp, npl = timed_steps(torch, plain_q, 2, 1)
+    out["query_only_embeddings_per_s"] = sum(nb) / tb
+    out["plain_embeddings_per_s"] = sum(npl) / tp
+    out["batched_over_plain"] = (sum(nb) / tb) / (sum(npl) / tp)
+    out["batch_ms"] = 1e3 * tb / 3
+    out["plain_ms"] = 1e3 * tp / 2
+    dg.free()
+    print("bench: batched vs plain done", file=sys.stderr, flush=True)
+    if args.hbm:
+        out["hbm"] = hbm_block(dm, W, ctx)
+        print("bench: HBM cases done", file=sys.stderr, flush=True)
+    if args.serve:
+        out["served"] = served_block(dm, W, ctx, args.serve_queries)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, pats)
     print(json.dumps(out), flush=True)
