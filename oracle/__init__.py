@@ -67,6 +67,10 @@ def load(path: str = LIB) -> C.CDLL:
         lib.oracle_enumerate_ex.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
                                             C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.POINTER(i32p),
                                             C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        lib.oracle_count_hash_range.restype = C.c_int
+        lib.oracle_count_hash_range.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
+                                                C.c_int32, C.c_int32, C.POINTER(C.c_int64),
+                                                C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         lib.oracle_count_hash_ex.restype = C.c_int
         lib.oracle_count_hash_ex.argtypes = [C.c_int32, C.c_int64, i32p, C.c_int32, C.c_int64, i32p,
                                              C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
@@ -199,6 +203,40 @@ def count_hash(n_d: int, edges_d, n_p: int, edges_p, lib: C.CDLL | None = None, 
     if rc != 0:
         raise OracleError(rc)
     return cnt.value, hs.value, hx.value
+
+
+def count_hash_range(n_d: int, edges_d, n_p: int, edges_p, root_range, lib: C.CDLL | None = None):
+    """``count_hash`` restricted to embeddings with ``f(0)`` in ``[lo, hi)``."""
+    lib = lib or load()
+    ed, ep = _edges(edges_d), _edges(edges_p)
+    cnt, hs, hx = C.c_int64(0), C.c_uint64(0), C.c_uint64(0)
+    rc = lib.oracle_count_hash_range(n_d, len(ed), _p(ed), n_p, len(ep), _p(ep), int(root_range[0]),
+                                     int(root_range[1]), C.byref(cnt), C.byref(hs), C.byref(hx))
+    if rc != 0:
+        raise OracleError(rc)
+    return cnt.value, hs.value, hx.value
+
+
+def count_hash_threads(n_d: int, edges_d, n_p: int, edges_p, threads: int, root_range=None,
+                       lib: C.CDLL | None = None):
+    """``count_hash`` (over ``root_range``, default every root) with the roots
+    split into ``threads`` contiguous ranges run on host threads (the C code
+    releases the interpreter lock); counts and sums add, hashes XOR."""
+    from concurrent.futures import ThreadPoolExecutor
+    lib = lib or load()
+    lo, hi = root_range if root_range is not None else (0, n_d)
+    pieces = max(1, min(threads * 8, hi - lo))
+    cuts = np.linspace(lo, hi, pieces + 1).astype(np.int64)
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        parts = list(ex.map(lambda i: count_hash_range(n_d, edges_d, n_p, edges_p,
+                                                       (int(cuts[i]), int(cuts[i + 1])), lib),
+                            range(pieces)))
+    c = sum(p[0] for p in parts)
+    hs = sum(p[1] for p in parts) % (1 << 64)
+    hx = 0
+    for p in parts:
+        hx ^= p[2]
+    return c, hs, hx
 
 
 def row_hash(row, lib: C.CDLL | None = None) -> int:

@@ -460,6 +460,16 @@ int oracle_count_hash(int32_t nd, int64_t md, const int32_t *ed,
     return run(nd, md, ed, np, mp, ep, 1, -1, 0, nd, 0, NULL, NULL, count, hsum, hxor);
 }
 
+/* As oracle_count_hash, counting only embeddings with f(0) in
+ * [root_lo, root_hi) (the sums and XORs of a partition of the roots combine
+ * into the full result). */
+int oracle_count_hash_range(int32_t nd, int64_t md, const int32_t *ed,
+                            int32_t np, int64_t mp, const int32_t *ep,
+                            int32_t root_lo, int32_t root_hi,
+                            int64_t *count, uint64_t *hsum, uint64_t *hxor) {
+    return run(nd, md, ed, np, mp, ep, 1, -1, root_lo, root_hi, 0, NULL, NULL, count, hsum, hxor);
+}
+
 /* As oracle_count_hash, with induced = 1 selecting induced embeddings. */
 int oracle_count_hash_ex(int32_t nd, int64_t md, const int32_t *ed,
                          int32_t np, int64_t mp, const int32_t *ep, int32_t induced,

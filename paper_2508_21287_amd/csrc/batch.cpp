@@ -317,12 +317,12 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     DM_HIP(hipMemcpyAsync(A + off_tops, tops, sizeof tops, hipMemcpyHostToDevice, s));
     DM_HIP(hipMemcpyAsync(A + off_jobs, host, host_size, hipMemcpyHostToDevice, s));
 
-    hipEvent_t ev[4];
+    hipEvent_t ev[6];
     for (auto& e : ev) DM_HIP(hipEventCreate(&e));
     struct EvGuard {
         hipEvent_t* e;
         ~EvGuard() {
-            for (int i = 0; i < 4; i++) (void)hipEventDestroy(e[i]);
+            for (int i = 0; i < 6; i++) (void)hipEventDestroy(e[i]);
         }
     } evg{ev};
 
@@ -449,14 +449,19 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
         }
         DM_HIP(hipMemcpyAsync(A + off_jobs, hjobs, sizeof(SortJob) * nb, hipMemcpyHostToDevice, s));
         DM_HIP(hipEventRecord(ev[2], s));
+        bool merged = false;
         DM_TRY(enqueue_sort(ctx, ws, (const SortJob*)(A + off_jobs), nb, nv, 0, max_rows, max_wp, &misc[1],
-                            (const uint32_t*)&misc[5]));
-        DM_HIP(hipEventRecord(ev[3], s));
+                            (const uint32_t*)&misc[5], (int32_t*)ws.stage_h, &ev[3], &merged));
         int32_t sc[4];
         DM_HIP(hipMemcpyAsync(sc, &misc[1], sizeof sc, hipMemcpyDeviceToHost, s));
         DM_HIP(hipStreamSynchronize(s));
         if (sc[3] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached a canonical table");
         (void)hipEventElapsedTime(&ms_sort, ev[2], ev[3]);
+        if (merged) {
+            float tm = 0;
+            (void)hipEventElapsedTime(&tm, ev[4], ev[5]);
+            ms_sort += tm;
+        }
     }
     if (timing)
         std::fprintf(stderr,

@@ -79,6 +79,11 @@ dm_status check_abort(uint32_t abort, const WaitDiag& d, const char* where) {
 
 // ------------------------------------------------------------- workspace
 
+// A fixed workspace cannot grow: the request does not fit its scratch.
+static dm_status fixed_full(const char* what) {
+    return fail(DM_ERR_BUDGET_EXCEEDED, std::string(what) + " does not fit the fixed scratch");
+}
+
 dm_status Workspace::init(dm_context* c, hipStream_t s) {
     ctx = c;
     stream = s;
@@ -134,6 +139,7 @@ void Workspace::release() {
 // caller synchronizes the stream before the buffer is reused or grown.
 dm_status Workspace::ensure_stage(size_t bytes) {
     if (stage_bytes >= bytes) return DM_OK;
+    if (fixed) return fixed_full("host staging");
     if (stage_h) {
         if (stream) DM_HIP(hipStreamSynchronize(stream));
         (void)hipHostFree(stage_h);
@@ -148,6 +154,7 @@ dm_status Workspace::ensure_stage(size_t bytes) {
 
 dm_status Workspace::ensure_buf(int i, int64_t elems) {
     if (buf_elems[i] >= elems) return DM_OK;
+    if (fixed) return fixed_full("an intermediate table");
     dev_free(ctx, buf[i], stream);
     buf[i] = nullptr;
     buf_elems[i] = 0;
@@ -159,6 +166,7 @@ dm_status Workspace::ensure_buf(int i, int64_t elems) {
 
 dm_status Workspace::ensure_status(int64_t words) {
     if (status_cap >= words) return DM_OK;
+    if (fixed) return fixed_full("the look-back words");
     dev_free(ctx, status, stream);
     status = nullptr;
     int64_t w = std::max<int64_t>(words, 1 << 14);
@@ -170,6 +178,7 @@ dm_status Workspace::ensure_status(int64_t words) {
 
 dm_status Workspace::ensure_spill(int64_t n) {
     if (spill_cap >= n) return DM_OK;
+    if (fixed) return fixed_full("the sort's segment lists");
     dev_free(ctx, spill, stream);
     spill = nullptr;
     int64_t c = std::max<int64_t>(n, 1024);
@@ -180,6 +189,7 @@ dm_status Workspace::ensure_spill(int64_t n) {
 
 dm_status Workspace::ensure_cbuf(int i, int64_t rows) {
     if (cbuf_rows[i] >= rows) return DM_OK;
+    if (fixed) return fixed_full("the layout costs");
     dev_free(ctx, cbuf[i], stream);
     cbuf[i] = nullptr;
     cbuf_rows[i] = 0;
@@ -192,6 +202,7 @@ dm_status Workspace::ensure_heap(int64_t elems, int64_t min_elems, int64_t min_w
     elems = std::max(elems, min_elems);
     int64_t words = std::max<int64_t>(elems / 32 + 65536, min_words);
     if (heap_elems >= elems && heap_words_cap >= words) return DM_OK;
+    if (fixed) return fixed_full("the batch heap");
     elems = std::max(elems, heap_elems);
     words = std::max(words, heap_words_cap);
     dev_free(ctx, heap, stream);
@@ -219,6 +230,7 @@ uint32_t Workspace::next_heap_epoch() {
 
 dm_status Workspace::ensure_sort_scratch(int64_t elems) {
     if (sort_scratch_elems >= elems) return DM_OK;
+    if (fixed) return fixed_full("the sort's index scratch");
     dev_free(ctx, sort_scratch, stream);
     sort_scratch = nullptr;
     int64_t c = std::max<int64_t>(elems, 1 << 16);
@@ -253,7 +265,9 @@ static int ejf_grid(int64_t in_cap, double est_in, int block) {
 }
 
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
-                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort) {
+                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
+                       int32_t* host_word, hipEvent_t* prof, bool* merged) {
+    if (merged) *merged = false;
     hipStream_t s = ws.stream;
     const int64_t items = (int64_t)n_jobs * nv;
     if (items >= (int64_t)INT32_MAX) return fail(DM_ERR_UNSUPPORTED, "batch too large: patterns x vertices >= 2^31");
@@ -285,16 +299,27 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.spill = ws.spill + ws.spill_cap;
     L.spill_n = &counters[1];
     DM_HIP(launch_sort_lds(L, 256, 1024, L.lds_bytes, s));
-    // tier 3: chunks of the tier-2 tile, merged pairwise
+    // tier 3: chunks of the tier-2 tile, merged pairwise.  No segment
+    // outgrows the tier-2 tile when no table has more rows than it holds;
+    // else the number of segments tier 2 passed on is read back first, and
+    // the chunk, merge and gather launches run only when there are any.
+    if (prof) DM_HIP(hipEventRecord(prof[0], s));
+    const int64_t r_min = std::max(lds_rows_of(L.lds_bytes, max_wp), 1);
+    if (max_in_cap <= r_min) return DM_OK;
+    DM_HIP(hipMemcpyAsync(host_word, &counters[1], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DM_HIP(hipStreamSynchronize(s));
+    if (*host_word == 0) return DM_OK;
+    if (merged) *merged = true;
+    if (prof) DM_HIP(hipEventRecord(prof[1], s));
     L.list = ws.spill + ws.spill_cap;
     L.list_n = &counters[1];
     L.spill = nullptr;
     L.spill_n = nullptr;
-    const int64_t r_min = std::max(lds_rows_of(L.lds_bytes, max_wp), 1);
     const int64_t chunks = (std::max<int64_t>(max_in_cap, 1) + r_min - 1) / r_min;
     int passes = 0;
     while (((int64_t)1 << passes) < chunks) passes++;
     DM_HIP(launch_sort_merge_tier(L, passes, s));
+    if (prof) DM_HIP(hipEventRecord(prof[2], s));
     return DM_OK;
 }
 
@@ -338,6 +363,8 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
     int64_t cap0 = (int64_t)std::min<double>(est_max * 2.0 + 4096.0, (double)first_max);
     cap0 = std::max<int64_t>(cap0, std::min<int64_t>(1 << 14, budget_rows));
     if (opt.initial_rows > 0) cap0 = std::min<int64_t>(opt.initial_rows, budget_rows);
+    // a fixed workspace: its buffers as they are (every table gets all of them)
+    if (ws.fixed) cap0 = std::max<int64_t>(std::min(ws.buf_elems[0], ws.buf_elems[1]) / k, 1);
     const int block = opt.block > 0 ? opt.block : auto_block(est_max);
 
     // capacity (rows) of each ping-pong buffer; stride of a table = its capacity
@@ -363,7 +390,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
     } result_guard{ctx, &result, &result_cost, s};
 
     if (opt.profile) {
-        while (ws.prof.size() < (size_t)(2 * nsteps + 2)) {
+        while (ws.prof.size() < (size_t)(2 * nsteps + 4)) {
             hipEvent_t e;
             DM_HIP(hipEventCreate(&e));
             ws.prof.push_back(e);
@@ -380,7 +407,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         int64_t maxcap = std::max<int64_t>(std::max(cap[0], cap[1]), (int64_t)dg->n);
         DM_TRY(ws.ensure_status(maxcap / 64 + 2));
         DM_HIP(launch_fill_u64((uint64_t*)ws.ctrl_d, 0, sizeof(Control) / 8, s));
-        DM_HIP(hipEventRecord(ws.ev[0], s));
+        if (ws.ev[0]) DM_HIP(hipEventRecord(ws.ev[0], s));
         bool redo = false;
         for (int i = 0; i < nsteps; i++) {
             const int ib = (i - 1) & 1, ob = i & 1;
@@ -430,6 +457,9 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
                 const int64_t need = ws.ctrl_h->counts[i + 1];
                 if (need > cap[ob]) {
                     // grow the output buffer only (the input stays intact) and redo
+                    if (ws.fixed)
+                        return fail(DM_ERR_BUDGET_EXCEEDED, "intermediate table of " + std::to_string(need) +
+                                                                " rows does not fit the fixed scratch");
                     if (need > budget_rows)
                         return fail(DM_ERR_BUDGET_EXCEEDED, "intermediate table of " + std::to_string(need) +
                                                                 " rows exceeds the memory budget");
@@ -449,43 +479,10 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             }
         }
         const int lb = (nsteps - 1) & 1;
-        if (!hash_mode && opt.sort) {
-            // canonicalize into a row-major table sized by the last buffer's capacity
-            int64_t rows_cap = cap[lb];
-            // a scored run sorts every row: its cap selects by cost afterwards
-            int64_t out_rows = (opt.cap >= 0 && !score) ? std::min<int64_t>(opt.cap, rows_cap) : rows_cap;
-            dev_free(ctx, result, s);
-            result = nullptr;
-            DM_TRY(dev_alloc(ctx, (void**)&result, sizeof(int32_t) * (size_t)std::max<int64_t>(out_rows * k, 1), s));
-            if (score) {
-                dev_free(ctx, result_cost, s);
-                result_cost = nullptr;
-                DM_TRY(dev_alloc(ctx, (void**)&result_cost, sizeof(uint64_t) * (size_t)std::max<int64_t>(out_rows, 1), s));
-            }
-            DM_TRY(ws.ensure_sort_scratch(2 * rows_cap + 2));
-            SortJob& job = *ws.job_h;
-            std::memset(&job, 0, sizeof job);
-            job.in = ws.buf[lb];
-            job.in_stride = cap[lb];
-            job.in_cap = cap[lb];
-            job.n_in = &ws.ctrl_d->counts[nsteps];
-            job.out = result;
-            job.out_rows = out_rows;
-            job.scratch_idx = ws.sort_scratch;
-            if (score) {
-                job.in_cost = ws.cbuf[lb];
-                job.out_cost = result_cost;
-            }
-            job.k = k;
-            sort_pack_layout(k, dg->n, &job);
-            for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
-            DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
-            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps], s));
-            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, cap[lb], job.wp, ws.ctrl_d->sort_counters,
-                                &ws.ctrl_d->abort));
-            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps + 1], s));
-        }
-        DM_HIP(hipEventRecord(ws.ev[1], s));
+        // one readback of the join counts: the result is allocated at its exact
+        // size (a buffer sized by the table's capacity would hold as much as
+        // the largest table this workspace ever grew to)
+        if (!(!hash_mode && opt.sort) && ws.ev[1]) DM_HIP(hipEventRecord(ws.ev[1], s));
         DM_HIP(hipMemcpyAsync(ws.ctrl_h, ws.ctrl_d, sizeof(Control), hipMemcpyDeviceToHost, s));
         DM_HIP(hipStreamSynchronize(s));
         const Control& c = *ws.ctrl_h;
@@ -501,6 +498,9 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             // counts are exact up to the first overflowing step: size from them and rerun step by step
             int64_t need = 0;
             for (int i = 0; i <= first_over; i++) need = std::max<int64_t>(need, c.counts[i + 1]);
+            if (ws.fixed)
+                return fail(DM_ERR_BUDGET_EXCEEDED, "intermediate table of " + std::to_string(need) +
+                                                        " rows does not fit the fixed scratch");
             if (need > budget_rows)
                 return fail(DM_ERR_BUDGET_EXCEEDED,
                             "intermediate table of " + std::to_string(need) + " rows exceeds the memory budget");
@@ -511,9 +511,59 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             retries++;
             continue;
         }
+        const int64_t n_final = std::min<int64_t>(c.counts[nsteps], cap[lb]);
+        bool sort_merged = false;  // the merge tier ran (its launches are timed apart from the LDS tiers)
+        if (!hash_mode && opt.sort) {
+            // canonicalize into a row-major table of exactly the kept rows
+            // (a scored run sorts every row: its cap selects by cost afterwards)
+            int64_t out_rows = (opt.cap >= 0 && !score) ? std::min<int64_t>(opt.cap, n_final) : n_final;
+            dev_free(ctx, result, s);
+            result = nullptr;
+            if (opt.out_buf) {
+                // the caller's buffer: the sort writes the prefix that fits
+                out_rows = std::min<int64_t>(out_rows, opt.out_buf_rows);
+            } else {
+                DM_TRY(dev_alloc(ctx, (void**)&result, sizeof(int32_t) * (size_t)std::max<int64_t>(out_rows * k, 1),
+                                 s));
+            }
+            if (score) {
+                dev_free(ctx, result_cost, s);
+                result_cost = nullptr;
+                DM_TRY(dev_alloc(ctx, (void**)&result_cost, sizeof(uint64_t) * (size_t)std::max<int64_t>(out_rows, 1), s));
+            }
+            DM_TRY(ws.ensure_sort_scratch(2 * n_final + 2));
+            SortJob& job = *ws.job_h;
+            std::memset(&job, 0, sizeof job);
+            job.in = ws.buf[lb];
+            job.in_stride = cap[lb];
+            job.in_cap = cap[lb];
+            job.n_in = &ws.ctrl_d->counts[nsteps];
+            job.out = opt.out_buf ? opt.out_buf : result;
+            job.out_rows = out_rows;
+            job.scratch_idx = ws.sort_scratch;
+            if (score) {
+                job.in_cost = ws.cbuf[lb];
+                job.out_cost = result_cost;
+            }
+            job.k = k;
+            sort_pack_layout(k, dg->n, &job);
+            for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
+            DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
+            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps], s));
+            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, n_final, job.wp, ws.ctrl_d->sort_counters,
+                                &ws.ctrl_d->abort, &ws.ctrl_h->sort_counters[1],
+                                opt.profile ? &ws.prof[2 * nsteps + 1] : nullptr, &sort_merged));
+            if (ws.ev[1]) DM_HIP(hipEventRecord(ws.ev[1], s));
+            DM_HIP(hipMemcpyAsync(ws.ctrl_h->sort_counters, ws.ctrl_d->sort_counters, sizeof(c.sort_counters),
+                                  hipMemcpyDeviceToHost, s));
+            DM_HIP(hipMemcpyAsync(&ws.ctrl_h->abort, &ws.ctrl_d->abort, sizeof(uint32_t) + sizeof(uint32_t) +
+                                  sizeof(WaitDiag), hipMemcpyDeviceToHost, s));
+            DM_HIP(hipStreamSynchronize(s));
+            DM_TRY(check_abort(c.abort, c.diag, "sort"));
+        }
         if (c.sort_counters[3] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached the canonical table");
         float ms = 0;
-        (void)hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]);
+        if (ws.ev[0] && ws.ev[1]) (void)hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]);
         o.stats.device_ms = ms;
         o.stats.n_steps = (int32_t)plan.steps.size();
         o.stats.retries = retries;
@@ -546,10 +596,13 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             o.stats.join_ms = jm;
             o.stats.join_launches = nsteps;
             if (!hash_mode && opt.sort) {
-                float t = 0;
+                // the LDS tiers, plus the merge tier when it ran (not the host
+                // round trip that decided it)
+                float t = 0, tm = 0;
                 (void)hipEventElapsedTime(&t, ws.prof[2 * nsteps], ws.prof[2 * nsteps + 1]);
-                o.stats.sort_ms = t;
-                o.stats.sort_launches = 3;
+                if (sort_merged) (void)hipEventElapsedTime(&tm, ws.prof[2 * nsteps + 2], ws.prof[2 * nsteps + 3]);
+                o.stats.sort_ms = t + tm;
+                o.stats.sort_launches = sort_merged ? 3 : 2;
             }
         }
         if (hash_mode) {
@@ -581,6 +634,14 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
                 o.costs = cost_guard.release();
             }
             o.sorted_rows = kk;
+        } else if (opt.sort && opt.out_buf) {
+            o.sorted_rows = opt.cap >= 0 ? std::min<int64_t>(opt.cap, o.rows) : o.rows;
+            if (o.sorted_rows > opt.out_buf_rows) {
+                *out = o;  // the count, for the caller to size its buffer
+                return fail(DM_ERR_BUDGET_EXCEEDED, std::to_string(o.sorted_rows) +
+                                                        " rows do not fit the caller's buffer of " +
+                                                        std::to_string(opt.out_buf_rows));
+            }
         } else if (opt.sort) {
             o.sorted = result;
             o.sorted_rows = opt.cap >= 0 ? std::min<int64_t>(opt.cap, o.rows) : o.rows;

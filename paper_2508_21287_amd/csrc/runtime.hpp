@@ -81,6 +81,10 @@ struct Workspace {
     uint64_t* heap_words = nullptr;
     int64_t heap_words_cap = 0;
     uint32_t heap_epoch = 0;
+    // fixed: every buffer above is a view into memory the workspace does not
+    // own (the allocation-free entry point's scratch array); a request beyond
+    // a buffer's size fails with DM_ERR_BUDGET_EXCEEDED instead of growing it
+    bool fixed = false;
 
     dm_status init(dm_context* c, hipStream_t s);
     void release();
@@ -192,6 +196,10 @@ struct RunOptions {
     bool score = false;        // layout costs per row; with cap >= 0 the cap best rows by (cost, row)
     int64_t result_limit = 0;  // bytes the kept rows may take (0 = what device memory holds)
     int64_t wait_limit_us = 0; // bound of device waits in microseconds (0 = the default)
+    // caller-owned destination of the sorted rows (row-major, out_buf_rows
+    // rows); nullptr = the run allocates its result
+    int32_t* out_buf = nullptr;
+    int64_t out_buf_rows = 0;
 };
 
 // Bounded-wait control of one run: the run's abort word and record, the
@@ -228,8 +236,14 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
 // (spill_n[2], max_chunks, dup), dup is nonzero afterwards if two rows of a
 // segment were equal.
 // abort: the run's abort word (the tiers do nothing once it is set).
+// max_in_cap bounds every job's rows; when it exceeds the tier-2 tile the
+// count of segments tier 2 passed on is read back through host_word (host
+// memory) and the merge tier is launched only if there are any.  prof
+// (optional, 3 events): recorded after the LDS tiers and around the merge
+// tier; *merged tells whether it ran.
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
-                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort);
+                       int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
+                       int32_t* host_word, hipEvent_t* prof = nullptr, bool* merged = nullptr);
 
 dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan);
 // zero layout costs for a data graph that has none set yet

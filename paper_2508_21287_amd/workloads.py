@@ -239,6 +239,32 @@ def lattice_subgraph_pattern(g: Graph, k: int, rng, thin: bool = True, adj=None)
     return Pattern(k, edges, f"sub{k}", planted=np.array(order, dtype=np.int32))
 
 
+def lattice_tree_pattern(g: Graph, k: int, seed: int, adj=None) -> Pattern:
+    """A random ``k``-vertex subtree of ``g``: random BFS from a uniform root
+    (seeded), each visited vertex joined to the vertex it was discovered
+    from.  Relabelled ``0..k-1`` in BFS order (``planted`` as for
+    ``lattice_subgraph_pattern``)."""
+    adj = adj if adj is not None else adjacency_lists(g)
+    rng = np.random.default_rng(seed)
+    root = int(rng.integers(0, g.n))
+    order, parent = [root], {root: -1}
+    frontier = [root]
+    while frontier and len(order) < k:
+        rng.shuffle(frontier)
+        u = frontier.pop()
+        nb = list(adj[u])
+        rng.shuffle(nb)
+        for w in nb:
+            if w not in parent and len(order) < k:
+                parent[w] = u
+                order.append(w)
+                frontier.append(w)
+    if len(order) < k:
+        raise ValueError("lattice component smaller than the requested tree")
+    edges, planted = _relabel(order, [(parent[v], v) for v in order[1:]])
+    return Pattern(k, edges, f"L{k}s{seed}", seed=seed, planted=planted)
+
+
 def circuit_pattern(g: Graph, seed: int, k_lo: int = 4, k_hi: int = 40, adj=None) -> Pattern:
     """Interaction graph of a random two-qubit-gate circuit on a lattice
     subgraph: ``k = round(exp(U[ln k_lo, ln k_hi]))`` qubits, ``H`` a random-BFS
@@ -317,13 +343,20 @@ def config3_lattices():
 
 def config3(lattice: str, n_trees: int = 4):
     """Scaling: one of HH(28,28), HH(56,56), HH(90,90), GRID(100,100), with
-    P8, P12, P16, C12, 16-vertex Pruefer trees (the first ``n_trees`` seeds whose
-    maximum degree does not exceed the lattice's) and the 2x3 / 3x3 grids."""
+    P8, P12, P16, C12, ``n_trees`` random 16-vertex trees and the 2x3 / 3x3
+    grids.  On the grid the trees are uniformly random labelled trees
+    (Pruefer codes; the first seeds whose maximum degree is at most 4).  A
+    random labelled tree almost never fits a heavy-hex lattice (its degree-3
+    vertices sit too close), so there the trees are random subtrees of the
+    lattice (``lattice_tree_pattern``, seeds 0..n_trees-1)."""
     g = config3_lattices()[lattice]
     dmax = max_degree(g)
     pats = [path(8), path(12), path(16), cycle(12)]
     s = 0
     trees = []
+    if lattice.startswith("HH"):
+        adj = adjacency_lists(g)
+        trees = [lattice_tree_pattern(g, 16, t, adj=adj) for t in range(n_trees)]
     while len(trees) < n_trees:
         t = prufer_tree(16, s)
         if max_degree(t) <= dmax:

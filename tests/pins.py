@@ -416,6 +416,25 @@ def pin_root_ranges(lib):
             parts.append(r)
             acc += t
         assert acc == total and np.array_equal(np.vstack(parts), full), p.name
+    # the streaming form over a root range: brute force restricted to those
+    # roots, hashed row by row here; a partition's pieces combine into the
+    # full count and hashes (sums add mod 2^64, hashes XOR)
+    g = W.heavy_hex(2, 5)
+    for p in [W.path(4), W.cycle(4), small_patterns()[11]]:
+        want = brute_force_rows(g.n, g.edges, p.n, p.edges)
+        hs = [py_row_hash(r) for r in want.tolist()]
+        c0, s0, x0 = oracle.count_hash(g.n, g.edges, p.n, p.edges, lib=lib)
+        acc_c, acc_s, acc_x = 0, 0, 0
+        for lo, hi in [(0, 1), (1, 4), (4, 4), (4, 11), (11, g.n)]:
+            sel = [h for r, h in zip(want.tolist(), hs) if lo <= r[0] < hi]
+            xr = 0
+            for h in sel:
+                xr ^= h
+            c, s, x = oracle.count_hash_range(g.n, g.edges, p.n, p.edges, (lo, hi), lib=lib)
+            assert (c, s, x) == (len(sel), sum(sel) & M64, xr), (p.name, lo, hi)
+            acc_c, acc_s, acc_x = acc_c + c, (acc_s + s) & M64, acc_x ^ x
+        assert (acc_c, acc_s, acc_x) == (c0, s0, x0), p.name
+        assert oracle.count_hash_threads(g.n, g.edges, p.n, p.edges, 3, lib=lib) == (c0, s0, x0), p.name
 
 
 def brute_force_induced_rows(nd, ed, k, ep):

@@ -70,7 +70,7 @@ def test_heavy_hex_10k(ctx):
             assert r.total == pins.nonbacktracking_paths(g, k)
     # full tables against the oracle where it is quick
     _, pats = W.config3("HH90", n_trees=2)
-    for p in [W.path(16)] + [q for q in pats if q.name.startswith("T16")]:
+    for p in [W.path(16)] + [q for q in pats if q.name.startswith("L16")]:
         say(f"HH90 {p.name}")
         c, hs, hx = oracle.count_hash(g.n, g.edges, p.n, p.edges)
         with dg.enumerate(p.n, p.edges, mode=dm.OUT_COUNT_HASH) as r:
@@ -120,4 +120,70 @@ def test_grid_100(ctx):
             assert (r.total, r.hash()[0], r.hash()[1]) == (want["count"], int(want["hash_sum"]),
                                                            int(want["hash_xor"]))
         check_root_segments(dg, g, p, sampled_roots(g.n, 2, 5))
+    dg.free()
+
+
+def gold_cases():
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_counts.json")))["cases"]
+
+
+@pytest.mark.parametrize("lat", ["HH28", "HH56", "HH90"])
+def test_heavy_hex_config3_tables(ctx, lat):
+    """Every scaling pattern on a heavy-hex lattice: the full sorted table
+    against the oracle's, and the count+hash mode against the stored value."""
+    g, pats = W.config3(lat)
+    gold = gold_cases()
+    dg = ctx.datagraph(g.n, g.edges)
+    for p in pats:
+        say(f"{lat} {p.name}")
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+        with dg.enumerate(p.n, p.edges) as r:
+            assert r.total == total and np.array_equal(r.to_numpy(), want), (lat, p.name)
+        w = gold[f"{lat}/{p.name}"]
+        with dg.enumerate(p.n, p.edges, mode=dm.OUT_COUNT_HASH) as r:
+            assert (r.total,) + r.hash() == (w["count"], int(w["hash_sum"]), int(w["hash_xor"])), (lat, p.name)
+    dg.free()
+
+
+def test_grid_100_c12_table(ctx):
+    """C12 on the grid as a full sorted table (2.8e7 rows through a 1.5e8-row
+    intermediate): strictly increasing rows whose multiset hash is the
+    oracle's, plus sampled root segments row for row."""
+    g = W.grid(100, 100)
+    p = W.cycle(12)
+    w = gold_cases()["GRID100/C12"]
+    dg = ctx.datagraph(g.n, g.edges)
+    with dg.enumerate(p.n, p.edges) as r:
+        assert r.total == r.rows == w["count"]
+        t = r.to_numpy()
+    pins.assert_strictly_sorted(t)
+    hsum = hxor = 0
+    for j in range(0, len(t), 1 << 22):
+        hs_j, hx_j = pins.row_hash_sum_xor(t[j:j + (1 << 22)])
+        hsum = (hsum + hs_j) % (1 << 64)
+        hxor ^= hx_j
+    assert (hsum, hxor) == (int(w["hash_sum"]), int(w["hash_xor"]))
+    pins.check_table(g, p, t[:: max(1, len(t) // 20000)])
+    del t
+    check_root_segments(dg, g, p, sampled_roots(g.n, 3, 11))
+    dg.free()
+
+
+@pytest.mark.parametrize("name", ["P12", "P16", "trees"])
+def test_grid_100_over_budget(ctx, name):
+    """The grid pairs far beyond the table budget (1e9..6e10 embeddings),
+    count+hash mode over root ranges chunked to the memory budget, against
+    the oracle's stored values; rows of sampled roots against the oracle."""
+    g, pats = W.config3("GRID100")
+    gold = gold_cases()
+    sel = [p for p in pats if (p.name == name if name != "trees" else p.name.startswith("T16"))]
+    assert sel
+    dg = ctx.datagraph(g.n, g.edges)
+    for p in sel:
+        w = gold[f"GRID100/{p.name}"]
+        say(f"grid100 {p.name}: expecting {w['count']} embeddings")
+        with dg.enumerate(p.n, p.edges, mode=dm.OUT_COUNT_HASH) as r:
+            assert (r.total,) + r.hash() == (w["count"], int(w["hash_sum"]), int(w["hash_xor"])), p.name
+            say(f"grid100 {p.name}: {r.total} in {r.stats()['chunks']} root-range chunks")
+        check_root_segments(dg, g, p, sampled_roots(g.n, 1, 13))
     dg.free()
