@@ -311,6 +311,37 @@ dm_status dm_estimate(dm_datagraph* dg, const dm_graph_desc* gp, const dm_plan_o
 dm_status dm_enumerate(dm_datagraph* dg, const dm_graph_desc* gp, int64_t max_embeddings,
                        const dm_plan_opts* opts, dm_result** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * enumeration as dm_enumerate, with no device allocation of any kind.  Every
+ * intermediate buffer of the run (the join tables, look-back words, tickets,
+ * control block and the sort's lists and index scratch) lives in one fixed
+ * device array of DM_NOALLOC_SCRATCH_MB MiB compiled into the library; each
+ * device the library runs on holds its own copy until the process ends.
+ *
+ * out: caller-owned device buffer of out_rows_cap rows of |V_p| int32,
+ *   receiving the lexicographically sorted rows (the first max_embeddings
+ *   when max_embeddings >= 0), row-major.  NULL or out_rows_cap == 0 in
+ *   table mode: only the count is produced (no sort).  Unused in count+hash
+ *   mode (opts->output_mode).
+ * rows: rows written; total: all embeddings; hash_sum / hash_xor (may be
+ *   NULL): the count+hash mode's multiset hash (see dm_result_hash).
+ * opts: as dm_enumerate; mem_budget, result_mb are ignored (the scratch
+ *   bounds the tables); score and profile are DM_ERR_UNSUPPORTED.
+ * Returns after the device work has finished (one readback).
+ * Errors: pattern validation codes; DM_ERR_BUDGET_EXCEEDED when an
+ *   intermediate table does not fit the scratch (the data graph, rows x
+ *   columns of the widest table and the sort's index scratch share it), or
+ *   when the kept rows exceed out_rows_cap (then *total holds the count and
+ *   out holds the first out_rows_cap rows); DM_ERR_DEVICE, DM_ERR_CANCELLED.
+ * Calls on one device share its array: the library runs them one at a time
+ * (a per-device lock held for the whole call), and a call leaves the array
+ * holding its own tables, which the next call overwrites. */
+#define DM_NOALLOC_SCRATCH_MB 64
+dm_status dm_enumerate_noalloc(dm_datagraph* dg, const dm_graph_desc* gp, int64_t max_embeddings,
+                               const dm_plan_opts* opts, int32_t* out, int64_t out_rows_cap, int64_t* rows,
+                               int64_t* total, uint64_t* hash_sum, uint64_t* hash_xor);
+
 /* Batched Algorithm 1: `n` patterns against the same resident data graph in
  * one persistent-kernel launch (per-pattern plans, device work queue).
  * caps may be NULL (all).  outs[i] receives pattern i's result; on error no

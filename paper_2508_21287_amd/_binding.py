@@ -133,7 +133,8 @@ EXPORTS = [
     "dm_datagraph_build",
     "dm_datagraph_free", "dm_datagraph_save", "dm_datagraph_load", "dm_datagraph_set_costs",
     "dm_result_device_costs", "dm_result_copy_costs", "dm_autotune_motifs", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
-    "dm_estimate", "dm_enumerate", "dm_enumerate_batch", "dm_result_rows", "dm_result_total",
+    "dm_estimate", "dm_enumerate", "dm_enumerate_noalloc", "dm_enumerate_batch", "dm_result_rows",
+    "dm_result_total",
     "dm_result_width", "dm_result_device_data", "dm_result_hash", "dm_result_copy_to_host",
     "dm_result_copy_to_device", "dm_result_stats", "dm_result_free", "dm_result_summaries",
     "dm_result_free_many", "dm_server_start", "dm_server_submit", "dm_server_wait", "dm_server_stop",
@@ -186,6 +187,9 @@ def lib() -> C.CDLL:
             "dm_estimate": (C.c_int, [vp, C.POINTER(GraphDesc), C.POINTER(PlanOpts), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]),
             "dm_enumerate": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_int64, C.POINTER(PlanOpts), C.POINTER(vp)]),
+            "dm_enumerate_noalloc": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_int64, C.POINTER(PlanOpts), vp,
+                                               C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                               C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
             "dm_enumerate_batch": (C.c_int, [vp, C.c_int32, C.POINTER(GraphDesc), C.POINTER(C.c_int64),
                                              C.POINTER(PlanOpts), C.POINTER(vp)]),
             "dm_result_rows": (C.c_int64, [vp]),
@@ -550,6 +554,20 @@ class DataGraph:
         h = C.c_void_p()
         _check(lib().dm_enumerate(self._h, C.byref(g.desc), int(cap), C.byref(o), C.byref(h)))
         return Result(h, self.ctx)
+
+    def enumerate_noalloc(self, n: int, edges, out_ptr: int, out_rows_cap: int, cap: int = -1,
+                          **opts) -> tuple[int, int, tuple[int, int]]:
+        """``dm_enumerate_noalloc``: the sorted rows into the caller's device
+        buffer at ``out_ptr`` (``out_rows_cap`` rows of ``n`` int32), with no
+        device allocation.  Returns ``(rows, total, (hash_sum, hash_xor))``."""
+        g = _Graph(n, edges)
+        o = _opts(**opts)
+        rows, total = C.c_int64(), C.c_int64()
+        hs, hx = C.c_uint64(), C.c_uint64()
+        _check(lib().dm_enumerate_noalloc(self._h, C.byref(g.desc), int(cap), C.byref(o),
+                                          C.c_void_p(int(out_ptr) or None), int(out_rows_cap), C.byref(rows),
+                                          C.byref(total), C.byref(hs), C.byref(hx)))
+        return rows.value, total.value, (hs.value, hx.value)
 
     def enumerate_batch(self, patterns, caps=None, **opts) -> list[Result]:
         descs, keep = _desc_array(patterns)

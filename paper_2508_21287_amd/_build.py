@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libdmotif.so")
 
-SOURCES = ["kernels.hip", "runtime.cpp", "planner.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "planner.cpp", "batch.cpp", "noalloc.hip"]
 
 # gfx950 only; packed-FP32 instructions stay disabled for every HIP object.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
