@@ -99,8 +99,13 @@ typedef enum {
 #define DM_MOTIF_M4_1 (1u << 7)
 #define DM_MOTIF_M6_2O (1u << 8)
 #define DM_MOTIF_M18_O_6 (1u << 9)
-#define DM_MOTIF_ALL 0x3FFu
-#define DM_NUM_MOTIFS 11
+/* M7 = the 7-vertex path, kept keyed at its ends only, each key group ordered
+ * by the far end: it closes 12-cycles as one two-key join of two 7-paths
+ * (Alg. 2 builds it from M4 joined with M4; Sec. III-D, larger motifs from
+ * joins of smaller ones). */
+#define DM_MOTIF_M7 (1u << 10)
+#define DM_MOTIF_ALL 0x7FFu
+#define DM_NUM_MOTIFS 12
 #define DM_MOTIF_AUTO 0u
 /* For dm_plan_opts.motif_mask: plan with M2 only (Sec. IV-B: one join per
  * pattern edge, the parallel analogue of tree search). */
@@ -220,7 +225,7 @@ typedef struct {
     int32_t has_bitmap;       /* adjacency bitmap built (|V| <= 32768) */
     uint32_t motif_mask;      /* motifs actually built */
     int64_t motif_rows[DM_NUM_MOTIFS]; /* rows of Res(M) for M2,M3,M4,M5,M6,C4,C6,C12,M4-1,M6-2O,
-                                          M18-O-6 (0 = absent) */
+                                          M18-O-6,M7 (0 = absent) */
     double build_ms;          /* device time of the whole build */
 } dm_datagraph_info;
 

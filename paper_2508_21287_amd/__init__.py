@@ -9,11 +9,11 @@ generators and imports nothing else from this package.
 from ._binding import (DMError, Context, DataGraph, Result, Server, plan, lib, EXPORTS, LIB_PATH, summarize,
                        free_results,
                        MOTIF_M3, MOTIF_M4, MOTIF_M5, MOTIF_M6, MOTIF_C4, MOTIF_C6, MOTIF_C12, MOTIF_M4_1,
-                       MOTIF_M6_2O, MOTIF_M18_O_6, MOTIF_ALL,
+                       MOTIF_M6_2O, MOTIF_M18_O_6, MOTIF_M7, MOTIF_ALL,
                        MOTIF_AUTO, MOTIF_M2_ONLY, MOTIF_NAMES, OUT_TABLE, OUT_COUNT_HASH)
 
 __all__ = ["DMError", "Context", "DataGraph", "Result", "Server", "plan", "lib", "EXPORTS", "LIB_PATH", "summarize",
            "free_results",
            "MOTIF_M3", "MOTIF_M4", "MOTIF_M5", "MOTIF_M6", "MOTIF_C4", "MOTIF_C6", "MOTIF_C12", "MOTIF_M4_1",
-           "MOTIF_M6_2O", "MOTIF_M18_O_6", "MOTIF_ALL",
+           "MOTIF_M6_2O", "MOTIF_M18_O_6", "MOTIF_M7", "MOTIF_ALL",
            "MOTIF_AUTO", "MOTIF_M2_ONLY", "MOTIF_NAMES", "OUT_TABLE", "OUT_COUNT_HASH"]

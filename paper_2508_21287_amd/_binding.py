@@ -36,9 +36,9 @@ STATUS = {0: "DM_OK", -1: "DM_ERR_INVALID_ARG", -2: "DM_ERR_VERTEX_RANGE", -3: "
 
 MOTIF_M3, MOTIF_M4, MOTIF_M5, MOTIF_M6 = 1 << 0, 1 << 1, 1 << 2, 1 << 3
 MOTIF_C4, MOTIF_C6, MOTIF_C12 = 1 << 4, 1 << 5, 1 << 6
-MOTIF_M4_1, MOTIF_M6_2O, MOTIF_M18_O_6 = 1 << 7, 1 << 8, 1 << 9
-MOTIF_ALL, MOTIF_AUTO, MOTIF_M2_ONLY = 0x3FF, 0, 0x80000000
-MOTIF_NAMES = ["M2", "M3", "M4", "M5", "M6", "M4-O", "M6-O", "M12-O", "M4-1", "M6-2O", "M18-O-6"]
+MOTIF_M4_1, MOTIF_M6_2O, MOTIF_M18_O_6, MOTIF_M7 = 1 << 7, 1 << 8, 1 << 9, 1 << 10
+MOTIF_ALL, MOTIF_AUTO, MOTIF_M2_ONLY = 0x7FF, 0, 0x80000000
+MOTIF_NAMES = ["M2", "M3", "M4", "M5", "M6", "M4-O", "M6-O", "M12-O", "M4-1", "M6-2O", "M18-O-6", "M7"]
 MAX_PATTERN_VERTICES = 128
 
 OUT_TABLE, OUT_COUNT_HASH = 0, 1
@@ -98,7 +98,7 @@ class PlanOpts(C.Structure):
 
 class DataGraphInfo(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("n_directed_edges", C.c_int64), ("max_degree", C.c_int32),
-                ("has_bitmap", C.c_int32), ("motif_mask", C.c_uint32), ("motif_rows", C.c_int64 * 11),
+                ("has_bitmap", C.c_int32), ("motif_mask", C.c_uint32), ("motif_rows", C.c_int64 * 12),
                 ("build_ms", C.c_double)]
 
 

@@ -19,9 +19,11 @@ constexpr int kMaxMotifEdges = 18;  // edges of a general-shape motif
 
 // Motif catalogue (Sec. III-A "Motifs": M_i = path of i vertices, -O =
 // cycle; the general shapes of Sec. VI-B: M4-1 = claw, M6-2O = 2x3 grid,
-// M18-O-6 = the heavy-hex cell with a pendant at every other vertex).
+// M18-O-6 = the heavy-hex cell with a pendant at every other vertex; M7, a
+// longer path keyed at its ends only, for two-key joins of path tables).
 // Index order matches dm_datagraph_info.motif_rows.
-enum MotifIndex { MOT_P2 = 0, MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23, MOT_H18 };
+enum MotifIndex { MOT_P2 = 0, MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23, MOT_H18,
+                  MOT_P7 };
 
 struct MotifInfo {
     int size;
@@ -31,6 +33,8 @@ struct MotifInfo {
     bool general;  // neither path nor cycle: shape given by `edges`
     int n_edges;
     int8_t edges[kMaxMotifEdges][2];
+    // a path whose table is keyed at its ends only (slices must share an end)
+    bool ends_only;
 };
 
 // General shapes are labelled so that positions 0..K-1 are one
@@ -56,7 +60,8 @@ inline const MotifInfo& motif_info(int m) {
         // the pendants {2,..})
         {18, false, DM_MOTIF_M18_O_6, "M18-O-6", true, 18,
          {{0, 1}, {1, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {7, 8}, {8, 9}, {9, 10}, {10, 11}, {11, 12}, {12, 0},
-          {0, 2}, {3, 13}, {5, 14}, {7, 15}, {9, 16}, {11, 17}}}};
+          {0, 2}, {3, 13}, {5, 14}, {7, 15}, {9, 16}, {11, 17}}},
+        {7, false, DM_MOTIF_M7, "M7", false, 0, {}, true}};
     return kInfo[m];
 }
 
@@ -71,6 +76,7 @@ const int8_t* general_motif_to_rep(int m, int pos);
 inline int motif_key_positions(int m) {
     const MotifInfo& mi = motif_info(m);
     if (mi.general) return general_motif_orbits(m);
+    if (mi.ends_only) return 1;
     return mi.cycle ? 1 : (mi.size + 1) / 2;
 }
 
@@ -117,6 +123,7 @@ struct Plan {
     int32_t pv_of[kMaxCols];   // table column -> pattern vertex
     double est_peak_rows_cols = 0;  // max over steps of rows*cols (in + out)
     double est_final_rows = 0;
+    double est_cost = 0;            // table values read, tested and written over all steps
 };
 
 struct NormPattern {

@@ -18,11 +18,14 @@ struct TableDev {
     int64_t rows;
     int32_t size;
     // 1 + the motif position by which the rows of every key group of at most
-    // kGroupSortMax rows are ascending (0: no such order)
+    // sorted_max rows are ascending (0: no such order)
     int32_t sorted_by;
+    int32_t sorted_max;
+    int32_t pad_;
 };
 
-constexpr int kGroupSortMax = 64;
+constexpr int kGroupSortMax = 64;    // groups the per-thread insertion sort orders
+constexpr int kGroupSortLds = 4096;  // groups the per-workgroup LDS sort orders
 
 // Normalized data graph: CSR (each list ascending) + optional adjacency bitmap
 // (bit v of row u set iff {u, v} is an edge; words_per_row 32-bit words/row).
@@ -301,6 +304,10 @@ hipError_t launch_claw_fill(const int32_t* rp, const int32_t* col, int32_t n, in
 // stride `stride`) by column `sec`, stably
 hipError_t launch_group_sort(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec, int32_t* data,
                              hipStream_t s);
+// The same order for groups of up to kGroupSortLds rows, any number of
+// columns, from `in` into `out` (larger groups copied unchanged)
+hipError_t launch_group_sort_lds(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec,
+                                 const int32_t* in, int32_t* out, hipStream_t s);
 // *nnz_dev (<= nnz_max) directed edges, read on the device
 hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int64_t nnz_max,
                              int32_t wpr, uint32_t* bitmap, hipStream_t s);

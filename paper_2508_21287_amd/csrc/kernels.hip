@@ -358,7 +358,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             lo = a.tbl.offs[key];
             hi = a.tbl.offs[key + 1];
             if (!LAT && st.n_eq > 0 && a.tbl.sorted_by == st.eq_pos[0] + 1 && hi - lo > 16 &&
-                hi - lo <= kGroupSortMax) {
+                hi - lo <= a.tbl.sorted_max) {
                 // the key group is ordered by the first further key's position:
                 // keep only its run equal to this row's value (the rest fail that
                 // key anyway, and the test below still checks every candidate)
@@ -1160,6 +1160,75 @@ __device__ __forceinline__ int glb_row_cmp(const SortJob& a, int64_t seg0, uint3
     return 0;
 }
 
+// Copy the rows [seg0, seg0 + len) of a final table to the row-major output
+// in pattern-vertex order (rows below out_rows only), checking on the way
+// that they increase strictly, in chunks staged in LDS: each column of a
+// chunk is read coalesced, the rows are compared with their predecessors
+// (the previous chunk's last row is kept), and the chunk is written
+// row-major, coalesced.  Stops at the first chunk out of order and returns
+// false (what was written is overwritten by the sort); true when the whole
+// segment was in order.  tile: at least k * (CH + 1) + k int32 of LDS with
+// CH = chunk rows.  Called by the whole workgroup.
+__device__ bool copy_if_sorted(const SortJob& job, int64_t seg0, int64_t len, int64_t out_rows, int32_t* tile,
+                               int lds_words) {
+    const int k = job.k, nt = (int)blockDim.x, tid = threadIdx.x;
+    int ch = (lds_words - k) / k - 1;  // chunk rows; stride ch + 1 is odd or at least not a bank multiple
+    if (ch > 1024) ch = 1024;
+    if (ch < 1) return false;
+    const int cs = ch + 1;
+    int32_t* prev = tile + (size_t)k * cs;
+    for (int64_t r0 = 0; r0 < len; r0 += ch) {
+        const int n = (int)((len - r0 < ch) ? (len - r0) : ch);
+        // stage: element e = j * n + r, (column, row) stepped without a division
+        {
+            const int dj = nt / n, dr = nt - dj * n;
+            int j = tid / n, r = tid - j * n;
+            for (int e = tid; e < n * k; e += nt) {
+                tile[j * cs + r] = job.in[(int64_t)job.perm[j] * job.in_stride + seg0 + r0 + r];
+                j += dj;
+                r += dr;
+                if (r >= n) {
+                    r -= n;
+                    j++;
+                }
+            }
+        }
+        __syncthreads();
+        int bad = 0;
+        for (int r = tid; r < n; r += nt) {
+            if (r0 == 0 && r == 0) continue;
+            int c = 0;
+            for (int j = 1; j < k && c == 0; j++) {
+                const int32_t a = r > 0 ? tile[j * cs + r - 1] : prev[j], b = tile[j * cs + r];
+                c = a < b ? -1 : (a > b ? 1 : 0);
+            }
+            bad |= c >= 0;
+        }
+        if (__syncthreads_or(bad)) return false;
+        const int64_t left = out_rows - (seg0 + r0);
+        const int nw = left <= 0 ? 0 : (left < n ? (int)left : n);
+        {
+            int32_t* dst = job.out + (seg0 + r0) * k;
+            const int dr = nt / k, dj = nt - dr * k;
+            int r = tid / k, j = tid - r * k;
+            for (int e = tid; e < nw * k; e += nt) {
+                dst[e] = tile[j * cs + r];
+                r += dr;
+                j += dj;
+                if (j >= k) {
+                    j -= k;
+                    r++;
+                }
+            }
+        }
+        if (job.out_cost)
+            for (int r = tid; r < nw; r += nt) job.out_cost[seg0 + r0 + r] = job.in_cost[seg0 + r0 + r];
+        if (tid < k) prev[tid] = tile[tid * cs + n - 1];
+        __syncthreads();
+    }
+    return true;
+}
+
 // LDS tiers: one workgroup per root segment.  Without an input list the items
 // are every (job, root vertex) pair and the segment is found by search;
 // segments larger than this tier's LDS tile are passed on.
@@ -1196,26 +1265,11 @@ __global__ __launch_bounds__(1024) void sort_lds_kernel(const SortLaunch L) {
         const int cap_rows = lds_rows_of(L.lds_bytes, wp);
         __syncthreads();  // every lane has read job and s_seg: the next item may overwrite them
         if (len == 0 || seg0 >= out_rows) continue;
+        // a segment the joins left in order (paths placed in label order, and
+        // every join that extends rows with candidates in ascending order)
+        // needs no sort: copied out in one coalesced pass while it is checked
+        if (!L.list && copy_if_sorted(job, seg0, len, out_rows, (int32_t*)lds, L.lds_bytes / 4)) continue;
         if (len > cap_rows) {
-            if (!L.list) {
-                // a large segment the joins left in order needs no sort at all:
-                // check it in the table and write it out directly
-                int uns = 0;
-                for (int64_t r = tid + 1; r < len; r += (int)blockDim.x) uns |= glb_row_cmp(job, seg0, r - 1, r) >= 0;
-                if (!__syncthreads_or(uns)) {
-                    const int64_t nw = (seg0 + len <= out_rows) ? len : (out_rows - seg0);
-                    int32_t* dst = job.out + seg0 * k;
-                    for (int64_t e = tid; e < nw * k; e += (int)blockDim.x) {
-                        const int64_t r = e / k;
-                        const int j = (int)(e - r * k);
-                        dst[e] = job.in[(int64_t)job.perm[j] * job.in_stride + seg0 + r];
-                    }
-                    if (job.out_cost)
-                        for (int64_t r = tid; r < nw; r += (int)blockDim.x) job.out_cost[seg0 + r] = job.in_cost[seg0 + r];
-                    __syncthreads();
-                    continue;
-                }
-            }
             if (tid == 0) push_segment(L, item, seg0, len);
             continue;
         }
@@ -1902,6 +1956,59 @@ hipError_t launch_group_sort(const int32_t* offs, int32_t n, int64_t stride, int
                              hipStream_t s) {
     if (n <= 0 || size > 6 || sec < 0 || sec >= size) return hipSuccess;
     hipLaunchKernelGGL(group_sort_kernel, dim3(grid_for(n, 64)), dim3(64), 0, s, offs, n, stride, size, sec, data);
+    return hipGetLastError();
+}
+
+// Order every key group (rows [offs[v], offs[v+1]) of the SoA table `in`,
+// `size` columns of stride `stride`) by column `sec`, stably, into `out`
+// (same offsets): one workgroup per key vertex sorts (value, position) pairs
+// with a bitonic network in LDS and writes every column permuted.  Groups of
+// more than kGroupSortLds rows are copied unchanged.
+__global__ __launch_bounds__(256) void group_sort_lds_kernel(const int32_t* offs, int32_t n, int64_t stride,
+                                                             int32_t size, int32_t sec, const int32_t* in,
+                                                             int32_t* out) {
+    __shared__ uint64_t key[kGroupSortLds];
+    const int tid = threadIdx.x, nt = (int)blockDim.x;
+    for (int32_t v = blockIdx.x; v < n; v += gridDim.x) {
+        const int32_t a = offs[v], len = offs[v + 1] - offs[v];
+        if (len <= 0) continue;
+        if (len == 1 || len > kGroupSortLds) {
+            for (int q = 0; q < size; q++)
+                for (int32_t i = tid; i < len; i += nt) out[(int64_t)q * stride + a + i] = in[(int64_t)q * stride + a + i];
+            continue;
+        }
+        int P = 1;
+        while (P < len) P <<= 1;
+        const int32_t* kc = in + (int64_t)sec * stride + a;
+        for (int i = tid; i < P; i += nt) key[i] = i < len ? (((uint64_t)(uint32_t)kc[i] << 32) | (uint32_t)i) : ~0ull;
+        __syncthreads();
+        for (int sz = 2; sz <= P; sz <<= 1) {
+            for (int st = sz >> 1; st > 0; st >>= 1) {
+                for (int t = tid; t < (P >> 1); t += nt) {
+                    const int lo = 2 * t - (t & (st - 1)), hi = lo + st;
+                    const uint64_t x = key[lo], y = key[hi];
+                    if ((x > y) == ((lo & sz) == 0)) {
+                        key[lo] = y;
+                        key[hi] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int q = 0; q < size; q++) {
+            const int32_t* src = in + (int64_t)q * stride + a;
+            int32_t* dst = out + (int64_t)q * stride + a;
+            for (int32_t i = tid; i < len; i += nt) dst[i] = src[(uint32_t)key[i]];
+        }
+        __syncthreads();  // key[] is refilled for the next group
+    }
+}
+
+hipError_t launch_group_sort_lds(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec,
+                                 const int32_t* in, int32_t* out, hipStream_t s) {
+    if (n <= 0 || sec < 0 || sec >= size) return hipSuccess;
+    hipLaunchKernelGGL(group_sort_lds_kernel, dim3(n < 16384 ? n : 16384), dim3(256), 0, s, offs, n, stride, size,
+                       sec, in, out);
     return hipGetLastError();
 }
 

@@ -199,6 +199,7 @@ struct Planner {
     // search state
     int32_t L = 0;
     bool cyc = false;
+    bool ends_only = false;
     int32_t seq[kMaxMotif];
     char inseq[kMaxCols];
     int64_t expansions = 0, found = 0;
@@ -242,6 +243,8 @@ struct Planner {
         int keys = 0, nnew = 0;
         for (int i = 0; i < L; i++) (mapped(seq[i]) ? keys : nnew)++;
         if (keys == 0 || nnew == 0) return;
+        // a motif keyed at its ends only: the slice must share an end
+        if (ends_only && !mapped(seq[0]) && !mapped(seq[L - 1])) return;
         int score = 2 * keys + count_checks(seq);
         if (score > best_score) {
             best_score = score;
@@ -268,9 +271,10 @@ struct Planner {
         }
     }
 
-    bool search(int32_t size, bool cycle) {
+    bool search(int32_t size, bool cycle, bool ends = false) {
         L = size;
         cyc = cycle;
+        ends_only = ends;
         expansions = found = 0;
         best_score = -1;
         std::memset(inseq, 0, sizeof inseq);
@@ -282,7 +286,7 @@ struct Planner {
             if (mapped(v)) placed.emplace_back(col_of[v], v);
         std::sort(placed.begin(), placed.end());
         for (auto& pv : placed) starts.push_back(pv.second);
-        if (!cycle)
+        if (!cycle && !ends)
             for (int32_t v = 0; v < k; v++)
                 if (!mapped(v)) starts.push_back(v);
         for (int32_t s : starts) {
@@ -473,13 +477,14 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
     const double br = std::max(deg - 1.0, 1.0);
     double rows = nv;  // identity table: one row per data vertex
     double peak = rows * 1;
+    double cost = 0;
 
     while (pl.ncols < k) {
         int chosen = -1;
         for (int m : order) {
             const MotifInfo& mi = motif_info(m);
             if (mi.size > k) continue;
-            if (mi.general ? pl.search_general(m) : pl.search(mi.size, mi.cycle)) {
+            if (mi.general ? pl.search_general(m) : pl.search(mi.size, mi.cycle, mi.ends_only)) {
                 chosen = m;
                 break;
             }
@@ -522,7 +527,14 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
                     bestd = std::min(i, L - 1 - i);
                     key = i;
                 }
-            if (key > (L - 1) / 2) {
+            if (L >= 3 && pl.mapped(s[0]) && pl.mapped(s[L - 1])) {
+                // both ends placed: key at position 0, the path oriented so that
+                // its new vertices run in ascending label order (the join emits
+                // each row's candidates in motif-position order, so rows then
+                // come out in label order and the final sort finds them sorted)
+                if (s[1] > s[L - 2]) std::reverse(s, s + L);
+                key = 0;
+            } else if (key > (L - 1) / 2) {
                 std::reverse(s, s + L);
                 key = L - 1 - key;
             }
@@ -599,6 +611,19 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
         for (int e = 0; e < d.n_eq; e++) nrows /= std::max(1.0, deg * std::pow(br, std::max(0, min_eq_dist - 1)));
         for (int e = 0; e < (int)checks.size(); e++) nrows /= std::max(1.0, deg * br);
         peak = std::max(peak, rows * d.c_in + nrows * (d.c_in + d.n_new));
+        // work of the step in table values: the input rows read, every
+        // candidate's loaded values and checks, the output rows written; a
+        // first step that only copies a motif table keyed at position 0 is
+        // taken in place (no work)
+        // taken in place (no work).  A path keyed at one end whose further key
+        // is the other end is binary-searched on a copy ordered by that end:
+        // only the matching run is tested.
+        const bool in_place = plan.steps.empty() && d.key_pos == 0 && d.n_eq == 0 && checks.empty() && !mi.general;
+        double cand = rows * fan;
+        if (!mi.general && !mi.cycle && d.key_pos == 0 && d.n_eq > 0 && d.eq_pos[0] == L - 1)
+            cand = cand / std::max(1.0, deg * std::pow(br, std::max(0, L - 2))) + rows * std::log2(std::max(fan, 2.0));
+        if (!in_place)
+            cost += rows * d.c_in + cand * (d.n_new + d.n_eq + (double)checks.size()) + nrows * (d.c_in + d.n_new);
         rows = nrows;
         ps.est_rows = rows;
         plan.steps.push_back(ps);
@@ -639,6 +664,7 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
     }
     plan.est_final_rows = rows;
     plan.est_peak_rows_cols = peak;
+    plan.est_cost = cost;
     *out = std::move(plan);
     return DM_OK;
 }

@@ -389,6 +389,31 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         }
     } result_guard{ctx, &result, &result_cost, s};
 
+    // Step 0 straight from the motif table, with no launch: over every root,
+    // the identity table joined with a motif keyed at position 0 whose new
+    // columns are positions 1..L-1 in order, with nothing to check, is the
+    // motif table itself (its rows are injective and grouped by the key in
+    // ascending order), so the next step reads the table in place.
+    bool zc0 = false;
+    const int32_t* zc_base = nullptr;
+    int64_t zc_stride = 0, zc_rows = 0;
+    {
+        const StepDesc& d0 = steps[0];
+        if (d0.motif >= 0 && !score && !opt.induced && v0 == 0 && v1 == dg->n && d0.key_pos == 0 && d0.n_eq == 0 &&
+            d0.n_edge == 0 && !(nsteps == 1 && hash_mode)) {
+            const MotifTable& t = dg->tab[d0.motif][0];
+            bool ident = d0.n_new == t.size - 1 && t.rows > 0 && t.cols[0] != nullptr;
+            for (int q = 0; q < d0.n_new && ident; q++) ident = d0.new_pos[q] == q + 1;
+            for (int q = 1; q < t.size && ident; q++) ident = t.cols[q] == t.cols[0] + (size_t)q * (size_t)t.stride;
+            if (ident) {
+                zc0 = true;
+                zc_base = t.cols[0];
+                zc_stride = t.stride;
+                zc_rows = t.rows;
+            }
+        }
+    }
+
     if (opt.profile) {
         while (ws.prof.size() < (size_t)(2 * nsteps + 4)) {
             hipEvent_t e;
@@ -411,14 +436,23 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         bool redo = false;
         for (int i = 0; i < nsteps; i++) {
             const int ib = (i - 1) & 1, ob = i & 1;
+            if (i == 0 && zc0) {
+                DM_HIP(launch_fill_u64((uint64_t*)&ws.ctrl_d->counts[1], (uint64_t)zc_rows, 1, s));
+                if (opt.profile) {
+                    DM_HIP(hipEventRecord(ws.prof[0], s));
+                    DM_HIP(hipEventRecord(ws.prof[1], s));
+                }
+                continue;
+            }
             EjfArgs a;
             std::memset(&a, 0, sizeof a);
             a.st = steps[i];
             if (a.st.motif >= 0) a.tbl = dg->table_dev_step(a.st);
             a.g = dg->graph_dev();
-            a.in = i == 0 ? nullptr : ws.buf[ib];
-            a.in_stride = i == 0 ? 0 : cap[ib];
-            a.in_cap = i == 0 ? 0 : cap[ib];
+            const bool from_table = i == 1 && zc0;  // the input is the motif table of step 0
+            a.in = i == 0 ? nullptr : (from_table ? zc_base : ws.buf[ib]);
+            a.in_stride = i == 0 ? 0 : (from_table ? zc_stride : cap[ib]);
+            a.in_cap = i == 0 ? 0 : (from_table ? zc_rows : cap[ib]);
             a.n_in = &ws.ctrl_d->counts[i];
             a.id_begin = v0;
             a.id_count = v1 - v0;
@@ -445,7 +479,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             }
             for (int c = 0; c < k; c++) a.pv[c] = (uint8_t)std::max(plan.pv_of[c], 0);
             const double est_in = i == 0 ? (double)(v1 - v0) : est[i - 1];
-            const int64_t in_cap = i == 0 ? (int64_t)(v1 - v0) : cap[ib];
+            const int64_t in_cap = i == 0 ? (int64_t)(v1 - v0) : a.in_cap;
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * i], s));
             const int blk = ejf_block_for(a.st.c_in, block);
             DM_HIP(launch_ejf(a, blk, ejf_grid(in_cap, est_in, blk), s));
@@ -511,7 +545,13 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             retries++;
             continue;
         }
-        const int64_t n_final = std::min<int64_t>(c.counts[nsteps], cap[lb]);
+        // the final table: the last step's output, or the motif table itself
+        // when the plan's only step was taken in place
+        const bool fin_table = zc0 && nsteps == 1;
+        int32_t* fin = fin_table ? const_cast<int32_t*>(zc_base) : ws.buf[lb];
+        const int64_t fin_stride = fin_table ? zc_stride : cap[lb];
+        const int64_t fin_cap = fin_table ? zc_rows : cap[lb];
+        const int64_t n_final = std::min<int64_t>(c.counts[nsteps], fin_cap);
         bool sort_merged = false;  // the merge tier ran (its launches are timed apart from the LDS tiers)
         if (!hash_mode && opt.sort) {
             // canonicalize into a row-major table of exactly the kept rows
@@ -534,9 +574,9 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             DM_TRY(ws.ensure_sort_scratch(2 * n_final + 2));
             SortJob& job = *ws.job_h;
             std::memset(&job, 0, sizeof job);
-            job.in = ws.buf[lb];
-            job.in_stride = cap[lb];
-            job.in_cap = cap[lb];
+            job.in = fin;
+            job.in_stride = fin_stride;
+            job.in_cap = fin_cap;
             job.n_in = &ws.ctrl_d->counts[nsteps];
             job.out = opt.out_buf ? opt.out_buf : result;
             job.out_rows = out_rows;
@@ -575,7 +615,9 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             int64_t r = (hash_mode && i == nsteps - 1) ? (int64_t)c.hash[0] : c.counts[i + 1];
             if (i < DM_MAX_PATTERN_VERTICES) o.stats.step_rows[i] = r;
             const int cols = steps[i].c_in + steps[i].n_new;
-            bytes += 4 * (prev_cols * prev_rows) + ((hash_mode && i == nsteps - 1) ? 0 : 4 * (int64_t)cols * r);
+            // a step taken in place from the motif table moves nothing
+            if (!(i == 0 && zc0))
+                bytes += 4 * (prev_cols * prev_rows) + ((hash_mode && i == nsteps - 1) ? 0 : 4 * (int64_t)cols * r);
             prev_rows = r;
             prev_cols = cols;
         }
@@ -594,7 +636,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
                 jm += t;
             }
             o.stats.join_ms = jm;
-            o.stats.join_launches = nsteps;
+            o.stats.join_launches = nsteps - (zc0 ? 1 : 0);
             if (!hash_mode && opt.sort) {
                 // the LDS tiers, plus the merge tier when it ran (not the host
                 // round trip that decided it)
@@ -649,8 +691,8 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             o.costs = result_cost;
             result_cost = nullptr;
         } else {
-            o.table = ws.buf[lb];
-            o.stride = cap[lb];
+            o.table = fin;
+            o.stride = fin_stride;
         }
         (void)redo;
         *out = o;
@@ -828,6 +870,7 @@ dm::TableDev dm_datagraph::table_dev(int motif, int key_pos) const {
     t.rows = m.rows;
     t.size = m.size;
     t.sorted_by = 0;
+    t.sorted_max = 0;
     return t;
 }
 
@@ -837,6 +880,7 @@ dm::TableDev dm_datagraph::table_dev_step(const dm::StepDesc& st) const {
     if (st.n_eq > 0 && m.sec_base && m.sorted_by == st.eq_pos[0] + 1) {
         t.base = m.sec_base;
         t.sorted_by = m.sorted_by;
+        t.sorted_max = m.sorted_max;
     }
     return t;
 }
@@ -1065,6 +1109,38 @@ static dm_status build_claw_direct(dm_datagraph* dg) {
 
 // Build Res(M) for motif m (every key position) by running Algorithm 1 on
 // the motif itself with the motifs already in the database (Algorithm 2).
+// A path table keyed at one end: a second copy, same offsets, with every key
+// group ordered by the other end, so that a join knowing both ends (a
+// cycle's closing step) binary-searches the group for its run.  The table
+// itself keeps the joins' order (paths extended from it come out in label
+// order, which the sort skips).  A key group holds at most d (d-1)^(L-2)
+// rows (d = the largest degree): groups up to the LDS tile are sorted one
+// workgroup each, else (paths up to 6 vertices) only the groups of at most
+// 64 rows, one thread each.
+static dm_status build_second_copy(dm_datagraph* dg, MotifTable& t) {
+    dm_context* ctx = dg->ctx;
+    hipStream_t s = ctx->stream;
+    const int L = t.size;
+    const double d = std::max(dg->max_degree, 1);
+    const double bound = d * std::pow(std::max(d - 1.0, 1.0), L - 2);
+    const bool lds = bound <= (double)kGroupSortLds;
+    if (!lds && L > 6) return DM_OK;
+    int32_t* sec = nullptr;
+    const size_t bytes = sizeof(int32_t) * (size_t)t.stride * (size_t)L;
+    DM_TRY(dev_alloc(ctx, (void**)&sec, bytes, s));
+    t.owned[2] = sec;
+    if (lds) {
+        DM_HIP(launch_group_sort_lds(t.offs, dg->n, t.stride, L, L - 1, t.cols[0], sec, s));
+    } else {
+        DM_HIP(hipMemcpyAsync(sec, t.cols[0], bytes, hipMemcpyDeviceToDevice, s));
+        DM_HIP(launch_group_sort(t.offs, dg->n, t.stride, L, L - 1, sec, s));
+    }
+    t.sec_base = sec;
+    t.sorted_by = L;
+    t.sorted_max = lds ? kGroupSortLds : kGroupSortMax;
+    return DM_OK;
+}
+
 static dm_status build_motif(dm_datagraph* dg, int m) {
     if (m == MOT_K13) {
         const dm_status st = build_claw_direct(dg);
@@ -1103,20 +1179,7 @@ static dm_status build_motif(dm_datagraph* dg, int m) {
         for (int q = 0; q < mi.size; q++) t.cols[q] = data + (size_t)q * (size_t)t.stride;
         DM_HIP(launch_offsets(t.cols[j], n_dev, ro.rows, dg->n, offs, s));
         t.offs = offs;
-        if (!mi.general && !mi.cycle && j == 0 && mi.size >= 3 && mi.size <= 6 && ro.rows > 0) {
-            // a path keyed at one end: a second copy with each key group ordered by
-            // the other end, so a join that knows both ends (a cycle's closing step)
-            // can binary-search it; the table itself keeps the joins' order (paths
-            // extended from it come out in label order, which the sort skips)
-            int32_t* sec = nullptr;
-            const size_t bytes = sizeof(int32_t) * (size_t)t.stride * (size_t)mi.size;
-            DM_TRY(dev_alloc(ctx, (void**)&sec, bytes, s));
-            t.owned[2] = sec;
-            DM_HIP(hipMemcpyAsync(sec, data, bytes, hipMemcpyDeviceToDevice, s));
-            DM_HIP(launch_group_sort(offs, dg->n, t.stride, mi.size, mi.size - 1, sec, s));
-            t.sec_base = sec;
-            t.sorted_by = mi.size;
-        }
+        if (!mi.general && !mi.cycle && j == 0 && mi.size >= 3 && ro.rows > 0) DM_TRY(build_second_copy(dg, t));
     }
     dg->motif_bits |= 1u << m;
     dg->mask_built |= mi.bit;
@@ -1369,7 +1432,10 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
                 if (st == DM_OK && !c4) free_motif(dg, MOT_C4);
             }
             if (c4) {
-                want = DM_MOTIF_M3 | DM_MOTIF_M4 | DM_MOTIF_C4;
+                // with degrees up to 4 also M7, the 7-path keyed at its ends
+                // (12-cycles close as one two-key join of two 7-paths); its
+                // table is checked against its size after M4 is built
+                want = DM_MOTIF_M3 | DM_MOTIF_M4 | DM_MOTIF_C4 | (dg->max_degree <= 4 ? DM_MOTIF_M7 : 0u);
             } else {
                 // the claw table has sum_v d(d-1)(d-2) rows: only for low degrees
                 double claws = 0;
@@ -1380,10 +1446,15 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
                 want = claws <= 5e7 ? DM_MOTIF_M4_1 : (DM_MOTIF_M3 | DM_MOTIF_M4);
             }
         }
-        const int order[] = {MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23, MOT_H18};
+        const int order[] = {MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_P7, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23, MOT_H18};
         for (int m : order) {
             if (st != DM_OK) break;
             if (!(want & motif_info(m).bit) || ((dg->motif_bits >> m) & 1)) continue;
+            if (aut && m == MOT_P7) {
+                // M7 only while its table (about M4 x (d-1)^3 rows, x 2 copies) stays moderate
+                const double d1 = std::max(dg->max_degree - 1, 1);
+                if (dg->stats.rows[MOT_P4] * d1 * d1 * d1 > 5e7) continue;
+            }
             st = build_motif(dg, m);
         }
         if (st == DM_OK && aut && !(want & (DM_MOTIF_C4 | DM_MOTIF_M4_1))) {
@@ -1590,6 +1661,9 @@ dm_status dm_datagraph_load(dm_context* ctx, const char* path, dm_datagraph** ou
             if (st == DM_OK && hipMemcpy(offs, ob.data(), sizeof(int32_t) * ob.size(), hipMemcpyHostToDevice))
                 st = fail(DM_ERR_DEVICE, "motif index upload failed");
             t.offs = offs;
+            const MotifInfo& mi = motif_info(m);
+            if (st == DM_OK && !mi.general && !mi.cycle && j == 0 && size >= 3 && rows > 0)
+                st = build_second_copy(dg, t);
         }
     }
     if (st == DM_OK && r.at != r.n) st = corrupt("trailing bytes");
@@ -1723,6 +1797,17 @@ dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_o
     std::string err;
     dm_status st = plan_pattern(p, 0, avail, &dg->stats, plan, &err);
     if (st != DM_OK) return fail(st, err);
+    // The decomposition takes the largest motif that fits first (Sec. III-C);
+    // a motif keyed at its ends only (M7) can fit a pattern where it costs
+    // more than smaller ones would (a 7-path through a 3x3 grid, filtered by
+    // chords): plan once without it and keep the plan with less estimated
+    // table work.
+    for (int m = 0; m < kNumMotifs; m++) {
+        if (!((avail >> m) & 1) || !motif_info(m).ends_only) continue;
+        Plan alt;
+        if (plan_pattern(p, 0, avail & ~(1u << m), &dg->stats, &alt, &err) == DM_OK && alt.est_cost < plan->est_cost)
+            *plan = std::move(alt);
+    }
     return DM_OK;
 }
 

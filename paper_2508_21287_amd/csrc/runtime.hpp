@@ -111,6 +111,7 @@ struct MotifTable {
     // by position sorted_by - 1, for steps whose first further key sits there
     int32_t* sec_base = nullptr;
     int32_t sorted_by = 0;
+    int32_t sorted_max = 0;  // largest key group the second copy orders
     int32_t* owned[3] = {nullptr, nullptr, nullptr};  // allocations to free (data, offs, second copy)
 };
 

@@ -15,7 +15,7 @@ from paper_2508_21287_amd import workloads as W
 
 MOTIF_SHAPES = {0: ("path", 2), 1: ("path", 3), 2: ("path", 4), 3: ("path", 5), 4: ("path", 6),
                 5: ("cycle", 4), 6: ("cycle", 6), 7: ("cycle", 12), 8: ("claw", 4), 9: ("grid2x3", 6),
-                10: ("cell18", 18)}
+                10: ("cell18", 18), 11: ("path", 7)}
 
 # heavy-hex cell with pendants: cycle 0-1-3-4-...-12-0, pendants 2,13..17 on 0,3,5,7,9,11
 CELL18_EDGES = [[0, 1], [1, 3], [3, 4], [4, 5], [5, 6], [6, 7], [7, 8], [8, 9], [9, 10], [10, 11], [11, 12],

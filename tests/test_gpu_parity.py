@@ -80,8 +80,8 @@ def test_ingest_errors(ctx):
 MOTIF_PATTERNS = {0: W.path(2), 1: W.path(3), 2: W.path(4), 3: W.path(5), 4: W.path(6), 5: W.cycle(4),
                   6: W.cycle(6), 7: W.cycle(12), 8: W.star(3),
                   9: W.Pattern(6, [[0, 1], [1, 2], [3, 4], [4, 5], [0, 3], [1, 4], [2, 5]], "2x3"),
-                  10: W.Pattern(18, plan_exec.CELL18_EDGES, "M18-O-6")}
-MOTIF_KEY_POSITIONS = {0: 1, 1: 2, 2: 2, 3: 3, 4: 3, 5: 1, 6: 1, 7: 1, 8: 2, 9: 2, 10: 3}
+                  10: W.Pattern(18, plan_exec.CELL18_EDGES, "M18-O-6"), 11: W.path(7)}
+MOTIF_KEY_POSITIONS = {0: 1, 1: 2, 2: 2, 3: 3, 4: 3, 5: 1, 6: 1, 7: 1, 8: 2, 9: 2, 10: 3, 11: 1}
 
 
 @pytest.mark.parametrize("gname", ["HH(3,9)", "HH(7,19)", "GRID(6,7)"])
@@ -169,6 +169,13 @@ def test_overflow_retry(ctx):
     g = W.grid(12, 12)
     dg = ctx.datagraph(g.n, g.edges)
     p = W.path(7)
+    want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+    # (M3 and M4 only: with M7 the whole pattern is one motif table taken in place)
+    with dg.enumerate(p.n, p.edges, initial_rows=1000, motif_mask=dm.MOTIF_M3 | dm.MOTIF_M4) as r:
+        assert np.array_equal(r.to_numpy(), want)
+        assert r.stats()["retries"] >= 1
+    # P9 = M7 in place, then a join whose 1000-row first table overflows
+    p = W.path(9)
     want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
     with dg.enumerate(p.n, p.edges, initial_rows=1000) as r:
         assert np.array_equal(r.to_numpy(), want)

@@ -153,9 +153,12 @@ def test_grid_100_c12_table(ctx):
     p = W.cycle(12)
     w = gold_cases()["GRID100/C12"]
     dg = ctx.datagraph(g.n, g.edges)
-    with dg.enumerate(p.n, p.edges) as r:
+    with dg.enumerate(p.n, p.edges, profile=True) as r:
         assert r.total == r.rows == w["count"]
+        st = r.stats()
         t = r.to_numpy()
+    # the 7-path table taken in place, closed by one two-key join with itself
+    assert st["n_steps"] == 2 and st["join_launches"] == 1, st
     pins.assert_strictly_sorted(t)
     hsum = hxor = 0
     for j in range(0, len(t), 1 << 22):
