@@ -83,9 +83,13 @@ typedef enum {
  * is built with a mask of these; a plan may use any subset of what was built.
  * DM_MOTIF_AUTO is topology-aware (Sec. VI-B): on a graph with 4-cycles
  * (grid-like) it builds M3, M4 and M4-O; without them and with low degrees
- * (heavy-hex-like: at most 5e7 claws) the claw M4-1, the set that measured
- * fastest on heavy-hex lattices (as in the paper's {M2, M4-1}); otherwise M3,
- * M4 and, when its table stays moderate, the 12-cycle M12-O. */
+ * (heavy-hex-like: at most 5e7 claws) the claw M4-1 (as in the paper's
+ * {M2, M4-1}); on either, at degrees up to 4, also M7 while its table stays
+ * moderate (it covers the pattern's chains: vertices of pattern degree 2);
+ * otherwise M3, M4 and, when its table stays moderate, the 12-cycle M12-O.
+ * Each pattern's plan is the one with the least estimated table work among
+ * the greedy decompositions with every motif built, without M7, and without
+ * the paths (M3..M7). */
 #define DM_MOTIF_M3 (1u << 0)
 #define DM_MOTIF_M4 (1u << 1)
 #define DM_MOTIF_M5 (1u << 2)
@@ -417,10 +421,15 @@ dm_status dm_result_summaries(dm_result* const* rs, int32_t n, dm_result_summary
 void dm_result_free_many(dm_result* const* rs, int32_t n);
 
 /* Served form: a request loop that keeps the data graph resident, groups
- * queued queries into batches by predicted intermediate-table memory (a
- * query predicted to need more than an eighth of the budget runs alone), and
+ * queued queries into batches by predicted intermediate-table memory, and
  * runs the batches continuously on several streams so that their work
- * overlaps on the device. */
+ * overlaps on the device.  A query predicted to build more than 128 MiB of
+ * tables is large: it runs in a batch of its own, through the per-step
+ * launches; with two or more streams the first one takes only small queries
+ * (from anywhere in the queue), so they never wait behind large ones.  A
+ * query whose predicted kept rows exceed 8 x mem_budget is refused at
+ * admission (DM_ERR_BUDGET_EXCEEDED from dm_server_wait); one that passes
+ * the budget while it runs fails the same way. */
 typedef struct {
     int32_t n_streams;       /* concurrent batches in flight (default 2) */
     int32_t max_batch;       /* patterns per batch launch (default 64) */

@@ -34,6 +34,10 @@ using namespace dm;
 namespace {
 
 constexpr int kBatchMaxCols = 127;   // widest input table the persistent kernel stages in LDS
+// Patterns whose predicted peak tables (rows x columns, input + output of a
+// step) pass this run through the per-step launches instead of the
+// persistent kernel.
+constexpr double kBatchLargeValues = 16.0 * 1024 * 1024;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -671,9 +675,14 @@ dm_status enumerate_many(dm_datagraph* dg, Workspace& ws, int32_t n, const dm_gr
         }
         int cm = 0;
         for (auto& d : it.steps) cm = std::max(cm, (int)d.c_in);
-        // a caller's root range and scored runs go through the single-pattern path
+        // a caller's root range and scored runs go through the single-pattern
+        // path, and so do patterns predicted to build large tables: the
+        // persistent kernel is made for many short chains of small tables
+        // (one workgroup per CU), the per-step launches for throughput
         const bool own_path = (opts && opts->root_end > opts->root_begin) || (opts && opts->score && mode == DM_OUT_TABLE);
-        if (cm > kBatchMaxCols || (int)it.steps.size() > kMaxSteps || own_path) {
+        const double share = (double)(it.r1 - it.r0) / std::max(dg->n, 1);
+        const bool large = it.plan.est_peak_rows_cols * share > kBatchLargeValues;
+        if (cm > kBatchMaxCols || (int)it.steps.size() > kMaxSteps || own_path || large) {
             solo.push_back(i);
             continue;
         }
@@ -758,12 +767,17 @@ extern "C" dm_status dm_autotune_motifs(dm_context* ctx, const dm_graph_desc* gd
 
 namespace {
 
+// Queries whose predicted tables exceed this are large: they leave the
+// small lane to small queries.
+constexpr int64_t kServeSmallBytes = (int64_t)128 << 20;
+
 struct Request {
     uint64_t ticket = 0;
     int32_t nv = 0;
     std::vector<int32_t> edges;
     int64_t cap = -1;
     int64_t est_bytes = 0;
+    bool large = false;  // predicted tables above the small lane's limit
     bool done = false;
     dm_status status = DM_OK;
     std::string err;
@@ -798,22 +812,48 @@ struct dm_server {
 static void server_worker(dm_server* s, int w) {
     (void)hipSetDevice(s->dg->ctx->device);
     Workspace& ws = *s->ws[w];
+    // with several streams, worker 0 is the small lane: it takes only small
+    // queries (from anywhere in the queue, in arrival order), so they never
+    // wait behind large ones that the other workers run
+    const bool small_lane = s->opts.n_streams > 1 && w == 0;
+    auto has_small = [&] {
+        for (auto& r : s->queue)
+            if (!r->large) return true;
+        return false;
+    };
     for (;;) {
         std::vector<std::shared_ptr<Request>> batch;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
-            if (s->queue.empty() && s->stopping) return;
-            int64_t batch_bytes = 0;
-            while (!s->queue.empty() && (int32_t)batch.size() < s->opts.max_batch) {
-                auto& r = s->queue.front();
-                const bool large = r->est_bytes > s->opts.mem_budget / 8;
-                if (!batch.empty() && (large || batch_bytes + r->est_bytes > s->opts.mem_budget)) break;
-                batch_bytes += r->est_bytes;
-                s->inflight++;
-                batch.push_back(r);
-                s->queue.pop_front();
-                if (large) break;
+            if (small_lane) {
+                s->cv_work.wait(lk, [&] { return s->stopping || has_small(); });
+                if (s->stopping && !has_small()) return;
+                int64_t batch_bytes = 0;
+                for (auto it = s->queue.begin(); it != s->queue.end() && (int32_t)batch.size() < s->opts.max_batch;) {
+                    auto& r = *it;
+                    if (r->large) {
+                        ++it;
+                        continue;
+                    }
+                    if (!batch.empty() && batch_bytes + r->est_bytes > s->opts.mem_budget) break;
+                    batch_bytes += r->est_bytes;
+                    s->inflight++;
+                    batch.push_back(r);
+                    it = s->queue.erase(it);
+                }
+            } else {
+                s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
+                if (s->queue.empty() && s->stopping) return;
+                int64_t batch_bytes = 0;
+                while (!s->queue.empty() && (int32_t)batch.size() < s->opts.max_batch) {
+                    auto& r = s->queue.front();
+                    if (!batch.empty() && (r->large || batch_bytes + r->est_bytes > s->opts.mem_budget)) break;
+                    batch_bytes += r->est_bytes;
+                    s->inflight++;
+                    batch.push_back(r);
+                    s->queue.pop_front();
+                    if (batch.back()->large) break;
+                }
             }
         }
         std::vector<dm_graph_desc> gps;
@@ -937,15 +977,29 @@ dm_status dm_server_submit(dm_server* s, const dm_graph_desc* gp, int64_t max_em
             est *= std::min(1.0, std::max(roots, 64.0) / nv);
         }
         r->est_bytes = (int64_t)std::max(1.0, std::min(est, (double)s->opts.mem_budget));
+        r->large = est > (double)kServeSmallBytes;
+        // refused at admission: a result predicted far beyond the budget it
+        // would run within (the prediction can be off by a few times, so
+        // only beyond 8x; the rest run and are refused if they pass it)
+        const double kept = max_embeddings >= 0 ? std::min((double)max_embeddings, (double)rows) : (double)rows;
+        if (kept * 4.0 * p.k > 8.0 * (double)s->opts.mem_budget) {
+            r->status = DM_ERR_BUDGET_EXCEEDED;
+            r->err = "predicted result of " + std::to_string((int64_t)kept) + " rows exceeds the server's budget";
+            r->done = true;
+        }
     }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) return fail(DM_ERR_CANCELLED, "server is stopping");
     if ((int32_t)s->queue.size() >= s->opts.max_queue) return fail(DM_ERR_BUSY, "server queue is full");
     r->ticket = s->next_ticket++;
     s->live[r->ticket] = r;
-    s->queue.push_back(r);
     *ticket = r->ticket;
-    s->cv_work.notify_one();
+    if (r->done) {
+        s->cv_done.notify_all();
+        return DM_OK;
+    }
+    s->queue.push_back(r);
+    s->cv_work.notify_all();  // the small lane waits only for small queries
     return DM_OK;
 }
 

@@ -84,6 +84,7 @@ struct EjfArgs {
     int64_t in_stride;
     int64_t in_cap;
     const int64_t* n_in;
+    const int64_t* in_row0;  // device: rows of `in` start here (nullptr = 0): a motif table read in place
     int32_t id_begin;
     int32_t id_count;
     int32_t* out;
@@ -126,6 +127,7 @@ struct SortJob {
     int64_t in_stride;
     int64_t in_cap;
     const int64_t* n_in;
+    const int64_t* in_row0;  // device: rows of `in` start here (nullptr = 0): a motif table read in place
     int32_t* out;
     int64_t out_rows;
     uint32_t* scratch_idx;  // merge tier: 2 * in_cap index scratch
@@ -270,6 +272,8 @@ int batch_grid_for(int block, int max_cols, int requested);
 hipError_t launch_batch(const BatchDev& b, int block, int max_cols, bool wide, int grid, hipStream_t s);
 int sort_max_lds_bytes();
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+// *row0 = offs[v0], *n = offs[v1] - offs[v0]: the rows of keys [v0, v1) of a motif table
+hipError_t launch_slice_rows(const int32_t* offs, int32_t v0, int32_t v1, int64_t* n, int64_t* row0, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_iota_i32(int32_t* p, int32_t start, int64_t n, hipStream_t s);
 hipError_t launch_offsets(const int32_t* key, const int64_t* n_rows, int64_t rows_cap, int32_t n_vertices,

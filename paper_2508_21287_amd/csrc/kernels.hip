@@ -328,7 +328,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
     const bool hash = a.mode == EJF_HASH;
     if (valid) {
         if (a.in) {
-            const int32_t* src = a.in + row;
+            const int32_t* src = a.in + (a.in_row0 ? *a.in_row0 : 0) + row;
             const int64_t is = a.in_stride;
             for (int c0 = 0; c0 < c_in; c0 += RCH) {
                 int32_t tv[RCH];
@@ -1621,6 +1621,18 @@ hipError_t launch_sort_merge_tier(const SortLaunch& a, int passes, hipStream_t s
 // ---------------------------------------------------------------------------
 // fills, offsets, column gathers
 // ---------------------------------------------------------------------------
+
+__global__ void slice_rows_kernel(const int32_t* offs, int32_t v0, int32_t v1, int64_t* n, int64_t* row0) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *row0 = offs[v0];
+        *n = (int64_t)offs[v1] - offs[v0];
+    }
+}
+
+hipError_t launch_slice_rows(const int32_t* offs, int32_t v0, int32_t v1, int64_t* n, int64_t* row0, hipStream_t s) {
+    hipLaunchKernelGGL(slice_rows_kernel, dim3(1), dim3(64), 0, s, offs, v0, v1, n, row0);
+    return hipGetLastError();
+}
 
 __global__ void fill_u64_kernel(uint64_t* p, uint64_t v, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

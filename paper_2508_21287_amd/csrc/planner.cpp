@@ -200,6 +200,7 @@ struct Planner {
     int32_t L = 0;
     bool cyc = false;
     bool ends_only = false;
+    bool ends_expand = false;  // end-keyed motifs may extend a chain from one placed end
     int32_t seq[kMaxMotif];
     char inseq[kMaxCols];
     int64_t expansions = 0, found = 0;
@@ -243,8 +244,18 @@ struct Planner {
         int keys = 0, nnew = 0;
         for (int i = 0; i < L; i++) (mapped(seq[i]) ? keys : nnew)++;
         if (keys == 0 || nnew == 0) return;
-        // a motif keyed at its ends only: the slice must share an end
-        if (ends_only && !mapped(seq[0]) && !mapped(seq[L - 1])) return;
+        // A motif keyed at its ends only covers a chain of the pattern (its
+        // inner vertices have no other pattern edges), as the first slice
+        // (its table read in place), to close a chain between two placed
+        // vertices (a two-key join, binary-searched), or, where its table has
+        // few rows per key, to extend a chain from one placed end; with many
+        // rows per key that would be a candidate loop as long as the fan-out.
+        if (ends_only) {
+            for (int i = 1; i + 1 < L; i++)
+                if ((int)nbrs[seq[i]].size() != 2) return;
+            const bool first = ncols == 1, both = mapped(seq[0]) && mapped(seq[L - 1]);
+            if (!(first || both || ends_expand)) return;
+        }
         int score = 2 * keys + count_checks(seq);
         if (score > best_score) {
             best_score = score;
@@ -474,6 +485,11 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
 
     const double nv = stats ? (double)stats->n_vertices : 0.0;
     const double deg = stats ? std::max(stats->avg_degree, 1.0) : 1.0;
+    // extending from one end reads every row of the end's key group: only
+    // where those groups are small
+    for (int m = 0; m < kNumMotifs; m++)
+        if (motif_info(m).ends_only && (avail >> m) & 1 && nv > 0 && stats->rows[m] / nv <= 64.0)
+            pl.ends_expand = true;
     const double br = std::max(deg - 1.0, 1.0);
     double rows = nv;  // identity table: one row per data vertex
     double peak = rows * 1;

@@ -389,18 +389,22 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         }
     } result_guard{ctx, &result, &result_cost, s};
 
-    // Step 0 straight from the motif table, with no launch: over every root,
-    // the identity table joined with a motif keyed at position 0 whose new
-    // columns are positions 1..L-1 in order, with nothing to check, is the
-    // motif table itself (its rows are injective and grouped by the key in
-    // ascending order), so the next step reads the table in place.
+    // Step 0 straight from the motif table, with no join launch: the identity
+    // table joined with a motif keyed at position 0 whose new columns are
+    // positions 1..L-1 in order, with nothing to check, is the motif table's
+    // slice of the root range (its rows are injective and grouped by the key
+    // in ascending order), so the next step reads the table in place.  Over
+    // every root the slice is the whole table; over a range its first row
+    // and length come from the table's index on the device.
     bool zc0 = false;
     const int32_t* zc_base = nullptr;
+    const int32_t* zc_offs = nullptr;
     int64_t zc_stride = 0, zc_rows = 0;
+    const bool full_range = v0 == 0 && v1 == dg->n;
     {
         const StepDesc& d0 = steps[0];
-        if (d0.motif >= 0 && !score && !opt.induced && v0 == 0 && v1 == dg->n && d0.key_pos == 0 && d0.n_eq == 0 &&
-            d0.n_edge == 0 && !(nsteps == 1 && hash_mode)) {
+        if (d0.motif >= 0 && !score && !opt.induced && (full_range || nsteps > 1) && d0.key_pos == 0 &&
+            d0.n_eq == 0 && d0.n_edge == 0 && !(nsteps == 1 && hash_mode)) {
             const MotifTable& t = dg->tab[d0.motif][0];
             bool ident = d0.n_new == t.size - 1 && t.rows > 0 && t.cols[0] != nullptr;
             for (int q = 0; q < d0.n_new && ident; q++) ident = d0.new_pos[q] == q + 1;
@@ -408,6 +412,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             if (ident) {
                 zc0 = true;
                 zc_base = t.cols[0];
+                zc_offs = t.offs;
                 zc_stride = t.stride;
                 zc_rows = t.rows;
             }
@@ -437,7 +442,8 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         for (int i = 0; i < nsteps; i++) {
             const int ib = (i - 1) & 1, ob = i & 1;
             if (i == 0 && zc0) {
-                DM_HIP(launch_fill_u64((uint64_t*)&ws.ctrl_d->counts[1], (uint64_t)zc_rows, 1, s));
+                if (full_range) DM_HIP(launch_fill_u64((uint64_t*)&ws.ctrl_d->counts[1], (uint64_t)zc_rows, 1, s));
+                else DM_HIP(launch_slice_rows(zc_offs, v0, v1, &ws.ctrl_d->counts[1], &ws.ctrl_d->slice_row0, s));
                 if (opt.profile) {
                     DM_HIP(hipEventRecord(ws.prof[0], s));
                     DM_HIP(hipEventRecord(ws.prof[1], s));
@@ -453,6 +459,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             a.in = i == 0 ? nullptr : (from_table ? zc_base : ws.buf[ib]);
             a.in_stride = i == 0 ? 0 : (from_table ? zc_stride : cap[ib]);
             a.in_cap = i == 0 ? 0 : (from_table ? zc_rows : cap[ib]);
+            a.in_row0 = (from_table && !full_range) ? &ws.ctrl_d->slice_row0 : nullptr;
             a.n_in = &ws.ctrl_d->counts[i];
             a.id_begin = v0;
             a.id_count = v1 - v0;
@@ -1443,7 +1450,10 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
                     const double d = csr.first[v + 1] - csr.first[v];
                     claws += d * (d - 1) * (d - 2);
                 }
-                want = claws <= 5e7 ? DM_MOTIF_M4_1 : (DM_MOTIF_M3 | DM_MOTIF_M4);
+                // with the claw, M7 for the pattern's chains (paths and
+                // cycles take a few long slices instead of one join per edge)
+                want = claws <= 5e7 ? (DM_MOTIF_M4_1 | (dg->max_degree <= 4 ? DM_MOTIF_M7 : 0u))
+                                    : (DM_MOTIF_M3 | DM_MOTIF_M4);
             }
         }
         const int order[] = {MOT_P3, MOT_P4, MOT_P5, MOT_P6, MOT_P7, MOT_C4, MOT_C6, MOT_C12, MOT_K13, MOT_G23, MOT_H18};
@@ -1794,20 +1804,49 @@ dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_o
         uint32_t want = motif_bits_from_mask(opts->motif_mask);
         avail &= want;
     }
+    // the plan depends on the pattern's edges, the motifs and the tables'
+    // statistics only
+    std::string key;
+    key.reserve(64 + 8 * p.edges.size());
+    auto put = [&](const void* x, size_t n) { key.append((const char*)x, n); };
+    put(&p.k, sizeof p.k);
+    put(&avail, sizeof avail);
+    put(&dg->stats.n_vertices, sizeof dg->stats.n_vertices);
+    put(dg->stats.rows, sizeof dg->stats.rows);
+    put(&dg->stats.avg_degree, sizeof dg->stats.avg_degree);
+    for (auto& e : p.edges) put(&e, sizeof e);
+    dm_context* ctx = dg->ctx;
+    {
+        std::lock_guard<std::mutex> lk(ctx->plan_mu);
+        auto it = ctx->plan_cache.find(key);
+        if (it != ctx->plan_cache.end()) {
+            *plan = it->second;
+            return DM_OK;
+        }
+    }
     std::string err;
     dm_status st = plan_pattern(p, 0, avail, &dg->stats, plan, &err);
     if (st != DM_OK) return fail(st, err);
-    // The decomposition takes the largest motif that fits first (Sec. III-C);
-    // a motif keyed at its ends only (M7) can fit a pattern where it costs
-    // more than smaller ones would (a 7-path through a 3x3 grid, filtered by
-    // chords): plan once without it and keep the plan with less estimated
-    // table work.
+    // The decomposition takes the largest motif that fits first (Sec. III-C),
+    // which is not always the cheapest (a 7-path through a 3x3 grid filtered
+    // by chords; paths where a claw fits a tree-like pattern better): plan
+    // again without the end-keyed motifs and without the longer paths, and
+    // keep the plan with the least estimated table work.
+    uint32_t ends = 0, paths = 0;
     for (int m = 0; m < kNumMotifs; m++) {
-        if (!((avail >> m) & 1) || !motif_info(m).ends_only) continue;
+        const MotifInfo& mi = motif_info(m);
+        if (mi.ends_only) ends |= 1u << m;
+        if (!mi.general && !mi.cycle && mi.size >= 3) paths |= 1u << m;
+    }
+    for (uint32_t drop : {ends, paths}) {
+        if (!(avail & drop) || (avail & ~drop) == avail) continue;
         Plan alt;
-        if (plan_pattern(p, 0, avail & ~(1u << m), &dg->stats, &alt, &err) == DM_OK && alt.est_cost < plan->est_cost)
+        if (plan_pattern(p, 0, avail & ~drop, &dg->stats, &alt, &err) == DM_OK && alt.est_cost < plan->est_cost)
             *plan = std::move(alt);
     }
+    std::lock_guard<std::mutex> lk(ctx->plan_mu);
+    if (ctx->plan_cache.size() >= 8192) ctx->plan_cache.clear();
+    ctx->plan_cache.emplace(std::move(key), *plan);
     return DM_OK;
 }
 

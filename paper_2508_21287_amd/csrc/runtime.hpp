@@ -5,6 +5,8 @@
 
 #include <atomic>
 #include <memory>
+#include <mutex>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -46,6 +48,7 @@ struct Control {
     uint32_t abort;            // WaitCtl::abort of the run
     uint32_t pad_;
     WaitDiag diag;             // WaitCtl::diag of the run
+    int64_t slice_row0;        // first row of a motif table read in place over a root range
 };
 
 // Scratch reused across runs of one stream: ping-pong SoA tables, look-back
@@ -129,6 +132,10 @@ struct dm_context {
     int64_t wall_khz = 100000;   // device wall-clock rate (bounded waits)
     dm::Workspace ws;
     int32_t sort_lds_max = 0;
+    // plans by (pattern, motif set, table statistics): a repeated pattern
+    // shape on a data graph with the same tables skips the decomposition
+    std::mutex plan_mu;
+    std::unordered_map<std::string, dm::Plan> plan_cache;
 };
 
 struct dm_datagraph {

@@ -62,15 +62,17 @@ def test_cancel_word(ctx):
 
 
 def test_wait_limit_gives_up(ctx):
-    # A 1 us bound: the persistent kernel's idle workgroups see no tile finish
-    # within it (the first tiles take tens of microseconds), give up, record
-    # the wait and leave; the call fails with DM_ERR_DEVICE naming it.
+    # A 1 us bound on a batch of one 16-vertex path: each of its 15 steps has
+    # a single tile, so while one workgroup runs it every other one polls
+    # for work with no tile finishing for microseconds; they give up, record
+    # the wait and leave, and the call fails with DM_ERR_DEVICE naming it.
     g, pats = W.config2(64)
     dg = ctx.datagraph(g.n, g.edges)
     specs = [(p.n, p.edges) for p in pats]
+    p16 = W.path(16)
     say("wait limit: batched call with a 1 us bound")
     with pytest.raises(dm.DMError) as ei:
-        dg.enumerate_batch(specs, wait_limit_us=1)
+        dg.enumerate_batch([(p16.n, p16.edges)], wait_limit_us=1, motif_mask=dm.MOTIF_M2_ONLY)
     assert ei.value.code == DEVICE, ei.value
     msg = str(ei.value)
     assert "persistent scheduler" in msg or "look-back" in msg, msg

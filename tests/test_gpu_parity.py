@@ -732,10 +732,11 @@ def test_result_summaries(ctx):
 
 def test_auto_motif_choice(ctx):
     # the AUTO set is decided from the CSR read back at ingest: 4-cycles
-    # present (grid) -> M3 + M4 + M4-O; none and a small claw count
-    # (heavy-hex) -> the claw; the tables it builds still give exact results
-    for g, want_set, absent in ((W.grid(6, 7), {"M3", "M4", "M4-O"}, {"M4-1"}),
-                                (W.heavy_hex(7, 19), {"M4-1"}, {"M3", "M4", "M4-O"})):
+    # present (grid) -> M3 + M4 + M4-O (+ M7 at degree <= 4); none and a small
+    # claw count (heavy-hex) -> the claw and M7; the tables it builds still
+    # give exact results
+    for g, want_set, absent in ((W.grid(6, 7), {"M3", "M4", "M4-O", "M7"}, {"M4-1"}),
+                                (W.heavy_hex(7, 19), {"M4-1", "M7"}, {"M3", "M4", "M4-O"})):
         say(f"case auto motif set on {g.name}")
         dg = ctx.datagraph(g.n, g.edges)
         rows = dg.info()["motif_rows"]
