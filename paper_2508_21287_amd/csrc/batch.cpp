@@ -27,6 +27,7 @@
 #include <thread>
 #include <unordered_map>
 
+#include "host_pool.hpp"
 #include "runtime.hpp"
 
 using namespace dm;
@@ -48,82 +49,6 @@ int env_int(const char* name, int dflt) {
     const int x = std::atoi(v);
     return x > 0 ? x : dflt;
 }
-
-// Host workers for the per-pattern validation and planning of a batch.
-// One parallel_for at a time (a concurrent caller runs its loop itself);
-// every worker checks in for every generation, so the loop body and its
-// count stay valid until the call returns.
-class HostPool {
-  public:
-    static HostPool& get() {
-        static HostPool pool;
-        return pool;
-    }
-    void parallel_for(int n, const std::function<void(int)>& f) {
-        std::unique_lock<std::mutex> busy(call_mu_, std::try_to_lock);
-        if (!busy.owns_lock() || workers_.empty() || n < 8) {
-            for (int i = 0; i < n; i++) f(i);
-            return;
-        }
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            fn_ = &f;
-            n_ = n;
-            next_.store(0);
-            checked_in_ = 0;
-            gen_++;
-        }
-        cv_.notify_all();
-        run();
-        std::unique_lock<std::mutex> lk(mu_);
-        cv_done_.wait(lk, [&] { return checked_in_ == (int)workers_.size(); });
-        fn_ = nullptr;
-    }
-    ~HostPool() {
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            stop_ = true;
-        }
-        cv_.notify_all();
-        for (auto& t : workers_) t.join();
-    }
-
-  private:
-    HostPool() {
-        // up to 15 workers + the calling thread: one GPU's share of host CPUs
-        const unsigned hw = std::thread::hardware_concurrency();
-        const int w = (int)std::min<unsigned>(hw > 1 ? hw - 1 : 0, 15);
-        for (int i = 0; i < w; i++) workers_.emplace_back([this] { loop(); });
-    }
-    void run() {
-        for (int i; (i = next_.fetch_add(1)) < n_;) (*fn_)(i);
-    }
-    void loop() {
-        uint64_t seen = 0;
-        for (;;) {
-            {
-                std::unique_lock<std::mutex> lk(mu_);
-                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
-                if (stop_) return;
-                seen = gen_;
-            }
-            run();
-            {
-                std::lock_guard<std::mutex> lk(mu_);
-                checked_in_++;
-            }
-            cv_done_.notify_all();
-        }
-    }
-    std::vector<std::thread> workers_;
-    std::mutex call_mu_, mu_;
-    std::condition_variable cv_, cv_done_;
-    const std::function<void(int)>* fn_ = nullptr;
-    std::atomic<int> next_{0};
-    int n_ = 0, checked_in_ = 0;
-    uint64_t gen_ = 0;
-    bool stop_ = false;
-};
 
 struct DevBlock {
     const dm_context* ctx = nullptr;

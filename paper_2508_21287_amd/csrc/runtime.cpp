@@ -1816,14 +1816,7 @@ dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_o
     put(&dg->stats.avg_degree, sizeof dg->stats.avg_degree);
     for (auto& e : p.edges) put(&e, sizeof e);
     dm_context* ctx = dg->ctx;
-    {
-        std::lock_guard<std::mutex> lk(ctx->plan_mu);
-        auto it = ctx->plan_cache.find(key);
-        if (it != ctx->plan_cache.end()) {
-            *plan = it->second;
-            return DM_OK;
-        }
-    }
+    if (ctx->plans.get(key, plan)) return DM_OK;
     std::string err;
     dm_status st = plan_pattern(p, 0, avail, &dg->stats, plan, &err);
     if (st != DM_OK) return fail(st, err);
@@ -1844,9 +1837,7 @@ dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_o
         if (plan_pattern(p, 0, avail & ~drop, &dg->stats, &alt, &err) == DM_OK && alt.est_cost < plan->est_cost)
             *plan = std::move(alt);
     }
-    std::lock_guard<std::mutex> lk(ctx->plan_mu);
-    if (ctx->plan_cache.size() >= 8192) ctx->plan_cache.clear();
-    ctx->plan_cache.emplace(std::move(key), *plan);
+    ctx->plans.put(std::move(key), *plan);
     return DM_OK;
 }
 

@@ -12,6 +12,7 @@
 
 #include "dm_common.hpp"
 #include "dm_device.hpp"
+#include "host_pool.hpp"
 
 struct dm_context;
 
@@ -132,10 +133,7 @@ struct dm_context {
     int64_t wall_khz = 100000;   // device wall-clock rate (bounded waits)
     dm::Workspace ws;
     int32_t sort_lds_max = 0;
-    // plans by (pattern, motif set, table statistics): a repeated pattern
-    // shape on a data graph with the same tables skips the decomposition
-    std::mutex plan_mu;
-    std::unordered_map<std::string, dm::Plan> plan_cache;
+    dm::PlanCache plans;  // by (pattern, motif set, table statistics)
 };
 
 struct dm_datagraph {
