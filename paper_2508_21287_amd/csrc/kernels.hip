@@ -301,38 +301,6 @@ struct TileShared {
 // Row stride (in int32) of the LDS row tile for c columns: odd, >= c.
 __host__ __device__ __forceinline__ int row_stride(int c) { return c | 1; }
 
-// First index i in [lo, hi) with sc[i] >= want (hi if none), sc ascending.
-// Each round reads 16 evenly spaced entries together (independent loads) and
-// keeps the sixteenth of the interval that holds the answer, so a group of
-// n rows takes about log16(n) dependent rounds instead of log2(n).
-__device__ __forceinline__ int32_t first_at_least(const int32_t* sc, int32_t lo, int32_t hi, int32_t want) {
-    while (hi - lo > 16) {
-        const int32_t step = (hi - lo + 15) >> 4;
-        int32_t v[16];
-#pragma unroll
-        for (int i = 0; i < 16; i++) {
-            int32_t p = lo + (i + 1) * step - 1;
-            v[i] = sc[p < hi ? p : hi - 1];
-        }
-        int c = 0;
-#pragma unroll
-        for (int i = 0; i < 16; i++) c += v[i] < want;
-        // the answer lies after probe c - 1 and at or before probe c
-        const int32_t nlo = c == 0 ? lo : lo + c * step;
-        const int32_t phi = lo + (c + 1) * step - 1;
-        hi = c == 16 ? hi : (phi < hi ? phi : hi - 1);
-        lo = nlo;
-        if (lo >= hi) return c == 16 ? hi : lo;
-    }
-    int32_t v[16];
-#pragma unroll
-    for (int i = 0; i < 16; i++) v[i] = lo + i < hi ? sc[lo + i] : want;
-    int c = 0;
-#pragma unroll
-    for (int i = 0; i < 16; i++) c += (lo + i < hi) && v[i] < want;
-    return lo + c;
-}
-
 // SCORE: the layout-cost column is carried (scored runs only; the batched
 // form never scores, so its instantiation carries no cost code).
 // LAT: the latency-bound persistent form.  Its tiles hand tables to other
@@ -396,9 +364,19 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
                 // key anyway, and the test below still checks every candidate)
                 const int32_t* sc = a.tbl.base + (int64_t)st.eq_pos[0] * a.tbl.stride;
                 const int32_t want = my[st.eq_col[0]];
-                const int32_t l = first_at_least(sc, lo, hi, want);
-                hi = first_at_least(sc, l, hi, want + 1);  // vertex ids < INT32_MAX
+                int32_t l = lo, h = hi;
+                while (l < h) {
+                    const int32_t mid = (l + h) >> 1;
+                    if (sc[mid] < want) l = mid + 1; else h = mid;
+                }
+                int32_t e = l;
+                h = hi;
+                while (e < h) {
+                    const int32_t mid = (e + h) >> 1;
+                    if (sc[mid] <= want) e = mid + 1; else h = mid;
+                }
                 lo = l;
+                hi = e;
             }
         } else {
             hi = 1;  // filter-only step: the row itself is the one candidate
@@ -636,10 +614,8 @@ __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
     auto claim = [&]() -> int64_t {
         return ld_rlx_u32(a.w.abort) != 0u ? -1 : (int64_t)atomicAdd((unsigned long long*)a.ticket, 1ull);
     };
-    int64_t next = 0;
-    if (tid == 0) next = claim();
     for (;;) {
-        if (tid == 0) s_tile = next;
+        if (tid == 0) s_tile = claim();
         __syncthreads();
         const int64_t tile = s_tile;
         __syncthreads();
@@ -651,10 +627,6 @@ __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
             if (a.mode == EJF_WRITE && tile == 0 && tid == 0) *a.n_out = 0;
             break;
         }
-        // the next tile is claimed before this one is worked on, so the
-        // ticket's round trip overlaps the work (a tile claimed early is
-        // still finished by a running workgroup: look-backs on it end)
-        if (tid == 0) next = claim();
         ejf_tile<BLOCK, NV, SCORE, false>(a, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
     }
     if (a.mode == EJF_HASH) hash_flush<BLOCK>(a.hash_acc, h_cnt, h_sum, h_xor, s_red);

@@ -436,6 +436,10 @@ struct Planner {
     }
 };
 
+// Fixed cost of one launched join step in table values (about 16 us of
+// launch and dependent-round latency at a few TB/s).
+constexpr double kStepCost = 16.0 * 1024 * 1024;
+
 double estimate_fanout(const MotifStats* st, int m) {
     if (!st || st->n_vertices <= 0) return 0;
     return st->rows[m] / (double)st->n_vertices;
@@ -638,8 +642,11 @@ dm_status plan_pattern(const NormPattern& p, int32_t root, uint32_t avail, const
         double cand = rows * fan;
         if (!mi.general && !mi.cycle && d.key_pos == 0 && d.n_eq > 0 && d.eq_pos[0] == L - 1)
             cand = cand / std::max(1.0, deg * std::pow(br, std::max(0, L - 2))) + rows * std::log2(std::max(fan, 2.0));
+        // each launched step also costs a fixed latency (launch, look-back
+        // chain, readbacks), here as many table values as move in that time
         if (!in_place)
-            cost += rows * d.c_in + cand * (d.n_new + d.n_eq + (double)checks.size()) + nrows * (d.c_in + d.n_new);
+            cost += kStepCost + rows * d.c_in + cand * (d.n_new + d.n_eq + (double)checks.size()) +
+                    nrows * (d.c_in + d.n_new);
         rows = nrows;
         ps.est_rows = rows;
         plan.steps.push_back(ps);
