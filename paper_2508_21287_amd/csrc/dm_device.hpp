@@ -13,7 +13,8 @@ namespace dm {
 // (direct-address index).
 struct TableDev {
     const int32_t* base;
-    int64_t stride;
+    int64_t stride;   // column stride (position p of row m at base + p * stride + m * rstride)
+    int64_t rstride;  // row stride: 1 for a column-major (SoA) table, `size` for a row-major one
     const int32_t* offs;
     int64_t rows;
     int32_t size;
@@ -22,6 +23,14 @@ struct TableDev {
     int32_t sorted_by;
     int32_t sorted_max;
     int32_t pad_;
+    // Run index of a table ordered by (key, position sorted_by - 1): for key
+    // v, the distinct values of that position are pair_far[pair_offs[v] ..
+    // pair_offs[v+1]) (ascending) and the run of value pair_far[i] starts at
+    // row pair_start[i] and ends where the next one starts (or at the group's
+    // end).  nullptr: none.
+    const int32_t* pair_offs;
+    const int32_t* pair_far;
+    const int32_t* pair_start;
 };
 
 constexpr int kGroupSortMax = 64;    // groups the per-thread insertion sort orders
@@ -309,9 +318,20 @@ hipError_t launch_claw_fill(const int32_t* rp, const int32_t* col, int32_t n, in
 hipError_t launch_group_sort(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec, int32_t* data,
                              hipStream_t s);
 // The same order for groups of up to kGroupSortLds rows, any number of
-// columns, from `in` into `out` (larger groups copied unchanged)
+// columns, from the SoA table `in` into `out`, row-major (size int32 per row;
+// larger groups copied in their order)
 hipError_t launch_group_sort_lds(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec,
                                  const int32_t* in, int32_t* out, hipStream_t s);
+// Run index of a row-major table of `rows` rows (`size` int32 each) ordered
+// by (column 0, column sec): flags[i] = 1 where a run starts (the scan of the
+// flags gives each run its index), then the runs' first rows and values, and
+// each key's first run (see TableDev::pair_offs)
+hipError_t launch_run_flags(const int32_t* aos, int64_t rows, int32_t size, int32_t sec, int32_t* flags,
+                            hipStream_t s);
+hipError_t launch_run_fill(const int32_t* aos, int64_t rows, int32_t size, int32_t sec, const int32_t* flags,
+                           const int32_t* idx, int32_t* run_far, int32_t* run_start, hipStream_t s);
+hipError_t launch_run_offs(const int32_t* offs, int32_t n, int64_t rows, const int32_t* idx, const int64_t* total,
+                           int32_t* run_offs, hipStream_t s);
 // *nnz_dev (<= nnz_max) directed edges, read on the device
 hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int64_t nnz_max,
                              int32_t wpr, uint32_t* bitmap, hipStream_t s);

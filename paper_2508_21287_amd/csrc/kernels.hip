@@ -233,7 +233,7 @@ __device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t* my, 
     const int c_in = st.c_in;
     if (st.motif >= 0) {
         // issue every load of this candidate before the first compare
-        const int32_t* tb = a.tbl.base + m;
+        const int32_t* tb = a.tbl.base + (int64_t)m * a.tbl.rstride;
         const int64_t ts = a.tbl.stride;
         const int n_new = st.n_new, n_eq = st.n_eq;
         int32_t ev[NEQ > 0 ? NEQ : 1];
@@ -357,26 +357,43 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             const int32_t key = my[st.key_col];
             lo = a.tbl.offs[key];
             hi = a.tbl.offs[key + 1];
-            if (!LAT && st.n_eq > 0 && a.tbl.sorted_by == st.eq_pos[0] + 1 && hi - lo > 16 &&
-                hi - lo <= a.tbl.sorted_max) {
+            if (!LAT && st.n_eq > 0 && a.tbl.sorted_by == st.eq_pos[0] + 1) {
                 // the key group is ordered by the first further key's position:
                 // keep only its run equal to this row's value (the rest fail that
                 // key anyway, and the test below still checks every candidate)
-                const int32_t* sc = a.tbl.base + (int64_t)st.eq_pos[0] * a.tbl.stride;
                 const int32_t want = my[st.eq_col[0]];
-                int32_t l = lo, h = hi;
-                while (l < h) {
-                    const int32_t mid = (l + h) >> 1;
-                    if (sc[mid] < want) l = mid + 1; else h = mid;
+                if (a.tbl.pair_offs) {
+                    // the group's distinct values of that position, with the
+                    // row each run starts at: one short search, few lines
+                    const int32_t pl = a.tbl.pair_offs[key], ph = a.tbl.pair_offs[key + 1];
+                    int32_t l = pl, h = ph;
+                    while (l < h) {
+                        const int32_t mid = (l + h) >> 1;
+                        if (a.tbl.pair_far[mid] < want) l = mid + 1; else h = mid;
+                    }
+                    if (l < ph && a.tbl.pair_far[l] == want) {
+                        lo = a.tbl.pair_start[l];
+                        hi = l + 1 < ph ? a.tbl.pair_start[l + 1] : hi;
+                    } else {
+                        lo = hi;
+                    }
+                } else if (hi - lo > 16 && hi - lo <= a.tbl.sorted_max) {
+                    const int32_t* sc = a.tbl.base + (int64_t)st.eq_pos[0] * a.tbl.stride;
+                    const int64_t rs = a.tbl.rstride;
+                    int32_t l = lo, h = hi;
+                    while (l < h) {
+                        const int32_t mid = (l + h) >> 1;
+                        if (sc[mid * rs] < want) l = mid + 1; else h = mid;
+                    }
+                    int32_t e = l;
+                    h = hi;
+                    while (e < h) {
+                        const int32_t mid = (e + h) >> 1;
+                        if (sc[mid * rs] <= want) e = mid + 1; else h = mid;
+                    }
+                    lo = l;
+                    hi = e;
                 }
-                int32_t e = l;
-                h = hi;
-                while (e < h) {
-                    const int32_t mid = (e + h) >> 1;
-                    if (sc[mid] <= want) e = mid + 1; else h = mid;
-                }
-                lo = l;
-                hi = e;
             }
         } else {
             hi = 1;  // filter-only step: the row itself is the one candidate
@@ -407,11 +424,12 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
         // Most candidates fail the first further join key: test it for eight
         // candidates per round of loads, then run the full test on the rest.
         const int32_t* kcol = a.tbl.base + (int64_t)st.eq_pos[0] * a.tbl.stride;
+        const int64_t krs = a.tbl.rstride;
         const int32_t want = my[st.eq_col[0]];
         for (int32_t m0 = lo; m0 < hi; m0 += 8) {
             int32_t k8[8];
 #pragma unroll
-            for (int j = 0; j < 8; j++) k8[j] = (m0 + j < hi) ? kcol[m0 + j] : ~want;
+            for (int j = 0; j < 8; j++) k8[j] = (m0 + j < hi) ? kcol[(int64_t)(m0 + j) * krs] : ~want;
             uint32_t pm = 0;
 #pragma unroll
             for (int j = 0; j < 8; j++) pm |= (uint32_t)(k8[j] == want) << j;
@@ -507,7 +525,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
                 if (LAT) st_out(dst + (int64_t)c * os, prow[c]);
                 else dst[(int64_t)c * os] = prow[c];
             }
-            const int32_t* tb = a.tbl.base + m;
+            const int32_t* tb = a.tbl.base + (int64_t)m * a.tbl.rstride;
             const int64_t ts = a.tbl.stride;
             if (n_new > 0) {
                 for (int t0 = 0; t0 < n_new; t0 += 4) {
@@ -1987,8 +2005,11 @@ __global__ __launch_bounds__(256) void group_sort_lds_kernel(const int32_t* offs
         const int32_t a = offs[v], len = offs[v + 1] - offs[v];
         if (len <= 0) continue;
         if (len == 1 || len > kGroupSortLds) {
-            for (int q = 0; q < size; q++)
-                for (int32_t i = tid; i < len; i += nt) out[(int64_t)q * stride + a + i] = in[(int64_t)q * stride + a + i];
+            for (int64_t e = tid; e < (int64_t)len * size; e += nt) {
+                const int64_t i = e / size;
+                const int q = (int)(e - i * size);
+                out[(int64_t)a * size + e] = in[(int64_t)q * stride + a + i];
+            }
             continue;
         }
         int P = 1;
@@ -2009,13 +2030,60 @@ __global__ __launch_bounds__(256) void group_sort_lds_kernel(const int32_t* offs
                 __syncthreads();
             }
         }
-        for (int q = 0; q < size; q++) {
-            const int32_t* src = in + (int64_t)q * stride + a;
-            int32_t* dst = out + (int64_t)q * stride + a;
-            for (int32_t i = tid; i < len; i += nt) dst[i] = src[(uint32_t)key[i]];
+        // row-major: consecutive threads write consecutive words of the rows
+        for (int32_t e = tid; e < len * size; e += nt) {
+            const int32_t i = e / size, q = e - i * size;
+            out[(int64_t)a * size + e] = in[(int64_t)q * stride + a + (uint32_t)key[i]];
         }
         __syncthreads();  // key[] is refilled for the next group
     }
+}
+
+// run starts of a row-major table ordered by (column 0, column sec)
+__global__ void run_flags_kernel(const int32_t* aos, int64_t rows, int32_t size, int32_t sec, int32_t* flags) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t* r = aos + i * size;
+        flags[i] = (i == 0 || r[0] != r[-size] || r[sec] != r[sec - size]) ? 1 : 0;
+    }
+}
+
+__global__ void run_fill_kernel(const int32_t* aos, int64_t rows, int32_t size, int32_t sec, const int32_t* flags,
+                                const int32_t* idx, int32_t* run_far, int32_t* run_start) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x)
+        if (flags[i]) {
+            run_far[idx[i]] = aos[i * size + sec];
+            run_start[idx[i]] = (int32_t)i;
+        }
+}
+
+__global__ void run_offs_kernel(const int32_t* offs, int32_t n, int64_t rows, const int32_t* idx,
+                                const int64_t* total, int32_t* run_offs) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = offs[v];
+        run_offs[v] = r < rows ? idx[r] : (int32_t)*total;
+    }
+}
+
+hipError_t launch_run_flags(const int32_t* aos, int64_t rows, int32_t size, int32_t sec, int32_t* flags,
+                            hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(run_flags_kernel, dim3(grid_for(rows, 256)), dim3(256), 0, s, aos, rows, size, sec, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_run_fill(const int32_t* aos, int64_t rows, int32_t size, int32_t sec, const int32_t* flags,
+                           const int32_t* idx, int32_t* run_far, int32_t* run_start, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(run_fill_kernel, dim3(grid_for(rows, 256)), dim3(256), 0, s, aos, rows, size, sec, flags, idx,
+                       run_far, run_start);
+    return hipGetLastError();
+}
+
+hipError_t launch_run_offs(const int32_t* offs, int32_t n, int64_t rows, const int32_t* idx, const int64_t* total,
+                           int32_t* run_offs, hipStream_t s) {
+    hipLaunchKernelGGL(run_offs_kernel, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, s, offs, n, rows, idx,
+                       total, run_offs);
+    return hipGetLastError();
 }
 
 hipError_t launch_group_sort_lds(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec,

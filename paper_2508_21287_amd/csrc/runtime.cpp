@@ -875,9 +875,11 @@ dm::TableDev dm_datagraph::table_dev(int motif, int key_pos) const {
     t.stride = m.stride;
     t.offs = m.offs;
     t.rows = m.rows;
+    t.rstride = 1;
     t.size = m.size;
     t.sorted_by = 0;
     t.sorted_max = 0;
+    t.pair_offs = t.pair_far = t.pair_start = nullptr;
     return t;
 }
 
@@ -886,8 +888,15 @@ dm::TableDev dm_datagraph::table_dev_step(const dm::StepDesc& st) const {
     const MotifTable& m = tab[st.motif][st.key_pos];
     if (st.n_eq > 0 && m.sec_base && m.sorted_by == st.eq_pos[0] + 1) {
         t.base = m.sec_base;
+        if (m.sec_rowmajor) {
+            t.stride = 1;
+            t.rstride = m.size;
+        }
         t.sorted_by = m.sorted_by;
         t.sorted_max = m.sorted_max;
+        t.pair_offs = m.run_offs;
+        t.pair_far = m.run_far;
+        t.pair_start = m.run_start;
     }
     return t;
 }
@@ -986,7 +995,7 @@ static void free_tables(dm_datagraph* dg) {
     for (int m = 0; m < kNumMotifs; m++)
         for (int j = 0; j < 6; j++) {
             MotifTable& t = dg->tab[m][j];
-            for (int q = 0; q < 3; q++) dev_free(ctx, t.owned[q], s);
+            for (int q = 0; q < 4; q++) dev_free(ctx, t.owned[q], s);
             t = MotifTable();
         }
 }
@@ -997,7 +1006,7 @@ static void free_motif(dm_datagraph* dg, int m) {
     const dm_context* ctx = dg->ctx;
     for (int j = 0; j < 6; j++) {
         MotifTable& t = dg->tab[m][j];
-        for (int q = 0; q < 3; q++) dev_free(ctx, t.owned[q], s);
+        for (int q = 0; q < 4; q++) dev_free(ctx, t.owned[q], s);
         t = MotifTable();
     }
     dg->motif_bits &= ~(1u << m);
@@ -1137,7 +1146,10 @@ static dm_status build_second_copy(dm_datagraph* dg, MotifTable& t) {
     DM_TRY(dev_alloc(ctx, (void**)&sec, bytes, s));
     t.owned[2] = sec;
     if (lds) {
+        // row-major: a run's candidates are a few consecutive rows, one or two
+        // cache lines instead of one per column
         DM_HIP(launch_group_sort_lds(t.offs, dg->n, t.stride, L, L - 1, t.cols[0], sec, s));
+        t.sec_rowmajor = true;
     } else {
         DM_HIP(hipMemcpyAsync(sec, t.cols[0], bytes, hipMemcpyDeviceToDevice, s));
         DM_HIP(launch_group_sort(t.offs, dg->n, t.stride, L, L - 1, sec, s));
@@ -1145,6 +1157,41 @@ static dm_status build_second_copy(dm_datagraph* dg, MotifTable& t) {
     t.sec_base = sec;
     t.sorted_by = L;
     t.sorted_max = lds ? kGroupSortLds : kGroupSortMax;
+    if (lds && t.rows > 0 && t.rows < INT32_MAX) {
+        // run index: per key, the distinct far ends and where their runs
+        // start (flags, their scan, then the runs and the per-key offsets);
+        // sized for one run per row, so no count is read back
+        Workspace& ws = ctx->ws;
+        const int64_t rows = t.rows;
+        const size_t a256 = 256;
+        auto al = [&](size_t x) { return (x + a256 - 1) / a256 * a256; };
+        const size_t b_rows = al(sizeof(int32_t) * (size_t)rows), b_offs = al(sizeof(int32_t) * (size_t)(dg->n + 1));
+        int32_t* blk = nullptr;
+        DM_TRY(dev_alloc(ctx, (void**)&blk, 2 * b_rows + b_offs, s));
+        t.owned[3] = blk;
+        t.run_far = blk;
+        t.run_start = (int32_t*)((char*)blk + b_rows);
+        t.run_offs = (int32_t*)((char*)blk + 2 * b_rows);
+        int32_t* tmp = nullptr;
+        DM_TRY(dev_alloc(ctx, (void**)&tmp, 2 * b_rows, s));
+        struct Tmp {
+            const dm_context* ctx;
+            int32_t* p;
+            hipStream_t s;
+            ~Tmp() { dev_free(ctx, p, s); }
+        } tmp_guard{ctx, tmp, s};
+        int32_t* flags = tmp;
+        int32_t* idx = (int32_t*)((char*)tmp + b_rows);
+        const int64_t tiles = rows / 1024 + 2;
+        DM_TRY(ws.ensure_status(tiles));
+        DM_HIP(launch_run_flags(sec, rows, L, L - 1, flags, s));
+        DM_HIP(launch_fill_u64(ws.status, 0, tiles, s));
+        DM_HIP(launch_fill_u64(ws.tickets, 0, 1, s));
+        DM_HIP(launch_scan_i32(flags, idx, rows, &ws.ctrl_d->counts[0], ws.status, ws.tickets,
+                               wait_ctl(ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, 0), s));
+        DM_HIP(launch_run_fill(sec, rows, L, L - 1, flags, idx, t.run_far, t.run_start, s));
+        DM_HIP(launch_run_offs(t.offs, dg->n, rows, idx, &ws.ctrl_d->counts[0], t.run_offs, s));
+    }
     return DM_OK;
 }
 

@@ -114,9 +114,15 @@ struct MotifTable {
     // A second copy of the rows (same offsets) whose key groups are ordered
     // by position sorted_by - 1, for steps whose first further key sits there
     int32_t* sec_base = nullptr;
+    bool sec_rowmajor = false;  // the second copy is row-major (size int32 per row)
     int32_t sorted_by = 0;
     int32_t sorted_max = 0;  // largest key group the second copy orders
-    int32_t* owned[3] = {nullptr, nullptr, nullptr};  // allocations to free (data, offs, second copy)
+    // run index of the row-major second copy (see TableDev::pair_offs)
+    int32_t* run_offs = nullptr;
+    int32_t* run_far = nullptr;
+    int32_t* run_start = nullptr;
+    // allocations to free (data, offs, second copy, run index)
+    int32_t* owned[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 struct DataGraph;
