@@ -114,6 +114,8 @@ struct EjfArgs {
     const int32_t* next_offs;
     int32_t next_key_col;
     int32_t induced;      // 1: pattern non-edges must map to data non-edges (StepDesc::padj)
+    int32_t cand_par;     // per-launch form: 1 = candidate-parallel tiles (many candidates per row, uneven)
+    int32_t pad_cp_;
     // Layout scoring: when out_cost is set, each output row's cost is its
     // input row's cost (identity input: the root's vertex cost) plus the
     // vertex costs of the new values and the edge costs of the pattern edges

@@ -287,6 +287,94 @@ __device__ __forceinline__ bool ejf_accept(const EjfArgs& a, const int32_t* my, 
     return true;
 }
 
+// Per-step constants of the per-launch candidate test, staged in LDS once
+// per workgroup: each candidate then reads them with a few broadcast loads
+// instead of holding them in scalar registers across the whole kernel.
+struct AcceptLds {
+    int64_t noff[kMaxMotif];  // element offset of new value t in a motif row; past the
+                              // step's last new value, that value's again
+    int64_t eoff[kMaxMotif];  // element offset of further join key e
+    int32_t eqcol[kMaxMotif]; // the input column it must equal
+};
+
+// Stage the step's constants (threads 0..kMaxMotif-1; a barrier follows before use).
+__device__ __forceinline__ void accept_lds_fill(const EjfArgs& a, AcceptLds& k) {
+    const int t = threadIdx.x;
+    if (t < kMaxMotif) {
+        const StepDesc& st = a.st;
+        const int nn = st.motif >= 0 ? st.n_new : 0;
+        const int64_t ts = a.tbl.stride;
+        k.noff[t] = nn > 0 ? (int64_t)st.new_pos[t < nn ? t : nn - 1] * ts : 0;
+        k.eoff[t] = t < st.n_eq ? (int64_t)st.eq_pos[t] * ts : 0;
+        k.eqcol[t] = t < st.n_eq ? st.eq_col[t] : 0;
+    }
+}
+
+// The test of ejf_accept for the per-launch form, written so that every
+// candidate runs the same instructions: all NV value loads unconditionally
+// (an instantiation's NV is the step's new-value count rounded up to the
+// next instantiated size; the extra slots repeat the last new value, which
+// changes no test), outcomes as predicates rather than early exits, and the
+// row scan that settles the summary's maybe-hits run once for the wave when
+// any lane needs it, as one compare per (row value, new value) pair.  Only
+// the edge and induced checks, after that, still leave early.
+template <int NV, class BL>
+__device__ __forceinline__ bool ejf_accept_flat(const EjfArgs& a, const AcceptLds& k, const int32_t* my,
+                                                const BL& bl, int32_t m, int32_t (&nv)[NV]) {
+    const StepDesc& st = a.st;
+    const int c_in = st.c_in;
+    bool ok = true;
+    if (st.motif >= 0) {
+        const int32_t* tb = a.tbl.base + (int64_t)m * a.tbl.rstride;
+#pragma unroll
+        for (int t = 0; t < NV; t++) nv[t] = tb[k.noff[t]];
+        for (int e = 0; e < st.n_eq; e++) ok &= tb[k.eoff[e]] == my[k.eqcol[e]];
+        bool hit = false;
+#pragma unroll
+        for (int t = 0; t < NV; t++) hit |= bl.maybe(nv[t]);
+        if (bl.is_exact()) {
+            ok &= !hit;
+        } else if (__any(ok && hit)) {
+            bool dup = false;
+            for (int c = 0; c < c_in; c++) {
+                const int32_t v = my[c];
+#pragma unroll
+                for (int t = 0; t < NV; t++) dup |= v == nv[t];
+            }
+            ok &= !dup;
+        }
+    }
+    if (st.n_edge > 0 || (a.induced && st.motif >= 0)) {
+        if (!ok) return false;
+        for (int e = 0; e < st.n_edge; e++) {
+            const int ca = st.edge_a[e], cb = st.edge_b[e];
+            const int32_t va = ca < c_in ? my[ca] : pick_new(nv, ca - c_in);
+            const int32_t vb = cb < c_in ? my[cb] : pick_new(nv, cb - c_in);
+            if (!adjacent(a.g, va, vb)) return false;
+        }
+        if (a.induced && st.motif >= 0) {
+            for (int t = 0; t < st.n_new; t++) {
+                const int32_t x = pick_new(nv, t);
+                const uint64_t m0 = st.padj[t][0], m1 = st.padj[t][1];
+                for (int32_t i = a.g.row_ptr[x], e = a.g.row_ptr[x + 1]; i < e; i++) {
+                    const int32_t w = a.g.col[i];
+                    int c = -1;
+                    if (bl.maybe(w))
+                        for (int q = 0; q < c_in; q++)
+                            if (my[q] == w) c = q;
+                    for (int q = 0; q < t; q++)
+                        if (pick_new(nv, q) == w) c = c_in + q;
+                    if (c >= 0 && !(((c < 64 ? m0 : m1) >> (c & 63)) & 1ull)) return false;
+                }
+            }
+        }
+    }
+    return ok;
+}
+
+// Candidate-parallel tiles keep at most this many 64-candidate chunks per wave.
+constexpr int kCpChunks = 64;
+
 template <int BLOCK>
 struct TileShared {
     static constexpr int CH = 8 * BLOCK;  // output rows staged per write pass
@@ -294,12 +382,196 @@ struct TileShared {
     int32_t total;
     int32_t wsum[BLOCK / 64];
     int32_t wexcl[BLOCK / 64];
-    int32_t mrow[CH];   // motif row of each staged output row
-    uint8_t src[CH];    // input row (lane of the tile) of each staged output row
+    union {
+        struct {
+            int32_t mrow[CH];   // motif row of each staged output row
+            uint8_t src[CH];    // input row (lane of the tile) of each staged output row
+        } st;
+        struct {  // candidate-parallel tiles (ejf_tile_cp)
+            int32_t cstart[BLOCK];              // first candidate index of each row within its wave
+            int32_t clo[BLOCK];                 // first motif row of each row's candidates
+            uint64_t bl[BLOCK][2];              // each row's summary words
+            uint64_t inner[BLOCK];              // count+hash mode: each row's inner hash
+            uint64_t mask[BLOCK / 64][kCpChunks];  // survivors of each 64-candidate chunk
+        } cp;
+    };
 };
 
 // Row stride (in int32) of the LDS row tile for c columns: odd, >= c.
 __host__ __device__ __forceinline__ int row_stride(int c) { return c | 1; }
+
+// Output offset of each wave's first row in this tile: wave totals scanned
+// across the workgroup, the tile's offset from the look-back chain.  Leaves
+// sh.base / sh.total (both 0 when the look-back gave up) and sh.wexcl.
+template <int BLOCK>
+__device__ __forceinline__ void tile_offsets(const EjfArgs& a, int64_t tile, int64_t n_tiles, TileShared<BLOCK>& sh,
+                                             int32_t wave_total) {
+    constexpr int NW = BLOCK / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (lane == 0) sh.wsum[wid] = wave_total;
+    __syncthreads();
+    if (wid == 0) {
+        int32_t w = lane < NW ? sh.wsum[lane] : 0;
+        int32_t wi = w;
+#pragma unroll
+        for (int o = 1; o < NW; o <<= 1) {
+            const int32_t y = __shfl_up(wi, o, 64);
+            if (lane >= o) wi += y;
+        }
+        if (lane < NW) sh.wexcl[lane] = wi - w;
+        const int32_t total = __shfl(wi, NW - 1, 64);
+        const int64_t excl = lookback_wave(a.status, a.epoch, tile, (uint64_t)total, lane, a.w, a.diag_pattern,
+                                           a.diag_step);
+        if (lane == 0) {
+            if (excl < 0) {
+                // the look-back gave up (the run is being aborted): write nothing
+                sh.base = 0;
+                sh.total = 0;
+            } else {
+                sh.base = excl;
+                sh.total = total;
+                if (tile == n_tiles - 1) *a.n_out = excl + total;
+                if (excl + total > a.out_cap) *a.overflow = 1;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Candidate-parallel form of a tile, for steps whose rows have many
+// candidates of uneven number (a key group of a large motif table, the run of
+// a two-key join).  Looping over its own candidates, a lane would keep its
+// wave as long as the row with the most; here the candidates of a wave's 64
+// rows are numbered consecutively (a scan of their counts) and the wave tests
+// them 64 at a time, lane i taking candidate 64 j + i, whose row is found by
+// a search over the scan.  Consecutive lanes read consecutive motif rows.
+// Survivors of each group of 64 are kept as one ballot word in LDS; after the
+// tile's offset is known, each lane writes its survivor's whole row, at the
+// survivor's rank among the tile's, so the output is the row-by-row one.
+// Returns false (the whole workgroup alike, before any output) when some wave
+// has more candidates than its ballot words can hold; the caller then runs
+// the row-per-lane form.
+template <int BLOCK, int NV>
+__device__ __forceinline__ bool ejf_tile_cp(const EjfArgs& a, const AcceptLds& ka, int64_t tile, int64_t n_tiles,
+                                            TileShared<BLOCK>& sh, const int32_t* rows, const Bloom<2, false>& bl,
+                                            int32_t lo, int32_t cnt,
+                                            uint64_t inner_old, uint64_t& h_cnt, uint64_t& h_sum, uint64_t& h_xor) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const StepDesc& st = a.st;
+    const int c_in = st.c_in;
+    const int RS = row_stride(c_in);
+    const bool hash = a.mode == EJF_HASH;
+    int32_t x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    const int32_t wtot = __builtin_amdgcn_readfirstlane(__shfl(x, 63, 64));  // wave-uniform
+    sh.cp.cstart[tid] = x - cnt;
+    sh.cp.clo[tid] = lo;
+    sh.cp.bl[tid][0] = bl.w0;
+    sh.cp.bl[tid][1] = bl.w1;
+    sh.cp.inner[tid] = inner_old;
+    if (__syncthreads_or(wtot > 64 * kCpChunks)) return false;
+
+    const int w0 = wid * 64;
+    const int32_t* cs = sh.cp.cstart + w0;
+    const int nch = (wtot + 63) >> 6;
+    const int n_new = st.n_new;
+    // the input row holding candidate c of this wave (c < wtot): the last
+    // row whose first candidate is at most c (rows without candidates share
+    // their successor's start and are passed over)
+    auto owner = [&](int32_t c) -> int {
+        int r = 0;
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1)
+            if (cs[r + s] <= c) r += s;
+        return r;
+    };
+    auto accept = [&](int r, int32_t m, int32_t (&nv)[NV]) -> bool {
+        Bloom<2, false> ob;
+        ob.init(a.g.n);
+        ob.w0 = sh.cp.bl[w0 + r][0];
+        ob.w1 = sh.cp.bl[w0 + r][1];
+        if (!ejf_accept_flat<NV>(a, ka, rows + (w0 + r) * RS, ob, m, nv)) return false;
+        if (hash) {
+            uint64_t inner = sh.cp.inner[w0 + r];
+#pragma unroll
+            for (int t = 0; t < NV; t++)
+                if (t < n_new) inner += mix64(((uint64_t)a.pv[c_in + t] << 32) | (uint32_t)nv[t]);
+            const uint64_t h = mix64(inner);
+            h_cnt++;
+            h_sum += h;
+            h_xor ^= h;
+        }
+        return true;
+    };
+    int32_t surv = 0;
+    for (int j = 0; j < nch; j++) {
+        const int32_t c = j * 64 + lane;
+        bool ok = false;
+        if (c < wtot) {
+            int32_t nv[NV];
+#pragma unroll
+            for (int t = 0; t < NV; t++) nv[t] = -1;
+            const int r = owner(c);
+            ok = accept(r, sh.cp.clo[w0 + r] + (c - cs[r]), nv);
+        }
+        if (!hash) {
+            const uint64_t mk = __ballot(ok);
+            if (lane == 0) sh.cp.mask[wid][j] = mk;
+            surv += __popcll(mk);
+        }
+    }
+    if (hash) return true;  // nothing written: the tile's LDS may be reused at once
+
+    tile_offsets<BLOCK>(a, tile, n_tiles, sh, surv);
+    if (sh.total == 0) return true;
+    const int64_t base = sh.base + sh.wexcl[wid];
+    const int64_t os = a.out_stride, ts = a.tbl.stride;
+    int64_t cand_acc = 0;
+    int32_t pre = 0;
+    for (int j = 0; j < nch; j++) {
+        const uint64_t mk = sh.cp.mask[wid][j];
+        if ((mk >> lane) & 1ull) {
+            const int64_t orow = base + pre + __popcll(mk & ((1ull << lane) - 1ull));
+            if (orow < a.out_cap) {
+                const int32_t c = j * 64 + lane;
+                const int r = owner(c);
+                const int32_t m = sh.cp.clo[w0 + r] + (c - cs[r]);
+                const int32_t* prow = rows + (w0 + r) * RS;
+                const int32_t* tb = a.tbl.base + (int64_t)m * a.tbl.rstride;
+                int32_t* dst = a.out + orow;
+                for (int cc = 0; cc < c_in; cc++) dst[(int64_t)cc * os] = prow[cc];
+                for (int t0 = 0; t0 < n_new; t0 += 4) {
+                    int32_t w4[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        if (t0 + q < n_new) w4[q] = tb[(int64_t)st.new_pos[t0 + q] * ts];
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        if (t0 + q < n_new) dst[(int64_t)(c_in + t0 + q) * os] = w4[q];
+                }
+                if (a.next_cand) {
+                    const int nk = a.next_key_col;
+                    if (nk < 0) {
+                        cand_acc += 1;
+                    } else {
+                        const int32_t kv = nk < c_in ? prow[nk] : tb[(int64_t)st.new_pos[nk - c_in] * ts];
+                        cand_acc += a.next_offs[kv + 1] - a.next_offs[kv];
+                    }
+                }
+            }
+        }
+        pre += __popcll(mk);
+    }
+    if (a.next_cand) {
+        const uint64_t w = wave_sum_u64((uint64_t)cand_acc);
+        if (lane == 0 && w) atomicAdd((unsigned long long*)a.next_cand, (unsigned long long)w);
+    }
+    return true;
+}
 
 // SCORE: the layout-cost column is carried (scored runs only; the batched
 // form never scores, so its instantiation carries no cost code).
@@ -308,11 +580,11 @@ __host__ __device__ __forceinline__ int row_stride(int c) { return c | 1; }
 // scope (nothing dirty left in L2 for the release to write back), and its
 // summary is 256 bits wide (exact up to 256 vertices).  The per-launch form
 // is throughput-bound on large tables: plain stores, 128 bits.
-template <int BLOCK, int NV, bool SCORE, bool LAT>
-__device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t n_in, int64_t n_tiles,
-                                         TileShared<BLOCK>& sh, int32_t* rows, uint64_t& h_cnt, uint64_t& h_sum,
-                                         uint64_t& h_xor) {
-    constexpr int NW = BLOCK / 64;
+// CP: steps marked for the candidate-parallel form try it first (ejf_tile_cp).
+template <int BLOCK, int NV, bool SCORE, bool LAT, bool CP = false>
+__device__ __forceinline__ void ejf_tile(const EjfArgs& a, const AcceptLds* ka, int64_t tile, int64_t n_in,
+                                         int64_t n_tiles, TileShared<BLOCK>& sh, int32_t* rows, uint64_t& h_cnt,
+                                         uint64_t& h_sum, uint64_t& h_xor) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const StepDesc& st = a.st;
     const int c_in = st.c_in;
@@ -326,6 +598,13 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
     constexpr int RCH = LAT ? 16 : 8;  // input columns loaded per round
     uint64_t inner_old = 0;
     const bool hash = a.mode == EJF_HASH;
+    // the latency-bound form keeps its early-exit test with further keys
+    // loaded up front; the per-launch form the flat one (per-step constants
+    // in LDS at ka)
+    auto accept = [&](int32_t m, int32_t (&v)[NV]) -> bool {
+        if constexpr (LAT) return ejf_accept<NV, NEQ>(a, my, bl, m, v);
+        else return ejf_accept_flat<NV>(a, *ka, my, bl, m, v);
+    };
     if (valid) {
         if (a.in) {
             const int32_t* src = a.in + (a.in_row0 ? *a.in_row0 : 0) + row;
@@ -399,13 +678,18 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             hi = 1;  // filter-only step: the row itself is the one candidate
         }
     }
+    if constexpr (CP && !LAT && !SCORE) {
+        if (ejf_tile_cp<BLOCK, NV>(a, *ka, tile, n_tiles, sh, rows, bl, lo, valid ? hi - lo : 0, inner_old,
+                                                 h_cnt, h_sum, h_xor))
+            return;
+    }
     int32_t nv[NV];
 #pragma unroll
     for (int t = 0; t < NV; t++) nv[t] = -1;
 
     if (hash) {
         for (int32_t m = lo; m < hi; m++) {
-            if (!ejf_accept<NV, NEQ>(a, my, bl, m, nv)) continue;
+            if (!accept(m, nv)) continue;
             uint64_t inner = inner_old;
 #pragma unroll
             for (int t = 0; t < NV; t++)
@@ -437,7 +721,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
                 const int j = __ffs((int)pm) - 1;
                 pm &= pm - 1;
                 const int32_t m = m0 + j;
-                if (ejf_accept<NV, NEQ>(a, my, bl, m, nv)) {
+                if (accept(m, nv)) {
                     if (m - lo < 64) mask |= 1ull << (m - lo);
                     cnt++;
                 }
@@ -445,7 +729,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
         }
     } else {
         for (int32_t m = lo; m < hi; m++) {
-            if (ejf_accept<NV, NEQ>(a, my, bl, m, nv)) {
+            if (accept(m, nv)) {
                 if (m - lo < 64) mask |= 1ull << (m - lo);
                 cnt++;
             }
@@ -458,34 +742,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
         const int32_t y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
-    if (lane == 63) sh.wsum[wid] = x;
-    __syncthreads();
-    if (wid == 0) {
-        int32_t w = lane < NW ? sh.wsum[lane] : 0;
-        int32_t wi = w;
-#pragma unroll
-        for (int o = 1; o < NW; o <<= 1) {
-            const int32_t y = __shfl_up(wi, o, 64);
-            if (lane >= o) wi += y;
-        }
-        if (lane < NW) sh.wexcl[lane] = wi - w;
-        const int32_t total = __shfl(wi, NW - 1, 64);
-        const int64_t excl = lookback_wave(a.status, a.epoch, tile, (uint64_t)total, lane, a.w, a.diag_pattern,
-                                           a.diag_step);
-        if (lane == 0) {
-            if (excl < 0) {
-                // the look-back gave up (the run is being aborted): write nothing
-                sh.base = 0;
-                sh.total = 0;
-            } else {
-                sh.base = excl;
-                sh.total = total;
-                if (tile == n_tiles - 1) *a.n_out = excl + total;
-                if (excl + total > a.out_cap) *a.overflow = 1;
-            }
-        }
-    }
-    __syncthreads();
+    tile_offsets<BLOCK>(a, tile, n_tiles, sh, __shfl(x, 63, 64));
     // Write phase: survivors are staged in LDS in output order as (input
     // lane, motif row); then each thread assembles whole output rows (parent
     // values from the LDS row tile, new values from the motif table) and
@@ -505,10 +762,10 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             const int32_t li = local0 + r_cur;
             if (li >= w0 + CH) break;  // belongs to a later pass
             const int32_t m = m_cur++;
-            const bool ok = (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : ejf_accept<NV, NEQ>(a, my, bl, m, nv);
+            const bool ok = (m - lo < 64) ? (bool)((mask >> (m - lo)) & 1ull) : accept(m, nv);
             if (!ok) continue;
-            sh.src[li - w0] = (uint8_t)tid;
-            sh.mrow[li - w0] = m;
+            sh.st.src[li - w0] = (uint8_t)tid;
+            sh.st.mrow[li - w0] = m;
             r_cur++;
         }
         __syncthreads();
@@ -517,8 +774,8 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
         for (int32_t o = tid; o < nrows; o += BLOCK) {
             const int64_t orow = obase + o;
             if (orow >= a.out_cap) break;
-            const int32_t* prow = rows + sh.src[o] * RS;
-            const int32_t m = sh.mrow[o];
+            const int32_t* prow = rows + sh.st.src[o] * RS;
+            const int32_t m = sh.st.mrow[o];
             int32_t* dst = a.out + orow;
             const int64_t os = a.out_stride;
             for (int c = 0; c < c_in; c++) {
@@ -543,7 +800,7 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, int64_t tile, int64_t
             }
             if (SCORE && a.out_cost) {
                 // layout cost: the parent's plus the new vertices' and the new edges'
-                uint64_t cst = a.in ? a.in_cost[tile * BLOCK + sh.src[o]] : (uint64_t)a.vcost[prow[0]];
+                uint64_t cst = a.in ? a.in_cost[tile * BLOCK + sh.st.src[o]] : (uint64_t)a.vcost[prow[0]];
                 for (int t = 0; t < n_new; t++) {
                     const int32_t x = tb[(int64_t)st.new_pos[t] * ts];
                     cst += a.vcost[x];
@@ -617,13 +874,15 @@ __device__ __forceinline__ int64_t clamp_rows(int64_t n, int64_t cap) { return n
 
 // One join-filter step over one table: workgroups claim tiles in ticket order
 // until the input is exhausted.  Dynamic LDS: BLOCK * row_stride(c_in) int32.
-template <int BLOCK, int NV, bool SCORE>
+template <int BLOCK, int NV, bool SCORE, bool CP>
 __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
     extern __shared__ int32_t rows[];
     __shared__ TileShared<BLOCK> sh;
+    __shared__ AcceptLds ka;
     __shared__ int64_t s_tile;
     __shared__ uint64_t s_red[3][BLOCK / 64];
     const int tid = threadIdx.x;
+    accept_lds_fill(a, ka);  // read after the barrier of the first claim
     const int64_t n_in = a.in ? clamp_rows(*a.n_in, a.in_cap) : (int64_t)a.id_count;
     const int64_t n_tiles = (n_in + BLOCK - 1) / BLOCK;
     uint64_t h_cnt = 0, h_sum = 0, h_xor = 0;
@@ -645,7 +904,7 @@ __global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
             if (a.mode == EJF_WRITE && tile == 0 && tid == 0) *a.n_out = 0;
             break;
         }
-        ejf_tile<BLOCK, NV, SCORE, false>(a, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
+        ejf_tile<BLOCK, NV, SCORE, false, CP>(a, &ka, tile, n_in, n_tiles, sh, rows, h_cnt, h_sum, h_xor);
     }
     if (a.mode == EJF_HASH) hash_flush<BLOCK>(a.hash_acc, h_cnt, h_sum, h_xor, s_red);
 }
@@ -661,23 +920,43 @@ hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s) {
     const int c = a.st.c_in;
     block = ejf_block_for(c, block);
     const size_t lds = sizeof(int32_t) * (size_t)block * row_stride(c);
-    // instantiations: wide (more than kNarrowNew new values) or narrow, scored or not
-#define DM_EJF_LAUNCH(NV, SC)                                                                      \
-    switch (block) {                                                                               \
-        case 64: hipLaunchKernelGGL((ejf_kernel<64, NV, SC>), dim3(grid), dim3(64), lds, s, a); break;    \
-        case 128: hipLaunchKernelGGL((ejf_kernel<128, NV, SC>), dim3(grid), dim3(128), lds, s, a); break; \
-        default: hipLaunchKernelGGL((ejf_kernel<256, NV, SC>), dim3(grid), dim3(256), lds, s, a); break;  \
+#define DM_EJF_LAUNCH(NV, SC, CP)                                                                          \
+    switch (block) {                                                                                       \
+        case 64: hipLaunchKernelGGL((ejf_kernel<64, NV, SC, CP>), dim3(grid), dim3(64), lds, s, a); break;    \
+        case 128: hipLaunchKernelGGL((ejf_kernel<128, NV, SC, CP>), dim3(grid), dim3(128), lds, s, a); break; \
+        default: hipLaunchKernelGGL((ejf_kernel<256, NV, SC, CP>), dim3(grid), dim3(256), lds, s, a); break;  \
     }
-    const bool wide = a.st.n_new > kNarrowNew, scored = a.out_cost != nullptr;
-    if (wide && scored) {
-        DM_EJF_LAUNCH(kMaxMotif, true)
-    } else if (wide) {
-        DM_EJF_LAUNCH(kMaxMotif, false)
-    } else if (scored) {
-        DM_EJF_LAUNCH(kNarrowNew, true)
+#define DM_EJF_LAUNCH_CP(NV)      \
+    if (cp) {                     \
+        DM_EJF_LAUNCH(NV, false, true) \
+    } else {                      \
+        DM_EJF_LAUNCH(NV, false, false) \
+    }
+    // instantiations: the step's new values rounded up to 1, 2, 4, 6, 12 or
+    // 18 (the test loads that many per candidate), each also in the
+    // candidate-parallel form; scored runs (rare) take 12 or 18
+    const int nn = a.st.motif >= 0 ? a.st.n_new : 0;
+    const bool scored = a.out_cost != nullptr, cp = a.cand_par != 0;
+    if (scored) {
+        if (nn > kNarrowNew) {
+            DM_EJF_LAUNCH(kMaxMotif, true, false)
+        } else {
+            DM_EJF_LAUNCH(kNarrowNew, true, false)
+        }
+    } else if (nn <= 1) {
+        DM_EJF_LAUNCH_CP(1)
+    } else if (nn <= 2) {
+        DM_EJF_LAUNCH_CP(2)
+    } else if (nn <= 4) {
+        DM_EJF_LAUNCH_CP(4)
+    } else if (nn <= 6) {
+        DM_EJF_LAUNCH_CP(6)
+    } else if (nn <= kNarrowNew) {
+        DM_EJF_LAUNCH_CP(kNarrowNew)
     } else {
-        DM_EJF_LAUNCH(kNarrowNew, false)
+        DM_EJF_LAUNCH_CP(kMaxMotif)
     }
+#undef DM_EJF_LAUNCH_CP
 #undef DM_EJF_LAUNCH
     return hipGetLastError();
 }
@@ -858,7 +1137,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const BatchDev b) {
         }
         __syncthreads();
         const int64_t n_in = s_nin;
-        ejf_tile<BLOCK, NV, false, true>(sa, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
+        ejf_tile<BLOCK, NV, false, true>(sa, nullptr, tile, n_in, n_tiles, sh, rows, hc, hs, hx);
         if (sa.mode == EJF_HASH) {
             hash_flush<BLOCK>(sa.hash_acc, hc, hs, hx, s_red);
             hc = hs = hx = 0;

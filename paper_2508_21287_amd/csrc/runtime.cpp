@@ -475,6 +475,10 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             a.mode = (last && hash_mode) ? EJF_HASH : EJF_WRITE;
             a.hash_acc = ws.ctrl_d->hash;
             a.induced = opt.induced ? 1 : 0;
+            // rows with many candidates of uneven number (large key groups, the
+            // runs of a two-key join): the wave tests candidates, not rows
+            if (a.st.motif >= 0 && !score)
+                a.cand_par = (a.tbl.pair_offs != nullptr || a.tbl.rows >= 8 * (int64_t)dg->n) ? 1 : 0;
             a.w = wait_ctl(ws.ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, opt.wait_limit_us);
             a.diag_pattern = -1;
             a.diag_step = i;
