@@ -4,6 +4,7 @@
 // (large tables) or by launch latency (small ones).
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "dm_device.hpp"
 
@@ -335,13 +336,15 @@ __device__ __forceinline__ bool ejf_accept_flat(const EjfArgs& a, const AcceptLd
         if (bl.is_exact()) {
             ok &= !hit;
         } else if (__any(ok && hit)) {
-            bool dup = false;
+            // zero iff some row value equals some new value (vector ALU only:
+            // a minimum of differences, no per-compare lane masks)
+            uint32_t d = ~0u;
             for (int c = 0; c < c_in; c++) {
-                const int32_t v = my[c];
+                const uint32_t v = (uint32_t)my[c];
 #pragma unroll
-                for (int t = 0; t < NV; t++) dup |= v == nv[t];
+                for (int t = 0; t < NV; t++) d = min(d, v ^ (uint32_t)nv[t]);
             }
-            ok &= !dup;
+            ok &= d != 0u;
         }
     }
     if (st.n_edge > 0 || (a.induced && st.motif >= 0)) {
@@ -372,10 +375,24 @@ __device__ __forceinline__ bool ejf_accept_flat(const EjfArgs& a, const AcceptLd
     return ok;
 }
 
-// Candidate-parallel tiles keep at most this many 64-candidate chunks per wave.
-constexpr int kCpChunks = 64;
+// Candidate-parallel tiles hold at most this many 64-candidate chunks per
+// wave, and test rows of at most kCpScanCols values by the row scan alone.
+constexpr int kCpChunks = 32;
+constexpr int kCpScanCols = 16;
 
 template <int BLOCK>
+struct CpShared {
+    int32_t mdelta[BLOCK];  // each row's first motif row minus its first candidate number
+    uint64_t bl[BLOCK][2];  // each row's summary words (rows wider than kCpScanCols)
+    uint64_t inner[BLOCK];  // count+hash mode: each row's inner hash
+    uint64_t mask[BLOCK / 64][kCpChunks];       // survivors of each 64-candidate chunk
+    uint8_t owner[BLOCK / 64][64 * kCpChunks];  // the row (lane) of each candidate of the wave
+};
+struct NoCpShared {};
+
+// CP: with the candidate-parallel part (kernels that have that form only,
+// so the others keep their smaller LDS footprint).
+template <int BLOCK, bool CP = false>
 struct TileShared {
     static constexpr int CH = 8 * BLOCK;  // output rows staged per write pass
     int64_t base;
@@ -387,14 +404,15 @@ struct TileShared {
             int32_t mrow[CH];   // motif row of each staged output row
             uint8_t src[CH];    // input row (lane of the tile) of each staged output row
         } st;
-        struct {  // candidate-parallel tiles (ejf_tile_cp)
-            int32_t cstart[BLOCK];              // first candidate index of each row within its wave
-            int32_t clo[BLOCK];                 // first motif row of each row's candidates
-            uint64_t bl[BLOCK][2];              // each row's summary words
-            uint64_t inner[BLOCK];              // count+hash mode: each row's inner hash
-            uint64_t mask[BLOCK / 64][kCpChunks];  // survivors of each 64-candidate chunk
-        } cp;
+        std::conditional_t<CP, CpShared<BLOCK>, NoCpShared> cp;
     };
+};
+
+// Stands in for the row summary where the row scan alone decides: every
+// value may be in the row.
+struct NoSummary {
+    __device__ __forceinline__ bool maybe(int32_t) const { return true; }
+    __device__ __forceinline__ bool is_exact() const { return false; }
 };
 
 // Row stride (in int32) of the LDS row tile for c columns: odd, >= c.
@@ -403,8 +421,8 @@ __host__ __device__ __forceinline__ int row_stride(int c) { return c | 1; }
 // Output offset of each wave's first row in this tile: wave totals scanned
 // across the workgroup, the tile's offset from the look-back chain.  Leaves
 // sh.base / sh.total (both 0 when the look-back gave up) and sh.wexcl.
-template <int BLOCK>
-__device__ __forceinline__ void tile_offsets(const EjfArgs& a, int64_t tile, int64_t n_tiles, TileShared<BLOCK>& sh,
+template <int BLOCK, class SH>
+__device__ __forceinline__ void tile_offsets(const EjfArgs& a, int64_t tile, int64_t n_tiles, SH& sh,
                                              int32_t wave_total) {
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -442,20 +460,20 @@ __device__ __forceinline__ void tile_offsets(const EjfArgs& a, int64_t tile, int
 // candidates of uneven number (a key group of a large motif table, the run of
 // a two-key join).  Looping over its own candidates, a lane would keep its
 // wave as long as the row with the most; here the candidates of a wave's 64
-// rows are numbered consecutively (a scan of their counts) and the wave tests
-// them 64 at a time, lane i taking candidate 64 j + i, whose row is found by
-// a search over the scan.  Consecutive lanes read consecutive motif rows.
-// Survivors of each group of 64 are kept as one ballot word in LDS; after the
-// tile's offset is known, each lane writes its survivor's whole row, at the
-// survivor's rank among the tile's, so the output is the row-by-row one.
-// Returns false (the whole workgroup alike, before any output) when some wave
-// has more candidates than its ballot words can hold; the caller then runs
-// the row-per-lane form.
+// rows are numbered consecutively (a scan of their counts; each row writes
+// its lane into the owner byte of its candidates) and the wave tests them 64
+// at a time, lane i taking candidate 64 j + i.  Consecutive lanes read
+// consecutive motif rows.  Survivors of each group of 64 are kept as one
+// ballot word in LDS; after the tile's offset is known, each lane writes its
+// survivor's whole row, at the survivor's rank among the tile's, so the output
+// is the row-by-row one.  Returns false (the whole workgroup alike, before any
+// output) when some wave has more candidates than its owner bytes hold; the
+// caller then runs the row-per-lane form.
 template <int BLOCK, int NV>
 __device__ __forceinline__ bool ejf_tile_cp(const EjfArgs& a, const AcceptLds& ka, int64_t tile, int64_t n_tiles,
-                                            TileShared<BLOCK>& sh, const int32_t* rows, const Bloom<2, false>& bl,
-                                            int32_t lo, int32_t cnt,
-                                            uint64_t inner_old, uint64_t& h_cnt, uint64_t& h_sum, uint64_t& h_xor) {
+                                            TileShared<BLOCK, true>& sh, const int32_t* rows,
+                                            const Bloom<2, false>& bl, int32_t lo, int32_t cnt, uint64_t inner_old,
+                                            uint64_t& h_cnt, uint64_t& h_sum, uint64_t& h_xor) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const StepDesc& st = a.st;
     const int c_in = st.c_in;
@@ -468,34 +486,34 @@ __device__ __forceinline__ bool ejf_tile_cp(const EjfArgs& a, const AcceptLds& k
         if (lane >= o) x += y;
     }
     const int32_t wtot = __builtin_amdgcn_readfirstlane(__shfl(x, 63, 64));  // wave-uniform
-    sh.cp.cstart[tid] = x - cnt;
-    sh.cp.clo[tid] = lo;
+    const bool fits = wtot <= 64 * kCpChunks;
+    const int32_t c0 = x - cnt;
+    uint8_t* own = sh.cp.owner[wid];
+    if (fits)
+        for (int32_t q = 0; q < cnt; q++) own[c0 + q] = (uint8_t)lane;
+    sh.cp.mdelta[tid] = lo - c0;
     sh.cp.bl[tid][0] = bl.w0;
     sh.cp.bl[tid][1] = bl.w1;
     sh.cp.inner[tid] = inner_old;
-    if (__syncthreads_or(wtot > 64 * kCpChunks)) return false;
+    if (__syncthreads_or(!fits)) return false;
 
     const int w0 = wid * 64;
-    const int32_t* cs = sh.cp.cstart + w0;
     const int nch = (wtot + 63) >> 6;
     const int n_new = st.n_new;
-    // the input row holding candidate c of this wave (c < wtot): the last
-    // row whose first candidate is at most c (rows without candidates share
-    // their successor's start and are passed over)
-    auto owner = [&](int32_t c) -> int {
-        int r = 0;
-#pragma unroll
-        for (int s = 32; s > 0; s >>= 1)
-            if (cs[r + s] <= c) r += s;
-        return r;
-    };
+    const bool scan_only = c_in <= kCpScanCols;
     auto accept = [&](int r, int32_t m, int32_t (&nv)[NV]) -> bool {
-        Bloom<2, false> ob;
-        ob.init(a.g.n);
-        ob.w0 = sh.cp.bl[w0 + r][0];
-        ob.w1 = sh.cp.bl[w0 + r][1];
-        if (!ejf_accept_flat<NV>(a, ka, rows + (w0 + r) * RS, ob, m, nv)) return false;
-        if (hash) {
+        const int32_t* orow = rows + (w0 + r) * RS;
+        bool ok;
+        if (scan_only) {
+            ok = ejf_accept_flat<NV>(a, ka, orow, NoSummary{}, m, nv);
+        } else {
+            Bloom<2, false> ob;
+            ob.init(a.g.n);
+            ob.w0 = sh.cp.bl[w0 + r][0];
+            ob.w1 = sh.cp.bl[w0 + r][1];
+            ok = ejf_accept_flat<NV>(a, ka, orow, ob, m, nv);
+        }
+        if (ok && hash) {
             uint64_t inner = sh.cp.inner[w0 + r];
 #pragma unroll
             for (int t = 0; t < NV; t++)
@@ -505,7 +523,7 @@ __device__ __forceinline__ bool ejf_tile_cp(const EjfArgs& a, const AcceptLds& k
             h_sum += h;
             h_xor ^= h;
         }
-        return true;
+        return ok;
     };
     int32_t surv = 0;
     for (int j = 0; j < nch; j++) {
@@ -513,10 +531,8 @@ __device__ __forceinline__ bool ejf_tile_cp(const EjfArgs& a, const AcceptLds& k
         bool ok = false;
         if (c < wtot) {
             int32_t nv[NV];
-#pragma unroll
-            for (int t = 0; t < NV; t++) nv[t] = -1;
-            const int r = owner(c);
-            ok = accept(r, sh.cp.clo[w0 + r] + (c - cs[r]), nv);
+            const int r = own[c];
+            ok = accept(r, c + sh.cp.mdelta[w0 + r], nv);
         }
         if (!hash) {
             const uint64_t mk = __ballot(ok);
@@ -538,8 +554,8 @@ __device__ __forceinline__ bool ejf_tile_cp(const EjfArgs& a, const AcceptLds& k
             const int64_t orow = base + pre + __popcll(mk & ((1ull << lane) - 1ull));
             if (orow < a.out_cap) {
                 const int32_t c = j * 64 + lane;
-                const int r = owner(c);
-                const int32_t m = sh.cp.clo[w0 + r] + (c - cs[r]);
+                const int r = own[c];
+                const int32_t m = c + sh.cp.mdelta[w0 + r];
                 const int32_t* prow = rows + (w0 + r) * RS;
                 const int32_t* tb = a.tbl.base + (int64_t)m * a.tbl.rstride;
                 int32_t* dst = a.out + orow;
@@ -583,7 +599,7 @@ __device__ __forceinline__ bool ejf_tile_cp(const EjfArgs& a, const AcceptLds& k
 // CP: steps marked for the candidate-parallel form try it first (ejf_tile_cp).
 template <int BLOCK, int NV, bool SCORE, bool LAT, bool CP = false>
 __device__ __forceinline__ void ejf_tile(const EjfArgs& a, const AcceptLds* ka, int64_t tile, int64_t n_in,
-                                         int64_t n_tiles, TileShared<BLOCK>& sh, int32_t* rows, uint64_t& h_cnt,
+                                         int64_t n_tiles, TileShared<BLOCK, CP>& sh, int32_t* rows, uint64_t& h_cnt,
                                          uint64_t& h_sum, uint64_t& h_xor) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const StepDesc& st = a.st;
@@ -875,9 +891,9 @@ __device__ __forceinline__ int64_t clamp_rows(int64_t n, int64_t cap) { return n
 // One join-filter step over one table: workgroups claim tiles in ticket order
 // until the input is exhausted.  Dynamic LDS: BLOCK * row_stride(c_in) int32.
 template <int BLOCK, int NV, bool SCORE, bool CP>
-__global__ __launch_bounds__(BLOCK) void ejf_kernel(const EjfArgs a) {
+__global__ __launch_bounds__(BLOCK, NV <= 6 ? 5 : 1) void ejf_kernel(const EjfArgs a) {
     extern __shared__ int32_t rows[];
-    __shared__ TileShared<BLOCK> sh;
+    __shared__ TileShared<BLOCK, CP> sh;
     __shared__ AcceptLds ka;
     __shared__ int64_t s_tile;
     __shared__ uint64_t s_red[3][BLOCK / 64];
