@@ -296,6 +296,8 @@ struct AcceptLds {
                               // step's last new value, that value's again
     int64_t eoff[kMaxMotif];  // element offset of further join key e
     int32_t eqcol[kMaxMotif]; // the input column it must equal
+    int32_t e0;               // first further key to test (1: the first one holds by
+                              // construction, the candidates being its run)
 };
 
 // Stage the step's constants (threads 0..kMaxMotif-1; a barrier follows before use).
@@ -308,6 +310,8 @@ __device__ __forceinline__ void accept_lds_fill(const EjfArgs& a, AcceptLds& k) 
         k.noff[t] = nn > 0 ? (int64_t)st.new_pos[t < nn ? t : nn - 1] * ts : 0;
         k.eoff[t] = t < st.n_eq ? (int64_t)st.eq_pos[t] * ts : 0;
         k.eqcol[t] = t < st.n_eq ? st.eq_col[t] : 0;
+        if (t == 0)
+            k.e0 = (st.motif >= 0 && st.n_eq > 0 && a.tbl.pair_offs && a.tbl.sorted_by == st.eq_pos[0] + 1) ? 1 : 0;
     }
 }
 
@@ -329,7 +333,7 @@ __device__ __forceinline__ bool ejf_accept_flat(const EjfArgs& a, const AcceptLd
         const int32_t* tb = a.tbl.base + (int64_t)m * a.tbl.rstride;
 #pragma unroll
         for (int t = 0; t < NV; t++) nv[t] = tb[k.noff[t]];
-        for (int e = 0; e < st.n_eq; e++) ok &= tb[k.eoff[e]] == my[k.eqcol[e]];
+        for (int e = k.e0; e < st.n_eq; e++) ok &= tb[k.eoff[e]] == my[k.eqcol[e]];
         bool hit = false;
 #pragma unroll
         for (int t = 0; t < NV; t++) hit |= bl.maybe(nv[t]);
@@ -545,7 +549,7 @@ __device__ __forceinline__ bool ejf_tile_cp(const EjfArgs& a, const AcceptLds& k
     tile_offsets<BLOCK>(a, tile, n_tiles, sh, surv);
     if (sh.total == 0) return true;
     const int64_t base = sh.base + sh.wexcl[wid];
-    const int64_t os = a.out_stride, ts = a.tbl.stride;
+    const int64_t os = a.out_stride;
     int64_t cand_acc = 0;
     int32_t pre = 0;
     for (int j = 0; j < nch; j++) {
@@ -558,23 +562,20 @@ __device__ __forceinline__ bool ejf_tile_cp(const EjfArgs& a, const AcceptLds& k
                 const int32_t m = c + sh.cp.mdelta[w0 + r];
                 const int32_t* prow = rows + (w0 + r) * RS;
                 const int32_t* tb = a.tbl.base + (int64_t)m * a.tbl.rstride;
+                int32_t nv[NV];
+#pragma unroll
+                for (int t = 0; t < NV; t++) nv[t] = tb[ka.noff[t]];
                 int32_t* dst = a.out + orow;
-                for (int cc = 0; cc < c_in; cc++) dst[(int64_t)cc * os] = prow[cc];
-                for (int t0 = 0; t0 < n_new; t0 += 4) {
-                    int32_t w4[4];
+                for (int cc = 0; cc < c_in; cc++, dst += os) *dst = prow[cc];
 #pragma unroll
-                    for (int q = 0; q < 4; q++)
-                        if (t0 + q < n_new) w4[q] = tb[(int64_t)st.new_pos[t0 + q] * ts];
-#pragma unroll
-                    for (int q = 0; q < 4; q++)
-                        if (t0 + q < n_new) dst[(int64_t)(c_in + t0 + q) * os] = w4[q];
-                }
+                for (int t = 0; t < NV; t++)
+                    if (t < n_new) dst[t * os] = nv[t];
                 if (a.next_cand) {
                     const int nk = a.next_key_col;
                     if (nk < 0) {
                         cand_acc += 1;
                     } else {
-                        const int32_t kv = nk < c_in ? prow[nk] : tb[(int64_t)st.new_pos[nk - c_in] * ts];
+                        const int32_t kv = nk < c_in ? prow[nk] : pick_new(nv, nk - c_in);
                         cand_acc += a.next_offs[kv + 1] - a.next_offs[kv];
                     }
                 }
@@ -794,9 +795,12 @@ __device__ __forceinline__ void ejf_tile(const EjfArgs& a, const AcceptLds* ka, 
             const int32_t m = sh.st.mrow[o];
             int32_t* dst = a.out + orow;
             const int64_t os = a.out_stride;
-            for (int c = 0; c < c_in; c++) {
-                if (LAT) st_out(dst + (int64_t)c * os, prow[c]);
-                else dst[(int64_t)c * os] = prow[c];
+            {
+                int32_t* d = dst;
+                for (int c = 0; c < c_in; c++, d += os) {
+                    if (LAT) st_out(d, prow[c]);
+                    else *d = prow[c];
+                }
             }
             const int32_t* tb = a.tbl.base + (int64_t)m * a.tbl.rstride;
             const int64_t ts = a.tbl.stride;
