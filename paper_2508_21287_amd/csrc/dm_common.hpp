@@ -124,6 +124,11 @@ struct Plan {
     double est_peak_rows_cols = 0;  // max over steps of rows*cols (in + out)
     double est_final_rows = 0;
     double est_cost = 0;            // table values read, tested and written over all steps
+    std::string cache_key;          // its entry in the context's plan cache
+    // whether the streaming sort pass pays for this plan's tables: -1 not yet
+    // known, 1 the last one found its root segments (nearly all) in order,
+    // 0 it did not (the per-segment tiers then take them directly)
+    int32_t sort_stream = -1;
 };
 
 struct NormPattern {

@@ -191,6 +191,7 @@ struct SortLaunch {
     int32_t* max_chunks;  // merge tier: most LDS chunks of any listed segment
     int32_t pass;         // merge tier: pass number of a merge launch
     const uint32_t* abort;// nonzero: a wait of the run gave up; the launch does nothing
+    const uint32_t* todo; // LDS tiers without a list: only items whose bit is set (nullptr = all)
 };
 
 // Packed rows of wp 64-bit words that an LDS tile of lds_bytes holds
@@ -266,6 +267,13 @@ int ejf_block_for(int c_in, int requested);
 hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s);
 // threads: workgroup size, a multiple of 64 up to 1024
 hipError_t launch_sort_lds(const SortLaunch& a, int grid, int threads, int lds_bytes, hipStream_t s);
+// One job's table (n_jobs == 1) in one streaming pass: every kept row written
+// to its place in the output (row-major, pattern order), the bit of each root
+// segment that is out of order set in `unsorted` (one bit per item, counted
+// in *n_unsorted), and duplicate neighbours counted.  The LDS tiers then sort
+// only the flagged segments.  in_cap_rows bounds the grid.
+hipError_t launch_sort_stream(const SortLaunch& a, uint32_t* unsorted, int32_t* n_unsorted, int64_t in_cap_rows, int k,
+                              hipStream_t s);
 // chunk sort + `passes` merge launches + row write for the segments in a.list
 hipError_t launch_sort_merge_tier(const SortLaunch& a, int passes, hipStream_t s);
 // The k (<= kTopkMax, <= n) rows of `table` (row-major, n x width) with the

@@ -116,6 +116,12 @@ class PlanCache {
         std::lock_guard<std::mutex> lk(mu_);
         return map_.size();
     }
+    // what the last sort of the plan's table learned (Plan::sort_stream)
+    void set_sort_stream(const std::string& key, int32_t v) {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = map_.find(key);
+        if (it != map_.end()) it->second.sort_stream = v;
+    }
 
   private:
     size_t max_;

@@ -1560,6 +1560,8 @@ __global__ __launch_bounds__(1024) void sort_lds_kernel(const SortLaunch L) {
     const int64_t n_items = L.list ? (int64_t)*L.list_n : (int64_t)L.n_jobs * L.n_vertices;
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int32_t item = L.list ? L.list[it].item : (int32_t)it;
+        // after the streaming pass: only the segments it found out of order
+        if (L.todo && !((L.todo[item >> 5] >> (item & 31)) & 1u)) continue;
         const int64_t jb = item / L.n_vertices;
         {
             const int32_t* src = (const int32_t*)&L.jobs[jb];
@@ -1614,6 +1616,91 @@ __global__ __launch_bounds__(1024) void sort_lds_kernel(const SortLaunch L) {
             for (int64_t r = tid; r < nw; r += (int)blockDim.x) job.out_cost[seg0 + r] = job.in_cost[seg0 + idx[r]];
         __syncthreads();
     }
+}
+
+// Rows per tile of the streaming pass for k columns (about 16 KB of LDS).
+__host__ __device__ __forceinline__ int stream_tile_rows(int k) { return k <= 16 ? 256 : (k <= 32 ? 128 : 64); }
+
+// The streaming pass over one job's table: tiles of T rows staged column by
+// column (pattern order) in LDS, each row compared with the one before it
+// (the tile's first with the previous tile's last, read again), rows written
+// row-major with coalesced stores.  Neighbours in one root segment that are
+// not strictly increasing flag the segment (its bit, set once) or, when
+// equal, count as a duplicate.
+__global__ __launch_bounds__(256) void sort_stream_kernel(const SortLaunch L, uint32_t* unsorted, int32_t* n_unsorted) {
+    extern __shared__ int32_t tile[];
+    __shared__ SortJob job;
+    const int tid = threadIdx.x, nt = (int)blockDim.x;
+    if (L.abort && *L.abort) return;
+    {
+        const int32_t* src = (const int32_t*)&L.jobs[0];
+        int32_t* dst = (int32_t*)&job;
+        for (int i = tid; i < (int)(sizeof(SortJob) / 4); i += nt) dst[i] = src[i];
+    }
+    __syncthreads();
+    const int k = job.k;
+    const int T = stream_tile_rows(k), cs = T + 1;
+    int32_t* prev = tile + (size_t)k * cs;
+    const int64_t n = clamp_rows(*job.n_in, job.in_cap);
+    const int64_t out_rows = job.out_rows;
+    const int64_t stride = job.in_stride;
+    const int shiftT = T == 256 ? 8 : (T == 128 ? 7 : 6);
+    for (int64_t r0 = (int64_t)blockIdx.x * T; r0 < n; r0 += (int64_t)gridDim.x * T) {
+        const int m = (int)((n - r0 < T) ? (n - r0) : T);
+        for (int e = tid; e < k * T; e += nt) {
+            const int j = e >> shiftT, r = e & (T - 1);
+            if (r < m) tile[j * cs + r] = job.in[(int64_t)job.perm[j] * stride + r0 + r];
+        }
+        if (r0 > 0 && tid < k) prev[tid] = job.in[(int64_t)job.perm[tid] * stride + r0 - 1];
+        __syncthreads();
+        for (int r = tid; r < m; r += nt) {
+            if (r0 + r == 0) continue;
+            const int32_t root = tile[r];
+            if ((r > 0 ? tile[r - 1] : prev[0]) != root) continue;  // first row of its segment
+            int c = 0;
+            for (int j = 1; j < k && c == 0; j++) {
+                const int32_t a = r > 0 ? tile[j * cs + r - 1] : prev[j], b = tile[j * cs + r];
+                c = a < b ? -1 : (a > b ? 1 : 0);
+            }
+            if (c == 0) {
+                atomicAdd(L.dup_count, 1);
+            } else if (c > 0) {
+                const int32_t item = root - L.v_begin;
+                const uint32_t bit = 1u << (item & 31);
+                if (!(__hip_atomic_load(&unsorted[item >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
+                    if (!(atomicOr(&unsorted[item >> 5], bit) & bit)) atomicAdd(n_unsorted, 1);
+            }
+        }
+        const int64_t left = out_rows - r0;
+        const int nw = left <= 0 ? 0 : (left < m ? (int)left : m);
+        {
+            int32_t* dst = job.out + r0 * k;
+            const int dr = nt / k, dj = nt - dr * k;
+            int r = tid / k, j = tid - r * k;
+            for (int e = tid; e < nw * k; e += nt) {
+                dst[e] = tile[j * cs + r];
+                r += dr;
+                j += dj;
+                if (j >= k) {
+                    j -= k;
+                    r++;
+                }
+            }
+        }
+        if (job.out_cost)
+            for (int r = tid; r < nw; r += nt) job.out_cost[r0 + r] = job.in_cost[r0 + r];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_sort_stream(const SortLaunch& a, uint32_t* unsorted, int32_t* n_unsorted, int64_t in_cap_rows, int k,
+                              hipStream_t s) {
+    const int T = stream_tile_rows(k);
+    const size_t lds = sizeof(int32_t) * ((size_t)k * (T + 1) + (size_t)k);
+    const int64_t tiles = (std::max<int64_t>(in_cap_rows, 1) + T - 1) / T;
+    const int grid = (int)std::min<int64_t>(tiles, 4096);
+    hipLaunchKernelGGL(sort_stream_kernel, dim3(grid), dim3(256), lds, s, a, unsorted, n_unsorted);
+    return hipGetLastError();
 }
 
 // ---- merge tier, for segments larger than the largest LDS tile --------------

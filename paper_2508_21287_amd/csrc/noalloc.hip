@@ -99,7 +99,9 @@ dm_status scratch_workspace(DeviceScratch& d, dm_context* ctx, int32_t nv, int k
     const int64_t spill = (int64_t)nv + 1;
     w.spill = (SegRef*)(d.ptr + off);
     w.spill_cap = spill;
-    off = align256(off + sizeof(SegRef) * 2 * (size_t)spill);
+    off += sizeof(SegRef) * 2 * (size_t)spill;
+    w.spill_bits = (uint32_t*)(d.ptr + off);
+    off = align256(off + sizeof(uint32_t) * (size_t)((spill + 31) / 32));
     if (off + 4096 > kScratchBytes) return fail(DM_ERR_BUDGET_EXCEEDED, "data graph too large for the fixed scratch");
     // rows r: index scratch (2r + 2) uint32 + two tables of r x k int32,
     // and r / 64 + 2 look-back words per step

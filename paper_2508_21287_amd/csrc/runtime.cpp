@@ -117,6 +117,8 @@ void Workspace::release() {
     tickets = nullptr;
     ctrl_d = nullptr;
     spill = nullptr;
+    spill_bits = nullptr;
+    spill_cap = 0;
     sort_scratch = nullptr;
     if (stream) (void)hipStreamSynchronize(stream);
     if (ctrl_h) (void)hipHostFree(ctrl_h);
@@ -181,9 +183,12 @@ dm_status Workspace::ensure_spill(int64_t n) {
     if (fixed) return fixed_full("the sort's segment lists");
     dev_free(ctx, spill, stream);
     spill = nullptr;
+    spill_bits = nullptr;
     int64_t c = std::max<int64_t>(n, 1024);
-    DM_TRY(dev_alloc(ctx, (void**)&spill, sizeof(SegRef) * 2 * (size_t)c, stream));
+    DM_TRY(dev_alloc(ctx, (void**)&spill, sizeof(SegRef) * 2 * (size_t)c + sizeof(uint32_t) * (size_t)((c + 31) / 32),
+                     stream));
     spill_cap = c;
+    spill_bits = (uint32_t*)(spill + 2 * c);
     return DM_OK;
 }
 
@@ -264,9 +269,12 @@ static int ejf_grid(int64_t in_cap, double est_in, int block) {
     return (int)std::max<int64_t>(g, 1);
 }
 
+// Mean root-segment rows up to which the plain sort takes the streaming pass.
+constexpr int64_t kStreamSegRows = 256;
+
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
                        int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
-                       int32_t* host_word, hipEvent_t* prof, bool* merged) {
+                       int32_t* host_word, hipEvent_t* prof, bool* merged, int32_t stream_k) {
     if (merged) *merged = false;
     hipStream_t s = ws.stream;
     const int64_t items = (int64_t)n_jobs * nv;
@@ -290,7 +298,16 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.list = nullptr;
     L.spill = ws.spill;
     L.spill_n = &counters[0];
-    DM_HIP(launch_sort_lds(L, (int)std::min<int64_t>(std::max<int64_t>(items, 1), 65536), 256, L.lds_bytes, s));
+    int64_t grid1 = std::min<int64_t>(std::max<int64_t>(items, 1), 65536);
+    if (n_jobs == 1 && stream_k > 0) {
+        // one table: a streaming pass writes every row in place and flags the
+        // root segments out of order; tier 1 visits the flagged ones only
+        DM_HIP(launch_fill_i32((int32_t*)ws.spill_bits, 0, (items + 31) / 32, s));
+        DM_HIP(launch_sort_stream(L, ws.spill_bits, &counters[4], max_in_cap, stream_k, s));
+        L.todo = ws.spill_bits;
+    }
+    DM_HIP(launch_sort_lds(L, (int)grid1, 256, L.lds_bytes, s));
+    L.todo = nullptr;
     // tier 2: the largest LDS allocation a workgroup can hold; one such
     // workgroup fills a CU, so it takes the largest block
     L.lds_bytes = ctx->sort_lds_max;
@@ -564,6 +581,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         const int64_t fin_cap = fin_table ? zc_rows : cap[lb];
         const int64_t n_final = std::min<int64_t>(c.counts[nsteps], fin_cap);
         bool sort_merged = false;  // the merge tier ran (its launches are timed apart from the LDS tiers)
+        bool sort_streamed = false;  // the streaming pass ran
         if (!hash_mode && opt.sort) {
             // canonicalize into a row-major table of exactly the kept rows
             // (a scored run sorts every row: its cap selects by cost afterwards)
@@ -601,9 +619,14 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
             DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps], s));
+            // the streaming pass: for small root segments (where a workgroup
+            // per segment costs more than its rows), unless the last sort of
+            // this plan found its segments out of order
+            const bool stream = plan.sort_stream != 0 && n_final <= kStreamSegRows * (int64_t)(v1 - v0);
             DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, n_final, job.wp, ws.ctrl_d->sort_counters,
                                 &ws.ctrl_d->abort, &ws.ctrl_h->sort_counters[1],
-                                opt.profile ? &ws.prof[2 * nsteps + 1] : nullptr, &sort_merged));
+                                opt.profile ? &ws.prof[2 * nsteps + 1] : nullptr, &sort_merged, stream ? k : 0));
+            sort_streamed = stream;
             if (ws.ev[1]) DM_HIP(hipEventRecord(ws.ev[1], s));
             DM_HIP(hipMemcpyAsync(ws.ctrl_h->sort_counters, ws.ctrl_d->sort_counters, sizeof(c.sort_counters),
                                   hipMemcpyDeviceToHost, s));
@@ -613,6 +636,11 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             DM_TRY(check_abort(c.abort, c.diag, "sort"));
         }
         if (c.sort_counters[3] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached the canonical table");
+        if (sort_streamed && !plan.cache_key.empty()) {
+            // keep the streaming pass while at most 1/16 of the segments need the tiers after it
+            const int32_t hint = 16 * (int64_t)c.sort_counters[4] <= (int64_t)(v1 - v0) ? 1 : 0;
+            if (hint != plan.sort_stream) ctx->plans.set_sort_stream(plan.cache_key, hint);
+        }
         float ms = 0;
         if (ws.ev[0] && ws.ev[1]) (void)hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]);
         o.stats.device_ms = ms;
@@ -655,7 +683,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
                 (void)hipEventElapsedTime(&t, ws.prof[2 * nsteps], ws.prof[2 * nsteps + 1]);
                 if (sort_merged) (void)hipEventElapsedTime(&tm, ws.prof[2 * nsteps + 2], ws.prof[2 * nsteps + 3]);
                 o.stats.sort_ms = t + tm;
-                o.stats.sort_launches = sort_merged ? 3 : 2;
+                o.stats.sort_launches = (sort_merged ? 3 : 2) + (sort_streamed ? 2 : 0);  // + the pass, its flags' clear
             }
         }
         if (hash_mode) {
@@ -1888,6 +1916,7 @@ dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_o
         if (plan_pattern(p, 0, avail & ~drop, &dg->stats, &alt, &err) == DM_OK && alt.est_cost < plan->est_cost)
             *plan = std::move(alt);
     }
+    plan->cache_key = key;
     ctx->plans.put(std::move(key), *plan);
     return DM_OK;
 }

@@ -45,7 +45,7 @@ struct Control {
     int64_t counts[kMaxSteps + 2];
     int32_t overflow[kMaxSteps + 2];
     uint64_t hash[4];
-    int32_t sort_counters[4];  // sort tiers: spill_n[2], max_chunks, dup
+    int32_t sort_counters[6];  // sort tiers: spill_n[2], max_chunks, dup, segments the streaming pass flagged, pad
     uint32_t abort;            // WaitCtl::abort of the run
     uint32_t pad_;
     WaitDiag diag;             // WaitCtl::diag of the run
@@ -67,6 +67,7 @@ struct Workspace {
     Control* ctrl_h = nullptr;    // pinned host mirror
     SegRef* spill = nullptr;      // 2 lists of n_vertices entries (sort tier hand-over)
     int64_t spill_cap = 0;
+    uint32_t* spill_bits = nullptr;  // spill_cap bits after the lists: segments left to sort
     uint32_t* sort_scratch = nullptr;
     int64_t sort_scratch_elems = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -255,7 +256,7 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
 // tier; *merged tells whether it ran.
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
                        int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
-                       int32_t* host_word, hipEvent_t* prof = nullptr, bool* merged = nullptr);
+                       int32_t* host_word, hipEvent_t* prof = nullptr, bool* merged = nullptr, int32_t stream_k = 0);
 
 dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan);
 // zero layout costs for a data graph that has none set yet
