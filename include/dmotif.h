@@ -390,7 +390,8 @@ typedef struct {
     /* filled when dm_plan_opts.profile = 1 (HIP events around each launch): */
     int32_t join_launches;    /* expand-join-filter kernel launches */
     int32_t sort_launches;
-    double join_ms;           /* summed device time of the join launches */
+    double join_ms;           /* device time from the first join launch's start to the last one's end
+                                 (one event pair: the kernel boundaries between them are included) */
     double sort_ms;           /* summed device time of the canonicalization launches */
     int64_t join_bytes;       /* algorithmic bytes of the join launches (4 * (c_in*n_in + c_out*n_out)) */
     int64_t sort_bytes;       /* algorithmic bytes of the sort (8 * width * rows) */

@@ -940,11 +940,12 @@ hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s) {
     const int c = a.st.c_in;
     block = ejf_block_for(c, block);
     const size_t lds = sizeof(int32_t) * (size_t)block * row_stride(c);
-#define DM_EJF_LAUNCH(NV, SC, CP)                                                                          \
-    switch (block) {                                                                                       \
-        case 64: hipLaunchKernelGGL((ejf_kernel<64, NV, SC, CP>), dim3(grid), dim3(64), lds, s, a); break;    \
-        case 128: hipLaunchKernelGGL((ejf_kernel<128, NV, SC, CP>), dim3(grid), dim3(128), lds, s, a); break; \
-        default: hipLaunchKernelGGL((ejf_kernel<256, NV, SC, CP>), dim3(grid), dim3(256), lds, s, a); break;  \
+#define DM_EJF_GO(B, NV, SC, CP) hipLaunchKernelGGL((ejf_kernel<B, NV, SC, CP>), dim3(grid), dim3(B), lds, s, a);
+#define DM_EJF_LAUNCH(NV, SC, CP)                  \
+    switch (block) {                               \
+        case 64: DM_EJF_GO(64, NV, SC, CP) break;   \
+        case 128: DM_EJF_GO(128, NV, SC, CP) break; \
+        default: DM_EJF_GO(256, NV, SC, CP) break;  \
     }
 #define DM_EJF_LAUNCH_CP(NV)      \
     if (cp) {                     \
@@ -977,6 +978,7 @@ hipError_t launch_ejf(const EjfArgs& a, int block, int grid, hipStream_t s) {
         DM_EJF_LAUNCH_CP(kMaxMotif)
     }
 #undef DM_EJF_LAUNCH_CP
+#undef DM_EJF_GO
 #undef DM_EJF_LAUNCH
     return hipGetLastError();
 }

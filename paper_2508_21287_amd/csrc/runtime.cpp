@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <functional>
 
@@ -23,6 +24,16 @@ dm_status hip_fail(hipError_t e, const char* what) {
     return e == hipErrorOutOfMemory ? DM_ERR_OUT_OF_MEMORY : DM_ERR_DEVICE;
 }
 
+// Return every cached block to the pool (on the context's stream).
+static void flush_blocks(const dm_context* ctx) {
+    BlockCache& bc = ctx->blocks;
+    std::lock_guard<std::mutex> lk(bc.mu);
+    for (auto& b : bc.bins)
+        for (void* q : b.second) (void)hipFreeAsync(q, ctx->stream);
+    bc.bins.clear();
+    bc.cached = 0;
+}
+
 dm_status dev_alloc(const dm_context* ctx, void** p, size_t bytes, hipStream_t s) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
@@ -32,7 +43,54 @@ dm_status dev_alloc(const dm_context* ctx, void** p, size_t bytes, hipStream_t s
                                                        std::to_string(bytes) + " bytes");
         return DM_OK;
     }
+    const bool cacheable = ctx && bytes <= BlockCache::kMaxBlock;
+    if (cacheable) {
+        BlockCache& bc = ctx->blocks;
+        const size_t cls = BlockCache::size_class(bytes);
+        {
+            std::lock_guard<std::mutex> lk(bc.mu);
+            auto it = bc.bins.find(cls);
+            if (it != bc.bins.end() && !it->second.empty()) {
+                bool ok = true;
+                if (s != ctx->stream) {
+                    // the block was freed in the context stream's order: this
+                    // stream waits for everything enqueued there so far
+                    if (!bc.ev) ok = hipEventCreateWithFlags(&bc.ev, hipEventDisableTiming) == hipSuccess;
+                    ok = ok && hipEventRecord(bc.ev, ctx->stream) == hipSuccess &&
+                         hipStreamWaitEvent(s, bc.ev, 0) == hipSuccess;
+                    if (!ok) (void)hipGetLastError();
+                }
+                if (ok) {
+                    *p = it->second.back();
+                    it->second.pop_back();
+                    bc.cached -= cls;
+                    bc.live[*p] = cls;
+                    return DM_OK;
+                }
+            }
+        }
+        hipError_t e = hipMallocAsync(p, cls, s);
+        if (e != hipSuccess) {
+            // the cache may hold what the pool lacks: give it back and retry once
+            (void)hipGetLastError();
+            flush_blocks(ctx);
+            e = hipMallocAsync(p, cls, s);
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return hip_fail(e, "hipMallocAsync");
+        }
+        std::lock_guard<std::mutex> lk(bc.mu);
+        bc.live[*p] = cls;
+        return DM_OK;
+    }
     hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e != hipSuccess && ctx) {
+        (void)hipGetLastError();
+        flush_blocks(ctx);
+        e = hipMallocAsync(p, bytes, s);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
@@ -43,8 +101,26 @@ dm_status dev_alloc(const dm_context* ctx, void** p, size_t bytes, hipStream_t s
 
 void dev_free(const dm_context* ctx, void* p, hipStream_t s) {
     if (!p) return;
-    if (ctx && ctx->has_alloc) ctx->alloc.free(p, (void*)s, ctx->alloc.user);
-    else (void)hipFreeAsync(p, s);
+    if (ctx && ctx->has_alloc) {
+        ctx->alloc.free(p, (void*)s, ctx->alloc.user);
+        return;
+    }
+    if (ctx) {
+        BlockCache& bc = ctx->blocks;
+        std::lock_guard<std::mutex> lk(bc.mu);
+        auto it = bc.live.find(p);
+        if (it != bc.live.end()) {
+            const size_t cls = it->second;
+            bc.live.erase(it);
+            // kept for reuse only when freed in the order of the context's stream
+            if (s == ctx->stream && bc.cached + cls <= BlockCache::kMaxCached) {
+                bc.bins[cls].push_back(p);
+                bc.cached += cls;
+                return;
+            }
+        }
+    }
+    (void)hipFreeAsync(p, s);
 }
 
 WaitCtl wait_ctl(const dm_context* ctx, uint32_t* abort, WaitDiag* diag, int64_t limit_us) {
@@ -436,8 +512,12 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         }
     }
 
+    // profiling: events 0/1 around the join launches (one span: a marker
+    // between dependent launches would cost more than the boundary it
+    // measures), 2/3 around the LDS sort tiers, 4/5 around the merge tier
+    const int first_launch = zc0 ? 1 : 0;
     if (opt.profile) {
-        while (ws.prof.size() < (size_t)(2 * nsteps + 4)) {
+        while (ws.prof.size() < (size_t)6) {
             hipEvent_t e;
             DM_HIP(hipEventCreate(&e));
             ws.prof.push_back(e);
@@ -461,7 +541,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             if (i == 0 && zc0) {
                 if (full_range) DM_HIP(launch_fill_u64((uint64_t*)&ws.ctrl_d->counts[1], (uint64_t)zc_rows, 1, s));
                 else DM_HIP(launch_slice_rows(zc_offs, v0, v1, &ws.ctrl_d->counts[1], &ws.ctrl_d->slice_row0, s));
-                if (opt.profile) {
+                if (opt.profile && nsteps == 1) {
                     DM_HIP(hipEventRecord(ws.prof[0], s));
                     DM_HIP(hipEventRecord(ws.prof[1], s));
                 }
@@ -508,10 +588,10 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             for (int c = 0; c < k; c++) a.pv[c] = (uint8_t)std::max(plan.pv_of[c], 0);
             const double est_in = i == 0 ? (double)(v1 - v0) : est[i - 1];
             const int64_t in_cap = i == 0 ? (int64_t)(v1 - v0) : a.in_cap;
-            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * i], s));
             const int blk = ejf_block_for(a.st.c_in, block);
+            if (opt.profile && i == first_launch) DM_HIP(hipEventRecord(ws.prof[0], s));
             DM_HIP(launch_ejf(a, blk, ejf_grid(in_cap, est_in, blk), s));
-            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * i + 1], s));
+            if (opt.profile && i == nsteps - 1) DM_HIP(hipEventRecord(ws.prof[1], s));
             if (sync_mode && !(last && hash_mode)) {
                 DM_HIP(hipMemcpyAsync(ws.ctrl_h, ws.ctrl_d, sizeof(Control), hipMemcpyDeviceToHost, s));
                 DM_HIP(hipStreamSynchronize(s));
@@ -618,20 +698,24 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             sort_pack_layout(k, dg->n, &job);
             for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
             DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
-            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2 * nsteps], s));
+            if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2], s));
             // the streaming pass: for small root segments (where a workgroup
             // per segment costs more than its rows), unless the last sort of
             // this plan found its segments out of order
             const bool stream = plan.sort_stream != 0 && n_final <= kStreamSegRows * (int64_t)(v1 - v0);
             DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, n_final, job.wp, ws.ctrl_d->sort_counters,
                                 &ws.ctrl_d->abort, &ws.ctrl_h->sort_counters[1],
-                                opt.profile ? &ws.prof[2 * nsteps + 1] : nullptr, &sort_merged, stream ? k : 0));
+                                opt.profile ? &ws.prof[3] : nullptr, &sort_merged, stream ? k : 0));
             sort_streamed = stream;
             if (ws.ev[1]) DM_HIP(hipEventRecord(ws.ev[1], s));
-            DM_HIP(hipMemcpyAsync(ws.ctrl_h->sort_counters, ws.ctrl_d->sort_counters, sizeof(c.sort_counters),
+            // the sort counters, the abort word and its diagnosis: adjacent in Control, one copy
+            static_assert(offsetof(Control, abort) == offsetof(Control, sort_counters) + sizeof(Control::sort_counters),
+                          "Control: abort must follow sort_counters");
+            static_assert(offsetof(Control, diag) == offsetof(Control, abort) + 2 * sizeof(uint32_t),
+                          "Control: diag must follow abort");
+            DM_HIP(hipMemcpyAsync(ws.ctrl_h->sort_counters, ws.ctrl_d->sort_counters,
+                                  offsetof(Control, diag) + sizeof(WaitDiag) - offsetof(Control, sort_counters),
                                   hipMemcpyDeviceToHost, s));
-            DM_HIP(hipMemcpyAsync(&ws.ctrl_h->abort, &ws.ctrl_d->abort, sizeof(uint32_t) + sizeof(uint32_t) +
-                                  sizeof(WaitDiag), hipMemcpyDeviceToHost, s));
             DM_HIP(hipStreamSynchronize(s));
             DM_TRY(check_abort(c.abort, c.diag, "sort"));
         }
@@ -668,20 +752,16 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
         }
         o.stats.bytes_moved = bytes;
         if (opt.profile) {
-            double jm = 0;
-            for (int i = 0; i < nsteps; i++) {
-                float t = 0;
-                (void)hipEventElapsedTime(&t, ws.prof[2 * i], ws.prof[2 * i + 1]);
-                jm += t;
-            }
+            float jm = 0;
+            (void)hipEventElapsedTime(&jm, ws.prof[0], ws.prof[1]);
             o.stats.join_ms = jm;
-            o.stats.join_launches = nsteps - (zc0 ? 1 : 0);
+            o.stats.join_launches = nsteps - first_launch;
             if (!hash_mode && opt.sort) {
                 // the LDS tiers, plus the merge tier when it ran (not the host
                 // round trip that decided it)
                 float t = 0, tm = 0;
-                (void)hipEventElapsedTime(&t, ws.prof[2 * nsteps], ws.prof[2 * nsteps + 1]);
-                if (sort_merged) (void)hipEventElapsedTime(&tm, ws.prof[2 * nsteps + 2], ws.prof[2 * nsteps + 3]);
+                (void)hipEventElapsedTime(&t, ws.prof[2], ws.prof[3]);
+                if (sort_merged) (void)hipEventElapsedTime(&tm, ws.prof[4], ws.prof[5]);
                 o.stats.sort_ms = t + tm;
                 o.stats.sort_launches = (sort_merged ? 3 : 2) + (sort_streamed ? 2 : 0);  // + the pass, its flags' clear
             }
@@ -1006,6 +1086,9 @@ void dm_context_destroy(dm_context* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     ctx->ws.release();
+    flush_blocks(ctx);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->blocks.ev) (void)hipEventDestroy(ctx->blocks.ev);
     if (ctx->cancel) (void)hipHostFree(ctx->cancel);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;

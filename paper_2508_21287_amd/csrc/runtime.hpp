@@ -130,6 +130,32 @@ struct DataGraph;
 
 }  // namespace dm
 
+namespace dm {
+// Device blocks freed on the context's own stream, kept for the next
+// allocation of the same size class: on that stream stream order makes the
+// reuse safe; another stream (a server's worker) first waits for an event
+// recorded on the context stream at that point.  A result and its release
+// then cost no memory-pool round trip.  Blocks of up to kMaxBlock bytes,
+// kMaxCached bytes in all.
+struct BlockCache {
+    static constexpr size_t kMaxBlock = (size_t)256 << 20;
+    static constexpr size_t kMaxCached = (size_t)1 << 30;
+    std::mutex mu;
+    hipEvent_t ev = nullptr;  // recorded on the context stream before a block moves to another stream
+    std::unordered_map<size_t, std::vector<void*>> bins;  // size class -> free blocks
+    std::unordered_map<void*, size_t> live;               // blocks handed out from a class
+    size_t cached = 0;
+    // the class of a request: 4 KiB, else rounded up to a quarter of its power of two
+    static size_t size_class(size_t bytes) {
+        if (bytes <= 4096) return 4096;
+        size_t p = 1;
+        while ((p << 1) <= bytes) p <<= 1;
+        const size_t step = p >> 2;
+        return (bytes + step - 1) / step * step;
+    }
+};
+}  // namespace dm
+
 struct dm_context {
     int32_t device = 0;
     hipStream_t stream = nullptr;
@@ -141,6 +167,7 @@ struct dm_context {
     dm::Workspace ws;
     int32_t sort_lds_max = 0;
     dm::PlanCache plans;  // by (pattern, motif set, table statistics)
+    mutable dm::BlockCache blocks;  // default-pool blocks freed on `stream`
 };
 
 struct dm_datagraph {
