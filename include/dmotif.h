@@ -421,16 +421,16 @@ dm_status dm_result_summaries(dm_result* const* rs, int32_t n, dm_result_summary
  * entries are skipped); the array itself stays the caller's. */
 void dm_result_free_many(dm_result* const* rs, int32_t n);
 
-/* Served form: a request loop that keeps the data graph resident, groups
- * queued queries into batches by predicted intermediate-table memory, and
- * runs the batches continuously on several streams so that their work
- * overlaps on the device.  A query predicted to build more than 128 MiB of
- * tables is large: it runs in a batch of its own, through the per-step
- * launches; with two or more streams the first one takes only small queries
- * (from anywhere in the queue), so they never wait behind large ones.  A
- * query whose predicted kept rows exceed 8 x mem_budget is refused at
- * admission (DM_ERR_BUDGET_EXCEEDED from dm_server_wait); one that passes
- * the budget while it runs fails the same way. */
+/* Served form: a request loop that keeps the data graph resident and runs
+ * queries continuously on several streams (one worker each), in arrival
+ * order, so that up to n_streams of them overlap on the device.  A query
+ * predicted to build at most 4 MiB of intermediate tables is tiny: it takes
+ * the tiny queries queued right behind it into one batch (one persistent
+ * launch, at most max_batch queries and 32 MiB of predicted tables); every
+ * other query runs alone through the per-step launches.  A query whose
+ * predicted kept rows exceed 8 x mem_budget is refused at admission
+ * (DM_ERR_BUDGET_EXCEEDED from dm_server_wait); one that passes the budget
+ * while it runs fails the same way. */
 typedef struct {
     int32_t n_streams;       /* concurrent batches in flight (default 2) */
     int32_t max_batch;       /* patterns per batch launch (default 64) */
@@ -448,6 +448,15 @@ dm_status dm_server_submit(dm_server* s, const dm_graph_desc* gp, int64_t max_em
 /* Wait up to timeout_ms (<0 = forever) for a ticket; DM_ERR_TIMEOUT if not done.
  * On DM_OK the caller owns *out.  A query's own failure is returned here. */
 dm_status dm_server_wait(dm_server* s, uint64_t ticket, int32_t timeout_ms, dm_result** out);
+/* Wait up to timeout_ms (<0 = forever) for any submitted query to finish
+ * (in completion order; tickets already taken by dm_server_wait are passed
+ * over); DM_ERR_TIMEOUT if none does.  On DM_OK, *ticket names the query and
+ * *status is its own outcome: DM_OK with *out owned by the caller, or the
+ * query's failure (e.g. DM_ERR_BUDGET_EXCEEDED) with *out NULL and the message
+ * in dm_last_error().  One blocking call per completion: a caller collecting
+ * results needs no polling. */
+dm_status dm_server_wait_any(dm_server* s, int32_t timeout_ms, uint64_t* ticket, dm_result** out,
+                             dm_status* status);
 /* Stop accepting, finish in-flight work, free the server. */
 dm_status dm_server_stop(dm_server* s);
 

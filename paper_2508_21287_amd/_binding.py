@@ -137,7 +137,7 @@ EXPORTS = [
     "dm_result_total",
     "dm_result_width", "dm_result_device_data", "dm_result_hash", "dm_result_copy_to_host",
     "dm_result_copy_to_device", "dm_result_stats", "dm_result_free", "dm_result_summaries",
-    "dm_result_free_many", "dm_server_start", "dm_server_submit", "dm_server_wait", "dm_server_stop",
+    "dm_result_free_many", "dm_server_start", "dm_server_submit", "dm_server_wait", "dm_server_wait_any", "dm_server_stop",
 ]
 
 
@@ -206,6 +206,8 @@ def lib() -> C.CDLL:
             "dm_server_start": (C.c_int, [vp, C.POINTER(ServerOpts), C.POINTER(vp)]),
             "dm_server_submit": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_int64, C.POINTER(C.c_uint64)]),
             "dm_server_wait": (C.c_int, [vp, C.c_uint64, C.c_int32, C.POINTER(vp)]),
+            "dm_server_wait_any": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_uint64), C.POINTER(vp),
+                                             C.POINTER(C.c_int32)]),
             "dm_server_stop": (C.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
@@ -621,6 +623,15 @@ class Server:
         h = C.c_void_p()
         _check(lib().dm_server_wait(self._h, C.c_uint64(ticket), int(timeout_ms), C.byref(h)))
         return Result(h, self.dg.ctx)
+
+    def wait_any(self, timeout_ms: int = -1):
+        """``dm_server_wait_any``: (ticket, Result or None, status) of the next
+        query to finish; status is the query's own code (0 = OK)."""
+        h = C.c_void_p()
+        t = C.c_uint64()
+        st = C.c_int32()
+        _check(lib().dm_server_wait_any(self._h, int(timeout_ms), C.byref(t), C.byref(h), C.byref(st)))
+        return t.value, (Result(h, self.dg.ctx) if st.value == 0 else None), st.value
 
     def stop(self):
         if self._h:

@@ -692,9 +692,10 @@ extern "C" dm_status dm_autotune_motifs(dm_context* ctx, const dm_graph_desc* gd
 
 namespace {
 
-// Queries whose predicted tables exceed this are large: they leave the
-// small lane to small queries.
-constexpr int64_t kServeSmallBytes = (int64_t)128 << 20;
+// Queries whose predicted tables stay within this are tiny: consecutive tiny
+// queries share one batch of at most kServeTinyBatchBytes predicted tables.
+constexpr int64_t kServeTinyBytes = (int64_t)4 << 20;
+constexpr int64_t kServeTinyBatchBytes = (int64_t)32 << 20;
 
 struct Request {
     uint64_t ticket = 0;
@@ -702,7 +703,7 @@ struct Request {
     std::vector<int32_t> edges;
     int64_t cap = -1;
     int64_t est_bytes = 0;
-    bool large = false;  // predicted tables above the small lane's limit
+    bool tiny = false;   // predicted tables within kServeTinyBytes: may share a batch
     bool done = false;
     dm_status status = DM_OK;
     std::string err;
@@ -721,64 +722,40 @@ struct dm_server {
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Request>> queue;
     std::unordered_map<uint64_t, std::shared_ptr<Request>> live;
+    std::deque<uint64_t> completed;  // finished tickets in completion order (dm_server_wait_any)
     uint64_t next_ticket = 1;
     int32_t inflight = 0;
     bool stopping = false;
 };
 
-// Each worker owns one stream + workspace.  It takes the requests at the head
-// of the queue (up to max_batch, their predicted tables within the memory
-// budget) and runs them as one batch; while that batch is on the GPU, the
-// other workers take newly arrived requests and run them on their own
-// streams, so batches overlap on the device.  A request predicted to need
-// more than an eighth of the budget runs as a batch of its own, so short
-// queries never wait inside a long one's batch.  Every query runs within the
-// budget, so the server holds at most n_streams x mem_budget of tables.
+// Each worker owns one stream + workspace and takes work from the head of
+// the queue, so queries start in arrival order and up to n_streams of them
+// overlap on the device (one query's host round trips and launch gaps are
+// filled by another's kernels).  A tiny query (predicted tables up to
+// kServeTinyBytes) takes the tiny ones queued right behind it into the same
+// batch (up to max_batch, kServeTinyBatchBytes of predicted tables): one
+// persistent launch then runs their short chains together.  Every other
+// query runs alone, through the per-step launches, so no query waits inside
+// a longer one's batch.  Every query runs within the budget, so the server
+// holds at most n_streams x mem_budget of tables.
 static void server_worker(dm_server* s, int w) {
     (void)hipSetDevice(s->dg->ctx->device);
     Workspace& ws = *s->ws[w];
-    // with several streams, worker 0 is the small lane: it takes only small
-    // queries (from anywhere in the queue, in arrival order), so they never
-    // wait behind large ones that the other workers run
-    const bool small_lane = s->opts.n_streams > 1 && w == 0;
-    auto has_small = [&] {
-        for (auto& r : s->queue)
-            if (!r->large) return true;
-        return false;
-    };
     for (;;) {
         std::vector<std::shared_ptr<Request>> batch;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            if (small_lane) {
-                s->cv_work.wait(lk, [&] { return s->stopping || has_small(); });
-                if (s->stopping && !has_small()) return;
-                int64_t batch_bytes = 0;
-                for (auto it = s->queue.begin(); it != s->queue.end() && (int32_t)batch.size() < s->opts.max_batch;) {
-                    auto& r = *it;
-                    if (r->large) {
-                        ++it;
-                        continue;
-                    }
-                    if (!batch.empty() && batch_bytes + r->est_bytes > s->opts.mem_budget) break;
-                    batch_bytes += r->est_bytes;
-                    s->inflight++;
-                    batch.push_back(r);
-                    it = s->queue.erase(it);
-                }
-            } else {
-                s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
-                if (s->queue.empty() && s->stopping) return;
-                int64_t batch_bytes = 0;
-                while (!s->queue.empty() && (int32_t)batch.size() < s->opts.max_batch) {
-                    auto& r = s->queue.front();
-                    if (!batch.empty() && (r->large || batch_bytes + r->est_bytes > s->opts.mem_budget)) break;
-                    batch_bytes += r->est_bytes;
-                    s->inflight++;
-                    batch.push_back(r);
-                    s->queue.pop_front();
-                    if (batch.back()->large) break;
-                }
+            s->cv_work.wait(lk, [&] { return s->stopping || !s->queue.empty(); });
+            if (s->queue.empty() && s->stopping) return;
+            int64_t batch_bytes = 0;
+            while (!s->queue.empty() && (int32_t)batch.size() < s->opts.max_batch) {
+                auto& r = s->queue.front();
+                if (!batch.empty() && (!r->tiny || batch_bytes + r->est_bytes > kServeTinyBatchBytes)) break;
+                batch_bytes += r->est_bytes;
+                s->inflight++;
+                batch.push_back(r);
+                s->queue.pop_front();
+                if (!batch.back()->tiny) break;
             }
         }
         std::vector<dm_graph_desc> gps;
@@ -794,8 +771,11 @@ static void server_worker(dm_server* s, int w) {
         run_opts.output_mode = DM_OUT_TABLE;
         run_opts.mem_budget = s->opts.mem_budget;
         run_opts.result_mb = (int32_t)std::min<int64_t>(std::max<int64_t>(s->opts.mem_budget >> 20, 1), INT32_MAX);
-        dm_status st = enumerate_many(s->dg, ws, (int32_t)batch.size(), gps.data(), caps.data(), &run_opts,
-                                      outs.data());
+        // a query alone takes the plain path (per-step launches); tiny ones share the persistent launch
+        dm_status st = (batch.size() == 1 && !batch[0]->tiny)
+                           ? enumerate_one(s->dg, ws, &gps[0], caps[0], &run_opts, &outs[0])
+                           : enumerate_many(s->dg, ws, (int32_t)batch.size(), gps.data(), caps.data(), &run_opts,
+                                            outs.data());
         std::string err = st == DM_OK ? std::string() : std::string(dm_last_error());
         if (st != DM_OK && batch.size() > 1) {
             // isolate the failing request(s): run them one by one
@@ -828,6 +808,7 @@ static void server_worker(dm_server* s, int w) {
                 r->result = r->status == DM_OK ? outs[i] : nullptr;
                 if (r->status != DM_OK && outs[i]) dm_result_free(outs[i]);
                 r->done = true;
+                s->completed.push_back(r->ticket);
                 s->inflight--;
             }
         }
@@ -902,7 +883,7 @@ dm_status dm_server_submit(dm_server* s, const dm_graph_desc* gp, int64_t max_em
             est *= std::min(1.0, std::max(roots, 64.0) / nv);
         }
         r->est_bytes = (int64_t)std::max(1.0, std::min(est, (double)s->opts.mem_budget));
-        r->large = est > (double)kServeSmallBytes;
+        r->tiny = est <= (double)kServeTinyBytes;
         // refused at admission: a result predicted far beyond the budget it
         // would run within (the prediction can be off by a few times, so
         // only beyond 8x; the rest run and are refused if they pass it)
@@ -920,11 +901,12 @@ dm_status dm_server_submit(dm_server* s, const dm_graph_desc* gp, int64_t max_em
     s->live[r->ticket] = r;
     *ticket = r->ticket;
     if (r->done) {
+        s->completed.push_back(r->ticket);
         s->cv_done.notify_all();
         return DM_OK;
     }
     s->queue.push_back(r);
-    s->cv_work.notify_all();  // the small lane waits only for small queries
+    s->cv_work.notify_one();
     return DM_OK;
 }
 
@@ -944,6 +926,33 @@ dm_status dm_server_wait(dm_server* s, uint64_t ticket, int32_t timeout_ms, dm_r
     s->live.erase(ticket);
     if (r->status != DM_OK) return fail(r->status, r->err);
     *out = r->result;
+    return DM_OK;
+}
+
+dm_status dm_server_wait_any(dm_server* s, int32_t timeout_ms, uint64_t* ticket, dm_result** out,
+                             dm_status* status) {
+    if (!s || !ticket || !out || !status) return fail(DM_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    *ticket = 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    // tickets already taken by dm_server_wait are passed over
+    auto ready = [&] {
+        while (!s->completed.empty() && !s->live.count(s->completed.front())) s->completed.pop_front();
+        return !s->completed.empty();
+    };
+    if (timeout_ms < 0) {
+        s->cv_done.wait(lk, ready);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
+        return fail(DM_ERR_TIMEOUT, "no request finished");
+    }
+    const uint64_t t = s->completed.front();
+    s->completed.pop_front();
+    auto r = s->live[t];
+    s->live.erase(t);
+    *ticket = t;
+    *status = r->status;
+    if (r->status == DM_OK) *out = r->result;
+    else set_error(r->err);
     return DM_OK;
 }
 

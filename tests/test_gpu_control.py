@@ -198,3 +198,31 @@ def test_datagraph_busy_while_served(ctx):
     srv.wait(t, 60000).free()
     srv.stop()
     dg.free()
+
+
+def test_server_wait_any(ctx):
+    # completions collected in completion order with one blocking call each;
+    # a ticket taken by wait() first is passed over by wait_any()
+    g, pats = W.config2(10)
+    dg = ctx.datagraph(g.n, g.edges)
+    srv = dm.Server(dg, n_streams=2, max_batch=4)
+    tickets = {srv.submit(p.n, p.edges): p for p in pats}
+    first = next(iter(tickets))
+    r0 = srv.wait(first, 60000)
+    want, _ = oracle.enumerate_embeddings(g.n, g.edges, tickets[first].n, tickets[first].edges)
+    assert np.array_equal(r0.to_numpy(), want)
+    r0.free()
+    seen = {first}
+    while len(seen) < len(tickets):
+        t, r, code = srv.wait_any(60000)
+        assert code == 0 and t in tickets and t not in seen, (t, code)
+        seen.add(t)
+        p = tickets[t]
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+        assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
+        r.free()
+    with pytest.raises(dm.DMError) as ei:
+        srv.wait_any(0)
+    assert ei.value.code == -10  # DM_ERR_TIMEOUT: nothing left
+    srv.stop()
+    dg.free()
