@@ -55,8 +55,9 @@ TRAFFIC_PROFILES = {"ejf_kernel": os.path.join(ROOT, "profiles", "ejf_kernel_con
 
 
 def measured_traffic(kernel):
-    """HBM bytes per dispatch of `kernel` from its committed counter summary,
-    or None when it is missing or the kernel source has changed since."""
+    """HBM bytes per launch of `kernel` (as the roofline counts launches) from
+    its committed counter summary, or None when it is missing, gives none, or
+    the kernel source has changed since."""
     import hashlib
     try:
         txt = open(TRAFFIC_PROFILES[kernel]).read()
@@ -70,9 +71,9 @@ def measured_traffic(kernel):
     src = os.path.join(ROOT, "paper_2508_21287_amd", "csrc", "kernels.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if vals.get("kernels_hip_sha256") != sha or "traffic_bytes_per_dispatch" not in vals:
+    if vals.get("kernels_hip_sha256") != sha or "traffic_bytes_per_launch" not in vals:
         return None
-    return float(vals["traffic_bytes_per_dispatch"])
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def parse():
