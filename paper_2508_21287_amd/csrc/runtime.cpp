@@ -350,7 +350,7 @@ constexpr int64_t kStreamSegRows = 256;
 
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
                        int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
-                       int32_t* host_word, hipEvent_t* prof, bool* merged, int32_t stream_k) {
+                       int32_t* host_word, hipEvent_t* prof, bool* merged, int32_t stream_k, bool* merge_later) {
     if (merged) *merged = false;
     hipStream_t s = ws.stream;
     const int64_t items = (int64_t)n_jobs * nv;
@@ -394,25 +394,44 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     DM_HIP(launch_sort_lds(L, 256, 1024, L.lds_bytes, s));
     // tier 3: chunks of the tier-2 tile, merged pairwise.  No segment
     // outgrows the tier-2 tile when no table has more rows than it holds;
-    // else the number of segments tier 2 passed on is read back first, and
-    // the chunk, merge and gather launches run only when there are any.
+    // else the number of segments tier 2 passed on decides: read back here,
+    // or, with merge_later, by the caller with its own readback (then
+    // enqueue_sort_merge runs the tier when there are any).
     if (prof) DM_HIP(hipEventRecord(prof[0], s));
     const int64_t r_min = std::max(lds_rows_of(L.lds_bytes, max_wp), 1);
-    if (max_in_cap <= r_min) return DM_OK;
+    if (merge_later) *merge_later = max_in_cap > r_min;
+    if (max_in_cap <= r_min || merge_later) return DM_OK;
     DM_HIP(hipMemcpyAsync(host_word, &counters[1], sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DM_HIP(hipStreamSynchronize(s));
     if (*host_word == 0) return DM_OK;
     if (merged) *merged = true;
-    if (prof) DM_HIP(hipEventRecord(prof[1], s));
+    return enqueue_sort_merge(ctx, ws, jobs_d, n_jobs, nv, v0, max_in_cap, max_wp, counters, abort,
+                              prof ? prof + 1 : nullptr);
+}
+
+dm_status enqueue_sort_merge(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
+                             int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
+                             hipEvent_t* prof) {
+    hipStream_t s = ws.stream;
+    SortLaunch L;
+    std::memset(&L, 0, sizeof L);
+    L.jobs = jobs_d;
+    L.n_jobs = n_jobs;
+    L.n_vertices = nv;
+    L.v_begin = v0;
+    L.dup_count = &counters[3];
+    L.max_chunks = &counters[2];
+    L.abort = abort;
+    L.lds_bytes = ctx->sort_lds_max;
+    const int64_t r_min = std::max(lds_rows_of(L.lds_bytes, max_wp), 1);
+    if (prof) DM_HIP(hipEventRecord(prof[0], s));
     L.list = ws.spill + ws.spill_cap;
     L.list_n = &counters[1];
-    L.spill = nullptr;
-    L.spill_n = nullptr;
     const int64_t chunks = (std::max<int64_t>(max_in_cap, 1) + r_min - 1) / r_min;
     int passes = 0;
     while (((int64_t)1 << passes) < chunks) passes++;
     DM_HIP(launch_sort_merge_tier(L, passes, s));
-    if (prof) DM_HIP(hipEventRecord(prof[2], s));
+    if (prof) DM_HIP(hipEventRecord(prof[1], s));
     return DM_OK;
 }
 
@@ -703,9 +722,11 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             // per segment costs more than its rows), unless the last sort of
             // this plan found its segments out of order
             const bool stream = plan.sort_stream != 0 && n_final <= kStreamSegRows * (int64_t)(v1 - v0);
+            // the merge tier's need is read back with the counters below
+            bool merge_pending = false;
             DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, n_final, job.wp, ws.ctrl_d->sort_counters,
                                 &ws.ctrl_d->abort, &ws.ctrl_h->sort_counters[1],
-                                opt.profile ? &ws.prof[3] : nullptr, &sort_merged, stream ? k : 0));
+                                opt.profile ? &ws.prof[3] : nullptr, &sort_merged, stream ? k : 0, &merge_pending));
             sort_streamed = stream;
             if (ws.ev[1]) DM_HIP(hipEventRecord(ws.ev[1], s));
             // the sort counters, the abort word and its diagnosis: adjacent in Control, one copy
@@ -713,11 +734,22 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
                           "Control: abort must follow sort_counters");
             static_assert(offsetof(Control, diag) == offsetof(Control, abort) + 2 * sizeof(uint32_t),
                           "Control: diag must follow abort");
-            DM_HIP(hipMemcpyAsync(ws.ctrl_h->sort_counters, ws.ctrl_d->sort_counters,
-                                  offsetof(Control, diag) + sizeof(WaitDiag) - offsetof(Control, sort_counters),
-                                  hipMemcpyDeviceToHost, s));
+            const size_t tail = offsetof(Control, diag) + sizeof(WaitDiag) - offsetof(Control, sort_counters);
+            DM_HIP(hipMemcpyAsync(ws.ctrl_h->sort_counters, ws.ctrl_d->sort_counters, tail, hipMemcpyDeviceToHost, s));
             DM_HIP(hipStreamSynchronize(s));
             DM_TRY(check_abort(c.abort, c.diag, "sort"));
+            if (merge_pending && c.sort_counters[1] > 0) {
+                // segments beyond the largest LDS tile: the merge tier, then the counters again
+                DM_TRY(enqueue_sort_merge(ctx, ws, ws.job_d, 1, v1 - v0, v0, n_final, job.wp,
+                                          ws.ctrl_d->sort_counters, &ws.ctrl_d->abort,
+                                          opt.profile ? &ws.prof[4] : nullptr));
+                sort_merged = true;
+                if (ws.ev[1]) DM_HIP(hipEventRecord(ws.ev[1], s));
+                DM_HIP(hipMemcpyAsync(ws.ctrl_h->sort_counters, ws.ctrl_d->sort_counters, tail,
+                                      hipMemcpyDeviceToHost, s));
+                DM_HIP(hipStreamSynchronize(s));
+                DM_TRY(check_abort(c.abort, c.diag, "sort"));
+            }
         }
         if (c.sort_counters[3] != 0) return fail(DM_ERR_INTERNAL, "duplicate rows reached the canonical table");
         if (sort_streamed && !plan.cache_key.empty()) {

@@ -283,7 +283,13 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
 // tier; *merged tells whether it ran.
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
                        int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
-                       int32_t* host_word, hipEvent_t* prof = nullptr, bool* merged = nullptr, int32_t stream_k = 0);
+                       int32_t* host_word, hipEvent_t* prof = nullptr, bool* merged = nullptr, int32_t stream_k = 0,
+                       bool* merge_later = nullptr);
+// The merge tier over the segments tier 2 passed on (counters[1] of them,
+// nonzero), for a caller that took enqueue_sort's merge_later.
+dm_status enqueue_sort_merge(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
+                             int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
+                             hipEvent_t* prof);
 
 dm_status plan_for(const dm_datagraph* dg, const NormPattern& p, const dm_plan_opts* opts, Plan* plan);
 // zero layout costs for a data graph that has none set yet
