@@ -294,6 +294,29 @@ dm_status dm_autotune_motifs(dm_context* ctx, const dm_graph_desc* gd, int32_t n
                              const dm_graph_desc* sample, const uint32_t* candidates, int32_t n_candidates,
                              int32_t reps, uint32_t* best_mask, double* ms_per_candidate);
 
+/* Launch shape of the batched form's persistent join launch. */
+typedef struct {
+    int32_t block_threads;   /* workgroup size: 64, 128 or 256 */
+    int32_t grid;            /* workgroups of the launch */
+    int32_t backoff;         /* most s_sleep pauses between two polls of an idle scheduler wave */
+    int32_t reserved;
+    double ms;               /* median time of one batched call on the sample */
+} dm_batch_tuning;
+
+/* Autotuner of the batched form (Sec. IV-C: parallelism across join-filter
+ * operations): times dm_enumerate_batch on `sample` (count+hash mode, `reps`
+ * calls per candidate) for each launch shape that fits the sample's widest
+ * step: block sizes of 256/128/64 threads as the row width allows, grids of
+ * 0.75x to 1.5x one 256-thread workgroup per CU (capped at what can be
+ * resident), idle-poll backoffs of 7, 15 and 31 pauses.  The fastest shape is kept on the data graph and used by its
+ * later batched calls (and server batches) whose widest step it fits; other
+ * calls keep the defaults.  *best receives it; tried (may be NULL) receives
+ * up to tried_cap candidates with their medians, *n_tried how many were run.
+ * Synchronous on the context stream.  Errors: DM_ERR_INVALID_ARG, and any
+ * error of the batched calls (the data graph then keeps its previous shape). */
+dm_status dm_autotune_batch(dm_datagraph* dg, int32_t n_sample, const dm_graph_desc* sample, int32_t reps,
+                            dm_batch_tuning* best, dm_batch_tuning* tried, int32_t tried_cap, int32_t* n_tried);
+
 /* Planner only (host, no device work): decompose a pattern with the motifs
  * in `motif_mask` (Sec. III-C) and serialize the plan into `buf` as int32:
  *   [k, n_steps, col_of[k] (pattern vertex -> table column), then per step:

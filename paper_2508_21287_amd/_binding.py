@@ -110,6 +110,12 @@ class RunStats(C.Structure):
                 ("join_bytes", C.c_int64), ("sort_bytes", C.c_int64)]
 
 
+class BatchTuning(C.Structure):
+    """``dm_batch_tuning``: launch shape of the batched form."""
+    _fields_ = [("block_threads", C.c_int32), ("grid", C.c_int32), ("backoff", C.c_int32),
+                ("reserved", C.c_int32), ("ms", C.c_double)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("n_streams", C.c_int32), ("max_batch", C.c_int32), ("mem_budget", C.c_int64),
                 ("max_queue", C.c_int32)]
@@ -132,7 +138,7 @@ EXPORTS = [
     "dm_version", "dm_last_error", "dm_context_create", "dm_context_destroy", "dm_context_cancel",
     "dm_datagraph_build",
     "dm_datagraph_free", "dm_datagraph_save", "dm_datagraph_load", "dm_datagraph_set_costs",
-    "dm_result_device_costs", "dm_result_copy_costs", "dm_autotune_motifs", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
+    "dm_result_device_costs", "dm_result_copy_costs", "dm_autotune_motifs", "dm_autotune_batch", "dm_datagraph_query", "dm_datagraph_copy_csr", "dm_datagraph_copy_motif", "dm_plan",
     "dm_estimate", "dm_enumerate", "dm_enumerate_noalloc", "dm_enumerate_batch", "dm_result_rows",
     "dm_result_total",
     "dm_result_width", "dm_result_device_data", "dm_result_hash", "dm_result_copy_to_host",
@@ -171,6 +177,9 @@ def lib() -> C.CDLL:
             "dm_datagraph_build": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_uint32, C.POINTER(vp)]),
             "dm_datagraph_free": (C.c_int, [vp]),
             "dm_datagraph_save": (C.c_int, [vp, C.c_char_p]),
+            "dm_autotune_batch": (C.c_int, [vp, C.c_int32, C.POINTER(GraphDesc), C.c_int32,
+                                            C.POINTER(BatchTuning), C.POINTER(BatchTuning), C.c_int32,
+                                            C.POINTER(C.c_int32)]),
             "dm_autotune_motifs": (C.c_int, [vp, C.POINTER(GraphDesc), C.c_int32, C.POINTER(GraphDesc),
                                              C.POINTER(C.c_uint32), C.c_int32, C.c_int32, C.POINTER(C.c_uint32),
                                              C.POINTER(C.c_double)]),
@@ -587,6 +596,24 @@ class DataGraph:
             C.cast(outs.ctypes.data, C.POINTER(C.c_void_p))))
         del keep  # the call copied the patterns
         return [Result(C.c_void_p(int(h)), self.ctx) for h in outs[:n].tolist()]
+
+    def autotune_batch(self, patterns, reps: int = 3) -> tuple[dict, list[dict]]:
+        """``dm_autotune_batch``: time the batched call on `patterns` for each
+        launch shape and keep the fastest on this data graph; returns (best,
+        tried) as dicts of block_threads, grid, backoff, ms."""
+        descs, keep = _desc_array(patterns)
+        n = len(descs)
+        best = BatchTuning()
+        tried = (BatchTuning * 64)()
+        nt = C.c_int32()
+        _check(lib().dm_autotune_batch(self._h, n, C.cast(descs.ctypes.data, C.POINTER(GraphDesc)) if n else None,
+                                       int(reps), C.byref(best), tried, 64, C.byref(nt)))
+        del keep
+
+        def as_dict(t):
+            return {"block_threads": t.block_threads, "grid": t.grid, "backoff": t.backoff, "ms": t.ms}
+
+        return as_dict(best), [as_dict(tried[i]) for i in range(min(nt.value, 64))]
 
     def free(self):
         if self._h:

@@ -105,8 +105,10 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     int total_steps = 0, cmax = 1, max_k = 1, max_wp = 1;
     for (auto& it : items)
         for (auto& d : it.steps) cmax = std::max(cmax, (int)d.c_in);
-    const int block = batch_block_for(cmax, env_int("DMOTIF_BATCH_BLOCK", 0));
-    const int grid = batch_grid_for(block, cmax, env_int("DMOTIF_BATCH_GRID", 0));
+    // the tuned launch shape when this batch's widest step fits it, else the defaults
+    const bool tuned = dg->batch_block > 0 && cmax <= dg->batch_max_cols;
+    const int block = batch_block_for(cmax, tuned ? dg->batch_block : 0);
+    const int grid = batch_grid_for(block, cmax, tuned && block == dg->batch_block ? dg->batch_grid : 0);
     int64_t heap0 = 0, words0 = 0;
     std::vector<int64_t> h_off(nb), w_off(nb), rows0(nb);
     for (int p = 0; p < nb; p++) {
@@ -272,7 +274,7 @@ static dm_status run_batch(dm_datagraph* dg, Workspace& ws, std::vector<Item>& i
     bd.words_top = (unsigned long long*)(A + off_tops) + 1;
     bd.row_limit = row_limit;
     bd.n_patterns = nb;
-    bd.max_backoff = env_int("DMOTIF_BATCH_BACKOFF", 15);
+    bd.max_backoff = tuned && dg->batch_backoff > 0 ? dg->batch_backoff : 15;
     bd.w = wait_ctl(ctx, (uint32_t*)&misc[5], (WaitDiag*)(A + off_diag), opts ? opts->wait_limit_us : 0);
     bd.tiles_done = (uint32_t*)&misc[6];
     const double t_stage = ms_since(t0);
@@ -685,6 +687,87 @@ extern "C" dm_status dm_autotune_motifs(dm_context* ctx, const dm_graph_desc* gd
         }
     }
     *best_mask = candidates[best_i];
+    return DM_OK;
+}
+
+// ------------------------------------------------------------------ launch-shape tuning
+
+extern "C" dm_status dm_autotune_batch(dm_datagraph* dg, int32_t n_sample, const dm_graph_desc* sample,
+                                       int32_t reps, dm_batch_tuning* best, dm_batch_tuning* tried,
+                                       int32_t tried_cap, int32_t* n_tried) {
+    if (!dg || n_sample <= 0 || !sample || reps <= 0 || !best || (tried_cap > 0 && !tried))
+        return fail(DM_ERR_INVALID_ARG, "invalid tuning arguments");
+    DM_HIP(hipSetDevice(dg->ctx->device));
+    // the sample's widest step decides which block sizes can run it
+    int cmax = 1;
+    for (int32_t i = 0; i < n_sample; i++) {
+        NormPattern p;
+        std::string err;
+        dm_status st = normalize_pattern(&sample[i], &p, &err);
+        if (st != DM_OK) return fail(st, "sample pattern " + std::to_string(i) + ": " + err);
+        if (p.k > dg->n) continue;
+        Plan plan;
+        DM_TRY(plan_for(dg, p, nullptr, &plan));
+        for (auto& s : plan.steps) cmax = std::max(cmax, (int)s.d.c_in);
+    }
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dg->ctx->device);
+    const int widest = batch_block_for(cmax, 0);
+    std::vector<dm_batch_tuning> cand;
+    for (int block : {256, 128, 64}) {
+        if (block > widest) continue;
+        for (double per_cu : {0.75, 1.0, 1.25, 1.5})
+            for (int backoff : {15, 7, 31}) {
+                dm_batch_tuning c{};
+                c.block_threads = block;
+                c.grid = std::max(1, (int)(per_cu * cus * (256 / block)));
+                c.backoff = backoff;
+                cand.push_back(c);
+            }
+    }
+    const int32_t old_block = dg->batch_block, old_grid = dg->batch_grid, old_backoff = dg->batch_backoff,
+                  old_cols = dg->batch_max_cols;
+    auto restore = [&]() {
+        dg->batch_block = old_block;
+        dg->batch_grid = old_grid;
+        dg->batch_backoff = old_backoff;
+        dg->batch_max_cols = old_cols;
+    };
+    dm_plan_opts opts;
+    std::memset(&opts, 0, sizeof opts);
+    opts.output_mode = DM_OUT_COUNT_HASH;
+    std::vector<dm_result*> outs((size_t)n_sample, nullptr);
+    int best_i = -1;
+    int32_t run = 0;
+    for (size_t ci = 0; ci < cand.size(); ci++) {
+        dm_batch_tuning& c = cand[ci];
+        dg->batch_block = c.block_threads;
+        dg->batch_grid = c.grid;
+        dg->batch_backoff = c.backoff;
+        dg->batch_max_cols = cmax;
+        std::vector<double> t;
+        for (int32_t r = 0; r < reps; r++) {
+            const auto t0 = std::chrono::steady_clock::now();
+            dm_status st = enumerate_many(dg, dg->ctx->ws, n_sample, sample, nullptr, &opts, outs.data());
+            for (auto*& o : outs) dm_result_free(o), o = nullptr;
+            if (st != DM_OK) {
+                restore();
+                return st;
+            }
+            t.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        std::sort(t.begin(), t.end());
+        c.ms = t[t.size() / 2];
+        if (run < tried_cap) tried[run] = c;
+        run++;
+        if (best_i < 0 || c.ms < cand[best_i].ms) best_i = (int)ci;
+    }
+    if (n_tried) *n_tried = run;
+    *best = cand[best_i];
+    dg->batch_block = best->block_threads;
+    dg->batch_grid = best->grid;
+    dg->batch_backoff = best->backoff;
+    dg->batch_max_cols = cmax;
     return DM_OK;
 }
 

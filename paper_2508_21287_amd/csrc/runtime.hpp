@@ -189,6 +189,8 @@ struct dm_datagraph {
     double build_ms = 0;
     std::vector<int32_t> host_row_ptr;  // CSR offsets read back at ingest (the degree sequence)
     std::atomic<int32_t> servers{0};    // servers started on this graph and not yet stopped
+    // batched form's launch shape chosen by dm_autotune_batch (0 = the defaults)
+    int32_t batch_block = 0, batch_grid = 0, batch_backoff = 0, batch_max_cols = 0;
 
     dm::GraphDev graph_dev() const {
         dm::GraphDev g;

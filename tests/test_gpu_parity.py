@@ -617,6 +617,25 @@ def test_autotune_motifs(ctx):
         ctx.autotune_motifs(g.n, g.edges, [], cands)
 
 
+def test_autotune_batch(ctx):
+    # launch shapes timed on a sample; later batched calls on the data graph
+    # run with the fastest and answer like the oracle
+    g, pats = W.config2(24)
+    dg = ctx.datagraph(g.n, g.edges)
+    specs = [(p.n, p.edges) for p in pats]
+    best, tried = dg.autotune_batch(specs[:12], reps=2)
+    assert best["block_threads"] in (64, 128, 256) and best["grid"] > 0 and best["ms"] > 0, best
+    assert len(tried) >= 6 and min(t["ms"] for t in tried) == best["ms"], tried
+    res = dg.enumerate_batch(specs)
+    for p, r in zip(pats, res):
+        want, total = oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)
+        assert r.total == total and np.array_equal(r.to_numpy(), want), p.name
+        r.free()
+    with pytest.raises(dm.DMError):
+        dg.autotune_batch([], reps=1)
+    dg.free()
+
+
 def test_cell_motif_wide_steps(ctx):
     # M18-O-6 adds up to 17 columns in one step: the wide join instantiation,
     # plain and batched, against the oracle
