@@ -345,8 +345,6 @@ static int ejf_grid(int64_t in_cap, double est_in, int block) {
     return (int)std::max<int64_t>(g, 1);
 }
 
-// Mean root-segment rows up to which the plain sort takes the streaming pass.
-constexpr int64_t kStreamSegRows = 256;
 
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
                        int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
@@ -718,10 +716,9 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
             DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2], s));
-            // the streaming pass: for small root segments (where a workgroup
-            // per segment costs more than its rows), unless the last sort of
-            // this plan found its segments out of order
-            const bool stream = plan.sort_stream != 0 && n_final <= kStreamSegRows * (int64_t)(v1 - v0);
+            // the streaming pass, unless the last sort of this plan found its
+            // segments out of order (then the per-segment tiers take them directly)
+            const bool stream = plan.sort_stream != 0;
             // the merge tier's need is read back with the counters below
             bool merge_pending = false;
             DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, n_final, job.wp, ws.ctrl_d->sort_counters,
