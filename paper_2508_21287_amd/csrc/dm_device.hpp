@@ -191,7 +191,10 @@ struct SortLaunch {
     int32_t* max_chunks;  // merge tier: most LDS chunks of any listed segment
     int32_t pass;         // merge tier: pass number of a merge launch
     const uint32_t* abort;// nonzero: a wait of the run gave up; the launch does nothing
-    const uint32_t* todo; // LDS tiers without a list: only items whose bit is set (nullptr = all)
+    const uint32_t* todo; // LDS tiers without a list: only items whose word equals todo_epoch (nullptr = all)
+    uint32_t todo_epoch;  // the streaming pass sets the words of the segments it finds out of order to this
+    int32_t pad_;
+    SortJob one;          // the job when `jobs` is nullptr (one table, passed with the launch)
 };
 
 // Packed rows of wp 64-bit words that an LDS tile of lds_bytes holds
@@ -294,6 +297,8 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 // *row0 = offs[v0], *n = offs[v1] - offs[v0]: the rows of keys [v0, v1) of a motif table
 hipError_t launch_slice_rows(const int32_t* offs, int32_t v0, int32_t v1, int64_t* n, int64_t* row0, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// p[0..n) = 0 except p[at] = v
+hipError_t launch_clear_set_u64(uint64_t* p, int64_t n, int64_t at, uint64_t v, hipStream_t s);
 hipError_t launch_iota_i32(int32_t* p, int32_t start, int64_t n, hipStream_t s);
 hipError_t launch_offsets(const int32_t* key, const int64_t* n_rows, int64_t rows_cap, int32_t n_vertices,
                           int32_t* offs, hipStream_t s);
@@ -304,8 +309,21 @@ hipError_t launch_gather_cols(const int32_t* in, int64_t in_stride, const int64_
 // graph ingest
 hipError_t launch_ingest_count(const int32_t* edges, int64_t m, int32_t n, int32_t* deg, int32_t* err,
                                hipStream_t s);
+// look-back words tagged with `epoch` (words of other epochs read as not
+// ready, so nothing is cleared first); the tile ticket is tickets[epoch]
 hipError_t launch_scan_i32(const int32_t* in, int32_t* out_excl, int64_t n, int64_t* total,
-                           uint64_t* status, uint64_t* ticket, const WaitCtl& w, hipStream_t s);
+                           uint64_t* status, uint64_t* tickets, uint32_t epoch, const WaitCtl& w, hipStream_t s);
+// up to kHostGather device ranges (sizes in bytes, multiples of 4, 4-byte
+// aligned) into pinned host memory, one launch
+constexpr int kHostGather = 6;
+struct HostGather {
+    const void* src[kHostGather];
+    void* dst[kHostGather];
+    int64_t bytes[kHostGather];
+    int32_t n;
+    int32_t pad_;
+};
+hipError_t launch_gather_to_host(const HostGather& g, hipStream_t s);
 // edges with an endpoint outside [0, n) are skipped (ingest_count flags them)
 hipError_t launch_ingest_scatter(const int32_t* edges, int64_t m, int32_t n, const int32_t* ptr, int32_t* cursor,
                                  int32_t* tmp, hipStream_t s);

@@ -1563,10 +1563,10 @@ __global__ __launch_bounds__(1024) void sort_lds_kernel(const SortLaunch L) {
     for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int32_t item = L.list ? L.list[it].item : (int32_t)it;
         // after the streaming pass: only the segments it found out of order
-        if (L.todo && !((L.todo[item >> 5] >> (item & 31)) & 1u)) continue;
+        if (L.todo && L.todo[item] != L.todo_epoch) continue;
         const int64_t jb = item / L.n_vertices;
         {
-            const int32_t* src = (const int32_t*)&L.jobs[jb];
+            const int32_t* src = L.jobs ? (const int32_t*)&L.jobs[jb] : (const int32_t*)&L.one;
             int32_t* dst = (int32_t*)&job;
             for (int i = tid; i < (int)(sizeof(SortJob) / 4); i += (int)blockDim.x) dst[i] = src[i];
         }
@@ -1635,7 +1635,7 @@ __global__ __launch_bounds__(256) void sort_stream_kernel(const SortLaunch L, ui
     const int tid = threadIdx.x, nt = (int)blockDim.x;
     if (L.abort && *L.abort) return;
     {
-        const int32_t* src = (const int32_t*)&L.jobs[0];
+        const int32_t* src = L.jobs ? (const int32_t*)&L.jobs[0] : (const int32_t*)&L.one;
         int32_t* dst = (int32_t*)&job;
         for (int i = tid; i < (int)(sizeof(SortJob) / 4); i += nt) dst[i] = src[i];
     }
@@ -1667,10 +1667,11 @@ __global__ __launch_bounds__(256) void sort_stream_kernel(const SortLaunch L, ui
             if (c == 0) {
                 atomicAdd(L.dup_count, 1);
             } else if (c > 0) {
+                // the segment's word takes this pass's epoch; the first to set it counts it
                 const int32_t item = root - L.v_begin;
-                const uint32_t bit = 1u << (item & 31);
-                if (!(__hip_atomic_load(&unsorted[item >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
-                    if (!(atomicOr(&unsorted[item >> 5], bit) & bit)) atomicAdd(n_unsorted, 1);
+                const uint32_t ep = L.todo_epoch;
+                if (__hip_atomic_load(&unsorted[item], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ep)
+                    if (atomicExch(&unsorted[item], ep) != ep) atomicAdd(n_unsorted, 1);
             }
         }
         const int64_t left = out_rows - r0;
@@ -2046,6 +2047,11 @@ __global__ void fill_u64_kernel(uint64_t* p, uint64_t v, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+// zeros, except p[at] = v
+__global__ void clear_set_u64_kernel(uint64_t* p, int64_t n, int64_t at, uint64_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = i == at ? v : 0ull;
+}
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -2065,6 +2071,11 @@ static int grid_for(int64_t n, int block, int max_grid = 4096) {
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_clear_set_u64(uint64_t* p, int64_t n, int64_t at, uint64_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(clear_set_u64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, at, v);
     return hipGetLastError();
 }
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
@@ -2145,7 +2156,7 @@ hipError_t launch_ingest_count(const int32_t* edges, int64_t m, int32_t n, int32
 constexpr int kScanBlock = 256, kScanItems = 4;
 __global__ __launch_bounds__(kScanBlock) void scan_i32_kernel(const int32_t* in, int32_t* out, int64_t n,
                                                               int64_t* total, uint64_t* status, uint64_t* ticket,
-                                                              const WaitCtl wc) {
+                                                              uint32_t epoch, const WaitCtl wc) {
     constexpr int NW = kScanBlock / 64;
     constexpr int TILE = kScanBlock * kScanItems;
     __shared__ int64_t s_tile, s_base;
@@ -2194,7 +2205,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_i32_kernel(const int32_t* in,
             // offsets come out smaller than the true ones, so what later
             // kernels index with them stays in bounds until the host sees the
             // abort word and fails the build
-            int64_t excl = lookback_wave(status, 0, tile, (uint64_t)tot, lane, wc, -1, -1);
+            int64_t excl = lookback_wave(status, epoch, tile, (uint64_t)tot, lane, wc, -1, -1);
             if (excl < 0) excl = 0;
             if (lane == 0) {
                 s_base = excl;
@@ -2215,10 +2226,33 @@ __global__ __launch_bounds__(kScanBlock) void scan_i32_kernel(const int32_t* in,
 }
 
 hipError_t launch_scan_i32(const int32_t* in, int32_t* out_excl, int64_t n, int64_t* total, uint64_t* status,
-                           uint64_t* ticket, const WaitCtl& w, hipStream_t s) {
+                           uint64_t* tickets, uint32_t epoch, const WaitCtl& w, hipStream_t s) {
     const int64_t tiles = (n + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems);
     hipLaunchKernelGGL(scan_i32_kernel, dim3(grid_for(tiles, 1, 1024)), dim3(kScanBlock), 0, s, in, out_excl, n,
-                       total, status, ticket, w);
+                       total, status, tickets + epoch, epoch, w);
+    return hipGetLastError();
+}
+
+// Several device ranges copied into pinned host memory by one kernel (the
+// stores reach host memory over the fabric; the system-scope fence makes
+// them visible before the kernel completes), in place of one copy each.
+__global__ void gather_to_host_kernel(const HostGather g) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int q = 0; q < g.n; q++) {
+        const uint32_t* src = (const uint32_t*)g.src[q];
+        uint32_t* dst = (uint32_t*)g.dst[q];
+        const int64_t words = g.bytes[q] / 4;
+        for (int64_t i = t0; i < words; i += stride) dst[i] = src[i];
+    }
+    __threadfence_system();
+}
+
+hipError_t launch_gather_to_host(const HostGather& g, hipStream_t s) {
+    int64_t words = 0;
+    for (int q = 0; q < g.n; q++) words = std::max<int64_t>(words, g.bytes[q] / 4);
+    if (words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_to_host_kernel, dim3(grid_for(words, 256, 64)), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 

@@ -101,8 +101,10 @@ dm_status scratch_workspace(DeviceScratch& d, dm_context* ctx, int32_t nv, int k
     w.spill_cap = spill;
     off += sizeof(SegRef) * 2 * (size_t)spill;
     w.spill_bits = (uint32_t*)(d.ptr + off);
-    off = align256(off + sizeof(uint32_t) * (size_t)((spill + 31) / 32));
+    off = align256(off + sizeof(uint32_t) * (size_t)spill);
     if (off + 4096 > kScratchBytes) return fail(DM_ERR_BUDGET_EXCEEDED, "data graph too large for the fixed scratch");
+    // the sort's epoch words: this layout moves with nv, so they start clear on every call
+    DM_HIP(launch_fill_i32((int32_t*)w.spill_bits, 0, spill, w.stream));
     // rows r: index scratch (2r + 2) uint32 + two tables of r x k int32,
     // and r / 64 + 2 look-back words per step
     const size_t left = kScratchBytes - off - 3 * 256;

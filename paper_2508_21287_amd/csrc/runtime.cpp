@@ -261,10 +261,11 @@ dm_status Workspace::ensure_spill(int64_t n) {
     spill = nullptr;
     spill_bits = nullptr;
     int64_t c = std::max<int64_t>(n, 1024);
-    DM_TRY(dev_alloc(ctx, (void**)&spill, sizeof(SegRef) * 2 * (size_t)c + sizeof(uint32_t) * (size_t)((c + 31) / 32),
-                     stream));
+    DM_TRY(dev_alloc(ctx, (void**)&spill, sizeof(SegRef) * 2 * (size_t)c + sizeof(uint32_t) * (size_t)c, stream));
     spill_cap = c;
     spill_bits = (uint32_t*)(spill + 2 * c);
+    // epoch words: zero is no epoch (epochs start at 1)
+    DM_HIP(launch_fill_i32((int32_t*)spill_bits, 0, c, stream));
     return DM_OK;
 }
 
@@ -323,9 +324,10 @@ dm_status Workspace::ensure_sort_scratch(int64_t elems) {
 dm_status Workspace::next_epoch(uint32_t* e) {
     epoch++;
     if (epoch >= kEpochs) {
-        // all epochs used: clear every look-back word and ticket, start over
+        // all epochs used: clear every look-back word, ticket and sort epoch word, start over
         DM_HIP(launch_fill_u64(status, 0, status_cap, stream));
         DM_HIP(launch_fill_u64(tickets, 0, kEpochs, stream));
+        if (spill_bits) DM_HIP(launch_fill_i32((int32_t*)spill_bits, 0, spill_cap, stream));
         epoch = 1;
     }
     *e = epoch;
@@ -348,15 +350,19 @@ static int ejf_grid(int64_t in_cap, double est_in, int block) {
 
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
                        int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
-                       int32_t* host_word, hipEvent_t* prof, bool* merged, int32_t stream_k, bool* merge_later) {
+                       int32_t* host_word, hipEvent_t* prof, bool* merged, int32_t stream_k, bool* merge_later,
+                       const SortJob* one) {
     if (merged) *merged = false;
+    if (one && (n_jobs != 1 || !merge_later))
+        return fail(DM_ERR_INTERNAL, "a sort job passed with the launch takes one table and the deferred merge tier");
     hipStream_t s = ws.stream;
     const int64_t items = (int64_t)n_jobs * nv;
     if (items >= (int64_t)INT32_MAX) return fail(DM_ERR_UNSUPPORTED, "batch too large: patterns x vertices >= 2^31");
     DM_TRY(ws.ensure_spill(items + 1));
     SortLaunch L;
     std::memset(&L, 0, sizeof L);
-    L.jobs = jobs_d;
+    L.jobs = one ? nullptr : jobs_d;
+    if (one) L.one = *one;
     L.n_jobs = n_jobs;
     L.n_vertices = nv;
     L.v_begin = v0;
@@ -374,9 +380,12 @@ dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, in
     L.spill_n = &counters[0];
     int64_t grid1 = std::min<int64_t>(std::max<int64_t>(items, 1), 65536);
     if (n_jobs == 1 && stream_k > 0) {
-        // one table: a streaming pass writes every row in place and flags the
-        // root segments out of order; tier 1 visits the flagged ones only
-        DM_HIP(launch_fill_i32((int32_t*)ws.spill_bits, 0, (items + 31) / 32, s));
+        // one table: a streaming pass writes every row in place and marks the
+        // root segments out of order with a fresh epoch (no clearing launch);
+        // tier 1 visits the marked ones only
+        uint32_t ep = 0;
+        DM_TRY(ws.next_epoch(&ep));
+        L.todo_epoch = ep;
         DM_HIP(launch_sort_stream(L, ws.spill_bits, &counters[4], max_in_cap, stream_k, s));
         L.todo = ws.spill_bits;
     }
@@ -550,14 +559,19 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             for (int b = 0; b < 2; b++) DM_TRY(ws.ensure_cbuf(b, cap[b]));
         int64_t maxcap = std::max<int64_t>(std::max(cap[0], cap[1]), (int64_t)dg->n);
         DM_TRY(ws.ensure_status(maxcap / 64 + 2));
-        DM_HIP(launch_fill_u64((uint64_t*)ws.ctrl_d, 0, sizeof(Control) / 8, s));
+        // the control block starts clear; a step 0 read in place over every
+        // root has its row count set in the same launch
+        if (zc0 && full_range)
+            DM_HIP(launch_clear_set_u64((uint64_t*)ws.ctrl_d, sizeof(Control) / 8,
+                                        (int64_t)(offsetof(Control, counts) / 8 + 1), (uint64_t)zc_rows, s));
+        else
+            DM_HIP(launch_fill_u64((uint64_t*)ws.ctrl_d, 0, sizeof(Control) / 8, s));
         if (ws.ev[0]) DM_HIP(hipEventRecord(ws.ev[0], s));
         bool redo = false;
         for (int i = 0; i < nsteps; i++) {
             const int ib = (i - 1) & 1, ob = i & 1;
             if (i == 0 && zc0) {
-                if (full_range) DM_HIP(launch_fill_u64((uint64_t*)&ws.ctrl_d->counts[1], (uint64_t)zc_rows, 1, s));
-                else DM_HIP(launch_slice_rows(zc_offs, v0, v1, &ws.ctrl_d->counts[1], &ws.ctrl_d->slice_row0, s));
+                if (!full_range) DM_HIP(launch_slice_rows(zc_offs, v0, v1, &ws.ctrl_d->counts[1], &ws.ctrl_d->slice_row0, s));
                 if (opt.profile && nsteps == 1) {
                     DM_HIP(hipEventRecord(ws.prof[0], s));
                     DM_HIP(hipEventRecord(ws.prof[1], s));
@@ -714,16 +728,18 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             job.k = k;
             sort_pack_layout(k, dg->n, &job);
             for (int j = 0; j < k; j++) job.perm[j] = (uint8_t)plan.col_of[j];
-            DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
+            // the job goes with the sort launches (no upload); the merge tier, when
+            // needed, reads it from the device
             if (opt.profile) DM_HIP(hipEventRecord(ws.prof[2], s));
             // the streaming pass, unless the last sort of this plan found its
             // segments out of order (then the per-segment tiers take them directly)
             const bool stream = plan.sort_stream != 0;
             // the merge tier's need is read back with the counters below
             bool merge_pending = false;
-            DM_TRY(enqueue_sort(ctx, ws, ws.job_d, 1, v1 - v0, v0, n_final, job.wp, ws.ctrl_d->sort_counters,
+            DM_TRY(enqueue_sort(ctx, ws, nullptr, 1, v1 - v0, v0, n_final, job.wp, ws.ctrl_d->sort_counters,
                                 &ws.ctrl_d->abort, &ws.ctrl_h->sort_counters[1],
-                                opt.profile ? &ws.prof[3] : nullptr, &sort_merged, stream ? k : 0, &merge_pending));
+                                opt.profile ? &ws.prof[3] : nullptr, &sort_merged, stream ? k : 0, &merge_pending,
+                                &job));
             sort_streamed = stream;
             if (ws.ev[1]) DM_HIP(hipEventRecord(ws.ev[1], s));
             // the sort counters, the abort word and its diagnosis: adjacent in Control, one copy
@@ -737,6 +753,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
             DM_TRY(check_abort(c.abort, c.diag, "sort"));
             if (merge_pending && c.sort_counters[1] > 0) {
                 // segments beyond the largest LDS tile: the merge tier, then the counters again
+                DM_HIP(hipMemcpyAsync(ws.job_d, ws.job_h, sizeof(SortJob), hipMemcpyHostToDevice, s));
                 DM_TRY(enqueue_sort_merge(ctx, ws, ws.job_d, 1, v1 - v0, v0, n_final, job.wp,
                                           ws.ctrl_d->sort_counters, &ws.ctrl_d->abort,
                                           opt.profile ? &ws.prof[4] : nullptr));
@@ -792,7 +809,7 @@ dm_status run_plan(dm_context* ctx, Workspace& ws, const dm_datagraph* dg, const
                 (void)hipEventElapsedTime(&t, ws.prof[2], ws.prof[3]);
                 if (sort_merged) (void)hipEventElapsedTime(&tm, ws.prof[4], ws.prof[5]);
                 o.stats.sort_ms = t + tm;
-                o.stats.sort_launches = (sort_merged ? 3 : 2) + (sort_streamed ? 2 : 0);  // + the pass, its flags' clear
+                o.stats.sort_launches = (sort_merged ? 3 : 2) + (sort_streamed ? 1 : 0);  // + the streaming pass
             }
         }
         if (hash_mode) {
@@ -1255,9 +1272,9 @@ static dm_status build_claw_direct(dm_datagraph* dg) {
         for (int q = 0; q < 4; q++) t.cols[q] = data + (size_t)q * (size_t)t.stride;
         t.offs = offs;
         DM_HIP(launch_claw_count(dg->row_ptr, dg->col, n, j, cnt, s));
-        DM_HIP(launch_fill_u64(ws.status, 0, tiles, s));
-        DM_HIP(launch_fill_u64(ws.tickets, 0, 1, s));
-        DM_HIP(launch_scan_i32(cnt, offs, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets,
+        uint32_t ep = 0;
+        DM_TRY(ws.next_epoch(&ep));
+        DM_HIP(launch_scan_i32(cnt, offs, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets, ep,
                                wait_ctl(ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, 0), s));
         DM_HIP(launch_claw_fill(dg->row_ptr, dg->col, n, j, offs, t.stride, data, s));
     }
@@ -1329,9 +1346,9 @@ static dm_status build_second_copy(dm_datagraph* dg, MotifTable& t) {
         const int64_t tiles = rows / 1024 + 2;
         DM_TRY(ws.ensure_status(tiles));
         DM_HIP(launch_run_flags(sec, rows, L, L - 1, flags, s));
-        DM_HIP(launch_fill_u64(ws.status, 0, tiles, s));
-        DM_HIP(launch_fill_u64(ws.tickets, 0, 1, s));
-        DM_HIP(launch_scan_i32(flags, idx, rows, &ws.ctrl_d->counts[0], ws.status, ws.tickets,
+        uint32_t ep = 0;
+        DM_TRY(ws.next_epoch(&ep));
+        DM_HIP(launch_scan_i32(flags, idx, rows, &ws.ctrl_d->counts[0], ws.status, ws.tickets, ep,
                                wait_ctl(ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, 0), s));
         DM_HIP(launch_run_fill(sec, rows, L, L - 1, flags, idx, t.run_far, t.run_start, s));
         DM_HIP(launch_run_offs(t.offs, dg->n, rows, idx, &ws.ctrl_d->counts[0], t.run_offs, s));
@@ -1410,19 +1427,19 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
         if ((st = dev_alloc(ctx, (void**)&scr, scr_bytes, s))) break;
         {
             char* q = scr;
+            // the arrays that start at zero first, so one fill clears them
             flags = (int32_t*)q, q += 256;
-            d_edges = (int32_t*)q, q += ebytes;
-            tmp = (int32_t*)q, q += ebytes;
             deg = (int32_t*)q, q += vbytes;
             tmp_ptr = (int32_t*)q, q += vbytes;
             cursor = (int32_t*)q, q += vbytes;
             udeg = (int32_t*)q, q += vbytes;
+            d_edges = (int32_t*)q, q += ebytes;
+            tmp = (int32_t*)q, q += ebytes;
             big = (int32_t*)q;
         }
         // the control block (counts, the abort word of the scans' look-backs) starts clear
         if (launch_fill_u64((uint64_t*)ws.ctrl_d, 0, sizeof(Control) / 8, s) ||
-            launch_fill_i32(flags, 0, 16, s) || launch_fill_i32(deg, 0, n + 1, s) ||
-            launch_fill_i32(cursor, 0, n + 1, s) || launch_fill_i32(udeg, 0, n + 1, s)) {
+            launch_fill_i32(flags, 0, (int64_t)((256 + 4 * vbytes) / sizeof(int32_t)), s)) {
             st = fail(DM_ERR_DEVICE, "fill launch failed");
             break;
         }
@@ -1437,9 +1454,9 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
         // exclusive scan of raw degrees -> tmp_ptr
         int64_t tiles = (int64_t)(n + 1) / 1024 + 2;
         if ((st = ws.ensure_status(tiles))) break;
-        (void)launch_fill_u64(ws.status, 0, tiles, s);
-        (void)launch_fill_u64(ws.tickets, 0, 1, s);
-        if (launch_scan_i32(deg, tmp_ptr, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets,
+        uint32_t ep = 0;
+        if ((st = ws.next_epoch(&ep))) break;
+        if (launch_scan_i32(deg, tmp_ptr, n, &ws.ctrl_d->counts[0], ws.status, ws.tickets, ep,
                             wait_ctl(ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, 0), s)) {
             st = fail(DM_ERR_DEVICE, "scan launch failed");
             break;
@@ -1455,9 +1472,8 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
             break;
         }
         if ((st = dev_alloc(ctx, (void**)&dg->row_ptr, sizeof(int32_t) * (size_t)(n + 1), s))) break;
-        (void)launch_fill_u64(ws.status, 0, tiles, s);
-        (void)launch_fill_u64(ws.tickets, 0, 1, s);
-        if (launch_scan_i32(udeg, dg->row_ptr, n, &ws.ctrl_d->counts[1], ws.status, ws.tickets,
+        if ((st = ws.next_epoch(&ep))) break;
+        if (launch_scan_i32(udeg, dg->row_ptr, n, &ws.ctrl_d->counts[1], ws.status, ws.tickets, ep,
                             wait_ctl(ctx, &ws.ctrl_d->abort, &ws.ctrl_d->diag, 0), s)) {
             st = fail(DM_ERR_DEVICE, "scan launch failed");
             break;
@@ -1486,15 +1502,20 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
         const size_t need = off_col + (host_csr ? sizeof(int32_t) * (size_t)emax : 0);
         if ((st = ws.ensure_stage(need))) break;
         char* H = ws.stage_h;
-        bool copied =
-            hipMemcpyAsync(H, &ws.ctrl_d->counts[1], sizeof(int64_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
-            hipMemcpyAsync(H + 64, flags, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
-            hipMemcpyAsync(H + 8, &ws.ctrl_d->abort, sizeof(uint32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
-            hipMemcpyAsync(H + off_rp, dg->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s) ==
-                hipSuccess;
-        if (copied && host_csr)
-            copied = hipMemcpyAsync(H + off_col, dg->col, sizeof(int32_t) * (size_t)emax, hipMemcpyDeviceToHost, s) ==
-                     hipSuccess;
+        HostGather hg;
+        std::memset(&hg, 0, sizeof hg);
+        auto add = [&](const void* src, size_t off, size_t bytes) {
+            hg.src[hg.n] = src;
+            hg.dst[hg.n] = H + off;
+            hg.bytes[hg.n] = (int64_t)bytes;
+            hg.n++;
+        };
+        add(&ws.ctrl_d->counts[1], 0, sizeof(int64_t));
+        add(&ws.ctrl_d->abort, 8, sizeof(uint32_t));
+        add(flags, 64, 16 * sizeof(int32_t));
+        add(dg->row_ptr, off_rp, sizeof(int32_t) * ((size_t)n + 1));
+        if (host_csr) add(dg->col, off_col, sizeof(int32_t) * (size_t)emax);
+        const bool copied = launch_gather_to_host(hg, s) == hipSuccess;
         if (!copied || hipStreamSynchronize(s) != hipSuccess) {
             st = fail(DM_ERR_DEVICE, "ingest readback failed");
             break;

@@ -67,7 +67,7 @@ struct Workspace {
     Control* ctrl_h = nullptr;    // pinned host mirror
     SegRef* spill = nullptr;      // 2 lists of n_vertices entries (sort tier hand-over)
     int64_t spill_cap = 0;
-    uint32_t* spill_bits = nullptr;  // spill_cap bits after the lists: segments left to sort
+    uint32_t* spill_bits = nullptr;  // spill_cap epoch words after the lists: segments left to sort
     uint32_t* sort_scratch = nullptr;
     int64_t sort_scratch_elems = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -282,11 +282,13 @@ dm_status run_plan_chunked(dm_context* ctx, Workspace& ws, const dm_datagraph* d
 // count of segments tier 2 passed on is read back through host_word (host
 // memory) and the merge tier is launched only if there are any.  prof
 // (optional, 3 events): recorded after the LDS tiers and around the merge
-// tier; *merged tells whether it ran.
+// tier; *merged tells whether it ran.  one (optional): a single job passed
+// with the launches instead of jobs_d (n_jobs 1, merge_later required: the
+// caller uploads the job before it runs the merge tier).
 dm_status enqueue_sort(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
                        int32_t v0, int64_t max_in_cap, int32_t max_wp, int32_t* counters, const uint32_t* abort,
                        int32_t* host_word, hipEvent_t* prof = nullptr, bool* merged = nullptr, int32_t stream_k = 0,
-                       bool* merge_later = nullptr);
+                       bool* merge_later = nullptr, const SortJob* one = nullptr);
 // The merge tier over the segments tier 2 passed on (counters[1] of them,
 // nonzero), for a caller that took enqueue_sort's merge_later.
 dm_status enqueue_sort_merge(dm_context* ctx, Workspace& ws, const SortJob* jobs_d, int32_t n_jobs, int32_t nv,
