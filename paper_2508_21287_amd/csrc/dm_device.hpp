@@ -360,6 +360,9 @@ hipError_t launch_run_fill(const int32_t* aos, int64_t rows, int32_t size, int32
                            const int32_t* idx, int32_t* run_far, int32_t* run_start, hipStream_t s);
 hipError_t launch_run_offs(const int32_t* offs, int32_t n, int64_t rows, const int32_t* idx, const int64_t* total,
                            int32_t* run_offs, hipStream_t s);
+// flags[0] |= 1: the graph (ascending merged CSR lists) has a 4-cycle;
+// flags[1] |= 1: a vertex of degree above 16 left the answer undecided
+hipError_t launch_c4_check(const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t* flags, hipStream_t s);
 // *nnz_dev (<= nnz_max) directed edges, read on the device
 hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int64_t nnz_max,
                              int32_t wpr, uint32_t* bitmap, hipStream_t s);

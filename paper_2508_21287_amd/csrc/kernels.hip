@@ -2152,13 +2152,17 @@ hipError_t launch_ingest_count(const int32_t* edges, int64_t m, int32_t n, int32
 
 // Exclusive scan of int32 values (sums must fit int32; checked by the host).
 // out_excl has n+1 entries; out_excl[n] = total.  Single pass: tiles of
-// 1024 values, decoupled look-back between tiles.
-constexpr int kScanBlock = 256, kScanItems = 4;
+// 256 * ITEMS values (each thread a run of ITEMS, 16-byte loads and stores
+// where whole and aligned), decoupled look-back between tiles.  Long inputs
+// take 16 per thread: the tile's look-back round, not its bytes, sets the
+// pace at 4.
+constexpr int kScanBlock = 256;
+template <int ITEMS>
 __global__ __launch_bounds__(kScanBlock) void scan_i32_kernel(const int32_t* in, int32_t* out, int64_t n,
                                                               int64_t* total, uint64_t* status, uint64_t* ticket,
                                                               uint32_t epoch, const WaitCtl wc) {
     constexpr int NW = kScanBlock / 64;
-    constexpr int TILE = kScanBlock * kScanItems;
+    constexpr int TILE = kScanBlock * ITEMS;
     __shared__ int64_t s_tile, s_base;
     __shared__ int32_t s_wsum[NW], s_wexcl[NW];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -2175,14 +2179,25 @@ __global__ __launch_bounds__(kScanBlock) void scan_i32_kernel(const int32_t* in,
             }
             break;
         }
-        int32_t vals[kScanItems];
+        int32_t vals[ITEMS];
         int32_t sum = 0;
-        const int64_t base_i = tile * TILE + (int64_t)tid * kScanItems;
+        const int64_t base_i = tile * TILE + (int64_t)tid * ITEMS;
+        const bool whole = base_i + ITEMS <= n;
+        if (whole && ((uintptr_t)(in + base_i) & 15) == 0) {
 #pragma unroll
-        for (int i = 0; i < kScanItems; i++) {
-            vals[i] = (base_i + i < n) ? in[base_i + i] : 0;
-            sum += vals[i];
+            for (int q = 0; q < ITEMS / 4; q++) {
+                const int4 v = *(const int4*)(in + base_i + 4 * q);
+                vals[4 * q] = v.x;
+                vals[4 * q + 1] = v.y;
+                vals[4 * q + 2] = v.z;
+                vals[4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) vals[i] = (base_i + i < n) ? in[base_i + i] : 0;
         }
+#pragma unroll
+        for (int i = 0; i < ITEMS; i++) sum += vals[i];
         int32_t x = sum;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -2217,19 +2232,41 @@ __global__ __launch_bounds__(kScanBlock) void scan_i32_kernel(const int32_t* in,
         }
         __syncthreads();
         int64_t run = s_base + s_wexcl[wid] + (x - sum);
+        if (whole && ((uintptr_t)(out + base_i) & 15) == 0) {
 #pragma unroll
-        for (int i = 0; i < kScanItems; i++) {
-            if (base_i + i < n) out[base_i + i] = (int32_t)run;
-            run += vals[i];
+            for (int q = 0; q < ITEMS / 4; q++) {
+                int4 v;
+                v.x = (int32_t)run;
+                run += vals[4 * q];
+                v.y = (int32_t)run;
+                run += vals[4 * q + 1];
+                v.z = (int32_t)run;
+                run += vals[4 * q + 2];
+                v.w = (int32_t)run;
+                run += vals[4 * q + 3];
+                *(int4*)(out + base_i + 4 * q) = v;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                if (base_i + i < n) out[base_i + i] = (int32_t)run;
+                run += vals[i];
+            }
         }
     }
 }
 
 hipError_t launch_scan_i32(const int32_t* in, int32_t* out_excl, int64_t n, int64_t* total, uint64_t* status,
                            uint64_t* tickets, uint32_t epoch, const WaitCtl& w, hipStream_t s) {
-    const int64_t tiles = (n + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems);
-    hipLaunchKernelGGL(scan_i32_kernel, dim3(grid_for(tiles, 1, 1024)), dim3(kScanBlock), 0, s, in, out_excl, n,
-                       total, status, tickets + epoch, epoch, w);
+    if (n >= ((int64_t)1 << 20)) {
+        const int64_t tiles = (n + kScanBlock * 16 - 1) / (kScanBlock * 16);
+        hipLaunchKernelGGL(scan_i32_kernel<16>, dim3(grid_for(tiles, 1, 1024)), dim3(kScanBlock), 0, s, in, out_excl,
+                           n, total, status, tickets + epoch, epoch, w);
+    } else {
+        const int64_t tiles = (n + kScanBlock * 4 - 1) / (kScanBlock * 4);
+        hipLaunchKernelGGL(scan_i32_kernel<4>, dim3(grid_for(tiles, 1, 1024)), dim3(kScanBlock), 0, s, in, out_excl,
+                           n, total, status, tickets + epoch, epoch, w);
+    }
     return hipGetLastError();
 }
 
@@ -2592,6 +2629,52 @@ __global__ void bitmap_set_kernel(const int32_t* src, const int32_t* col, const 
         const int32_t u = src[e], w = col[e];
         atomicOr(&bm[(size_t)u * (size_t)wpr + (size_t)(w >> 5)], 1u << (w & 31));
     }
+}
+
+// A 4-cycle v-u-w-u'-v exists iff some vertex v has two distinct neighbours
+// with a common neighbour other than v.  Thread per vertex: every pair of its
+// neighbours, their ascending lists merged.  flags[0] |= 1 when one is found;
+// flags[1] |= 1 when a vertex has more than kC4MaxDegree neighbours (then the
+// answer is left to the caller).
+constexpr int kC4MaxDegree = 16;
+__global__ void c4_check_kernel(const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t* flags) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = row_ptr[v], e = row_ptr[v + 1];
+        if (e - b > kC4MaxDegree) {
+            atomicOr(&flags[1], 1);
+            continue;
+        }
+        bool found = false;
+        for (int32_t i = b; i < e && !found; i++) {
+            const int32_t u1 = col[i];
+            for (int32_t j = i + 1; j < e && !found; j++) {
+                const int32_t u2 = col[j];
+                int32_t p = row_ptr[u1], pe = row_ptr[u1 + 1], q = row_ptr[u2], qe = row_ptr[u2 + 1];
+                while (p < pe && q < qe) {
+                    const int32_t a = col[p], c = col[q];
+                    if (a == c) {
+                        if (a != (int32_t)v) {
+                            found = true;
+                            break;
+                        }
+                        p++;
+                        q++;
+                    } else if (a < c) {
+                        p++;
+                    } else {
+                        q++;
+                    }
+                }
+            }
+        }
+        if (found) atomicOr(&flags[0], 1);
+    }
+}
+
+hipError_t launch_c4_check(const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t* flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(c4_check_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, row_ptr, col, n, flags);
+    return hipGetLastError();
 }
 
 hipError_t launch_bitmap_set(const int32_t* src, const int32_t* col, const int64_t* nnz_dev, int64_t nnz_max,

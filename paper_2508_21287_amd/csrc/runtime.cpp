@@ -1402,9 +1402,12 @@ static dm_status build_motif(dm_datagraph* dg, int m) {
     return DM_OK;
 }
 
-// host_csr (optional): receives row_ptr and col, read back with the edge count.
+// host_csr (optional): receives row_ptr and col, read back with the edge
+// count, and *has_c4 whether the graph has a 4-cycle (1 / 0, -1 when a vertex
+// of degree above 16 left it undecided).
 static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
-                        std::pair<std::vector<int32_t>, std::vector<int32_t>>* host_csr = nullptr) {
+                        std::pair<std::vector<int32_t>, std::vector<int32_t>>* host_csr = nullptr,
+                        int* has_c4 = nullptr) {
     dm_context* ctx = dg->ctx;
     hipStream_t s = ctx->stream;
     Workspace& ws = ctx->ws;
@@ -1443,9 +1446,18 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
             st = fail(DM_ERR_DEVICE, "fill launch failed");
             break;
         }
-        if (m > 0 && hipMemcpyAsync(d_edges, gd->edges, sizeof(int32_t) * 2 * (size_t)m, hipMemcpyHostToDevice, s)) {
-            st = fail(DM_ERR_DEVICE, "edge upload failed");
-            break;
+        // the pinned staging buffer carries the edges up and, at the end, the
+        // results back: a copy from pageable memory would wait for the host
+        const size_t off_rp = 128, off_col = off_rp + a256(sizeof(int32_t) * (size_t)(n + 1));
+        const size_t need = off_col + (host_csr ? sizeof(int32_t) * (size_t)emax : 0);
+        const size_t edge_bytes = sizeof(int32_t) * 2 * (size_t)m;
+        if ((st = ws.ensure_stage(std::max(need, edge_bytes)))) break;
+        if (m > 0) {
+            std::memcpy(ws.stage_h, gd->edges, edge_bytes);
+            if (hipMemcpyAsync(d_edges, ws.stage_h, edge_bytes, hipMemcpyHostToDevice, s)) {
+                st = fail(DM_ERR_DEVICE, "edge upload failed");
+                break;
+            }
         }
         if (launch_ingest_count(d_edges, m, n, deg, flags, s)) {
             st = fail(DM_ERR_DEVICE, "ingest_count launch failed");
@@ -1486,6 +1498,10 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
             st = fail(DM_ERR_DEVICE, "compact launch failed");
             break;
         }
+        if (has_c4 && launch_c4_check(dg->row_ptr, dg->col, n, flags + 3, s)) {
+            st = fail(DM_ERR_DEVICE, "4-cycle check launch failed");
+            break;
+        }
         if (n <= 32768 && n > 0) {
             dg->words_per_row = (n + 31) / 32;
             int64_t words = (int64_t)n * dg->words_per_row;
@@ -1496,11 +1512,9 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
                 break;
             }
         }
-        // one readback through the pinned staging buffer: edge count, flags,
-        // row offsets, and the adjacency lists when the caller wants them
-        const size_t off_rp = 128, off_col = off_rp + a256(sizeof(int32_t) * (size_t)(n + 1));
-        const size_t need = off_col + (host_csr ? sizeof(int32_t) * (size_t)emax : 0);
-        if ((st = ws.ensure_stage(need))) break;
+        // one readback through the pinned staging buffer (its edges were
+        // copied up before any kernel below ran): edge count, flags, row
+        // offsets, and the adjacency lists when the caller wants them
         char* H = ws.stage_h;
         HostGather hg;
         std::memset(&hg, 0, sizeof hg);
@@ -1549,6 +1563,7 @@ static dm_status ingest(dm_datagraph* dg, const dm_graph_desc* gd,
             host_csr->second.assign((const int32_t*)(H + off_col), (const int32_t*)(H + off_col) + nnz);
         }
         dg->max_degree = hflags[2];
+        if (has_c4) *has_c4 = hflags[4] ? -1 : (hflags[3] ? 1 : 0);
     } while (0);
     cleanup();
     if (st == DM_OK) {
@@ -1636,14 +1651,16 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
     const bool aut = (motif_mask == DM_MOTIF_AUTO);
     std::pair<std::vector<int32_t>, std::vector<int32_t>> csr;  // host copy for the AUTO choice
     const auto tb0 = std::chrono::steady_clock::now();
-    dm_status st = ingest(dg, gd, aut ? &csr : nullptr);
+    int c4_dev = -1;
+    dm_status st = ingest(dg, gd, aut ? &csr : nullptr, aut ? &c4_dev : nullptr);
     const auto tb1 = std::chrono::steady_clock::now();
     if (st == DM_OK && dg->n > 0) {
         uint32_t want = motif_mask;
         if (aut) {
             // topology-aware set (Sec. VI-B): the square cell on grid-like graphs,
             // the claw on low-degree graphs without 4-cycles (heavy-hex-like)
-            int c4 = host_has_4cycle(csr.first, csr.second, dg->n);
+            // (decided on the device with the ingest, else walked here)
+            int c4 = c4_dev >= 0 ? c4_dev : host_has_4cycle(csr.first, csr.second, dg->n);
             if (c4 < 0) {
                 // too many 2-paths to check on the host: the cycle table decides
                 st = build_motif(dg, MOT_C4);

@@ -763,3 +763,51 @@ def test_auto_motif_choice(ctx):
         assert all(rows[m] == 0 for m in absent), (g.name, rows)
         check_enum(dg, g, W.cycle(6) if "M4-O" in want_set else W.path(8))
         dg.free()
+
+
+def has_4cycle_brute(n, edges):
+    # two distinct neighbours of one vertex sharing another neighbour
+    adj = [set() for _ in range(n)]
+    for u, v in np.asarray(edges).tolist():
+        if u != v:
+            adj[u].add(v)
+            adj[v].add(u)
+    for v in range(n):
+        nb = sorted(adj[v])
+        for i in range(len(nb)):
+            for j in range(i + 1, len(nb)):
+                if (adj[nb[i]] & adj[nb[j]]) - {v}:
+                    return True
+    return False
+
+
+def test_auto_4cycle_decision(ctx):
+    # the AUTO choice's 4-cycle test runs on the device with the ingest (a
+    # vertex above degree 16 leaves it to the host): one chord closing a single
+    # 4-cycle in a heavy-hex lattice, a hub of degree 20 on a cycle-free graph,
+    # and two hubs of degree 17 sharing their leaves
+    hh = W.heavy_hex(7, 19)
+    adj = [set() for _ in range(hh.n)]
+    for u, v in hh.edges.tolist():
+        adj[u].add(v)
+        adj[v].add(u)
+    a = 40
+    b = sorted(adj[a])[0]
+    c = next(x for x in sorted(adj[b]) if x != a)
+    d = next(x for x in sorted(adj[c]) if x != b and x not in adj[a])
+    chord = W.Graph(hh.n, np.vstack([hh.edges, [[a, d]]]).astype(np.int32), "HH(7,19)+chord")
+    hub = W.Graph(60, np.array([[0, i] for i in range(1, 21)] + [[i, i + 1] for i in range(20, 59)], np.int32),
+                  "hub20+path")
+    k217 = W.Graph(19, np.array([[h, i] for h in (0, 1) for i in range(2, 19)], np.int32), "K(2,17)")
+    for g in (chord, hub, k217):
+        c4 = has_4cycle_brute(g.n, g.edges)
+        say(f"case auto 4-cycle decision on {g.name}: 4-cycle {c4}")
+        dg = ctx.datagraph(g.n, g.edges)
+        rows = dg.info()["motif_rows"]
+        if c4:
+            assert rows["M4-O"] > 0 and rows["M4-1"] == 0, (g.name, rows)
+        else:
+            assert rows["M4-O"] == 0 and rows["M3"] == 0, (g.name, rows)
+        check_enum(dg, g, W.cycle(4))
+        check_enum(dg, g, W.path(5))
+        dg.free()
