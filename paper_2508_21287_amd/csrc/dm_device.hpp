@@ -345,11 +345,11 @@ hipError_t launch_claw_fill(const int32_t* rp, const int32_t* col, int32_t n, in
 // stride `stride`) by column `sec`, stably
 hipError_t launch_group_sort(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec, int32_t* data,
                              hipStream_t s);
-// The same order for groups of up to kGroupSortLds rows, any number of
-// columns, from the SoA table `in` into `out`, row-major (size int32 per row;
-// larger groups copied in their order)
+// The same order for groups of up to cap rows (a power of two, at most
+// kGroupSortLds), any number of columns, from the SoA table `in` into `out`,
+// row-major (size int32 per row; larger groups copied in their order)
 hipError_t launch_group_sort_lds(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec,
-                                 const int32_t* in, int32_t* out, hipStream_t s);
+                                 const int32_t* in, int32_t* out, int32_t cap, hipStream_t s);
 // Run index of a row-major table of `rows` rows (`size` int32 each) ordered
 // by (column 0, column sec): flags[i] = 1 where a run starts (the scan of the
 // flags gives each run its index), then the runs' first rows and values, and

@@ -2454,16 +2454,17 @@ hipError_t launch_group_sort(const int32_t* offs, int32_t n, int64_t stride, int
 // `size` columns of stride `stride`) by column `sec`, stably, into `out`
 // (same offsets): one workgroup per key vertex sorts (value, position) pairs
 // with a bitonic network in LDS and writes every column permuted.  Groups of
-// more than kGroupSortLds rows are copied unchanged.
+// more than cap rows (the dynamic LDS holds cap pairs, a power of two) are
+// copied unchanged.
 __global__ __launch_bounds__(256) void group_sort_lds_kernel(const int32_t* offs, int32_t n, int64_t stride,
                                                              int32_t size, int32_t sec, const int32_t* in,
-                                                             int32_t* out) {
-    __shared__ uint64_t key[kGroupSortLds];
+                                                             int32_t* out, int32_t cap) {
+    extern __shared__ uint64_t key[];
     const int tid = threadIdx.x, nt = (int)blockDim.x;
     for (int32_t v = blockIdx.x; v < n; v += gridDim.x) {
         const int32_t a = offs[v], len = offs[v + 1] - offs[v];
         if (len <= 0) continue;
-        if (len == 1 || len > kGroupSortLds) {
+        if (len == 1 || len > cap) {
             for (int64_t e = tid; e < (int64_t)len * size; e += nt) {
                 const int64_t i = e / size;
                 const int q = (int)(e - i * size);
@@ -2546,10 +2547,13 @@ hipError_t launch_run_offs(const int32_t* offs, int32_t n, int64_t rows, const i
 }
 
 hipError_t launch_group_sort_lds(const int32_t* offs, int32_t n, int64_t stride, int32_t size, int32_t sec,
-                                 const int32_t* in, int32_t* out, hipStream_t s) {
-    if (n <= 0 || sec < 0 || sec >= size) return hipSuccess;
-    hipLaunchKernelGGL(group_sort_lds_kernel, dim3(n < 16384 ? n : 16384), dim3(256), 0, s, offs, n, stride, size,
-                       sec, in, out);
+                                 const int32_t* in, int32_t* out, int32_t cap, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (sec < 0 || sec >= size || cap <= 0 || cap > kGroupSortLds || (cap & (cap - 1))) return hipErrorInvalidValue;
+    // LDS sized by the largest group, not by the kernel's limit: more
+    // workgroups resident per CU when the groups are small
+    hipLaunchKernelGGL(group_sort_lds_kernel, dim3(n < 16384 ? n : 16384), dim3(256), sizeof(uint64_t) * (size_t)cap,
+                       s, offs, n, stride, size, sec, in, out, cap);
     return hipGetLastError();
 }
 

@@ -1301,6 +1301,8 @@ static dm_status build_second_copy(dm_datagraph* dg, MotifTable& t) {
     const double d = std::max(dg->max_degree, 1);
     const double bound = d * std::pow(std::max(d - 1.0, 1.0), L - 2);
     const bool lds = bound <= (double)kGroupSortLds;
+    int32_t cap = 1;  // LDS pairs: the group-size bound rounded up to a power of two
+    while (lds && cap < (int32_t)bound) cap <<= 1;
     if (!lds && L > 6) return DM_OK;
     int32_t* sec = nullptr;
     const size_t bytes = sizeof(int32_t) * (size_t)t.stride * (size_t)L;
@@ -1309,7 +1311,7 @@ static dm_status build_second_copy(dm_datagraph* dg, MotifTable& t) {
     if (lds) {
         // row-major: a run's candidates are a few consecutive rows, one or two
         // cache lines instead of one per column
-        DM_HIP(launch_group_sort_lds(t.offs, dg->n, t.stride, L, L - 1, t.cols[0], sec, s));
+        DM_HIP(launch_group_sort_lds(t.offs, dg->n, t.stride, L, L - 1, t.cols[0], sec, cap, s));
         t.sec_rowmajor = true;
     } else {
         DM_HIP(hipMemcpyAsync(sec, t.cols[0], bytes, hipMemcpyDeviceToDevice, s));
@@ -1317,7 +1319,7 @@ static dm_status build_second_copy(dm_datagraph* dg, MotifTable& t) {
     }
     t.sec_base = sec;
     t.sorted_by = L;
-    t.sorted_max = lds ? kGroupSortLds : kGroupSortMax;
+    t.sorted_max = lds ? cap : kGroupSortMax;
     if (lds && t.rows > 0 && t.rows < INT32_MAX) {
         // run index: per key, the distinct far ends and where their runs
         // start (flags, their scan, then the runs and the per-key offsets);

@@ -293,6 +293,34 @@ def test_determinism(ctx):
     dg.free()
 
 
+def test_epoch_wrap(ctx):
+    # look-back words, scan tickets and the sort's segment marks carry a
+    # 14-bit epoch instead of being cleared per launch; once 16384 epochs are
+    # used the workspace clears them and starts over.  Run past that point
+    # (a few epochs per call) and check that tables, a data graph built after
+    # it and its CSR stay exact.
+    g = W.heavy_hex(3, 9)
+    dg = ctx.datagraph(g.n, g.edges)
+    pats = [W.path(6), W.prufer_tree(8, 3)]
+    want = [oracle.enumerate_embeddings(g.n, g.edges, p.n, p.edges)[0] for p in pats]
+    say(f"case epoch wrap on {g.name}: {[len(w) for w in want]} rows")
+    for i in range(12000):
+        p = pats[i & 1]
+        with dg.enumerate(p.n, p.edges) as r:
+            assert r.total == len(want[i & 1]), (i, p.name, r.total)
+            if i % 97 < 2:
+                assert np.array_equal(r.to_numpy(), want[i & 1]), (i, p.name)
+    dg.free()
+    dg = ctx.datagraph(g.n, g.edges)
+    rp, col = dg.csr()
+    rp0, col0 = oracle.normalize(g.n, g.edges)
+    assert np.array_equal(rp, rp0) and np.array_equal(col, col0)
+    for p, w in zip(pats, want):
+        with dg.enumerate(p.n, p.edges) as r:
+            assert np.array_equal(r.to_numpy(), w), p.name
+    dg.free()
+
+
 def test_to_torch(ctx):
     import torch
     g, pats = W.config1()
