@@ -2641,12 +2641,54 @@ __global__ void bitmap_set_kernel(const int32_t* src, const int32_t* col, const 
 // flags[1] |= 1 when a vertex has more than kC4MaxDegree neighbours (then the
 // answer is left to the caller).
 constexpr int kC4MaxDegree = 16;
+// Degree <= 4 around v (lattices): the neighbours' lists in registers,
+// four dependent load rounds, every pair compared.  Returns -1 when some
+// neighbour has more than 4 neighbours (the merge walk decides then).
+__device__ __forceinline__ int c4_small(const int32_t* row_ptr, const int32_t* col, int32_t v, int32_t b, int32_t d) {
+    int32_t u[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) u[i] = i < d ? col[b + i] : -1;
+    int32_t rs[4], du[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        rs[i] = u[i] >= 0 ? row_ptr[u[i]] : 0;
+        du[i] = u[i] >= 0 ? row_ptr[u[i] + 1] - rs[i] : 0;
+    }
+    bool wide = false;
+#pragma unroll
+    for (int i = 0; i < 4; i++) wide |= du[i] > 4;
+    if (wide) return -1;
+    int32_t w[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int32_t x = j < du[i] ? col[rs[i] + j] : -1;
+            w[i][j] = x == v ? -1 : x;  // v itself closes nothing
+        }
+    bool found = false;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int i2 = i + 1; i2 < 4; i2++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+#pragma unroll
+                for (int j2 = 0; j2 < 4; j2++) found |= w[i][j] >= 0 && w[i][j] == w[i2][j2];
+    return found ? 1 : 0;
+}
+
 __global__ void c4_check_kernel(const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t* flags) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t b = row_ptr[v], e = row_ptr[v + 1];
         if (e - b > kC4MaxDegree) {
             atomicOr(&flags[1], 1);
             continue;
+        }
+        if (e - b <= 4) {
+            const int r = c4_small(row_ptr, col, (int32_t)v, b, e - b);
+            if (r == 1) atomicOr(&flags[0], 1);
+            if (r >= 0) continue;
         }
         bool found = false;
         for (int32_t i = b; i < e && !found; i++) {
