@@ -321,6 +321,23 @@ def test_epoch_wrap(ctx):
     dg.free()
 
 
+def test_sort_small_segment_tier(ctx):
+    # tables whose root segments average at most 32 rows are sorted by
+    # one-wave workgroups with a small LDS tile, and a segment longer than
+    # that tile goes on to the next tier: here one root (the hub of a star)
+    # holds 1560 rows of the 3-path rooted at its middle vertex, the other
+    # roots 2 rows each on average
+    star = [[0, i] for i in range(1, 41)]
+    path = [[i, i + 1] for i in range(41, 240)]
+    g = W.Graph(241, np.array(star + path, np.int32), "star40+path200")
+    mid = W.Pattern(3, np.array([[0, 1], [0, 2]], np.int32), "P3-mid")
+    dg = ctx.datagraph(g.n, g.edges)
+    for p in (mid, W.path(3), W.path(4)):
+        check_enum(dg, g, p)
+    check_enum(dg, g, mid, cap=1000)
+    dg.free()
+
+
 def test_to_torch(ctx):
     import torch
     g, pats = W.config1()
