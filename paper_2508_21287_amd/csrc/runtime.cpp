@@ -1719,12 +1719,15 @@ dm_status dm_datagraph_build(dm_context* ctx, const dm_graph_desc* gd, uint32_t 
     }
     (void)hipEventRecord(e1, ctx->stream);
     const auto tb2 = std::chrono::steady_clock::now();
-    if (st == DM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(DM_ERR_DEVICE, "build sync failed");
     if (st == DM_OK) {
-        // a scan look-back that gave up leaves its mark in the control block
+        // a scan look-back that gave up leaves its mark in the control block:
+        // its abort word and diagnosis come back with the build's last sync
         Control* h = ctx->ws.ctrl_h;
-        if (hipMemcpy(h, ctx->ws.ctrl_d, sizeof(Control), hipMemcpyDeviceToHost) != hipSuccess)
-            st = fail(DM_ERR_DEVICE, "build readback failed");
+        const size_t at = offsetof(Control, abort), len = offsetof(Control, diag) + sizeof(WaitDiag) - at;
+        if (hipMemcpyAsync((char*)h + at, (const char*)ctx->ws.ctrl_d + at, len, hipMemcpyDeviceToHost,
+                           ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            st = fail(DM_ERR_DEVICE, "build sync failed");
         else
             st = check_abort(h->abort, h->diag, "data-graph build");
     }
